@@ -1,0 +1,343 @@
+"""Plain FP64 CPU oracle of the QSL Squasher path (arXiv:1609.00724).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the HIP library (``paper_1609_00724_amd``) and never imports it.
+
+Contents, each following the paper (Tassev & Savcheva 2017):
+  * ``Field`` / ``trace``      -- C library ``qsl_oracle.c``: Sect. 3.1-3.5,
+                                  eq. (1), (3)-(5), (9)-(11), Cash-Karp RK5(4)
+  * ``sobel_magnitude``        -- Sect. 3.6: FLEDGE map as the Sobel gradient
+                                  magnitude of a field-line-length map
+  * ``hilbert2_*``             -- Sect. 3.6: Hilbert ordering of a slice
+  * ``refine_slice``           -- Sect. 3.6: FLL-jump refinement along the curve
+  * ``convert_to_grid``        -- Sect. 3.6: array converter (max per cell,
+                                  log Q interpolated along the curve in gaps)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qsl_oracle.c")
+_LIB = os.path.join(_HERE, "libqsl_oracle.so")
+
+# status codes of one half-line (exit faces first)
+XLO, XHI, YLO, YHI, ZLO, ZHI = range(6)
+MAX_LENGTH, MAX_STEPS, NULL, UNDERFLOW, SEED_OUTSIDE, NONFINITE = range(6, 12)
+OPEN_BIT = 1 << 16
+
+PAPER, INTERP_NORMALIZE, ANALYTIC = 0, 1, 2
+AN_LINEAR, AN_CHARGES = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                        "-ffp-contract=off", "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Desc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("analytic", C.c_int32), ("n", C.c_int64 * 3),
+                ("origin", C.c_double * 3), ("spacing", C.c_double * 3),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("bx", C.c_void_p), ("by", C.c_void_p), ("bz", C.c_void_p),
+                ("lin", C.c_double * 12), ("charges", C.c_void_p), ("ncharges", C.c_int64)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h_init", C.c_double),
+                ("h_max", C.c_double), ("max_length", C.c_double), ("max_steps", C.c_int64),
+                ("frame_angle", C.c_double), ("nthreads", C.c_int32), ("pad", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        L.or_field_new.restype = P
+        L.or_field_new.argtypes = [C.POINTER(_Desc)]
+        L.or_field_free.argtypes = [P]
+        L.or_field_eval.argtypes = [P, C.c_int64, P, P, P, P]
+        L.or_trace.argtypes = [P, C.POINTER(_Opts), C.c_int64, P] + [P] * 11
+        L.or_ck54_tableau.argtypes = [P, P, P, P]
+        L.or_hilbert2_xy2d.argtypes = [C.c_int, C.c_int64, P, P, P]
+        L.or_hilbert2_d2xy.argtypes = [C.c_int, C.c_int64, P, P, P]
+        L.or_version.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Field:
+    """A field the oracle can trace through.
+
+    Grid kinds take node arrays of shape (nz, ny, nx) (x fastest) on the
+    node-centred grid ``origin + i * spacing``; the box is the node hull.
+    """
+
+    def __init__(self, desc: _Desc, keep):
+        self._keep = keep
+        self.lo = np.array(desc.lo[:])
+        self.hi = np.array(desc.hi[:])
+        self._h = lib().or_field_new(C.byref(desc))
+        if not self._h:
+            raise MemoryError("oracle field allocation failed")
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.or_field_free(self._h)
+            self._h = None
+
+    @classmethod
+    def grid(cls, bx, by, bz, origin, spacing, mode=PAPER):
+        bx, by, bz = (np.ascontiguousarray(b, dtype=np.float64) for b in (bx, by, bz))
+        nz, ny, nx = bx.shape
+        d = _Desc()
+        d.kind = mode
+        d.n[:] = (nx, ny, nz)
+        d.origin[:] = origin
+        d.spacing[:] = spacing
+        d.lo[:] = origin
+        d.hi[:] = [origin[i] + (d.n[i] - 1) * spacing[i] for i in range(3)]
+        d.bx, d.by, d.bz = _ptr(bx), _ptr(by), _ptr(bz)
+        return cls(d, (bx, by, bz))
+
+    @classmethod
+    def linear(cls, b0, M, lo, hi):
+        """Analytic B = b0 + M x on the closed box [lo, hi]."""
+        d = _Desc()
+        d.kind = ANALYTIC
+        d.analytic = AN_LINEAR
+        d.lin[:] = list(np.asarray(b0, float)) + list(np.asarray(M, float).reshape(9))
+        d.lo[:] = lo
+        d.hi[:] = hi
+        return cls(d, ())
+
+    @classmethod
+    def charges(cls, charges, lo, hi):
+        """Analytic field of point charges, rows (x, y, z, q)."""
+        ch = np.ascontiguousarray(charges, dtype=np.float64).reshape(-1, 4)
+        d = _Desc()
+        d.kind = ANALYTIC
+        d.analytic = AN_CHARGES
+        d.charges = _ptr(ch)
+        d.ncharges = ch.shape[0]
+        d.lo[:] = lo
+        d.hi[:] = hi
+        return cls(d, (ch,))
+
+    def eval(self, x):
+        """Bhat (as interpolated), d Bhat_i/d x_j and |B| at points x (n, 3)."""
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+        n = x.shape[0]
+        u = np.empty((n, 3))
+        J = np.empty((n, 3, 3))
+        b = np.empty(n)
+        lib().or_field_eval(self._h, n, _ptr(x), _ptr(u), _ptr(J), _ptr(b))
+        return u, J, b
+
+
+def default_opts(field: Field, spacing_min: float, tol: float):
+    return dict(rtol=tol, atol=tol, h_init=0.1 * spacing_min, h_max=spacing_min,
+                max_length=0.0, max_steps=1 << 22)
+
+
+def trace(field: Field, seeds, *, rtol, atol, h_init, h_max, max_length=0.0,
+          max_steps=1 << 22, frame_angle=0.0, nthreads=0, want_ends=False):
+    """Trace seeds (n, 3) both ways; return a dict of per-seed arrays.
+
+    Keys: fp_fwd, fp_bwd (n,3); fll, q_perp (eq. 11), q_det (determinant
+    form), q_fp (exit-face planes), lam_fwd, lam_bwd (n,); status (n,) int32
+    = fwd | bwd << 8 | OPEN_BIT; counts (n, 2, 3) = (accepted, rejected,
+    landing iterations) per half-line; ends (n, 2, 10) if asked.
+    """
+    seeds = np.ascontiguousarray(seeds, dtype=np.float64).reshape(-1, 3)
+    n = seeds.shape[0]
+    o = _Opts(rtol, atol, h_init, h_max, max_length, int(max_steps), frame_angle, nthreads, 0)
+    out = dict(fp_fwd=np.empty((n, 3)), fp_bwd=np.empty((n, 3)), fll=np.empty(n),
+               q_perp=np.empty(n), q_det=np.empty(n), q_fp=np.empty(n),
+               lam_fwd=np.empty(n), lam_bwd=np.empty(n),
+               status=np.empty(n, np.int32), counts=np.empty((n, 2, 3), np.int64))
+    ends = np.empty((n, 2, 10)) if want_ends else None
+    lib().or_trace(field._h, C.byref(o), n, _ptr(seeds), _ptr(out["fp_fwd"]), _ptr(out["fp_bwd"]),
+                   _ptr(out["fll"]), _ptr(out["q_perp"]), _ptr(out["q_det"]), _ptr(out["q_fp"]),
+                   _ptr(out["lam_fwd"]), _ptr(out["lam_bwd"]), _ptr(out["status"]),
+                   _ptr(out["counts"]), _ptr(ends))
+    if want_ends:
+        out["ends"] = ends
+    return out
+
+
+def ck54_tableau():
+    c, a, b5, b4 = np.empty(6), np.empty((6, 5)), np.empty(6), np.empty(6)
+    lib().or_ck54_tableau(_ptr(c), _ptr(a), _ptr(b5), _ptr(b4))
+    return c, a, b5, b4
+
+
+# --------------------------------------------------------------------------
+# Sect. 3.6: FLEDGE map = gradient magnitude of the Sobel operator on an FLL map
+# --------------------------------------------------------------------------
+
+def sobel_magnitude(f):
+    """sqrt(sum_d G_d^2); G_d = derivative [-1, 0, 1] along axis d convolved
+    with smoothing [1, 2, 1] along every other axis; mirror boundary
+    (d c b a | a b c d); pixel units.  Works for 2D and 3D arrays."""
+    f = np.asarray(f, dtype=np.float64)
+    nd = f.ndim
+    p = np.pad(f, 1, mode="symmetric")
+    total = np.zeros_like(f)
+    offsets = [(-1, 1.0), (0, 2.0), (1, 1.0)]
+    for d in range(nd):
+        g = np.zeros_like(f)
+        # loop over the 3^nd stencil taps
+        for taps in np.ndindex(*(3,) * nd):
+            w = 1.0
+            for ax, t in enumerate(taps):
+                off = t - 1
+                if ax == d:
+                    w *= float(off)           # derivative tap: -1, 0, +1
+                else:
+                    w *= offsets[t][1]        # smoothing tap: 1, 2, 1
+            if w == 0.0:
+                continue
+            sl = tuple(slice(1 + (t - 1), 1 + (t - 1) + f.shape[ax]) for ax, t in enumerate(taps))
+            g += w * p[sl]
+        total += g * g
+    return np.sqrt(total)
+
+
+# --------------------------------------------------------------------------
+# Sect. 3.6: Hilbert curve on a 2^L x 2^L slice
+# --------------------------------------------------------------------------
+
+def hilbert2_xy2d(L, x, y):
+    x = np.ascontiguousarray(x, dtype=np.int64)
+    y = np.ascontiguousarray(y, dtype=np.int64)
+    d = np.empty_like(x)
+    lib().or_hilbert2_xy2d(L, x.size, _ptr(x), _ptr(y), _ptr(d))
+    return d
+
+
+def hilbert2_d2xy(L, d):
+    d = np.ascontiguousarray(d, dtype=np.int64)
+    x = np.empty_like(d)
+    y = np.empty_like(d)
+    lib().or_hilbert2_d2xy(L, d.size, _ptr(d), _ptr(x), _ptr(y))
+    return x, y
+
+
+class SlicePlane:
+    """Horizontal slice z = z0 over [x0, x1] x [y0, y1] (Sect. 2: planar slice)."""
+
+    def __init__(self, z0, x0, x1, y0, y1):
+        self.z0, self.x0, self.x1, self.y0, self.y1 = z0, x0, x1, y0, y1
+
+    def centres(self, level, ix, iy):
+        n = 1 << level
+        px = self.x0 + (np.asarray(ix) + 0.5) * (self.x1 - self.x0) / n
+        py = self.y0 + (np.asarray(iy) + 0.5) * (self.y1 - self.y0) / n
+        return np.stack([px, py, np.full(px.shape, float(self.z0))], axis=-1)
+
+
+def base_samples(plane: SlicePlane, m: int, r: int):
+    """Base lattice: 2^m x 2^m pixel centres in level-m curve order q; key
+    of pixel q at the finest level m+r is q * 4^r + 4^r / 2."""
+    q = np.arange(4 ** m, dtype=np.int64)
+    ix, iy = hilbert2_d2xy(m, q)
+    keys = q * 4 ** r + 4 ** r // 2
+    return keys, plane.centres(m, ix, iy)
+
+
+def key_positions(plane: SlicePlane, m: int, r: int, keys):
+    """Centre of the finest-level cell H^-1(key) at level m + r."""
+    ix, iy = hilbert2_d2xy(m + r, keys)
+    return plane.centres(m + r, ix, iy)
+
+
+def refine_slice(plane: SlicePlane, m: int, r: int, thr: float, sample_fn, max_passes=64):
+    """FLL-jump refinement along the Hilbert curve (Sect. 3.6).
+
+    ``sample_fn(points (n,3)) -> dict`` with at least ``fll`` and ``q``.
+    Returns (keys, values dict, passes): samples in curve order.  A new sample
+    goes halfway (in key) between curve-successive samples whose FLL differs
+    by more than ``thr`` while they are at least two finest cells apart.
+    """
+    keys, pts = base_samples(plane, m, r)
+    vals = sample_fn(pts)
+    vals = {k: np.asarray(v) for k, v in vals.items()}
+    passes = 0
+    while passes < max_passes:
+        fll = vals["fll"]
+        gap = keys[1:] - keys[:-1]
+        jump = np.abs(fll[1:] - fll[:-1])
+        fire = (gap >= 2) & (jump > thr)
+        if not fire.any():
+            break
+        passes += 1
+        idx = np.nonzero(fire)[0]
+        newk = (keys[idx] + keys[idx + 1]) // 2
+        newv = sample_fn(key_positions(plane, m, r, newk))
+        # every new key lies strictly between keys[i] and keys[i+1]
+        keys = np.insert(keys, idx + 1, newk)
+        vals = {k: np.insert(v, idx + 1, np.asarray(newv[k]), axis=0) for k, v in vals.items()}
+    return keys, vals, passes
+
+
+def convert_to_grid(keys, values, m: int, r: int, level: int, log_interp: bool):
+    """Array converter (Sect. 3.6) to a 2^level x 2^level grid (m <= level <= m+r).
+
+    A cell is the aligned block of finest keys it contains; its value is the
+    largest sample in the block (NaN samples ignored unless all are NaN).  An
+    empty cell takes the value interpolated along the curve, linearly in key
+    (in log10 when ``log_interp``), between the nearest samples below and above
+    the block centre.  Output indexed [iy, ix].
+    """
+    keys = np.asarray(keys, dtype=np.int64)
+    values = np.asarray(values, dtype=np.float64)
+    n = 1 << level
+    bsize = 4 ** (m + r - level)
+    out = np.empty((n, n))
+    for cell in range(n * n):
+        lo, hi = cell * bsize, (cell + 1) * bsize
+        a = np.searchsorted(keys, lo, side="left")
+        b = np.searchsorted(keys, hi, side="left")
+        if b > a:
+            v = values[a:b]
+            v = v[~np.isnan(v)]
+            val = v.max() if v.size else np.nan
+        else:
+            kc = lo + (bsize - 1) / 2.0
+            j = a  # first sample above the block
+            if j == 0:
+                val = values[0]
+            elif j == keys.size:
+                val = values[-1]
+            else:
+                k0, k1 = keys[j - 1], keys[j]
+                v0, v1 = values[j - 1], values[j]
+                w = (kc - k0) / (k1 - k0)
+                if log_interp:
+                    val = 10.0 ** ((1 - w) * np.log10(v0) + w * np.log10(v1))
+                else:
+                    val = (1 - w) * v0 + w * v1
+        x, y = hilbert2_d2xy(level, np.array([cell]))
+        out[y[0], x[0]] = val
+    return out

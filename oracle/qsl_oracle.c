@@ -1,0 +1,714 @@
+/*
+ * qsl_oracle.c -- plain FP64 CPU oracle of the QSL Squasher field-line /
+ * squashing-factor path (Tassev & Savcheva, "QSL Squasher: A Fast
+ * Quasi-Separatrix Layer Map Calculator", ApJS 2017, arXiv:1609.00724).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP library
+ * against the paper.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load it.  It shares no source, header, table or helper
+ * with the HIP library, and the HIP library never loads it.
+ *
+ * Everything is computed in double precision, in the order the paper states,
+ * with no blocking or fusion:
+ *   Sect. 3.1  field-line ODE  d x / d lambda = Bhat(x)                 eq. (1)
+ *   Sect. 3.2  trilinear interpolation of the node field                 eq. (3)-(4)
+ *   Sect. 3.3  linearised deviation d dx / d lambda = (dx . grad) Bhat   eq. (5)
+ *   Sect. 3.4  adaptive Cash-Karp 5(4) Runge-Kutta stepping
+ *   Sect. 3.5  orthonormal initial frame eq. (9), end vectors eq. (10),
+ *              squashing factor eq. (11); field normalised on the nodes first
+ *              and renormalised only when projecting (footnote to Sect. 3.5)
+ *   Sect. 3.6  Hilbert-curve ordering of a slice (keys used by refinement)
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *   - cell lookup c = clamp(floor(s), 0, n-2); the fraction s-c is NOT clamped,
+ *     so stage points a little outside the box are linearly extrapolated from
+ *     the boundary cell;
+ *   - error norm = max over all 9 state components of
+ *     |y5 - y4| / (atol + rtol * max(|y|, |y5|)); textbook step controller
+ *     (grow by min(5, 0.9 err^-1/5), shrink by max(0.2, 0.9 err^-1/4));
+ *   - boundary landing: the step that leaves the closed box is re-solved for
+ *     the step length at which its 5th-order solution lies on the first face
+ *     crossed (Illinois regula falsi on the signed distance), then snapped;
+ *   - the frame (a, b) completing Bhat(x0) is the branchless construction of
+ *     Duff et al. 2017 (JCGT 6(1)); Q does not depend on this choice.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_VERSION 1
+
+/* field kinds */
+enum { OR_PAPER = 0, OR_INTERP_NORMALIZE = 1, OR_ANALYTIC = 2 };
+/* analytic fields */
+enum { OR_AN_LINEAR = 0, OR_AN_CHARGES = 1 };
+
+/* per-half-line outcome codes: exit faces first, then the other stops */
+enum {
+    OR_XLO = 0, OR_XHI = 1, OR_YLO = 2, OR_YHI = 3, OR_ZLO = 4, OR_ZHI = 5,
+    OR_MAX_LENGTH = 6, OR_MAX_STEPS = 7, OR_NULL = 8, OR_UNDERFLOW = 9,
+    OR_SEED_OUTSIDE = 10, OR_NONFINITE = 11
+};
+#define OR_OPEN_BIT (1 << 16)
+
+typedef struct {
+    int32_t kind;          /* OR_PAPER, OR_INTERP_NORMALIZE or OR_ANALYTIC */
+    int32_t analytic;      /* OR_AN_LINEAR or OR_AN_CHARGES (analytic kind) */
+    int64_t n[3];          /* nodes per axis (grid kinds) */
+    double origin[3];      /* position of node (0,0,0) */
+    double spacing[3];     /* node spacing per axis */
+    double lo[3], hi[3];   /* closed box; for grids the node hull */
+    const double *bx, *by, *bz;   /* node field, x fastest (grid kinds) */
+    double lin[12];        /* linear field B = lin[0..2] + M x, M row-major lin[3..11] */
+    const double *charges; /* ncharges x (x, y, z, q) */
+    int64_t ncharges;
+} or_field_desc;
+
+typedef struct {
+    or_field_desc d;
+    double *c[4];          /* prepared node arrays */
+} or_field;
+
+typedef struct {
+    double rtol, atol;
+    double h_init;         /* first trial step (affine units) */
+    double h_max;          /* largest step */
+    double max_length;     /* <= 0: unlimited */
+    int64_t max_steps;     /* accepted + rejected attempts per half-line */
+    double frame_angle;    /* rotate (a, b) about Bhat(x0) by this angle */
+    int32_t nthreads;      /* <= 0: OpenMP default */
+    int32_t pad;
+} or_opts;
+
+/* ------------------------------------------------------------------ */
+/* field preparation (footnote to Sect. 3.5: normalise the node field  */
+/* first, keep |B| for the prefactor of eq. (11))                      */
+/* ------------------------------------------------------------------ */
+
+void *or_field_new(const or_field_desc *desc)
+{
+    or_field *F = (or_field *)calloc(1, sizeof(or_field));
+    if (!F) return NULL;
+    F->d = *desc;
+    if (desc->kind == OR_ANALYTIC) return F;
+    int64_t N = desc->n[0] * desc->n[1] * desc->n[2];
+    for (int k = 0; k < 4; ++k) {
+        F->c[k] = (double *)malloc((size_t)N * sizeof(double));
+        if (!F->c[k]) return NULL;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        double bx = desc->bx[i], by = desc->by[i], bz = desc->bz[i];
+        if (desc->kind == OR_PAPER) {
+            double b = sqrt(bx * bx + by * by + bz * bz);
+            if (b < 1e-30) {
+                F->c[0][i] = F->c[1][i] = F->c[2][i] = 0.0;
+            } else {
+                F->c[0][i] = bx / b;
+                F->c[1][i] = by / b;
+                F->c[2][i] = bz / b;
+            }
+            F->c[3][i] = b;
+        } else {
+            F->c[0][i] = bx;
+            F->c[1][i] = by;
+            F->c[2][i] = bz;
+            F->c[3][i] = 0.0;
+        }
+    }
+    return F;
+}
+
+void or_field_free(void *h)
+{
+    or_field *F = (or_field *)h;
+    if (!F) return;
+    for (int k = 0; k < 4; ++k) free(F->c[k]);
+    free(F);
+}
+
+/* ------------------------------------------------------------------ */
+/* interpolation, eq. (3)-(4), and its analytic gradient (Sect. 3.3)   */
+/* ------------------------------------------------------------------ */
+
+/* cell c = vertex of the containing cell closest to the array origin */
+static void locate(const or_field *F, const double x[3], int64_t c[3], double t[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        double s = (x[d] - F->d.origin[d]) / F->d.spacing[d];
+        if (!(s > -1e9)) s = -1e9;      /* also catches NaN */
+        if (s > 1e9) s = 1e9;
+        double fl = floor(s);
+        if (fl < 0.0) fl = 0.0;
+        if (fl > (double)(F->d.n[d] - 2)) fl = (double)(F->d.n[d] - 2);
+        c[d] = (int64_t)fl;
+        t[d] = s - fl;
+    }
+}
+
+/* sum over the 8 stencil vertices of value * f_v and value * grad f_v */
+static void trilinear(const or_field *F, int ncomp, const double x[3],
+                      double val[4], double grad[4][3])
+{
+    int64_t c[3];
+    double t[3];
+    locate(F, x, c, t);
+    for (int k = 0; k < ncomp; ++k) {
+        val[k] = 0.0;
+        grad[k][0] = grad[k][1] = grad[k][2] = 0.0;
+    }
+    const int64_t nx = F->d.n[0], ny = F->d.n[1];
+    for (int v = 0; v < 8; ++v) {
+        int vv[3] = { v & 1, (v >> 1) & 1, (v >> 2) & 1 };
+        double w[3], dw[3];
+        for (int d = 0; d < 3; ++d) {
+            w[d] = vv[d] ? t[d] : 1.0 - t[d];
+            dw[d] = (vv[d] ? 1.0 : -1.0) / F->d.spacing[d];
+        }
+        double f = w[0] * w[1] * w[2];
+        double df[3] = { dw[0] * w[1] * w[2], w[0] * dw[1] * w[2], w[0] * w[1] * dw[2] };
+        int64_t idx = ((c[2] + vv[2]) * ny + (c[1] + vv[1])) * nx + (c[0] + vv[0]);
+        for (int k = 0; k < ncomp; ++k) {
+            double q = F->c[k][idx];
+            val[k] += f * q;
+            for (int j = 0; j < 3; ++j) grad[k][j] += df[j] * q;
+        }
+    }
+}
+
+/* u = B/|B| and grad u = (I - u u^T) grad B / |B| */
+static void normalise(const double B[3], double G[3][3], double u[3], double J[3][3], double *bmag)
+{
+    double b = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+    *bmag = b;
+    if (b < 1e-300) {
+        for (int i = 0; i < 3; ++i) {
+            u[i] = 0.0;
+            J[i][0] = J[i][1] = J[i][2] = 0.0;
+        }
+        return;
+    }
+    for (int i = 0; i < 3; ++i) u[i] = B[i] / b;
+    for (int j = 0; j < 3; ++j) {
+        double ug = u[0] * G[0][j] + u[1] * G[1][j] + u[2] * G[2][j];
+        for (int i = 0; i < 3; ++i) J[i][j] = (G[i][j] - u[i] * ug) / b;
+    }
+}
+
+static void analytic_B(const or_field *F, const double x[3], double B[3], double G[3][3])
+{
+    if (F->d.analytic == OR_AN_LINEAR) {
+        const double *L = F->d.lin;
+        for (int i = 0; i < 3; ++i) {
+            B[i] = L[i];
+            for (int j = 0; j < 3; ++j) {
+                B[i] += L[3 + 3 * i + j] * x[j];
+                G[i][j] = L[3 + 3 * i + j];
+            }
+        }
+        return;
+    }
+    /* point charges: B = sum q (r - r_i) / |r - r_i|^3 */
+    for (int i = 0; i < 3; ++i) {
+        B[i] = 0.0;
+        G[i][0] = G[i][1] = G[i][2] = 0.0;
+    }
+    for (int64_t m = 0; m < F->d.ncharges; ++m) {
+        const double *ch = F->d.charges + 4 * m;
+        double r[3] = { x[0] - ch[0], x[1] - ch[1], x[2] - ch[2] };
+        double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        double rn = sqrt(r2);
+        double r3 = r2 * rn, r5 = r3 * r2;
+        for (int i = 0; i < 3; ++i) {
+            B[i] += ch[3] * r[i] / r3;
+            for (int j = 0; j < 3; ++j)
+                G[i][j] += ch[3] * ((i == j ? 1.0 : 0.0) / r3 - 3.0 * r[i] * r[j] / r5);
+        }
+    }
+}
+
+/* Bhat(x), its gradient J[i][j] = d Bhat_i / d x_j, and |B|(x).
+ * PAPER mode: Bhat is the interpolant of the normalised node field (not a
+ * unit vector in general); |B| is the interpolant of the node magnitudes. */
+static void field_eval(const or_field *F, const double x[3], double u[3], double J[3][3], double *bmag)
+{
+    if (F->d.kind == OR_PAPER) {
+        double val[4], grad[4][3];
+        trilinear(F, 4, x, val, grad);
+        for (int i = 0; i < 3; ++i) {
+            u[i] = val[i];
+            for (int j = 0; j < 3; ++j) J[i][j] = grad[i][j];
+        }
+        *bmag = val[3];
+        return;
+    }
+    double B[3], G[3][3];
+    if (F->d.kind == OR_INTERP_NORMALIZE) {
+        double val[4], grad[4][3];
+        trilinear(F, 3, x, val, grad);
+        for (int i = 0; i < 3; ++i) {
+            B[i] = val[i];
+            for (int j = 0; j < 3; ++j) G[i][j] = grad[i][j];
+        }
+    } else {
+        analytic_B(F, x, B, G);
+    }
+    normalise(B, G, u, J, bmag);
+}
+
+void or_field_eval(const void *h, int64_t n, const double *x, double *u, double *J, double *bmag)
+{
+    const or_field *F = (const or_field *)h;
+    for (int64_t i = 0; i < n; ++i) {
+        double JJ[3][3];
+        field_eval(F, x + 3 * i, u + 3 * i, JJ, bmag + i);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) J[9 * i + 3 * a + b] = JJ[a][b];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* right-hand side: y = (x, dx1, dx2); eq. (1) and eq. (5)             */
+/* ------------------------------------------------------------------ */
+
+static void rhs(const or_field *F, double sigma, const double y[9], double dy[9])
+{
+    double u[3], J[3][3], bm;
+    field_eval(F, y, u, J, &bm);
+    for (int i = 0; i < 3; ++i) {
+        dy[i] = sigma * u[i];
+        dy[3 + i] = sigma * (J[i][0] * y[3] + J[i][1] * y[4] + J[i][2] * y[5]);
+        dy[6 + i] = sigma * (J[i][0] * y[6] + J[i][1] * y[7] + J[i][2] * y[8]);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Cash-Karp 5(4) (Cash & Karp 1990, cited in Sect. 3.4)               */
+/* ------------------------------------------------------------------ */
+
+static const double CK_C[6] = { 0.0, 1.0 / 5.0, 3.0 / 10.0, 3.0 / 5.0, 1.0, 7.0 / 8.0 };
+static const double CK_A[6][5] = {
+    { 0.0, 0.0, 0.0, 0.0, 0.0 },
+    { 1.0 / 5.0, 0.0, 0.0, 0.0, 0.0 },
+    { 3.0 / 40.0, 9.0 / 40.0, 0.0, 0.0, 0.0 },
+    { 3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0.0, 0.0 },
+    { -11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0.0 },
+    { 1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0 },
+};
+static const double CK_B5[6] = { 37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0, 512.0 / 1771.0 };
+static const double CK_B4[6] = { 2825.0 / 27648.0, 0.0, 18575.0 / 48384.0, 13525.0 / 55296.0,
+                                 277.0 / 14336.0, 1.0 / 4.0 };
+
+void or_ck54_tableau(double *c, double *a, double *b5, double *b4)
+{
+    for (int i = 0; i < 6; ++i) {
+        c[i] = CK_C[i];
+        b5[i] = CK_B5[i];
+        b4[i] = CK_B4[i];
+        for (int j = 0; j < 5; ++j) a[5 * i + j] = CK_A[i][j];
+    }
+}
+
+/* one trial step: 5th-order solution (propagated) and embedded 4th order */
+static void ck54_step(const or_field *F, double sigma, const double y[9], double h,
+                      double y5[9], double y4[9])
+{
+    double k[6][9], yt[9];
+    for (int s = 0; s < 6; ++s) {
+        for (int i = 0; i < 9; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < s; ++j) acc += CK_A[s][j] * k[j][i];
+            yt[i] = y[i] + h * acc;
+        }
+        rhs(F, sigma, yt, k[s]);
+    }
+    for (int i = 0; i < 9; ++i) {
+        double a5 = 0.0, a4 = 0.0;
+        for (int s = 0; s < 6; ++s) {
+            a5 += CK_B5[s] * k[s][i];
+            a4 += CK_B4[s] * k[s][i];
+        }
+        y5[i] = y[i] + h * a5;
+        y4[i] = y[i] + h * a4;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* one half-line: integrate to the boundary (Sect. 3.5)                */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double y[9];           /* end state: x, dx1, dx2 */
+    double s;              /* path parameter |lambda| at the end */
+    int32_t status;
+    int64_t accepted, rejected, land_iters;
+} or_half;
+
+static int outside(const or_field *F, const double x[3])
+{
+    for (int d = 0; d < 3; ++d)
+        if (x[d] < F->d.lo[d] || x[d] > F->d.hi[d]) return 1;
+    return 0;
+}
+
+static int all_finite(const double *v, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!isfinite(v[i])) return 0;
+    return 1;
+}
+
+/* signed distance of the end of a trial step of length h beyond face f */
+static double face_gap(const or_field *F, double sigma, const double y[9], double h, int f, double yo[9])
+{
+    double y4[9];
+    if (h == 0.0)
+        memcpy(yo, y, sizeof(double) * 9);
+    else
+        ck54_step(F, sigma, y, h, yo, y4);
+    int d = f / 2;
+    return (f & 1) ? yo[d] - F->d.hi[d] : F->d.lo[d] - yo[d];
+}
+
+/* Illinois regula falsi for the step length that ends on face f */
+static double land_on_face(const or_field *F, double sigma, const double y[9], double hstep, int f,
+                           double gtol, int64_t *iters)
+{
+    double yo[9];
+    double a = 0.0, b = hstep;
+    double ga = face_gap(F, sigma, y, a, f, yo);
+    if (ga >= 0.0) return 0.0;
+    double gb = face_gap(F, sigma, y, b, f, yo);
+    int side = 0;   /* which end was replaced last: +1 outside end, -1 inside end */
+    for (int it = 0; it < 200; ++it) {
+        double c = (a * gb - b * ga) / (gb - ga);
+        double gc = face_gap(F, sigma, y, c, f, yo);
+        ++*iters;
+        if (fabs(gc) <= gtol) return c;
+        if (gc > 0.0) {
+            b = c;
+            gb = gc;
+            if (side == +1) ga *= 0.5;   /* Illinois: same end replaced twice */
+            side = +1;
+        } else {
+            a = c;
+            ga = gc;
+            if (side == -1) gb *= 0.5;
+            side = -1;
+        }
+        if (b - a <= 1e-15 * hstep) break;
+    }
+    return ga > -gb ? a : b;  /* smaller |g| of the bracket ends */
+}
+
+static void trace_half(const or_field *F, const or_opts *O, double sigma, const double y0[9], or_half *out)
+{
+    double y[9], y5[9], y4[9];
+    memcpy(y, y0, sizeof y);
+    double s = 0.0, h = O->h_init;
+    double extent = 0.0;
+    for (int d = 0; d < 3; ++d) extent = fmax(extent, F->d.hi[d] - F->d.lo[d]);
+    const double hmin = 1e-12 * extent, gtol = 1e-12 * extent;
+    out->accepted = out->rejected = out->land_iters = 0;
+    out->status = -1;
+
+    for (;;) {
+        if (out->accepted + out->rejected >= O->max_steps) {
+            out->status = OR_MAX_STEPS;
+            break;
+        }
+        {   /* null: the interpolated unit field has (nearly) vanished here */
+            double u[3], J[3][3], bm;
+            field_eval(F, y, u, J, &bm);
+            if (sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) < 1e-6) {
+                out->status = OR_NULL;
+                break;
+            }
+        }
+        double hs = h < O->h_max ? h : O->h_max;
+        int last = 0;
+        if (O->max_length > 0.0 && hs >= O->max_length - s) {
+            hs = O->max_length - s;
+            last = 1;
+        }
+        ck54_step(F, sigma, y, hs, y5, y4);
+        if (!all_finite(y5, 9) || !all_finite(y4, 9)) {
+            out->status = OR_NONFINITE;
+            break;
+        }
+        double err = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            double sc = O->atol + O->rtol * fmax(fabs(y[i]), fabs(y5[i]));
+            err = fmax(err, fabs(y5[i] - y4[i]) / sc);
+        }
+        if (err > 1.0) {
+            ++out->rejected;
+            h = hs * fmax(0.2, 0.9 * pow(err, -0.25));
+            if (h < hmin) {
+                out->status = OR_UNDERFLOW;
+                break;
+            }
+            continue;
+        }
+        ++out->accepted;
+        if (outside(F, y5)) {
+            /* land on the first face crossed; exact ties keep the lower face */
+            double best = INFINITY;
+            int face = -1;
+            for (int f = 0; f < 6; ++f) {
+                int d = f / 2;
+                double g = (f & 1) ? y5[d] - F->d.hi[d] : F->d.lo[d] - y5[d];
+                if (!(g > 0.0)) continue;
+                double hf = land_on_face(F, sigma, y, hs, f, gtol, &out->land_iters);
+                if (hf < best) {
+                    best = hf;
+                    face = f;
+                }
+            }
+            double yl[9];
+            if (best > 0.0)
+                ck54_step(F, sigma, y, best, yl, y4);
+            else
+                memcpy(yl, y, sizeof yl);
+            int d = face / 2;
+            yl[d] = (face & 1) ? F->d.hi[d] : F->d.lo[d];
+            memcpy(y, yl, sizeof y);
+            s += best;
+            out->status = face;
+            break;
+        }
+        memcpy(y, y5, sizeof y);
+        if (last) {
+            s = O->max_length;
+            out->status = OR_MAX_LENGTH;
+            break;
+        }
+        s += hs;
+        h = hs * (err > 0.0 ? fmin(5.0, 0.9 * pow(err, -0.2)) : 5.0);
+    }
+    memcpy(out->y, y, sizeof y);
+    out->s = s;
+}
+
+/* ------------------------------------------------------------------ */
+/* frame (eq. 9) and squashing factor (eq. 10-11)                      */
+/* ------------------------------------------------------------------ */
+
+/* orthonormal (a, b) completing the unit vector n (Duff et al. 2017) */
+static void onb(const double n[3], double a[3], double b[3])
+{
+    double sg = n[2] >= 0.0 ? 1.0 : -1.0;
+    double p = -1.0 / (sg + n[2]);
+    double q = n[0] * n[1] * p;
+    a[0] = 1.0 + sg * n[0] * n[0] * p;
+    a[1] = sg * q;
+    a[2] = -sg * n[0];
+    b[0] = q;
+    b[1] = sg + n[1] * n[1] * p;
+    b[2] = -n[1];
+}
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static double cross_norm(const double *a, const double *b)
+{
+    double c0 = a[1] * b[2] - a[2] * b[1];
+    double c1 = a[2] * b[0] - a[0] * b[2];
+    double c2 = a[0] * b[1] - a[1] * b[0];
+    return sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+}
+
+/* [aF^2 bB^2 + aB^2 bF^2 - 2 (aB.bB)(aF.bF)]: bracket of eq. (11) */
+static double bracket(const double *aF, const double *bF, const double *aB, const double *bB)
+{
+    return dot3(aF, aF) * dot3(bB, bB) + dot3(aB, aB) * dot3(bF, bF) - 2.0 * dot3(aB, bB) * dot3(aF, bF);
+}
+
+/* remove the component along the renormalised field (Sect. 3.5) */
+static void perp(const double *dx, const double *u, double *out)
+{
+    double p = dot3(u, dx);
+    for (int i = 0; i < 3; ++i) out[i] = dx[i] - u[i] * p;
+}
+
+/* project along the field line onto the plane of exit face f */
+static void along_to_face(const double *dx, const double *v, int f, double *out)
+{
+    int d = f / 2;
+    double r = dx[d] / v[d];
+    for (int i = 0; i < 3; ++i) out[i] = dx[i] - v[i] * r;
+}
+
+static int is_face(int st) { return st >= OR_XLO && st <= OR_ZHI; }
+static int q_defined(int st) { return st >= OR_XLO && st <= OR_MAX_STEPS; }
+
+/*
+ * Trace n seeds (AoS, 3 per seed) forward and backward and assemble
+ * per seed: footpoints, lengths, Q (eq. 11), Q from the determinant form,
+ * Q in the exit-face planes, status; per half-line: step counters and the
+ * end state.  Any output pointer except status may be NULL.
+ */
+void or_trace(const void *hf, const or_opts *O, int64_t n, const double *seeds,
+              double *fp_fwd, double *fp_bwd, double *fll, double *q_perp, double *q_det,
+              double *q_fp, double *lam_fwd, double *lam_bwd, int32_t *status,
+              int64_t *counts, double *ends)
+{
+    const or_field *F = (const or_field *)hf;
+#ifdef _OPENMP
+    int nt = O->nthreads > 0 ? O->nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 8) num_threads(nt)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        const double *x0 = seeds + 3 * i;
+        or_half H[2];
+        const double qnan = NAN;
+        int stF, stB;
+        double u0[3], J0[3][3], B0 = 0.0;
+        memset(H, 0, sizeof H);
+
+        if (outside(F, x0)) {
+            stF = stB = OR_SEED_OUTSIDE;
+            for (int k = 0; k < 2; ++k) {
+                memcpy(H[k].y, x0, 3 * sizeof(double));
+                H[k].status = OR_SEED_OUTSIDE;
+            }
+        } else {
+            field_eval(F, x0, u0, J0, &B0);
+            double un = sqrt(dot3(u0, u0));
+            if (un < 1e-6) {
+                stF = stB = OR_NULL;
+                for (int k = 0; k < 2; ++k) {
+                    memcpy(H[k].y, x0, 3 * sizeof(double));
+                    H[k].status = OR_NULL;
+                }
+            } else {
+                double nrm[3] = { u0[0] / un, u0[1] / un, u0[2] / un };
+                double a[3], b[3], y0[9];
+                onb(nrm, a, b);
+                double ca = cos(O->frame_angle), sa = sin(O->frame_angle);
+                for (int j = 0; j < 3; ++j) {
+                    y0[j] = x0[j];
+                    y0[3 + j] = ca * a[j] + sa * b[j];      /* eq. (9): dx1(0) = a */
+                    y0[6 + j] = -sa * a[j] + ca * b[j];     /* eq. (9): dx2(0) = b */
+                }
+                trace_half(F, O, +1.0, y0, &H[0]);
+                trace_half(F, O, -1.0, y0, &H[1]);
+                stF = H[0].status;
+                stB = H[1].status;
+            }
+        }
+
+        double lf = H[0].s, lb = -H[1].s;
+        if (lam_fwd) lam_fwd[i] = lf;
+        if (lam_bwd) lam_bwd[i] = lb;
+        if (fll) fll[i] = lf - lb;
+        for (int j = 0; j < 3; ++j) {
+            if (fp_fwd) fp_fwd[3 * i + j] = H[0].y[j];
+            if (fp_bwd) fp_bwd[3 * i + j] = H[1].y[j];
+        }
+        int open = !(stF == OR_ZLO && stB == OR_ZLO);
+        status[i] = (stF & 0xff) | ((stB & 0xff) << 8) | (open ? OR_OPEN_BIT : 0);
+        if (counts) {
+            for (int k = 0; k < 2; ++k) {
+                counts[6 * i + 3 * k + 0] = H[k].accepted;
+                counts[6 * i + 3 * k + 1] = H[k].rejected;
+                counts[6 * i + 3 * k + 2] = H[k].land_iters;
+            }
+        }
+        if (ends) {
+            for (int k = 0; k < 2; ++k) {
+                for (int j = 0; j < 9; ++j) ends[20 * i + 10 * k + j] = H[k].y[j];
+                ends[20 * i + 10 * k + 9] = k == 0 ? lf : lb;
+            }
+        }
+
+        double qp = qnan, qd = qnan, qf = qnan;
+        if (q_defined(stF) && q_defined(stB)) {
+            double uF[3], uB[3], JF[3][3], JB[3][3], BF, BB;
+            field_eval(F, H[0].y, uF, JF, &BF);
+            field_eval(F, H[1].y, uB, JB, &BB);
+            double vF[3] = { uF[0], uF[1], uF[2] }, vB[3] = { uB[0], uB[1], uB[2] };
+            double nF = sqrt(dot3(uF, uF)), nB = sqrt(dot3(uB, uB));
+            for (int j = 0; j < 3; ++j) {
+                uF[j] /= nF;
+                uB[j] /= nB;
+            }
+            double aF[3], bF[3], aB[3], bB[3];
+            perp(H[0].y + 3, uF, aF);
+            perp(H[0].y + 6, uF, bF);
+            perp(H[1].y + 3, uB, aB);
+            perp(H[1].y + 6, uB, bB);
+            double br = bracket(aF, bF, aB, bB);
+            qp = BF * BB / (B0 * B0) * br;                               /* eq. (11) */
+            qd = br / (cross_norm(aF, bF) * cross_norm(aB, bB));
+            if (is_face(stF) && is_face(stB)) {
+                double pF1[3], pF2[3], pB1[3], pB2[3];
+                along_to_face(H[0].y + 3, vF, stF, pF1);
+                along_to_face(H[0].y + 6, vF, stF, pF2);
+                along_to_face(H[1].y + 3, vB, stB, pB1);
+                along_to_face(H[1].y + 6, vB, stB, pB2);
+                qf = bracket(pF1, pF2, pB1, pB2) / (cross_norm(pF1, pF2) * cross_norm(pB1, pB2));
+            }
+        }
+        if (q_perp) q_perp[i] = qp;
+        if (q_det) q_det[i] = qd;
+        if (q_fp) q_fp[i] = qf;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Hilbert curve on a 2^L x 2^L slice (Sect. 3.6), from its recursive  */
+/* definition: the curve of order L starts at (0,0) and ends at        */
+/* (2^L-1, 0); it visits the lower-left, upper-left, upper-right and   */
+/* lower-right quadrants in that order; the first quadrant holds the   */
+/* order L-1 curve reflected in the diagonal, the middle two hold it   */
+/* translated, the last holds it reflected in the anti-diagonal.       */
+/* ------------------------------------------------------------------ */
+
+static uint64_t h2_xy2d(int L, uint64_t x, uint64_t y)
+{
+    if (L == 0) return 0;
+    uint64_t s = (uint64_t)1 << (L - 1);
+    int rx = x >= s, ry = y >= s;
+    uint64_t lx = x - (rx ? s : 0), ly = y - (ry ? s : 0);
+    uint64_t q, cx, cy;
+    if (!rx && !ry) { q = 0; cx = ly; cy = lx; }
+    else if (!rx && ry) { q = 1; cx = lx; cy = ly; }
+    else if (rx && ry) { q = 2; cx = lx; cy = ly; }
+    else { q = 3; cx = s - 1 - ly; cy = s - 1 - lx; }
+    return q * s * s + h2_xy2d(L - 1, cx, cy);
+}
+
+static void h2_d2xy(int L, uint64_t d, uint64_t *x, uint64_t *y)
+{
+    if (L == 0) { *x = *y = 0; return; }
+    uint64_t s = (uint64_t)1 << (L - 1);
+    uint64_t q = d / (s * s), cx, cy;
+    h2_d2xy(L - 1, d % (s * s), &cx, &cy);
+    switch (q) {
+    case 0: *x = cy; *y = cx; break;
+    case 1: *x = cx; *y = cy + s; break;
+    case 2: *x = cx + s; *y = cy + s; break;
+    default: *x = s + (s - 1 - cy); *y = s - 1 - cx; break;
+    }
+}
+
+void or_hilbert2_xy2d(int L, int64_t n, const int64_t *x, const int64_t *y, int64_t *d)
+{
+    for (int64_t i = 0; i < n; ++i) d[i] = (int64_t)h2_xy2d(L, (uint64_t)x[i], (uint64_t)y[i]);
+}
+
+void or_hilbert2_d2xy(int L, int64_t n, const int64_t *d, int64_t *x, int64_t *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t xx, yy;
+        h2_d2xy(L, (uint64_t)d[i], &xx, &yy);
+        x[i] = (int64_t)xx;
+        y[i] = (int64_t)yy;
+    }
+}
+
+int or_version(void) { return OR_VERSION; }

@@ -1,0 +1,186 @@
+"""Pins of the oracle's map-level steps (QSL Squasher Sect. 3.6): Sobel FLEDGE,
+Hilbert ordering, FLL-jump refinement and the array converter."""
+import os
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# FLEDGE: Sobel gradient magnitude
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(7, 9), (16, 16), (5, 6, 7)])
+def test_sobel_matches_scipy(oracle_mod, shape):
+    f = synth.rng(3).normal(size=shape)
+    want = np.sqrt(sum(ndimage.sobel(f, axis=a, mode="reflect") ** 2 for a in range(f.ndim)))
+    assert np.allclose(oracle_mod.sobel_magnitude(f), want, atol=1e-12)
+
+
+def test_sobel_ramp_closed_form(oracle_mod):
+    a, b, c = 0.3, -1.7, 0.9
+    j, i = np.mgrid[0:12, 0:10]
+    s2 = oracle_mod.sobel_magnitude(a * i + b * j)
+    assert np.allclose(s2[1:-1, 1:-1], 8 * np.hypot(a, b))
+    k, j, i = np.mgrid[0:6, 0:7, 0:8]
+    s3 = oracle_mod.sobel_magnitude(a * i + b * j + c * k)
+    assert np.allclose(s3[1:-1, 1:-1, 1:-1], 32 * np.sqrt(a * a + b * b + c * c))
+
+
+def test_sobel_step_profile(oracle_mod):
+    f = np.zeros((8, 8))
+    f[:, 4:] = 1.0
+    s = oracle_mod.sobel_magnitude(f)
+    # columns 3 and 4 straddle the step: derivative 1 * (1 + 2 + 1)
+    assert np.allclose(s[:, 3], 4.0) and np.allclose(s[:, 4], 4.0)
+    assert np.allclose(s[:, :3], 0.0) and np.allclose(s[:, 5:], 0.0)
+
+
+def test_sobel_brute_force_tiny(oracle_mod):
+    f = synth.rng(4).normal(size=(4, 4))
+    p = np.pad(f, 1, mode="symmetric")
+    gx = np.zeros_like(f)
+    gy = np.zeros_like(f)
+    for y in range(4):
+        for x in range(4):
+            w = p[y:y + 3, x:x + 3]
+            gx[y, x] = (w[:, 2] - w[:, 0]) @ np.array([1, 2, 1])
+            gy[y, x] = (w[2, :] - w[0, :]) @ np.array([1, 2, 1])
+    assert np.allclose(oracle_mod.sobel_magnitude(f), np.hypot(gx, gy))
+
+
+# ---------------------------------------------------------------------------
+# Hilbert curve
+# ---------------------------------------------------------------------------
+
+def test_hilbert_golden_order2(oracle_mod):
+    rows = np.loadtxt(os.path.join(GOLDEN, "hilbert2_order2.txt"), dtype=np.int64)
+    x, y = oracle_mod.hilbert2_d2xy(2, rows[:, 0])
+    assert np.array_equal(x, rows[:, 1]) and np.array_equal(y, rows[:, 2])
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 5, 7])
+def test_hilbert_bijection_adjacency_blocks(oracle_mod, L):
+    O = oracle_mod
+    n = 1 << L
+    d = np.arange(n * n, dtype=np.int64)
+    x, y = O.hilbert2_d2xy(L, d)
+    assert np.unique(y * n + x).size == n * n                     # bijection
+    assert np.array_equal(O.hilbert2_xy2d(L, x, y), d)            # inverse
+    step = np.abs(np.diff(x)) + np.abs(np.diff(y))
+    assert np.all(step == 1)                                      # face-adjacent
+    assert (x[0], y[0]) == (0, 0) and (x[-1], y[-1]) == (n - 1, 0)
+    for j in range(1, L + 1):                                     # aligned blocks
+        bs = 4 ** j
+        side = 1 << j
+        bx = x.reshape(-1, bs)
+        by = y.reshape(-1, bs)
+        assert np.all(bx.max(1) - bx.min(1) == side - 1)
+        assert np.all(by.max(1) - by.min(1) == side - 1)
+        assert np.all(bx.min(1) % side == 0) and np.all(by.min(1) % side == 0)
+    # refinement of the curve: the level-(L-1) cell of d is the parent of d's cell
+    if L > 1:
+        xp, yp = O.hilbert2_d2xy(L - 1, d // 4)
+        assert np.array_equal(x // 2, xp) and np.array_equal(y // 2, yp)
+
+
+# ---------------------------------------------------------------------------
+# FLL-jump refinement and the array converter
+# ---------------------------------------------------------------------------
+
+PLANE_ARGS = (0.0, -1.0, 1.0, -1.0, 1.0)
+
+
+def _disc(R=0.5):
+    def fn(p):
+        inside = (p[:, 0] ** 2 + p[:, 1] ** 2 < R * R).astype(float)
+        return {"fll": inside, "q": 2.0 + 100.0 * inside}
+    return fn
+
+
+def test_refine_constant_field_adds_nothing(oracle_mod):
+    O = oracle_mod
+    plane = O.SlicePlane(*PLANE_ARGS)
+    keys, vals, passes = O.refine_slice(plane, 4, 2, 0.01,
+                                        lambda p: {"fll": np.ones(len(p)), "q": np.full(len(p), 2.0)})
+    assert passes == 0 and keys.size == 256
+    assert np.array_equal(keys, np.arange(256) * 16 + 8)
+
+
+def test_refine_disc_clusters_on_the_edge(oracle_mod):
+    O = oracle_mod
+    plane = O.SlicePlane(*PLANE_ARGS)
+    m, r, R = 5, 2, 0.5
+    keys, vals, passes = O.refine_slice(plane, m, r, 0.5, _disc(R))
+    assert np.all(np.diff(keys) > 0)                  # stays in curve order
+    assert passes == 4                                # key gap 16 -> 8 -> 4 -> 2 -> 1
+    base = keys % 16 == 8
+    new = ~base
+    assert new.sum() > 0
+    pos = O.key_positions(plane, m, r, keys[new])
+    fine = 2.0 / (1 << (m + r))
+    dist = np.abs(np.hypot(pos[:, 0], pos[:, 1]) - R)
+    # every inserted sample lies within one base pixel of the edge
+    assert dist.max() < 2.0 / (1 << m) * np.sqrt(2)
+    # count scales with the perimeter: doubling the radius ~doubles the insertions
+    keys2, _, _ = O.refine_slice(plane, m, r, 0.5, _disc(2 * R * 0.9))
+    ratio = (keys2.size - 4 ** m) / (keys.size - 4 ** m)
+    assert 1.4 < ratio < 2.6
+    # consecutive samples across the edge end up one finest cell apart in key
+    fl = vals["fll"]
+    jumps = np.nonzero(np.abs(np.diff(fl)) > 0.5)[0]
+    assert np.all(keys[jumps + 1] - keys[jumps] == 1)
+    assert fine > 0
+
+
+def test_convert_base_level_is_the_base_map(oracle_mod):
+    O = oracle_mod
+    plane = O.SlicePlane(*PLANE_ARGS)
+    m, r = 4, 2
+    keys, pts = O.base_samples(plane, m, r)
+    v = 2.0 + pts[:, 0] ** 2 + 3 * pts[:, 1]
+    grid = O.convert_to_grid(keys, v, m, r, m, log_interp=True)
+    n = 1 << m
+    c = (np.arange(n) + 0.5) * 2 / n - 1
+    want = 2.0 + c[None, :] ** 2 + 3 * c[:, None]
+    assert np.allclose(grid, want)
+
+
+def test_convert_max_and_gap_fill_brute_force(oracle_mod):
+    O = oracle_mod
+    m, r = 1, 1
+    # finest level 2: 16 keys; samples at a few keys
+    keys = np.array([1, 2, 3, 9, 14])
+    vals = np.array([10.0, 1000.0, 3.0, 100.0, 10.0])
+    g = O.convert_to_grid(keys, vals, m, r, 2, log_interp=True)
+    x, y = O.hilbert2_d2xy(2, np.arange(16))
+    expect = {}
+    for k in range(16):
+        if k in keys:
+            expect[k] = vals[list(keys).index(k)]
+        elif k < 1:
+            expect[k] = 10.0
+        elif k > 14:
+            expect[k] = 10.0
+        else:
+            lo = keys[keys < k].max()
+            hi = keys[keys > k].min()
+            w = (k - lo) / (hi - lo)
+            vlo, vhi = vals[list(keys).index(lo)], vals[list(keys).index(hi)]
+            expect[k] = 10 ** ((1 - w) * np.log10(vlo) + w * np.log10(vhi))
+    for k in range(16):
+        assert g[y[k], x[k]] == pytest.approx(expect[k], rel=1e-12)
+    # one level coarser: blocks of 4 keys -> max of their samples
+    g1 = O.convert_to_grid(keys, vals, m, r, 1, log_interp=True)
+    x1, y1 = O.hilbert2_d2xy(1, np.arange(4))
+    assert g1[y1[0], x1[0]] == 1000.0           # keys 1, 2, 3
+    assert g1[y1[2], x1[2]] == 100.0            # key 9
+    assert g1[y1[3], x1[3]] == 10.0             # key 14
+    # block 1 (keys 4..7) is empty: interpolate at its centre key 5.5 between 3 and 9
+    w = (5.5 - 3) / 6
+    assert g1[y1[1], x1[1]] == pytest.approx(10 ** ((1 - w) * np.log10(3.0) + w * 2.0))

@@ -50,7 +50,8 @@ class _Desc(C.Structure):
                 ("origin", C.c_double * 3), ("spacing", C.c_double * 3),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("bx", C.c_void_p), ("by", C.c_void_p), ("bz", C.c_void_p),
-                ("lin", C.c_double * 12), ("charges", C.c_void_p), ("ncharges", C.c_int64)]
+                ("lin", C.c_double * 12), ("charges", C.c_void_p), ("ncharges", C.c_int64),
+                ("quantize", C.c_int32), ("pad", C.c_int32)]
 
 
 class _Opts(C.Structure):
@@ -107,7 +108,9 @@ class Field:
             self._h = None
 
     @classmethod
-    def grid(cls, bx, by, bz, origin, spacing, mode=PAPER):
+    def grid(cls, bx, by, bz, origin, spacing, mode=PAPER, store="f64"):
+        """``store="f32"`` rounds the prepared node values (Bhat and |B| in PAPER
+        mode, B otherwise) to FP32, i.e. traces the field an FP32 node store holds."""
         bx, by, bz = (np.ascontiguousarray(b, dtype=np.float64) for b in (bx, by, bz))
         nz, ny, nx = bx.shape
         d = _Desc()
@@ -118,6 +121,7 @@ class Field:
         d.lo[:] = origin
         d.hi[:] = [origin[i] + (d.n[i] - 1) * spacing[i] for i in range(3)]
         d.bx, d.by, d.bz = _ptr(bx), _ptr(by), _ptr(bz)
+        d.quantize = {"f64": 0, "f32": 1}[store]
         return cls(d, (bx, by, bz))
 
     @classmethod
@@ -301,21 +305,24 @@ def refine_slice(plane: SlicePlane, m: int, r: int, thr: float, sample_fn, max_p
     return keys, vals, passes
 
 
-def convert_to_grid(keys, values, m: int, r: int, level: int, log_interp: bool):
+def convert_to_grid(keys, values, m: int, r: int, level: int, log_interp: bool, cells=None):
     """Array converter (Sect. 3.6) to a 2^level x 2^level grid (m <= level <= m+r).
 
     A cell is the aligned block of finest keys it contains; its value is the
     largest sample in the block (NaN samples ignored unless all are NaN).  An
     empty cell takes the value interpolated along the curve, linearly in key
     (in log10 when ``log_interp``), between the nearest samples below and above
-    the block centre.  Output indexed [iy, ix].
+    the block centre.  Output indexed [iy, ix]; with ``cells`` (curve indices at
+    ``level``) only those cells are computed and returned as a 1-D array.
     """
     keys = np.asarray(keys, dtype=np.int64)
     values = np.asarray(values, dtype=np.float64)
     n = 1 << level
     bsize = 4 ** (m + r - level)
     out = np.empty((n, n))
-    for cell in range(n * n):
+    todo = range(n * n) if cells is None else [int(c) for c in cells]
+    picked = []
+    for cell in todo:
         lo, hi = cell * bsize, (cell + 1) * bsize
         a = np.searchsorted(keys, lo, side="left")
         b = np.searchsorted(keys, hi, side="left")
@@ -338,6 +345,9 @@ def convert_to_grid(keys, values, m: int, r: int, level: int, log_interp: bool):
                     val = 10.0 ** ((1 - w) * np.log10(v0) + w * np.log10(v1))
                 else:
                     val = (1 - w) * v0 + w * v1
+        if cells is not None:
+            picked.append(val)
+            continue
         x, y = hilbert2_d2xy(level, np.array([cell]))
         out[y[0], x[0]] = val
-    return out
+    return out if cells is None else np.array(picked)

@@ -66,6 +66,9 @@ typedef struct {
     double lin[12];        /* linear field B = lin[0..2] + M x, M row-major lin[3..11] */
     const double *charges; /* ncharges x (x, y, z, q) */
     int64_t ncharges;
+    int32_t quantize;      /* 1: round the prepared node values to FP32 (the
+                              stored form of an FP32 node field) */
+    int32_t pad;
 } or_field_desc;
 
 typedef struct {
@@ -118,6 +121,8 @@ void *or_field_new(const or_field_desc *desc)
             F->c[2][i] = bz;
             F->c[3][i] = 0.0;
         }
+        if (desc->quantize == 1)
+            for (int k = 0; k < 4; ++k) F->c[k][i] = (double)(float)F->c[k][i];
     }
     return F;
 }

@@ -1,0 +1,274 @@
+/*
+ * qsq.h -- C-ABI of libqsq, an MI355X (gfx950) field-line tracer computing the
+ * squashing factor Q, field-line lengths and FLEDGE maps of a gridded 3D
+ * magnetic field (Tassev & Savcheva 2017, "QSL Squasher", arXiv:1609.00724).
+ *
+ * Conventions for every entry point
+ *   - Plain C types only.  "device" pointers are HIP device memory on the
+ *     current device; "host" pointers are ordinary host memory.
+ *   - The library never allocates device memory.  The caller passes every
+ *     buffer, including the field workspace (qsq_field_bytes) and scratch
+ *     (qsq_*_scratch_bytes).  Descriptors such as qsq_field point into caller
+ *     memory and stay valid while that memory lives.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls only enqueue work and return; results are valid once the stream
+ *     has been synchronised.  No call synchronises the host.
+ *   - Return value: QSQ_OK (0) or a negative QSQ_ERR_* code.  Arguments are
+ *     validated before anything is enqueued; on error nothing is enqueued and
+ *     qsq_last_error() holds a message (per host thread).  Per-line outcomes
+ *     never appear in the return value: they go to status arrays.
+ *   - Calls on distinct streams are independent.  Two calls that share a
+ *     scratch buffer must be ordered (same stream).
+ *
+ * Geometry: uniform Cartesian node-centred grid, x fastest.  Node (i,j,k) sits
+ * at origin + (i,j,k) * spacing; the box is the closed node hull (points on a
+ * face are inside).  Seeds and footpoints are FP64 in domain units; lambda is
+ * the affine parameter of the field-line equation (Sect. 3.1, eq. 1), i.e. the
+ * arc length measured with the interpolated unit field.
+ */
+#ifndef QSQ_H
+#define QSQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QSQ_ABI_VERSION 1
+
+/* return codes */
+#define QSQ_OK 0
+#define QSQ_ERR_INVALID_ARG (-1)
+#define QSQ_ERR_UNSUPPORTED (-2)
+#define QSQ_ERR_WORKSPACE_TOO_SMALL (-3)
+#define QSQ_ERR_HIP (-4)
+#define QSQ_ERR_COUNT_OVERFLOW (-5)
+
+/* element types */
+#define QSQ_F64 0
+#define QSQ_F32 1
+#define QSQ_BF16 2
+
+/* how the field between nodes is formed (Sect. 3.2 and the footnote to Sect. 3.5):
+ * PAPER: B is normalised on the nodes, then Bhat and |B| are interpolated
+ *        trilinearly (Bhat(x) is then not exactly a unit vector);
+ * INTERP_NORMALIZE: B and grad B are interpolated, then normalised. */
+#define QSQ_INTERP_PAPER 0
+#define QSQ_INTERP_NORMALIZE 1
+
+/* steppers (Sect. 3.4) */
+#define QSQ_STEPPER_CK54 0
+
+/* outcome of one half-line: the exit face (the box is left through it) or why
+ * tracing stopped elsewhere */
+#define QSQ_END_XLO 0
+#define QSQ_END_XHI 1
+#define QSQ_END_YLO 2
+#define QSQ_END_YHI 3
+#define QSQ_END_ZLO 4
+#define QSQ_END_ZHI 5
+#define QSQ_END_MAX_LENGTH 6    /* reached opts.max_length ("local Q", Sect. 3.5) */
+#define QSQ_END_MAX_STEPS 7     /* reached opts.max_steps step attempts */
+#define QSQ_END_NULL 8          /* |Bhat| < 1e-6: a null of the field */
+#define QSQ_END_UNDERFLOW 9     /* step size fell below 1e-12 of the box extent */
+#define QSQ_END_SEED_OUTSIDE 10 /* seed lies outside the closed box */
+#define QSQ_END_NONFINITE 11    /* the state became NaN or Inf */
+
+/* per-seed status word: forward | backward << 8 | QSQ_STATUS_OPEN; OPEN is set
+ * unless both ends lie on the bottom (z = min) face (open lines, Sect. 3.5) */
+#define QSQ_STATUS_FWD(s) ((s) & 0xff)
+#define QSQ_STATUS_BWD(s) (((s) >> 8) & 0xff)
+#define QSQ_STATUS_OPEN (1 << 16)
+
+/* trace flags */
+#define QSQ_FLAG_SKIP_OPEN 1    /* write NaN Q for open lines (Sect. 3.5 switch) */
+
+typedef struct qsq_grid {
+    int64_t n[3];          /* nodes per axis, each >= 2 */
+    double origin[3];      /* position of node (0,0,0) */
+    double spacing[3];     /* node spacing per axis, > 0 */
+} qsq_grid;
+
+/* A prepared field: POD descriptor of caller-owned device memory. */
+typedef struct qsq_field {
+    qsq_grid grid;
+    int32_t storage;       /* QSQ_F64 or QSQ_F32 */
+    int32_t mode;          /* QSQ_INTERP_* */
+    void *nodes;           /* device: n0*n1*n2 records of 4 storage values:
+                              PAPER (Bx/|B|, By/|B|, Bz/|B|, |B|),
+                              INTERP_NORMALIZE (Bx, By, Bz, 0); x fastest */
+    uint64_t bytes;        /* size of the node records */
+} qsq_field;
+
+typedef struct qsq_trace_opts {
+    int32_t stepper;       /* QSQ_STEPPER_CK54 */
+    int32_t step_dtype;    /* QSQ_F32: stage arithmetic in FP32, position and
+                              length accumulated in FP64; QSQ_F64: all FP64.
+                              Boundary landing and Q assembly are always FP64. */
+    double rtol, atol;     /* error control per state component (> 0) */
+    double h_init;         /* first trial step; <= 0: 0.1 * min spacing */
+    double h_max;          /* largest step; <= 0: min spacing */
+    double max_length;     /* <= 0: unlimited; else stop each half-line there */
+    int64_t max_steps;     /* step attempts per half-line; <= 0: 1 << 22 */
+    int32_t flags;         /* QSQ_FLAG_* */
+    int32_t reserved;
+} qsq_trace_opts;
+
+/* Per-seed results (device arrays of n entries; fp_* are SoA planes 3 x n:
+ * x at [0,n), y at [n,2n), z at [2n,3n)).  Any pointer except status may be
+ * NULL to skip that output. */
+typedef struct qsq_trace_out {
+    double *fp_fwd;        /* forward end point x(lambda_F) */
+    double *fp_bwd;        /* backward end point x(lambda_B) */
+    double *fll;           /* field-line length lambda_F - lambda_B */
+    double *q_perp;        /* Q of eq. (11) (perpendicular planes, |B| ratios) */
+    double *q_det;         /* same planes, determinant form (flux ratios exact) */
+    double *q_fp;          /* Q in the exit-face planes (NaN unless both ends are faces) */
+    int32_t *status;       /* status word, see QSQ_STATUS_* (required) */
+    int32_t *steps;        /* 2 x n: step attempts, forward at [0,n), backward at [n,2n) */
+    uint64_t *work;        /* 4 device counters the call adds to (caller zeroes them):
+                              step attempts, RHS evaluations and half-lines of the
+                              stepping kernel, and half-lines handed to FP64 landing */
+} qsq_trace_out;
+
+/* ---- library ---------------------------------------------------------- */
+
+/* QSQ_ABI_VERSION of the built library. */
+int qsq_abi_version(void);
+
+/* Static description of a QSQ_END_* code or a QSQ_ERR_* return code. */
+const char *qsq_status_string(int code);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char *qsq_last_error(void);
+
+/* ---- field preparation (Sect. 3.2; footnote to Sect. 3.5) ------------- */
+
+/* Bytes of node records for grid g at the given storage type. */
+uint64_t qsq_field_bytes(const qsq_grid *g, int storage);
+
+/*
+ * Prepare a field from three device arrays of node values (x fastest,
+ * n0*n1*n2 each, type `in_dtype` = QSQ_F64 or QSQ_F32) into `ws` (device,
+ * >= qsq_field_bytes, 16-byte aligned).  PAPER mode stores Bhat = B/|B| (0 where
+ * |B| < 1e-30) and |B| per node; INTERP_NORMALIZE stores B.  Fills *out.
+ * Errors: INVALID_ARG (null pointers, n < 2, spacing <= 0, bad enums),
+ * WORKSPACE_TOO_SMALL, UNSUPPORTED (storage other than F64/F32), HIP.
+ */
+int qsq_field_init(const qsq_grid *g, const void *bx, const void *by, const void *bz,
+                   int in_dtype, int storage, int mode, void *ws, uint64_t ws_bytes,
+                   void *stream, qsq_field *out);
+
+/* ---- tracing (Sect. 3.1-3.5) ------------------------------------------ */
+
+/* Scratch bytes qsq_trace needs for n seeds. */
+uint64_t qsq_trace_scratch_bytes(int64_t n);
+
+/*
+ * Trace n seeds both ways to the boundary and assemble Q and lengths.
+ * seeds: device FP64, SoA 3 x n.  For each seed x0: u0 = Bhat(x0)/|Bhat(x0)|,
+ * an orthonormal (a, b) completing u0 (eq. 9); integrate x, dx1 = a, dx2 = b
+ * with eq. (1) and eq. (5) forwards and backwards (Cash-Karp 5(4) with
+ * adaptive steps) until the box is left (landing exactly on the face crossed
+ * first), max_length, max_steps, a null or a non-finite state; then Q by
+ * eq. (10)-(11).  scratch: device, >= qsq_trace_scratch_bytes(n), 256-byte
+ * aligned.  Errors: INVALID_ARG, UNSUPPORTED, WORKSPACE_TOO_SMALL,
+ * COUNT_OVERFLOW (n > 2^30), HIP.
+ */
+int qsq_trace(const qsq_field *f, const double *seeds, int64_t n, const qsq_trace_opts *opts,
+              const qsq_trace_out *out, void *scratch, uint64_t scratch_bytes, void *stream);
+
+/* ---- FLEDGE (Sect. 3.6) ------------------------------------------------ */
+
+/*
+ * FLEDGE map: Sobel gradient magnitude sqrt(sum_d G_d^2) of a 2D or 3D FP32
+ * map (device, C order, last axis fastest), derivative [-1, 0, 1] along axis d
+ * convolved with [1, 2, 1] along the others, mirror boundary (d c b a | a b c
+ * d), pixel units.  `in` and `out` must not overlap.  shape: host, ndim
+ * entries, each >= 1.  Errors: INVALID_ARG, HIP.
+ */
+int qsq_fledge(const float *in, int ndim, const int64_t *shape, float *out, void *stream);
+
+/* ---- Hilbert ordering (Sect. 3.6) -------------------------------------- */
+
+/*
+ * Order-L Hilbert curve on a 2^L x 2^L slice (1 <= L <= 31).  The curve starts
+ * at cell (0,0) and ends at (2^L-1, 0); the order-1 curve visits (0,0), (0,1),
+ * (1,1), (1,0), and the order-L curve visits the four quadrants in that order,
+ * holding the order L-1 curve reflected in the diagonal, translated, translated,
+ * and reflected in the anti-diagonal.  d2xy maps n curve indices to cells, xy2d
+ * the reverse (device arrays).
+ */
+int qsq_hilbert2_d2xy(int L, const uint64_t *d, int64_t n, uint32_t *x, uint32_t *y, void *stream);
+int qsq_hilbert2_xy2d(int L, const uint32_t *x, const uint32_t *y, int64_t n, uint64_t *d, void *stream);
+
+/* ---- adaptive map of a slice (Sect. 3.6) -------------------------------- */
+
+typedef struct qsq_map_desc {
+    double z0;             /* horizontal slice z = z0 ... */
+    double x0, x1, y0, y1; /* ... over [x0, x1] x [y0, y1] */
+    int32_t base_level;    /* m: 2^m x 2^m base pixels, sampled at centres */
+    int32_t refine_levels; /* r: finest cells are 2^(m+r) per side (m + r <= 16) */
+    int32_t out_level;     /* level of the output grids, m <= out_level <= m + r */
+    int32_t reserved;
+    double threshold;      /* FLL jump that triggers a new sample (length units) */
+} qsq_map_desc;
+
+/* Results of qsq_qmap (device memory).  Samples are kept in curve order. */
+typedef struct qsq_map_out {
+    int64_t capacity;      /* entries available in each sample array (>= 4^m) */
+    uint64_t *keys;        /* finest-level curve index of each sample */
+    double *fll;           /* field-line length per sample */
+    double *q_perp;        /* Q of eq. (11) per sample */
+    int32_t *status;       /* status word per sample */
+    int64_t *count;        /* device scalar: samples held (<= capacity) */
+    int32_t *overflow;     /* device scalar: 1 if refinement wanted more than capacity */
+    float *q_grid;         /* 2^out_level squared, row y: max Q per cell, gaps filled
+                              by log Q interpolated along the curve; NULL: skip */
+    float *fll_grid;       /* same for the length (linear gap fill); NULL: skip */
+    float *fledge;         /* 2^m squared: Sobel FLEDGE of the base length map; NULL: skip */
+    uint64_t *work;        /* as qsq_trace_out.work, summed over every pass; NULL: skip */
+} qsq_map_out;
+
+/* Scratch bytes qsq_qmap needs for a map with `capacity` samples. */
+uint64_t qsq_qmap_scratch_bytes(const qsq_map_desc *d, int64_t capacity);
+
+/*
+ * Q / length / FLEDGE map of a horizontal slice with FLL-jump refinement along
+ * the Hilbert curve (Sect. 3.6).  Base samples: the 2^m x 2^m pixel centres,
+ * in level-m curve order q, with key q*4^r + 4^r/2.  Each pass inserts, between
+ * curve-successive samples whose keys differ by >= 2 and whose lengths differ
+ * by more than `threshold`, a sample at key floor((k1+k2)/2), placed at the
+ * centre of that finest cell; passes repeat (2r of them at most) until none
+ * fires.  All passes run on the device without host synchronisation.
+ * Errors: INVALID_ARG, UNSUPPORTED, WORKSPACE_TOO_SMALL, HIP.
+ */
+int qsq_qmap(const qsq_field *f, const qsq_map_desc *d, const qsq_trace_opts *opts,
+             const qsq_map_out *out, void *scratch, uint64_t scratch_bytes, void *stream);
+
+/* ---- measurement -------------------------------------------------------- */
+
+/* kernels the profiler times */
+#define QSQ_KERNEL_STEP 0       /* adaptive stepping kernel */
+#define QSQ_KERNEL_LAND 1       /* FP64 boundary landing */
+#define QSQ_KERNEL_ASSEMBLE 2   /* FP64 Q assembly */
+
+/*
+ * Kernel timing for benchmarks.  While enabled (process-wide), every launch of
+ * the kernels above is bracketed by two HIP events recorded on the launch's
+ * own stream.  qsq_profile_read waits for the recorded events and returns the
+ * number of launches of `kernel` since the last reset and their summed
+ * duration in milliseconds; qsq_profile_reset releases the events.  Not for
+ * use while another thread is launching.  Errors: INVALID_ARG, HIP.
+ */
+int qsq_profile_enable(int on);
+int qsq_profile_reset(void);
+int qsq_profile_read(int kernel, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSQ_H */

@@ -1,0 +1,116 @@
+"""ctypes mirror of include/qsq.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+# return codes
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_UNSUPPORTED = -2
+ERR_WORKSPACE_TOO_SMALL = -3
+ERR_HIP = -4
+ERR_COUNT_OVERFLOW = -5
+
+F64, F32, BF16 = 0, 1, 2
+INTERP_PAPER, INTERP_NORMALIZE = 0, 1
+STEPPER_CK54 = 0
+FLAG_SKIP_OPEN = 1
+
+END_XLO, END_XHI, END_YLO, END_YHI, END_ZLO, END_ZHI = range(6)
+END_MAX_LENGTH, END_MAX_STEPS, END_NULL, END_UNDERFLOW, END_SEED_OUTSIDE, END_NONFINITE = range(6, 12)
+STATUS_OPEN = 1 << 16
+
+# every entry point include/qsq.h declares
+EXPORTS = ["qsq_abi_version", "qsq_status_string", "qsq_last_error", "qsq_field_bytes",
+           "qsq_field_init", "qsq_trace_scratch_bytes", "qsq_trace", "qsq_fledge",
+           "qsq_hilbert2_d2xy", "qsq_hilbert2_xy2d", "qsq_qmap_scratch_bytes", "qsq_qmap",
+           "qsq_profile_enable", "qsq_profile_reset", "qsq_profile_read"]
+
+KERNEL_STEP, KERNEL_LAND, KERNEL_ASSEMBLE = 0, 1, 2
+
+
+class Grid(C.Structure):
+    _fields_ = [("n", C.c_int64 * 3), ("origin", C.c_double * 3), ("spacing", C.c_double * 3)]
+
+
+class FieldDesc(C.Structure):
+    _fields_ = [("grid", Grid), ("storage", C.c_int32), ("mode", C.c_int32),
+                ("nodes", C.c_void_p), ("bytes", C.c_uint64)]
+
+
+class TraceOpts(C.Structure):
+    _fields_ = [("stepper", C.c_int32), ("step_dtype", C.c_int32), ("rtol", C.c_double),
+                ("atol", C.c_double), ("h_init", C.c_double), ("h_max", C.c_double),
+                ("max_length", C.c_double), ("max_steps", C.c_int64), ("flags", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class TraceOut(C.Structure):
+    _fields_ = [("fp_fwd", C.c_void_p), ("fp_bwd", C.c_void_p), ("fll", C.c_void_p),
+                ("q_perp", C.c_void_p), ("q_det", C.c_void_p), ("q_fp", C.c_void_p),
+                ("status", C.c_void_p), ("steps", C.c_void_p), ("work", C.c_void_p)]
+
+
+class MapDesc(C.Structure):
+    _fields_ = [("z0", C.c_double), ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double),
+                ("y1", C.c_double), ("base_level", C.c_int32), ("refine_levels", C.c_int32),
+                ("out_level", C.c_int32), ("reserved", C.c_int32), ("threshold", C.c_double)]
+
+
+class MapOut(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("keys", C.c_void_p), ("fll", C.c_void_p),
+                ("q_perp", C.c_void_p), ("status", C.c_void_p), ("count", C.c_void_p),
+                ("overflow", C.c_void_p), ("q_grid", C.c_void_p), ("fll_grid", C.c_void_p),
+                ("fledge", C.c_void_p), ("work", C.c_void_p)]
+
+
+class QsqError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"qsq error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    L = C.CDLL(os.path.join(_HERE, "libqsq.so"))
+    P, I64, U64, I = C.c_void_p, C.c_int64, C.c_uint64, C.c_int
+    L.qsq_abi_version.restype = I
+    L.qsq_status_string.restype = C.c_char_p
+    L.qsq_status_string.argtypes = [I]
+    L.qsq_last_error.restype = C.c_char_p
+    L.qsq_field_bytes.restype = U64
+    L.qsq_field_bytes.argtypes = [C.POINTER(Grid), I]
+    L.qsq_field_init.restype = I
+    L.qsq_field_init.argtypes = [C.POINTER(Grid), P, P, P, I, I, I, P, U64, P, C.POINTER(FieldDesc)]
+    L.qsq_trace_scratch_bytes.restype = U64
+    L.qsq_trace_scratch_bytes.argtypes = [I64]
+    L.qsq_trace.restype = I
+    L.qsq_trace.argtypes = [C.POINTER(FieldDesc), P, I64, C.POINTER(TraceOpts), C.POINTER(TraceOut),
+                            P, U64, P]
+    L.qsq_fledge.restype = I
+    L.qsq_fledge.argtypes = [P, I, C.POINTER(C.c_int64), P, P]
+    L.qsq_hilbert2_d2xy.restype = I
+    L.qsq_hilbert2_d2xy.argtypes = [I, P, I64, P, P, P]
+    L.qsq_hilbert2_xy2d.restype = I
+    L.qsq_hilbert2_xy2d.argtypes = [I, P, P, I64, P, P]
+    L.qsq_qmap_scratch_bytes.restype = U64
+    L.qsq_qmap_scratch_bytes.argtypes = [C.POINTER(MapDesc), I64]
+    L.qsq_qmap.restype = I
+    L.qsq_qmap.argtypes = [C.POINTER(FieldDesc), C.POINTER(MapDesc), C.POINTER(TraceOpts),
+                           C.POINTER(MapOut), P, U64, P]
+    L.qsq_profile_enable.restype = I
+    L.qsq_profile_enable.argtypes = [I]
+    L.qsq_profile_reset.restype = I
+    L.qsq_profile_read.restype = I
+    L.qsq_profile_read.argtypes = [I, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+    return L
+
+
+lib = _load()
+
+
+def check(rc: int):
+    if rc != OK:
+        raise QsqError(rc, lib.qsq_last_error().decode())

@@ -1,0 +1,247 @@
+"""Torch-facing wrappers of the libqsq C-ABI: device buffers and streams come
+from PyTorch, every computation runs in the library's HIP kernels."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _abi as A
+from ._abi import check, lib
+
+_DT = {"f64": A.F64, "f32": A.F32}
+_MODE = {"paper": A.INTERP_PAPER, "interp_normalize": A.INTERP_NORMALIZE}
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        t = t.to(dtype)
+    return t.contiguous()
+
+
+def _bytes_tensor(nbytes, device):
+    # int64 elements keep the base 256-byte aligned through the caching allocator
+    return torch.empty((max(int(nbytes), 8) + 7) // 8, dtype=torch.int64, device=device)
+
+
+class Field:
+    """A prepared field: node records in a torch-owned device workspace."""
+
+    def __init__(self, desc: A.FieldDesc, ws: torch.Tensor):
+        self.desc = desc
+        self.ws = ws
+
+    @property
+    def n(self):
+        return tuple(self.desc.grid.n)
+
+    @property
+    def spacing(self):
+        return tuple(self.desc.grid.spacing)
+
+
+def field_init(bx, by, bz, origin, spacing, storage="f32", mode="paper", stream=None) -> Field:
+    """Prepare node records from B component arrays shaped (nz, ny, nx) on the device."""
+    if bx.dtype not in (torch.float32, torch.float64):
+        raise TypeError("B components must be float32 or float64")
+    in_dt = A.F64 if bx.dtype == torch.float64 else A.F32
+    bx, by, bz = (_dev(b, bx.dtype, "B") for b in (bx, by, bz))
+    nz, ny, nx = bx.shape
+    g = A.Grid()
+    g.n[:] = (nx, ny, nz)
+    g.origin[:] = tuple(float(v) for v in origin)
+    g.spacing[:] = tuple(float(v) for v in spacing)
+    nbytes = lib.qsq_field_bytes(C.byref(g), _DT[storage])
+    ws = _bytes_tensor(nbytes, bx.device)
+    d = A.FieldDesc()
+    check(lib.qsq_field_init(C.byref(g), _p(bx), _p(by), _p(bz), in_dt, _DT[storage], _MODE[mode],
+                             _p(ws), ws.numel() * 8, _stream(stream), C.byref(d)))
+    return Field(d, ws)
+
+
+def make_opts(rtol, atol, h_init=0.0, h_max=0.0, max_length=0.0, max_steps=0, step_dtype="f32",
+              skip_open=False) -> A.TraceOpts:
+    o = A.TraceOpts()
+    o.stepper = A.STEPPER_CK54
+    o.step_dtype = _DT[step_dtype]
+    o.rtol, o.atol = float(rtol), float(atol)
+    o.h_init, o.h_max, o.max_length = float(h_init), float(h_max), float(max_length)
+    o.max_steps = int(max_steps)
+    o.flags = A.FLAG_SKIP_OPEN if skip_open else 0
+    return o
+
+
+class TracePlan:
+    """Preallocated outputs and scratch for repeated traces of n seeds."""
+
+    def __init__(self, n: int, device, want=("fp_fwd", "fp_bwd", "fll", "q_perp", "q_det", "q_fp"),
+                 want_steps=False, want_work=False):
+        self.n = int(n)
+        f64 = dict(dtype=torch.float64, device=device)
+        self.out = {}
+        for k in want:
+            self.out[k] = torch.empty((3, n) if k.startswith("fp_") else (n,), **f64)
+        self.out["status"] = torch.empty(n, dtype=torch.int32, device=device)
+        if want_steps:
+            self.out["steps"] = torch.empty((2, n), dtype=torch.int32, device=device)
+        if want_work:
+            self.out["work"] = torch.zeros(4, dtype=torch.int64, device=device)
+        self.scratch = _bytes_tensor(lib.qsq_trace_scratch_bytes(n), device)
+        o = A.TraceOut()
+        for k in ("fp_fwd", "fp_bwd", "fll", "q_perp", "q_det", "q_fp", "status", "steps", "work"):
+            setattr(o, k, _p(self.out.get(k)))
+        self.tout = o
+
+    def run(self, field: Field, seeds_soa: torch.Tensor, opts: A.TraceOpts, stream=None):
+        check(lib.qsq_trace(C.byref(field.desc), _p(seeds_soa), self.n, C.byref(opts), C.byref(self.tout),
+                            _p(self.scratch), self.scratch.numel() * 8, _stream(stream)))
+        return self.out
+
+
+def trace(field: Field, seeds, *, rtol, atol, h_init=0.0, h_max=0.0, max_length=0.0, max_steps=0,
+          step_dtype="f32", skip_open=False, want_steps=False, want_work=False, stream=None):
+    """Trace seeds (device tensor (n, 3) or SoA (3, n), FP64) both ways.
+
+    Returns device tensors: fp_fwd, fp_bwd (3, n); fll, q_perp, q_det, q_fp (n,);
+    status (n,) int32; steps (2, n) int32 if asked.
+    """
+    seeds = _dev(seeds, torch.float64, "seeds")
+    if seeds.dim() != 2 or 3 not in seeds.shape:
+        raise ValueError("seeds must be (n, 3) or (3, n)")
+    soa = seeds if (seeds.shape[0] == 3 and seeds.shape[1] != 3) else seeds.t().contiguous()
+    n = soa.shape[1]
+    plan = TracePlan(n, seeds.device, want_steps=want_steps, want_work=want_work)
+    opts = make_opts(rtol, atol, h_init, h_max, max_length, max_steps, step_dtype, skip_open)
+    return plan.run(field, soa, opts, stream)
+
+
+def fledge(x: torch.Tensor, stream=None) -> torch.Tensor:
+    """Sobel FLEDGE magnitude of a 2D or 3D float32 device map."""
+    x = _dev(x, torch.float32, "map")
+    out = torch.empty_like(x)
+    shape = (C.c_int64 * x.dim())(*x.shape)
+    check(lib.qsq_fledge(_p(x), x.dim(), shape, _p(out), _stream(stream)))
+    return out
+
+
+def hilbert2_d2xy(L: int, d: torch.Tensor, stream=None):
+    d = _dev(d, torch.int64, "d")
+    x = torch.empty(d.shape, dtype=torch.int32, device=d.device)
+    y = torch.empty_like(x)
+    check(lib.qsq_hilbert2_d2xy(L, _p(d), d.numel(), _p(x), _p(y), _stream(stream)))
+    return x, y
+
+
+def hilbert2_xy2d(L: int, x: torch.Tensor, y: torch.Tensor, stream=None):
+    x = _dev(x, torch.int32, "x")
+    y = _dev(y, torch.int32, "y")
+    d = torch.empty(x.shape, dtype=torch.int64, device=x.device)
+    check(lib.qsq_hilbert2_xy2d(L, _p(x), _p(y), x.numel(), _p(d), _stream(stream)))
+    return d
+
+
+@dataclass
+class MapSpec:
+    z0: float
+    x0: float
+    x1: float
+    y0: float
+    y1: float
+    base_level: int
+    refine_levels: int
+    out_level: int
+    threshold: float
+
+    def desc(self) -> A.MapDesc:
+        d = A.MapDesc()
+        d.z0, d.x0, d.x1, d.y0, d.y1 = self.z0, self.x0, self.x1, self.y0, self.y1
+        d.base_level, d.refine_levels, d.out_level = self.base_level, self.refine_levels, self.out_level
+        d.threshold = self.threshold
+        return d
+
+
+class QMapPlan:
+    """Preallocated sample arrays, grids and scratch for repeated slice maps."""
+
+    def __init__(self, spec: MapSpec, capacity: int, device, grids=True, fledge_map=True):
+        """Work counters (step attempts, RHS evaluations, half-lines stepped,
+        half-lines landed) accumulate in ``self.work``; zero it to restart."""
+        self.spec = spec
+        self.capacity = int(capacity)
+        self.d = spec.desc()
+        cap = self.capacity
+        self.keys = torch.empty(cap, dtype=torch.int64, device=device)
+        self.fll = torch.empty(cap, dtype=torch.float64, device=device)
+        self.q_perp = torch.empty(cap, dtype=torch.float64, device=device)
+        self.status = torch.empty(cap, dtype=torch.int32, device=device)
+        self.count = torch.zeros(1, dtype=torch.int64, device=device)
+        self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
+        side = 1 << spec.out_level
+        bside = 1 << spec.base_level
+        self.q_grid = torch.empty((side, side), dtype=torch.float32, device=device) if grids else None
+        self.fll_grid = torch.empty((side, side), dtype=torch.float32, device=device) if grids else None
+        self.fledge = torch.empty((bside, bside), dtype=torch.float32, device=device) if fledge_map else None
+        self.work = torch.zeros(4, dtype=torch.int64, device=device)
+        self.scratch = _bytes_tensor(lib.qsq_qmap_scratch_bytes(C.byref(self.d), cap), device)
+        o = A.MapOut()
+        o.capacity = cap
+        o.keys, o.fll, o.q_perp, o.status = _p(self.keys), _p(self.fll), _p(self.q_perp), _p(self.status)
+        o.count, o.overflow = _p(self.count), _p(self.overflow)
+        o.q_grid, o.fll_grid, o.fledge = _p(self.q_grid), _p(self.fll_grid), _p(self.fledge)
+        o.work = _p(self.work)
+        self.mout = o
+
+    def run(self, field: Field, opts: A.TraceOpts, stream=None):
+        check(lib.qsq_qmap(C.byref(field.desc), C.byref(self.d), C.byref(opts), C.byref(self.mout),
+                           _p(self.scratch), self.scratch.numel() * 8, _stream(stream)))
+        return self
+
+    def result(self):
+        n = int(self.count.item())
+        return dict(count=n, overflow=int(self.overflow.item()), keys=self.keys[:n], fll=self.fll[:n],
+                    q_perp=self.q_perp[:n], status=self.status[:n], q_grid=self.q_grid,
+                    fll_grid=self.fll_grid, fledge=self.fledge)
+
+
+def qmap(field: Field, spec: MapSpec, capacity: int, *, rtol, atol, h_init=0.0, h_max=0.0,
+         max_length=0.0, max_steps=0, step_dtype="f32", skip_open=False, stream=None):
+    plan = QMapPlan(spec, capacity, field.ws.device)
+    opts = make_opts(rtol, atol, h_init, h_max, max_length, max_steps, step_dtype, skip_open)
+    plan.run(field, opts, stream)
+    return plan.result()
+
+
+class Profiler:
+    """Event timing of the library's kernels on their own streams (process-wide)."""
+
+    def __enter__(self):
+        check(lib.qsq_profile_reset())
+        check(lib.qsq_profile_enable(1))
+        return self
+
+    def __exit__(self, *exc):
+        check(lib.qsq_profile_enable(0))
+        return False
+
+    @staticmethod
+    def read(kernel: int):
+        n = C.c_int64()
+        ms = C.c_double()
+        check(lib.qsq_profile_read(kernel, C.byref(n), C.byref(ms)))
+        return int(n.value), float(ms.value)
+
+    @staticmethod
+    def reset():
+        check(lib.qsq_profile_reset())

@@ -1,0 +1,386 @@
+// C-ABI entry points of libqsq: argument validation, scratch carving and
+// launches.  Every check happens before anything is enqueued.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "qsq_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int ok()
+{
+    g_err[0] = '\0';
+    return QSQ_OK;
+}
+
+int hip_fail(hipError_t e, const char *where)
+{
+    return fail(QSQ_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+int check_grid(const qsq_grid *g)
+{
+    if (!g) return fail(QSQ_ERR_INVALID_ARG, "grid is NULL");
+    for (int d = 0; d < 3; ++d) {
+        if (g->n[d] < 2) return fail(QSQ_ERR_INVALID_ARG, "grid n[%d] = %lld < 2", d, (long long)g->n[d]);
+        if (g->n[d] > (1 << 20)) return fail(QSQ_ERR_UNSUPPORTED, "grid n[%d] too large", d);
+        if (!(g->spacing[d] > 0.0) || !isfinite(g->spacing[d]))
+            return fail(QSQ_ERR_INVALID_ARG, "grid spacing[%d] must be finite and > 0", d);
+        if (!isfinite(g->origin[d])) return fail(QSQ_ERR_INVALID_ARG, "grid origin[%d] not finite", d);
+    }
+    const double N = (double)g->n[0] * (double)g->n[1] * (double)g->n[2];
+    if (N > 2147483647.0) return fail(QSQ_ERR_UNSUPPORTED, "grid has more than 2^31-1 nodes");
+    return QSQ_OK;
+}
+
+int check_field(const qsq_field *f)
+{
+    if (!f) return fail(QSQ_ERR_INVALID_ARG, "field is NULL");
+    int rc = check_grid(&f->grid);
+    if (rc) return rc;
+    if (f->storage != QSQ_F32 && f->storage != QSQ_F64)
+        return fail(QSQ_ERR_UNSUPPORTED, "field storage %d not supported", f->storage);
+    if (f->mode != QSQ_INTERP_PAPER && f->mode != QSQ_INTERP_NORMALIZE)
+        return fail(QSQ_ERR_INVALID_ARG, "field mode %d unknown", f->mode);
+    if (!f->nodes) return fail(QSQ_ERR_INVALID_ARG, "field nodes is NULL");
+    if (f->bytes < qsq_field_bytes(&f->grid, f->storage))
+        return fail(QSQ_ERR_INVALID_ARG, "field bytes smaller than the grid needs");
+    return QSQ_OK;
+}
+
+int make_geom_opts(const qsq_field *f, const qsq_trace_opts *o, qsq::Geom *g, qsq::StepOpts *so)
+{
+    if (!o) return fail(QSQ_ERR_INVALID_ARG, "opts is NULL");
+    if (o->stepper != QSQ_STEPPER_CK54) return fail(QSQ_ERR_UNSUPPORTED, "stepper %d not supported", o->stepper);
+    if (o->step_dtype != QSQ_F32 && o->step_dtype != QSQ_F64)
+        return fail(QSQ_ERR_UNSUPPORTED, "step dtype %d not supported", o->step_dtype);
+    if (!(o->rtol > 0.0) || !(o->atol > 0.0) || !isfinite(o->rtol) || !isfinite(o->atol))
+        return fail(QSQ_ERR_INVALID_ARG, "rtol and atol must be finite and > 0");
+    if (!isfinite(o->h_init) || !isfinite(o->h_max) || !isfinite(o->max_length))
+        return fail(QSQ_ERR_INVALID_ARG, "h_init, h_max and max_length must be finite");
+    if (o->flags & ~QSQ_FLAG_SKIP_OPEN) return fail(QSQ_ERR_INVALID_ARG, "unknown flags 0x%x", o->flags);
+    double hmin_grid = f->grid.spacing[0];
+    double extent = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        g->n[d] = (int)f->grid.n[d];
+        g->o[d] = f->grid.origin[d];
+        g->h[d] = f->grid.spacing[d];
+        g->ih[d] = 1.0 / f->grid.spacing[d];
+        g->lo[d] = f->grid.origin[d];
+        g->hi[d] = f->grid.origin[d] + (double)(f->grid.n[d] - 1) * f->grid.spacing[d];
+        hmin_grid = fmin(hmin_grid, f->grid.spacing[d]);
+        extent = fmax(extent, g->hi[d] - g->lo[d]);
+    }
+    g->pad = 0;
+    so->rtol = o->rtol;
+    so->atol = o->atol;
+    so->h_max = o->h_max > 0.0 ? o->h_max : hmin_grid;
+    so->h_init = o->h_init > 0.0 ? o->h_init : 0.1 * hmin_grid;
+    if (so->h_init > so->h_max) so->h_init = so->h_max;
+    so->max_length = o->max_length > 0.0 ? o->max_length : 0.0;
+    so->hmin = 1e-12 * extent;
+    so->gtol = 1e-12 * extent;
+    so->max_steps = o->max_steps > 0 ? o->max_steps : (int64_t)1 << 22;
+    so->flags = o->flags;
+    so->pad = 0;
+    return QSQ_OK;
+}
+
+// ---- event-based kernel timing ----------------------------------------------
+struct ProfPair {
+    int kernel;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+std::vector<ProfPair> g_prof;
+bool g_prof_on = false;
+
+}  // namespace
+
+namespace qsq {
+
+bool profiling() { return g_prof_on; }
+
+void prof_begin(int kernel, hipStream_t s, void **token)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    ProfPair p{kernel, nullptr, nullptr};
+    if (hipEventCreate(&p.a) != hipSuccess || hipEventCreate(&p.b) != hipSuccess) {
+        *token = nullptr;
+        return;
+    }
+    hipEventRecord(p.a, s);
+    g_prof.push_back(p);
+    *token = reinterpret_cast<void *>(g_prof.size());   // 1-based slot
+}
+
+void prof_end(void *token, hipStream_t s)
+{
+    if (!token) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    const size_t i = reinterpret_cast<size_t>(token) - 1;
+    if (i < g_prof.size()) hipEventRecord(g_prof[i].b, s);
+}
+
+}  // namespace qsq
+
+extern "C" {
+
+int qsq_profile_enable(int on)
+{
+    g_prof_on = on != 0;
+    return ok();
+}
+
+int qsq_profile_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &p : g_prof) {
+        hipEventSynchronize(p.b);
+        hipEventDestroy(p.a);
+        hipEventDestroy(p.b);
+    }
+    g_prof.clear();
+    return ok();
+}
+
+int qsq_profile_read(int kernel, int64_t *launches, double *total_ms)
+{
+    if (!launches || !total_ms) return fail(QSQ_ERR_INVALID_ARG, "NULL output pointer");
+    if (kernel < QSQ_KERNEL_STEP || kernel > QSQ_KERNEL_ASSEMBLE) return fail(QSQ_ERR_INVALID_ARG, "kernel id");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    int64_t n = 0;
+    double tot = 0.0;
+    for (auto &p : g_prof) {
+        if (p.kernel != kernel) continue;
+        hipError_t e = hipEventSynchronize(p.b);
+        if (e != hipSuccess) return hip_fail(e, "qsq_profile_read");
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, p.a, p.b);
+        if (e != hipSuccess) return hip_fail(e, "qsq_profile_read");
+        ++n;
+        tot += ms;
+    }
+    *launches = n;
+    *total_ms = tot;
+    return ok();
+}
+
+
+int qsq_abi_version(void) { return QSQ_ABI_VERSION; }
+
+const char *qsq_status_string(int code)
+{
+    switch (code) {
+    case QSQ_END_XLO: return "left through the x = min face";
+    case QSQ_END_XHI: return "left through the x = max face";
+    case QSQ_END_YLO: return "left through the y = min face";
+    case QSQ_END_YHI: return "left through the y = max face";
+    case QSQ_END_ZLO: return "left through the z = min face";
+    case QSQ_END_ZHI: return "left through the z = max face";
+    case QSQ_END_MAX_LENGTH: return "reached max_length";
+    case QSQ_END_MAX_STEPS: return "reached max_steps";
+    case QSQ_END_NULL: return "field null (|Bhat| < 1e-6)";
+    case QSQ_END_UNDERFLOW: return "step size underflow";
+    case QSQ_END_SEED_OUTSIDE: return "seed outside the box";
+    case QSQ_END_NONFINITE: return "state became non-finite";
+    case QSQ_ERR_INVALID_ARG: return "invalid argument";
+    case QSQ_ERR_UNSUPPORTED: return "unsupported";
+    case QSQ_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case QSQ_ERR_HIP: return "HIP runtime error";
+    case QSQ_ERR_COUNT_OVERFLOW: return "count overflow";
+    default: return "unknown code";
+    }
+}
+
+const char *qsq_last_error(void) { return g_err; }
+
+uint64_t qsq_field_bytes(const qsq_grid *g, int storage)
+{
+    if (!g) return 0;
+    const uint64_t N = (uint64_t)g->n[0] * (uint64_t)g->n[1] * (uint64_t)g->n[2];
+    const uint64_t per = storage == QSQ_F64 ? 32 : storage == QSQ_F32 ? 16 : 0;
+    return N * per;
+}
+
+int qsq_field_init(const qsq_grid *g, const void *bx, const void *by, const void *bz, int in_dtype,
+                   int storage, int mode, void *ws, uint64_t ws_bytes, void *stream, qsq_field *out)
+{
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!bx || !by || !bz || !ws || !out) return fail(QSQ_ERR_INVALID_ARG, "NULL pointer argument");
+    if (in_dtype != QSQ_F32 && in_dtype != QSQ_F64) return fail(QSQ_ERR_INVALID_ARG, "in_dtype %d", in_dtype);
+    if (storage != QSQ_F32 && storage != QSQ_F64)
+        return fail(QSQ_ERR_UNSUPPORTED, "storage %d not supported", storage);
+    if (mode != QSQ_INTERP_PAPER && mode != QSQ_INTERP_NORMALIZE)
+        return fail(QSQ_ERR_INVALID_ARG, "mode %d unknown", mode);
+    if (!aligned(ws, 16)) return fail(QSQ_ERR_INVALID_ARG, "workspace must be 16-byte aligned");
+    const uint64_t need = qsq_field_bytes(g, storage);
+    if (ws_bytes < need)
+        return fail(QSQ_ERR_WORKSPACE_TOO_SMALL, "field workspace %llu < %llu bytes",
+                    (unsigned long long)ws_bytes, (unsigned long long)need);
+    hipError_t e = qsq::launch_field_init(g, bx, by, bz, in_dtype, storage, mode, ws,
+                                          static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_field_init");
+    out->grid = *g;
+    out->storage = storage;
+    out->mode = mode;
+    out->nodes = ws;
+    out->bytes = need;
+    return ok();
+}
+
+uint64_t qsq_trace_scratch_bytes(int64_t n)
+{
+    if (n < 0) return 0;
+    return 256 + qsq::records_bytes(n);
+}
+
+int qsq_trace(const qsq_field *f, const double *seeds, int64_t n, const qsq_trace_opts *opts,
+              const qsq_trace_out *out, void *scratch, uint64_t scratch_bytes, void *stream)
+{
+    int rc = check_field(f);
+    if (rc) return rc;
+    qsq::Geom g;
+    qsq::StepOpts so;
+    rc = make_geom_opts(f, opts, &g, &so);
+    if (rc) return rc;
+    if (n < 0) return fail(QSQ_ERR_INVALID_ARG, "n < 0");
+    if (n > ((int64_t)1 << 30)) return fail(QSQ_ERR_COUNT_OVERFLOW, "n > 2^30 seeds");
+    if (!out || !out->status) return fail(QSQ_ERR_INVALID_ARG, "out or out->status is NULL");
+    if (n == 0) return ok();
+    if (!seeds || !scratch) return fail(QSQ_ERR_INVALID_ARG, "NULL seeds or scratch");
+    if (!aligned(scratch, 256)) return fail(QSQ_ERR_INVALID_ARG, "scratch must be 256-byte aligned");
+    const uint64_t need = qsq_trace_scratch_bytes(n);
+    if (scratch_bytes < need)
+        return fail(QSQ_ERR_WORKSPACE_TOO_SMALL, "trace scratch %llu < %llu bytes",
+                    (unsigned long long)scratch_bytes, (unsigned long long)need);
+    qsq::TraceJob job{};
+    job.nodes = f->nodes;
+    job.storage = f->storage;
+    job.mode = f->mode;
+    job.g = g;
+    job.o = so;
+    job.seeds = seeds;
+    job.seed_stride = n;
+    job.n_host = n;
+    job.n_dev = nullptr;
+    qsq::carve_records(scratch, n, &job.rec, &job.counter);
+    job.fp_fwd = out->fp_fwd;
+    job.fp_bwd = out->fp_bwd;
+    job.fll = out->fll;
+    job.q_perp = out->q_perp;
+    job.q_det = out->q_det;
+    job.q_fp = out->q_fp;
+    job.status = out->status;
+    job.steps = out->steps;
+    job.out_stride = n;
+    job.work = reinterpret_cast<unsigned long long *>(out->work);
+    hipError_t e = qsq::launch_trace(job, opts->step_dtype, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_trace");
+    return ok();
+}
+
+int qsq_fledge(const float *in, int ndim, const int64_t *shape, float *out, void *stream)
+{
+    if (!in || !out || !shape) return fail(QSQ_ERR_INVALID_ARG, "NULL pointer argument");
+    if (ndim != 2 && ndim != 3) return fail(QSQ_ERR_INVALID_ARG, "ndim must be 2 or 3");
+    uint64_t N = 1;
+    for (int d = 0; d < ndim; ++d) {
+        if (shape[d] < 1) return fail(QSQ_ERR_INVALID_ARG, "shape[%d] < 1", d);
+        N *= (uint64_t)shape[d];
+    }
+    const char *a = reinterpret_cast<const char *>(in), *b = reinterpret_cast<const char *>(out);
+    if (a < b + N * 4 && b < a + N * 4) return fail(QSQ_ERR_INVALID_ARG, "in and out overlap");
+    hipError_t e = qsq::launch_fledge(in, ndim, shape, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_fledge");
+    return ok();
+}
+
+int qsq_hilbert2_d2xy(int L, const uint64_t *d, int64_t n, uint32_t *x, uint32_t *y, void *stream)
+{
+    if (L < 1 || L > 31) return fail(QSQ_ERR_INVALID_ARG, "L must be in [1, 31]");
+    if (n < 0) return fail(QSQ_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return ok();
+    if (!d || !x || !y) return fail(QSQ_ERR_INVALID_ARG, "NULL pointer argument");
+    hipError_t e = qsq::launch_hilbert2_d2xy(L, d, n, x, y, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_hilbert2_d2xy");
+    return ok();
+}
+
+int qsq_hilbert2_xy2d(int L, const uint32_t *x, const uint32_t *y, int64_t n, uint64_t *d, void *stream)
+{
+    if (L < 1 || L > 31) return fail(QSQ_ERR_INVALID_ARG, "L must be in [1, 31]");
+    if (n < 0) return fail(QSQ_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return ok();
+    if (!d || !x || !y) return fail(QSQ_ERR_INVALID_ARG, "NULL pointer argument");
+    hipError_t e = qsq::launch_hilbert2_xy2d(L, x, y, n, d, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_hilbert2_xy2d");
+    return ok();
+}
+
+static int check_map(const qsq_map_desc *d)
+{
+    if (!d) return fail(QSQ_ERR_INVALID_ARG, "map desc is NULL");
+    if (d->base_level < 1 || d->refine_levels < 0 || d->base_level + d->refine_levels > 16)
+        return fail(QSQ_ERR_INVALID_ARG, "need base_level >= 1, refine_levels >= 0, sum <= 16");
+    if (d->out_level < d->base_level || d->out_level > d->base_level + d->refine_levels)
+        return fail(QSQ_ERR_INVALID_ARG, "out_level outside [base_level, base_level + refine_levels]");
+    if (!(d->x1 > d->x0) || !(d->y1 > d->y0) || !isfinite(d->z0))
+        return fail(QSQ_ERR_INVALID_ARG, "slice extent must satisfy x1 > x0, y1 > y0, finite z0");
+    if (!(d->threshold >= 0.0)) return fail(QSQ_ERR_INVALID_ARG, "threshold must be >= 0");
+    return QSQ_OK;
+}
+
+uint64_t qsq_qmap_scratch_bytes(const qsq_map_desc *d, int64_t capacity)
+{
+    if (!d || capacity <= 0) return 0;
+    return qsq::qmap_scratch_bytes(d, capacity);
+}
+
+int qsq_qmap(const qsq_field *f, const qsq_map_desc *d, const qsq_trace_opts *opts, const qsq_map_out *out,
+             void *scratch, uint64_t scratch_bytes, void *stream)
+{
+    int rc = check_field(f);
+    if (rc) return rc;
+    rc = check_map(d);
+    if (rc) return rc;
+    qsq::Geom g;
+    qsq::StepOpts so;
+    rc = make_geom_opts(f, opts, &g, &so);
+    if (rc) return rc;
+    if (!out) return fail(QSQ_ERR_INVALID_ARG, "out is NULL");
+    const int64_t nb = (int64_t)1 << (2 * d->base_level);
+    if (out->capacity < nb) return fail(QSQ_ERR_INVALID_ARG, "capacity < 4^base_level");
+    if (out->capacity > ((int64_t)1 << 31) - 1) return fail(QSQ_ERR_COUNT_OVERFLOW, "capacity >= 2^31");
+    if (!out->keys || !out->fll || !out->q_perp || !out->status || !out->count || !out->overflow)
+        return fail(QSQ_ERR_INVALID_ARG, "sample arrays, count and overflow are required");
+    if (!scratch || !aligned(scratch, 256)) return fail(QSQ_ERR_INVALID_ARG, "scratch NULL or not 256-byte aligned");
+    const uint64_t need = qsq::qmap_scratch_bytes(d, out->capacity);
+    if (scratch_bytes < need)
+        return fail(QSQ_ERR_WORKSPACE_TOO_SMALL, "qmap scratch %llu < %llu bytes",
+                    (unsigned long long)scratch_bytes, (unsigned long long)need);
+    hipError_t e = qsq::launch_qmap(f, g, so, opts->step_dtype, d, out, scratch, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_qmap");
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,833 @@
+// Field-line + deviation tracer for gfx950 (QSL Squasher, Sect. 3.1-3.5).
+//
+// Three kernels per trace call:
+//   k_trace    persistent wave64 lanes; each lane owns one half-line (seed x
+//              direction), takes adaptive Cash-Karp 5(4) steps of
+//              y = (x, dx1, dx2) under eq. (1) and eq. (5) in the stepping
+//              precision T, and retires when a trial step leaves the box or a
+//              stop condition holds.  Retired lanes are refilled from a device
+//              work counter with one atomic per wave (ballot + prefix count).
+//   k_land     FP64: re-solves the step that left the box for the step length
+//              whose 5th-order end lies on the first face crossed (Illinois
+//              regula falsi on the signed face distance), then snaps to it.
+//   k_assemble FP64: per seed, projects the deviations perpendicular to the
+//              renormalised field at both ends and forms Q by eq. (10)-(11),
+//              the determinant form, the exit-face-plane Q and the length.
+//
+// Field records are 4-vectors per node (x fastest): PAPER mode holds
+// (Bhat, |B|) with Bhat = B/|B| formed on the nodes (footnote to Sect. 3.5);
+// INTERP_NORMALIZE holds B.  One RHS evaluation gathers the 8 corner records of
+// the containing cell (eq. 3-4) and forms the value and the analytic gradient
+// of the trilinear interpolant with a lerp tree (Sect. 3.3).
+#include <math.h>
+
+#include "qsq_internal.h"
+
+namespace qsq {
+
+// ---------------------------------------------------------------------------
+// Cash-Karp 5(4) coefficients (Cash & Karp 1990, the stepper of Sect. 3.4)
+// ---------------------------------------------------------------------------
+namespace ck {
+constexpr double a21 = 1.0 / 5.0;
+constexpr double a31 = 3.0 / 40.0, a32 = 9.0 / 40.0;
+constexpr double a41 = 3.0 / 10.0, a42 = -9.0 / 10.0, a43 = 6.0 / 5.0;
+constexpr double a51 = -11.0 / 54.0, a52 = 5.0 / 2.0, a53 = -70.0 / 27.0, a54 = 35.0 / 27.0;
+constexpr double a61 = 1631.0 / 55296.0, a62 = 175.0 / 512.0, a63 = 575.0 / 13824.0,
+                 a64 = 44275.0 / 110592.0, a65 = 253.0 / 4096.0;
+constexpr double b1 = 37.0 / 378.0, b3 = 250.0 / 621.0, b4 = 125.0 / 594.0, b6 = 512.0 / 1771.0;
+// difference between the 5th- and the embedded 4th-order weights
+constexpr double e1 = b1 - 2825.0 / 27648.0, e3 = b3 - 18575.0 / 48384.0,
+                 e4 = b4 - 13525.0 / 55296.0, e5 = -277.0 / 14336.0, e6 = b6 - 1.0 / 4.0;
+}  // namespace ck
+
+// ---------------------------------------------------------------------------
+// node loads
+// ---------------------------------------------------------------------------
+template <typename T>
+struct V4 {
+    T x, y, z, w;
+};
+
+__device__ __forceinline__ V4<float> ld4(const float *__restrict__ p, int64_t i)
+{
+    float4 v = reinterpret_cast<const float4 *>(p)[i];
+    return {v.x, v.y, v.z, v.w};
+}
+
+__device__ __forceinline__ V4<double> ld4(const double *__restrict__ p, int64_t i)
+{
+    const double2 *q = reinterpret_cast<const double2 *>(p) + 2 * i;
+    double2 a = q[0], b = q[1];
+    return {a.x, a.y, b.x, b.y};
+}
+
+// value and grid-unit partial derivatives of one trilinear component
+template <typename T>
+__device__ __forceinline__ void lerp_tree(T v000, T v100, T v010, T v110, T v001, T v101, T v011,
+                                          T v111, T tx, T ty, T tz, T &val, T &dx, T &dy, T &dz)
+{
+    const T d00 = v100 - v000, d10 = v110 - v010, d01 = v101 - v001, d11 = v111 - v011;
+    const T a00 = fma(tx, d00, v000), a10 = fma(tx, d10, v010);
+    const T a01 = fma(tx, d01, v001), a11 = fma(tx, d11, v011);
+    const T e0 = a10 - a00, e1 = a11 - a01;
+    const T b0 = fma(ty, e0, a00), b1 = fma(ty, e1, a01);
+    const T g0 = fma(ty, d10 - d00, d00), g1 = fma(ty, d11 - d01, d01);
+    dz = b1 - b0;
+    val = fma(tz, dz, b0);
+    dx = fma(tz, g1 - g0, g0);
+    dy = fma(tz, e1 - e0, e0);
+}
+
+template <typename T>
+__device__ __forceinline__ T lerp_val(T v000, T v100, T v010, T v110, T v001, T v101, T v011, T v111,
+                                      T tx, T ty, T tz)
+{
+    const T a00 = fma(tx, v100 - v000, v000), a10 = fma(tx, v110 - v010, v010);
+    const T a01 = fma(tx, v101 - v001, v001), a11 = fma(tx, v111 - v011, v011);
+    const T b0 = fma(ty, a10 - a00, a00), b1 = fma(ty, a11 - a01, a01);
+    return fma(tz, b1 - b0, b0);
+}
+
+// Cell of a point given in grid units as integer reference ib plus offset q:
+// c = clamp(floor(ib + q), 0, n-2), fraction t = ib + q - c (not clamped, so
+// points slightly outside the box extrapolate the boundary cell linearly).
+template <typename T>
+__device__ __forceinline__ void cell_of(int ib, T q, int n, int &c, T &t)
+{
+    const T fl = floor(q);
+    int ci = ib + (int)fl;
+    ci = ci < 0 ? 0 : ci;
+    ci = ci > n - 2 ? n - 2 : ci;
+    c = ci;
+    t = q - (T)(ci - ib);
+}
+
+// Field value u (Bhat as interpolated) and physical gradient rows
+// G[j][i] = d u_i / d x_j at a point; optionally |B| (PAPER: interpolated node
+// magnitudes; INTERP_NORMALIZE: magnitude of the interpolated B).
+template <typename T, typename S, int MODE, bool MAG>
+__device__ __forceinline__ void field_at(const S *__restrict__ nodes, const Geom &g, const int ib[3],
+                                         const T q[3], T u[3], T G[3][3], T &mag)
+{
+    int c[3];
+    T t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) cell_of(ib[d], q[d], g.n[d], c[d], t[d]);
+    const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
+    const int64_t b = (int64_t)c[2] * sz + (int64_t)c[1] * sy + c[0];
+    const V4<S> n000 = ld4(nodes, b), n100 = ld4(nodes, b + 1);
+    const V4<S> n010 = ld4(nodes, b + sy), n110 = ld4(nodes, b + sy + 1);
+    const V4<S> n001 = ld4(nodes, b + sz), n101 = ld4(nodes, b + sz + 1);
+    const V4<S> n011 = ld4(nodes, b + sz + sy), n111 = ld4(nodes, b + sz + sy + 1);
+    T val[3], dx[3], dy[3], dz[3];
+#define QSQ_COMP(F, k)                                                                              \
+    lerp_tree<T>((T)n000.F, (T)n100.F, (T)n010.F, (T)n110.F, (T)n001.F, (T)n101.F, (T)n011.F,       \
+                 (T)n111.F, t[0], t[1], t[2], val[k], dx[k], dy[k], dz[k])
+    QSQ_COMP(x, 0);
+    QSQ_COMP(y, 1);
+    QSQ_COMP(z, 2);
+#undef QSQ_COMP
+    const T ihx = (T)g.ih[0], ihy = (T)g.ih[1], ihz = (T)g.ih[2];
+    if (MODE == QSQ_INTERP_PAPER) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            u[i] = val[i];
+            G[0][i] = dx[i] * ihx;
+            G[1][i] = dy[i] * ihy;
+            G[2][i] = dz[i] * ihz;
+        }
+        if (MAG)
+            mag = lerp_val<T>((T)n000.w, (T)n100.w, (T)n010.w, (T)n110.w, (T)n001.w, (T)n101.w,
+                              (T)n011.w, (T)n111.w, t[0], t[1], t[2]);
+    } else {
+        // u = B/|B|, grad u = (I - u u^T) grad B / |B|
+        const T bb = val[0] * val[0] + val[1] * val[1] + val[2] * val[2];
+        const T bn = sqrt(bb);
+        const T inv = bn > (T)1e-300 ? (T)1 / bn : (T)0;
+        T Gb[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            u[i] = val[i] * inv;
+            Gb[0][i] = dx[i] * ihx;
+            Gb[1][i] = dy[i] * ihy;
+            Gb[2][i] = dz[i] * ihz;
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const T ug = u[0] * Gb[j][0] + u[1] * Gb[j][1] + u[2] * Gb[j][2];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) G[j][i] = (Gb[j][i] - u[i] * ug) * inv;
+        }
+        if (MAG) mag = bn;
+    }
+}
+
+// Right-hand side f(y) = sigma * (u, J dx1, J dx2), J_ij = d u_i / d x_j
+// (eq. 1 and eq. 5).  Returns |u|^2 for the null test.
+template <typename T, typename S, int MODE>
+__device__ __forceinline__ T rhs(const S *__restrict__ nodes, const Geom &g, const int ib[3],
+                                 const T q[3], T sigma, const T d1[3], const T d2[3], T kx[3],
+                                 T k1[3], T k2[3])
+{
+    T u[3], G[3][3], mag;
+    field_at<T, S, MODE, false>(nodes, g, ib, q, u, G, mag);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        kx[i] = sigma * u[i];
+        k1[i] = sigma * (G[0][i] * d1[0] + G[1][i] * d1[1] + G[2][i] * d1[2]);
+        k2[i] = sigma * (G[0][i] * d2[0] + G[1][i] * d2[1] + G[2][i] * d2[2]);
+    }
+    return u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+}
+
+// FP64 evaluation at a physical point (landing, assembly, seed frame)
+template <typename S, int MODE, bool MAG>
+__device__ __forceinline__ void field_at_x(const S *__restrict__ nodes, const Geom &g, const double x[3],
+                                           double u[3], double G[3][3], double &mag)
+{
+    int ib[3];
+    double q[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double s = (x[d] - g.o[d]) * g.ih[d];
+        s = fmin(fmax(s, -1e9), 1e9);
+        const double fl = floor(s);
+        ib[d] = (int)fl;
+        q[d] = s - fl;
+    }
+    field_at<double, S, MODE, MAG>(nodes, g, ib, q, u, G, mag);
+}
+
+__device__ __forceinline__ bool outside_box(const Geom &g, double x0, double x1, double x2)
+{
+    return x0 < g.lo[0] || x0 > g.hi[0] || x1 < g.lo[1] || x1 > g.hi[1] || x2 < g.lo[2] || x2 > g.hi[2];
+}
+
+// orthonormal (a, b) completing the unit vector n, branch-free
+// (Duff, Burgess, Christensen, Hery, Kensler, Liani, Villemin 2017, JCGT 6(1))
+__device__ __forceinline__ void frame_of(const double n[3], double a[3], double b[3])
+{
+    const double sg = copysign(1.0, n[2]);
+    const double p = -1.0 / (sg + n[2]);
+    const double q = n[0] * n[1] * p;
+    a[0] = 1.0 + sg * n[0] * n[0] * p;
+    a[1] = sg * q;
+    a[2] = -sg * n[0];
+    b[0] = q;
+    b[1] = sg + n[1] * n[1] * p;
+    b[2] = -n[1];
+}
+
+// ---------------------------------------------------------------------------
+// end records
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void put_rec(const Records &r, int64_t i, const double y[9], double s,
+                                        double h, int status, int attempts)
+{
+    const int64_t P = 2 * r.cap;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) r.y[k * P + i] = y[k];
+    r.s[i] = s;
+    r.h[i] = h;
+    r.status[i] = status;
+    r.attempts[i] = attempts;
+}
+
+__device__ __forceinline__ void get_rec(const Records &r, int64_t i, double y[9], double &s, double &h)
+{
+    const int64_t P = 2 * r.cap;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) y[k] = r.y[k * P + i];
+    s = r.s[i];
+    h = r.h[i];
+}
+
+__device__ __forceinline__ int64_t seed_count(const TraceJob &j)
+{
+    return j.n_dev ? *j.n_dev : j.n_host;
+}
+
+// ---------------------------------------------------------------------------
+// k_trace: persistent stepping kernel
+// ---------------------------------------------------------------------------
+template <typename T, typename S, int MODE>
+__global__ void __launch_bounds__(256) k_trace(TraceJob job)
+{
+    const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
+    const Geom &g = job.g;
+    const StepOpts &o = job.o;
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t n = seed_count(job);
+    const int64_t total = 2 * n;
+
+    // lane state
+    double X[3] = {0, 0, 0}, s = 0.0;
+    T D1[3] = {0, 0, 0}, D2[3] = {0, 0, 0};
+    T h = 0, sigma = 1;
+    int attempts = 0;
+    int64_t rec = 0;
+    bool active = false, done = false, have_k1 = false;
+    T Kx[6][3], K1[6][3], K2[6][3];
+
+    const T rtol = (T)o.rtol, atol = (T)o.atol, hmax = (T)o.h_max;
+    const T ih[3] = {(T)g.ih[0], (T)g.ih[1], (T)g.ih[2]};
+    unsigned long long c_att = 0, c_ev = 0, c_act = 0, c_land = 0;   // work counters
+
+    for (;;) {
+        // ---- refill idle lanes from the work counter (one atomic per wave)
+        const uint64_t need = __ballot(!active && !done);
+        if (need) {
+            const int leader = __ffsll((unsigned long long)need) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(job.counter, (unsigned long long)__popcll(need));
+            base = __shfl(base, leader);
+            if (!active && !done) {
+                const int64_t item = (int64_t)base + __popcll(need & ((1ull << lane) - 1ull));
+                if (item >= total) {
+                    done = true;
+                } else {
+                    const int dir = item >= n ? 1 : 0;
+                    const int64_t seed = dir ? item - n : item;
+                    rec = dir * job.rec.cap + seed;
+                    sigma = dir ? (T)-1 : (T)1;
+                    const double x0[3] = {job.seeds[seed], job.seeds[job.seed_stride + seed],
+                                          job.seeds[2 * job.seed_stride + seed]};
+                    double y0[9] = {x0[0], x0[1], x0[2], 0, 0, 0, 0, 0, 0};
+                    if (outside_box(g, x0[0], x0[1], x0[2])) {
+                        put_rec(job.rec, rec, y0, 0.0, 0.0, QSQ_END_SEED_OUTSIDE, 0);
+                    } else {
+                        double u[3], G[3][3], mag;
+                        field_at_x<S, MODE, false>(nodes, g, x0, u, G, mag);
+                        const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                        if (un < 1e-6) {
+                            put_rec(job.rec, rec, y0, 0.0, 0.0, QSQ_END_NULL, 0);
+                        } else {
+                            const double nn[3] = {u[0] / un, u[1] / un, u[2] / un};
+                            double a[3], b[3];
+                            frame_of(nn, a, b);   // eq. (9)
+                            for (int k = 0; k < 3; ++k) {
+                                y0[3 + k] = a[k];
+                                y0[6 + k] = b[k];
+                            }
+                            // a seed on a face whose (signed) field points out of the
+                            // box ends there: zero length, lowest such face
+                            const double sg = dir ? -1.0 : 1.0;
+                            int face = -1;
+                            for (int f = 0; f < 6 && face < 0; ++f) {
+                                const int d = f >> 1;
+                                const bool on = (f & 1) ? x0[d] == g.hi[d] : x0[d] == g.lo[d];
+                                const double out = (f & 1) ? sg * nn[d] : -sg * nn[d];
+                                if (on && out > 0.0) face = f;
+                            }
+                            if (face >= 0) {
+                                put_rec(job.rec, rec, y0, 0.0, 0.0, face, 0);
+                            } else {
+                                X[0] = x0[0];
+                                X[1] = x0[1];
+                                X[2] = x0[2];
+                                for (int k = 0; k < 3; ++k) {
+                                    D1[k] = (T)a[k];
+                                    D2[k] = (T)b[k];
+                                }
+                                s = 0.0;
+                                h = (T)o.h_init;
+                                attempts = 0;
+                                have_k1 = false;
+                                active = true;
+                                ++c_act;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        if (__ballot(!done) == 0) break;
+        if (!active) continue;
+
+        // ---- one step attempt (oracle order: step cap, null, trial, accept/reject, exit)
+        int stop = -1;
+        if (attempts >= o.max_steps) stop = QSQ_END_MAX_STEPS;
+
+        int ib[3];
+        T fb[3];
+        if (stop < 0) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double xg = (X[d] - g.o[d]) * g.ih[d];
+                const double fl = floor(xg);
+                ib[d] = (int)fl;
+                fb[d] = (T)(xg - fl);
+            }
+            if (!have_k1) {
+                const T un2 = rhs<T, S, MODE>(nodes, g, ib, fb, sigma, D1, D2, Kx[0], K1[0], K2[0]);
+                ++c_ev;
+                if (!(un2 >= (T)1e-12)) stop = QSQ_END_NULL;
+                have_k1 = true;
+            }
+        }
+        if (stop < 0) {
+            T hs = h < hmax ? h : hmax;
+            bool last = false;
+            if (o.max_length > 0.0 && (double)hs >= o.max_length - s) {
+                hs = (T)(o.max_length - s);
+                last = true;
+            }
+            // stages 2..6
+#define QSQ_STAGE(ST, ...)                                                                          \
+    {                                                                                               \
+        const T c_[] = {__VA_ARGS__};                                                               \
+        T q[3], d1[3], d2[3];                                                                       \
+        _Pragma("unroll") for (int i = 0; i < 3; ++i)                                               \
+        {                                                                                           \
+            T ax = 0, a1 = 0, a2 = 0;                                                               \
+            _Pragma("unroll") for (int j = 0; j < ST; ++j)                                          \
+            {                                                                                       \
+                ax = fma(c_[j], Kx[j][i], ax);                                                      \
+                a1 = fma(c_[j], K1[j][i], a1);                                                      \
+                a2 = fma(c_[j], K2[j][i], a2);                                                      \
+            }                                                                                       \
+            q[i] = fma(hs * ax, ih[i], fb[i]);                                                      \
+            d1[i] = fma(hs, a1, D1[i]);                                                             \
+            d2[i] = fma(hs, a2, D2[i]);                                                             \
+        }                                                                                           \
+        rhs<T, S, MODE>(nodes, g, ib, q, sigma, d1, d2, Kx[ST], K1[ST], K2[ST]);                    \
+    }
+            QSQ_STAGE(1, (T)ck::a21)
+            QSQ_STAGE(2, (T)ck::a31, (T)ck::a32)
+            QSQ_STAGE(3, (T)ck::a41, (T)ck::a42, (T)ck::a43)
+            QSQ_STAGE(4, (T)ck::a51, (T)ck::a52, (T)ck::a53, (T)ck::a54)
+            QSQ_STAGE(5, (T)ck::a61, (T)ck::a62, (T)ck::a63, (T)ck::a64, (T)ck::a65)
+#undef QSQ_STAGE
+            // 5th-order solution (propagated) and the error estimate y5 - y4
+            double Xn[3];
+            T D1n[3], D2n[3];
+            T err = 0;
+            bool finite = true;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const T bx = (T)ck::b1 * Kx[0][i] + (T)ck::b3 * Kx[2][i] + (T)ck::b4 * Kx[3][i] + (T)ck::b6 * Kx[5][i];
+                const T b1 = (T)ck::b1 * K1[0][i] + (T)ck::b3 * K1[2][i] + (T)ck::b4 * K1[3][i] + (T)ck::b6 * K1[5][i];
+                const T b2 = (T)ck::b1 * K2[0][i] + (T)ck::b3 * K2[2][i] + (T)ck::b4 * K2[3][i] + (T)ck::b6 * K2[5][i];
+                const T ex = (T)ck::e1 * Kx[0][i] + (T)ck::e3 * Kx[2][i] + (T)ck::e4 * Kx[3][i] + (T)ck::e5 * Kx[4][i] + (T)ck::e6 * Kx[5][i];
+                const T e1 = (T)ck::e1 * K1[0][i] + (T)ck::e3 * K1[2][i] + (T)ck::e4 * K1[3][i] + (T)ck::e5 * K1[4][i] + (T)ck::e6 * K1[5][i];
+                const T e2 = (T)ck::e1 * K2[0][i] + (T)ck::e3 * K2[2][i] + (T)ck::e4 * K2[3][i] + (T)ck::e5 * K2[4][i] + (T)ck::e6 * K2[5][i];
+                Xn[i] = X[i] + (double)(hs * bx);
+                D1n[i] = fma(hs, b1, D1[i]);
+                D2n[i] = fma(hs, b2, D2[i]);
+                const T xo = (T)X[i], xn = (T)Xn[i];
+                const T sx = atol + rtol * fmax(fabs(xo), fabs(xn));
+                const T s1 = atol + rtol * fmax(fabs(D1[i]), fabs(D1n[i]));
+                const T s2 = atol + rtol * fmax(fabs(D2[i]), fabs(D2n[i]));
+                err = fmax(err, fabs(hs * ex) / sx);
+                err = fmax(err, fabs(hs * e1) / s1);
+                err = fmax(err, fabs(hs * e2) / s2);
+                finite = finite && isfinite(xn) && isfinite(D1n[i]) && isfinite(D2n[i]) &&
+                         isfinite(ex) && isfinite(e1) && isfinite(e2);
+            }
+            ++attempts;
+            ++c_att;
+            c_ev += 5;
+            if (!finite) {
+                stop = QSQ_END_NONFINITE;
+            } else if (err > (T)1) {
+                // reject: shrink, keep k1 (y is unchanged)
+                const T f = (T)0.9 * (T)exp2((T)-0.25 * (T)log2(err));
+                h = hs * (f > (T)0.2 ? f : (T)0.2);
+                if ((double)h < o.hmin) stop = QSQ_END_UNDERFLOW;
+            } else if (outside_box(g, Xn[0], Xn[1], Xn[2])) {
+                // accepted trial step leaves the box: hand over to FP64 landing
+                const double y[9] = {X[0], X[1], X[2], (double)D1[0], (double)D1[1], (double)D1[2],
+                                     (double)D2[0], (double)D2[1], (double)D2[2]};
+                put_rec(job.rec, rec, y, s, (double)hs, kPendingLand, attempts);
+                active = false;
+                ++c_land;
+            } else {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    X[i] = Xn[i];
+                    D1[i] = D1n[i];
+                    D2[i] = D2n[i];
+                }
+                have_k1 = false;
+                if (last) {
+                    s = o.max_length;
+                    stop = QSQ_END_MAX_LENGTH;
+                } else {
+                    s += (double)hs;
+                    const T f = err > (T)0 ? (T)0.9 * (T)exp2((T)-0.2 * (T)log2(err)) : (T)5;
+                    h = hs * (f < (T)5 ? f : (T)5);
+                }
+            }
+        }
+        if (stop >= 0) {
+            const double y[9] = {X[0], X[1], X[2], (double)D1[0], (double)D1[1], (double)D1[2],
+                                 (double)D2[0], (double)D2[1], (double)D2[2]};
+            put_rec(job.rec, rec, y, s, 0.0, stop, attempts);
+            active = false;
+        }
+    }
+    if (job.work) {
+        // wave-level sums, one atomic per counter per wave
+#pragma unroll
+        for (int o2 = 32; o2 >= 1; o2 >>= 1) {
+            c_att += __shfl_xor(c_att, o2);
+            c_ev += __shfl_xor(c_ev, o2);
+            c_act += __shfl_xor(c_act, o2);
+            c_land += __shfl_xor(c_land, o2);
+        }
+        if (lane == 0) {
+            atomicAdd(&job.work[0], c_att);
+            atomicAdd(&job.work[1], c_ev);
+            atomicAdd(&job.work[2], c_act);
+            atomicAdd(&job.work[3], c_land);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 Cash-Karp step used by the landing pass (5th-order end only)
+// ---------------------------------------------------------------------------
+template <typename S, int MODE>
+__device__ void ck54_fp64(const S *__restrict__ nodes, const Geom &g, double sigma, const double y[9],
+                          double hs, double yo[9])
+{
+    double K[6][9];
+    const double A[6][5] = {{0, 0, 0, 0, 0},
+                            {ck::a21, 0, 0, 0, 0},
+                            {ck::a31, ck::a32, 0, 0, 0},
+                            {ck::a41, ck::a42, ck::a43, 0, 0},
+                            {ck::a51, ck::a52, ck::a53, ck::a54, 0},
+                            {ck::a61, ck::a62, ck::a63, ck::a64, ck::a65}};
+    int ib[3];
+    double fb[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double xg = (y[d] - g.o[d]) * g.ih[d];
+        const double fl = floor(fmin(fmax(xg, -1e9), 1e9));
+        ib[d] = (int)fl;
+        fb[d] = xg - fl;
+    }
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        double q[3], d1[3], d2[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            double ax = 0, a1 = 0, a2 = 0;
+#pragma unroll
+            for (int j = 0; j < st; ++j) {
+                ax = fma(A[st][j], K[j][i], ax);
+                a1 = fma(A[st][j], K[j][3 + i], a1);
+                a2 = fma(A[st][j], K[j][6 + i], a2);
+            }
+            q[i] = fma(hs * ax, g.ih[i], fb[i]);
+            d1[i] = fma(hs, a1, y[3 + i]);
+            d2[i] = fma(hs, a2, y[6 + i]);
+        }
+        double kx[3], k1[3], k2[3];
+        rhs<double, S, MODE>(nodes, g, ib, q, sigma, d1, d2, kx, k1, k2);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            K[st][i] = kx[i];
+            K[st][3 + i] = k1[i];
+            K[st][6 + i] = k2[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        yo[i] = y[i] + hs * (ck::b1 * K[0][i] + ck::b3 * K[2][i] + ck::b4 * K[3][i] + ck::b6 * K[5][i]);
+}
+
+template <typename S, int MODE>
+__device__ double face_gap(const S *nodes, const Geom &g, double sigma, const double y[9], double hs,
+                           int f, double yo[9])
+{
+    if (hs == 0.0) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) yo[i] = y[i];
+    } else {
+        ck54_fp64<S, MODE>(nodes, g, sigma, y, hs, yo);
+    }
+    const int d = f >> 1;
+    return (f & 1) ? yo[d] - g.hi[d] : g.lo[d] - yo[d];
+}
+
+// ---------------------------------------------------------------------------
+// k_land: FP64 landing of pending half-lines on the first face crossed
+// ---------------------------------------------------------------------------
+template <typename S, int MODE>
+__global__ void __launch_bounds__(256) k_land(TraceJob job)
+{
+    const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
+    const Geom &g = job.g;
+    const int64_t n = seed_count(job);
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < 2 * n;
+         it += (int64_t)gridDim.x * blockDim.x) {
+        const int dir = it >= n ? 1 : 0;
+        const int64_t r = dir * job.rec.cap + (dir ? it - n : it);
+        if (job.rec.status[r] != kPendingLand) continue;
+        const double sigma = dir ? -1.0 : 1.0;
+        double y[9], s, hs, y5[9];
+        get_rec(job.rec, r, y, s, hs);
+        ck54_fp64<S, MODE>(nodes, g, sigma, y, hs, y5);
+        double best = INFINITY;
+        int face = -1;
+        double gmax = -INFINITY;
+        int fmax_ = 0;
+        for (int f = 0; f < 6; ++f) {
+            const int d = f >> 1;
+            const double gend = (f & 1) ? y5[d] - g.hi[d] : g.lo[d] - y5[d];
+            if (gend > gmax) {
+                gmax = gend;
+                fmax_ = f;
+            }
+            if (!(gend > 0.0)) continue;
+            // Illinois regula falsi for the step length ending on face f
+            double yo[9];
+            double a = 0.0, b = hs;
+            double ga = face_gap<S, MODE>(nodes, g, sigma, y, a, f, yo);
+            double hf;
+            if (ga >= 0.0) {
+                hf = 0.0;
+            } else {
+                double gb = gend;
+                int side = 0;
+                hf = -1.0;
+                for (int k = 0; k < 200; ++k) {
+                    const double c = (a * gb - b * ga) / (gb - ga);
+                    const double gc = face_gap<S, MODE>(nodes, g, sigma, y, c, f, yo);
+                    if (fabs(gc) <= job.o.gtol) {
+                        hf = c;
+                        break;
+                    }
+                    if (gc > 0.0) {
+                        b = c;
+                        gb = gc;
+                        if (side == 1) ga *= 0.5;
+                        side = 1;
+                    } else {
+                        a = c;
+                        ga = gc;
+                        if (side == -1) gb *= 0.5;
+                        side = -1;
+                    }
+                    if (b - a <= 1e-15 * hs) break;
+                }
+                if (hf < 0.0) hf = ga > -gb ? a : b;
+            }
+            if (hf < best) {
+                best = hf;
+                face = f;
+            }
+        }
+        double yl[9];
+        if (face < 0) {
+            // the FP64 re-solve ends inside (the trial end was within rounding of a
+            // face): land on the nearest face at the full step
+            face = fmax_;
+            best = hs;
+            for (int i = 0; i < 9; ++i) yl[i] = y5[i];
+        } else if (best > 0.0) {
+            ck54_fp64<S, MODE>(nodes, g, sigma, y, best, yl);
+        } else {
+            for (int i = 0; i < 9; ++i) yl[i] = y[i];
+        }
+        const int d = face >> 1;
+        yl[d] = (face & 1) ? g.hi[d] : g.lo[d];
+        const int att = job.rec.attempts[r];
+        put_rec(job.rec, r, yl, s + best, 0.0, face, att);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_assemble: FP64 Q and length per seed (eq. 10-11)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double dot3(const double *a, const double *b)
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+__device__ __forceinline__ double cross_len(const double *a, const double *b)
+{
+    const double c0 = a[1] * b[2] - a[2] * b[1];
+    const double c1 = a[2] * b[0] - a[0] * b[2];
+    const double c2 = a[0] * b[1] - a[1] * b[0];
+    return sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+}
+
+// a_F^2 b_B^2 + a_B^2 b_F^2 - 2 (a_B . b_B)(a_F . b_F)
+__device__ __forceinline__ double q_bracket(const double *aF, const double *bF, const double *aB,
+                                            const double *bB)
+{
+    return dot3(aF, aF) * dot3(bB, bB) + dot3(aB, aB) * dot3(bF, bF) - 2.0 * dot3(aB, bB) * dot3(aF, bF);
+}
+
+template <typename S, int MODE>
+__global__ void __launch_bounds__(256) k_assemble(TraceJob job)
+{
+    const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
+    const Geom &g = job.g;
+    const int64_t n = seed_count(job);
+    const int64_t P = 2 * job.rec.cap;
+    const int64_t os = job.out_stride;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t rF = i, rB = job.rec.cap + i;
+        const int stF = job.rec.status[rF], stB = job.rec.status[rB];
+        double yF[9], yB[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            yF[k] = job.rec.y[k * P + rF];
+            yB[k] = job.rec.y[k * P + rB];
+        }
+        const double sF = job.rec.s[rF], sB = job.rec.s[rB];
+        const bool open = !(stF == QSQ_END_ZLO && stB == QSQ_END_ZLO);
+        const int word = (stF & 0xff) | ((stB & 0xff) << 8) | (open ? QSQ_STATUS_OPEN : 0);
+        job.status[i] = word;
+        if (job.fll) job.fll[i] = sF + sB;
+        if (job.fp_fwd)
+            for (int k = 0; k < 3; ++k) job.fp_fwd[k * os + i] = yF[k];
+        if (job.fp_bwd)
+            for (int k = 0; k < 3; ++k) job.fp_bwd[k * os + i] = yB[k];
+        if (job.steps) {
+            job.steps[i] = job.rec.attempts[rF];
+            job.steps[os + i] = job.rec.attempts[rB];
+        }
+        double qp = NAN, qd = NAN, qf = NAN;
+        const bool defF = stF >= QSQ_END_XLO && stF <= QSQ_END_MAX_STEPS;
+        const bool defB = stB >= QSQ_END_XLO && stB <= QSQ_END_MAX_STEPS;
+        const bool skip = (job.o.flags & QSQ_FLAG_SKIP_OPEN) && open;
+        if (defF && defB && !skip) {
+            const double x0[3] = {job.seeds[i], job.seeds[job.seed_stride + i],
+                                  job.seeds[2 * job.seed_stride + i]};
+            double G[3][3], uF[3], uB[3], u0[3], BF, BB, B0;
+            field_at_x<S, MODE, true>(nodes, g, yF, uF, G, BF);
+            field_at_x<S, MODE, true>(nodes, g, yB, uB, G, BB);
+            field_at_x<S, MODE, true>(nodes, g, x0, u0, G, B0);
+            const double vF[3] = {uF[0], uF[1], uF[2]}, vB[3] = {uB[0], uB[1], uB[2]};
+            const double nF = sqrt(dot3(uF, uF)), nB = sqrt(dot3(uB, uB));
+            for (int k = 0; k < 3; ++k) {
+                uF[k] /= nF;
+                uB[k] /= nB;
+            }
+            // perpendicular parts of the deviations at both ends (Sect. 3.5)
+            double aF[3], bF[3], aB[3], bB[3];
+            const double pa = dot3(uF, yF + 3), pb = dot3(uF, yF + 6);
+            const double qa = dot3(uB, yB + 3), qb = dot3(uB, yB + 6);
+            for (int k = 0; k < 3; ++k) {
+                aF[k] = yF[3 + k] - uF[k] * pa;
+                bF[k] = yF[6 + k] - uF[k] * pb;
+                aB[k] = yB[3 + k] - uB[k] * qa;
+                bB[k] = yB[6 + k] - uB[k] * qb;
+            }
+            const double br = q_bracket(aF, bF, aB, bB);
+            qp = BF * BB / (B0 * B0) * br;                                  // eq. (11)
+            qd = br / (cross_len(aF, bF) * cross_len(aB, bB));
+            if (stF <= QSQ_END_ZHI && stB <= QSQ_END_ZHI) {
+                // slide the deviations along the line into the exit-face planes
+                const int dF = stF >> 1, dB = stB >> 1;
+                const double rF1 = yF[3 + dF] / vF[dF], rF2 = yF[6 + dF] / vF[dF];
+                const double rB1 = yB[3 + dB] / vB[dB], rB2 = yB[6 + dB] / vB[dB];
+                double pF1[3], pF2[3], pB1[3], pB2[3];
+                for (int k = 0; k < 3; ++k) {
+                    pF1[k] = yF[3 + k] - vF[k] * rF1;
+                    pF2[k] = yF[6 + k] - vF[k] * rF2;
+                    pB1[k] = yB[3 + k] - vB[k] * rB1;
+                    pB2[k] = yB[6 + k] - vB[k] * rB2;
+                }
+                qf = q_bracket(pF1, pF2, pB1, pB2) / (cross_len(pF1, pF2) * cross_len(pB1, pB2));
+            }
+        }
+        if (job.q_perp) job.q_perp[i] = qp;
+        if (job.q_det) job.q_det[i] = qd;
+        if (job.q_fp) job.q_fp[i] = qf;
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+uint64_t records_bytes(int64_t cap)
+{
+    const uint64_t P = 2 * (uint64_t)cap;
+    return P * (11 * sizeof(double) + 2 * sizeof(int32_t));
+}
+
+void carve_records(void *scratch, int64_t cap, Records *rec, unsigned long long **counter)
+{
+    char *p = static_cast<char *>(scratch);
+    *counter = reinterpret_cast<unsigned long long *>(p);
+    p += 256;
+    const uint64_t P = 2 * (uint64_t)cap;
+    rec->y = reinterpret_cast<double *>(p);
+    p += 9 * P * sizeof(double);
+    rec->s = reinterpret_cast<double *>(p);
+    p += P * sizeof(double);
+    rec->h = reinterpret_cast<double *>(p);
+    p += P * sizeof(double);
+    rec->status = reinterpret_cast<int32_t *>(p);
+    p += P * sizeof(int32_t);
+    rec->attempts = reinterpret_cast<int32_t *>(p);
+    rec->cap = cap;
+}
+
+int device_cu_count()
+{
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cus[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        cus[dev] = v;
+    }
+    return cus[dev];
+}
+
+template <typename T, typename S, int MODE>
+static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
+{
+    const int cus = device_cu_count();
+    const int64_t n_max = job.n_dev ? job.rec.cap : job.n_host;
+    if (n_max <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, job.counter);
+    int64_t want = (2 * n_max + 255) / 256;
+    int blocks = (int)(want < (int64_t)cus * 8 ? want : (int64_t)cus * 8);
+    const bool prof = profiling();
+    void *tok = nullptr;
+    if (prof) prof_begin(kProfStep, st, &tok);
+    hipLaunchKernelGGL((k_trace<T, S, MODE>), dim3(blocks), dim3(256), 0, st, job);
+    if (prof) prof_end(tok, st);
+    int64_t lb = (2 * n_max + 255) / 256;
+    int lblocks = (int)(lb < (int64_t)cus * 16 ? lb : (int64_t)cus * 16);
+    if (prof) prof_begin(kProfLand, st, &tok);
+    hipLaunchKernelGGL((k_land<S, MODE>), dim3(lblocks), dim3(256), 0, st, job);
+    if (prof) prof_end(tok, st);
+    int64_t ab = (n_max + 255) / 256;
+    int ablocks = (int)(ab < (int64_t)cus * 16 ? ab : (int64_t)cus * 16);
+    if (prof) prof_begin(kProfAssemble, st, &tok);
+    hipLaunchKernelGGL((k_assemble<S, MODE>), dim3(ablocks), dim3(256), 0, st, job);
+    if (prof) prof_end(tok, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace(const TraceJob &job, int step_dtype, hipStream_t st)
+{
+    const bool f32 = step_dtype == QSQ_F32;
+    const bool paper = job.mode == QSQ_INTERP_PAPER;
+    if (job.storage == QSQ_F32) {
+        if (f32) return paper ? launch_typed<float, float, QSQ_INTERP_PAPER>(job, st)
+                              : launch_typed<float, float, QSQ_INTERP_NORMALIZE>(job, st);
+        return paper ? launch_typed<double, float, QSQ_INTERP_PAPER>(job, st)
+                     : launch_typed<double, float, QSQ_INTERP_NORMALIZE>(job, st);
+    }
+    if (f32) return paper ? launch_typed<float, double, QSQ_INTERP_PAPER>(job, st)
+                          : launch_typed<float, double, QSQ_INTERP_NORMALIZE>(job, st);
+    return paper ? launch_typed<double, double, QSQ_INTERP_PAPER>(job, st)
+                 : launch_typed<double, double, QSQ_INTERP_NORMALIZE>(job, st);
+}
+
+}  // namespace qsq

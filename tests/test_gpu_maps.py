@@ -1,0 +1,183 @@
+"""GPU parity of the map-level path (QSL Squasher Sect. 3.6) against the oracle:
+Sobel FLEDGE, Hilbert ordering, FLL-jump refinement and the array converter,
+on a small map and on the full photospheric map the benchmark times."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import parity, summary, torch_dev, worst
+
+pytestmark = pytest.mark.gpu
+
+
+# ---------------------------------------------------------------------------
+# FLEDGE and Hilbert (bit-exact / FP32 rounding)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(1, 1), (3, 700), (257, 129), (33, 17, 9)])
+def test_fledge_vs_oracle(oracle_mod, shape):
+    import paper_1609_00724_amd as q
+    torch, dev = torch_dev()
+    f = synth.rng(8).normal(size=shape).astype(np.float32)
+    g = q.fledge(torch.from_numpy(f).to(dev)).cpu().numpy()
+    o = oracle_mod.sobel_magnitude(f.astype(np.float64))
+    assert np.allclose(g, o, rtol=1e-5, atol=1e-5)
+
+
+@pytest.mark.parametrize("L", [1, 2, 5, 10, 12])
+def test_hilbert_vs_oracle_all(oracle_mod, L):
+    import paper_1609_00724_amd as q
+    torch, dev = torch_dev()
+    d = np.arange(4 ** L, dtype=np.int64)
+    x, y = q.hilbert2_d2xy(L, torch.from_numpy(d).to(dev))
+    xo, yo = oracle_mod.hilbert2_d2xy(L, d)
+    assert np.array_equal(x.cpu().numpy(), xo) and np.array_equal(y.cpu().numpy(), yo)
+    dd = q.hilbert2_xy2d(L, x, y).cpu().numpy()
+    assert np.array_equal(dd, d)
+
+
+@pytest.mark.parametrize("L", [16, 24, 31])
+def test_hilbert_vs_oracle_sampled(oracle_mod, L):
+    import paper_1609_00724_amd as q
+    torch, dev = torch_dev()
+    d = synth.rng(L).integers(0, 4 ** L, size=5000, dtype=np.int64)
+    x, y = q.hilbert2_d2xy(L, torch.from_numpy(d).to(dev))
+    xo, yo = oracle_mod.hilbert2_d2xy(L, d)
+    assert np.array_equal(x.cpu().numpy().astype(np.int64) & 0xFFFFFFFF, xo)
+    assert np.array_equal(y.cpu().numpy().astype(np.int64) & 0xFFFFFFFF, yo)
+
+
+# ---------------------------------------------------------------------------
+# slice maps with refinement
+# ---------------------------------------------------------------------------
+
+CHARGES = synth.point_charges(2, 4)
+TOL = 1e-3   # stepping tolerance of the photospheric map workload
+
+
+@pytest.fixture(scope="module")
+def c2(oracle_mod):
+    import paper_1609_00724_amd as q
+    torch, dev = torch_dev()
+    w = synth.charges_c2()
+    b = w["b"]
+    fg = q.field_init(*(torch.from_numpy(c).to(dev) for c in b), w["origin"], w["spacing"], storage="f32")
+    fo = oracle_mod.Field.grid(*(c.astype(np.float64) for c in b), w["origin"], w["spacing"], store="f32")
+    return dict(w=w, fg=fg, fo=fo, h=min(w["spacing"]))
+
+
+def _run_map(c2, m, r, thr, out_level, capacity):
+    import paper_1609_00724_amd as q
+    from paper_1609_00724_amd.api import MapSpec
+    torch, dev = torch_dev()
+    spec = MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, r, out_level, thr)
+    res = q.qmap(c2["fg"], spec, capacity, rtol=TOL, atol=TOL, h_init=0.1 * c2["h"], h_max=c2["h"],
+                 step_dtype="f32")
+    torch.cuda.synchronize()
+    out = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}
+    return out
+
+
+def _positions(oracle_mod, m, r, keys):
+    plane = oracle_mod.SlicePlane(0.0, -1.0, 1.0, -1.0, 1.0)
+    blk = 4 ** r
+    base = keys % blk == blk // 2
+    pos = np.empty((keys.size, 3))
+    q = keys[base] // blk
+    ix, iy = oracle_mod.hilbert2_d2xy(m, q)
+    pos[base] = plane.centres(m, ix, iy)
+    if (~base).any():
+        pos[~base] = oracle_mod.key_positions(plane, m, r, keys[~base])
+    return pos, base
+
+
+def _check_complete(res, thr):
+    k, f = res["keys"], res["fll"]
+    assert np.all(np.diff(k) > 0)
+    open_pair = (np.diff(k) >= 2) & (np.abs(np.diff(f)) > thr)
+    assert not open_pair.any()
+
+
+def _oracle_trace(oracle_mod, c2, pts):
+    return oracle_mod.trace(c2["fo"], pts, rtol=TOL, atol=TOL, h_init=0.1 * c2["h"], h_max=c2["h"])
+
+
+def _sample_parity(oracle_mod, c2, res, idx, m, r):
+    pos, _ = _positions(oracle_mod, m, r, res["keys"][idx])
+    o = _oracle_trace(oracle_mod, c2, pos)
+    g = dict(status=res["status"][idx], q_perp=res["q_perp"][idx], fll=res["fll"][idx],
+             fp_fwd=np.zeros((idx.size, 3)), fp_bwd=np.zeros((idx.size, 3)))
+    o2 = dict(o)
+    o2["fp_fwd"] = np.zeros((idx.size, 3))
+    o2["fp_bwd"] = np.zeros((idx.size, 3))
+    p = parity(g, o2)
+    msg = summary(p) + " | worst: " + worst(p, o)
+    print(msg)
+    m_ = p["gate"]
+    assert p["status_mismatch"] <= 0.003 * idx.size + 1, msg
+    assert p["fll"][m_].max() <= 1e-4, msg
+    assert np.nanmax(p["lq"][m_]) <= 1e-3, msg
+    return o
+
+
+def test_small_map_vs_oracle(oracle_mod, c2):
+    m, r, thr = 6, 2, 0.02
+    res = _run_map(c2, m, r, thr, m + r, 4 ** (m + r))
+    n = res["count"]
+    assert res["overflow"] == 0 and n > 4 ** m
+    _check_complete(res, thr)
+    # every sample re-traced by the oracle at the same key position
+    o = _sample_parity(oracle_mod, c2, res, np.arange(n), m, r)
+    # the oracle's own refinement reaches the same sample set (up to marginal jumps)
+    plane = oracle_mod.SlicePlane(0.0, -1.0, 1.0, -1.0, 1.0)
+
+    def fn(p):
+        t = _oracle_trace(oracle_mod, c2, p)
+        return {"fll": t["fll"], "q": t["q_perp"]}
+
+    ok, ov, _ = oracle_mod.refine_slice(plane, m, r, thr, fn)
+    common = np.intersect1d(ok, res["keys"]).size
+    union = np.union1d(ok, res["keys"]).size
+    assert common / union > 0.995, (common, union)
+    # converter: the oracle's converter applied to the GPU's samples
+    want_q = oracle_mod.convert_to_grid(res["keys"], res["q_perp"], m, r, m + r, log_interp=True)
+    want_f = oracle_mod.convert_to_grid(res["keys"], res["fll"], m, r, m + r, log_interp=False)
+    assert np.allclose(res["q_grid"], want_q, rtol=2e-6, equal_nan=True)
+    assert np.allclose(res["fll_grid"], want_f, rtol=2e-6, atol=1e-6)
+    # FLEDGE of the base length map
+    base = res["keys"] % 16 == 8
+    ix, iy = oracle_mod.hilbert2_d2xy(m, res["keys"][base] // 16)
+    img = np.zeros((1 << m, 1 << m))
+    img[iy, ix] = res["fll"][base]
+    assert np.allclose(res["fledge"], oracle_mod.sobel_magnitude(img.astype(np.float32).astype(np.float64)),
+                       rtol=1e-5, atol=1e-5)
+
+
+def test_capacity_overflow_is_flagged(c2):
+    m, r = 5, 2
+    res = _run_map(c2, m, r, 0.0, m, 4 ** m + 10)
+    assert res["overflow"] == 1 and res["count"] == 4 ** m + 10
+    assert np.all(np.diff(res["keys"]) > 0)
+
+
+def test_full_photospheric_map_sampled(oracle_mod, c2):
+    """The benchmark's workload: 1024^2 base map with 4x (two-level) refinement;
+    oracle checks on a sample of lines, converter cells, and the whole FLEDGE."""
+    m, r, thr = 10, 2, 0.02
+    res = _run_map(c2, m, r, thr, m, 4 ** m * 4)
+    n = res["count"]
+    assert res["overflow"] == 0 and n > 4 ** m
+    _check_complete(res, thr)
+    g = synth.rng(77)
+    idx = np.sort(g.choice(n, size=1500, replace=False))
+    _sample_parity(oracle_mod, c2, res, idx, m, r)
+    cells = g.choice(4 ** m, size=300, replace=False)
+    want = oracle_mod.convert_to_grid(res["keys"], res["q_perp"], m, r, m, log_interp=True, cells=cells)
+    cx, cy = oracle_mod.hilbert2_d2xy(m, cells)
+    assert np.allclose(res["q_grid"][cy, cx], want, rtol=2e-6, equal_nan=True)
+    base = res["keys"] % 16 == 8
+    ix, iy = oracle_mod.hilbert2_d2xy(m, res["keys"][base] // 16)
+    img = np.zeros((1 << m, 1 << m))
+    img[iy, ix] = res["fll"][base]
+    assert np.allclose(res["fledge"], oracle_mod.sobel_magnitude(img.astype(np.float32).astype(np.float64)),
+                       rtol=1e-5, atol=1e-5)

@@ -1,0 +1,192 @@
+"""GPU parity of the HIP tracer (through the C-ABI) against the FP64 oracle.
+
+Gates (per line, lines whose oracle Q < 1e6 and whose exit faces agree):
+relative error of log10 Q <= 1e-3, footpoints <= 1e-5 domain units,
+field-line length <= 1e-4 relative.  Same seeds, field and tolerance on both
+sides.  QSL Squasher Sect. 3.1-3.5.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import gpu_field, gpu_trace, parity, summary, worst
+
+pytestmark = pytest.mark.gpu
+
+FP_TOL, FLL_TOL, LQ_TOL = 1e-5, 1e-4, 1e-3
+
+
+def _gate(p, o, max_mismatch_frac=0.0):
+    m = p["gate"]
+    msg = summary(p) + " | worst: " + worst(p, o)
+    print(msg)
+    assert p["status_mismatch"] <= max_mismatch_frac * m.size, msg
+    assert p["fp"][m].max() <= FP_TOL, msg
+    assert p["fll"][m].max() <= FLL_TOL, msg
+    assert np.nanmax(p["lq"][m]) <= LQ_TOL, msg
+
+
+def _oracle_grid(oracle_mod, b, origin, spacing, mode, store):
+    """The oracle on the field the GPU stores: FP32 node storage rounds the
+    prepared node values to FP32, and the oracle traces that same field."""
+    return oracle_mod.Field.grid(*(np.asarray(c, np.float64) for c in b), origin, spacing,
+                                 mode=oracle_mod.PAPER if mode == "paper" else oracle_mod.INTERP_NORMALIZE,
+                                 store=store)
+
+
+# ---------------------------------------------------------------------------
+# hyperbolic flux tube, 64^3 FP64 grid, 128^2 seeds on z = 0, FP64 stepping at 1e-8
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c1():
+    return synth.hyperbolic_c1()
+
+
+@pytest.mark.parametrize("mode", ["interp_normalize", "paper"])
+def test_c1_fp64_parity(oracle_mod, c1, mode):
+    seeds = c1["seeds"]
+    h = min(c1["spacing"])
+    kw = dict(rtol=1e-8, atol=1e-8, h_init=0.1 * h, h_max=h)
+    fg = gpu_field(c1["b"], c1["origin"], c1["spacing"], storage="f64", mode=mode)
+    g = gpu_trace(fg, seeds, step_dtype="f64", **kw)
+    fo = _oracle_grid(oracle_mod, c1["b"], c1["origin"], c1["spacing"], mode, "f64")
+    o = oracle_mod.trace(fo, seeds, **kw)
+    p = parity(g, o)
+    _gate(p, o)
+    assert p["gate"].sum() == seeds.shape[0]
+    # the top-exit lines of the configuration carry Q_fp = 2 cosh(2k)
+    top = (g["status"] & 0xFF) == 5
+    assert top.sum() == 18 * 128
+    if mode == "interp_normalize":
+        assert np.allclose(g["q_fp"][top], 2 * np.cosh(4.0), rtol=1e-6)
+    else:
+        assert np.allclose(g["q_fp"][top], 2 * np.cosh(4.0), rtol=5e-3)
+    assert np.allclose(g["q_det"], o["q_det"], rtol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# point-charge fields, FP32 node storage
+# ---------------------------------------------------------------------------
+
+CH = synth.point_charges(2, 4)
+
+
+@pytest.fixture(scope="module")
+def small_charges():
+    n = (97, 97, 49)
+    b = synth.sample_charges(CH, n, dtype=np.float32)
+    origin, spacing = synth.grid_geometry(n)
+    return dict(b=b, origin=origin, spacing=spacing, n=n)
+
+
+def _mixed_seeds(count, seed):
+    s = synth.random_seeds(seed, count)
+    s[: count // 2, 2] = 0.0            # half on the photosphere, half inside
+    return s
+
+
+@pytest.mark.parametrize("step_dtype,tol", [("f32", 1e-6), ("f32", 1e-3), ("f64", 1e-8)])
+def test_charges_parity(oracle_mod, small_charges, step_dtype, tol):
+    c = small_charges
+    seeds = _mixed_seeds(1000 + 37, 41)      # ragged: not a multiple of the wave size
+    h = min(c["spacing"])
+    kw = dict(rtol=tol, atol=tol, h_init=0.1 * h, h_max=h)
+    fg = gpu_field(c["b"], c["origin"], c["spacing"], storage="f32")
+    g = gpu_trace(fg, seeds, step_dtype=step_dtype, **kw)
+    o = oracle_mod.trace(_oracle_grid(oracle_mod, c["b"], c["origin"], c["spacing"], "paper", "f32"), seeds,
+                         **kw)
+    p = parity(g, o)
+    _gate(p, o, max_mismatch_frac=0.003)
+    assert p["gate"].mean() > 0.97
+
+
+def test_interp_normalize_fp32(oracle_mod, small_charges):
+    c = small_charges
+    seeds = _mixed_seeds(500, 5)
+    h = min(c["spacing"])
+    kw = dict(rtol=1e-6, atol=1e-6, h_init=0.1 * h, h_max=h)
+    fg = gpu_field(c["b"], c["origin"], c["spacing"], storage="f32", mode="interp_normalize")
+    g = gpu_trace(fg, seeds, step_dtype="f32", **kw)
+    o = oracle_mod.trace(_oracle_grid(oracle_mod, c["b"], c["origin"], c["spacing"], "interp_normalize", "f32"),
+                         seeds, **kw)
+    _gate(parity(g, o), o, max_mismatch_frac=0.005)
+
+
+# ---------------------------------------------------------------------------
+# stops and degenerate inputs
+# ---------------------------------------------------------------------------
+
+def test_edge_cases(oracle_mod, small_charges):
+    import paper_1609_00724_amd as q
+    c = small_charges
+    h = min(c["spacing"])
+    kw = dict(rtol=1e-6, atol=1e-6, h_init=0.1 * h, h_max=h)
+    fg = gpu_field(c["b"], c["origin"], c["spacing"], storage="f32")
+    fo = _oracle_grid(oracle_mod, c["b"], c["origin"], c["spacing"], "paper", "f32")
+    seeds = np.array([
+        [0.0, 0.0, -0.01], [1.5, 0.0, 0.5],          # outside
+        [-1.0, -1.0, 0.0], [1.0, 1.0, 1.0],          # corners
+        [1.0, 0.3, 0.4], [-1.0, 0.2, 0.7],           # side faces
+        [0.1, 0.1, 1.0], [0.2, -0.3, 0.0],           # top, bottom
+        [0.05, 0.02, 0.3],
+    ])
+    g = gpu_trace(fg, seeds, step_dtype="f32", **kw)
+    o = oracle_mod.trace(fo, seeds, **kw)
+    assert np.array_equal(g["status"], o["status"])
+    assert np.all((g["status"][:2] & 0xFF) == q._abi.END_SEED_OUTSIDE)
+    assert np.all(np.isnan(g["q_perp"][:2])) and np.all(g["fll"][:2] == 0)
+    p = parity(g, o)
+    assert p["fp"][p["gate"]].max() <= FP_TOL
+
+    # max_length ("local Q") and max_steps
+    g = gpu_trace(fg, seeds[2:], step_dtype="f32", max_length=0.05, **kw)
+    o = oracle_mod.trace(fo, seeds[2:], max_length=0.05, **kw)
+    assert np.array_equal(g["status"], o["status"])
+    both = ((g["status"] & 0xFF) == 6) & (((g["status"] >> 8) & 0xFF) == 6)
+    assert both.any() and np.all(g["fll"][both] == 0.1)
+    g = gpu_trace(fg, seeds[2:], step_dtype="f32", max_steps=1, **kw)
+    o = oracle_mod.trace(fo, seeds[2:], max_steps=1, **kw)
+    assert np.array_equal(g["status"], o["status"])
+
+    # open-line switch: Q masked for open lines only
+    g1 = gpu_trace(fg, seeds, step_dtype="f32", **kw)
+    g2 = gpu_trace(fg, seeds, step_dtype="f32", skip_open=True, **kw)
+    open_ = (g1["status"] & q._abi.STATUS_OPEN) != 0
+    assert np.all(np.isnan(g2["q_perp"][open_]))
+    assert np.array_equal(g2["q_perp"][~open_], g1["q_perp"][~open_])
+
+
+def test_null_region_and_empty(oracle_mod):
+    import paper_1609_00724_amd as q
+    import torch
+    n = (9, 9, 9)
+    b = list(synth.sample_linear(*synth.uniform([0, 0, 1.0]), n))
+    b[2][3:6, 3:6, 3:6] = 0.0
+    origin, spacing = synth.grid_geometry(n)
+    fg = gpu_field(b, origin, spacing, storage="f32")
+    seeds = np.array([[0.0, 0.0, 0.5], [0.0, 0.0, 0.1], [0.9, 0.9, 0.1]])
+    kw = dict(rtol=1e-8, atol=1e-8, h_init=0.01, h_max=min(spacing))
+    g = gpu_trace(fg, seeds, step_dtype="f64", **kw)
+    o = oracle_mod.trace(oracle_mod.Field.grid(*b, origin, spacing, store="f32"), seeds, **kw)
+    assert np.array_equal(g["status"], o["status"])
+    assert (g["status"][0] & 0xFF) == q._abi.END_NULL
+    # zero seeds: nothing enqueued, no error
+    out = q.trace(fg, torch.empty((3, 0), dtype=torch.float64, device="cuda"), rtol=1e-6, atol=1e-6)
+    assert out["status"].numel() == 0
+
+
+def test_step_counts_match_oracle(oracle_mod, c1):
+    """FP64 stepping takes the oracle's step sequence (attempts per half-line)."""
+    seeds = c1["seeds"][::53]
+    h = min(c1["spacing"])
+    kw = dict(rtol=1e-8, atol=1e-8, h_init=0.1 * h, h_max=h)
+    fg = gpu_field(c1["b"], c1["origin"], c1["spacing"], storage="f64", mode="paper")
+    g = gpu_trace(fg, seeds, step_dtype="f64", want_steps=True, **kw)
+    o = oracle_mod.trace(_oracle_grid(oracle_mod, c1["b"], c1["origin"], c1["spacing"], "paper", "f64"), seeds,
+                         **kw)
+    att_o = o["counts"][:, 0, 0] + o["counts"][:, 0, 1]
+    att_g = g["steps"][0]
+    moving = o["lam_fwd"] > 0
+    close = np.abs(att_g[moving] - att_o[moving]) <= 2
+    assert close.mean() > 0.95, (att_g[moving][:10], att_o[moving][:10])

@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--tol", type=float, default=1e-3, help="stepping rtol = atol")
+    ap.add_argument("--tol", type=float, default=1e-4, help="stepping rtol = atol")
     ap.add_argument("--base-level", type=int, default=10)
     ap.add_argument("--refine-levels", type=int, default=2)
     ap.add_argument("--threshold", type=float, default=0.02)
@@ -175,7 +175,7 @@ def accuracy(args, field, w, h):
     import paper_1609_00724_amd as q
     import synth
     seeds = synth.random_seeds(2024, args.accuracy_lines, z=0.0)
-    g = q.trace(field, torch.from_numpy(seeds.T.copy()).cuda(), rtol=args.tol, atol=args.tol,
+    g = q.trace(field, torch.from_numpy(seeds).cuda(), rtol=args.tol, atol=args.tol,
                 h_init=0.1 * h, h_max=h, step_dtype="f32")
     torch.cuda.synchronize()
     qg = g["q_perp"].cpu().numpy()
@@ -184,7 +184,8 @@ def accuracy(args, field, w, h):
     m = np.isfinite(qo) & np.isfinite(qg) & (qo < 1e6) & (g["status"].cpu().numpy() == o["status"])
     rel = np.abs(np.log10(qg[m]) - np.log10(qo[m])) / np.abs(np.log10(qo[m]))
     return {"median_rel_log10q_err": float(np.median(rel)), "p90": float(np.percentile(rel, 90)),
-            "lines": int(m.sum()), "reference": "FP64 oracle, tol 1e-10", "target": 1e-3}
+            "p99": float(np.percentile(rel, 99)), "max": float(rel.max()),
+            "lines": int(m.sum()), "reference": "FP64 oracle, tol 1e-10", "target_median": 1e-3}
 
 
 def cpu_baseline(args, w, h):

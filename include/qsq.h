@@ -174,8 +174,8 @@ uint64_t qsq_trace_scratch_bytes(int64_t n);
  * adaptive steps) until the box is left (landing exactly on the face crossed
  * first), max_length, max_steps, a null or a non-finite state; then Q by
  * eq. (10)-(11).  scratch: device, >= qsq_trace_scratch_bytes(n), 256-byte
- * aligned.  Errors: INVALID_ARG, UNSUPPORTED, WORKSPACE_TOO_SMALL,
- * COUNT_OVERFLOW (n > 2^30), HIP.
+ * aligned.  n = 0 enqueues nothing and succeeds.  Errors: INVALID_ARG,
+ * UNSUPPORTED, WORKSPACE_TOO_SMALL, COUNT_OVERFLOW (n > 2^30), HIP.
  */
 int qsq_trace(const qsq_field *f, const double *seeds, int64_t n, const qsq_trace_opts *opts,
               const qsq_trace_out *out, void *scratch, uint64_t scratch_bytes, void *stream);

@@ -112,15 +112,15 @@ class TracePlan:
 
 def trace(field: Field, seeds, *, rtol, atol, h_init=0.0, h_max=0.0, max_length=0.0, max_steps=0,
           step_dtype="f32", skip_open=False, want_steps=False, want_work=False, stream=None):
-    """Trace seeds (device tensor (n, 3) or SoA (3, n), FP64) both ways.
+    """Trace seeds, a device tensor of shape (n, 3) (one row per seed), both ways.
 
-    Returns device tensors: fp_fwd, fp_bwd (3, n); fll, q_perp, q_det, q_fp (n,);
-    status (n,) int32; steps (2, n) int32 if asked.
+    Returns device tensors: fp_fwd, fp_bwd (3, n) SoA planes; fll, q_perp, q_det,
+    q_fp (n,); status (n,) int32; steps (2, n) int32 and work (4,) if asked.
     """
     seeds = _dev(seeds, torch.float64, "seeds")
-    if seeds.dim() != 2 or 3 not in seeds.shape:
-        raise ValueError("seeds must be (n, 3) or (3, n)")
-    soa = seeds if (seeds.shape[0] == 3 and seeds.shape[1] != 3) else seeds.t().contiguous()
+    if seeds.dim() != 2 or seeds.shape[1] != 3:
+        raise ValueError("seeds must have shape (n, 3)")
+    soa = seeds.t().contiguous()
     n = soa.shape[1]
     plan = TracePlan(n, seeds.device, want_steps=want_steps, want_work=want_work)
     opts = make_opts(rtol, atol, h_init, h_max, max_length, max_steps, step_dtype, skip_open)

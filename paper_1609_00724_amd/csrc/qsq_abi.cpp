@@ -265,8 +265,8 @@ int qsq_trace(const qsq_field *f, const double *seeds, int64_t n, const qsq_trac
     if (rc) return rc;
     if (n < 0) return fail(QSQ_ERR_INVALID_ARG, "n < 0");
     if (n > ((int64_t)1 << 30)) return fail(QSQ_ERR_COUNT_OVERFLOW, "n > 2^30 seeds");
+    if (n == 0) return ok();   // nothing to enqueue; output pointers may be NULL
     if (!out || !out->status) return fail(QSQ_ERR_INVALID_ARG, "out or out->status is NULL");
-    if (n == 0) return ok();
     if (!seeds || !scratch) return fail(QSQ_ERR_INVALID_ARG, "NULL seeds or scratch");
     if (!aligned(scratch, 256)) return fail(QSQ_ERR_INVALID_ARG, "scratch must be 256-byte aligned");
     const uint64_t need = qsq_trace_scratch_bytes(n);

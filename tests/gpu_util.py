@@ -18,7 +18,7 @@ def gpu_field(b, origin, spacing, storage="f32", mode="paper"):
 def gpu_trace(field, seeds, **kw):
     import paper_1609_00724_amd as q
     torch, dev = torch_dev()
-    s = torch.from_numpy(np.ascontiguousarray(seeds.T)).to(dev)
+    s = torch.from_numpy(np.ascontiguousarray(seeds)).to(dev)
     out = q.trace(field, s, **kw)
     torch.cuda.synchronize()
     r = {k: v.cpu().numpy() for k, v in out.items()}
@@ -45,6 +45,70 @@ def parity(g, o, qmax=1e6):
     return dict(gate=gate, fp=fp, fll=fll, lq=lq, status_mismatch=int((~same).sum()),
                 nonfinite_both=int((~np.isfinite(qo) & ~np.isfinite(g["q_perp"])).sum()),
                 over_qmax=int((same & fin & (qo >= qmax)).sum()))
+
+
+FP_TOL, FLL_TOL, LQ_TOL = 1e-5, 1e-4, 1e-3
+
+
+def line_ok(p):
+    """Per-line gates: footpoints <= 1e-5 domain units, length <= 1e-4 relative,
+    relative log10 Q error <= 1e-3."""
+    lq = np.nan_to_num(p["lq"], nan=np.inf)
+    return (p["fp"] <= FP_TOL) & (p["fll"] <= FLL_TOL) & (lq <= LQ_TOL)
+
+
+def check_lines(p, o, strict, min_frac=0.998, max_mismatch_frac=0.003):
+    """strict (FP64 stepping): every gated line meets the per-line gates.
+    Otherwise (FP32 stepping): at least min_frac of the gated lines meet them
+    and the median log10 Q error stays <= 1e-5; the rest are counted.  FP32
+    stage points differ from FP64 ones by ~1e-7 cell, so a stage that falls on
+    the other side of a cell face (where the trilinear gradient jumps) or an
+    accept/reject decision at err ~ 1 occasionally sends a line down a
+    different, equally valid step sequence."""
+    m = p["gate"]
+    ok = line_ok(p)
+    n_bad = int((~ok[m]).sum())
+    msg = (summary(p) + f" | outside per-line gates: {n_bad}/{int(m.sum())} | worst: " + worst(p, o))
+    print(msg)
+    assert p["status_mismatch"] <= max_mismatch_frac * m.size + (0 if strict else 1), msg
+    if strict:
+        assert n_bad == 0, msg
+    else:
+        assert ok[m].mean() >= min_frac, msg
+        assert np.nanmedian(p["lq"][m]) <= 1e-5, msg
+    return n_bad
+
+
+def lq_vs(a, ref):
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.abs(np.log10(a) - np.log10(ref)) / np.abs(np.log10(ref))
+
+
+def check_fp32(p, g, o, ref, min_frac=0.95):
+    """FP32 stepping against the FP64 oracle at the same tolerance (o) and
+    against the converged FP64 oracle at tolerance 1e-10 (ref).
+
+    FP32 stage arithmetic acts like a ~1e-7 perturbation of the stage points,
+    and the discretised method (trilinear gradients jump at cell faces) sends a
+    few lines down a different, equally valid step sequence under such
+    perturbations (the oracle shows the same lines moving when its own seeds
+    move by 1e-7).  So: most lines meet the per-line gates against o, and the
+    FP32 error against the converged answer is statistically no larger than the
+    FP64 oracle's own error at the same tolerance."""
+    m = p["gate"] & np.isfinite(ref["q_perp"]) & (ref["status"] == o["status"])
+    ok = line_ok(p)
+    e_g = lq_vs(g["q_perp"][m], ref["q_perp"][m])
+    e_o = lq_vs(o["q_perp"][m], ref["q_perp"][m])
+    msg = (summary(p) + f" | within per-line gates {ok[p['gate']].mean():.4f}"
+           f" | vs converged: gpu median {np.nanmedian(e_g):.2e} p90 {np.nanpercentile(e_g, 90):.2e}"
+           f" max {np.nanmax(e_g):.2e}; oracle same tol median {np.nanmedian(e_o):.2e}"
+           f" p90 {np.nanpercentile(e_o, 90):.2e} max {np.nanmax(e_o):.2e} | worst: " + worst(p, o))
+    print(msg)
+    assert p["status_mismatch"] <= 0.003 * p["gate"].size + 1, msg
+    assert ok[p["gate"]].mean() >= min_frac, msg
+    assert np.nanmedian(p["lq"][p["gate"]]) <= 1e-5, msg
+    assert np.nanmedian(e_g) <= 1.25 * np.nanmedian(e_o) + 1e-6, msg
+    assert np.nanpercentile(e_g, 90) <= 1.5 * np.nanpercentile(e_o, 90) + 1e-6, msg
 
 
 def worst(p, o, k=3):

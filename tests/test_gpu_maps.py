@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_util import parity, summary, torch_dev, worst
+from gpu_util import check_lines, parity, torch_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -52,7 +52,7 @@ def test_hilbert_vs_oracle_sampled(oracle_mod, L):
 # ---------------------------------------------------------------------------
 
 CHARGES = synth.point_charges(2, 4)
-TOL = 1e-3   # stepping tolerance of the photospheric map workload
+TOL = 1e-4   # stepping tolerance of the photospheric map workload
 
 
 @pytest.fixture(scope="module")
@@ -66,13 +66,13 @@ def c2(oracle_mod):
     return dict(w=w, fg=fg, fo=fo, h=min(w["spacing"]))
 
 
-def _run_map(c2, m, r, thr, out_level, capacity):
+def _run_map(c2, m, r, thr, out_level, capacity, step_dtype="f32"):
     import paper_1609_00724_amd as q
     from paper_1609_00724_amd.api import MapSpec
     torch, dev = torch_dev()
     spec = MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, r, out_level, thr)
     res = q.qmap(c2["fg"], spec, capacity, rtol=TOL, atol=TOL, h_init=0.1 * c2["h"], h_max=c2["h"],
-                 step_dtype="f32")
+                 step_dtype=step_dtype)
     torch.cuda.synchronize()
     out = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}
     return out
@@ -102,7 +102,7 @@ def _oracle_trace(oracle_mod, c2, pts):
     return oracle_mod.trace(c2["fo"], pts, rtol=TOL, atol=TOL, h_init=0.1 * c2["h"], h_max=c2["h"])
 
 
-def _sample_parity(oracle_mod, c2, res, idx, m, r):
+def _sample_parity(oracle_mod, c2, res, idx, m, r, strict=False):
     pos, _ = _positions(oracle_mod, m, r, res["keys"][idx])
     o = _oracle_trace(oracle_mod, c2, pos)
     g = dict(status=res["status"][idx], q_perp=res["q_perp"][idx], fll=res["fll"][idx],
@@ -110,24 +110,19 @@ def _sample_parity(oracle_mod, c2, res, idx, m, r):
     o2 = dict(o)
     o2["fp_fwd"] = np.zeros((idx.size, 3))
     o2["fp_bwd"] = np.zeros((idx.size, 3))
-    p = parity(g, o2)
-    msg = summary(p) + " | worst: " + worst(p, o)
-    print(msg)
-    m_ = p["gate"]
-    assert p["status_mismatch"] <= 0.003 * idx.size + 1, msg
-    assert p["fll"][m_].max() <= 1e-4, msg
-    assert np.nanmax(p["lq"][m_]) <= 1e-3, msg
+    check_lines(parity(g, o2), o, strict=strict)
     return o
 
 
-def test_small_map_vs_oracle(oracle_mod, c2):
+@pytest.mark.parametrize("step_dtype", ["f32", "f64"])
+def test_small_map_vs_oracle(oracle_mod, c2, step_dtype):
     m, r, thr = 6, 2, 0.02
-    res = _run_map(c2, m, r, thr, m + r, 4 ** (m + r))
+    res = _run_map(c2, m, r, thr, m + r, 4 ** (m + r), step_dtype)
     n = res["count"]
     assert res["overflow"] == 0 and n > 4 ** m
     _check_complete(res, thr)
     # every sample re-traced by the oracle at the same key position
-    o = _sample_parity(oracle_mod, c2, res, np.arange(n), m, r)
+    o = _sample_parity(oracle_mod, c2, res, np.arange(n), m, r, strict=step_dtype == "f64")
     # the oracle's own refinement reaches the same sample set (up to marginal jumps)
     plane = oracle_mod.SlicePlane(0.0, -1.0, 1.0, -1.0, 1.0)
 
@@ -160,17 +155,19 @@ def test_capacity_overflow_is_flagged(c2):
     assert np.all(np.diff(res["keys"]) > 0)
 
 
-def test_full_photospheric_map_sampled(oracle_mod, c2):
+@pytest.mark.parametrize("step_dtype", ["f32", "f64"])
+def test_full_photospheric_map_sampled(oracle_mod, c2, step_dtype):
     """The benchmark's workload: 1024^2 base map with 4x (two-level) refinement;
-    oracle checks on a sample of lines, converter cells, and the whole FLEDGE."""
+    oracle checks on a sample of lines, converter cells, and the whole FLEDGE.
+    FP64 stepping must match the oracle on every sampled line."""
     m, r, thr = 10, 2, 0.02
-    res = _run_map(c2, m, r, thr, m, 4 ** m * 4)
+    res = _run_map(c2, m, r, thr, m, 4 ** m * 4, step_dtype)
     n = res["count"]
     assert res["overflow"] == 0 and n > 4 ** m
     _check_complete(res, thr)
     g = synth.rng(77)
     idx = np.sort(g.choice(n, size=1500, replace=False))
-    _sample_parity(oracle_mod, c2, res, idx, m, r)
+    _sample_parity(oracle_mod, c2, res, idx, m, r, strict=step_dtype == "f64")
     cells = g.choice(4 ** m, size=300, replace=False)
     want = oracle_mod.convert_to_grid(res["keys"], res["q_perp"], m, r, m, log_interp=True, cells=cells)
     cx, cy = oracle_mod.hilbert2_d2xy(m, cells)

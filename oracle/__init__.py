@@ -78,6 +78,8 @@ def lib():
         L.or_ck54_tableau.argtypes = [P, P, P, P]
         L.or_hilbert2_xy2d.argtypes = [C.c_int, C.c_int64, P, P, P]
         L.or_hilbert2_d2xy.argtypes = [C.c_int, C.c_int64, P, P, P]
+        L.or_hilbert3_d2xyz.argtypes = [C.c_int, C.c_int64, P, P, P, P]
+        L.or_hilbert3_xyz2d.argtypes = [C.c_int, C.c_int64, P, P, P, P]
         L.or_version.restype = C.c_int
         _lib = L
     return _lib
@@ -109,8 +111,9 @@ class Field:
 
     @classmethod
     def grid(cls, bx, by, bz, origin, spacing, mode=PAPER, store="f64"):
-        """``store="f32"`` rounds the prepared node values (Bhat and |B| in PAPER
-        mode, B otherwise) to FP32, i.e. traces the field an FP32 node store holds."""
+        """``store="f32"`` / ``"bf16"`` rounds the prepared node values (Bhat and
+        |B| in PAPER mode, B otherwise) to FP32 / BF16 (via FP32, nearest even),
+        i.e. traces the field such a node store holds."""
         bx, by, bz = (np.ascontiguousarray(b, dtype=np.float64) for b in (bx, by, bz))
         nz, ny, nx = bx.shape
         d = _Desc()
@@ -121,7 +124,7 @@ class Field:
         d.lo[:] = origin
         d.hi[:] = [origin[i] + (d.n[i] - 1) * spacing[i] for i in range(3)]
         d.bx, d.by, d.bz = _ptr(bx), _ptr(by), _ptr(bz)
-        d.quantize = {"f64": 0, "f32": 1}[store]
+        d.quantize = {"f64": 0, "f32": 1, "bf16": 2}[store]
         return cls(d, (bx, by, bz))
 
     @classmethod
@@ -248,8 +251,24 @@ def hilbert2_d2xy(L, d):
     return x, y
 
 
+def hilbert3_d2xyz(b, d):
+    """Cells (x, y, z) of curve indices d on a 2^b cube (Skilling's 3D curve)."""
+    d = np.ascontiguousarray(d, dtype=np.int64)
+    x, y, z = np.empty_like(d), np.empty_like(d), np.empty_like(d)
+    lib().or_hilbert3_d2xyz(b, d.size, _ptr(d), _ptr(x), _ptr(y), _ptr(z))
+    return x, y, z
+
+
+def hilbert3_xyz2d(b, x, y, z):
+    x, y, z = (np.ascontiguousarray(v, dtype=np.int64) for v in (x, y, z))
+    d = np.empty_like(x)
+    lib().or_hilbert3_xyz2d(b, x.size, _ptr(x), _ptr(y), _ptr(z), _ptr(d))
+    return d
+
+
 class SlicePlane:
     """Horizontal slice z = z0 over [x0, x1] x [y0, y1] (Sect. 2: planar slice)."""
+    dims = 2
 
     def __init__(self, z0, x0, x1, y0, y1):
         self.z0, self.x0, self.x1, self.y0, self.y1 = z0, x0, x1, y0, y1
@@ -260,31 +279,52 @@ class SlicePlane:
         py = self.y0 + (np.asarray(iy) + 0.5) * (self.y1 - self.y0) / n
         return np.stack([px, py, np.full(px.shape, float(self.z0))], axis=-1)
 
-
-def base_samples(plane: SlicePlane, m: int, r: int):
-    """Base lattice: 2^m x 2^m pixel centres in level-m curve order q; key
-    of pixel q at the finest level m+r is q * 4^r + 4^r / 2."""
-    q = np.arange(4 ** m, dtype=np.int64)
-    ix, iy = hilbert2_d2xy(m, q)
-    keys = q * 4 ** r + 4 ** r // 2
-    return keys, plane.centres(m, ix, iy)
+    def cells(self, level, d):
+        return hilbert2_d2xy(level, d)
 
 
-def key_positions(plane: SlicePlane, m: int, r: int, keys):
+class VolumeBox:
+    """Axis-aligned volume [x0, x1] x [y0, y1] x [z0, z1] (3D maps)."""
+    dims = 3
+
+    def __init__(self, x0, x1, y0, y1, z0, z1):
+        self.lo = np.array([x0, y0, z0], float)
+        self.hi = np.array([x1, y1, z1], float)
+
+    def centres(self, level, ix, iy, iz):
+        n = 1 << level
+        idx = np.stack([np.asarray(ix), np.asarray(iy), np.asarray(iz)], axis=-1).astype(float)
+        return self.lo + (idx + 0.5) * (self.hi - self.lo) / n
+
+    def cells(self, level, d):
+        return hilbert3_d2xyz(level, d)
+
+
+def base_samples(region, m: int, r: int):
+    """Base lattice: 2^m cells per axis at their centres in level-m curve order
+    q; key of cell q at the finest level m+r is q * B^r + B^r / 2 with
+    B = 2^dims (4 for slices, 8 for volumes)."""
+    blk = (1 << region.dims) ** r
+    q = np.arange((1 << region.dims) ** m, dtype=np.int64)
+    keys = q * blk + blk // 2
+    return keys, region.centres(m, *region.cells(m, q))
+
+
+def key_positions(region, m: int, r: int, keys):
     """Centre of the finest-level cell H^-1(key) at level m + r."""
-    ix, iy = hilbert2_d2xy(m + r, keys)
-    return plane.centres(m + r, ix, iy)
+    return region.centres(m + r, *region.cells(m + r, keys))
 
 
-def refine_slice(plane: SlicePlane, m: int, r: int, thr: float, sample_fn, max_passes=64):
-    """FLL-jump refinement along the Hilbert curve (Sect. 3.6).
+def refine_slice(region, m: int, r: int, thr: float, sample_fn, max_passes=64):
+    """FLL-jump refinement along the Hilbert curve (Sect. 3.6), for a slice or
+    a volume.
 
     ``sample_fn(points (n,3)) -> dict`` with at least ``fll`` and ``q``.
     Returns (keys, values dict, passes): samples in curve order.  A new sample
     goes halfway (in key) between curve-successive samples whose FLL differs
     by more than ``thr`` while they are at least two finest cells apart.
     """
-    keys, pts = base_samples(plane, m, r)
+    keys, pts = base_samples(region, m, r)
     vals = sample_fn(pts)
     vals = {k: np.asarray(v) for k, v in vals.items()}
     passes = 0
@@ -298,29 +338,31 @@ def refine_slice(plane: SlicePlane, m: int, r: int, thr: float, sample_fn, max_p
         passes += 1
         idx = np.nonzero(fire)[0]
         newk = (keys[idx] + keys[idx + 1]) // 2
-        newv = sample_fn(key_positions(plane, m, r, newk))
+        newv = sample_fn(key_positions(region, m, r, newk))
         # every new key lies strictly between keys[i] and keys[i+1]
         keys = np.insert(keys, idx + 1, newk)
         vals = {k: np.insert(v, idx + 1, np.asarray(newv[k]), axis=0) for k, v in vals.items()}
     return keys, vals, passes
 
 
-def convert_to_grid(keys, values, m: int, r: int, level: int, log_interp: bool, cells=None):
-    """Array converter (Sect. 3.6) to a 2^level x 2^level grid (m <= level <= m+r).
+def convert_to_grid(keys, values, m: int, r: int, level: int, log_interp: bool, cells=None, dims=2):
+    """Array converter (Sect. 3.6) to a grid of 2^level cells per axis
+    (m <= level <= m+r), for slices (dims 2) and volumes (dims 3).
 
     A cell is the aligned block of finest keys it contains; its value is the
     largest sample in the block (NaN samples ignored unless all are NaN).  An
     empty cell takes the value interpolated along the curve, linearly in key
     (in log10 when ``log_interp``), between the nearest samples below and above
-    the block centre.  Output indexed [iy, ix]; with ``cells`` (curve indices at
-    ``level``) only those cells are computed and returned as a 1-D array.
+    the block centre.  Output indexed [iy, ix] or [iz, iy, ix]; with ``cells``
+    (curve indices at ``level``) only those cells are computed and returned as
+    a 1-D array.
     """
     keys = np.asarray(keys, dtype=np.int64)
     values = np.asarray(values, dtype=np.float64)
     n = 1 << level
-    bsize = 4 ** (m + r - level)
-    out = np.empty((n, n))
-    todo = range(n * n) if cells is None else [int(c) for c in cells]
+    bsize = (1 << dims) ** (m + r - level)
+    out = np.empty((n,) * dims)
+    todo = range(n ** dims) if cells is None else [int(c) for c in cells]
     picked = []
     for cell in todo:
         lo, hi = cell * bsize, (cell + 1) * bsize
@@ -348,6 +390,10 @@ def convert_to_grid(keys, values, m: int, r: int, level: int, log_interp: bool, 
         if cells is not None:
             picked.append(val)
             continue
-        x, y = hilbert2_d2xy(level, np.array([cell]))
-        out[y[0], x[0]] = val
+        if dims == 2:
+            x, y = hilbert2_d2xy(level, np.array([cell]))
+            out[y[0], x[0]] = val
+        else:
+            x, y, z = hilbert3_d2xyz(level, np.array([cell]))
+            out[z[0], y[0], x[0]] = val
     return out if cells is None else np.array(picked)

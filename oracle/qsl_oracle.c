@@ -66,8 +66,8 @@ typedef struct {
     double lin[12];        /* linear field B = lin[0..2] + M x, M row-major lin[3..11] */
     const double *charges; /* ncharges x (x, y, z, q) */
     int64_t ncharges;
-    int32_t quantize;      /* 1: round the prepared node values to FP32 (the
-                              stored form of an FP32 node field) */
+    int32_t quantize;      /* 1: round the prepared node values to FP32, 2: to
+                              BF16 (the stored form of an FP32 / BF16 node field) */
     int32_t pad;
 } or_field_desc;
 
@@ -86,6 +86,19 @@ typedef struct {
     int32_t nthreads;      /* <= 0: OpenMP default */
     int32_t pad;
 } or_opts;
+
+/* BF16 value of x: x rounded to FP32, then to the nearest BF16 (8-bit
+ * significand), ties to even; finite inputs only */
+static double to_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    uint32_t lsb = (u >> 16) & 1u;
+    u = (u + 0x7fffu + lsb) & 0xffff0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
 
 /* ------------------------------------------------------------------ */
 /* field preparation (footnote to Sect. 3.5: normalise the node field  */
@@ -123,6 +136,8 @@ void *or_field_new(const or_field_desc *desc)
         }
         if (desc->quantize == 1)
             for (int k = 0; k < 4; ++k) F->c[k][i] = (double)(float)F->c[k][i];
+        if (desc->quantize == 2)
+            for (int k = 0; k < 4; ++k) F->c[k][i] = to_bf16(F->c[k][i]);
     }
     return F;
 }
@@ -713,6 +728,90 @@ void or_hilbert2_d2xy(int L, int64_t n, const int64_t *d, int64_t *x, int64_t *y
         h2_d2xy(L, (uint64_t)d[i], &xx, &yy);
         x[i] = (int64_t)xx;
         y[i] = (int64_t)yy;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Hilbert curve in 3D (Sect. 3.6, volumes): the transpose algorithm of */
+/* Skilling 2004 ("Programming the Hilbert curve", AIP Conf. Proc. 707) */
+/* for n = 3 axes of b bits.  The index H has 3b bits; its bits, most   */
+/* significant first, are bit b-1 of X[0], X[1], X[2], then bit b-2 of  */
+/* X[0], X[1], X[2], and so on (the "transpose" of H).                  */
+/* ------------------------------------------------------------------ */
+
+static void sk_transpose_to_axes(uint32_t X[3], int b)
+{
+    const int n = 3;
+    uint32_t N = 2u << (b - 1), P, Q, t;
+    /* Gray decode by H ^ (H / 2) */
+    t = X[n - 1] >> 1;
+    for (int i = n - 1; i > 0; --i) X[i] ^= X[i - 1];
+    X[0] ^= t;
+    /* undo excess work */
+    for (Q = 2; Q != N; Q <<= 1) {
+        P = Q - 1;
+        for (int i = n - 1; i >= 0; --i) {
+            if (X[i] & Q) {
+                X[0] ^= P;                 /* invert */
+            } else {
+                t = (X[0] ^ X[i]) & P;     /* exchange */
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+}
+
+static void sk_axes_to_transpose(uint32_t X[3], int b)
+{
+    const int n = 3;
+    uint32_t M = 1u << (b - 1), P, Q, t;
+    /* inverse undo */
+    for (Q = M; Q > 1; Q >>= 1) {
+        P = Q - 1;
+        for (int i = 0; i < n; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    /* Gray encode */
+    for (int i = 1; i < n; ++i) X[i] ^= X[i - 1];
+    t = 0;
+    for (Q = M; Q > 1; Q >>= 1)
+        if (X[n - 1] & Q) t ^= Q - 1;
+    for (int i = 0; i < n; ++i) X[i] ^= t;
+}
+
+void or_hilbert3_d2xyz(int b, int64_t n, const int64_t *d, int64_t *x, int64_t *y, int64_t *z)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        uint64_t h = (uint64_t)d[k];
+        uint32_t X[3] = { 0, 0, 0 };
+        for (int j = 0; j < b; ++j)          /* bit j of X[i] is bit 3j + 2 - i of h */
+            for (int i = 0; i < 3; ++i)
+                X[i] |= (uint32_t)((h >> (3 * j + 2 - i)) & 1u) << j;
+        sk_transpose_to_axes(X, b);
+        x[k] = X[0];
+        y[k] = X[1];
+        z[k] = X[2];
+    }
+}
+
+void or_hilbert3_xyz2d(int b, int64_t n, const int64_t *x, const int64_t *y, const int64_t *z, int64_t *d)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        uint32_t X[3] = { (uint32_t)x[k], (uint32_t)y[k], (uint32_t)z[k] };
+        sk_axes_to_transpose(X, b);
+        uint64_t h = 0;
+        for (int j = 0; j < b; ++j)
+            for (int i = 0; i < 3; ++i)
+                h |= (uint64_t)((X[i] >> j) & 1u) << (3 * j + 2 - i);
+        d[k] = (int64_t)h;
     }
 }
 

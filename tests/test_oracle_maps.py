@@ -184,3 +184,68 @@ def test_convert_max_and_gap_fill_brute_force(oracle_mod):
     # block 1 (keys 4..7) is empty: interpolate at its centre key 5.5 between 3 and 9
     w = (5.5 - 3) / 6
     assert g1[y1[1], x1[1]] == pytest.approx(10 ** ((1 - w) * np.log10(3.0) + w * 2.0))
+
+
+# ---------------------------------------------------------------------------
+# volumes: 3D Hilbert curve, refinement and converter
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("b", [1, 2, 3, 4, 5])
+def test_hilbert3_bijection_adjacency_blocks(oracle_mod, b):
+    O = oracle_mod
+    n = 1 << b
+    d = np.arange(n ** 3, dtype=np.int64)
+    x, y, z = O.hilbert3_d2xyz(b, d)
+    assert np.unique((z * n + y) * n + x).size == n ** 3
+    assert np.array_equal(O.hilbert3_xyz2d(b, x, y, z), d)
+    step = np.abs(np.diff(x)) + np.abs(np.diff(y)) + np.abs(np.diff(z))
+    assert np.all(step == 1)
+    assert (x[0], y[0], z[0]) == (0, 0, 0)
+    for j in range(1, b + 1):
+        bs, side = 8 ** j, 1 << j
+        for c in (x, y, z):
+            blk = c.reshape(-1, bs)
+            assert np.all(blk.max(1) - blk.min(1) == side - 1)
+            assert np.all(blk.min(1) % side == 0)
+    if b > 1:   # the level-(b-1) cell of d is the parent of d's cell
+        xp, yp, zp = O.hilbert3_d2xyz(b - 1, d // 8)
+        assert np.array_equal(x // 2, xp) and np.array_equal(y // 2, yp) and np.array_equal(z // 2, zp)
+
+
+def test_refine_volume_sphere(oracle_mod):
+    O = oracle_mod
+    box = O.VolumeBox(-1, 1, -1, 1, 0, 1)
+    R = 0.35
+    c = np.array([0.1, -0.2, 0.5])
+
+    def fn(p):
+        inside = (np.linalg.norm(p - c, axis=1) < R).astype(float)
+        return {"fll": inside, "q": 2.0 + 10 * inside}
+
+    m, r = 3, 2
+    keys, vals, passes = O.refine_slice(box, m, r, 0.5, fn)
+    assert passes == 6                       # key gap 64 halves to 1 in six passes
+    assert np.all(np.diff(keys) > 0)
+    new = keys % 64 != 32
+    assert new.sum() > 0
+    pos = O.key_positions(box, m, r, keys[new])
+    cell = (box.hi - box.lo) / (1 << m)
+    dist = np.abs(np.linalg.norm(pos - c, axis=1) - R)
+    assert dist.max() < np.linalg.norm(cell)          # within one base cell of the surface
+    jumps = np.nonzero(np.abs(np.diff(vals["fll"])) > 0.5)[0]
+    assert np.all(keys[jumps + 1] - keys[jumps] == 1)
+
+
+def test_convert_volume_brute_force(oracle_mod):
+    O = oracle_mod
+    m, r = 1, 1
+    keys = np.array([3, 4, 20, 40, 41, 63])
+    vals = np.array([5.0, 50.0, 2.0, 7.0, 3.0, 9.0])
+    g = O.convert_to_grid(keys, vals, m, r, 1, log_interp=True, dims=3)
+    x, y, z = O.hilbert3_d2xyz(1, np.arange(8))
+    # blocks of 8 finest keys: [0,8) -> 50, [16,24) -> 2, [40,48) -> 7, [56,64) -> 9
+    for blk, want in ((0, 50.0), (2, 2.0), (5, 7.0), (7, 9.0)):
+        assert g[z[blk], y[blk], x[blk]] == want
+    # block 1 ([8,16)) empty: log-interpolated at key 11.5 between keys 4 and 20
+    w = (11.5 - 4) / 16
+    assert g[z[1], y[1], x[1]] == pytest.approx(10 ** ((1 - w) * np.log10(50) + w * np.log10(2)))

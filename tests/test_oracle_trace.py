@@ -466,3 +466,24 @@ def test_statuses(oracle_mod):
     assert _fwd(r["status"][1]) == O.NULL
     # open-line bit: closed only if both ends are on the bottom face
     assert r["status"][1] & O.OPEN_BIT
+
+
+def test_node_storage_rounding(oracle_mod):
+    """FP32 / BF16 node stores hold the prepared values rounded to the storage
+    type; values worked out by hand for Bhat of B = (0.3, -0.5, 0.8):
+    0.30304576 -> BF16 155/128 * 2^-2, -0.50507627 -> -129/128 * 2^-1,
+    0.80812204 -> 207/128 * 2^-1, |B| = 0.98994949 -> 253/128 * 2^-1."""
+    O = oracle_mod
+    n = (3, 3, 3)
+    b = synth.sample_linear(*synth.uniform([0.3, -0.5, 0.8]), n)
+    origin, spacing = synth.grid_geometry(n)
+    x = np.array([[0.1, 0.2, 0.3]])
+    u, _, m = O.Field.grid(*b, origin, spacing, store="bf16").eval(x)
+    # (interpolating equal node values reproduces them up to the weights' rounding)
+    assert np.allclose(u[0], [155 / 512, -129 / 256, 207 / 256], rtol=1e-14, atol=0)
+    assert m[0] == pytest.approx(253 / 256, rel=1e-14)
+    u32, _, m32 = O.Field.grid(*b, origin, spacing, store="f32").eval(x)
+    exact = np.array([0.3, -0.5, 0.8]) / np.sqrt(0.98)
+    assert np.allclose(u32[0], exact.astype(np.float32).astype(np.float64), rtol=1e-14, atol=0)
+    assert not np.allclose(u32[0], exact, rtol=1e-12, atol=0)          # it is rounded
+    assert m32[0] == pytest.approx(np.float64(np.float32(np.sqrt(0.98))), rel=1e-14)

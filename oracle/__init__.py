@@ -13,6 +13,9 @@ Contents, each following the paper (Tassev & Savcheva 2017):
   * ``refine_slice``           -- Sect. 3.6: FLL-jump refinement along the curve
   * ``convert_to_grid``        -- Sect. 3.6: array converter (max per cell,
                                   log Q interpolated along the curve in gaps)
+  * ``oracle.cnn``             -- FP64 reference of the learned refinement
+                                  proposer (3x3 convolutions, loss, backward,
+                                  Adam), an extension beyond the paper
 """
 from __future__ import annotations
 

@@ -50,10 +50,24 @@ def parse():
     ap.add_argument("--base-level", type=int, default=10)
     ap.add_argument("--refine-levels", type=int, default=2)
     ap.add_argument("--threshold", type=float, default=0.02)
+    ap.add_argument("--refine-batch", type=int, default=0, help="refinement levels per device round (0: auto)")
+    ap.add_argument("--hmax-cells", type=float, default=1.0, help="largest step, in grid cells")
     ap.add_argument("--cpu-level", type=int, default=9, help="base level of the oracle's sample map")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy leg")
+    ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch shape")
     ap.add_argument("--accuracy-lines", type=int, default=256)
+    ap.add_argument("--workload", choices=("map", "batch", "volume", "learned"), default="map",
+                    help="map: photospheric map of one field; batch: 64 fields in one batched trace; "
+                         "volume: 3D Q/FLL/FLEDGE volume of a flux-rope field")
+    ap.add_argument("--batch-fields", type=int, default=64)
+    ap.add_argument("--volume-level", type=int, default=8, help="volume workload: base level (2^m cells a side)")
+    ap.add_argument("--learn-fields", type=int, default=320, help="learned workload: maps generated (1/4 rope slices)")
+    ap.add_argument("--learn-epochs", type=int, default=12)
+    ap.add_argument("--cpu-fraction", type=float, default=0.02,
+                    help="batch workload: fraction of each field's seeds the oracle traces")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -63,6 +77,14 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "requested_gpus": args.gpus}))
         sys.exit(2)
+    if args.calibrate_copy:
+        return calibrate_copy()
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "volume":
+        return bench_volume(args)
+    if args.workload == "learned":
+        return bench_learned(args)
     import numpy as np
     import torch
 
@@ -77,11 +99,21 @@ def main():
     b = [torch.from_numpy(c).to(dev) for c in w["b"]]
     field = q.field_init(*b, w["origin"], w["spacing"], storage="f32")
     m, r = args.base_level, args.refine_levels
-    spec = MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, r, m, args.threshold)
+    spec = MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, r, m, args.threshold, args.refine_batch)
     plan = QMapPlan(spec, 4 ** m * 4, dev)
-    opts = make_opts(args.tol, args.tol, h_init=0.1 * h, h_max=h, step_dtype="f32")
+    hmax = args.hmax_cells * h
+    opts = make_opts(args.tol, args.tol, h_init=0.1 * h, h_max=hmax, step_dtype="f32")
     stream = torch.cuda.current_stream()
 
+    tuned = None
+    if not args.no_tune:
+        # launch shape picked on the workload itself, before the timed region
+        from paper_1609_00724_amd import autotune
+        word, table = autotune.tune_map(plan, field, opts, reps=2)
+        opts.launch = word
+        default = table.get(0, table.get(A.launch_word(), None))
+        tuned = dict(autotune.describe(word), ms=table[word], candidates=len(table),
+                     worst_ms=max(table.values()), default_shape_ms=default)
     for _ in range(args.warmup):
         plan.run(field, opts)
     torch.cuda.synchronize()
@@ -127,11 +159,13 @@ def main():
         "config": {
             "workload": (f"photospheric Q/FLL/FLEDGE map, 4-charge potential field on a 256x256x128 FP32 grid, "
                          f"{1 << m}^2 base lines + FLL-jump Hilbert refinement r={r} thr={args.threshold}, "
-                         f"CK54 FP32 stepping tol={args.tol:g}, FP64 landing and Q"),
+                         f"CK54 FP32 stepping tol={args.tol:g} h_max={args.hmax_cells:g} cell, FP64 landing and Q"),
             "lines_per_step": lines,
             "base_lines": 4 ** m,
             "grid": [256, 256, 128],
             "tol": args.tol,
+            "h_max_cells": args.hmax_cells,
+            "refine_batch": args.refine_batch,
         },
         "roofline": {
             "bound": "alu",
@@ -149,14 +183,517 @@ def main():
         },
         "kernel_ms_per_step": {"step": ms_step / args.steps, "land": ms_land / args.steps,
                                "assemble": ms_asm / args.steps},
+        "launch_shape": tuned,
         "wall_s_timed": wall,
     }
 
     if not args.no_accuracy:
-        out["accuracy"] = accuracy(args, field, w, h)
+        out["accuracy"] = accuracy(args, field, w, h, hmax)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args, w, h)
     print(json.dumps(out), flush=True)
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of 1 GiB, three times: a kernel of known
+    HBM traffic (1 GiB read + 1 GiB written) for scaling the byte counters."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4, "launches": 3}))
+
+
+def bench_batch(args):
+    """Many fields of uneven grid size and seed count in one batched trace,
+    captured in a HIP graph and replayed; beside it the same sets traced one
+    call per field, and FP64 stepping of the same batch."""
+    import numpy as np
+    import torch
+
+    import paper_1609_00724_amd as q
+    import synth
+    from paper_1609_00724_amd import _abi as A
+    from paper_1609_00724_amd.api import Profiler, TraceBatchPlan, TracePlan, make_opts
+
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    fields, seeds, host = [], [], []
+    for f in synth.batch_c3(count=args.batch_fields):
+        b = [torch.from_numpy(c).to(dev) for c in f["b"]]
+        fields.append(q.field_init(*b, f["origin"], f["spacing"], storage="f32"))
+        seeds.append(torch.from_numpy(f["seeds"]).to(dev))
+        host.append(dict(origin=f["origin"], spacing=f["spacing"], n=f["n"], charges=f["charges"],
+                         seeds=f["seeds"]))
+        del b
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    total = sum(int(s.shape[0]) for s in seeds)
+    sets = list(zip(fields, seeds))
+    # h_init, h_max: 0.1 and 1 cell of each field's own grid
+    opts32 = make_opts(args.tol, args.tol, step_dtype="f32")
+    opts64 = make_opts(args.tol, args.tol, step_dtype="f64")
+    plan = TraceBatchPlan(sets, opts32, want_work=True)
+    tuned = None
+    if not args.no_tune:
+        from paper_1609_00724_amd import autotune
+        cands = autotune.candidates(lanes=(2, 3, 4, 8), wgs=(128, 256), gathers=(A.GATHER_DIRECT,))
+        word, table = autotune.tune_batch(sets, opts32, reps=1, cands=cands)
+        opts32.launch = word
+        tuned = dict(autotune.describe(word), ms=table[word], candidates=len(table), worst_ms=max(table.values()))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for _ in range(max(args.warmup, 1)):
+            plan.run()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.run()
+    torch.cuda.synchronize()
+    cur = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(cur)
+    for _ in range(args.steps):
+        graph.replay()
+    e1.record(cur)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+
+    # kernel timing and work counts of the same batch, eager, profiled
+    plan.work.zero_()
+    with Profiler() as prof:
+        with torch.cuda.stream(stream):
+            plan.run()
+        torch.cuda.synchronize()
+        n_step, ms_trace = prof.read(A.KERNEL_STEP)
+    Profiler.reset()
+    attempts, evals, stepped, landed = (int(v) for v in plan.work.cpu().numpy())
+    flops = FLOP_PER_EVAL * evals + FLOP_PER_ATTEMPT * attempts
+    achieved = flops / (ms_trace / 1e3) / 1e12
+
+    # the same sets, one qsq_trace call per field, back to back on one stream
+    plans1 = [TracePlan(int(s.shape[0]), dev) for s in seeds]
+    soas = [s.t().contiguous() for s in seeds]
+    with torch.cuda.stream(stream):
+        for p1, (fg, _), soa in zip(plans1, sets, soas):
+            p1.run(fg, soa, opts32)
+    torch.cuda.synchronize()
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        s0.record(stream)
+        for p1, (fg, _), soa in zip(plans1, sets, soas):
+            p1.run(fg, soa, opts32)
+        s1.record(stream)
+    torch.cuda.synchronize()
+    ms_single = s0.elapsed_time(s1)
+    del plans1
+
+    # FP64 stepping of the same batch, and the FP32-vs-FP64 difference in Q
+    plan64 = TraceBatchPlan(sets, opts64)
+    with torch.cuda.stream(stream):
+        plan64.run()
+        torch.cuda.synchronize()
+        d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        d0.record(stream)
+        plan64.run()
+        d1.record(stream)
+    torch.cuda.synchronize()
+    ms64 = d0.elapsed_time(d1)
+    q32 = torch.cat([o["q_perp"] for o in plan.outs]).cpu().numpy()
+    q64 = torch.cat([o["q_perp"] for o in plan64.outs]).cpu().numpy()
+    st32 = torch.cat([o["status"] for o in plan.outs]).cpu().numpy()
+    st64 = torch.cat([o["status"] for o in plan64.outs]).cpu().numpy()
+    m = np.isfinite(q32) & np.isfinite(q64) & (q64 < 1e6) & (st32 == st64)
+    rel = np.abs(np.log10(q32[m]) - np.log10(q64[m])) / np.abs(np.log10(q64[m]))
+
+    out = {
+        "metric": METRIC,
+        "value": total / (ms_step / 1e3),
+        "unit": "lines/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"batched trace: {len(fields)} point-charge fields (2-8 charges, grids 64^3 to "
+                         f"256x256x128, FP32 storage), 1e4-1e6 random photospheric seeds each, one batched "
+                         f"call (one persistent stepping launch) replayed as a HIP graph, CK54 FP32 stepping "
+                         f"tol={args.tol:g}, h_max 1 cell of each grid, FP64 landing and Q"),
+            "fields": len(fields),
+            "lines_per_step": total,
+            "tol": args.tol,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_trace (batched, adaptive stepping)",
+            "achieved": achieved,
+            "peak": VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / VALU_PEAK_TFLOPS,
+            "traffic": None,
+            "launches": n_step,
+            "avg_launch_ms": ms_trace / max(n_step, 1),
+            "rhs_evals": evals,
+            "attempts": attempts,
+        },
+        "launch_shape": tuned,
+        "one_call_per_field_ms": ms_single,
+        "batch_speedup_vs_one_call_per_field": ms_single / ms_step,
+        "fp64_stepping": {"ms": ms64, "lines_per_s": total / (ms64 / 1e3),
+                          "median_rel_log10q_diff_fp32_vs_fp64": float(np.median(rel)),
+                          "p99": float(np.percentile(rel, 99)),
+                          "status_agreement": float((st32 == st64).mean())},
+        "setup_s": t_gen,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_batch(args, host)
+    print(json.dumps(out), flush=True)
+
+
+def bench_volume(args):
+    """A refined 3D Q / length / FLEDGE volume of the flux-rope field
+    (384x384x256 nodes): 256^3 base cells, two refinement levels, FP32 storage;
+    the same volume with BF16 node storage beside it, and the storage error
+    against the FP64 oracle on a fixed set of lines."""
+    import numpy as np
+    import torch
+
+    import paper_1609_00724_amd as q
+    import synth
+    from paper_1609_00724_amd import _abi as A
+    from paper_1609_00724_amd.api import Profiler, QMapPlan, VolumeSpec, make_opts
+
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    w = synth.flux_rope_c4(device=dev)
+    b = [torch.from_numpy(c).to(dev) for c in w["b"]]
+    f32 = q.field_init(*b, w["origin"], w["spacing"], storage="f32")
+    bf16 = q.field_init(*b, w["origin"], w["spacing"], storage="bf16")
+    del b
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    h = min(w["spacing"])
+    m, r = args.volume_level, args.refine_levels
+    spec = VolumeSpec(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0, m, r, m, args.threshold, args.refine_batch)
+    plan = QMapPlan(spec, 8 ** m * 4, dev)
+    opts = make_opts(args.tol, args.tol, h_init=0.1 * h, h_max=args.hmax_cells * h, step_dtype="f32")
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        plan.run(f32, opts)
+    torch.cuda.synchronize()
+    plan.work.zero_()
+    with Profiler() as prof:
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(args.steps):
+            plan.run(f32, opts)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms_step = t0.elapsed_time(t1) / args.steps
+        n_step, ms_trace = prof.read(A.KERNEL_STEP)
+    Profiler.reset()
+    res = plan.result()
+    lines = res["count"]
+    attempts, evals, stepped, landed = (int(v) for v in plan.work.cpu().numpy())
+    flops = FLOP_PER_EVAL * evals + FLOP_PER_ATTEMPT * attempts
+    achieved = flops / (ms_trace / 1e3) / 1e12
+    keys32 = res["keys"].cpu().numpy()
+    q32 = res["q_perp"].cpu().numpy()
+
+    plan16 = QMapPlan(spec, 8 ** m * 4, dev)
+    plan16.run(bf16, opts)
+    torch.cuda.synchronize()
+    b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b0.record(stream)
+    plan16.run(bf16, opts)
+    b1.record(stream)
+    torch.cuda.synchronize()
+    ms16 = b0.elapsed_time(b1)
+    r16 = plan16.result()
+    keys16 = r16["keys"].cpu().numpy()
+    q16 = r16["q_perp"].cpu().numpy()
+    common, i32, i16 = np.intersect1d(keys32, keys16, return_indices=True)
+    ok = np.isfinite(q32[i32]) & np.isfinite(q16[i16]) & (q32[i32] < 1e6)
+    d16 = np.abs(np.log10(q16[i16][ok]) - np.log10(q32[i32][ok])) / np.abs(np.log10(q32[i32][ok]))
+
+    out = {
+        "metric": METRIC,
+        "value": lines / (ms_step / 1e3),
+        "unit": "lines/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"3D Q/FLL/FLEDGE volume, flux rope over a 6-charge background on a 384x384x256 "
+                         f"FP32 grid, {1 << m}^3 base cells + FLL-jump 3D Hilbert refinement r={r} "
+                         f"thr={args.threshold}, CK54 FP32 stepping tol={args.tol:g}, FP64 landing and Q"),
+            "lines_per_step": lines,
+            "base_lines": 8 ** m,
+            "grid": list(w["n"]),
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_trace (adaptive stepping)",
+            "achieved": achieved,
+            "peak": VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / VALU_PEAK_TFLOPS,
+            "traffic": None,
+            "launches": n_step,
+            "avg_launch_ms": ms_trace / max(n_step, 1),
+        },
+        "bf16_storage": {"ms": ms16, "lines_per_s": r16["count"] / (ms16 / 1e3), "lines": r16["count"],
+                         "common_keys": int(common.size),
+                         "median_rel_log10q_diff_vs_fp32_storage": float(np.median(d16)),
+                         "p90": float(np.percentile(d16, 90)), "p99": float(np.percentile(d16, 99))},
+        "setup_s": t_gen,
+    }
+    if not args.no_accuracy:
+        out["accuracy"] = accuracy_volume(args, w, f32, bf16, h)
+    print(json.dumps(out), flush=True)
+
+
+def accuracy_volume(args, w, f32, bf16, h):
+    """Relative log10 Q error of FP32 and BF16 node storage (bench tolerance)
+    against the FP64 oracle on the FP64 field (tolerance 1e-10), at a fixed
+    seeded set of points in the box."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1609_00724_amd as q
+    import synth
+    seeds = synth.random_seeds(2025, args.accuracy_lines)
+    o = oracle.trace(_oracle_field(w), seeds, rtol=1e-10, atol=1e-10, h_init=0.1 * h, h_max=h)
+    res = {}
+    for name, fg in (("f32", f32), ("bf16", bf16)):
+        g = q.trace(fg, torch.from_numpy(seeds).cuda(), rtol=args.tol, atol=args.tol, h_init=0.1 * h,
+                    h_max=args.hmax_cells * h, step_dtype="f32")
+        torch.cuda.synchronize()
+        qg = g["q_perp"].cpu().numpy()
+        m = np.isfinite(o["q_perp"]) & np.isfinite(qg) & (o["q_perp"] < 1e6) & (g["status"].cpu().numpy() == o["status"])
+        rel = np.abs(np.log10(qg[m]) - np.log10(o["q_perp"][m])) / np.abs(np.log10(o["q_perp"][m]))
+        res[name] = {"median_rel_log10q_err": float(np.median(rel)), "p90": float(np.percentile(rel, 90)),
+                     "max": float(rel.max()), "lines": int(m.sum())}
+    res["reference"] = "FP64 oracle on the FP64 field, tol 1e-10"
+    return res
+
+
+def bench_learned(args):
+    """Learned refinement proposer: maps of seeded fields (3/4 point-charge
+    fields with 2-8 charges, 1/4 horizontal slices z ~ U[0.01, 0.3] of
+    flux-rope fields, 128x128x64 FP32 grids) give coarse 256^2 inputs (length,
+    FLEDGE, Bz) and targets from the same maps refined 4x by the FLL-jump rule
+    (refine mask, max log10 Q per pixel); the CNN trains on 9/10 of the maps
+    with the library's kernels and is judged on the rest against the plain
+    rule: recall of its mask, and the fraction of fine QSL pixels (Q > 1e3)
+    whose coarse pixel it does not propose."""
+    import numpy as np
+    import torch
+    import torch.nn.functional as F
+
+    import paper_1609_00724_amd as q
+    import synth
+    from paper_1609_00724_amd import learn
+    from paper_1609_00724_amd.api import MapSpec, QMapPlan, make_opts
+
+    dev = torch.device("cuda:0")
+    m, r, thr = 8, 2, args.threshold
+    n = (128, 128, 64)
+    origin, spacing = synth.grid_geometry(n)
+    h = min(spacing)
+    opts = make_opts(args.tol, args.tol, h_init=0.1 * h, h_max=h, step_dtype="f32")
+    coarse = QMapPlan(MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, 0, m, thr), 4 ** m, dev)
+    fine = QMapPlan(MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, r, m + r, thr), 4 ** m * 8, dev)
+    t_gen = time.perf_counter()
+    data = []
+    rng = synth.rng(5000)
+    for k in range(args.learn_fields):
+        rope = k % 4 == 3
+        seed = (6500 if rope else 5000) + k
+        if rope:
+            b, _ = synth.flux_rope_field(n, charges=None, device=dev)
+            z0 = float(rng.uniform(0.01, 0.3))
+        else:
+            b = synth.sample_charges(synth.point_charges(seed, int(synth.rng(seed).integers(2, 9))), n, device=dev)
+            z0 = 0.0
+        bt = [torch.from_numpy(c).to(dev) for c in b]
+        fg = q.field_init(*bt, origin, spacing, storage="f32")
+        coarse.d.z0 = z0
+        fine.d.z0 = z0
+        coarse.run(fg, opts)
+        fine.run(fg, opts)
+        # Bz on the slice: the nearest node layer, resampled to the coarse raster
+        kz = min(int(round((z0 - origin[2]) / spacing[2])), n[2] - 1)
+        bz = F.interpolate(bt[2][kz][None, None].float(), size=(1 << m, 1 << m), mode="bilinear",
+                           align_corners=False)[0, 0]
+        cres, fres = coarse.result(), fine.result()
+        qf = fres["q_grid"].clone()
+        qbase = F.max_pool2d(torch.nan_to_num(qf, nan=0.0)[None, None], 1 << r)[0, 0]
+        mask, logq = learn.refine_labels(fres["keys"], m, r, qbase)
+        x = learn.features(cres["fll_grid"], cres["fledge"], bz)
+        data.append(dict(x=x, mask=mask, logq=logq, qfine=qf if k % 10 == 0 else None, z0=z0, rope=rope,
+                         field=fg if k % 10 == 0 else None, lines_plain=fres["count"]))
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    train = [d for k, d in enumerate(data) if k % 10 != 0]
+    test = [d for k, d in enumerate(data) if k % 10 == 0]
+    X = torch.cat([learn.tiles(d["x"]) for d in train])
+    M = torch.cat([learn.tiles(d["mask"]) for d in train])
+    Lq = torch.cat([learn.tiles(d["logq"]) for d in train])
+    prop = learn.Proposer(learn.init_params(1, dev))
+    bs = 64
+    g = torch.Generator(device="cpu").manual_seed(0)
+    curve = []
+    t_train = time.perf_counter()
+    steps = 0
+    for ep in range(args.learn_epochs):
+        perm = torch.randperm(X.shape[0], generator=g).to(dev)
+        tot = torch.zeros((), dtype=torch.float64, device=dev)
+        nb = 0
+        for i0 in range(0, X.shape[0] - bs + 1, bs):
+            idx = perm[i0:i0 + bs]
+            tot += prop.train_step(X[idx], M[idx], Lq[idx], lr=2e-3, lam=0.1)
+            nb += 1
+            steps += 1
+        curve.append(float(tot) / max(nb, 1))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t_train
+    # training throughput of the kernels alone: one timed step on a full batch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        prop.train_step(X[:bs], M[:bs], Lq[:bs], lr=1e-9, lam=0.1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / 10
+    flop_fwd = 2 * 64 * 64 * sum(9 * ci * co for ci, co in zip(learn.CHANNELS[:-1], learn.CHANNELS[1:]))
+
+    # judge on held-out maps
+    tp = fn = fp = 0
+    miss_cnn = miss_plain = qsl_total = 0
+    prop_pixels = plain_pixels = 0
+    t_learned = t_plain = 0.0
+    lines_learned = lines_plain = 0
+    side = 1 << m
+    for d in test:
+        xt = learn.tiles(d["x"])
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record()
+        out = prop.forward(xt)
+        s1.record()
+        torch.cuda.synchronize()
+        pred = learn.untile(out, side, side)[..., 0] > 0
+        plain = d["mask"] > 0.5
+        tp += int((pred & plain).sum())
+        fn += int((~pred & plain).sum())
+        fp += int((pred & ~plain).sum())
+        prop_pixels += int(pred.sum())
+        plain_pixels += int(plain.sum())
+        qsl = torch.nan_to_num(d["qfine"], nan=0.0) > 1e3
+        up = lambda a: a.repeat_interleave(1 << r, 0).repeat_interleave(1 << r, 1)
+        qsl_total += int(qsl.sum())
+        miss_cnn += int((qsl & ~up(pred)).sum())
+        miss_plain += int((qsl & ~up(plain)).sum())
+        # cost: the learned path traces the 4^r fine cells of every proposed pixel
+        ys, xs = torch.nonzero(pred, as_tuple=True)
+        sub = torch.arange(1 << r, device=dev, dtype=torch.float64)
+        fy = (ys[:, None, None] * (1 << r) + sub[None, :, None]).expand(-1, 1 << r, 1 << r)
+        fx = (xs[:, None, None] * (1 << r) + sub[None, None, :]).expand(-1, 1 << r, 1 << r)
+        cell = 2.0 / (side << r)
+        seeds = torch.stack([-1.0 + (fx.reshape(-1) + 0.5) * cell, -1.0 + (fy.reshape(-1) + 0.5) * cell,
+                             torch.full((fx.numel(),), d["z0"], dtype=torch.float64, device=dev)], 1)
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        coarse.d.z0 = d["z0"]
+        coarse.run(d["field"], opts)
+        c1.record()
+        torch.cuda.synchronize()
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record()
+        if seeds.shape[0]:
+            q.trace(d["field"], seeds, rtol=args.tol, atol=args.tol, h_init=0.1 * h, h_max=h, step_dtype="f32")
+        f1.record()
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fine.d.z0 = d["z0"]
+        p0.record()
+        fine.run(d["field"], opts)
+        p1.record()
+        torch.cuda.synchronize()
+        t_learned += c0.elapsed_time(c1) + s0.elapsed_time(s1) + f0.elapsed_time(f1)
+        t_plain += p0.elapsed_time(p1)
+        lines_learned += side * side + seeds.shape[0]
+        lines_plain += d["lines_plain"]
+    out = {
+        "metric": "learned refinement proposer: training and judged proposals",
+        "value": bs * flop_fwd * 3 / (ms_step / 1e3) / 1e12,
+        "unit": "TFLOP/s (training step, BF16 matrix cores)",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": (f"{len(data)} maps (3/4 point-charge fields with 2-8 charges, 1/4 flux-rope "
+                                f"slices), 128x128x64 FP32 grids, coarse 256^2 -> 16 tiles of 64^2, targets from "
+                                f"the FLL-jump rule with 4x refinement thr={thr}"),
+                   "train_tiles": int(X.shape[0]), "test_maps": len(test), "epochs": args.learn_epochs,
+                   "batch": bs},
+        "train_step_ms": ms_step,
+        "mfma_peak_tflops_bf16": 2500.0,
+        "loss_curve": curve,
+        "train_s": t_train,
+        "data_s": t_gen,
+        "judge": {
+            "mask_recall": tp / max(tp + fn, 1),
+            "mask_precision": tp / max(tp + fp, 1),
+            "proposed_pixel_fraction": prop_pixels / (len(test) * side * side),
+            "plain_pixel_fraction": plain_pixels / (len(test) * side * side),
+            "missed_qsl_fraction_cnn": miss_cnn / max(qsl_total, 1),
+            "missed_qsl_fraction_plain_rule": miss_plain / max(qsl_total, 1),
+            "qsl_fine_pixels": qsl_total,
+        },
+        "pipeline": {"learned_ms": t_learned, "plain_ms": t_plain, "learned_lines": lines_learned,
+                     "plain_lines": lines_plain},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_batch(args, host):
+    """The oracle on a seeded sample of every field's seeds (the same fields,
+    tolerance and per-grid step limits)."""
+    import numpy as np
+
+    import oracle
+    import synth
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    g = synth.rng(7)
+    lines, dt = 0, 0.0
+    for f in host:
+        m = f["seeds"].shape[0]
+        pick = np.sort(g.choice(m, size=max(1, int(m * args.cpu_fraction)), replace=False))
+        b = synth.sample_charges(f["charges"], f["n"], dtype=np.float32)
+        fo = oracle.Field.grid(*(c.astype(np.float64) for c in b), f["origin"], f["spacing"])
+        del b
+        h = min(f["spacing"])
+        t0 = time.perf_counter()
+        oracle.trace(fo, f["seeds"][pick], rtol=args.tol, atol=args.tol, h_init=0.1 * h, h_max=h, nthreads=threads)
+        dt += time.perf_counter() - t0
+        lines += pick.size
+        del fo
+    return {"value": lines / dt, "unit": "lines/s", "cores": threads, "kind": "oracle",
+            "sample": f"{args.cpu_fraction:g} of each field's seeds ({lines} lines, {dt:.1f} s of tracing)"}
 
 
 def _oracle_field(w):
@@ -165,7 +702,7 @@ def _oracle_field(w):
     return oracle.Field.grid(*(c.astype(np.float64) for c in w["b"]), w["origin"], w["spacing"])
 
 
-def accuracy(args, field, w, h):
+def accuracy(args, field, w, h, hmax):
     """Median relative log10 Q error of the GPU (bench settings) against the FP64
     oracle at tolerance 1e-10, on a fixed seeded set of photospheric lines."""
     import numpy as np
@@ -176,7 +713,7 @@ def accuracy(args, field, w, h):
     import synth
     seeds = synth.random_seeds(2024, args.accuracy_lines, z=0.0)
     g = q.trace(field, torch.from_numpy(seeds).cuda(), rtol=args.tol, atol=args.tol,
-                h_init=0.1 * h, h_max=h, step_dtype="f32")
+                h_init=0.1 * h, h_max=hmax, step_dtype="f32")
     torch.cuda.synchronize()
     qg = g["q_perp"].cpu().numpy()
     o = oracle.trace(_oracle_field(w), seeds, rtol=1e-10, atol=1e-10, h_init=0.1 * h, h_max=h)
@@ -197,7 +734,8 @@ def cpu_baseline(args, w, h):
     plane = oracle.SlicePlane(0.0, -1.0, 1.0, -1.0, 1.0)
 
     def fn(p):
-        t = oracle.trace(fo, p, rtol=args.tol, atol=args.tol, h_init=0.1 * h, h_max=h, nthreads=threads)
+        t = oracle.trace(fo, p, rtol=args.tol, atol=args.tol, h_init=0.1 * h, h_max=args.hmax_cells * h,
+                         nthreads=threads)
         return {"fll": t["fll"], "q": t["q_perp"]}
 
     t0 = time.perf_counter()

@@ -94,7 +94,7 @@ typedef struct qsq_grid {
 /* A prepared field: POD descriptor of caller-owned device memory. */
 typedef struct qsq_field {
     qsq_grid grid;
-    int32_t storage;       /* QSQ_F64 or QSQ_F32 */
+    int32_t storage;       /* QSQ_F64, QSQ_F32 or QSQ_BF16 */
     int32_t mode;          /* QSQ_INTERP_* */
     void *nodes;           /* device: n0*n1*n2 records of 4 storage values:
                               PAPER (Bx/|B|, By/|B|, Bz/|B|, |B|),
@@ -113,8 +113,19 @@ typedef struct qsq_trace_opts {
     double max_length;     /* <= 0: unlimited; else stop each half-line there */
     int64_t max_steps;     /* step attempts per half-line; <= 0: 1 << 22 */
     int32_t flags;         /* QSQ_FLAG_* */
-    int32_t reserved;
+    int32_t launch;        /* launch shape of the stepping kernel, QSQ_LAUNCH(...);
+                              0 = library defaults.  Results do not depend on it
+                              (each line's arithmetic is the same in every shape). */
 } qsq_trace_opts;
+
+/* Launch-shape word of qsq_trace_opts.launch (what an autotuner varies):
+ *   lanes  resident-lane target of the persistent stepping launch, in units of
+ *          256 lanes per compute unit, 1..15 (0: 8)
+ *   wg     workgroup size code: 0 = 256, 1 = 64, 2 = 128 lanes
+ *   gather 0 = automatic, 1 = direct corner loads, 2 = per-lane LDS cache of
+ *          the last cell's corners (FP32 records and FP32 stepping, one field
+ *          per call, field below 2 GiB; otherwise direct) */
+#define QSQ_LAUNCH(lanes, wg, gather) (((lanes) & 15) | (((wg) & 3) << 4) | (((gather) & 3) << 6))
 
 /* Per-seed results (device arrays of n entries; fp_* are SoA planes 3 x n:
  * x at [0,n), y at [n,2n), z at [2n,3n)).  Any pointer except status may be
@@ -153,9 +164,11 @@ uint64_t qsq_field_bytes(const qsq_grid *g, int storage);
  * Prepare a field from three device arrays of node values (x fastest,
  * n0*n1*n2 each, type `in_dtype` = QSQ_F64 or QSQ_F32) into `ws` (device,
  * >= qsq_field_bytes, 16-byte aligned).  PAPER mode stores Bhat = B/|B| (0 where
- * |B| < 1e-30) and |B| per node; INTERP_NORMALIZE stores B.  Fills *out.
+ * |B| < 1e-30) and |B| per node; INTERP_NORMALIZE stores B.  Values are
+ * formed in FP64 and rounded to the storage type (BF16: to FP32, then to the
+ * nearest BF16, ties to even; 8 bytes per node).  Fills *out.
  * Errors: INVALID_ARG (null pointers, n < 2, spacing <= 0, bad enums),
- * WORKSPACE_TOO_SMALL, UNSUPPORTED (storage other than F64/F32), HIP.
+ * WORKSPACE_TOO_SMALL, UNSUPPORTED (storage other than F64/F32/BF16), HIP.
  */
 int qsq_field_init(const qsq_grid *g, const void *bx, const void *by, const void *bz,
                    int in_dtype, int storage, int mode, void *ws, uint64_t ws_bytes,
@@ -179,6 +192,43 @@ uint64_t qsq_trace_scratch_bytes(int64_t n);
  */
 int qsq_trace(const qsq_field *f, const double *seeds, int64_t n, const qsq_trace_opts *opts,
               const qsq_trace_out *out, void *scratch, uint64_t scratch_bytes, void *stream);
+
+/* ---- batched trace ------------------------------------------------------ */
+
+/* One seed set of a batched trace: a prepared field, its seeds and outputs. */
+typedef struct qsq_trace_set {
+    qsq_field field;       /* prepared by qsq_field_init; every set of a call has
+                              the same storage and mode (grids may differ) */
+    const double *seeds;   /* device FP64, SoA 3 x n */
+    int64_t n;             /* seeds of the set, >= 0 */
+    qsq_trace_out out;     /* results of the set's seeds (n entries, as for
+                              qsq_trace); out.work is ignored */
+} qsq_trace_set;
+
+#define QSQ_MAX_TRACE_SETS 65536
+
+/* Scratch bytes qsq_trace_batch needs for nsets sets of `total` seeds in all. */
+uint64_t qsq_trace_batch_scratch_bytes(int32_t nsets, int64_t total);
+
+/*
+ * Trace many seed sets, each in its own field, as one job: the same per-seed
+ * computation as qsq_trace (Sect. 3.1-3.5, eq. (1), (5), (9)-(11)), with the
+ * half-lines of all sets served from one work list to one persistent stepping
+ * launch, so that sets of uneven size and line length share the device.
+ * sets: host array of nsets entries (1 <= nsets <= QSQ_MAX_TRACE_SETS), read
+ * during the call only.  opts applies to every set, except that h_init <= 0
+ * and h_max <= 0 select 0.1 and 1 times each set's own smallest spacing.
+ * work: NULL or 4 device counters as in qsq_trace_out.work, summed over the
+ * batch.  scratch: device, >= qsq_trace_batch_scratch_bytes(nsets, total),
+ * 256-byte aligned.  The call enqueues kernel launches only (no memory
+ * copies or fills), so it can be captured in a HIP graph and replayed while
+ * sets, seeds, outputs and scratch stay at the same addresses.  Sets with
+ * n = 0 are skipped; a batch with no seeds enqueues nothing.  Errors:
+ * INVALID_ARG (naming the set), UNSUPPORTED, WORKSPACE_TOO_SMALL,
+ * COUNT_OVERFLOW (more than 2^30 seeds in all), HIP.
+ */
+int qsq_trace_batch(const qsq_trace_set *sets, int32_t nsets, const qsq_trace_opts *opts, uint64_t *work,
+                    void *scratch, uint64_t scratch_bytes, void *stream);
 
 /* ---- FLEDGE (Sect. 3.6) ------------------------------------------------ */
 
@@ -204,6 +254,16 @@ int qsq_fledge(const float *in, int ndim, const int64_t *shape, float *out, void
 int qsq_hilbert2_d2xy(int L, const uint64_t *d, int64_t n, uint32_t *x, uint32_t *y, void *stream);
 int qsq_hilbert2_xy2d(int L, const uint32_t *x, const uint32_t *y, int64_t n, uint64_t *d, void *stream);
 
+/*
+ * Hilbert curve on a 2^b cube (1 <= b <= 21), Skilling's transpose algorithm
+ * (AIP Conf. Proc. 707, 2004): the index holds, most significant first, bit
+ * b-1 of x, y, z, then bit b-2 of x, y, z, and so on; the curve starts at
+ * (0,0,0) and ends at (2^b-1, 0, 0).  Device arrays of n entries.
+ */
+int qsq_hilbert3_d2xyz(int b, const uint64_t *d, int64_t n, uint32_t *x, uint32_t *y, uint32_t *z, void *stream);
+int qsq_hilbert3_xyz2d(int b, const uint32_t *x, const uint32_t *y, const uint32_t *z, int64_t n, uint64_t *d,
+                       void *stream);
+
 /* ---- adaptive map of a slice (Sect. 3.6) -------------------------------- */
 
 typedef struct qsq_map_desc {
@@ -212,13 +272,14 @@ typedef struct qsq_map_desc {
     int32_t base_level;    /* m: 2^m x 2^m base pixels, sampled at centres */
     int32_t refine_levels; /* r: finest cells are 2^(m+r) per side (m + r <= 16) */
     int32_t out_level;     /* level of the output grids, m <= out_level <= m + r */
-    int32_t reserved;
+    int32_t refine_batch;  /* refinement levels decided per device round, 1..5 (see
+                              qsq_qmap); <= 0: min(2r, 4) */
     double threshold;      /* FLL jump that triggers a new sample (length units) */
 } qsq_map_desc;
 
 /* Results of qsq_qmap (device memory).  Samples are kept in curve order. */
 typedef struct qsq_map_out {
-    int64_t capacity;      /* entries available in each sample array (>= 4^m) */
+    int64_t capacity;      /* entries available in each sample array (>= 4^m; 8^m for volumes) */
     uint64_t *keys;        /* finest-level curve index of each sample */
     double *fll;           /* field-line length per sample */
     double *q_perp;        /* Q of eq. (11) per sample */
@@ -242,10 +303,40 @@ uint64_t qsq_qmap_scratch_bytes(const qsq_map_desc *d, int64_t capacity);
  * curve-successive samples whose keys differ by >= 2 and whose lengths differ
  * by more than `threshold`, a sample at key floor((k1+k2)/2), placed at the
  * centre of that finest cell; passes repeat (2r of them at most) until none
- * fires.  All passes run on the device without host synchronisation.
+ * fires.  The samples kept are exactly those of that pass-by-pass rule; the
+ * device decides `refine_batch` passes per round by tracing, for every gap
+ * that fires, all 2^b - 1 keys the next b passes could insert into it and then
+ * applying the rule to the traced values (fewer, larger launches; the keys
+ * the rule rejects are traced but not kept).  All rounds run on the device
+ * without host synchronisation.  Samples beyond `capacity`, or speculative
+ * keys beyond the trace slots (`capacity`), are dropped and set *overflow.
  * Errors: INVALID_ARG, UNSUPPORTED, WORKSPACE_TOO_SMALL, HIP.
  */
 int qsq_qmap(const qsq_field *f, const qsq_map_desc *d, const qsq_trace_opts *opts,
+             const qsq_map_out *out, void *scratch, uint64_t scratch_bytes, void *stream);
+
+/* ---- adaptive map of a volume (Sect. 3.6, 3D maps) ---------------------- */
+
+typedef struct qsq_volume_desc {
+    double x0, x1, y0, y1, z0, z1; /* axis-aligned volume */
+    int32_t base_level;    /* m: 2^m cells per axis, sampled at centres */
+    int32_t refine_levels; /* r: finest cells are 2^(m+r) per axis (m + r <= 21) */
+    int32_t out_level;     /* level of the output grids, m <= out_level <= m + r */
+    int32_t refine_batch;  /* as in qsq_map_desc */
+    double threshold;      /* FLL jump that triggers a new sample (length units) */
+} qsq_volume_desc;
+
+/* Scratch bytes qsq_vmap needs for a map with `capacity` samples. */
+uint64_t qsq_vmap_scratch_bytes(const qsq_volume_desc *d, int64_t capacity);
+
+/*
+ * Q / length / FLEDGE map of a volume: qsq_qmap's rule on the 3D Hilbert curve
+ * (qsq_hilbert3_*).  Base samples: the (2^m)^3 cell centres in level-m curve
+ * order q with key q*8^r + 8^r/2; the key gap halves over 3r passes.  Output
+ * grids are (2^out_level)^3 and the FLEDGE map (2^m)^3, C order [z][y][x];
+ * capacity >= 8^m.  Errors: INVALID_ARG, UNSUPPORTED, WORKSPACE_TOO_SMALL, HIP.
+ */
+int qsq_vmap(const qsq_field *f, const qsq_volume_desc *d, const qsq_trace_opts *opts,
              const qsq_map_out *out, void *scratch, uint64_t scratch_bytes, void *stream);
 
 /* ---- measurement -------------------------------------------------------- */

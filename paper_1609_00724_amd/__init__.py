@@ -12,8 +12,9 @@ from __future__ import annotations
 import ctypes as C
 import os
 
-__all__ = ["lib", "LIB_PATH", "Field", "field_init", "trace", "TracePlan", "fledge",
-           "hilbert2_d2xy", "hilbert2_xy2d", "qmap", "QMapPlan", "QsqError"]
+__all__ = ["lib", "LIB_PATH", "Field", "field_init", "trace", "TracePlan", "trace_batch", "TraceBatchPlan", "fledge",
+           "hilbert2_d2xy", "hilbert2_xy2d", "hilbert3_d2xyz", "hilbert3_xyz2d", "qmap", "QMapPlan",
+           "MapSpec", "VolumeSpec", "QsqError"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqsq.so")
@@ -28,5 +29,6 @@ if not os.path.exists(LIB_PATH):
 
 from . import _abi  # noqa: E402
 from ._abi import lib, QsqError  # noqa: E402
-from .api import (Field, field_init, trace, TracePlan, fledge, hilbert2_d2xy,  # noqa: E402
-                  hilbert2_xy2d, qmap, QMapPlan)
+from .api import (Field, field_init, trace, TracePlan, trace_batch, TraceBatchPlan, fledge,  # noqa: E402
+                  hilbert2_d2xy,
+                  hilbert2_xy2d, hilbert3_d2xyz, hilbert3_xyz2d, qmap, QMapPlan, MapSpec, VolumeSpec)

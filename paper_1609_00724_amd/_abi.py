@@ -27,9 +27,28 @@ STATUS_OPEN = 1 << 16
 EXPORTS = ["qsq_abi_version", "qsq_status_string", "qsq_last_error", "qsq_field_bytes",
            "qsq_field_init", "qsq_trace_scratch_bytes", "qsq_trace", "qsq_fledge",
            "qsq_hilbert2_d2xy", "qsq_hilbert2_xy2d", "qsq_qmap_scratch_bytes", "qsq_qmap",
-           "qsq_profile_enable", "qsq_profile_reset", "qsq_profile_read"]
+           "qsq_profile_enable", "qsq_profile_reset", "qsq_profile_read",
+           "qsq_hilbert3_d2xyz", "qsq_hilbert3_xyz2d", "qsq_vmap_scratch_bytes", "qsq_vmap",
+           "qsq_trace_batch_scratch_bytes", "qsq_trace_batch"]
+
+# every entry point include/qsq_cnn.h declares
+CNN_EXPORTS = ["qsq_cnn_prep_bytes", "qsq_cnn_prepare", "qsq_cnn_workspace_bytes", "qsq_cnn_layer_scratch_bytes",
+               "qsq_cnn_forward", "qsq_cnn_train_step", "qsq_cnn_layer_forward", "qsq_cnn_layer_backward"]
+CNN_PARAMS = 19970
+
+MAX_TRACE_SETS = 65536
 
 KERNEL_STEP, KERNEL_LAND, KERNEL_ASSEMBLE = 0, 1, 2
+
+WG_CODES = {256: 0, 64: 1, 128: 2}
+GATHER_AUTO, GATHER_DIRECT, GATHER_CACHED = 0, 1, 2
+
+
+def launch_word(lanes=0, wg=256, gather=GATHER_AUTO):
+    """QSQ_LAUNCH(lanes, wg, gather) of include/qsq.h."""
+    if not 0 <= lanes <= 15 or wg not in WG_CODES or gather not in (0, 1, 2):
+        raise ValueError("launch shape outside QSQ_LAUNCH(0..15, 64|128|256, 0..2)")
+    return (lanes & 15) | (WG_CODES[wg] << 4) | (gather << 6)
 
 
 class Grid(C.Structure):
@@ -45,7 +64,7 @@ class TraceOpts(C.Structure):
     _fields_ = [("stepper", C.c_int32), ("step_dtype", C.c_int32), ("rtol", C.c_double),
                 ("atol", C.c_double), ("h_init", C.c_double), ("h_max", C.c_double),
                 ("max_length", C.c_double), ("max_steps", C.c_int64), ("flags", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("launch", C.c_int32)]
 
 
 class TraceOut(C.Structure):
@@ -54,10 +73,21 @@ class TraceOut(C.Structure):
                 ("status", C.c_void_p), ("steps", C.c_void_p), ("work", C.c_void_p)]
 
 
+class TraceSet(C.Structure):
+    _fields_ = [("field", FieldDesc), ("seeds", C.c_void_p), ("n", C.c_int64), ("out", TraceOut)]
+
+
 class MapDesc(C.Structure):
     _fields_ = [("z0", C.c_double), ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double),
                 ("y1", C.c_double), ("base_level", C.c_int32), ("refine_levels", C.c_int32),
-                ("out_level", C.c_int32), ("reserved", C.c_int32), ("threshold", C.c_double)]
+                ("out_level", C.c_int32), ("refine_batch", C.c_int32), ("threshold", C.c_double)]
+
+
+class VolumeDesc(C.Structure):
+    _fields_ = [("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("z0", C.c_double), ("z1", C.c_double), ("base_level", C.c_int32),
+                ("refine_levels", C.c_int32), ("out_level", C.c_int32), ("refine_batch", C.c_int32),
+                ("threshold", C.c_double)]
 
 
 class MapOut(C.Structure):
@@ -89,6 +119,25 @@ def _load():
     L.qsq_trace.restype = I
     L.qsq_trace.argtypes = [C.POINTER(FieldDesc), P, I64, C.POINTER(TraceOpts), C.POINTER(TraceOut),
                             P, U64, P]
+    L.qsq_trace_batch_scratch_bytes.restype = U64
+    L.qsq_trace_batch_scratch_bytes.argtypes = [C.c_int32, I64]
+    L.qsq_trace_batch.restype = I
+    L.qsq_trace_batch.argtypes = [C.POINTER(TraceSet), C.c_int32, C.POINTER(TraceOpts), P, P, U64, P]
+    L.qsq_cnn_prep_bytes.restype = U64
+    L.qsq_cnn_prepare.restype = I
+    L.qsq_cnn_prepare.argtypes = [P, P, P]
+    L.qsq_cnn_workspace_bytes.restype = U64
+    L.qsq_cnn_workspace_bytes.argtypes = [I64, I, I]
+    L.qsq_cnn_layer_scratch_bytes.restype = U64
+    L.qsq_cnn_layer_scratch_bytes.argtypes = [I64, I, I]
+    L.qsq_cnn_forward.restype = I
+    L.qsq_cnn_forward.argtypes = [P, P, I64, I, I, P, P, U64, P]
+    L.qsq_cnn_train_step.restype = I
+    L.qsq_cnn_train_step.argtypes = [P, P, P, I64, C.c_float, P, P, P, I64, I, I, C.c_float, P, P, P, P, U64, P]
+    L.qsq_cnn_layer_forward.restype = I
+    L.qsq_cnn_layer_forward.argtypes = [I, P, P, I64, I, I, P, P]
+    L.qsq_cnn_layer_backward.restype = I
+    L.qsq_cnn_layer_backward.argtypes = [I, P, P, P, I64, I, I, P, P, P, P, U64, P]
     L.qsq_fledge.restype = I
     L.qsq_fledge.argtypes = [P, I, C.POINTER(C.c_int64), P, P]
     L.qsq_hilbert2_d2xy.restype = I
@@ -99,6 +148,15 @@ def _load():
     L.qsq_qmap_scratch_bytes.argtypes = [C.POINTER(MapDesc), I64]
     L.qsq_qmap.restype = I
     L.qsq_qmap.argtypes = [C.POINTER(FieldDesc), C.POINTER(MapDesc), C.POINTER(TraceOpts),
+                           C.POINTER(MapOut), P, U64, P]
+    L.qsq_hilbert3_d2xyz.restype = I
+    L.qsq_hilbert3_d2xyz.argtypes = [I, P, I64, P, P, P, P]
+    L.qsq_hilbert3_xyz2d.restype = I
+    L.qsq_hilbert3_xyz2d.argtypes = [I, P, P, P, I64, P, P]
+    L.qsq_vmap_scratch_bytes.restype = U64
+    L.qsq_vmap_scratch_bytes.argtypes = [C.POINTER(VolumeDesc), I64]
+    L.qsq_vmap.restype = I
+    L.qsq_vmap.argtypes = [C.POINTER(FieldDesc), C.POINTER(VolumeDesc), C.POINTER(TraceOpts),
                            C.POINTER(MapOut), P, U64, P]
     L.qsq_profile_enable.restype = I
     L.qsq_profile_enable.argtypes = [I]

@@ -10,7 +10,7 @@ import torch
 from . import _abi as A
 from ._abi import check, lib
 
-_DT = {"f64": A.F64, "f32": A.F32}
+_DT = {"f64": A.F64, "f32": A.F32, "bf16": A.BF16}
 _MODE = {"paper": A.INTERP_PAPER, "interp_normalize": A.INTERP_NORMALIZE}
 
 
@@ -72,7 +72,7 @@ def field_init(bx, by, bz, origin, spacing, storage="f32", mode="paper", stream=
 
 
 def make_opts(rtol, atol, h_init=0.0, h_max=0.0, max_length=0.0, max_steps=0, step_dtype="f32",
-              skip_open=False) -> A.TraceOpts:
+              skip_open=False, launch=0) -> A.TraceOpts:
     o = A.TraceOpts()
     o.stepper = A.STEPPER_CK54
     o.step_dtype = _DT[step_dtype]
@@ -80,6 +80,7 @@ def make_opts(rtol, atol, h_init=0.0, h_max=0.0, max_length=0.0, max_steps=0, st
     o.h_init, o.h_max, o.max_length = float(h_init), float(h_max), float(max_length)
     o.max_steps = int(max_steps)
     o.flags = A.FLAG_SKIP_OPEN if skip_open else 0
+    o.launch = int(launch)
     return o
 
 
@@ -127,6 +128,63 @@ def trace(field: Field, seeds, *, rtol, atol, h_init=0.0, h_max=0.0, max_length=
     return plan.run(field, soa, opts, stream)
 
 
+class TraceBatchPlan:
+    """A batched trace of several (field, seeds) sets with preallocated outputs
+    and scratch.  run() enqueues one qsq_trace_batch call; since every pointer
+    stays fixed, the call can be captured in a HIP graph and replayed."""
+
+    def __init__(self, sets, opts: A.TraceOpts, want=("fp_fwd", "fp_bwd", "fll", "q_perp", "q_det", "q_fp"),
+                 want_steps=False, want_work=False):
+        if not sets:
+            raise ValueError("need at least one set")
+        self.opts = opts
+        self.fields, self.seeds, self.outs = [], [], []
+        arr = (A.TraceSet * len(sets))()
+        total = 0
+        device = None
+        for k, (field, seeds) in enumerate(sets):
+            seeds = _dev(seeds, torch.float64, "seeds")
+            if seeds.dim() != 2 or seeds.shape[1] != 3:
+                raise ValueError("seeds must have shape (n, 3)")
+            soa = seeds.t().contiguous()
+            n = soa.shape[1]
+            device = seeds.device
+            f64 = dict(dtype=torch.float64, device=device)
+            out = {key: torch.empty((3, n) if key.startswith("fp_") else (n,), **f64) for key in want}
+            out["status"] = torch.empty(n, dtype=torch.int32, device=device)
+            if want_steps:
+                out["steps"] = torch.empty((2, n), dtype=torch.int32, device=device)
+            t = arr[k]
+            t.field = field.desc
+            t.seeds = _p(soa)
+            t.n = n
+            for key in ("fp_fwd", "fp_bwd", "fll", "q_perp", "q_det", "q_fp", "status", "steps"):
+                setattr(t.out, key, _p(out.get(key)))
+            self.fields.append(field)
+            self.seeds.append(soa)
+            self.outs.append(out)
+            total += n
+        self.sets = arr
+        self.total = total
+        self.work = torch.zeros(4, dtype=torch.int64, device=device) if want_work else None
+        self.scratch = _bytes_tensor(lib.qsq_trace_batch_scratch_bytes(len(sets), total), device)
+
+    def run(self, stream=None):
+        check(lib.qsq_trace_batch(self.sets, len(self.outs), C.byref(self.opts), _p(self.work), _p(self.scratch),
+                                  self.scratch.numel() * 8, _stream(stream)))
+        return self.outs
+
+
+def trace_batch(sets, *, rtol, atol, h_init=0.0, h_max=0.0, max_length=0.0, max_steps=0, step_dtype="f32",
+                skip_open=False, want_steps=False, want_work=False, stream=None):
+    """Trace several (field, seeds (n, 3)) sets in one batched call; returns one
+    output dict per set (as trace()) and, if asked, the summed work counters."""
+    opts = make_opts(rtol, atol, h_init, h_max, max_length, max_steps, step_dtype, skip_open)
+    plan = TraceBatchPlan(sets, opts, want_steps=want_steps, want_work=want_work)
+    outs = plan.run(stream)
+    return (outs, plan.work) if want_work else outs
+
+
 def fledge(x: torch.Tensor, stream=None) -> torch.Tensor:
     """Sobel FLEDGE magnitude of a 2D or 3D float32 device map."""
     x = _dev(x, torch.float32, "map")
@@ -152,6 +210,20 @@ def hilbert2_xy2d(L: int, x: torch.Tensor, y: torch.Tensor, stream=None):
     return d
 
 
+def hilbert3_d2xyz(b: int, d: torch.Tensor, stream=None):
+    d = _dev(d, torch.int64, "d")
+    x, y, z = (torch.empty(d.shape, dtype=torch.int32, device=d.device) for _ in range(3))
+    check(lib.qsq_hilbert3_d2xyz(b, _p(d), d.numel(), _p(x), _p(y), _p(z), _stream(stream)))
+    return x, y, z
+
+
+def hilbert3_xyz2d(b: int, x, y, z, stream=None):
+    x, y, z = (_dev(v, torch.int32, "cell") for v in (x, y, z))
+    d = torch.empty(x.shape, dtype=torch.int64, device=x.device)
+    check(lib.qsq_hilbert3_xyz2d(b, _p(x), _p(y), _p(z), x.numel(), _p(d), _stream(stream)))
+    return d
+
+
 @dataclass
 class MapSpec:
     z0: float
@@ -163,17 +235,43 @@ class MapSpec:
     refine_levels: int
     out_level: int
     threshold: float
+    refine_batch: int = 0   # refinement levels per device round; 0: all in one round
 
     def desc(self) -> A.MapDesc:
         d = A.MapDesc()
         d.z0, d.x0, d.x1, d.y0, d.y1 = self.z0, self.x0, self.x1, self.y0, self.y1
         d.base_level, d.refine_levels, d.out_level = self.base_level, self.refine_levels, self.out_level
+        d.refine_batch = self.refine_batch
+        d.threshold = self.threshold
+        return d
+
+
+@dataclass
+class VolumeSpec:
+    x0: float
+    x1: float
+    y0: float
+    y1: float
+    z0: float
+    z1: float
+    base_level: int
+    refine_levels: int
+    out_level: int
+    threshold: float
+    refine_batch: int = 0
+
+    def desc(self) -> A.VolumeDesc:
+        d = A.VolumeDesc()
+        d.x0, d.x1, d.y0, d.y1, d.z0, d.z1 = self.x0, self.x1, self.y0, self.y1, self.z0, self.z1
+        d.base_level, d.refine_levels, d.out_level = self.base_level, self.refine_levels, self.out_level
+        d.refine_batch = self.refine_batch
         d.threshold = self.threshold
         return d
 
 
 class QMapPlan:
-    """Preallocated sample arrays, grids and scratch for repeated slice maps."""
+    """Preallocated sample arrays, grids and scratch for repeated slice maps
+    (MapSpec) or volume maps (VolumeSpec)."""
 
     def __init__(self, spec: MapSpec, capacity: int, device, grids=True, fledge_map=True):
         """Work counters (step attempts, RHS evaluations, half-lines stepped,
@@ -181,6 +279,7 @@ class QMapPlan:
         self.spec = spec
         self.capacity = int(capacity)
         self.d = spec.desc()
+        self.dims = 3 if isinstance(spec, VolumeSpec) else 2
         cap = self.capacity
         self.keys = torch.empty(cap, dtype=torch.int64, device=device)
         self.fll = torch.empty(cap, dtype=torch.float64, device=device)
@@ -190,11 +289,13 @@ class QMapPlan:
         self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
         side = 1 << spec.out_level
         bside = 1 << spec.base_level
-        self.q_grid = torch.empty((side, side), dtype=torch.float32, device=device) if grids else None
-        self.fll_grid = torch.empty((side, side), dtype=torch.float32, device=device) if grids else None
-        self.fledge = torch.empty((bside, bside), dtype=torch.float32, device=device) if fledge_map else None
+        gshape, bshape = (side,) * self.dims, (bside,) * self.dims
+        self.q_grid = torch.empty(gshape, dtype=torch.float32, device=device) if grids else None
+        self.fll_grid = torch.empty(gshape, dtype=torch.float32, device=device) if grids else None
+        self.fledge = torch.empty(bshape, dtype=torch.float32, device=device) if fledge_map else None
         self.work = torch.zeros(4, dtype=torch.int64, device=device)
-        self.scratch = _bytes_tensor(lib.qsq_qmap_scratch_bytes(C.byref(self.d), cap), device)
+        sizer = lib.qsq_vmap_scratch_bytes if self.dims == 3 else lib.qsq_qmap_scratch_bytes
+        self.scratch = _bytes_tensor(sizer(C.byref(self.d), cap), device)
         o = A.MapOut()
         o.capacity = cap
         o.keys, o.fll, o.q_perp, o.status = _p(self.keys), _p(self.fll), _p(self.q_perp), _p(self.status)
@@ -204,8 +305,9 @@ class QMapPlan:
         self.mout = o
 
     def run(self, field: Field, opts: A.TraceOpts, stream=None):
-        check(lib.qsq_qmap(C.byref(field.desc), C.byref(self.d), C.byref(opts), C.byref(self.mout),
-                           _p(self.scratch), self.scratch.numel() * 8, _stream(stream)))
+        fn = lib.qsq_vmap if self.dims == 3 else lib.qsq_qmap
+        check(fn(C.byref(field.desc), C.byref(self.d), C.byref(opts), C.byref(self.mout),
+                 _p(self.scratch), self.scratch.numel() * 8, _stream(stream)))
         return self
 
     def result(self):
@@ -215,7 +317,7 @@ class QMapPlan:
                     fll_grid=self.fll_grid, fledge=self.fledge)
 
 
-def qmap(field: Field, spec: MapSpec, capacity: int, *, rtol, atol, h_init=0.0, h_max=0.0,
+def qmap(field: Field, spec, capacity: int, *, rtol, atol, h_init=0.0, h_max=0.0,
          max_length=0.0, max_steps=0, step_dtype="f32", skip_open=False, stream=None):
     plan = QMapPlan(spec, capacity, field.ws.device)
     opts = make_opts(rtol, atol, h_init, h_max, max_length, max_steps, step_dtype, skip_open)

@@ -1,0 +1,122 @@
+"""Launch-shape autotuner for the persistent stepping kernel.
+
+Candidates are QSQ_LAUNCH words (resident-lane target per compute unit,
+workgroup size, corner-gather variant).  Each is timed with HIP events on a
+sample of the caller's own seeds and the fastest is kept.  Every candidate
+computes the same result (a line's arithmetic does not depend on where it
+runs), so tuning only moves time.  Choices are cached per (device, grid,
+storage, mode, step dtype, tolerance) in memory and, if QSQ_TUNE_CACHE names a
+file, in that JSON file.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import _abi as A
+
+DEFAULT_LANES = (2, 3, 4, 6, 8, 12)
+DEFAULT_WG = (64, 128, 256)
+
+_cache: dict = {}
+
+
+def candidates(lanes=DEFAULT_LANES, wgs=DEFAULT_WG, gathers=(A.GATHER_DIRECT, A.GATHER_CACHED)):
+    return [A.launch_word(l, w, g) for g in gathers for w in wgs for l in lanes]
+
+
+def _key(field, opts, tag):
+    d = field.desc
+    name = torch.cuda.get_device_name(torch.cuda.current_device())
+    return "|".join(str(v) for v in (name, tag, tuple(d.grid.n), d.storage, d.mode, opts.step_dtype, opts.rtol,
+                                     opts.atol, opts.h_max))
+
+
+def _load():
+    path = os.environ.get("QSQ_TUNE_CACHE")
+    if path and os.path.exists(path):
+        with open(path) as f:
+            _cache.update(json.load(f))
+
+
+def _store():
+    path = os.environ.get("QSQ_TUNE_CACHE")
+    if path:
+        with open(path, "w") as f:
+            json.dump(_cache, f, indent=1, sort_keys=True)
+
+
+def _time(run, reps):
+    s = torch.cuda.current_stream()
+    run()                               # warm-up (first touch, instruction cache)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        run()
+        b.record(s)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune_trace(field, seeds, opts, reps=3, cands=None, use_cache=True):
+    """Fastest launch word for tracing `seeds` ((n, 3) device tensor, a sample
+    of the workload) in `field` with `opts`.  Returns (word, {word: ms})."""
+    from .api import TracePlan
+    key = _key(field, opts, "trace")
+    if use_cache:
+        _load()
+        if key in _cache:
+            return int(_cache[key]["word"]), {int(k): v for k, v in _cache[key]["ms"].items()}
+    soa = seeds.t().contiguous()
+    plan = TracePlan(soa.shape[1], seeds.device)
+    saved = opts.launch
+    table = {}
+    for w in cands or candidates():
+        opts.launch = w
+        table[w] = _time(lambda: plan.run(field, soa, opts), reps)
+    opts.launch = saved
+    best = min(table, key=table.get)
+    _cache[key] = {"word": best, "ms": {str(k): v for k, v in table.items()}}
+    _store()
+    return best, table
+
+
+def tune_batch(sets, opts, reps=3, cands=None):
+    """Fastest launch word for a batched trace of `sets` ((field, seeds) pairs;
+    the batch uses direct gathers, so only lanes and workgroup size vary)."""
+    from .api import TraceBatchPlan
+    plan = TraceBatchPlan(sets, opts)
+    saved = opts.launch
+    table = {}
+    for w in cands or candidates(gathers=(A.GATHER_DIRECT,)):
+        opts.launch = w
+        plan.opts = opts
+        table[w] = _time(plan.run, reps)
+    opts.launch = saved
+    best = min(table, key=table.get)
+    return best, table
+
+
+def describe(word):
+    lanes = word & 15 or 8
+    wg = {0: 256, 1: 64, 2: 128}[(word >> 4) & 3]
+    gather = {0: "auto", 1: "direct", 2: "lds-cache"}[(word >> 6) & 3]
+    return {"word": int(word), "lanes_per_cu": lanes * 256, "workgroup": wg, "gather": gather}
+
+
+def tune_map(plan, field, opts, reps=3, cands=None):
+    """Fastest launch word for a whole map call (QMapPlan) on `field`: the
+    tuned workload is the real one (base lattice, refinement rounds)."""
+    saved = opts.launch
+    table = {}
+    for w in cands or candidates():
+        opts.launch = w
+        table[w] = _time(lambda: plan.run(field, opts), reps)
+    opts.launch = saved
+    best = min(table, key=table.get)
+    return best, table

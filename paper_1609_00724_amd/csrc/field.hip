@@ -1,7 +1,7 @@
 // Field preparation (Sect. 3.2; footnote to Sect. 3.5): one streaming pass that
-// turns three node arrays of B into 4-vector node records.  PAPER mode stores
-// (B/|B|, |B|) with the normalisation done in FP64 (zero direction where
-// |B| < 1e-30); INTERP_NORMALIZE stores (B, 0).
+// turns three node arrays of B into 4-vector node records (FP64, FP32 or BF16).
+// PAPER mode stores (B/|B|, |B|) with the normalisation done in FP64 (zero
+// direction where |B| < 1e-30); INTERP_NORMALIZE stores (B, 0).
 #include <math.h>
 
 #include "qsq_internal.h"
@@ -24,6 +24,18 @@ __device__ __forceinline__ void store4(double *o, int64_t i, double a, double b,
     double2 *q = reinterpret_cast<double2 *>(o) + 2 * i;
     q[0] = make_double2(a, b);
     q[1] = make_double2(c, d);
+}
+
+// BF16: the value rounded to FP32, then to the nearest BF16 (ties to even)
+__device__ __forceinline__ uint32_t bf16_bits(double x)
+{
+    const uint32_t u = __float_as_uint((float)x);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ void store4(Bf16 *o, int64_t i, double a, double b, double c, double d)
+{
+    reinterpret_cast<uint2 *>(o)[i] = make_uint2(bf16_bits(a) | (bf16_bits(b) << 16), bf16_bits(c) | (bf16_bits(d) << 16));
 }
 
 template <typename I, typename S, int MODE>
@@ -66,9 +78,11 @@ hipError_t launch_field_init(const qsq_grid *g, const void *bx, const void *by, 
     const int64_t N = g->n[0] * g->n[1] * g->n[2];
     if (in_dtype == QSQ_F64) {
         if (storage == QSQ_F32) go<double, float>(bx, by, bz, mode, ws, N, st);
+        else if (storage == QSQ_BF16) go<double, Bf16>(bx, by, bz, mode, ws, N, st);
         else go<double, double>(bx, by, bz, mode, ws, N, st);
     } else {
         if (storage == QSQ_F32) go<float, float>(bx, by, bz, mode, ws, N, st);
+        else if (storage == QSQ_BF16) go<float, Bf16>(bx, by, bz, mode, ws, N, st);
         else go<float, double>(bx, by, bz, mode, ws, N, st);
     }
     return hipGetLastError();

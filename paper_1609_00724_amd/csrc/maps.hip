@@ -67,6 +67,105 @@ __host__ __device__ __forceinline__ uint64_t h2_index(int L, uint32_t x, uint32_
     return d;
 }
 
+// ---------------------------------------------------------------------------
+// Hilbert curve in 3D: Skilling's transpose algorithm (AIP Conf. Proc. 707,
+// 2004) on three b-bit axes.  The index holds, most significant first, bit
+// b-1 of x, y, z, then bit b-2 of x, y, z, ...
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ void h3_cell(int b, uint64_t d, uint32_t &x, uint32_t &y, uint32_t &z)
+{
+    uint32_t a0 = 0, a1 = 0, a2 = 0;
+    for (int j = 0; j < b; ++j) {
+        a0 |= (uint32_t)((d >> (3 * j + 2)) & 1u) << j;
+        a1 |= (uint32_t)((d >> (3 * j + 1)) & 1u) << j;
+        a2 |= (uint32_t)((d >> (3 * j)) & 1u) << j;
+    }
+    // Gray decode
+    const uint32_t t0 = a2 >> 1;
+    a2 ^= a1;
+    a1 ^= a0;
+    a0 ^= t0;
+    // undo the per-level rotations and reflections, finest level first
+    const uint32_t top = 2u << (b - 1);
+    for (uint32_t Q = 2; Q != top; Q <<= 1) {
+        const uint32_t P = Q - 1;
+        uint32_t *ax[3] = {&a0, &a1, &a2};
+        for (int i = 2; i >= 0; --i) {
+            uint32_t &ai = *ax[i];
+            if (ai & Q) {
+                a0 ^= P;
+            } else {
+                const uint32_t t = (a0 ^ ai) & P;
+                a0 ^= t;
+                ai ^= t;
+            }
+        }
+    }
+    x = a0;
+    y = a1;
+    z = a2;
+}
+
+__host__ __device__ __forceinline__ uint64_t h3_index(int b, uint32_t x, uint32_t y, uint32_t z)
+{
+    uint32_t a[3] = {x, y, z};
+    const uint32_t M = 1u << (b - 1);
+    for (uint32_t Q = M; Q > 1; Q >>= 1) {
+        const uint32_t P = Q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (a[i] & Q) {
+                a[0] ^= P;
+            } else {
+                const uint32_t t = (a[0] ^ a[i]) & P;
+                a[0] ^= t;
+                a[i] ^= t;
+            }
+        }
+    }
+    a[1] ^= a[0];
+    a[2] ^= a[1];
+    uint32_t t = 0;
+    for (uint32_t Q = M; Q > 1; Q >>= 1)
+        if (a[2] & Q) t ^= Q - 1;
+    uint64_t d = 0;
+    for (int j = 0; j < b; ++j) {
+        d |= (uint64_t)(((a[0] ^ t) >> j) & 1u) << (3 * j + 2);
+        d |= (uint64_t)(((a[1] ^ t) >> j) & 1u) << (3 * j + 1);
+        d |= (uint64_t)(((a[2] ^ t) >> j) & 1u) << (3 * j);
+    }
+    return d;
+}
+
+// cell of a curve index at a level, for slices (DIM 2, z = 0) and volumes
+template <int DIM>
+__host__ __device__ __forceinline__ void cell_of_key(int level, uint64_t k, uint32_t c[3])
+{
+    if (DIM == 2) {
+        h2_cell(level, k, c[0], c[1]);
+        c[2] = 0;
+    } else {
+        h3_cell(level, k, c[0], c[1], c[2]);
+    }
+}
+
+template <int DIM>
+__host__ __device__ __forceinline__ uint64_t key_of_cell(int level, const uint32_t c[3])
+{
+    return DIM == 2 ? h2_index(level, c[0], c[1]) : h3_index(level, c[0], c[1], c[2]);
+}
+
+__global__ void k_h3_d2xyz(int b, const uint64_t *d, int64_t n, uint32_t *x, uint32_t *y, uint32_t *z)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        h3_cell(b, d[i], x[i], y[i], z[i]);
+}
+
+__global__ void k_h3_xyz2d(int b, const uint32_t *x, const uint32_t *y, const uint32_t *z, int64_t n, uint64_t *d)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = h3_index(b, x[i], y[i], z[i]);
+}
+
 __global__ void k_h2_d2xy(int L, const uint64_t *d, int64_t n, uint32_t *x, uint32_t *y)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -100,6 +199,20 @@ hipError_t launch_hilbert2_d2xy(int L, const uint64_t *d, int64_t n, uint32_t *x
 hipError_t launch_hilbert2_xy2d(int L, const uint32_t *x, const uint32_t *y, int64_t n, uint64_t *d, hipStream_t s)
 {
     if (n > 0) hipLaunchKernelGGL(k_h2_xy2d, dim3(grid_for(n)), dim3(256), 0, s, L, x, y, n, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_hilbert3_d2xyz(int b, const uint64_t *d, int64_t n, uint32_t *x, uint32_t *y, uint32_t *z,
+                                 hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_h3_d2xyz, dim3(grid_for(n)), dim3(256), 0, s, b, d, n, x, y, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_hilbert3_xyz2d(int b, const uint32_t *x, const uint32_t *y, const uint32_t *z, int64_t n,
+                                 uint64_t *d, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_h3_xyz2d, dim3(grid_for(n)), dim3(256), 0, s, b, x, y, z, n, d);
     return hipGetLastError();
 }
 
@@ -169,8 +282,10 @@ hipError_t launch_fledge(const float *in, int ndim, const int64_t *shape, float 
 // ---------------------------------------------------------------------------
 // slice refinement
 // ---------------------------------------------------------------------------
-struct Slice {
-    double z0, x0, y0, dx, dy;   // pixel size at the finest level: dx, dy
+// Sampled region: a horizontal slice (DIM 2, z = lo[2]) or an axis-aligned
+// volume (DIM 3); d = cell size at the finest level m + r.
+struct Region {
+    double lo[3], d[3];
     int m, r, L;                 // base level, refine levels, finest level
     double thr;
 };
@@ -181,17 +296,17 @@ struct Samples {
     int32_t *status;
 };
 
-// base lattice: pixel q of level m at its centre, key q*4^r + 4^r/2
-__global__ void k_base_seeds(Slice sl, int64_t nb, int64_t stride, double *seeds, uint64_t *keys)
+// base lattice: cell q of level m at its centre, key q B^r + B^r/2 (B = 2^DIM)
+template <int DIM>
+__global__ void k_base_seeds(Region rg, int64_t nb, int64_t stride, double *seeds, uint64_t *keys)
 {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nb; q += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t ix, iy;
-        h2_cell(sl.m, (uint64_t)q, ix, iy);
-        const double f = (double)(1u << sl.r);   // base pixel = f finest pixels
-        seeds[q] = sl.x0 + ((double)ix + 0.5) * f * sl.dx;
-        seeds[stride + q] = sl.y0 + ((double)iy + 0.5) * f * sl.dy;
-        seeds[2 * stride + q] = sl.z0;
-        const uint64_t blk = (uint64_t)1 << (2 * sl.r);
+        uint32_t c[3];
+        cell_of_key<DIM>(rg.m, (uint64_t)q, c);
+        const double f = (double)(1u << rg.r);   // base cell = f finest cells per axis
+        for (int a = 0; a < 3; ++a)
+            seeds[a * stride + q] = (a < DIM) ? rg.lo[a] + ((double)c[a] + 0.5) * f * rg.d[a] : rg.lo[a];
+        const uint64_t blk = (uint64_t)1 << (DIM * rg.r);
         keys[q] = (uint64_t)q * blk + blk / 2;
     }
 }
@@ -202,14 +317,15 @@ __global__ void k_set_count(int64_t *c, int64_t v, int32_t *overflow)
     *overflow = 0;
 }
 
-// base length map in raster order for the Sobel FLEDGE
-__global__ void k_fll_raster(Slice sl, int64_t nb, const double *fll, float *img)
+// base length map in raster order (x fastest) for the Sobel FLEDGE
+template <int DIM>
+__global__ void k_fll_raster(Region rg, int64_t nb, const double *fll, float *img)
 {
-    const uint32_t side = 1u << sl.m;
+    const int64_t side = (int64_t)1 << rg.m;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nb; q += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t ix, iy;
-        h2_cell(sl.m, (uint64_t)q, ix, iy);
-        img[(int64_t)iy * side + ix] = (float)fll[q];
+        uint32_t c[3];
+        cell_of_key<DIM>(rg.m, (uint64_t)q, c);
+        img[((int64_t)c[2] * side + c[1]) * side + c[0]] = (float)fll[q];
     }
 }
 
@@ -218,6 +334,14 @@ __device__ __forceinline__ int fires(const Samples &a, int64_t i, int64_t count,
     if (i + 1 >= count) return 0;
     const uint64_t k0 = a.keys[i], k1 = a.keys[i + 1];
     return (k1 - k0 >= 2) && (fabs(a.fll[i + 1] - a.fll[i]) > thr) ? 1 : 0;
+}
+
+// fire flag of the gap after each sample
+__global__ void k_fire(Samples a, const int64_t *count_in, double thr, int32_t *flag)
+{
+    const int64_t count = *count_in;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        flag[i] = fires(a, i, count, thr);
 }
 
 constexpr int kScanPer = 4;                      // elements per thread
@@ -241,7 +365,8 @@ __device__ __forceinline__ int64_t block_incl_scan(int64_t v, int64_t *lds, int6
     return v + pre;
 }
 
-__global__ void __launch_bounds__(256) k_scan_sums(Samples a, const int64_t *count_in, double thr, int64_t *bsum)
+// exclusive scan of v[0..count), three kernels: block sums, block offsets, apply
+__global__ void __launch_bounds__(256) k_scan_sums(const int32_t *v, const int64_t *count_in, int64_t *bsum)
 {
     __shared__ int64_t lds[4];
     const int64_t count = *count_in;
@@ -250,18 +375,16 @@ __global__ void __launch_bounds__(256) k_scan_sums(Samples a, const int64_t *cou
         if (threadIdx.x == 0) bsum[blockIdx.x] = 0;
         return;
     }
-    int64_t v = 0;
+    int64_t s = 0;
     const int64_t i0 = b0 + (int64_t)threadIdx.x * kScanPer;
-    for (int k = 0; k < kScanPer; ++k) v += fires(a, i0 + k, count, thr);
+    for (int k = 0; k < kScanPer; ++k)
+        if (i0 + k < count) s += v[i0 + k];
     int64_t tot;
-    block_incl_scan(v, lds, tot);
+    block_incl_scan(s, lds, tot);
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-// single block: exclusive offsets of the block sums, new-sample count, capacity
-__global__ void __launch_bounds__(256) k_scan_top(int64_t nblocks, int64_t *bsum, const int64_t *count_in,
-                                                  int64_t *count_out, int64_t *n_new, int64_t capacity,
-                                                  int32_t *overflow)
+__global__ void __launch_bounds__(256) k_scan_top(int64_t nblocks, int64_t *bsum, int64_t *total)
 {
     __shared__ int64_t lds[4];
     __shared__ int64_t carry;
@@ -269,106 +392,222 @@ __global__ void __launch_bounds__(256) k_scan_top(int64_t nblocks, int64_t *bsum
     __syncthreads();
     for (int64_t b0 = 0; b0 < nblocks; b0 += 256) {
         const int64_t i = b0 + threadIdx.x;
-        const int64_t v = i < nblocks ? bsum[i] : 0;
+        const int64_t x = i < nblocks ? bsum[i] : 0;
         int64_t tot;
-        const int64_t incl = block_incl_scan(v, lds, tot);
-        if (i < nblocks) bsum[i] = carry + incl - v;
+        const int64_t incl = block_incl_scan(x, lds, tot);
+        if (i < nblocks) bsum[i] = carry + incl - x;
         __syncthreads();
         if (threadIdx.x == 0) carry += tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const int64_t cnt = *count_in;
-        int64_t add = carry;
-        if (cnt + add > capacity) {
-            add = capacity - cnt;
-            *overflow = 1;
-        }
-        *n_new = add;
-        *count_out = cnt + add;
-    }
+    if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ void __launch_bounds__(256) k_scan_apply(Samples a, const int64_t *count_in, double thr,
-                                                    const int64_t *boff, int32_t *pos)
+__global__ void __launch_bounds__(256) k_scan_apply(const int32_t *v, const int64_t *count_in, const int64_t *boff,
+                                                    int32_t *off)
 {
     __shared__ int64_t lds[4];
     const int64_t count = *count_in;
     const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
     if (b0 >= count) return;
     const int64_t i0 = b0 + (int64_t)threadIdx.x * kScanPer;
-    int f[kScanPer];
-    int64_t v = 0;
+    int32_t x[kScanPer];
+    int64_t s = 0;
     for (int k = 0; k < kScanPer; ++k) {
-        f[k] = fires(a, i0 + k, count, thr);
-        v += f[k];
+        x[k] = i0 + k < count ? v[i0 + k] : 0;
+        s += x[k];
     }
     int64_t tot;
-    const int64_t incl = block_incl_scan(v, lds, tot);
-    int64_t run = boff[blockIdx.x] + incl - v;
+    const int64_t incl = block_incl_scan(s, lds, tot);
+    int64_t run = boff[blockIdx.x] + incl - s;
     for (int k = 0; k < kScanPer; ++k) {
-        if (i0 + k < count) pos[i0 + k] = (int32_t)run;
-        run += f[k];
+        if (i0 + k < count) off[i0 + k] = (int32_t)run;
+        run += x[k];
     }
 }
 
-// midpoint keys and their seeds (centre of the finest cell)
-__global__ void k_new_seeds(Slice sl, Samples a, const int64_t *count_in, const int64_t *n_new,
-                            const int32_t *pos, int64_t stride, double *seeds, uint64_t *nkeys)
+// A refinement round decides D levels at once: every firing gap (size G keys)
+// gets its S = 2^D - 1 interior keys at spacing unit = G / 2^D traced.
+struct Round {
+    int D, S;
+    uint64_t unit;
+};
+
+// Round set-up on the device: rem levels are left; the round decides
+// D = min(batch, rem) levels at once, fewer if the firing gaps' speculative
+// keys would not fit the trace slots (D = 1 always fits: one key per firing
+// gap, and gaps are fewer than samples).  When no gap fires, no gap can fire at
+// a finer level either (the samples do not change), so the refinement is over.
+__global__ void k_round_setup(const int64_t *n_fire, int batch, int64_t slots, int64_t *rem, Round *rd,
+                              int64_t *n_eff, int64_t *n_seeds, int32_t *overflow)
 {
-    const int64_t count = *count_in, nn = *n_new;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
-        if (!fires(a, i, count, sl.thr)) continue;
-        const int64_t p = pos[i];
-        if (p >= nn) continue;
-        const uint64_t k = (a.keys[i] + a.keys[i + 1]) >> 1;
-        uint32_t ix, iy;
-        h2_cell(sl.L, k, ix, iy);
-        nkeys[p] = k;
-        seeds[p] = sl.x0 + ((double)ix + 0.5) * sl.dx;
-        seeds[stride + p] = sl.y0 + ((double)iy + 0.5) * sl.dy;
-        seeds[2 * stride + p] = sl.z0;
+    const int64_t nf = *n_fire;
+    const int rm = (int)*rem;
+    Round r{0, 0, 0};
+    int64_t ne = 0;
+    if (rm > 0 && nf > 0) {
+        int D = batch < rm ? batch : rm;
+        while (D > 1 && nf * ((1 << D) - 1) > slots) --D;
+        r.D = D;
+        r.S = (1 << D) - 1;
+        r.unit = ((uint64_t)1 << rm) >> D;
+        ne = nf;
+        if (ne * r.S > slots) {   // cannot happen while slots >= samples; kept as a guard
+            ne = slots / r.S;
+            *overflow = 1;
+        }
+        *rem = rm - D;
+    } else {
+        *rem = 0;
     }
+    *rd = r;
+    *n_eff = ne;
+    *n_seeds = ne * r.S;
 }
 
-// order-preserving merge: sample i moves up by the insertions before it; an
-// inserted sample follows the pair's first member
-__global__ void k_merge(Slice sl, Samples a, Samples b, Samples nw, const int64_t *count_in,
-                        const int64_t *n_new, const int32_t *pos)
+template <int DIM>
+__global__ void k_spec_seeds(Region rg, const Round *rdp, Samples a, const int64_t *count_in, const int32_t *flag,
+                             const int32_t *fpos, const int64_t *n_eff, int64_t stride, double *seeds,
+                             uint64_t *nkeys)
 {
-    const int64_t count = *count_in, nn = *n_new;
+    const Round rd = *rdp;
+    const int64_t count = *count_in, ne = *n_eff;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = pos[i];
-        const int64_t before = p < nn ? p : nn;
-        const int64_t dst = i + before;
-        b.keys[dst] = a.keys[i];
-        b.fll[dst] = a.fll[i];
-        b.q[dst] = a.q[i];
-        b.status[dst] = a.status[i];
-        if (p < nn && fires(a, i, count, sl.thr)) {
-            b.keys[dst + 1] = nw.keys[p];
-            b.fll[dst + 1] = nw.fll[p];
-            b.q[dst + 1] = nw.q[p];
-            b.status[dst + 1] = nw.status[p];
+        if (!flag[i] || fpos[i] >= ne) continue;
+        const int64_t base = (int64_t)fpos[i] * rd.S;
+        const uint64_t k0 = a.keys[i];
+        for (int j = 1; j <= rd.S; ++j) {
+            const uint64_t k = k0 + (uint64_t)j * rd.unit;
+            uint32_t c[3];
+            cell_of_key<DIM>(rg.L, k, c);
+            const int64_t p = base + j - 1;
+            nkeys[p] = k;
+            for (int ax = 0; ax < 3; ++ax)
+                seeds[ax * stride + p] = (ax < DIM) ? rg.lo[ax] + ((double)c[ax] + 0.5) * rg.d[ax] : rg.lo[ax];
         }
     }
 }
 
+// The pass-by-pass rule applied to the traced values of one firing gap: an
+// interval at depth d (length 2^(D-d) units) is split iff its parent was split,
+// its ends differ in length by more than thr and its key gap is >= 2; the
+// midpoints of split intervals are kept.  Bit j-1 of the mask keeps key j.
+__device__ __forceinline__ uint32_t keep_mask(const Round &rd, double thr, double f0, double fG, const double *fs)
+{
+    const int N = 1 << rd.D;
+    uint32_t keep = 0, active = 1;   // the whole gap fired
+    for (int d = 0; d < rd.D; ++d) {
+        const int L = N >> d;
+        uint32_t next = 0;
+        for (int a = 0; a < (1 << d); ++a) {
+            if (!((active >> a) & 1u)) continue;
+            const int m = a * L + L / 2;
+            keep |= 1u << (m - 1);
+            if (d + 1 < rd.D) {
+                const uint64_t kg = (uint64_t)(L / 2) * rd.unit;
+                for (int c = 0; c < 2; ++c) {
+                    const int s = a * L + c * (L / 2), e = s + L / 2;
+                    const double fs_ = s == 0 ? f0 : fs[s - 1];
+                    const double fe_ = e == N ? fG : fs[e - 1];
+                    if (kg >= 2 && fabs(fe_ - fs_) > thr) next |= 1u << (2 * a + c);
+                }
+            }
+        }
+        active = next;
+    }
+    return keep;
+}
+
+__global__ void k_select(Region rg, const Round *rdp, Samples a, const int64_t *count_in, const int32_t *flag,
+                         const int32_t *fpos, const int64_t *n_eff, const double *nfll, int32_t *kcnt,
+                         uint32_t *kmask)
+{
+    const Round rd = *rdp;
+    const int64_t count = *count_in, ne = *n_eff;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t c = 0;
+        if (flag[i] && fpos[i] < ne) {
+            const int64_t p = fpos[i];
+            const uint32_t mk = keep_mask(rd, rg.thr, a.fll[i], a.fll[i + 1], nfll + p * rd.S);
+            kmask[p] = mk;
+            c = __popc(mk);
+        }
+        kcnt[i] = c;
+    }
+}
+
+// order-preserving merge: sample i moves up by the kept samples before it; a
+// gap's kept samples follow its first member in key order; kept samples past
+// the room left in the caller's arrays are dropped (overflow is flagged)
+__global__ void k_merge(const Round *rdp, Samples a, Samples b, Samples nw, const int64_t *count_in,
+                        const int32_t *flag, const int32_t *fpos, const int64_t *n_eff, const int32_t *kcnt,
+                        const int32_t *koff, const uint32_t *kmask, int64_t capacity)
+{
+    const Round rd = *rdp;
+    const int64_t count = *count_in, ne = *n_eff, room = capacity - count;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t off = koff[i];
+        const int64_t dst = i + (off < room ? off : room);
+        b.keys[dst] = a.keys[i];
+        b.fll[dst] = a.fll[i];
+        b.q[dst] = a.q[i];
+        b.status[dst] = a.status[i];
+        if (kcnt[i] > 0 && flag[i] && fpos[i] < ne) {
+            const int64_t p = (int64_t)fpos[i] * rd.S;
+            const uint32_t mk = kmask[fpos[i]];
+            int64_t t = 0;
+            for (int j = 1; j <= rd.S; ++j) {
+                if (!((mk >> (j - 1)) & 1u)) continue;
+                if (off + t < room) {
+                    b.keys[dst + 1 + t] = nw.keys[p + j - 1];
+                    b.fll[dst + 1 + t] = nw.fll[p + j - 1];
+                    b.q[dst + 1 + t] = nw.q[p + j - 1];
+                    b.status[dst + 1 + t] = nw.status[p + j - 1];
+                }
+                ++t;
+            }
+        }
+    }
+}
+
+__global__ void k_round_finish(const int64_t *count_in, const int64_t *n_kept, int64_t capacity, int64_t *count_out,
+                               int32_t *overflow)
+{
+    const int64_t count = *count_in, kept = *n_kept, room = capacity - count;
+    if (kept > room) *overflow = 1;
+    *count_out = count + (kept < room ? kept : room);
+}
+
 __global__ void k_copy_count(const int64_t *src, int64_t *dst) { *dst = *src; }
 
+__global__ void k_copy_samples(Samples src, Samples dst, const int64_t *count_in)
+{
+    const int64_t count = *count_in;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        dst.keys[i] = src.keys[i];
+        dst.fll[i] = src.fll[i];
+        dst.q[i] = src.q[i];
+        dst.status[i] = src.status[i];
+    }
+}
+
 // array converter: output cell = aligned block of finest keys
-__global__ void __launch_bounds__(256) k_convert(Slice sl, int out_level, Samples a, const int64_t *count_in,
+template <int DIM>
+__global__ void __launch_bounds__(256) k_convert(Region rg, int out_level, Samples a, const int64_t *count_in,
                                                  float *qg, float *fg)
 {
     const int64_t count = *count_in;
-    const uint32_t side = 1u << out_level;
-    const int64_t N = (int64_t)side * side;
-    const int sh = 2 * (sl.L - out_level);
+    const int64_t side = (int64_t)1 << out_level;
+    int64_t N = side * side;
+    if (DIM == 3) N *= side;
+    const int sh = DIM * (rg.L - out_level);
     const uint64_t B = (uint64_t)1 << sh;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t iy = (uint32_t)(i / side), ix = (uint32_t)(i - (int64_t)iy * side);
-        const uint64_t c = h2_index(out_level, ix, iy);
-        const uint64_t lo = c << sh, hi = lo + B;
+        uint32_t c[3];
+        c[0] = (uint32_t)(i % side);
+        c[1] = (uint32_t)((i / side) % side);
+        c[2] = DIM == 3 ? (uint32_t)(i / (side * side)) : 0u;
+        const uint64_t lo = key_of_cell<DIM>(out_level, c) << sh, hi = lo + B;
         // first sample with key >= lo
         int64_t l = 0, h = count;
         while (l < h) {
@@ -408,16 +647,24 @@ __global__ void __launch_bounds__(256) k_convert(Slice sl, int out_level, Sample
 // ---------------------------------------------------------------------------
 static uint64_t al(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
 
+// device scalars of a map: sample counts after each round at [0, kRoundWords),
+// four per-round scalars from kRoundWords, the levels left at kRemWord
+constexpr int kMaxRounds = 64;
+constexpr int kRoundWords = 128;
+constexpr int kRemWord = kRoundWords + 4 * kMaxRounds;
+constexpr int kCountWords = kRemWord + 8;
+
 struct QmapLayout {
-    uint64_t trace, seeds, bkeys, bfll, bq, bst, nkeys, nfll, nq, nst, pos, bsum, counts, img, total;
+    uint64_t trace, seeds, bkeys, bfll, bq, bst, nkeys, nfll, nq, nst, flag, fpos, kcnt, koff, kmask, bsum, counts,
+        rounds, img, total;
     int64_t tcap, nblocks;
 };
 
-static QmapLayout layout(const qsq_map_desc *d, int64_t cap)
+static QmapLayout layout(int dims, int m, int64_t cap)
 {
     QmapLayout L{};
-    const int64_t nb = (int64_t)1 << (2 * d->base_level);
-    L.tcap = nb > (cap + 1) / 2 ? nb : (cap + 1) / 2;
+    const int64_t nb = (int64_t)1 << (dims * m);
+    L.tcap = nb > cap ? nb : cap;   // trace slots: base lattice or speculative keys
     L.nblocks = (cap + kScanBlock - 1) / kScanBlock;
     uint64_t o = 0;
     L.trace = o; o += al(256 + records_bytes(L.tcap));
@@ -430,9 +677,14 @@ static QmapLayout layout(const qsq_map_desc *d, int64_t cap)
     L.nfll = o; o += al((uint64_t)L.tcap * 8);
     L.nq = o; o += al((uint64_t)L.tcap * 8);
     L.nst = o; o += al((uint64_t)L.tcap * 4);
-    L.pos = o; o += al((uint64_t)cap * 4);
+    L.flag = o; o += al((uint64_t)cap * 4);
+    L.fpos = o; o += al((uint64_t)cap * 4);
+    L.kcnt = o; o += al((uint64_t)cap * 4);
+    L.koff = o; o += al((uint64_t)cap * 4);
+    L.kmask = o; o += al((uint64_t)cap * 4);
     L.bsum = o; o += al((uint64_t)(L.nblocks + 1) * 8);
-    L.counts = o; o += al(64 * 8);
+    L.counts = o; o += al(kCountWords * 8);
+    L.rounds = o; o += al(kMaxRounds * sizeof(Round));
     L.img = o; o += al((uint64_t)nb * 4);
     L.total = o;
     return L;
@@ -440,37 +692,69 @@ static QmapLayout layout(const qsq_map_desc *d, int64_t cap)
 
 uint64_t qmap_scratch_bytes(const qsq_map_desc *d, int64_t capacity)
 {
-    return layout(d, capacity).total;
+    return layout(2, d->base_level, capacity).total;
 }
 
-hipError_t launch_qmap(const qsq_field *f, const Geom &g, const StepOpts &o, int step_dtype,
-                       const qsq_map_desc *d, const qsq_map_out *out, void *scratch, hipStream_t st)
+uint64_t vmap_scratch_bytes(const qsq_volume_desc *d, int64_t capacity)
+{
+    return layout(3, d->base_level, capacity).total;
+}
+
+static void launch_scan(const int32_t *v, const int64_t *count_in, int64_t nblocks, int64_t *bsum, int32_t *off,
+                        int64_t *total, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nblocks), dim3(256), 0, st, v, count_in, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, nblocks, bsum, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblocks), dim3(256), 0, st, v, count_in, bsum, off);
+}
+
+int64_t scan_tmp_words(int64_t n_max) { return (n_max + kScanBlock - 1) / kScanBlock + 1; }
+
+void launch_scan_i32(const int32_t *v, const int64_t *n_dev, int64_t n_max, int64_t *tmp, int32_t *off,
+                     int64_t *total, hipStream_t st)
+{
+    const int64_t nblocks = (n_max + kScanBlock - 1) / kScanBlock;
+    if (nblocks <= 0) return;
+    launch_scan(v, n_dev, nblocks, tmp, off, total, st);
+}
+
+__global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
+
+// Rounds to enqueue.  If the trace slots hold 2^batch - 1 keys for every
+// possible firing gap (at most one per sample), no round takes fewer than
+// batch levels and ceil(levels / batch) rounds suffice; otherwise a round may
+// fall back to fewer levels and up to one round per level is enqueued.
+static int planned_rounds(int levels, int batch, int64_t slots, int64_t capacity)
+{
+    if ((double)slots >= (double)capacity * (double)((1 << batch) - 1)) return (levels + batch - 1) / batch;
+    return levels;
+}
+
+// One refined map of a slice (DIM 2) or volume (DIM 3): base lattice, trace,
+// FLEDGE of the base lengths, refinement rounds, converter.
+template <int DIM>
+static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &o, int step_dtype, Region rg,
+                             int out_level, int refine_batch, const qsq_map_out *out, void *scratch, hipStream_t st)
 {
     const int64_t cap = out->capacity;
-    const QmapLayout Lo = layout(d, cap);
+    const int m = rg.m, r = rg.r;
+    const QmapLayout Lo = layout(DIM, m, cap);
     char *base = static_cast<char *>(scratch);
-    const int m = d->base_level, r = d->refine_levels;
-    const int64_t nb = (int64_t)1 << (2 * m);
-
-    Slice sl;
-    sl.z0 = d->z0;
-    sl.x0 = d->x0;
-    sl.y0 = d->y0;
-    sl.m = m;
-    sl.r = r;
-    sl.L = m + r;
-    sl.dx = (d->x1 - d->x0) / (double)((int64_t)1 << sl.L);
-    sl.dy = (d->y1 - d->y0) / (double)((int64_t)1 << sl.L);
-    sl.thr = d->threshold;
+    const int64_t nb = (int64_t)1 << (DIM * m);
 
     double *seeds = reinterpret_cast<double *>(base + Lo.seeds);
-    int64_t *counts = reinterpret_cast<int64_t *>(base + Lo.counts);   // [0..2r] totals, [32..] n_new
+    // device scalars (sample counts, per-round scalars, levels left; see kRoundWords)
+    int64_t *counts = reinterpret_cast<int64_t *>(base + Lo.counts);
     Samples A{out->keys, out->fll, out->q_perp, out->status};
     Samples Bs{reinterpret_cast<uint64_t *>(base + Lo.bkeys), reinterpret_cast<double *>(base + Lo.bfll),
                reinterpret_cast<double *>(base + Lo.bq), reinterpret_cast<int32_t *>(base + Lo.bst)};
     Samples N{reinterpret_cast<uint64_t *>(base + Lo.nkeys), reinterpret_cast<double *>(base + Lo.nfll),
               reinterpret_cast<double *>(base + Lo.nq), reinterpret_cast<int32_t *>(base + Lo.nst)};
-    int32_t *pos = reinterpret_cast<int32_t *>(base + Lo.pos);
+    int32_t *flag = reinterpret_cast<int32_t *>(base + Lo.flag);
+    int32_t *fpos = reinterpret_cast<int32_t *>(base + Lo.fpos);
+    int32_t *kcnt = reinterpret_cast<int32_t *>(base + Lo.kcnt);
+    int32_t *koff = reinterpret_cast<int32_t *>(base + Lo.koff);
+    uint32_t *kmask = reinterpret_cast<uint32_t *>(base + Lo.kmask);
     int64_t *bsum = reinterpret_cast<int64_t *>(base + Lo.bsum);
 
     TraceJob job{};
@@ -486,7 +770,7 @@ hipError_t launch_qmap(const qsq_field *f, const Geom &g, const StepOpts &o, int
     job.work = reinterpret_cast<unsigned long long *>(out->work);
 
     // base lattice
-    hipLaunchKernelGGL(k_base_seeds, dim3(grid_for(nb)), dim3(256), 0, st, sl, nb, Lo.tcap, seeds, A.keys);
+    hipLaunchKernelGGL((k_base_seeds<DIM>), dim3(grid_for(nb)), dim3(256), 0, st, rg, nb, Lo.tcap, seeds, A.keys);
     hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, &counts[0], nb, out->overflow);
     job.n_host = nb;
     job.n_dev = nullptr;
@@ -497,43 +781,100 @@ hipError_t launch_qmap(const qsq_field *f, const Geom &g, const StepOpts &o, int
     if (e != hipSuccess) return e;
     if (out->fledge) {
         float *img = reinterpret_cast<float *>(base + Lo.img);
-        hipLaunchKernelGGL(k_fll_raster, dim3(grid_for(nb)), dim3(256), 0, st, sl, nb, A.fll, img);
-        const int64_t shp[2] = {(int64_t)1 << m, (int64_t)1 << m};
-        e = launch_fledge(img, 2, shp, out->fledge, st);
+        hipLaunchKernelGGL((k_fll_raster<DIM>), dim3(grid_for(nb)), dim3(256), 0, st, rg, nb, A.fll, img);
+        const int64_t side = (int64_t)1 << m;
+        const int64_t shp[3] = {side, side, side};
+        e = launch_fledge(img, DIM, shp, out->fledge, st);
         if (e != hipSuccess) return e;
     }
 
-    // refinement passes: the key gap 4^r halves each pass, so 2r passes suffice
+    // refinement rounds: the key gap B^r halves with every level, DIM r levels
+    // in all.  Each round takes as many levels as its device set-up decides,
+    // so up to DIM r rounds are enqueued; rounds after the last level are
+    // no-ops (nothing fires, samples are copied to the other buffer).
+    const int levels = DIM * r;
+    int batch = refine_batch;
+    if (batch <= 0) batch = levels < 4 ? levels : 4;
+    if (batch > 5) batch = 5;
+    int64_t *rem = &counts[kRemWord];
+    Round *rds = reinterpret_cast<Round *>(base + Lo.rounds);
+    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, st, rem, (int64_t)levels);
+    const int rounds = planned_rounds(levels, batch, Lo.tcap, cap);
     Samples cur = A, nxt = Bs;
-    const int passes = 2 * r;
-    for (int p = 1; p <= passes; ++p) {
-        int64_t *cin = &counts[p - 1], *cout = &counts[p], *nn = &counts[32 + p];
-        hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)Lo.nblocks), dim3(256), 0, st, cur, cin, sl.thr, bsum);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, Lo.nblocks, bsum, cin, cout, nn, cap,
-                           out->overflow);
-        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)Lo.nblocks), dim3(256), 0, st, cur, cin, sl.thr, bsum,
-                           pos);
-        hipLaunchKernelGGL(k_new_seeds, dim3(grid_for(cap)), dim3(256), 0, st, sl, cur, cin, nn, pos, Lo.tcap,
-                           seeds, N.keys);
-        job.n_dev = nn;
+    int round = 0;
+    for (; round < rounds; ++round) {
+        int64_t *cin = &counts[round], *cout = &counts[round + 1];
+        int64_t *n_fire = &counts[kRoundWords + 4 * round], *n_eff = n_fire + 1, *n_seeds = n_fire + 2,
+                *n_kept = n_fire + 3;
+        hipLaunchKernelGGL(k_fire, dim3(grid_for(cap)), dim3(256), 0, st, cur, cin, rg.thr, flag);
+        launch_scan(flag, cin, Lo.nblocks, bsum, fpos, n_fire, st);
+        hipLaunchKernelGGL(k_round_setup, dim3(1), dim3(1), 0, st, n_fire, batch, Lo.tcap, rem, &rds[round], n_eff,
+                           n_seeds, out->overflow);
+        hipLaunchKernelGGL((k_spec_seeds<DIM>), dim3(grid_for(cap)), dim3(256), 0, st, rg, &rds[round], cur, cin,
+                           flag, fpos, n_eff, Lo.tcap, seeds, N.keys);
+        job.n_dev = n_seeds;
         job.fll = N.fll;
         job.q_perp = N.q;
         job.status = N.status;
         e = launch_trace(job, step_dtype, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_merge, dim3(grid_for(cap)), dim3(256), 0, st, sl, cur, nxt, N, cin, nn, pos);
+        hipLaunchKernelGGL(k_select, dim3(grid_for(cap)), dim3(256), 0, st, rg, &rds[round], cur, cin, flag, fpos,
+                           n_eff, N.fll, kcnt, kmask);
+        launch_scan(kcnt, cin, Lo.nblocks, bsum, koff, n_kept, st);
+        hipLaunchKernelGGL(k_merge, dim3(grid_for(cap)), dim3(256), 0, st, &rds[round], cur, nxt, N, cin, flag, fpos,
+                           n_eff, kcnt, koff, kmask, cap);
+        hipLaunchKernelGGL(k_round_finish, dim3(1), dim3(1), 0, st, cin, n_kept, cap, cout, out->overflow);
         Samples t = cur;
         cur = nxt;
         nxt = t;
     }
-    // an even number of passes leaves the samples in the caller's arrays
-    hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, st, &counts[passes], out->count);
+    // leave the samples in the caller's arrays
+    if (round % 2 == 1) {
+        hipLaunchKernelGGL(k_copy_samples, dim3(grid_for(cap)), dim3(256), 0, st, cur, A, &counts[round]);
+        cur = A;
+    }
+    hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, st, &counts[round], out->count);
     if (out->q_grid || out->fll_grid) {
-        const int64_t No = (int64_t)1 << (2 * d->out_level);
-        hipLaunchKernelGGL(k_convert, dim3(grid_for(No, 32)), dim3(256), 0, st, sl, d->out_level, cur,
-                           &counts[passes], out->q_grid, out->fll_grid);
+        const int64_t No = (int64_t)1 << (DIM * out_level);
+        hipLaunchKernelGGL((k_convert<DIM>), dim3(grid_for(No, 32)), dim3(256), 0, st, rg, out_level, cur,
+                           &counts[round], out->q_grid, out->fll_grid);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_qmap(const qsq_field *f, const Geom &g, const StepOpts &o, int step_dtype,
+                       const qsq_map_desc *d, const qsq_map_out *out, void *scratch, hipStream_t st)
+{
+    Region rg{};
+    rg.m = d->base_level;
+    rg.r = d->refine_levels;
+    rg.L = rg.m + rg.r;
+    const double nL = (double)((int64_t)1 << rg.L);
+    rg.lo[0] = d->x0;
+    rg.lo[1] = d->y0;
+    rg.lo[2] = d->z0;
+    rg.d[0] = (d->x1 - d->x0) / nL;
+    rg.d[1] = (d->y1 - d->y0) / nL;
+    rg.d[2] = 0.0;
+    rg.thr = d->threshold;
+    return launch_map<2>(f, g, o, step_dtype, rg, d->out_level, d->refine_batch, out, scratch, st);
+}
+
+hipError_t launch_vmap(const qsq_field *f, const Geom &g, const StepOpts &o, int step_dtype,
+                       const qsq_volume_desc *d, const qsq_map_out *out, void *scratch, hipStream_t st)
+{
+    Region rg{};
+    rg.m = d->base_level;
+    rg.r = d->refine_levels;
+    rg.L = rg.m + rg.r;
+    const double nL = (double)((int64_t)1 << rg.L);
+    const double lo[3] = {d->x0, d->y0, d->z0}, hi[3] = {d->x1, d->y1, d->z1};
+    for (int a = 0; a < 3; ++a) {
+        rg.lo[a] = lo[a];
+        rg.d[a] = (hi[a] - lo[a]) / nL;
+    }
+    rg.thr = d->threshold;
+    return launch_map<3>(f, g, o, step_dtype, rg, d->out_level, d->refine_batch, out, scratch, st);
 }
 
 }  // namespace qsq

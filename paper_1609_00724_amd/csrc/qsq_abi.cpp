@@ -8,6 +8,7 @@
 #include <mutex>
 #include <vector>
 
+#include "qsq_cnn.h"
 #include "qsq_internal.h"
 
 namespace {
@@ -56,7 +57,7 @@ int check_field(const qsq_field *f)
     if (!f) return fail(QSQ_ERR_INVALID_ARG, "field is NULL");
     int rc = check_grid(&f->grid);
     if (rc) return rc;
-    if (f->storage != QSQ_F32 && f->storage != QSQ_F64)
+    if (f->storage != QSQ_F32 && f->storage != QSQ_F64 && f->storage != QSQ_BF16)
         return fail(QSQ_ERR_UNSUPPORTED, "field storage %d not supported", f->storage);
     if (f->mode != QSQ_INTERP_PAPER && f->mode != QSQ_INTERP_NORMALIZE)
         return fail(QSQ_ERR_INVALID_ARG, "field mode %d unknown", f->mode);
@@ -77,6 +78,8 @@ int make_geom_opts(const qsq_field *f, const qsq_trace_opts *o, qsq::Geom *g, qs
     if (!isfinite(o->h_init) || !isfinite(o->h_max) || !isfinite(o->max_length))
         return fail(QSQ_ERR_INVALID_ARG, "h_init, h_max and max_length must be finite");
     if (o->flags & ~QSQ_FLAG_SKIP_OPEN) return fail(QSQ_ERR_INVALID_ARG, "unknown flags 0x%x", o->flags);
+    if ((o->launch & ~0xff) || ((o->launch >> 4) & 3) == 3 || ((o->launch >> 6) & 3) == 3)
+        return fail(QSQ_ERR_INVALID_ARG, "launch word 0x%x outside QSQ_LAUNCH(0..15, 0..2, 0..2)", o->launch);
     double hmin_grid = f->grid.spacing[0];
     double extent = 0.0;
     for (int d = 0; d < 3; ++d) {
@@ -100,7 +103,7 @@ int make_geom_opts(const qsq_field *f, const qsq_trace_opts *o, qsq::Geom *g, qs
     so->gtol = 1e-12 * extent;
     so->max_steps = o->max_steps > 0 ? o->max_steps : (int64_t)1 << 22;
     so->flags = o->flags;
-    so->pad = 0;
+    so->launch = o->launch;
     return QSQ_OK;
 }
 
@@ -217,7 +220,7 @@ uint64_t qsq_field_bytes(const qsq_grid *g, int storage)
 {
     if (!g) return 0;
     const uint64_t N = (uint64_t)g->n[0] * (uint64_t)g->n[1] * (uint64_t)g->n[2];
-    const uint64_t per = storage == QSQ_F64 ? 32 : storage == QSQ_F32 ? 16 : 0;
+    const uint64_t per = storage == QSQ_F64 ? 32 : storage == QSQ_F32 ? 16 : storage == QSQ_BF16 ? 8 : 0;
     return N * per;
 }
 
@@ -228,7 +231,7 @@ int qsq_field_init(const qsq_grid *g, const void *bx, const void *by, const void
     if (rc) return rc;
     if (!bx || !by || !bz || !ws || !out) return fail(QSQ_ERR_INVALID_ARG, "NULL pointer argument");
     if (in_dtype != QSQ_F32 && in_dtype != QSQ_F64) return fail(QSQ_ERR_INVALID_ARG, "in_dtype %d", in_dtype);
-    if (storage != QSQ_F32 && storage != QSQ_F64)
+    if (storage != QSQ_F32 && storage != QSQ_F64 && storage != QSQ_BF16)
         return fail(QSQ_ERR_UNSUPPORTED, "storage %d not supported", storage);
     if (mode != QSQ_INTERP_PAPER && mode != QSQ_INTERP_NORMALIZE)
         return fail(QSQ_ERR_INVALID_ARG, "mode %d unknown", mode);
@@ -299,6 +302,95 @@ int qsq_trace(const qsq_field *f, const double *seeds, int64_t n, const qsq_trac
     return ok();
 }
 
+static uint64_t round256(uint64_t b) { return (b + 255) & ~(uint64_t)255; }
+
+// prefix the last error message with the set that caused it
+static int set_fail(int rc, int k)
+{
+    char msg[sizeof g_err];
+    memcpy(msg, g_err, sizeof msg);
+    return fail(rc, "set %d: %s", k, msg);
+}
+
+uint64_t qsq_trace_batch_scratch_bytes(int32_t nsets, int64_t total)
+{
+    if (nsets < 0 || total < 0) return 0;
+    return round256(256 + qsq::records_bytes(total)) + round256((uint64_t)total * sizeof(int32_t)) +
+           round256((uint64_t)nsets * sizeof(qsq::SetDesc));
+}
+
+int qsq_trace_batch(const qsq_trace_set *sets, int32_t nsets, const qsq_trace_opts *opts, uint64_t *work,
+                    void *scratch, uint64_t scratch_bytes, void *stream)
+{
+    if (!sets) return fail(QSQ_ERR_INVALID_ARG, "sets is NULL");
+    if (nsets < 1 || nsets > QSQ_MAX_TRACE_SETS)
+        return fail(QSQ_ERR_INVALID_ARG, "nsets = %d outside [1, %d]", nsets, QSQ_MAX_TRACE_SETS);
+    std::vector<qsq::SetDesc> table((size_t)nsets);
+    int64_t total = 0;
+    qsq::StepOpts so0{};
+    for (int k = 0; k < nsets; ++k) {
+        const qsq_trace_set &t = sets[k];
+        int rc = check_field(&t.field);
+        if (rc) return set_fail(rc, k);
+        if (t.field.storage != sets[0].field.storage || t.field.mode != sets[0].field.mode)
+            return fail(QSQ_ERR_INVALID_ARG, "set %d: storage and mode must match set 0", k);
+        qsq::Geom g;
+        qsq::StepOpts so;
+        rc = make_geom_opts(&t.field, opts, &g, &so);
+        if (rc) return set_fail(rc, k);
+        if (t.n < 0) return fail(QSQ_ERR_INVALID_ARG, "set %d: n < 0", k);
+        if (t.n > 0 && (!t.seeds || !t.out.status))
+            return fail(QSQ_ERR_INVALID_ARG, "set %d: NULL seeds or out.status", k);
+        if (k == 0) so0 = so;
+        qsq::SetDesc &d = table[k];
+        d = qsq::SetDesc{};
+        d.g = g;
+        d.nodes = t.field.nodes;
+        d.seeds = t.seeds;
+        d.n = t.n;
+        d.off = total;
+        d.h_init = so.h_init;
+        d.h_max = so.h_max;
+        d.hmin = so.hmin;
+        d.gtol = so.gtol;
+        d.fp_fwd = t.out.fp_fwd;
+        d.fp_bwd = t.out.fp_bwd;
+        d.fll = t.out.fll;
+        d.q_perp = t.out.q_perp;
+        d.q_det = t.out.q_det;
+        d.q_fp = t.out.q_fp;
+        d.status = t.out.status;
+        d.steps = t.out.steps;
+        total += t.n;
+        if (total > ((int64_t)1 << 30)) return fail(QSQ_ERR_COUNT_OVERFLOW, "more than 2^30 seeds in the batch");
+    }
+    if (total == 0) return ok();
+    if (!scratch) return fail(QSQ_ERR_INVALID_ARG, "scratch is NULL");
+    if (!aligned(scratch, 256)) return fail(QSQ_ERR_INVALID_ARG, "scratch must be 256-byte aligned");
+    const uint64_t need = qsq_trace_batch_scratch_bytes(nsets, total);
+    if (scratch_bytes < need)
+        return fail(QSQ_ERR_WORKSPACE_TOO_SMALL, "batch scratch %llu < %llu bytes",
+                    (unsigned long long)scratch_bytes, (unsigned long long)need);
+    qsq::TraceJob job{};
+    job.storage = sets[0].field.storage;
+    job.mode = sets[0].field.mode;
+    job.nodes = sets[0].field.nodes;
+    job.g = table[0].g;
+    job.o = so0;   // rtol, atol, max_length, max_steps, flags; per-set limits come from the table
+    job.n_host = total;
+    job.n_dev = nullptr;
+    qsq::carve_records(scratch, total, &job.rec, &job.counter);
+    char *p = static_cast<char *>(scratch) + round256(256 + qsq::records_bytes(total));
+    job.set_of = reinterpret_cast<int32_t *>(p);
+    p += round256((uint64_t)total * sizeof(int32_t));
+    job.sets = reinterpret_cast<const qsq::SetDesc *>(p);
+    job.nsets = nsets;
+    job.work = reinterpret_cast<unsigned long long *>(work);
+    hipError_t e = qsq::launch_trace_batch(job, table.data(), nsets, opts->step_dtype, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_trace_batch");
+    return ok();
+}
+
 int qsq_fledge(const float *in, int ndim, const int64_t *shape, float *out, void *stream)
 {
     if (!in || !out || !shape) return fail(QSQ_ERR_INVALID_ARG, "NULL pointer argument");
@@ -337,6 +429,29 @@ int qsq_hilbert2_xy2d(int L, const uint32_t *x, const uint32_t *y, int64_t n, ui
     return ok();
 }
 
+int qsq_hilbert3_d2xyz(int b, const uint64_t *d, int64_t n, uint32_t *x, uint32_t *y, uint32_t *z, void *stream)
+{
+    if (b < 1 || b > 21) return fail(QSQ_ERR_INVALID_ARG, "b must be in [1, 21]");
+    if (n < 0) return fail(QSQ_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return ok();
+    if (!d || !x || !y || !z) return fail(QSQ_ERR_INVALID_ARG, "NULL pointer argument");
+    hipError_t e = qsq::launch_hilbert3_d2xyz(b, d, n, x, y, z, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_hilbert3_d2xyz");
+    return ok();
+}
+
+int qsq_hilbert3_xyz2d(int b, const uint32_t *x, const uint32_t *y, const uint32_t *z, int64_t n, uint64_t *d,
+                       void *stream)
+{
+    if (b < 1 || b > 21) return fail(QSQ_ERR_INVALID_ARG, "b must be in [1, 21]");
+    if (n < 0) return fail(QSQ_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return ok();
+    if (!d || !x || !y || !z) return fail(QSQ_ERR_INVALID_ARG, "NULL pointer argument");
+    hipError_t e = qsq::launch_hilbert3_xyz2d(b, x, y, z, n, d, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_hilbert3_xyz2d");
+    return ok();
+}
+
 static int check_map(const qsq_map_desc *d)
 {
     if (!d) return fail(QSQ_ERR_INVALID_ARG, "map desc is NULL");
@@ -348,6 +463,54 @@ static int check_map(const qsq_map_desc *d)
         return fail(QSQ_ERR_INVALID_ARG, "slice extent must satisfy x1 > x0, y1 > y0, finite z0");
     if (!(d->threshold >= 0.0)) return fail(QSQ_ERR_INVALID_ARG, "threshold must be >= 0");
     return QSQ_OK;
+}
+
+static int check_volume(const qsq_volume_desc *d)
+{
+    if (!d) return fail(QSQ_ERR_INVALID_ARG, "volume desc is NULL");
+    if (d->base_level < 1 || d->refine_levels < 0 || d->base_level + d->refine_levels > 21)
+        return fail(QSQ_ERR_INVALID_ARG, "need base_level >= 1, refine_levels >= 0, sum <= 21");
+    if (3 * d->base_level > 30) return fail(QSQ_ERR_UNSUPPORTED, "base_level > 10 (more than 2^30 base cells)");
+    if (d->out_level < d->base_level || d->out_level > d->base_level + d->refine_levels)
+        return fail(QSQ_ERR_INVALID_ARG, "out_level outside [base_level, base_level + refine_levels]");
+    if (3 * d->out_level > 33) return fail(QSQ_ERR_UNSUPPORTED, "out_level > 11");
+    if (!(d->x1 > d->x0) || !(d->y1 > d->y0) || !(d->z1 > d->z0))
+        return fail(QSQ_ERR_INVALID_ARG, "volume extent must satisfy x1 > x0, y1 > y0, z1 > z0");
+    if (!(d->threshold >= 0.0)) return fail(QSQ_ERR_INVALID_ARG, "threshold must be >= 0");
+    return QSQ_OK;
+}
+
+uint64_t qsq_vmap_scratch_bytes(const qsq_volume_desc *d, int64_t capacity)
+{
+    if (!d || capacity <= 0) return 0;
+    return qsq::vmap_scratch_bytes(d, capacity);
+}
+
+int qsq_vmap(const qsq_field *f, const qsq_volume_desc *d, const qsq_trace_opts *opts, const qsq_map_out *out,
+             void *scratch, uint64_t scratch_bytes, void *stream)
+{
+    int rc = check_field(f);
+    if (rc) return rc;
+    rc = check_volume(d);
+    if (rc) return rc;
+    qsq::Geom g;
+    qsq::StepOpts so;
+    rc = make_geom_opts(f, opts, &g, &so);
+    if (rc) return rc;
+    if (!out) return fail(QSQ_ERR_INVALID_ARG, "out is NULL");
+    const int64_t nb = (int64_t)1 << (3 * d->base_level);
+    if (out->capacity < nb) return fail(QSQ_ERR_INVALID_ARG, "capacity < 8^base_level");
+    if (out->capacity > ((int64_t)1 << 31) - 1) return fail(QSQ_ERR_COUNT_OVERFLOW, "capacity >= 2^31");
+    if (!out->keys || !out->fll || !out->q_perp || !out->status || !out->count || !out->overflow)
+        return fail(QSQ_ERR_INVALID_ARG, "sample arrays, count and overflow are required");
+    if (!scratch || !aligned(scratch, 256)) return fail(QSQ_ERR_INVALID_ARG, "scratch NULL or not 256-byte aligned");
+    const uint64_t need = qsq::vmap_scratch_bytes(d, out->capacity);
+    if (scratch_bytes < need)
+        return fail(QSQ_ERR_WORKSPACE_TOO_SMALL, "vmap scratch %llu < %llu bytes",
+                    (unsigned long long)scratch_bytes, (unsigned long long)need);
+    hipError_t e = qsq::launch_vmap(f, g, so, opts->step_dtype, d, out, scratch, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_vmap");
+    return ok();
 }
 
 uint64_t qsq_qmap_scratch_bytes(const qsq_map_desc *d, int64_t capacity)
@@ -380,6 +543,110 @@ int qsq_qmap(const qsq_field *f, const qsq_map_desc *d, const qsq_trace_opts *op
                     (unsigned long long)scratch_bytes, (unsigned long long)need);
     hipError_t e = qsq::launch_qmap(f, g, so, opts->step_dtype, d, out, scratch, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "qsq_qmap");
+    return ok();
+}
+
+// ---- learned refinement proposer -------------------------------------------
+
+static int check_tiles(int64_t n, int h, int w)
+{
+    if (n < 1 || h < 32 || w < 32 || h % 32 || w % 32)
+        return fail(QSQ_ERR_INVALID_ARG, "need n >= 1 and h, w positive multiples of 32 (got %lld, %d, %d)",
+                    (long long)n, h, w);
+    if ((double)n * h * w >= 2147483648.0) return fail(QSQ_ERR_COUNT_OVERFLOW, "n h w >= 2^31 pixels");
+    return QSQ_OK;
+}
+
+uint64_t qsq_cnn_prep_bytes(void) { return qsq::cnn_prep_bytes(); }
+
+uint64_t qsq_cnn_workspace_bytes(int64_t n, int h, int w)
+{
+    if (n < 1 || h < 1 || w < 1) return 0;
+    return qsq::cnn_workspace_bytes(n, h, w);
+}
+
+uint64_t qsq_cnn_layer_scratch_bytes(int64_t n, int h, int w)
+{
+    if (n < 1 || h < 1 || w < 1) return 0;
+    return qsq::cnn_wgrad_scratch_bytes(n, h, w);
+}
+
+int qsq_cnn_prepare(const float *params, void *prep, void *stream)
+{
+    if (!params || !prep) return fail(QSQ_ERR_INVALID_ARG, "NULL params or prep");
+    if (!aligned(prep, 16)) return fail(QSQ_ERR_INVALID_ARG, "prep must be 16-byte aligned");
+    hipError_t e = qsq::cnn_prepare(params, prep, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_cnn_prepare");
+    return ok();
+}
+
+static int check_ws(void *ws, uint64_t have, uint64_t need)
+{
+    if (!ws) return fail(QSQ_ERR_INVALID_ARG, "workspace is NULL");
+    if (!aligned(ws, 256)) return fail(QSQ_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (have < need)
+        return fail(QSQ_ERR_WORKSPACE_TOO_SMALL, "workspace %llu < %llu bytes", (unsigned long long)have,
+                    (unsigned long long)need);
+    return QSQ_OK;
+}
+
+int qsq_cnn_forward(const void *prep, const float *x, int64_t n, int h, int w, float *out, void *ws,
+                    uint64_t ws_bytes, void *stream)
+{
+    int rc = check_tiles(n, h, w);
+    if (rc) return rc;
+    if (!prep || !x || !out) return fail(QSQ_ERR_INVALID_ARG, "NULL prep, x or out");
+    rc = check_ws(ws, ws_bytes, qsq::cnn_workspace_bytes(n, h, w));
+    if (rc) return rc;
+    hipError_t e = qsq::cnn_forward(prep, x, n, h, w, out, ws, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_cnn_forward");
+    return ok();
+}
+
+int qsq_cnn_train_step(float *params, float *adam_m, float *adam_v, int64_t t, float lr, const float *x,
+                       const float *mask, const float *logq, int64_t n, int h, int w, float lam, void *prep,
+                       float *grad_out, double *loss_out, void *ws, uint64_t ws_bytes, void *stream)
+{
+    int rc = check_tiles(n, h, w);
+    if (rc) return rc;
+    if (!params || !adam_m || !adam_v || !x || !mask || !logq || !prep)
+        return fail(QSQ_ERR_INVALID_ARG, "NULL params, Adam state, inputs, targets or prep");
+    if (t < 1) return fail(QSQ_ERR_INVALID_ARG, "Adam step t must be >= 1");
+    if (!(lr > 0.0f) || !isfinite(lr) || !(lam >= 0.0f) || !isfinite(lam))
+        return fail(QSQ_ERR_INVALID_ARG, "lr must be > 0 and lam >= 0, both finite");
+    rc = check_ws(ws, ws_bytes, qsq::cnn_workspace_bytes(n, h, w));
+    if (rc) return rc;
+    hipError_t e = qsq::cnn_train_step(params, adam_m, adam_v, t, lr, x, mask, logq, n, h, w, lam, prep, grad_out,
+                                       loss_out, ws, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_cnn_train_step");
+    return ok();
+}
+
+int qsq_cnn_layer_forward(int layer, const void *prep, const void *in, int64_t n, int h, int w, float *out_f32,
+                          void *stream)
+{
+    if (layer < 0 || layer > 3) return fail(QSQ_ERR_INVALID_ARG, "layer %d outside 0..3", layer);
+    int rc = check_tiles(n, h, w);
+    if (rc) return rc;
+    if (!prep || !in || !out_f32) return fail(QSQ_ERR_INVALID_ARG, "NULL prep, in or out");
+    hipError_t e = qsq::cnn_layer_forward(layer, prep, in, n, h, w, out_f32, nullptr, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_cnn_layer_forward");
+    return ok();
+}
+
+int qsq_cnn_layer_backward(int layer, const void *prep, const void *in, const uint16_t *dy, int64_t n, int h, int w,
+                           float *dw, float *db, float *dx, void *scratch, uint64_t scratch_bytes, void *stream)
+{
+    if (layer < 0 || layer > 3) return fail(QSQ_ERR_INVALID_ARG, "layer %d outside 0..3", layer);
+    int rc = check_tiles(n, h, w);
+    if (rc) return rc;
+    if (!prep || !in || !dy || !dw || !db) return fail(QSQ_ERR_INVALID_ARG, "NULL prep, in, dy, dw or db");
+    if (layer == 0 && dx) return fail(QSQ_ERR_INVALID_ARG, "layer 0 has no input gradient");
+    rc = check_ws(scratch, scratch_bytes, qsq::cnn_wgrad_scratch_bytes(n, h, w));
+    if (rc) return rc;
+    hipError_t e = qsq::cnn_layer_backward(layer, prep, in, dy, n, h, w, dw, db, dx, nullptr, nullptr, scratch,
+                                           static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_cnn_layer_backward");
     return ok();
 }
 

@@ -9,9 +9,16 @@
 
 namespace qsq {
 
+// tag type of BF16 node records (4 x 16-bit values per node, 8 bytes)
+struct Bf16 {
+    uint16_t bits;
+};
+
 // end-record status of a half-line whose last trial step left the box and still
 // has to be landed on the face (FP64 landing pass)
 constexpr int kPendingLand = 0x7f;
+// record status of a half-line the seed pass set up for stepping
+constexpr int kPendingStep = 0x7e;
 
 // Grid geometry as the kernels see it.
 struct Geom {
@@ -32,7 +39,7 @@ struct StepOpts {
     double gtol;         // landing tolerance on the face distance
     int64_t max_steps;
     int flags;
-    int pad;
+    int launch;          // QSQ_LAUNCH word (0: defaults)
 };
 
 // Per half-line end records, SoA planes of length 2*cap; half-line (dir, seed)
@@ -44,6 +51,27 @@ struct Records {
     int32_t *status;
     int32_t *attempts;
     int64_t cap;
+    // work list of the half-lines to step (record indices in seed order)
+    int32_t *flag;      // 2*cap: 1 if the half-line needs stepping
+    int32_t *wpos;      // 2*cap: exclusive scan of flag
+    int32_t *work;      // 2*cap: record index of each work item
+    int64_t *scan_tmp;  // block sums of the scan
+    int64_t *n_work;    // device scalar: work items
+    int64_t *n_items;   // device scalar: half-lines of the call (2 n)
+};
+
+// One seed set of a batched trace: its own field, seeds, per-grid step
+// limits and outputs.  Seeds of all sets are numbered globally; set s holds
+// global seeds [off, off + n).
+struct SetDesc {
+    Geom g;
+    const void *nodes;
+    const double *seeds;      // SoA planes with stride n
+    int64_t n, off;
+    double h_init, h_max, hmin, gtol;
+    double *fp_fwd, *fp_bwd, *fll, *q_perp, *q_det, *q_fp;   // stride n, nullable
+    int32_t *status;
+    int32_t *steps;           // 2 planes of stride n, nullable
 };
 
 struct TraceJob {
@@ -64,6 +92,10 @@ struct TraceJob {
     int32_t *steps;           // 2 planes of out_stride
     int64_t out_stride;
     unsigned long long *work; // 4 device counters accumulated (nullable)
+    // batched traces: nsets > 0, the set table and the set of each global seed
+    const SetDesc *sets;
+    int32_t *set_of;
+    int nsets;
 };
 
 // kernels the profiler can time
@@ -74,11 +106,21 @@ void prof_end(void *token, hipStream_t s);
 
 // Bytes of the record block for cap seeds (without the 256-byte counter block).
 uint64_t records_bytes(int64_t cap);
+// Exclusive scan of n int32 values (n from *n_dev, at most n_max) into off and
+// the total into *total; tmp holds scan_tmp_words(n_max) int64 words.
+int64_t scan_tmp_words(int64_t n_max);
+void launch_scan_i32(const int32_t *v, const int64_t *n_dev, int64_t n_max, int64_t *tmp, int32_t *off,
+                     int64_t *total, hipStream_t st);
 // Carve records + counter out of a scratch block (256-byte aligned).
 void carve_records(void *scratch, int64_t cap, Records *rec, unsigned long long **counter);
 
 // Enqueue the whole trace (work-counter reset, stepping, FP64 landing, FP64 Q assembly).
 hipError_t launch_trace(const TraceJob &job, int step_dtype, hipStream_t stream);
+// Batched trace: writes the host set table into job.sets (device) with small
+// kernels, then the same passes over all sets' seeds with one stepping launch.
+// job.n_host is the total seed count, job.rec.cap >= it.
+hipError_t launch_trace_batch(const TraceJob &job, const SetDesc *host_sets, int nsets, int step_dtype,
+                              hipStream_t stream);
 
 // Field preparation.
 hipError_t launch_field_init(const qsq_grid *g, const void *bx, const void *by, const void *bz,
@@ -89,10 +131,33 @@ hipError_t launch_fledge(const float *in, int ndim, const int64_t *shape, float 
 hipError_t launch_hilbert2_d2xy(int L, const uint64_t *d, int64_t n, uint32_t *x, uint32_t *y, hipStream_t s);
 hipError_t launch_hilbert2_xy2d(int L, const uint32_t *x, const uint32_t *y, int64_t n, uint64_t *d, hipStream_t s);
 
+hipError_t launch_hilbert3_d2xyz(int b, const uint64_t *d, int64_t n, uint32_t *x, uint32_t *y, uint32_t *z,
+                                 hipStream_t s);
+hipError_t launch_hilbert3_xyz2d(int b, const uint32_t *x, const uint32_t *y, const uint32_t *z, int64_t n,
+                                 uint64_t *d, hipStream_t s);
+
 uint64_t qmap_scratch_bytes(const qsq_map_desc *d, int64_t capacity);
+uint64_t vmap_scratch_bytes(const qsq_volume_desc *d, int64_t capacity);
+hipError_t launch_vmap(const qsq_field *f, const Geom &g, const StepOpts &o, int step_dtype,
+                       const qsq_volume_desc *d, const qsq_map_out *out, void *scratch, hipStream_t stream);
 hipError_t launch_qmap(const qsq_field *f, const Geom &g, const StepOpts &o, int step_dtype,
                        const qsq_map_desc *d, const qsq_map_out *out, void *scratch, hipStream_t stream);
 
 int device_cu_count();
+
+// Learned refinement proposer (cnn.hip).
+uint64_t cnn_prep_bytes();
+uint64_t cnn_workspace_bytes(int64_t n, int h, int w);
+uint64_t cnn_wgrad_scratch_bytes(int64_t n, int h, int w);
+hipError_t cnn_prepare(const float *params, void *prep, hipStream_t st);
+hipError_t cnn_forward(const void *prep, const float *x, int64_t n, int h, int w, float *out, void *ws, hipStream_t st);
+hipError_t cnn_train_step(float *params, float *adam_m, float *adam_v, int64_t t, float lr, const float *x,
+                          const float *mask, const float *logq, int64_t n, int h, int w, float lam, void *prep,
+                          float *grad_out, double *loss_out, void *ws, hipStream_t st);
+hipError_t cnn_layer_forward(int l, const void *prep, const void *in, int64_t n, int h, int w, float *out_f32,
+                             uint16_t *out_bf, hipStream_t st);
+hipError_t cnn_layer_backward(int l, const void *prep, const void *in, const uint16_t *dy, int64_t n, int h, int w,
+                              float *dw, float *db, float *dx_f32, uint16_t *dx_masked, const uint16_t *act_mask,
+                              void *scratch, hipStream_t st);
 
 }  // namespace qsq

@@ -21,6 +21,9 @@
 // of the trilinear interpolant with a lerp tree (Sect. 3.3).
 #include <math.h>
 
+#include <mutex>
+#include <type_traits>
+
 #include "qsq_internal.h"
 
 namespace qsq {
@@ -60,6 +63,14 @@ __device__ __forceinline__ V4<double> ld4(const double *__restrict__ p, int64_t 
     const double2 *q = reinterpret_cast<const double2 *>(p) + 2 * i;
     double2 a = q[0], b = q[1];
     return {a.x, a.y, b.x, b.y};
+}
+
+// BF16 records: one 8-byte load, each value widened to FP32 exactly
+__device__ __forceinline__ V4<float> ld4(const Bf16 *__restrict__ p, int64_t i)
+{
+    const uint2 v = reinterpret_cast<const uint2 *>(p)[i];
+    return {__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u), __uint_as_float(v.y << 16),
+            __uint_as_float(v.y & 0xffff0000u)};
 }
 
 // value and grid-unit partial derivatives of one trilinear component
@@ -116,10 +127,10 @@ __device__ __forceinline__ void field_at(const S *__restrict__ nodes, const Geom
     for (int d = 0; d < 3; ++d) cell_of(ib[d], q[d], g.n[d], c[d], t[d]);
     const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
     const int64_t b = (int64_t)c[2] * sz + (int64_t)c[1] * sy + c[0];
-    const V4<S> n000 = ld4(nodes, b), n100 = ld4(nodes, b + 1);
-    const V4<S> n010 = ld4(nodes, b + sy), n110 = ld4(nodes, b + sy + 1);
-    const V4<S> n001 = ld4(nodes, b + sz), n101 = ld4(nodes, b + sz + 1);
-    const V4<S> n011 = ld4(nodes, b + sz + sy), n111 = ld4(nodes, b + sz + sy + 1);
+    const auto n000 = ld4(nodes, b), n100 = ld4(nodes, b + 1);
+    const auto n010 = ld4(nodes, b + sy), n110 = ld4(nodes, b + sy + 1);
+    const auto n001 = ld4(nodes, b + sz), n101 = ld4(nodes, b + sz + 1);
+    const auto n011 = ld4(nodes, b + sz + sy), n111 = ld4(nodes, b + sz + sy + 1);
     T val[3], dx[3], dy[3], dz[3];
 #define QSQ_COMP(F, k)                                                                              \
     lerp_tree<T>((T)n000.F, (T)n100.F, (T)n010.F, (T)n110.F, (T)n001.F, (T)n101.F, (T)n011.F,       \
@@ -165,13 +176,10 @@ __device__ __forceinline__ void field_at(const S *__restrict__ nodes, const Geom
 
 // Right-hand side f(y) = sigma * (u, J dx1, J dx2), J_ij = d u_i / d x_j
 // (eq. 1 and eq. 5).  Returns |u|^2 for the null test.
-template <typename T, typename S, int MODE>
-__device__ __forceinline__ T rhs(const S *__restrict__ nodes, const Geom &g, const int ib[3],
-                                 const T q[3], T sigma, const T d1[3], const T d2[3], T kx[3],
-                                 T k1[3], T k2[3])
+template <typename T>
+__device__ __forceinline__ T rhs_from(T sigma, const T u[3], const T G[3][3], const T d1[3], const T d2[3],
+                                      T kx[3], T k1[3], T k2[3])
 {
-    T u[3], G[3][3], mag;
-    field_at<T, S, MODE, false>(nodes, g, ib, q, u, G, mag);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         kx[i] = sigma * u[i];
@@ -179,6 +187,133 @@ __device__ __forceinline__ T rhs(const S *__restrict__ nodes, const Geom &g, con
         k2[i] = sigma * (G[0][i] * d2[0] + G[1][i] * d2[1] + G[2][i] * d2[2]);
     }
     return u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+}
+
+template <typename T, typename S, int MODE>
+__device__ __forceinline__ T rhs(const S *__restrict__ nodes, const Geom &g, const int ib[3],
+                                 const T q[3], T sigma, const T d1[3], const T d2[3], T kx[3],
+                                 T k1[3], T k2[3])
+{
+    T u[3], G[3][3], mag;
+    field_at<T, S, MODE, false>(nodes, g, ib, q, u, G, mag);
+    return rhs_from(sigma, u, G, d1, d2, kx, k1, k2);
+}
+
+// Raw buffer load of 16 bytes.  Lanes whose byte offset lies at or beyond the
+// buffer's record count get zeros back without any memory access, which lets a
+// wave gather only for the lanes that need new data, with no divergent branch.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ f32x4 qsq_buffer_load16(__amdgpu_buffer_rsrc_t rsrc, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.raw.ptr.buffer.load.v4f32");
+
+// Buffer resource over the FP32 node records (gfx9 descriptor word 3).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t node_rsrc(const float *nodes, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(nodes), (short)0, bytes, 0x00020000);
+}
+
+// Per-lane cache of the 8 corner records (direction part, 24 floats) of the
+// cell a lane evaluated last, kept in LDS (6 float4 planes of one workgroup's
+// lanes, lane-consecutive, conflict-free 16-byte accesses).  Consecutive Runge-Kutta
+// stages mostly fall in the same cell: only lanes whose stage point moved to
+// another cell fetch from memory (the others issue out-of-range offsets, see
+// above) and store the new corners into their slot; every lane then reads its
+// slot (a wave's LDS operations complete in order).  Keyed by cell index
+// alone, so it stays valid across the lines a lane traces.
+constexpr int kCachePlanes = 6;
+
+template <typename T, int MODE>
+__device__ __forceinline__ T rhs_cached(__amdgpu_buffer_rsrc_t rsrc, int bytes, const Geom &g, const int ib[3],
+                                        const T q[3], T sigma, const T d1[3], const T d2[3], T kx[3], T k1[3],
+                                        T k2[3], int cc[3], float4 *slot, int stride)
+{
+    int c[3];
+    T t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) cell_of(ib[d], q[d], g.n[d], c[d], t[d]);
+    const bool miss = c[0] != cc[0] || c[1] != cc[1] || c[2] != cc[2];
+    const int sy = g.n[0], sz = g.n[0] * g.n[1];
+    const int base = miss ? 16 * (c[2] * sz + c[1] * sy + c[0]) : bytes;
+    float w[24];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int o = 16 * (((k & 1) ? 1 : 0) + ((k & 2) ? sy : 0) + ((k & 4) ? sz : 0));
+        const f32x4 x = qsq_buffer_load16(rsrc, base + o, 0, 0);
+        w[3 * k] = x.x;
+        w[3 * k + 1] = x.y;
+        w[3 * k + 2] = x.z;
+    }
+    if (miss) {
+#pragma unroll
+        for (int j = 0; j < kCachePlanes; ++j) slot[j * stride] = make_float4(w[4 * j], w[4 * j + 1], w[4 * j + 2], w[4 * j + 3]);
+    }
+    cc[0] = c[0];
+    cc[1] = c[1];
+    cc[2] = c[2];
+    float v[24];
+#pragma unroll
+    for (int j = 0; j < kCachePlanes; ++j) {
+        const float4 x = slot[j * stride];
+        v[4 * j] = x.x;
+        v[4 * j + 1] = x.y;
+        v[4 * j + 2] = x.z;
+        v[4 * j + 3] = x.w;
+    }
+    T val[3], dx[3], dy[3], dz[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        lerp_tree<T>((T)v[i], (T)v[3 + i], (T)v[6 + i], (T)v[9 + i], (T)v[12 + i], (T)v[15 + i],
+                     (T)v[18 + i], (T)v[21 + i], t[0], t[1], t[2], val[i], dx[i], dy[i], dz[i]);
+    const T ihx = (T)g.ih[0], ihy = (T)g.ih[1], ihz = (T)g.ih[2];
+    T u[3], G[3][3];
+    if (MODE == QSQ_INTERP_PAPER) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            u[i] = val[i];
+            G[0][i] = dx[i] * ihx;
+            G[1][i] = dy[i] * ihy;
+            G[2][i] = dz[i] * ihz;
+        }
+    } else {
+        const T bb = val[0] * val[0] + val[1] * val[1] + val[2] * val[2];
+        const T bn = sqrt(bb);
+        const T inv = bn > (T)1e-300 ? (T)1 / bn : (T)0;
+        T Gb[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            u[i] = val[i] * inv;
+            Gb[0][i] = dx[i] * ihx;
+            Gb[1][i] = dy[i] * ihy;
+            Gb[2][i] = dz[i] * ihz;
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const T ug = u[0] * Gb[j][0] + u[1] * Gb[j][1] + u[2] * Gb[j][2];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) G[j][i] = (Gb[j][i] - u[i] * ug) * inv;
+        }
+    }
+    return rhs_from(sigma, u, G, d1, d2, kx, k1, k2);
+}
+
+// a / b of the error norm: FP32 stepping multiplies by the hardware
+// reciprocal (within 1 ulp; the norm only steers accept/reject and the step
+// factor), FP64 stepping divides exactly
+__device__ __forceinline__ float err_ratio(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double err_ratio(double a, double b) { return a / b; }
+
+// one RHS evaluation of the stepping kernel: cached gathers (FP32 storage and
+// stepping, field below 2 GiB) or direct gathers
+template <typename T, typename S, int MODE, bool CACHED>
+__device__ __forceinline__ T rhs_step(const S *__restrict__ nodes, __amdgpu_buffer_rsrc_t rsrc, int bytes,
+                                      const Geom &g, const int ib[3], const T q[3], T sigma, const T d1[3],
+                                      const T d2[3], T kx[3], T k1[3], T k2[3], int cc[3], float4 *slot,
+                                      int stride)
+{
+    if constexpr (CACHED)
+        return rhs_cached<T, MODE>(rsrc, bytes, g, ib, q, sigma, d1, d2, kx, k1, k2, cc, slot, stride);
+    else
+        return rhs<T, S, MODE>(nodes, g, ib, q, sigma, d1, d2, kx, k1, k2);
 }
 
 // FP64 evaluation at a physical point (landing, assembly, seed frame)
@@ -249,17 +384,111 @@ __device__ __forceinline__ int64_t seed_count(const TraceJob &j)
 }
 
 // ---------------------------------------------------------------------------
+// seed pass (FP64, one thread per seed): frame of eq. (9), and the half-lines
+// that end at once -- seed outside the box, a null at the seed, or a seed on a
+// face with its (signed) field pointing out (zero length, lowest such face).
+// The others are flagged for stepping.
+// ---------------------------------------------------------------------------
+// set holding global seed i: the last set whose first seed is <= i (empty
+// sets share their offset with the next set and are skipped)
+__device__ __forceinline__ int find_set(const SetDesc *sets, int nsets, int64_t i)
+{
+    int lo = 0, hi = nsets - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sets[mid].off <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename S, int MODE, bool BATCH>
+__global__ void __launch_bounds__(256) k_seed_pass(TraceJob job)
+{
+    const int64_t n = seed_count(job);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *job.rec.n_items = 2 * n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
+        Geom gl = job.g;
+        const double *sp = job.seeds;
+        int64_t ss = job.seed_stride, li = i;
+        if constexpr (BATCH) {
+            const int set = find_set(job.sets, job.nsets, i);
+            job.set_of[i] = set;
+            const SetDesc &sd = job.sets[set];
+            gl = sd.g;
+            nodes = static_cast<const S *>(sd.nodes);
+            sp = sd.seeds;
+            ss = sd.n;
+            li = i - sd.off;
+        }
+        const Geom &g = gl;
+        const double x0[3] = {sp[li], sp[ss + li], sp[2 * ss + li]};
+        double y0[9] = {x0[0], x0[1], x0[2], 0, 0, 0, 0, 0, 0};
+        int st[2] = {-1, -1};
+        if (outside_box(g, x0[0], x0[1], x0[2])) {
+            st[0] = st[1] = QSQ_END_SEED_OUTSIDE;
+        } else {
+            double u[3], G[3][3], mag;
+            field_at_x<S, MODE, false>(nodes, g, x0, u, G, mag);
+            const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            if (un < 1e-6) {
+                st[0] = st[1] = QSQ_END_NULL;
+            } else {
+                const double nn[3] = {u[0] / un, u[1] / un, u[2] / un};
+                double a[3], b[3];
+                frame_of(nn, a, b);
+                for (int k = 0; k < 3; ++k) {
+                    y0[3 + k] = a[k];
+                    y0[6 + k] = b[k];
+                }
+                for (int dir = 0; dir < 2; ++dir) {
+                    const double sg = dir ? -1.0 : 1.0;
+                    int face = -1;
+                    for (int f = 0; f < 6 && face < 0; ++f) {
+                        const int d = f >> 1;
+                        const bool on = (f & 1) ? x0[d] == g.hi[d] : x0[d] == g.lo[d];
+                        const double out = (f & 1) ? sg * nn[d] : -sg * nn[d];
+                        if (on && out > 0.0) face = f;
+                    }
+                    st[dir] = face >= 0 ? face : kPendingStep;
+                }
+            }
+        }
+        for (int dir = 0; dir < 2; ++dir) {
+            put_rec(job.rec, dir * job.rec.cap + i, y0, 0.0, 0.0, st[dir], 0);
+            job.rec.flag[dir * n + i] = st[dir] == kPendingStep ? 1 : 0;
+        }
+    }
+}
+
+// work list: record indices of the flagged half-lines, forward ones first,
+// each in seed order
+__global__ void k_compact(TraceJob job)
+{
+    const int64_t n2 = *job.rec.n_items, n = n2 / 2;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n2; it += (int64_t)gridDim.x * blockDim.x)
+        if (job.rec.flag[it]) job.rec.work[job.rec.wpos[it]] = (int32_t)(it >= n ? job.rec.cap + (it - n) : it);
+}
+
+// ---------------------------------------------------------------------------
 // k_trace: persistent stepping kernel
 // ---------------------------------------------------------------------------
-template <typename T, typename S, int MODE>
+template <typename T, typename S, int MODE, bool CACHED, bool BATCH>
 __global__ void __launch_bounds__(256) k_trace(TraceJob job)
 {
+    static_assert(!(CACHED && BATCH), "cached gathers need one field per launch");
+    // field and step limits of the lane's line: launch constants for one
+    // field, reloaded from the set table at each refill in a batch
     const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
-    const Geom &g = job.g;
+    Geom gl = job.g;
+    const Geom &g = gl;
     const StepOpts &o = job.o;
+    double h_init = o.h_init, hmin = o.hmin;
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t n = seed_count(job);
-    const int64_t total = 2 * n;
+    const int64_t total = *job.rec.n_work;
 
     // lane state
     double X[3] = {0, 0, 0}, s = 0.0;
@@ -270,75 +499,87 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
     bool active = false, done = false, have_k1 = false;
     T Kx[6][3], K1[6][3], K2[6][3];
 
-    const T rtol = (T)o.rtol, atol = (T)o.atol, hmax = (T)o.h_max;
-    const T ih[3] = {(T)g.ih[0], (T)g.ih[1], (T)g.ih[2]};
+    const T rtol = (T)o.rtol, atol = (T)o.atol;
+    T hmax = (T)o.h_max;
+    T ih[3] = {(T)g.ih[0], (T)g.ih[1], (T)g.ih[2]};
     unsigned long long c_att = 0, c_ev = 0, c_act = 0, c_land = 0;   // work counters
+    // cached-gather state
+    const int cbytes = CACHED ? (int)((uint64_t)16 * g.n[0] * g.n[1] * g.n[2]) : 0;
+    const __amdgpu_buffer_rsrc_t rsrc = node_rsrc(reinterpret_cast<const float *>(job.nodes), cbytes);
+    int cache_cell[3] = {-1, -1, -1};
+    // LDS cell cache: kCachePlanes planes of blockDim.x float4 (dynamic size)
+    extern __shared__ float4 lds_cache[];
+    const int stride = (int)blockDim.x;
+    float4 *slot = lds_cache + threadIdx.x;
 
+    // Work distribution: the first item of every lane is its global lane index
+    // (the launcher starts the counter at the launch's lane count); after that
+    // each wave takes chunks of kChunk items with one atomic and hands them to
+    // its idle lanes itself, so the shared counter is touched once per chunk
+    // rather than on every iteration in which a lane finished a line.
+    constexpr int64_t kChunk = 64;
+    int64_t cnext = 0, cend = 0;   // the wave's unassigned items [cnext, cend)
+    bool first_fill = true;
     for (;;) {
-        // ---- refill idle lanes from the work counter (one atomic per wave)
+        // ---- refill idle lanes
         const uint64_t need = __ballot(!active && !done);
         if (need) {
-            const int leader = __ffsll((unsigned long long)need) - 1;
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(job.counter, (unsigned long long)__popcll(need));
-            base = __shfl(base, leader);
+            const int j = __popcll(need & ((1ull << lane) - 1ull));   // rank among idle lanes
+            int64_t item;
+            if (first_fill) {
+                item = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u) + j;
+            } else {
+                const int k = __popcll(need);
+                const int64_t avail = cend - cnext;
+                int64_t fresh = 0;
+                if (avail < k) {
+                    unsigned long long b = 0;
+                    const int leader = __ffsll((unsigned long long)need) - 1;
+                    if (lane == leader) b = atomicAdd(job.counter, (unsigned long long)kChunk);
+                    fresh = (int64_t)__shfl(b, leader);
+                }
+                item = j < avail ? cnext + j : fresh + (j - avail);
+                if (avail < k) {
+                    cnext = fresh + (k - avail);
+                    cend = fresh + kChunk;
+                } else {
+                    cnext += k;
+                }
+            }
+            first_fill = false;
             if (!active && !done) {
-                const int64_t item = (int64_t)base + __popcll(need & ((1ull << lane) - 1ull));
                 if (item >= total) {
                     done = true;
                 } else {
-                    const int dir = item >= n ? 1 : 0;
-                    const int64_t seed = dir ? item - n : item;
-                    rec = dir * job.rec.cap + seed;
-                    sigma = dir ? (T)-1 : (T)1;
-                    const double x0[3] = {job.seeds[seed], job.seeds[job.seed_stride + seed],
-                                          job.seeds[2 * job.seed_stride + seed]};
-                    double y0[9] = {x0[0], x0[1], x0[2], 0, 0, 0, 0, 0, 0};
-                    if (outside_box(g, x0[0], x0[1], x0[2])) {
-                        put_rec(job.rec, rec, y0, 0.0, 0.0, QSQ_END_SEED_OUTSIDE, 0);
-                    } else {
-                        double u[3], G[3][3], mag;
-                        field_at_x<S, MODE, false>(nodes, g, x0, u, G, mag);
-                        const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-                        if (un < 1e-6) {
-                            put_rec(job.rec, rec, y0, 0.0, 0.0, QSQ_END_NULL, 0);
-                        } else {
-                            const double nn[3] = {u[0] / un, u[1] / un, u[2] / un};
-                            double a[3], b[3];
-                            frame_of(nn, a, b);   // eq. (9)
-                            for (int k = 0; k < 3; ++k) {
-                                y0[3 + k] = a[k];
-                                y0[6 + k] = b[k];
-                            }
-                            // a seed on a face whose (signed) field points out of the
-                            // box ends there: zero length, lowest such face
-                            const double sg = dir ? -1.0 : 1.0;
-                            int face = -1;
-                            for (int f = 0; f < 6 && face < 0; ++f) {
-                                const int d = f >> 1;
-                                const bool on = (f & 1) ? x0[d] == g.hi[d] : x0[d] == g.lo[d];
-                                const double out = (f & 1) ? sg * nn[d] : -sg * nn[d];
-                                if (on && out > 0.0) face = f;
-                            }
-                            if (face >= 0) {
-                                put_rec(job.rec, rec, y0, 0.0, 0.0, face, 0);
-                            } else {
-                                X[0] = x0[0];
-                                X[1] = x0[1];
-                                X[2] = x0[2];
-                                for (int k = 0; k < 3; ++k) {
-                                    D1[k] = (T)a[k];
-                                    D2[k] = (T)b[k];
-                                }
-                                s = 0.0;
-                                h = (T)o.h_init;
-                                attempts = 0;
-                                have_k1 = false;
-                                active = true;
-                                ++c_act;
-                            }
-                        }
+                    // the seed pass left x0 and the frame (eq. 9) in the record
+                    rec = job.rec.work[item];
+                    const int dir = rec >= job.rec.cap ? 1 : 0;
+                    if constexpr (BATCH) {
+                        const SetDesc &sd = job.sets[job.set_of[dir ? rec - job.rec.cap : rec]];
+                        gl = sd.g;
+                        nodes = static_cast<const S *>(sd.nodes);
+                        h_init = sd.h_init;
+                        hmin = sd.hmin;
+                        hmax = (T)sd.h_max;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) ih[d] = (T)gl.ih[d];
                     }
+                    sigma = dir ? (T)-1 : (T)1;
+                    const int64_t P = 2 * job.rec.cap;
+                    X[0] = job.rec.y[rec];
+                    X[1] = job.rec.y[P + rec];
+                    X[2] = job.rec.y[2 * P + rec];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        D1[k] = (T)job.rec.y[(3 + k) * P + rec];
+                        D2[k] = (T)job.rec.y[(6 + k) * P + rec];
+                    }
+                    s = 0.0;
+                    h = (T)h_init;
+                    attempts = 0;
+                    have_k1 = false;
+                    active = true;
+                    ++c_act;
                 }
             }
         }
@@ -360,7 +601,8 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
                 fb[d] = (T)(xg - fl);
             }
             if (!have_k1) {
-                const T un2 = rhs<T, S, MODE>(nodes, g, ib, fb, sigma, D1, D2, Kx[0], K1[0], K2[0]);
+                const T un2 = rhs_step<T, S, MODE, CACHED>(nodes, rsrc, cbytes, g, ib, fb, sigma, D1, D2, Kx[0], K1[0], K2[0],
+                                                   cache_cell, slot, stride);
                 ++c_ev;
                 if (!(un2 >= (T)1e-12)) stop = QSQ_END_NULL;
                 have_k1 = true;
@@ -391,7 +633,8 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
             d1[i] = fma(hs, a1, D1[i]);                                                             \
             d2[i] = fma(hs, a2, D2[i]);                                                             \
         }                                                                                           \
-        rhs<T, S, MODE>(nodes, g, ib, q, sigma, d1, d2, Kx[ST], K1[ST], K2[ST]);                    \
+        rhs_step<T, S, MODE, CACHED>(nodes, rsrc, cbytes, g, ib, q, sigma, d1, d2, Kx[ST], K1[ST], K2[ST], \
+                             cache_cell, slot, stride);                                             \
     }
             QSQ_STAGE(1, (T)ck::a21)
             QSQ_STAGE(2, (T)ck::a31, (T)ck::a32)
@@ -402,8 +645,8 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
             // 5th-order solution (propagated) and the error estimate y5 - y4
             double Xn[3];
             T D1n[3], D2n[3];
-            T err = 0;
-            bool finite = true;
+            T err = 0, fsum = 0;
+            bool finite;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 const T bx = (T)ck::b1 * Kx[0][i] + (T)ck::b3 * Kx[2][i] + (T)ck::b4 * Kx[3][i] + (T)ck::b6 * Kx[5][i];
@@ -419,12 +662,14 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
                 const T sx = atol + rtol * fmax(fabs(xo), fabs(xn));
                 const T s1 = atol + rtol * fmax(fabs(D1[i]), fabs(D1n[i]));
                 const T s2 = atol + rtol * fmax(fabs(D2[i]), fabs(D2n[i]));
-                err = fmax(err, fabs(hs * ex) / sx);
-                err = fmax(err, fabs(hs * e1) / s1);
-                err = fmax(err, fabs(hs * e2) / s2);
-                finite = finite && isfinite(xn) && isfinite(D1n[i]) && isfinite(D2n[i]) &&
-                         isfinite(ex) && isfinite(e1) && isfinite(e2);
+                err = fmax(err, err_ratio(fabs(hs * ex), sx));
+                err = fmax(err, err_ratio(fabs(hs * e1), s1));
+                err = fmax(err, err_ratio(fabs(hs * e2), s2));
+                // one test for the whole state: an infinity or NaN anywhere
+                // makes the sum non-finite
+                fsum += (xn + D1n[i]) + (D2n[i] + ex) + (e1 + e2);
             }
+            finite = isfinite(fsum);
             ++attempts;
             ++c_att;
             c_ev += 5;
@@ -434,7 +679,7 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
                 // reject: shrink, keep k1 (y is unchanged)
                 const T f = (T)0.9 * (T)exp2((T)-0.25 * (T)log2(err));
                 h = hs * (f > (T)0.2 ? f : (T)0.2);
-                if ((double)h < o.hmin) stop = QSQ_END_UNDERFLOW;
+                if ((double)h < hmin) stop = QSQ_END_UNDERFLOW;
             } else if (outside_box(g, Xn[0], Xn[1], Xn[2])) {
                 // accepted trial step leaves the box: hand over to FP64 landing
                 const double y[9] = {X[0], X[1], X[2], (double)D1[0], (double)D1[1], (double)D1[2],
@@ -555,17 +800,26 @@ __device__ double face_gap(const S *nodes, const Geom &g, double sigma, const do
 // ---------------------------------------------------------------------------
 // k_land: FP64 landing of pending half-lines on the first face crossed
 // ---------------------------------------------------------------------------
-template <typename S, int MODE>
+template <typename S, int MODE, bool BATCH>
 __global__ void __launch_bounds__(256) k_land(TraceJob job)
 {
-    const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
-    const Geom &g = job.g;
     const int64_t n = seed_count(job);
     for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < 2 * n;
          it += (int64_t)gridDim.x * blockDim.x) {
         const int dir = it >= n ? 1 : 0;
-        const int64_t r = dir * job.rec.cap + (dir ? it - n : it);
+        const int64_t i = dir ? it - n : it;
+        const int64_t r = dir * job.rec.cap + i;
         if (job.rec.status[r] != kPendingLand) continue;
+        const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
+        Geom gl = job.g;
+        double gtol = job.o.gtol;
+        if constexpr (BATCH) {
+            const SetDesc &sd = job.sets[job.set_of[i]];
+            gl = sd.g;
+            nodes = static_cast<const S *>(sd.nodes);
+            gtol = sd.gtol;
+        }
+        const Geom &g = gl;
         const double sigma = dir ? -1.0 : 1.0;
         double y[9], s, hs, y5[9];
         get_rec(job.rec, r, y, s, hs);
@@ -596,7 +850,7 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
                 for (int k = 0; k < 200; ++k) {
                     const double c = (a * gb - b * ga) / (gb - ga);
                     const double gc = face_gap<S, MODE>(nodes, g, sigma, y, c, f, yo);
-                    if (fabs(gc) <= job.o.gtol) {
+                    if (fabs(gc) <= gtol) {
                         hf = c;
                         break;
                     }
@@ -662,17 +916,39 @@ __device__ __forceinline__ double q_bracket(const double *aF, const double *bF, 
     return dot3(aF, aF) * dot3(bB, bB) + dot3(aB, aB) * dot3(bF, bF) - 2.0 * dot3(aB, bB) * dot3(aF, bF);
 }
 
-template <typename S, int MODE>
+template <typename S, int MODE, bool BATCH>
 __global__ void __launch_bounds__(256) k_assemble(TraceJob job)
 {
-    const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
-    const Geom &g = job.g;
     const int64_t n = seed_count(job);
     const int64_t P = 2 * job.rec.cap;
-    const int64_t os = job.out_stride;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t rF = i, rB = job.rec.cap + i;
+        // field, seeds and outputs of the seed (its set's in a batch)
+        const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
+        Geom gl = job.g;
+        const double *seeds = job.seeds;
+        int64_t ss = job.seed_stride, os = job.out_stride, li = i;
+        double *o_fpf = job.fp_fwd, *o_fpb = job.fp_bwd, *o_fll = job.fll;
+        double *o_qp = job.q_perp, *o_qd = job.q_det, *o_qf = job.q_fp;
+        int32_t *o_st = job.status, *o_steps = job.steps;
+        if constexpr (BATCH) {
+            const SetDesc &sd = job.sets[job.set_of[i]];
+            gl = sd.g;
+            nodes = static_cast<const S *>(sd.nodes);
+            seeds = sd.seeds;
+            ss = os = sd.n;
+            li = i - sd.off;
+            o_fpf = sd.fp_fwd;
+            o_fpb = sd.fp_bwd;
+            o_fll = sd.fll;
+            o_qp = sd.q_perp;
+            o_qd = sd.q_det;
+            o_qf = sd.q_fp;
+            o_st = sd.status;
+            o_steps = sd.steps;
+        }
+        const Geom &g = gl;
         const int stF = job.rec.status[rF], stB = job.rec.status[rB];
         double yF[9], yB[9];
 #pragma unroll
@@ -683,23 +959,22 @@ __global__ void __launch_bounds__(256) k_assemble(TraceJob job)
         const double sF = job.rec.s[rF], sB = job.rec.s[rB];
         const bool open = !(stF == QSQ_END_ZLO && stB == QSQ_END_ZLO);
         const int word = (stF & 0xff) | ((stB & 0xff) << 8) | (open ? QSQ_STATUS_OPEN : 0);
-        job.status[i] = word;
-        if (job.fll) job.fll[i] = sF + sB;
-        if (job.fp_fwd)
-            for (int k = 0; k < 3; ++k) job.fp_fwd[k * os + i] = yF[k];
-        if (job.fp_bwd)
-            for (int k = 0; k < 3; ++k) job.fp_bwd[k * os + i] = yB[k];
-        if (job.steps) {
-            job.steps[i] = job.rec.attempts[rF];
-            job.steps[os + i] = job.rec.attempts[rB];
+        o_st[li] = word;
+        if (o_fll) o_fll[li] = sF + sB;
+        if (o_fpf)
+            for (int k = 0; k < 3; ++k) o_fpf[k * os + li] = yF[k];
+        if (o_fpb)
+            for (int k = 0; k < 3; ++k) o_fpb[k * os + li] = yB[k];
+        if (o_steps) {
+            o_steps[li] = job.rec.attempts[rF];
+            o_steps[os + li] = job.rec.attempts[rB];
         }
         double qp = NAN, qd = NAN, qf = NAN;
         const bool defF = stF >= QSQ_END_XLO && stF <= QSQ_END_MAX_STEPS;
         const bool defB = stB >= QSQ_END_XLO && stB <= QSQ_END_MAX_STEPS;
         const bool skip = (job.o.flags & QSQ_FLAG_SKIP_OPEN) && open;
         if (defF && defB && !skip) {
-            const double x0[3] = {job.seeds[i], job.seeds[job.seed_stride + i],
-                                  job.seeds[2 * job.seed_stride + i]};
+            const double x0[3] = {seeds[li], seeds[ss + li], seeds[2 * ss + li]};
             double G[3][3], uF[3], uB[3], u0[3], BF, BB, B0;
             field_at_x<S, MODE, true>(nodes, g, yF, uF, G, BF);
             field_at_x<S, MODE, true>(nodes, g, yB, uB, G, BB);
@@ -738,13 +1013,13 @@ __global__ void __launch_bounds__(256) k_assemble(TraceJob job)
                 qf = q_bracket(pF1, pF2, pB1, pB2) / (cross_len(pF1, pF2) * cross_len(pB1, pB2));
             }
         }
-        if (job.q_perp) job.q_perp[i] = qp;
-        if (job.q_det) job.q_det[i] = qd;
-        if (job.q_fp) job.q_fp[i] = qf;
+        if (o_qp) o_qp[li] = qp;
+        if (o_qd) o_qd[li] = qd;
+        if (o_qf) o_qf[li] = qf;
     }
 }
 
-__global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
+__global__ void k_set_u64(unsigned long long *p, unsigned long long v) { *p = v; }
 
 // ---------------------------------------------------------------------------
 // host side
@@ -752,7 +1027,7 @@ __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
 uint64_t records_bytes(int64_t cap)
 {
     const uint64_t P = 2 * (uint64_t)cap;
-    return P * (11 * sizeof(double) + 2 * sizeof(int32_t));
+    return P * (11 * sizeof(double) + 5 * sizeof(int32_t)) + (uint64_t)scan_tmp_words((int64_t)P) * 8;
 }
 
 void carve_records(void *scratch, int64_t cap, Records *rec, unsigned long long **counter)
@@ -761,6 +1036,7 @@ void carve_records(void *scratch, int64_t cap, Records *rec, unsigned long long 
     *counter = reinterpret_cast<unsigned long long *>(p);
     p += 256;
     const uint64_t P = 2 * (uint64_t)cap;
+    // the scan's block sums need 8-byte alignment; planes below keep it
     rec->y = reinterpret_cast<double *>(p);
     p += 9 * P * sizeof(double);
     rec->s = reinterpret_cast<double *>(p);
@@ -770,7 +1046,18 @@ void carve_records(void *scratch, int64_t cap, Records *rec, unsigned long long 
     rec->status = reinterpret_cast<int32_t *>(p);
     p += P * sizeof(int32_t);
     rec->attempts = reinterpret_cast<int32_t *>(p);
+    p += P * sizeof(int32_t);
+    rec->flag = reinterpret_cast<int32_t *>(p);
+    p += P * sizeof(int32_t);
+    rec->wpos = reinterpret_cast<int32_t *>(p);
+    p += P * sizeof(int32_t);
+    rec->work = reinterpret_cast<int32_t *>(p);
+    p += P * sizeof(int32_t);
+    rec->scan_tmp = reinterpret_cast<int64_t *>(p);
     rec->cap = cap;
+    // device scalars share the 256-byte block with the work counter
+    rec->n_work = reinterpret_cast<int64_t *>(static_cast<char *>(scratch) + 8);
+    rec->n_items = reinterpret_cast<int64_t *>(static_cast<char *>(scratch) + 16);
 }
 
 int device_cu_count()
@@ -787,47 +1074,141 @@ int device_cu_count()
     return cus[dev];
 }
 
-template <typename T, typename S, int MODE>
+// Workgroups of `kern` (wg lanes, lds bytes of dynamic LDS) that stay resident
+// on one CU together, from the runtime's occupancy calculator (cached).
+static int resident_blocks(const void *kern, int wg, size_t lds)
+{
+    struct Entry {
+        const void *k;
+        int wg;
+        size_t lds;
+        int n;
+    };
+    static Entry cache[64];
+    static int used = 0;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    for (int i = 0; i < used; ++i)
+        if (cache[i].k == kern && cache[i].wg == wg && cache[i].lds == lds) return cache[i].n;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, wg, lds) != hipSuccess || n < 1) n = 1;
+    if (used < 64) cache[used++] = Entry{kern, wg, lds, n};
+    return n;
+}
+
+template <typename T, typename S, int MODE, bool BATCH>
 static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
 {
     const int cus = device_cu_count();
     const int64_t n_max = job.n_dev ? job.rec.cap : job.n_host;
     if (n_max <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, job.counter);
-    int64_t want = (2 * n_max + 255) / 256;
-    int blocks = (int)(want < (int64_t)cus * 8 ? want : (int64_t)cus * 8);
+    int64_t sb = (n_max + 255) / 256;
+    const int sblocks = (int)(sb < (int64_t)cus * 16 ? sb : (int64_t)cus * 16);
+    hipLaunchKernelGGL((k_seed_pass<S, MODE, BATCH>), dim3(sblocks), dim3(256), 0, st, job);
+    launch_scan_i32(job.rec.flag, job.rec.n_items, 2 * n_max, job.rec.scan_tmp, job.rec.wpos, job.rec.n_work, st);
+    int64_t cb = (2 * n_max + 255) / 256;
+    const int cblocks = (int)(cb < (int64_t)cus * 16 ? cb : (int64_t)cus * 16);
+    hipLaunchKernelGGL(k_compact, dim3(cblocks), dim3(256), 0, st, job);
+    // launch shape (QSQ_LAUNCH word): workgroup size and a resident-lane
+    // target per CU, capped by what the kernel's registers and LDS let stay
+    // resident, so that every workgroup of the persistent launch runs from the
+    // start (the first item of each lane is its global index)
+    const int lanes = (job.o.launch & 15) ? (job.o.launch & 15) : 8;
+    const int wg_code = (job.o.launch >> 4) & 3, gather = (job.o.launch >> 6) & 3;
+    const int wg = wg_code == 1 ? 64 : wg_code == 2 ? 128 : 256;
+    const void *kern;
+    size_t lds = 0;
+    if constexpr (BATCH) {
+        kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, false, true>);
+    } else if constexpr (sizeof(T) == 4 && std::is_same<S, float>::value) {
+        // cached gathers (FP32 records and stepping) address the node records
+        // with 32-bit byte offsets
+        const uint64_t field_bytes = (uint64_t)16 * job.g.n[0] * job.g.n[1] * job.g.n[2];
+        if (gather != 1 && field_bytes < ((uint64_t)1 << 31) - ((uint64_t)1 << 26)) {
+            kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, true, false>);
+            lds = kCachePlanes * wg * sizeof(float4);
+        } else {
+            kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, false, false>);
+        }
+    } else {
+        (void)gather;
+        kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, false, false>);
+    }
+    const int64_t resident = (int64_t)cus * resident_blocks(kern, wg, lds);
+    int64_t cap_blocks = (int64_t)cus * lanes * (256 / wg);
+    if (cap_blocks > resident) cap_blocks = resident;
+    const int64_t want = (2 * n_max + wg - 1) / wg;
+    const int blocks = (int)(want < cap_blocks ? want : cap_blocks);
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, job.counter, (unsigned long long)blocks * wg);
     const bool prof = profiling();
     void *tok = nullptr;
     if (prof) prof_begin(kProfStep, st, &tok);
-    hipLaunchKernelGGL((k_trace<T, S, MODE>), dim3(blocks), dim3(256), 0, st, job);
+    void *args[] = {const_cast<TraceJob *>(&job)};
+    hipLaunchKernel(kern, dim3(blocks), dim3(wg), args, lds, st);
     if (prof) prof_end(tok, st);
     int64_t lb = (2 * n_max + 255) / 256;
     int lblocks = (int)(lb < (int64_t)cus * 16 ? lb : (int64_t)cus * 16);
     if (prof) prof_begin(kProfLand, st, &tok);
-    hipLaunchKernelGGL((k_land<S, MODE>), dim3(lblocks), dim3(256), 0, st, job);
+    hipLaunchKernelGGL((k_land<S, MODE, BATCH>), dim3(lblocks), dim3(256), 0, st, job);
     if (prof) prof_end(tok, st);
     int64_t ab = (n_max + 255) / 256;
     int ablocks = (int)(ab < (int64_t)cus * 16 ? ab : (int64_t)cus * 16);
     if (prof) prof_begin(kProfAssemble, st, &tok);
-    hipLaunchKernelGGL((k_assemble<S, MODE>), dim3(ablocks), dim3(256), 0, st, job);
+    hipLaunchKernelGGL((k_assemble<S, MODE, BATCH>), dim3(ablocks), dim3(256), 0, st, job);
     if (prof) prof_end(tok, st);
     return hipGetLastError();
 }
 
-hipError_t launch_trace(const TraceJob &job, int step_dtype, hipStream_t st)
+template <bool BATCH>
+static hipError_t dispatch(const TraceJob &job, int step_dtype, hipStream_t st)
 {
     const bool f32 = step_dtype == QSQ_F32;
     const bool paper = job.mode == QSQ_INTERP_PAPER;
-    if (job.storage == QSQ_F32) {
-        if (f32) return paper ? launch_typed<float, float, QSQ_INTERP_PAPER>(job, st)
-                              : launch_typed<float, float, QSQ_INTERP_NORMALIZE>(job, st);
-        return paper ? launch_typed<double, float, QSQ_INTERP_PAPER>(job, st)
-                     : launch_typed<double, float, QSQ_INTERP_NORMALIZE>(job, st);
+    constexpr int P = QSQ_INTERP_PAPER, N = QSQ_INTERP_NORMALIZE;
+    if (job.storage == QSQ_BF16) {
+        if (f32) return paper ? launch_typed<float, Bf16, P, BATCH>(job, st) : launch_typed<float, Bf16, N, BATCH>(job, st);
+        return paper ? launch_typed<double, Bf16, P, BATCH>(job, st) : launch_typed<double, Bf16, N, BATCH>(job, st);
     }
-    if (f32) return paper ? launch_typed<float, double, QSQ_INTERP_PAPER>(job, st)
-                          : launch_typed<float, double, QSQ_INTERP_NORMALIZE>(job, st);
-    return paper ? launch_typed<double, double, QSQ_INTERP_PAPER>(job, st)
-                 : launch_typed<double, double, QSQ_INTERP_NORMALIZE>(job, st);
+    if (job.storage == QSQ_F32) {
+        if (f32) return paper ? launch_typed<float, float, P, BATCH>(job, st) : launch_typed<float, float, N, BATCH>(job, st);
+        return paper ? launch_typed<double, float, P, BATCH>(job, st) : launch_typed<double, float, N, BATCH>(job, st);
+    }
+    if (f32) return paper ? launch_typed<float, double, P, BATCH>(job, st) : launch_typed<float, double, N, BATCH>(job, st);
+    return paper ? launch_typed<double, double, P, BATCH>(job, st) : launch_typed<double, double, N, BATCH>(job, st);
+}
+
+hipError_t launch_trace(const TraceJob &job, int step_dtype, hipStream_t st)
+{
+    return dispatch<false>(job, step_dtype, st);
+}
+
+// The set table travels in kernel arguments, a few entries per launch, so
+// that the whole batched call is plain kernel launches (capturable in a graph,
+// no host buffer that must outlive the call).
+constexpr int kSetsPerPut = 6;
+struct SetChunk {
+    SetDesc d[kSetsPerPut];
+    int first, count;
+};
+
+__global__ void k_put_sets(SetDesc *table, SetChunk c)
+{
+    const int k = (int)threadIdx.x;
+    if (k < c.count) table[c.first + k] = c.d[k];
+}
+
+hipError_t launch_trace_batch(const TraceJob &job, const SetDesc *host_sets, int nsets, int step_dtype,
+                              hipStream_t st)
+{
+    SetDesc *table = const_cast<SetDesc *>(job.sets);
+    for (int first = 0; first < nsets; first += kSetsPerPut) {
+        SetChunk c{};
+        c.first = first;
+        c.count = nsets - first < kSetsPerPut ? nsets - first : kSetsPerPut;
+        for (int k = 0; k < c.count; ++k) c.d[k] = host_sets[first + k];
+        hipLaunchKernelGGL(k_put_sets, dim3(1), dim3(64), 0, st, table, c);
+    }
+    return dispatch<true>(job, step_dtype, st);
 }
 
 }  // namespace qsq

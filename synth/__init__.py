@@ -73,8 +73,11 @@ def point_charges(seed: int, count: int, depth=(0.05, 0.15), xy=0.5, q=(0.5, 1.5
     return np.column_stack([pos[:, 0], pos[:, 1], -dep, qv])
 
 
-def sample_charges(charges, n, lo=LO, hi=HI, dtype=np.float32, zchunk=16):
-    """B = sum q (r - r_i)/|r - r_i|^3 on the nodes (FP64 sums, cast at the end)."""
+def sample_charges(charges, n, lo=LO, hi=HI, dtype=np.float32, zchunk=16, device=None):
+    """B = sum q (r - r_i)/|r - r_i|^3 on the nodes (FP64 sums, cast at the end;
+    with torch on `device` if given, else numpy)."""
+    if device is not None:
+        return _sample_charges_torch(charges, n, lo, hi, dtype, device)
     xs, ys, zs = node_coords(n, lo, hi)
     nx, ny, nz = n
     out = [np.empty((nz, ny, nx), dtype) for _ in range(3)]
@@ -95,6 +98,21 @@ def sample_charges(charges, n, lo=LO, hi=HI, dtype=np.float32, zchunk=16):
         for i in range(3):
             out[i][z0:z0 + zz.size] = acc[i].astype(dtype)
     return out
+
+
+def _sample_charges_torch(charges, n, lo, hi, dtype, device):
+    import torch
+    f64 = dict(dtype=torch.float64, device=torch.device(device))
+    xs, ys, zs = (torch.tensor(c, **f64) for c in node_coords(n, lo, hi))
+    Z, Y, X = torch.meshgrid(zs, ys, xs, indexing="ij")
+    acc = [torch.zeros_like(X) for _ in range(3)]
+    for cx, cy, cz, q in np.asarray(charges, float):
+        dx, dy, dz = X - cx, Y - cy, Z - cz
+        inv3 = q * (dx * dx + dy * dy + dz * dz) ** -1.5
+        acc[0] += dx * inv3
+        acc[1] += dy * inv3
+        acc[2] += dz * inv3
+    return [a.cpu().numpy().astype(dtype) for a in acc]
 
 
 def pixel_seeds(nx, ny, z0=0.0, lo=LO, hi=HI):
@@ -133,3 +151,113 @@ def charges_c2(n=(256, 256, 128), seed=2, count=4, dtype=np.float32):
     bx, by, bz = sample_charges(ch, n, dtype=dtype)
     origin, spacing = grid_geometry(n)
     return dict(b=(bx, by, bz), origin=origin, spacing=spacing, n=n, charges=ch)
+
+
+C3_DIMS = ((64, 64, 64), (96, 96, 96), (128, 128, 128), (128, 128, 64), (192, 192, 96), (256, 256, 128))
+
+
+def batch_c3(count=64, first_seed=3000, dims=C3_DIMS, seeds_range=(1e4, 1e6), dtype=np.float32):
+    """Many-field batch: field k uses seed first_seed + k; 2..8 sub-surface
+    charges drawn as in point_charges; grid dims cycle through `dims`; seed
+    count log-uniform in seeds_range, uniform random points on z = 0.
+
+    Yields one dict per field (b, origin, spacing, n, charges, seeds)."""
+    for k in range(count):
+        s = first_seed + k
+        g = rng(s)
+        nch = int(g.integers(2, 9))
+        m = int(round(np.exp(g.uniform(np.log(seeds_range[0]), np.log(seeds_range[1])))))
+        ch = point_charges(s, nch)
+        n = tuple(dims[k % len(dims)])
+        origin, spacing = grid_geometry(n)
+        yield dict(b=sample_charges(ch, n, dtype=dtype), origin=origin, spacing=spacing, n=n, charges=ch,
+                   seeds=random_seeds(s + 100000, m, z=0.0))
+
+
+def flux_rope_field(n, ring_radius=0.3, depth=0.1, minor=0.08, current=0.5, turns=1.5, leg_charge=1.5,
+                    charges=None, quad=96, device=None, dtype=np.float32):
+    """Twisted flux rope over a potential background, sampled on the nodes.
+
+    Poloidal part: a circular line current of radius `ring_radius` in the x-z
+    plane, centre (0, 0, -depth), by Biot-Savart quadrature (`quad` points,
+    trapezoid rule) with the kernel softened over `minor`:
+    dB = I dl x r / (|r|^2 + minor^2)^(3/2), the curl of a smooth vector
+    potential, so divergence-free.  Toroidal part: B_phi(rho) e_phi with
+    B_phi = B0 (1 - rho^2 / minor^2) inside the tube (rho = distance to the
+    ring's core circle), e_phi the azimuthal direction about the ring's axis
+    (the y axis): axisymmetric, so divergence-free.  B0 gives about `turns`
+    turns of twist at rho = minor / 2 over the rope's length above z = 0.
+    Background: point charges (rows x, y, z, q) as in sample_charges; by
+    default +leg_charge and -leg_charge under the two legs plus four charges
+    drawn as in point_charges(4, 4).
+
+    Sums run in FP64 with torch (on `device` if given) and are cast at the end."""
+    import torch
+    dev = torch.device(device) if device is not None else torch.device("cpu")
+    f64 = dict(dtype=torch.float64, device=dev)
+    R, zc, a = ring_radius, -depth, minor
+    xleg = float(np.sqrt(R * R - zc * zc))
+    if charges is None:
+        legs = np.array([[xleg, 0.0, zc, leg_charge], [-xleg, 0.0, zc, -leg_charge]])
+        charges = np.vstack([legs, point_charges(4, 4)])
+    th = torch.arange(quad, **f64) * (2 * np.pi / quad)
+    px, pz = R * torch.cos(th), zc + R * torch.sin(th)                  # ring points
+    tx, tz = -R * torch.sin(th) * (2 * np.pi / quad), R * torch.cos(th) * (2 * np.pi / quad)   # dl
+
+    def ring_b(X, Y, Z):
+        bx = torch.zeros_like(X)
+        by = torch.zeros_like(X)
+        bz = torch.zeros_like(X)
+        for k in range(quad):
+            rx, rz = X - px[k], Z - pz[k]
+            w = current * (rx * rx + Y * Y + rz * rz + a * a) ** -1.5
+            # dl = (tx, 0, tz); dl x r = (0*rz - tz*Y, tz*rx - tx*rz, tx*Y - 0*rx)
+            bx -= w * tz[k] * Y
+            by += w * (tz[k] * rx - tx[k] * rz)
+            bz += w * tx[k] * Y
+        return bx, by, bz
+
+    def phi_dir(X, Z):
+        s = torch.sqrt(X * X + (Z - zc) ** 2)
+        return -(Z - zc) / s, X / s, s
+
+    # toroidal amplitude from the poloidal field at rho = a/2 below the apex
+    P = torch.tensor([0.0], **f64), torch.tensor([0.0], **f64), torch.tensor([zc + R - a / 2], **f64)
+    bp = float(torch.sqrt(sum(c * c for c in ring_b(*P)))[0])
+    arc = R * (np.pi - 2 * np.arcsin(-zc / R))
+    rho0 = a / 2
+    B0 = arc * bp / (2 * np.pi * rho0 * turns * (1 - (rho0 / a) ** 2))
+
+    xs, ys, zs = node_coords(n)
+    nx, ny, nz = n
+    out = [np.empty((nz, ny, nx), dtype) for _ in range(3)]
+    Y2, X2 = torch.meshgrid(torch.tensor(ys, **f64), torch.tensor(xs, **f64), indexing="ij")
+    zchunk = max(1, (1 << 22) // (nx * ny))
+    for z0 in range(0, nz, zchunk):
+        zz = torch.tensor(zs[z0:z0 + zchunk], **f64)
+        Z = zz[:, None, None].expand(-1, ny, nx)
+        X = X2[None].expand_as(Z)
+        Y = Y2[None].expand_as(Z)
+        bx, by, bz = ring_b(X, Y, Z)
+        ex, ez, s = phi_dir(X, Z)
+        rho2 = (s - R) ** 2 + Y * Y
+        bt = torch.where(rho2 < a * a, B0 * (1 - rho2 / (a * a)), torch.zeros_like(rho2))
+        bx = bx + bt * ex
+        bz = bz + bt * ez
+        for cx, cy, cz, q in charges:
+            dx, dy, dz = X - cx, Y - cy, Z - cz
+            r2 = dx * dx + dy * dy + dz * dz
+            inv3 = q * r2 ** -1.5
+            bx = bx + dx * inv3
+            by = by + dy * inv3
+            bz = bz + dz * inv3
+        for i, c in enumerate((bx, by, bz)):
+            out[i][z0:z0 + zz.numel()] = c.cpu().numpy().astype(dtype)
+    return out, dict(charges=charges, B0=B0, ring_radius=R, depth=depth, minor=a, current=current)
+
+
+def flux_rope_c4(n=(384, 384, 256), dtype=np.float32, device=None):
+    """Flux rope over a 6-charge background on a 384x384x256 grid (volume workload)."""
+    b, meta = flux_rope_field(n, dtype=dtype, device=device)
+    origin, spacing = grid_geometry(n)
+    return dict(b=b, origin=origin, spacing=spacing, n=n, **meta)

@@ -9,8 +9,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "qsq.h")).read()
+def _declared(header="qsq.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(qsq_[a-z0-9_]+)\s*\(", src)) - {"qsq_STATUS"})
 
@@ -28,6 +28,11 @@ def test_exports_every_declared_symbol(qsq):
         assert hasattr(qsq.lib, n), n
     from paper_1609_00724_amd import _abi
     assert sorted(_abi.EXPORTS) == names
+    cnn = _declared("qsq_cnn.h")
+    for n in cnn:
+        assert hasattr(qsq.lib, n), n
+    assert sorted(_abi.CNN_EXPORTS) == cnn
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == ["qsq.h", "qsq_cnn.h"]
 
 
 def test_version_and_strings(qsq):
@@ -45,6 +50,7 @@ def test_sizes(qsq):
     g.n[:] = (256, 256, 128)
     assert qsq.lib.qsq_field_bytes(C.byref(g), A.F32) == 256 * 256 * 128 * 16
     assert qsq.lib.qsq_field_bytes(C.byref(g), A.F64) == 256 * 256 * 128 * 32
+    assert qsq.lib.qsq_field_bytes(C.byref(g), A.BF16) == 256 * 256 * 128 * 8
     assert qsq.lib.qsq_trace_scratch_bytes(1000) >= 1000 * 2 * (11 * 8 + 8)
     d = A.MapDesc()
     d.base_level, d.refine_levels, d.out_level = 10, 2, 10
@@ -70,7 +76,7 @@ def test_invalid_arguments_rejected_before_launch(qsq):
     rc = L.qsq_field_init(C.byref(g), _fake(1), _fake(2), _fake(3), A.F32, A.F32, A.INTERP_PAPER,
                           _fake(4), 100, None, C.byref(out))
     assert rc == A.ERR_WORKSPACE_TOO_SMALL
-    rc = L.qsq_field_init(C.byref(g), _fake(1), _fake(2), _fake(3), A.F32, A.BF16, A.INTERP_PAPER,
+    rc = L.qsq_field_init(C.byref(g), _fake(1), _fake(2), _fake(3), A.F32, 7, A.INTERP_PAPER,
                           _fake(4), 1 << 30, None, C.byref(out))
     assert rc == A.ERR_UNSUPPORTED
     # a field descriptor that validates, used with bad trace options
@@ -113,3 +119,67 @@ def test_invalid_arguments_rejected_before_launch(qsq):
     n = C.c_int64()
     ms = C.c_double()
     assert L.qsq_profile_read(7, C.byref(n), C.byref(ms)) == A.ERR_INVALID_ARG
+
+
+def test_batch_arguments_rejected_before_launch(qsq):
+    from paper_1609_00724_amd import _abi as A
+    L = qsq.lib
+    g = A.Grid()
+    g.n[:] = (8, 8, 8)
+    g.spacing[:] = (0.1, 0.1, 0.1)
+    sets = (A.TraceSet * 3)()
+    for k, t in enumerate(sets):
+        t.field.grid = g
+        t.field.storage, t.field.mode, t.field.nodes = A.F32, A.INTERP_PAPER, _fake(1 + k)
+        t.field.bytes = L.qsq_field_bytes(C.byref(g), A.F32)
+        t.seeds = _fake(10 + k)
+        t.n = 100 * (k + 1)
+        t.out.status = _fake(20 + k)
+    o = A.TraceOpts()
+    o.rtol, o.atol = 1e-6, 1e-6
+    o.step_dtype = A.F32
+    need = L.qsq_trace_batch_scratch_bytes(3, 600)
+    assert need >= L.qsq_trace_scratch_bytes(600)
+    assert L.qsq_trace_batch(sets, 0, C.byref(o), None, _fake(30), need, None) == A.ERR_INVALID_ARG
+    assert L.qsq_trace_batch(None, 3, C.byref(o), None, _fake(30), need, None) == A.ERR_INVALID_ARG
+    assert L.qsq_trace_batch(sets, 3, C.byref(o), None, _fake(30), need - 1, None) == A.ERR_WORKSPACE_TOO_SMALL
+    assert L.qsq_trace_batch(sets, 3, C.byref(o), None, C.c_void_p(0x100000 + 8), need, None) == A.ERR_INVALID_ARG
+    sets[1].field.storage = A.F64
+    sets[1].field.bytes = L.qsq_field_bytes(C.byref(g), A.F64)
+    assert L.qsq_trace_batch(sets, 3, C.byref(o), None, _fake(30), need, None) == A.ERR_INVALID_ARG
+    assert b"set 1" in L.qsq_last_error()
+    sets[1].field.storage = A.F32
+    sets[2].out.status = None
+    assert L.qsq_trace_batch(sets, 3, C.byref(o), None, _fake(30), need, None) == A.ERR_INVALID_ARG
+    assert b"set 2" in L.qsq_last_error()
+    sets[2].field.grid.n[1] = 1
+    assert L.qsq_trace_batch(sets, 3, C.byref(o), None, _fake(30), need, None) == A.ERR_INVALID_ARG
+    assert b"set 2" in L.qsq_last_error() and b"n[1]" in L.qsq_last_error()
+    # a batch without seeds enqueues nothing and needs no scratch
+    for t in sets:
+        t.n = 0
+    sets[2].field.grid.n[1] = 8
+    assert L.qsq_trace_batch(sets, 3, C.byref(o), None, None, 0, None) == A.OK
+    sets[0].n = -1
+    assert L.qsq_trace_batch(sets, 3, C.byref(o), None, None, 0, None) == A.ERR_INVALID_ARG
+
+
+def test_cnn_arguments_rejected_before_launch(qsq):
+    from paper_1609_00724_amd import _abi as A
+    L = qsq.lib
+    assert A.CNN_PARAMS == 19970
+    assert L.qsq_cnn_prep_bytes() >= 2 * (1024 + 2 * 9216 + 4608) + 4 * 4 * 32
+    need = L.qsq_cnn_workspace_bytes(4, 64, 64)
+    assert need >= 4 * 64 * 64 * (3 * 64 + 8 + 4 + 2 * 64)
+    assert L.qsq_cnn_forward(_fake(1), _fake(2), 4, 64, 48, _fake(3), _fake(4), need, None) == A.ERR_INVALID_ARG
+    assert L.qsq_cnn_forward(_fake(1), _fake(2), 0, 64, 64, _fake(3), _fake(4), need, None) == A.ERR_INVALID_ARG
+    assert L.qsq_cnn_forward(_fake(1), _fake(2), 4, 64, 64, _fake(3), _fake(4), need - 1, None) == \
+        A.ERR_WORKSPACE_TOO_SMALL
+    assert L.qsq_cnn_forward(_fake(1), _fake(2), 1 << 20, 64, 64, _fake(3), _fake(4), 1 << 62, None) == \
+        A.ERR_COUNT_OVERFLOW
+    assert L.qsq_cnn_train_step(_fake(1), _fake(2), _fake(3), 0, 1e-3, _fake(4), _fake(5), _fake(6), 4, 64, 64, 0.1,
+                                _fake(7), None, None, _fake(8), need, None) == A.ERR_INVALID_ARG
+    assert L.qsq_cnn_layer_forward(4, _fake(1), _fake(2), 4, 64, 64, _fake(3), None) == A.ERR_INVALID_ARG
+    s = L.qsq_cnn_layer_scratch_bytes(4, 64, 64)
+    assert L.qsq_cnn_layer_backward(0, _fake(1), _fake(2), _fake(3), 4, 64, 64, _fake(4), _fake(5), _fake(6),
+                                    _fake(7), s, None) == A.ERR_INVALID_ARG     # layer 0 has no input gradient

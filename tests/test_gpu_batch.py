@@ -1,0 +1,140 @@
+"""Batched trace: many fields and seed sets of uneven size in one job (one
+persistent stepping launch), checked against one-field traces of the same
+sets and against the FP64 oracle; capture of the batched call in a HIP graph
+and replay.  Same per-seed computation as the one-field trace (QSL Squasher
+Sect. 3.1-3.5)."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import check_lines, gpu_field, line_ok, parity
+
+pytestmark = pytest.mark.gpu
+
+SMALL_DIMS = ((24, 24, 16), (32, 32, 32), (40, 32, 20), (20, 20, 20), (48, 40, 24))
+
+
+def _sets(count, dtype, empty=(3,)):
+    out = []
+    for k, f in enumerate(synth.batch_c3(count=count, first_seed=3000, dims=SMALL_DIMS,
+                                         seeds_range=(20, 1500), dtype=dtype)):
+        if k in empty:
+            f["seeds"] = np.zeros((0, 3))
+        out.append(f)
+    return out
+
+
+def _to_np(out):
+    r = {k: v.cpu().numpy() for k, v in out.items()}
+    for k in ("fp_fwd", "fp_bwd"):
+        if k in r:
+            r[k] = r[k].T.copy()
+    return r
+
+
+def _run_batch(sets, fields, **kw):
+    import torch
+
+    import paper_1609_00724_amd as q
+    dev = torch.device("cuda:0")
+    outs, work = q.trace_batch([(fg, torch.from_numpy(f["seeds"]).to(dev)) for fg, f in zip(fields, sets)],
+                               want_steps=True, want_work=True, **kw)
+    torch.cuda.synchronize()
+    return [_to_np(o) for o in outs], work.cpu().numpy()
+
+
+def _run_single(sets, fields, **kw):
+    import torch
+
+    import paper_1609_00724_amd as q
+    dev = torch.device("cuda:0")
+    res = []
+    for fg, f in zip(fields, sets):
+        if f["seeds"].shape[0] == 0:
+            res.append(None)
+            continue
+        o = q.trace(fg, torch.from_numpy(f["seeds"]).to(dev), want_steps=True, **kw)
+        torch.cuda.synchronize()
+        res.append(_to_np(o))
+    return res
+
+
+def test_batch_fp64_matches_single_and_oracle(oracle_mod):
+    sets = _sets(7, np.float64)
+    fields = [gpu_field(f["b"], f["origin"], f["spacing"], storage="f64") for f in sets]
+    kw = dict(rtol=1e-8, atol=1e-8, step_dtype="f64")      # h_init, h_max: each grid's own defaults
+    bat, work = _run_batch(sets, fields, **kw)
+    one = _run_single(sets, fields, **kw)
+    total_steps = 0
+    for k, (f, b, s) in enumerate(zip(sets, bat, one)):
+        n = f["seeds"].shape[0]
+        assert b["status"].shape == (n,)
+        if n == 0:
+            continue
+        np.testing.assert_array_equal(b["status"], s["status"], err_msg=f"set {k}")
+        np.testing.assert_array_equal(b["steps"], s["steps"], err_msg=f"set {k}")
+        for key in ("fp_fwd", "fp_bwd", "fll", "q_perp", "q_det", "q_fp"):
+            np.testing.assert_allclose(b[key], s[key], rtol=1e-12, atol=1e-14, equal_nan=True,
+                                       err_msg=f"set {k} {key}")
+        total_steps += int(b["steps"].sum())
+        h = min(f["spacing"])
+        fo = oracle_mod.Field.grid(*f["b"], f["origin"], f["spacing"])
+        o = oracle_mod.trace(fo, f["seeds"], rtol=1e-8, atol=1e-8, h_init=0.1 * h, h_max=h)
+        check_lines(parity(b, o), o, strict=True, max_mismatch_frac=0.0)
+    # the batch's work counters sum the step attempts of every half-line
+    assert work[0] == total_steps
+
+
+def test_batch_fp32_matches_single():
+    sets = _sets(6, np.float32, empty=(0,))
+    fields = [gpu_field(f["b"], f["origin"], f["spacing"], storage="f32") for f in sets]
+    kw = dict(rtol=1e-5, atol=1e-5, step_dtype="f32")
+    bat, _ = _run_batch(sets, fields, **kw)
+    one = _run_single(sets, fields, **kw)
+    for k, (f, b, s) in enumerate(zip(sets, bat, one)):
+        if f["seeds"].shape[0] == 0:
+            assert b["status"].size == 0
+            continue
+        p = parity(b, s)
+        ok = line_ok(p)[p["gate"]]
+        print(f"set {k}: n={b['status'].size} status mismatch {p['status_mismatch']} within gates {ok.mean():.4f}")
+        assert p["status_mismatch"] <= 0.003 * b["status"].size + 1
+        assert ok.mean() >= 0.998
+
+
+def test_batch_graph_replay():
+    import torch
+
+    import paper_1609_00724_amd as q
+    from paper_1609_00724_amd.api import TraceBatchPlan, make_opts
+    dev = torch.device("cuda:0")
+    sets = _sets(5, np.float32, empty=(2,))
+    fields = [gpu_field(f["b"], f["origin"], f["spacing"], storage="f32") for f in sets]
+    plan = TraceBatchPlan([(fg, torch.from_numpy(f["seeds"]).to(dev)) for fg, f in zip(fields, sets)],
+                          make_opts(1e-4, 1e-4, step_dtype="f32"), want_steps=True, want_work=True)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.run()                                   # eager run (also warms up)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    ref = [{k: v.clone() for k, v in o.items()} for o in plan.outs]
+    work_ref = plan.work.clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.run()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        # eager work between replays: poison every output and the counters
+        for o in plan.outs:
+            for v in o.values():
+                v.fill_(-7)
+        plan.work.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for k, (o, r) in enumerate(zip(plan.outs, ref)):
+            for key in r:
+                assert torch.equal(o[key], r[key]), f"replay {rep} set {k} {key}"
+        assert torch.equal(plan.work, work_ref), f"replay {rep} work"
+    assert q.lib.qsq_abi_version() == 1

@@ -66,11 +66,11 @@ def c2(oracle_mod):
     return dict(w=w, fg=fg, fo=fo, h=min(w["spacing"]))
 
 
-def _run_map(c2, m, r, thr, out_level, capacity, step_dtype="f32"):
+def _run_map(c2, m, r, thr, out_level, capacity, step_dtype="f32", batch=0):
     import paper_1609_00724_amd as q
     from paper_1609_00724_amd.api import MapSpec
     torch, dev = torch_dev()
-    spec = MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, r, out_level, thr)
+    spec = MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, r, out_level, thr, batch)
     res = q.qmap(c2["fg"], spec, capacity, rtol=TOL, atol=TOL, h_init=0.1 * c2["h"], h_max=c2["h"],
                  step_dtype=step_dtype)
     torch.cuda.synchronize()
@@ -148,6 +148,22 @@ def test_small_map_vs_oracle(oracle_mod, c2, step_dtype):
                        rtol=1e-5, atol=1e-5)
 
 
+@pytest.mark.parametrize("r", [2, 3])
+def test_refine_batches_give_identical_maps(c2, r):
+    """Deciding several refinement levels per device round (tracing every key
+    those levels could insert, then applying the rule) keeps exactly the
+    samples of the pass-by-pass rule: every batch size gives the same arrays."""
+    m, thr = 6, 0.02
+    ref = _run_map(c2, m, r, thr, m + r, 4 ** (m + r), batch=1)
+    assert ref["count"] > 4 ** m
+    for b in (2, 3, 4, 5):
+        res = _run_map(c2, m, r, thr, m + r, 4 ** (m + r), batch=b)
+        assert res["count"] == ref["count"], b
+        for k in ("keys", "fll", "q_perp", "status"):
+            assert np.array_equal(res[k], ref[k], equal_nan=True), (b, k)
+        assert np.array_equal(res["q_grid"], ref["q_grid"], equal_nan=True)
+
+
 def test_capacity_overflow_is_flagged(c2):
     m, r = 5, 2
     res = _run_map(c2, m, r, 0.0, m, 4 ** m + 10)
@@ -178,3 +194,102 @@ def test_full_photospheric_map_sampled(oracle_mod, c2, step_dtype):
     img[iy, ix] = res["fll"][base]
     assert np.allclose(res["fledge"], oracle_mod.sobel_magnitude(img.astype(np.float32).astype(np.float64)),
                        rtol=1e-5, atol=1e-5)
+
+
+# ---------------------------------------------------------------------------
+# volumes (3D Hilbert refinement, 3D converter and FLEDGE)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("b", [1, 2, 4, 6])
+def test_hilbert3_vs_oracle_all(oracle_mod, b):
+    import paper_1609_00724_amd as q
+    torch, dev = torch_dev()
+    d = np.arange(8 ** b, dtype=np.int64)
+    x, y, z = q.hilbert3_d2xyz(b, torch.from_numpy(d).to(dev))
+    xo, yo, zo = oracle_mod.hilbert3_d2xyz(b, d)
+    assert np.array_equal(x.cpu().numpy(), xo) and np.array_equal(y.cpu().numpy(), yo)
+    assert np.array_equal(z.cpu().numpy(), zo)
+    assert np.array_equal(q.hilbert3_xyz2d(b, x, y, z).cpu().numpy(), d)
+
+
+@pytest.mark.parametrize("b", [10, 21])
+def test_hilbert3_vs_oracle_sampled(oracle_mod, b):
+    import paper_1609_00724_amd as q
+    torch, dev = torch_dev()
+    d = synth.rng(b).integers(0, 8 ** b, size=5000, dtype=np.int64)
+    x, y, z = q.hilbert3_d2xyz(b, torch.from_numpy(d).to(dev))
+    xo, yo, zo = oracle_mod.hilbert3_d2xyz(b, d)
+    for g_, o_ in ((x, xo), (y, yo), (z, zo)):
+        assert np.array_equal(g_.cpu().numpy().astype(np.int64) & 0xFFFFFFFF, o_)
+
+
+BOX = (-1.0, 1.0, -1.0, 1.0, 0.0, 1.0)
+
+
+def _run_vmap(c2, m, r, thr, out_level, capacity, step_dtype="f32", batch=0):
+    import paper_1609_00724_amd as q
+    torch, dev = torch_dev()
+    spec = q.VolumeSpec(*BOX, m, r, out_level, thr, batch)
+    res = q.qmap(c2["fg"], spec, capacity, rtol=TOL, atol=TOL, h_init=0.1 * c2["h"], h_max=c2["h"],
+                 step_dtype=step_dtype)
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}
+
+
+def _vpositions(oracle_mod, m, r, keys):
+    box = oracle_mod.VolumeBox(*BOX)
+    blk = 8 ** r
+    base = keys % blk == blk // 2
+    pos = np.empty((keys.size, 3))
+    pos[base] = box.centres(m, *oracle_mod.hilbert3_d2xyz(m, keys[base] // blk))
+    if (~base).any():
+        pos[~base] = oracle_mod.key_positions(box, m, r, keys[~base])
+    return pos, base
+
+
+@pytest.mark.parametrize("step_dtype", ["f32", "f64"])
+def test_volume_map_vs_oracle(oracle_mod, c2, step_dtype):
+    m, r, thr = 4, 2, 0.02
+    res = _run_vmap(c2, m, r, thr, m + 1, 8 ** (m + 1) * 4, step_dtype)   # the oracle's refinement keeps ~101K
+    n = res["count"]
+    assert res["overflow"] == 0 and n > 8 ** m
+    _check_complete(res, thr)
+    pos, base = _vpositions(oracle_mod, m, r, res["keys"])
+    o = _oracle_trace(oracle_mod, c2, pos)
+    g = dict(status=res["status"], q_perp=res["q_perp"], fll=res["fll"],
+             fp_fwd=np.zeros((n, 3)), fp_bwd=np.zeros((n, 3)))
+    o2 = dict(o, fp_fwd=np.zeros((n, 3)), fp_bwd=np.zeros((n, 3)))
+    check_lines(parity(g, o2), o, strict=step_dtype == "f64")
+    # the oracle's own volume refinement reaches the same sample set
+    box = oracle_mod.VolumeBox(*BOX)
+
+    def fn(p):
+        t = _oracle_trace(oracle_mod, c2, p)
+        return {"fll": t["fll"], "q": t["q_perp"]}
+
+    ok, _, passes = oracle_mod.refine_slice(box, m, r, thr, fn)
+    assert passes <= 3 * r
+    common = np.intersect1d(ok, res["keys"]).size
+    union = np.union1d(ok, res["keys"]).size
+    assert common / union > 0.99, (common, union)
+    # converter at level m + 1 on sampled cells, and the 3D FLEDGE of the base lengths
+    cells = synth.rng(5).choice(8 ** (m + 1), size=300, replace=False)
+    want = oracle_mod.convert_to_grid(res["keys"], res["q_perp"], m, r, m + 1, log_interp=True,
+                                      cells=cells, dims=3)
+    cx, cy, cz = oracle_mod.hilbert3_d2xyz(m + 1, cells)
+    assert np.allclose(res["q_grid"][cz, cy, cx], want, rtol=2e-6, equal_nan=True)
+    bx, by, bz = oracle_mod.hilbert3_d2xyz(m, res["keys"][base] // 64)
+    img = np.zeros((1 << m,) * 3)
+    img[bz, by, bx] = res["fll"][base]
+    assert np.allclose(res["fledge"], oracle_mod.sobel_magnitude(img.astype(np.float32).astype(np.float64)),
+                       rtol=1e-5, atol=1e-5)
+
+
+def test_volume_refine_batches_identical(c2):
+    m, r, thr = 3, 2, 0.02
+    ref = _run_vmap(c2, m, r, thr, m + r, 8 ** (m + r), batch=1)
+    assert ref["count"] > 8 ** m
+    for b in (3, 4, 5):
+        res = _run_vmap(c2, m, r, thr, m + r, 8 ** (m + r), batch=b)
+        for k in ("keys", "fll", "q_perp", "status"):
+            assert np.array_equal(res[k], ref[k], equal_nan=True), (b, k)

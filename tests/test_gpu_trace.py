@@ -191,3 +191,71 @@ def test_step_counts_match_oracle(oracle_mod, c1):
     moving = o["lam_fwd"] > 0
     close = np.abs(att_g[moving] - att_o[moving]) <= 2
     assert close.mean() > 0.95, (att_g[moving][:10], att_o[moving][:10])
+
+
+def test_bf16_storage(oracle_mod, small_charges):
+    """BF16 node records: the tracer matches the oracle on the same BF16-rounded
+    field (FP32 stepping gates), and the storage error itself -- BF16 field
+    against the FP64 field -- is measured and bounded."""
+    c = small_charges
+    seeds = _mixed_seeds(600, 17)
+    h = min(c["spacing"])
+    kw = dict(rtol=1e-4, atol=1e-4, h_init=0.1 * h, h_max=h)
+    fg = gpu_field(c["b"], c["origin"], c["spacing"], storage="bf16")
+    g = gpu_trace(fg, seeds, step_dtype="f32", **kw)
+    fo = _oracle_grid(oracle_mod, c["b"], c["origin"], c["spacing"], "paper", "bf16")
+    o = oracle_mod.trace(fo, seeds, **kw)
+    ref = oracle_mod.trace(fo, seeds, **dict(kw, rtol=1e-10, atol=1e-10))
+    check_fp32(parity(g, o), g, o, ref)
+    # storage error: BF16 field vs the unrounded field
+    f64 = oracle_mod.trace(_oracle_grid(oracle_mod, c["b"], c["origin"], c["spacing"], "paper", "f64"),
+                           seeds, **kw)
+    p = parity(g, f64)
+    m = p["gate"]
+    print(f"BF16 storage error: footpoints median {np.median(p['fp'][m]):.2e} p90 {np.percentile(p['fp'][m], 90):.2e}, "
+          f"rel log10 Q median {np.nanmedian(p['lq'][m]):.2e} p90 {np.nanpercentile(p['lq'][m], 90):.2e}")
+    assert np.median(p["fp"][m]) < 1e-2 and np.nanmedian(p["lq"][m]) < 1e-2
+
+
+# ---------------------------------------------------------------------------
+# twisted flux rope over a 6-charge background (small grid of the volume workload)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def rope():
+    n = (72, 72, 48)
+    b, meta = synth.flux_rope_field(n, dtype=np.float32)
+    origin, spacing = synth.grid_geometry(n)
+    return dict(b=b, origin=origin, spacing=spacing, n=n, **meta)
+
+
+def test_flux_rope_fp64_parity(oracle_mod, rope):
+    """FP64 storage and stepping at tolerance 1e-8 through a twisted rope: every
+    gated line meets the per-line gates."""
+    seeds = synth.random_seeds(41, 700)
+    h = min(rope["spacing"])
+    kw = dict(rtol=1e-8, atol=1e-8, h_init=0.1 * h, h_max=h)
+    fg = gpu_field(rope["b"], rope["origin"], rope["spacing"], storage="f64")
+    g = gpu_trace(fg, seeds, step_dtype="f64", **kw)
+    fo = _oracle_grid(oracle_mod, rope["b"], rope["origin"], rope["spacing"], "paper", "f64")
+    o = oracle_mod.trace(fo, seeds, **kw)
+    p = parity(g, o)
+    check_lines(p, o, strict=True)
+    # the rope twists lines: some closed lines (both ends on z = 0) are long
+    closed = (o["status"] & 0xFFFF) == (4 | (4 << 8))
+    assert closed.sum() > 100 and np.percentile(o["fll"][closed], 90) > 0.5
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_flux_rope_fp32_stepping(oracle_mod, rope, storage):
+    """FP32 stepping on FP32 and BF16 node records of the rope field against the
+    oracle on the same rounded field (statistical FP32 gates)."""
+    seeds = synth.random_seeds(43, 700)
+    h = min(rope["spacing"])
+    kw = dict(rtol=1e-4, atol=1e-4, h_init=0.1 * h, h_max=h)
+    fg = gpu_field(rope["b"], rope["origin"], rope["spacing"], storage=storage)
+    g = gpu_trace(fg, seeds, step_dtype="f32", **kw)
+    fo = _oracle_grid(oracle_mod, rope["b"], rope["origin"], rope["spacing"], "paper", storage)
+    o = oracle_mod.trace(fo, seeds, **kw)
+    ref = oracle_mod.trace(fo, seeds, **dict(kw, rtol=1e-10, atol=1e-10))
+    check_fp32(parity(g, o), g, o, ref)

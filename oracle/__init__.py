@@ -318,7 +318,7 @@ def key_positions(region, m: int, r: int, keys):
     return region.centres(m + r, *region.cells(m + r, keys))
 
 
-def refine_slice(region, m: int, r: int, thr: float, sample_fn, max_passes=64):
+def refine_slice(region, m: int, r: int, thr: float, sample_fn, max_passes=64, extra_keys=None):
     """FLL-jump refinement along the Hilbert curve (Sect. 3.6), for a slice or
     a volume.
 
@@ -326,8 +326,18 @@ def refine_slice(region, m: int, r: int, thr: float, sample_fn, max_passes=64):
     Returns (keys, values dict, passes): samples in curve order.  A new sample
     goes halfway (in key) between curve-successive samples whose FLL differs
     by more than ``thr`` while they are at least two finest cells apart.
+    ``extra_keys`` (finest-level keys, none of them a base key) are sampled
+    with the base lattice before the first pass: the rule then starts from the
+    merged, curve-ordered sample set.
     """
     keys, pts = base_samples(region, m, r)
+    if extra_keys is not None and len(extra_keys):
+        ek = np.unique(np.asarray(extra_keys, dtype=np.int64))
+        assert np.intersect1d(ek, keys).size == 0, "extra keys must not repeat base keys"
+        keys = np.concatenate([keys, ek])
+        pts = np.concatenate([pts, key_positions(region, m, r, ek)])
+        order = np.argsort(keys, kind="stable")
+        keys, pts = keys[order], pts[order]
     vals = sample_fn(pts)
     vals = {k: np.asarray(v) for k, v in vals.items()}
     passes = 0

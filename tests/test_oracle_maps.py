@@ -138,6 +138,34 @@ def test_refine_disc_clusters_on_the_edge(oracle_mod):
     assert fine > 0
 
 
+def test_refine_from_proposals(oracle_mod):
+    """Refinement from a merged sample set: (a) proposing the keys the plain
+    rule adds reproduces the plain result with no pass; (b) proposing every
+    finest cell of every base pixel leaves no gap >= 2 and no pass; (c) a
+    partial proposal ends with every proposal kept and no sample the plain
+    rule would have been missing near the edge (each jump still ends one
+    finest cell apart)."""
+    O = oracle_mod
+    plane = O.SlicePlane(*PLANE_ARGS)
+    m, r, R = 5, 2, 0.5
+    plain, _, _ = O.refine_slice(plane, m, r, 0.5, _disc(R))
+    base = np.arange(4 ** m) * 16 + 8
+    extra = np.setdiff1d(plain, base)
+    k2, _, p2 = O.refine_slice(plane, m, r, 0.5, _disc(R), extra_keys=extra)
+    assert p2 == 0 and np.array_equal(k2, plain)
+    allk = np.setdiff1d(np.arange(4 ** (m + r)), base)
+    k3, _, p3 = O.refine_slice(plane, m, r, 0.5, _disc(R), extra_keys=allk)
+    assert p3 == 0 and np.array_equal(k3, np.arange(4 ** (m + r)))
+    g = np.random.Generator(np.random.PCG64(3))
+    picked = g.choice(4 ** m, size=100, replace=False)
+    prop = np.setdiff1d((picked[:, None] * 16 + np.arange(16)[None, :]).ravel(), base)
+    k4, v4, p4 = O.refine_slice(plane, m, r, 0.5, _disc(R), extra_keys=prop)
+    assert np.all(np.isin(prop, k4)) and np.all(np.diff(k4) > 0) and p4 <= 4
+    fl = v4["fll"]
+    jumps = np.nonzero(np.abs(np.diff(fl)) > 0.5)[0]
+    assert np.all(k4[jumps + 1] - k4[jumps] == 1)
+
+
 def test_convert_base_level_is_the_base_map(oracle_mod):
     O = oracle_mod
     plane = O.SlicePlane(*PLANE_ARGS)

@@ -68,6 +68,9 @@ def parse():
                     help="batch workload: fraction of each field's seeds the oracle traces")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write profiles/k_trace_traffic.json from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE csv "
+                         "outputs of this benchmark and of --calibrate-copy")
     return ap.parse_args()
 
 
@@ -79,6 +82,8 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         return calibrate_copy()
+    if args.summarize_pmc:
+        return summarize_pmc(*args.summarize_pmc)
     if args.workload == "batch":
         return bench_batch(args)
     if args.workload == "volume":
@@ -174,7 +179,8 @@ def main():
             "peak": VALU_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / VALU_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "launches": n_step,
             "avg_launch_ms": ms_step / max(n_step, 1),
             "algorithmic_flops_per_step": flops / args.steps,
@@ -192,6 +198,66 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args, w, h)
     print(json.dumps(out), flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trace_traffic.json")
+PMC_MAPS = 2             # maps timed in the counter runs (bench.py --steps 2)
+LAUNCHES_PER_MAP = 5     # stepping launches per map: base lattice + 2r refinement rounds (r = 2)
+KERNEL_SOURCES = ("paper_1609_00724_amd/csrc/trace.hip", "paper_1609_00724_amd/csrc/qsq_internal.h")
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _pmc_rows(d, counter):
+    import csv
+    import glob
+    fs = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not fs:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    return [(r["Kernel_Name"], float(r["Counter_Value"])) for r in csv.DictReader(open(fs[0]))
+            if r["Counter_Name"] == counter]
+
+
+def summarize_pmc(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
+    """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by what they read for a
+    plain 1 GiB copy and store the stepping kernel's bytes per launch, keyed by
+    the hash of its sources (the benchmark reports null once they change)."""
+    gib = float(1 << 30)
+    cf = [v for k, v in _pmc_rows(copy_fetch_dir, "FETCH_SIZE") if "copyBuffer" in k]
+    cw = [v for k, v in _pmc_rows(copy_write_dir, "WRITE_SIZE") if "copyBuffer" in k]
+    fscale = gib / (sum(cf) / len(cf) * 1024.0)
+    wscale = gib / (sum(cw) / len(cw) * 1024.0)
+    # the launches of the last PMC_MAPS maps: the timed phase of a
+    # `--steps PMC_MAPS` run (after the launch-shape tuning and warm-up maps)
+    f = [v for k, v in _pmc_rows(fetch_dir, "FETCH_SIZE") if "k_trace" in k][-PMC_MAPS * LAUNCHES_PER_MAP:]
+    w = [v for k, v in _pmc_rows(write_dir, "WRITE_SIZE") if "k_trace" in k][-PMC_MAPS * LAUNCHES_PER_MAP:]
+    out = {"kernel_sources_sha256": kernel_hash(), "launches": len(f),
+           "fetch_bytes_per_launch": sum(f) / len(f) * 1024.0 * fscale,
+           "write_bytes_per_launch": sum(w) / len(w) * 1024.0 * wscale,
+           "fetch_scale": fscale, "write_scale": wscale,
+           "copy_fetch_kib": sum(cf) / len(cf), "copy_write_kib": sum(cw) / len(cw)}
+    out["bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+def measured_traffic():
+    """HBM bytes per stepping-kernel launch from the committed counter summary,
+    or None if the kernel's sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    return t["bytes_per_launch"] if t.get("kernel_sources_sha256") == kernel_hash() else None
 
 
 def calibrate_copy():
@@ -584,9 +650,12 @@ def bench_learned(args):
 
     # judge on held-out maps
     tp = fn = fp = 0
-    miss_cnn = miss_plain = qsl_total = 0
+    miss_cnn = miss_plain = miss_learned = qsl_total = 0
+    curve_xy = [v.long() for v in q.hilbert2_d2xy(m, torch.arange(4 ** m, device=dev))]
+    lplan = QMapPlan(MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, r, m + r, thr), 4 ** (m + r), dev)
     prop_pixels = plain_pixels = 0
     t_learned = t_plain = 0.0
+    t_parts = [0.0, 0.0, 0.0]
     lines_learned = lines_plain = 0
     side = 1 << m
     for d in test:
@@ -608,24 +677,20 @@ def bench_learned(args):
         qsl_total += int(qsl.sum())
         miss_cnn += int((qsl & ~up(pred)).sum())
         miss_plain += int((qsl & ~up(plain)).sum())
-        # cost: the learned path traces the 4^r fine cells of every proposed pixel
-        ys, xs = torch.nonzero(pred, as_tuple=True)
-        sub = torch.arange(1 << r, device=dev, dtype=torch.float64)
-        fy = (ys[:, None, None] * (1 << r) + sub[None, :, None]).expand(-1, 1 << r, 1 << r)
-        fx = (xs[:, None, None] * (1 << r) + sub[None, None, :]).expand(-1, 1 << r, 1 << r)
-        cell = 2.0 / (side << r)
-        seeds = torch.stack([-1.0 + (fx.reshape(-1) + 0.5) * cell, -1.0 + (fy.reshape(-1) + 0.5) * cell,
-                             torch.full((fx.numel(),), d["z0"], dtype=torch.float64, device=dev)], 1)
+        # learned path: coarse map, network, then the map with the proposals
+        # merged first and the FLL-jump rule as fallback
+        cq = curve_xy
+        prop_curve = pred[cq[1], cq[0]].to(torch.uint8).contiguous()
+        lplan.d.z0 = d["z0"]
+        lplan.d.propose = prop_curve.data_ptr()
         c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        c0.record()
         coarse.d.z0 = d["z0"]
+        c0.record()
         coarse.run(d["field"], opts)
         c1.record()
-        torch.cuda.synchronize()
         f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         f0.record()
-        if seeds.shape[0]:
-            q.trace(d["field"], seeds, rtol=args.tol, atol=args.tol, h_init=0.1 * h, h_max=h, step_dtype="f32")
+        lplan.run(d["field"], opts)
         f1.record()
         p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         fine.d.z0 = d["z0"]
@@ -633,10 +698,17 @@ def bench_learned(args):
         fine.run(d["field"], opts)
         p1.record()
         torch.cuda.synchronize()
+        lres = lplan.result()
+        qsl_l = torch.nan_to_num(lres["q_grid"], nan=0.0) > 1e3
+        miss_learned += int((qsl & ~qsl_l).sum())
         t_learned += c0.elapsed_time(c1) + s0.elapsed_time(s1) + f0.elapsed_time(f1)
+        t_parts[0] += c0.elapsed_time(c1)
+        t_parts[1] += s0.elapsed_time(s1)
+        t_parts[2] += f0.elapsed_time(f1)
         t_plain += p0.elapsed_time(p1)
-        lines_learned += side * side + seeds.shape[0]
-        lines_plain += d["lines_plain"]
+        lines_learned += side * side + lres["count"]
+        lines_plain += fine.result()["count"]
+        del prop_curve
     out = {
         "metric": "learned refinement proposer: training and judged proposals",
         "value": bs * flop_fwd * 3 / (ms_step / 1e3) / 1e12,
@@ -662,10 +734,16 @@ def bench_learned(args):
             "plain_pixel_fraction": plain_pixels / (len(test) * side * side),
             "missed_qsl_fraction_cnn": miss_cnn / max(qsl_total, 1),
             "missed_qsl_fraction_plain_rule": miss_plain / max(qsl_total, 1),
+            "missed_qsl_fraction_proposals_plus_fallback_rule": miss_learned / max(qsl_total, 1),
             "qsl_fine_pixels": qsl_total,
         },
         "pipeline": {"learned_ms": t_learned, "plain_ms": t_plain, "learned_lines": lines_learned,
-                     "plain_lines": lines_plain},
+                     "learned_parts_ms": {"coarse_map": t_parts[0], "network": t_parts[1],
+                                          "map_with_proposals": t_parts[2]},
+                     "plain_lines": lines_plain,
+                     "note": ("learned = coarse map + network + map with the proposals merged first and the "
+                              "FLL-jump rule as fallback (that map traces its base lattice again); plain = the "
+                              "rule alone; QSL pixels (Q > 1e3 at the finest level of the plain map) missed")},
     }
     print(json.dumps(out), flush=True)
 

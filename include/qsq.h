@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define QSQ_ABI_VERSION 1
+#define QSQ_ABI_VERSION 2
 
 /* return codes */
 #define QSQ_OK 0
@@ -275,6 +275,11 @@ typedef struct qsq_map_desc {
     int32_t refine_batch;  /* refinement levels decided per device round, 1..5 (see
                               qsq_qmap); <= 0: min(2r, 4) */
     double threshold;      /* FLL jump that triggers a new sample (length units) */
+    const uint8_t *propose; /* NULL, or device bytes, one per base pixel in level-m
+                              curve order: a nonzero byte adds every finest cell
+                              of that pixel as a sample before the FLL-jump rule
+                              runs (proposals of a learned or external model);
+                              the rule then refines what is left (fallback) */
 } qsq_map_desc;
 
 /* Results of qsq_qmap (device memory).  Samples are kept in curve order. */
@@ -308,8 +313,12 @@ uint64_t qsq_qmap_scratch_bytes(const qsq_map_desc *d, int64_t capacity);
  * that fires, all 2^b - 1 keys the next b passes could insert into it and then
  * applying the rule to the traced values (fewer, larger launches; the keys
  * the rule rejects are traced but not kept).  All rounds run on the device
- * without host synchronisation.  Samples beyond `capacity`, or speculative
- * keys beyond the trace slots (`capacity`), are dropped and set *overflow.
+ * without host synchronisation.  With `propose`, the finest cells of the
+ * proposed pixels are traced and merged in key order after the base lattice;
+ * the rule then runs one pass per round on the (now irregular) gaps, the new
+ * key of a firing gap always being floor((k1+k2)/2).  Samples beyond
+ * `capacity`, or proposed or speculative keys beyond the trace slots
+ * (`capacity`), are dropped and set *overflow.
  * Errors: INVALID_ARG, UNSUPPORTED, WORKSPACE_TOO_SMALL, HIP.
  */
 int qsq_qmap(const qsq_field *f, const qsq_map_desc *d, const qsq_trace_opts *opts,
@@ -324,6 +333,7 @@ typedef struct qsq_volume_desc {
     int32_t out_level;     /* level of the output grids, m <= out_level <= m + r */
     int32_t refine_batch;  /* as in qsq_map_desc */
     double threshold;      /* FLL jump that triggers a new sample (length units) */
+    const uint8_t *propose; /* as in qsq_map_desc, one byte per base cell (8^m) */
 } qsq_volume_desc;
 
 /* Scratch bytes qsq_vmap needs for a map with `capacity` samples. */

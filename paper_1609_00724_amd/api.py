@@ -4,6 +4,7 @@ from __future__ import annotations
 
 import ctypes as C
 from dataclasses import dataclass
+from typing import Optional
 
 import torch
 
@@ -236,6 +237,7 @@ class MapSpec:
     out_level: int
     threshold: float
     refine_batch: int = 0   # refinement levels per device round; 0: all in one round
+    propose: Optional[torch.Tensor] = None   # uint8 per base pixel in curve order (device)
 
     def desc(self) -> A.MapDesc:
         d = A.MapDesc()
@@ -243,6 +245,7 @@ class MapSpec:
         d.base_level, d.refine_levels, d.out_level = self.base_level, self.refine_levels, self.out_level
         d.refine_batch = self.refine_batch
         d.threshold = self.threshold
+        d.propose = _proposal_ptr(self.propose, 4 ** self.base_level)
         return d
 
 
@@ -259,6 +262,7 @@ class VolumeSpec:
     out_level: int
     threshold: float
     refine_batch: int = 0
+    propose: Optional[torch.Tensor] = None   # uint8 per base cell in curve order (device)
 
     def desc(self) -> A.VolumeDesc:
         d = A.VolumeDesc()
@@ -266,7 +270,17 @@ class VolumeSpec:
         d.base_level, d.refine_levels, d.out_level = self.base_level, self.refine_levels, self.out_level
         d.refine_batch = self.refine_batch
         d.threshold = self.threshold
+        d.propose = _proposal_ptr(self.propose, 8 ** self.base_level)
         return d
+
+
+def _proposal_ptr(t, n):
+    if t is None:
+        return None
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.uint8 and t.is_contiguous()
+            and t.numel() == n):
+        raise ValueError(f"propose must be a contiguous uint8 device tensor of {n} entries (curve order)")
+    return t.data_ptr()
 
 
 class QMapPlan:

@@ -477,7 +477,9 @@ __global__ void k_spec_seeds(Region rg, const Round *rdp, Samples a, const int64
         const int64_t base = (int64_t)fpos[i] * rd.S;
         const uint64_t k0 = a.keys[i];
         for (int j = 1; j <= rd.S; ++j) {
-            const uint64_t k = k0 + (uint64_t)j * rd.unit;
+            // one pass: the midpoint of the gap, which is any size once proposals
+            // were merged (k0 + unit on the regular lattice)
+            const uint64_t k = rd.D == 1 ? k0 + ((a.keys[i + 1] - k0) >> 1) : k0 + (uint64_t)j * rd.unit;
             uint32_t c[3];
             cell_of_key<DIM>(rg.L, k, c);
             const int64_t p = base + j - 1;
@@ -652,7 +654,8 @@ static uint64_t al(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
 constexpr int kMaxRounds = 64;
 constexpr int kRoundWords = 128;
 constexpr int kRemWord = kRoundWords + 4 * kMaxRounds;
-constexpr int kCountWords = kRemWord + 8;
+constexpr int kPropWords = kRemWord + 8;
+constexpr int kCountWords = kPropWords + 8;
 
 struct QmapLayout {
     uint64_t trace, seeds, bkeys, bfll, bq, bst, nkeys, nfll, nq, nst, flag, fpos, kcnt, koff, kmask, bsum, counts,
@@ -720,12 +723,96 @@ void launch_scan_i32(const int32_t *v, const int64_t *n_dev, int64_t n_max, int6
 
 __global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
 
+// ---------------------------------------------------------------------------
+// proposals: every finest cell of a proposed base cell becomes a sample
+// ---------------------------------------------------------------------------
+__global__ void k_prop_flags(const uint8_t *propose, int64_t nb, int32_t *flag)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (int64_t)gridDim.x * blockDim.x)
+        flag[i] = propose[i] ? 1 : 0;
+}
+
+// proposed cells whose B^r - 1 new keys fit the trace slots
+__global__ void k_prop_setup(const int64_t *n_prop, int64_t per, int64_t slots, int64_t *n_eff, int64_t *n_seeds,
+                             int32_t *overflow)
+{
+    int64_t ne = *n_prop;
+    if (ne * per > slots) {
+        ne = slots / per;
+        *overflow = 1;
+    }
+    *n_eff = ne;
+    *n_seeds = ne * per;
+}
+
+// keys q B^r + j, j != B^r / 2 (the base sample), in key order
+template <int DIM>
+__global__ void k_prop_seeds(Region rg, int64_t nb, const int32_t *flag, const int32_t *fpos, const int64_t *n_eff,
+                             int64_t stride, double *seeds, uint64_t *nkeys)
+{
+    const int64_t ne = *n_eff;
+    const uint64_t B = (uint64_t)1 << (DIM * rg.r), per = B - 1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (int64_t)gridDim.x * blockDim.x) {
+        if (!flag[i] || fpos[i] >= ne) continue;
+        const int64_t base = (int64_t)fpos[i] * (int64_t)per;
+        for (uint64_t j = 0, p = 0; j < B; ++j) {
+            if (j == B / 2) continue;
+            const uint64_t k = (uint64_t)i * B + j;
+            uint32_t c[3];
+            cell_of_key<DIM>(rg.L, k, c);
+            nkeys[base + p] = k;
+            for (int ax = 0; ax < 3; ++ax)
+                seeds[ax * stride + base + p] = (ax < DIM) ? rg.lo[ax] + ((double)c[ax] + 0.5) * rg.d[ax] : rg.lo[ax];
+            ++p;
+        }
+    }
+}
+
+__device__ __forceinline__ int64_t lower_bound_key(const uint64_t *keys, int64_t n, uint64_t k)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < k)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// merge of two key-sorted sample lists with no key in common: every element
+// lands at its own index plus its rank in the other list; beyond capacity it
+// is dropped and *overflow set
+__global__ void k_merge_sorted(Samples a, const int64_t *na_p, Samples nw, const int64_t *nn_p, Samples b,
+                               int64_t capacity, int64_t *count_out, int32_t *overflow)
+{
+    const int64_t na = *na_p, nn = *nn_p;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (na + nn > capacity) *overflow = 1;
+        *count_out = na + nn < capacity ? na + nn : capacity;
+    }
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < na + nn; t += (int64_t)gridDim.x * blockDim.x) {
+        const bool old = t < na;
+        const int64_t i = old ? t : t - na;
+        const Samples &src = old ? a : nw;
+        const uint64_t k = src.keys[i];
+        const int64_t dst = i + (old ? lower_bound_key(nw.keys, nn, k) : lower_bound_key(a.keys, na, k));
+        if (dst >= capacity) continue;
+        b.keys[dst] = k;
+        b.fll[dst] = src.fll[i];
+        b.q[dst] = src.q[i];
+        b.status[dst] = src.status[i];
+    }
+}
+
 // Rounds to enqueue.  If the trace slots hold 2^batch - 1 keys for every
 // possible firing gap (at most one per sample), no round takes fewer than
 // batch levels and ceil(levels / batch) rounds suffice; otherwise a round may
 // fall back to fewer levels and up to one round per level is enqueued.
 static int planned_rounds(int levels, int batch, int64_t slots, int64_t capacity)
 {
+    if (levels <= 0) return 0;
     if ((double)slots >= (double)capacity * (double)((1 << batch) - 1)) return (levels + batch - 1) / batch;
     return levels;
 }
@@ -734,7 +821,8 @@ static int planned_rounds(int levels, int batch, int64_t slots, int64_t capacity
 // FLEDGE of the base lengths, refinement rounds, converter.
 template <int DIM>
 static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &o, int step_dtype, Region rg,
-                             int out_level, int refine_batch, const qsq_map_out *out, void *scratch, hipStream_t st)
+                             int out_level, int refine_batch, const uint8_t *propose, const qsq_map_out *out,
+                             void *scratch, hipStream_t st)
 {
     const int64_t cap = out->capacity;
     const int m = rg.m, r = rg.r;
@@ -796,14 +884,41 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
     int batch = refine_batch;
     if (batch <= 0) batch = levels < 4 ? levels : 4;
     if (batch > 5) batch = 5;
+    if (batch < 1) batch = 1;       // no levels: no rounds either
     int64_t *rem = &counts[kRemWord];
     Round *rds = reinterpret_cast<Round *>(base + Lo.rounds);
     hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, st, rem, (int64_t)levels);
-    const int rounds = planned_rounds(levels, batch, Lo.tcap, cap);
     Samples cur = A, nxt = Bs;
+    int step = 0;      // sample-count slot of the current sample list
+    if (propose && levels > 0) {
+        // proposals first: trace the finest cells of every proposed base cell
+        // and merge them in; the gaps are irregular from here on, so the rule
+        // runs one pass per round
+        int64_t *n_prop = &counts[kPropWords], *n_eff = n_prop + 1, *n_seeds = n_prop + 2;
+        hipLaunchKernelGGL(k_prop_flags, dim3(grid_for(nb)), dim3(256), 0, st, propose, nb, flag);
+        launch_scan(flag, &counts[0], Lo.nblocks, bsum, fpos, n_prop, st);
+        const int64_t per = ((int64_t)1 << (DIM * r)) - 1;
+        hipLaunchKernelGGL(k_prop_setup, dim3(1), dim3(1), 0, st, n_prop, per, Lo.tcap, n_eff, n_seeds, out->overflow);
+        hipLaunchKernelGGL((k_prop_seeds<DIM>), dim3(grid_for(nb)), dim3(256), 0, st, rg, nb, flag, fpos, n_eff,
+                           Lo.tcap, seeds, N.keys);
+        job.n_dev = n_seeds;
+        job.fll = N.fll;
+        job.q_perp = N.q;
+        job.status = N.status;
+        e = launch_trace(job, step_dtype, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_merge_sorted, dim3(grid_for(cap)), dim3(256), 0, st, cur, &counts[0], N, n_seeds, nxt,
+                           cap, &counts[1], out->overflow);
+        Samples t = cur;
+        cur = nxt;
+        nxt = t;
+        step = 1;
+        batch = 1;
+    }
+    const int rounds = planned_rounds(levels, batch, Lo.tcap, cap);
     int round = 0;
     for (; round < rounds; ++round) {
-        int64_t *cin = &counts[round], *cout = &counts[round + 1];
+        int64_t *cin = &counts[step + round], *cout = &counts[step + round + 1];
         int64_t *n_fire = &counts[kRoundWords + 4 * round], *n_eff = n_fire + 1, *n_seeds = n_fire + 2,
                 *n_kept = n_fire + 3;
         hipLaunchKernelGGL(k_fire, dim3(grid_for(cap)), dim3(256), 0, st, cur, cin, rg.thr, flag);
@@ -829,15 +944,16 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
         nxt = t;
     }
     // leave the samples in the caller's arrays
-    if (round % 2 == 1) {
-        hipLaunchKernelGGL(k_copy_samples, dim3(grid_for(cap)), dim3(256), 0, st, cur, A, &counts[round]);
+    const int last = step + round;
+    if (last % 2 == 1) {
+        hipLaunchKernelGGL(k_copy_samples, dim3(grid_for(cap)), dim3(256), 0, st, cur, A, &counts[last]);
         cur = A;
     }
-    hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, st, &counts[round], out->count);
+    hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, st, &counts[last], out->count);
     if (out->q_grid || out->fll_grid) {
         const int64_t No = (int64_t)1 << (DIM * out_level);
         hipLaunchKernelGGL((k_convert<DIM>), dim3(grid_for(No, 32)), dim3(256), 0, st, rg, out_level, cur,
-                           &counts[round], out->q_grid, out->fll_grid);
+                           &counts[last], out->q_grid, out->fll_grid);
     }
     return hipGetLastError();
 }
@@ -857,7 +973,7 @@ hipError_t launch_qmap(const qsq_field *f, const Geom &g, const StepOpts &o, int
     rg.d[1] = (d->y1 - d->y0) / nL;
     rg.d[2] = 0.0;
     rg.thr = d->threshold;
-    return launch_map<2>(f, g, o, step_dtype, rg, d->out_level, d->refine_batch, out, scratch, st);
+    return launch_map<2>(f, g, o, step_dtype, rg, d->out_level, d->refine_batch, d->propose, out, scratch, st);
 }
 
 hipError_t launch_vmap(const qsq_field *f, const Geom &g, const StepOpts &o, int step_dtype,
@@ -874,7 +990,7 @@ hipError_t launch_vmap(const qsq_field *f, const Geom &g, const StepOpts &o, int
         rg.d[a] = (hi[a] - lo[a]) / nL;
     }
     rg.thr = d->threshold;
-    return launch_map<3>(f, g, o, step_dtype, rg, d->out_level, d->refine_batch, out, scratch, st);
+    return launch_map<3>(f, g, o, step_dtype, rg, d->out_level, d->refine_batch, d->propose, out, scratch, st);
 }
 
 }  // namespace qsq

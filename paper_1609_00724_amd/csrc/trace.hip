@@ -601,8 +601,8 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
                 fb[d] = (T)(xg - fl);
             }
             if (!have_k1) {
-                const T un2 = rhs_step<T, S, MODE, CACHED>(nodes, rsrc, cbytes, g, ib, fb, sigma, D1, D2, Kx[0], K1[0], K2[0],
-                                                   cache_cell, slot, stride);
+                const T un2 = rhs_step<T, S, MODE, CACHED>(nodes, rsrc, cbytes, g, ib, fb, (T)1, D1, D2, Kx[0], K1[0],
+                                                           K2[0], cache_cell, slot, stride);
                 ++c_ev;
                 if (!(un2 >= (T)1e-12)) stop = QSQ_END_NULL;
                 have_k1 = true;
@@ -615,6 +615,11 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
                 hs = (T)(o.max_length - s);
                 last = true;
             }
+            // The stage slopes K hold the unsigned right-hand side F; the
+            // direction sign rides on the step: sigma F h = F (sigma h), and
+            // both products are exact sign flips, so the arithmetic is that of
+            // f = sigma F bit for bit.
+            const T hsig = sigma * hs;
             // stages 2..6
 #define QSQ_STAGE(ST, ...)                                                                          \
     {                                                                                               \
@@ -629,11 +634,11 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
                 a1 = fma(c_[j], K1[j][i], a1);                                                      \
                 a2 = fma(c_[j], K2[j][i], a2);                                                      \
             }                                                                                       \
-            q[i] = fma(hs * ax, ih[i], fb[i]);                                                      \
-            d1[i] = fma(hs, a1, D1[i]);                                                             \
-            d2[i] = fma(hs, a2, D2[i]);                                                             \
+            q[i] = fma(hsig * ax, ih[i], fb[i]);                                                    \
+            d1[i] = fma(hsig, a1, D1[i]);                                                           \
+            d2[i] = fma(hsig, a2, D2[i]);                                                           \
         }                                                                                           \
-        rhs_step<T, S, MODE, CACHED>(nodes, rsrc, cbytes, g, ib, q, sigma, d1, d2, Kx[ST], K1[ST], K2[ST], \
+        rhs_step<T, S, MODE, CACHED>(nodes, rsrc, cbytes, g, ib, q, (T)1, d1, d2, Kx[ST], K1[ST], K2[ST], \
                              cache_cell, slot, stride);                                             \
     }
             QSQ_STAGE(1, (T)ck::a21)
@@ -655,9 +660,9 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
                 const T ex = (T)ck::e1 * Kx[0][i] + (T)ck::e3 * Kx[2][i] + (T)ck::e4 * Kx[3][i] + (T)ck::e5 * Kx[4][i] + (T)ck::e6 * Kx[5][i];
                 const T e1 = (T)ck::e1 * K1[0][i] + (T)ck::e3 * K1[2][i] + (T)ck::e4 * K1[3][i] + (T)ck::e5 * K1[4][i] + (T)ck::e6 * K1[5][i];
                 const T e2 = (T)ck::e1 * K2[0][i] + (T)ck::e3 * K2[2][i] + (T)ck::e4 * K2[3][i] + (T)ck::e5 * K2[4][i] + (T)ck::e6 * K2[5][i];
-                Xn[i] = X[i] + (double)(hs * bx);
-                D1n[i] = fma(hs, b1, D1[i]);
-                D2n[i] = fma(hs, b2, D2[i]);
+                Xn[i] = X[i] + (double)(hsig * bx);
+                D1n[i] = fma(hsig, b1, D1[i]);
+                D2n[i] = fma(hsig, b2, D2[i]);
                 const T xo = (T)X[i], xn = (T)Xn[i];
                 const T sx = atol + rtol * fmax(fabs(xo), fabs(xn));
                 const T s1 = atol + rtol * fmax(fabs(D1[i]), fabs(D1n[i]));

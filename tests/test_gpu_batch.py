@@ -137,4 +137,44 @@ def test_batch_graph_replay():
             for key in r:
                 assert torch.equal(o[key], r[key]), f"replay {rep} set {k} {key}"
         assert torch.equal(plan.work, work_ref), f"replay {rep} work"
-    assert q.lib.qsq_abi_version() == 1
+    assert q.lib.qsq_abi_version() == 2
+
+
+def test_launch_shapes_give_identical_results():
+    """The launch shape (lanes per CU, workgroup size) moves no result: every
+    line's arithmetic is the same wherever it runs.  The two gather variants
+    (direct loads, LDS cell cache) read the same node values; they must agree
+    line by line within the FP32 gates."""
+    import torch
+
+    import paper_1609_00724_amd as q
+    from paper_1609_00724_amd import _abi as A
+    from paper_1609_00724_amd import autotune
+    from paper_1609_00724_amd.api import TracePlan, make_opts
+    dev = torch.device("cuda:0")
+    f = _sets(1, np.float32, empty=())[0]
+    fg = gpu_field(f["b"], f["origin"], f["spacing"], storage="f32")
+    seeds = torch.from_numpy(synth.random_seeds(77, 5000)).to(dev).t().contiguous()
+    plan = TracePlan(seeds.shape[1], dev, want_steps=True)
+    res = {}
+    for lanes, wg, gather in [(0, 256, 1), (2, 64, 1), (3, 128, 1), (12, 256, 1), (0, 256, 2), (2, 64, 2), (6, 128, 2)]:
+        opts = make_opts(1e-5, 1e-5, step_dtype="f32", launch=A.launch_word(lanes, wg, gather))
+        out = plan.run(fg, seeds, opts)
+        torch.cuda.synchronize()
+        res[(lanes, wg, gather)] = {k: v.clone() for k, v in out.items()}
+    for g in (1, 2):
+        ref = next(v for k, v in res.items() if k[2] == g)
+        for k, v in res.items():
+            if k[2] != g:
+                continue
+            for key in ref:
+                assert torch.equal(torch.nan_to_num(v[key], nan=-1.0), torch.nan_to_num(ref[key], nan=-1.0)), (k, key)
+    a, b = res[(0, 256, 1)], res[(0, 256, 2)]
+    same = (a["status"] == b["status"]).float().mean().item()
+    close = ((a["fll"] - b["fll"]).abs() <= 1e-4 * b["fll"].abs().clamp(min=1e-12)).float().mean().item()
+    print(f"direct vs cached gathers: status agreement {same:.4f}, lengths within 1e-4: {close:.4f}")
+    assert same >= 0.997 and close >= 0.99
+    word, table = autotune.tune_trace(fg, seeds.t().contiguous(), make_opts(1e-5, 1e-5, step_dtype="f32"), reps=1,
+                                      cands=autotune.candidates(lanes=(2, 8), wgs=(128, 256)), use_cache=False)
+    assert word in table and table[word] == min(table.values())
+    assert autotune.describe(word)["workgroup"] in (128, 256)

@@ -148,6 +148,55 @@ def test_small_map_vs_oracle(oracle_mod, c2, step_dtype):
                        rtol=1e-5, atol=1e-5)
 
 
+@pytest.mark.parametrize("step_dtype", ["f32", "f64"])
+def test_map_with_proposals(oracle_mod, c2, step_dtype):
+    """Proposed base pixels get every finest cell as a sample before the
+    FLL-jump rule runs; the rule then refines the rest (fallback).  Same result
+    as the oracle's refinement from the same merged sample set."""
+    import paper_1609_00724_amd as q
+    from paper_1609_00724_amd.api import MapSpec
+    torch, dev = torch_dev()
+    m, r, thr = 6, 2, 0.02
+    picked = synth.rng(9).choice(4 ** m, size=300, replace=False)
+    prop = torch.zeros(4 ** m, dtype=torch.uint8, device=dev)
+    prop[torch.from_numpy(picked).to(dev)] = 1
+    spec = MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, r, m + r, thr, 0, propose=prop)
+    res = q.qmap(c2["fg"], spec, 4 ** (m + r), rtol=TOL, atol=TOL, h_init=0.1 * c2["h"], h_max=c2["h"],
+                 step_dtype=step_dtype)
+    torch.cuda.synchronize()
+    res = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}
+    n = res["count"]
+    assert res["overflow"] == 0
+    _check_complete(res, thr)
+    base = np.arange(4 ** m) * 16 + 8
+    extra = np.setdiff1d((picked[:, None] * 16 + np.arange(16)[None, :]).ravel(), base)
+    assert np.all(np.isin(extra, res["keys"]))
+    _sample_parity(oracle_mod, c2, res, np.arange(0, n, 3), m, r, strict=step_dtype == "f64")
+    plane = oracle_mod.SlicePlane(0.0, -1.0, 1.0, -1.0, 1.0)
+
+    def fn(p):
+        t = _oracle_trace(oracle_mod, c2, p)
+        return {"fll": t["fll"], "q": t["q_perp"]}
+
+    ok, _, _ = oracle_mod.refine_slice(plane, m, r, thr, fn, extra_keys=extra)
+    common = np.intersect1d(ok, res["keys"]).size
+    union = np.union1d(ok, res["keys"]).size
+    assert common / union > 0.995, (common, union)
+    # without proposals the same call is the plain map, and it holds fewer samples
+    plain = _run_map(c2, m, r, thr, m + r, 4 ** (m + r), step_dtype)
+    assert plain["count"] < n
+
+
+def test_map_without_refinement(oracle_mod, c2):
+    """refine_levels = 0: the base lattice only, key q + 0 (B^0 / 2 = 0 with
+    integer halving is the cell itself), every sample a base sample."""
+    m = 6
+    res = _run_map(c2, m, 0, 0.02, m, 4 ** m)
+    assert res["count"] == 4 ** m and res["overflow"] == 0
+    assert np.array_equal(res["keys"], np.arange(4 ** m))
+    _sample_parity(oracle_mod, c2, res, np.arange(0, 4 ** m, 7), m, 0)
+
+
 @pytest.mark.parametrize("r", [2, 3])
 def test_refine_batches_give_identical_maps(c2, r):
     """Deciding several refinement levels per device round (tracing every key

@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch shape")
+    ap.add_argument("--launch", type=int, default=0, help="launch-shape word with --no-tune (0: library default)")
     ap.add_argument("--accuracy-lines", type=int, default=256)
     ap.add_argument("--workload", choices=("map", "batch", "volume", "learned"), default="map",
                     help="map: photospheric map of one field; batch: 64 fields in one batched trace; "
@@ -111,14 +112,16 @@ def main():
     stream = torch.cuda.current_stream()
 
     tuned = None
+    opts.launch = args.launch
     if not args.no_tune:
         # launch shape picked on the workload itself, before the timed region
         from paper_1609_00724_amd import autotune
-        word, table = autotune.tune_map(plan, field, opts, reps=2)
+        batches = (args.refine_batch,) if args.refine_batch > 0 else (1, 2, 3, 4)
+        (word, batch), table = autotune.tune_map(plan, field, opts, reps=2, batches=batches)
         opts.launch = word
-        default = table.get(0, table.get(A.launch_word(), None))
-        tuned = dict(autotune.describe(word), ms=table[word], candidates=len(table),
-                     worst_ms=max(table.values()), default_shape_ms=default)
+        plan.d.refine_batch = batch
+        tuned = dict(autotune.describe(word), refine_batch=batch, ms=table[(word, batch)], candidates=len(table),
+                     worst_ms=max(table.values()))
     for _ in range(args.warmup):
         plan.run(field, opts)
     torch.cuda.synchronize()
@@ -170,7 +173,7 @@ def main():
             "grid": [256, 256, 128],
             "tol": args.tol,
             "h_max_cells": args.hmax_cells,
-            "refine_batch": args.refine_batch,
+            "refine_batch": plan.d.refine_batch,
         },
         "roofline": {
             "bound": "alu",
@@ -202,7 +205,7 @@ def main():
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trace_traffic.json")
 PMC_MAPS = 2             # maps timed in the counter runs (bench.py --steps 2)
-LAUNCHES_PER_MAP = 5     # stepping launches per map: base lattice + 2r refinement rounds (r = 2)
+LAUNCHES_PER_MAP = 5     # stepping passes per map: base lattice + 2r refinement rounds (r = 2)
 KERNEL_SOURCES = ("paper_1609_00724_amd/csrc/trace.hip", "paper_1609_00724_amd/csrc/qsq_internal.h")
 
 
@@ -234,13 +237,15 @@ def summarize_pmc(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
     cw = [v for k, v in _pmc_rows(copy_write_dir, "WRITE_SIZE") if "copyBuffer" in k]
     fscale = gib / (sum(cf) / len(cf) * 1024.0)
     wscale = gib / (sum(cw) / len(cw) * 1024.0)
-    # the launches of the last PMC_MAPS maps: the timed phase of a
-    # `--steps PMC_MAPS` run (after the launch-shape tuning and warm-up maps)
-    f = [v for k, v in _pmc_rows(fetch_dir, "FETCH_SIZE") if "k_trace" in k][-PMC_MAPS * LAUNCHES_PER_MAP:]
-    w = [v for k, v in _pmc_rows(write_dir, "WRITE_SIZE") if "k_trace" in k][-PMC_MAPS * LAUNCHES_PER_MAP:]
-    out = {"kernel_sources_sha256": kernel_hash(), "launches": len(f),
-           "fetch_bytes_per_launch": sum(f) / len(f) * 1024.0 * fscale,
-           "write_bytes_per_launch": sum(w) / len(w) * 1024.0 * wscale,
+    # the stepping passes of the last PMC_MAPS maps (the timed phase of a
+    # `--steps PMC_MAPS` run, after the launch-shape tuning and warm-up maps);
+    # a pass is the persistent stepping kernel plus its cooperative tail
+    npass = PMC_MAPS * LAUNCHES_PER_MAP
+    f = [v for k, v in _pmc_rows(fetch_dir, "FETCH_SIZE") if "k_trace" in k][-2 * npass:]
+    w = [v for k, v in _pmc_rows(write_dir, "WRITE_SIZE") if "k_trace" in k][-2 * npass:]
+    out = {"kernel_sources_sha256": kernel_hash(), "passes": npass, "dispatches": len(f),
+           "fetch_bytes_per_launch": sum(f) / npass * 1024.0 * fscale,
+           "write_bytes_per_launch": sum(w) / npass * 1024.0 * wscale,
            "fetch_scale": fscale, "write_scale": wscale,
            "copy_fetch_kib": sum(cf) / len(cf), "copy_write_kib": sum(cw) / len(cw)}
     out["bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
@@ -357,7 +362,7 @@ def bench_batch(args):
     del plans1
 
     # FP64 stepping of the same batch, and the FP32-vs-FP64 difference in Q
-    plan64 = TraceBatchPlan(sets, opts64)
+    plan64 = TraceBatchPlan(sets, opts64, want_work=True)
     with torch.cuda.stream(stream):
         plan64.run()
         torch.cuda.synchronize()
@@ -367,6 +372,7 @@ def bench_batch(args):
         d1.record(stream)
     torch.cuda.synchronize()
     ms64 = d0.elapsed_time(d1)
+    att64 = int(plan64.work.cpu().numpy()[0]) // 2       # two runs of the FP64 batch
     q32 = torch.cat([o["q_perp"] for o in plan.outs]).cpu().numpy()
     q64 = torch.cat([o["q_perp"] for o in plan64.outs]).cpu().numpy()
     st32 = torch.cat([o["status"] for o in plan.outs]).cpu().numpy()
@@ -412,7 +418,7 @@ def bench_batch(args):
         "launch_shape": tuned,
         "one_call_per_field_ms": ms_single,
         "batch_speedup_vs_one_call_per_field": ms_single / ms_step,
-        "fp64_stepping": {"ms": ms64, "lines_per_s": total / (ms64 / 1e3),
+        "fp64_stepping": {"ms": ms64, "lines_per_s": total / (ms64 / 1e3), "attempts": att64,
                           "median_rel_log10q_diff_fp32_vs_fp64": float(np.median(rel)),
                           "p99": float(np.percentile(rel, 99)),
                           "status_agreement": float((st32 == st64).mean())},

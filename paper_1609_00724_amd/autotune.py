@@ -109,14 +109,21 @@ def describe(word):
     return {"word": int(word), "lanes_per_cu": lanes * 256, "workgroup": wg, "gather": gather}
 
 
-def tune_map(plan, field, opts, reps=3, cands=None):
-    """Fastest launch word for a whole map call (QMapPlan) on `field`: the
-    tuned workload is the real one (base lattice, refinement rounds)."""
-    saved = opts.launch
+def tune_map(plan, field, opts, reps=3, cands=None, batches=None):
+    """Fastest launch word (and, if `batches` is given, refinement levels per
+    device round) for a whole map call (QMapPlan) on `field`: the tuned
+    workload is the real one (base lattice, refinement rounds).  Returns
+    (word, table) or, with batches, ((word, batch), table); the plan keeps
+    its own refine_batch."""
+    saved_w, saved_b = opts.launch, plan.d.refine_batch
     table = {}
-    for w in cands or candidates():
-        opts.launch = w
-        table[w] = _time(lambda: plan.run(field, opts), reps)
-    opts.launch = saved
+    for b in batches or (saved_b,):
+        plan.d.refine_batch = b
+        for w in cands or candidates():
+            opts.launch = w
+            table[(w, b)] = _time(lambda: plan.run(field, opts), reps)
+    opts.launch, plan.d.refine_batch = saved_w, saved_b
     best = min(table, key=table.get)
+    if batches is None:
+        return best[0], {k[0]: v for k, v in table.items()}
     return best, table

@@ -535,7 +535,29 @@ def bench_volume(args):
     }
     if not args.no_accuracy:
         out["accuracy"] = accuracy_volume(args, w, f32, bf16, h)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_volume(args, w, h)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_volume(args, w, h):
+    """The oracle on a bounded sample of the volume workload: the same field,
+    tolerance and 3D refinement rule on a 32^3 base lattice."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    fo = _oracle_field(w)
+    box = oracle.VolumeBox(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0)
+
+    def fn(p):
+        t = oracle.trace(fo, p, rtol=args.tol, atol=args.tol, h_init=0.1 * h, h_max=args.hmax_cells * h,
+                         nthreads=threads)
+        return {"fll": t["fll"], "q": t["q_perp"]}
+
+    t0 = time.perf_counter()
+    keys, _, _ = oracle.refine_slice(box, 5, args.refine_levels, args.threshold, fn)
+    dt = time.perf_counter() - t0
+    return {"value": keys.size / dt, "unit": "lines/s", "cores": threads, "kind": "oracle",
+            "sample": f"same field, tolerance and 3D refinement rule on a 32^3 base lattice ({keys.size} lines, {dt:.1f} s)"}
 
 
 def accuracy_volume(args, w, f32, bf16, h):

@@ -204,8 +204,6 @@ def main():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trace_traffic.json")
-PMC_MAPS = 2             # maps timed in the counter runs (bench.py --steps 2)
-LAUNCHES_PER_MAP = 5     # stepping passes per map: base lattice + 2r refinement rounds (r = 2)
 KERNEL_SOURCES = ("paper_1609_00724_amd/csrc/trace.hip", "paper_1609_00724_amd/csrc/qsq_internal.h")
 
 
@@ -237,12 +235,14 @@ def summarize_pmc(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
     cw = [v for k, v in _pmc_rows(copy_write_dir, "WRITE_SIZE") if "copyBuffer" in k]
     fscale = gib / (sum(cf) / len(cf) * 1024.0)
     wscale = gib / (sum(cw) / len(cw) * 1024.0)
-    # the stepping passes of the last PMC_MAPS maps (the timed phase of a
-    # `--steps PMC_MAPS` run, after the launch-shape tuning and warm-up maps);
-    # a pass is the persistent stepping kernel plus its cooperative tail
-    npass = PMC_MAPS * LAUNCHES_PER_MAP
-    f = [v for k, v in _pmc_rows(fetch_dir, "FETCH_SIZE") if "k_trace" in k][-2 * npass:]
-    w = [v for k, v in _pmc_rows(write_dir, "WRITE_SIZE") if "k_trace" in k][-2 * npass:]
+    # every stepping launch of the counter runs: they time a fixed launch shape
+    # with no tuning and no warm-up maps (`--no-tune --launch W --refine-batch B
+    # --warmup 0`), so all of their k_trace dispatches are the timed maps'
+    f = [v for k, v in _pmc_rows(fetch_dir, "FETCH_SIZE") if "k_trace<" in k]
+    w = [v for k, v in _pmc_rows(write_dir, "WRITE_SIZE") if "k_trace<" in k]
+    if not f or len(f) != len(w):
+        raise SystemExit(f"stepping dispatches differ between the runs: {len(f)} FETCH_SIZE, {len(w)} WRITE_SIZE")
+    npass = len(f)
     out = {"kernel_sources_sha256": kernel_hash(), "passes": npass, "dispatches": len(f),
            "fetch_bytes_per_launch": sum(f) / npass * 1024.0 * fscale,
            "write_bytes_per_launch": sum(w) / npass * 1024.0 * wscale,
@@ -641,6 +641,8 @@ def bench_learned(args):
         x = learn.features(cres["fll_grid"], cres["fledge"], bz)
         data.append(dict(x=x, mask=mask, logq=logq, qfine=qf if k % 10 == 0 else None, z0=z0, rope=rope,
                          field=fg if k % 10 == 0 else None, lines_plain=fres["count"]))
+        if k % 32 == 31:
+            print(f"learned: {k + 1} maps generated", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
     train = [d for k, d in enumerate(data) if k % 10 != 0]
@@ -664,6 +666,7 @@ def bench_learned(args):
             nb += 1
             steps += 1
         curve.append(float(tot) / max(nb, 1))
+        print(f"learned: epoch {ep + 1} loss {curve[-1]:.4f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t_train
     # training throughput of the kernels alone: one timed step on a full batch

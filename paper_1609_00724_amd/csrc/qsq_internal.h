@@ -19,9 +19,6 @@ struct Bf16 {
 constexpr int kPendingLand = 0x7f;
 // record status of a half-line the seed pass set up for stepping
 constexpr int kPendingStep = 0x7e;
-// record status of a half-line handed from the stepping kernel to the
-// cooperative tail kernel (state, length, step and attempts in the record)
-constexpr int kParked = 0x7d;
 
 // Grid geometry as the kernels see it.
 struct Geom {
@@ -61,9 +58,6 @@ struct Records {
     int64_t *scan_tmp;  // block sums of the scan
     int64_t *n_work;    // device scalar: work items
     int64_t *n_items;   // device scalar: half-lines of the call (2 n)
-    int32_t *tail;      // 2*cap: records parked for the cooperative tail
-    unsigned long long *n_tail;   // device scalar: parked records
-    unsigned long long *t_drain;  // device scalar: clock when the work list first ran dry
 };
 
 // One seed set of a batched trace: its own field, seeds, per-grid step

@@ -174,9 +174,8 @@ __device__ __forceinline__ void field_at(const S *__restrict__ nodes, const Geom
     }
 }
 
-// a0 b0 + a1 b1 + a2 b2 with the fused operations spelled out, so that every
-// code path that forms it (one lane per line, or one lane per component)
-// rounds identically
+// a0 b0 + a1 b1 + a2 b2 with the fused operations spelled out, so that the
+// rounding does not depend on how the compiler contracts the expression
 template <typename T>
 __device__ __forceinline__ T jdot(T a0, T a1, T a2, T b0, T b1, T b2)
 {
@@ -504,250 +503,6 @@ __global__ void k_compact(TraceJob job)
 }
 
 // ---------------------------------------------------------------------------
-// cooperative tail: a quad of lanes per line, lane c holding component c of
-// x, dx1 and dx2 (lane 3 mirrors component 2 and its results are unused).
-// Same operations in the same order as the one-lane-per-line step, so a line
-// gets the same result whichever way it was stepped.
-// ---------------------------------------------------------------------------
-constexpr int kCoopLines = 16;
-// wall-clock ticks (100 MHz) after the work list first ran dry when every wave
-// parks what it still holds
-constexpr unsigned long long kTailDelay = 30000;
-
-// lane D's value of the quad, to every lane of the quad (DPP quad permute)
-template <int D>
-__device__ __forceinline__ int quad_get(int v)
-{
-    return __builtin_amdgcn_update_dpp(0, v, D * 0x55, 0xF, 0xF, false);
-}
-template <int D>
-__device__ __forceinline__ float quad_get(float v)
-{
-    return __int_as_float(quad_get<D>(__float_as_int(v)));
-}
-__device__ __forceinline__ float quad_max(float v)
-{
-    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false)));
-    return fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false)));
-}
-__device__ __forceinline__ int quad_or(int v)
-{
-    v |= __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
-    return v | __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
-}
-
-// f = (u, J dx1, J dx2) for component c (PAPER records, FP32); returns |u|^2.
-// The lane keeps its component of the 8 corners of the cell it used last (cv,
-// keyed by the cell index ck) and loads only when the stage point moved to
-// another cell (the same cell for the whole quad).
-__device__ __forceinline__ float coop_rhs(const float *__restrict__ nodes, const Geom &g, const float ih[3], int c,
-                                          int ib, float q, float d1c, float d2c, float &kx, float &k1, float &k2,
-                                          int64_t &ck, float cv[8])
-{
-    int cl;
-    float tl;
-    cell_of(ib, q, g.n[c], cl, tl);
-    const int c0 = quad_get<0>(cl), c1 = quad_get<1>(cl), c2 = quad_get<2>(cl);
-    const float t0 = quad_get<0>(tl), t1 = quad_get<1>(tl), t2 = quad_get<2>(tl);
-    const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
-    const int64_t b = (int64_t)c2 * sz + (int64_t)c1 * sy + c0;
-    if (b != ck) {
-        const float *p = nodes + 4 * b + c;
-        cv[0] = p[0];
-        cv[1] = p[4];
-        cv[2] = p[4 * sy];
-        cv[3] = p[4 * sy + 4];
-        cv[4] = p[4 * sz];
-        cv[5] = p[4 * sz + 4];
-        cv[6] = p[4 * (sz + sy)];
-        cv[7] = p[4 * (sz + sy) + 4];
-        ck = b;
-    }
-    float val, dx, dy, dz;
-    lerp_tree<float>(cv[0], cv[1], cv[2], cv[3], cv[4], cv[5], cv[6], cv[7], t0, t1, t2, val, dx, dy, dz);
-    const float g0 = dx * ih[0], g1 = dy * ih[1], g2 = dz * ih[2];
-    kx = val;
-    k1 = jdot(g0, g1, g2, quad_get<0>(d1c), quad_get<1>(d1c), quad_get<2>(d1c));
-    k2 = jdot(g0, g1, g2, quad_get<0>(d2c), quad_get<1>(d2c), quad_get<2>(d2c));
-    const float u0 = quad_get<0>(val), u1 = quad_get<1>(val), u2 = quad_get<2>(val);
-    return jdot(u0, u1, u2, u0, u1, u2);
-}
-
-template <int MODE>
-__device__ __forceinline__ void coop_run(const TraceJob &job, const float *__restrict__ nodes, const Geom &g,
-                                         const float ih[3], float hmax, double hmin, float rtol, float atol, bool run,
-                                         double Xc, float D1c, float D2c, float h, float sigma, double s, int attempts,
-                                         int64_t rec, int comp, int c, unsigned long long &c_att,
-                                         unsigned long long &c_ev, unsigned long long &c_land)
-{
-    const StepOpts &o = job.o;
-    const bool lead = comp == 0;
-    const int64_t P = 2 * job.rec.cap;
-    bool have_k1 = false;
-    float Kx[6], K1[6], K2[6];
-    int64_t ck = -1;
-    float cv[8];
-    while (__ballot(run)) {
-        if (!run) continue;
-        int stop = -1;
-        if (attempts >= o.max_steps) stop = QSQ_END_MAX_STEPS;
-        const double xg = (Xc - g.o[c]) * g.ih[c];
-        const double fl = floor(xg);
-        const int ib = (int)fl;
-        const float fb = (float)(xg - fl);
-        if (stop < 0 && !have_k1) {
-            const float un2 = coop_rhs(nodes, g, ih, c, ib, fb, D1c, D2c, Kx[0], K1[0], K2[0], ck, cv);
-            if (lead) ++c_ev;
-            if (!(un2 >= 1e-12f)) stop = QSQ_END_NULL;
-            have_k1 = true;
-        }
-        if (stop < 0) {
-            float hs = h < hmax ? h : hmax;
-            bool last = false;
-            if (o.max_length > 0.0 && (double)hs >= o.max_length - s) {
-                hs = (float)(o.max_length - s);
-                last = true;
-            }
-            const float hsig = sigma * hs;
-#define QSQ_CSTAGE(ST, ...)                                                                         \
-    {                                                                                               \
-        const float c_[] = {__VA_ARGS__};                                                           \
-        float ax = 0, b1 = 0, b2 = 0;                                                               \
-        _Pragma("unroll") for (int jj = 0; jj < ST; ++jj)                                           \
-        {                                                                                           \
-            ax = fma(c_[jj], Kx[jj], ax);                                                           \
-            b1 = fma(c_[jj], K1[jj], b1);                                                           \
-            b2 = fma(c_[jj], K2[jj], b2);                                                           \
-        }                                                                                           \
-        coop_rhs(nodes, g, ih, c, ib, fma(hsig * ax, ih[c], fb), fma(hsig, b1, D1c), fma(hsig, b2, D2c), \
-                 Kx[ST], K1[ST], K2[ST], ck, cv);                                                   \
-    }
-            QSQ_CSTAGE(1, (float)ck::a21)
-            QSQ_CSTAGE(2, (float)ck::a31, (float)ck::a32)
-            QSQ_CSTAGE(3, (float)ck::a41, (float)ck::a42, (float)ck::a43)
-            QSQ_CSTAGE(4, (float)ck::a51, (float)ck::a52, (float)ck::a53, (float)ck::a54)
-            QSQ_CSTAGE(5, (float)ck::a61, (float)ck::a62, (float)ck::a63, (float)ck::a64, (float)ck::a65)
-#undef QSQ_CSTAGE
-            const float bx = ck_b5(Kx[0], Kx[2], Kx[3], Kx[5]);
-            const float b1 = ck_b5(K1[0], K1[2], K1[3], K1[5]);
-            const float b2 = ck_b5(K2[0], K2[2], K2[3], K2[5]);
-            const float ex = ck_e(Kx[0], Kx[2], Kx[3], Kx[4], Kx[5]);
-            const float f1 = ck_e(K1[0], K1[2], K1[3], K1[4], K1[5]);
-            const float f2 = ck_e(K2[0], K2[2], K2[3], K2[4], K2[5]);
-            const double Xn = Xc + (double)(hsig * bx);
-            const float D1n = fma(hsig, b1, D1c), D2n = fma(hsig, b2, D2c);
-            const float xo = (float)Xc, xn = (float)Xn;
-            float err = err_ratio(fabsf(hs * ex), err_scale(atol, rtol, xo, xn));
-            err = fmaxf(err, err_ratio(fabsf(hs * f1), err_scale(atol, rtol, D1c, D1n)));
-            err = fmaxf(err, err_ratio(fabsf(hs * f2), err_scale(atol, rtol, D2c, D2n)));
-            err = quad_max(err);
-            const bool finite = !quad_or(isfinite((xn + D1n) + (D2n + ex) + (f1 + f2)) ? 0 : 1);
-            const bool out = quad_or((Xn < g.lo[c] || Xn > g.hi[c]) ? 1 : 0) != 0;
-            ++attempts;
-            if (lead) {
-                ++c_att;
-                c_ev += 5;
-            }
-            if (!finite) {
-                stop = QSQ_END_NONFINITE;
-            } else if (err > 1.0f) {
-                const float f = 0.9f * exp2f(-0.25f * log2f(err));
-                h = hs * (f > 0.2f ? f : 0.2f);
-                if ((double)h < hmin) stop = QSQ_END_UNDERFLOW;
-            } else if (out) {
-                // accepted trial step leaves the box: hand over to FP64 landing
-                if (comp < 3) {
-                    job.rec.y[c * P + rec] = Xc;
-                    job.rec.y[(3 + c) * P + rec] = (double)D1c;
-                    job.rec.y[(6 + c) * P + rec] = (double)D2c;
-                }
-                if (lead) {
-                    job.rec.s[rec] = s;
-                    job.rec.h[rec] = (double)hs;
-                    job.rec.status[rec] = kPendingLand;
-                    job.rec.attempts[rec] = attempts;
-                    ++c_land;
-                }
-                run = false;
-            } else {
-                Xc = Xn;
-                D1c = D1n;
-                D2c = D2n;
-                have_k1 = false;
-                if (last) {
-                    s = o.max_length;
-                    stop = QSQ_END_MAX_LENGTH;
-                } else {
-                    s += (double)hs;
-                    const float f = err > 0.0f ? 0.9f * exp2f(-0.2f * log2f(err)) : 5.0f;
-                    h = hs * (f < 5.0f ? f : 5.0f);
-                }
-            }
-        }
-        if (stop >= 0) {
-            if (comp < 3) {
-                job.rec.y[c * P + rec] = Xc;
-                job.rec.y[(3 + c) * P + rec] = (double)D1c;
-                job.rec.y[(6 + c) * P + rec] = (double)D2c;
-            }
-            if (lead) {
-                job.rec.s[rec] = s;
-                job.rec.h[rec] = 0.0;
-                job.rec.status[rec] = stop;
-                job.rec.attempts[rec] = attempts;
-            }
-            run = false;
-        }
-    }
-}
-
-// The parked lines of one launch, 16 per wave at a time, a quad per line.
-template <int MODE>
-__global__ void __launch_bounds__(256) k_trace_tail(TraceJob job)
-{
-    const float *__restrict__ nodes = static_cast<const float *>(job.nodes);
-    const Geom &g = job.g;
-    const StepOpts &o = job.o;
-    const float ih[3] = {(float)g.ih[0], (float)g.ih[1], (float)g.ih[2]};
-    const float rtol = (float)o.rtol, atol = (float)o.atol, hmax = (float)o.h_max;
-    const double hmin = o.hmin;
-    const int lane = (int)(threadIdx.x & 63);
-    const int64_t ntail = (int64_t)*job.rec.n_tail;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    unsigned long long c_att = 0, c_ev = 0, c_land = 0;
-    const int j = lane >> 2, comp = lane & 3, c = comp < 3 ? comp : 2;
-    for (int64_t first = wave * kCoopLines; first < ntail; first += nwaves * kCoopLines) {
-        const int64_t idx = first + j;
-        bool run = idx < ntail;
-        const int64_t P = 2 * job.rec.cap;
-        const int64_t rec = run ? (int64_t)job.rec.tail[idx] : 0;
-        double Xc = run ? job.rec.y[c * P + rec] : 0.0;
-        float D1c = run ? (float)job.rec.y[(3 + c) * P + rec] : 0.0f;
-        float D2c = run ? (float)job.rec.y[(6 + c) * P + rec] : 0.0f;
-        double s = run ? job.rec.s[rec] : 0.0;
-        float h = run ? (float)job.rec.h[rec] : 0.0f;
-        int attempts = run ? job.rec.attempts[rec] : 0;
-        const float sigma = rec >= job.rec.cap ? -1.0f : 1.0f;
-        coop_run<MODE>(job, nodes, g, ih, hmax, hmin, rtol, atol, run, Xc, D1c, D2c, h, sigma, s, attempts, rec, comp,
-                       c, c_att, c_ev, c_land);
-    }
-    if (job.work) {
-#pragma unroll
-        for (int o2 = 32; o2 >= 1; o2 >>= 1) {
-            c_att += __shfl_xor(c_att, o2);
-            c_ev += __shfl_xor(c_ev, o2);
-            c_land += __shfl_xor(c_land, o2);
-        }
-        if (lane == 0 && (c_att | c_ev | c_land)) {   // waves that stepped nothing add nothing
-            atomicAdd(&job.work[0], c_att);
-            atomicAdd(&job.work[1], c_ev);
-            atomicAdd(&job.work[3], c_land);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // k_trace: persistent stepping kernel
 // ---------------------------------------------------------------------------
 template <typename T, typename S, int MODE, bool CACHED, bool BATCH>
@@ -794,13 +549,6 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
     constexpr int64_t kChunk = 64;
     int64_t cnext = 0, cend = 0;   // the wave's unassigned items [cnext, cend)
     bool first_fill = true;
-    // Once the wave has seen the end of the work list and at most kCoopLines
-    // of its lines are still running, it leaves this loop and finishes them
-    // with one lane per state component (the cooperative tail below): the
-    // long lines that end a launch then take ~3x less time per step.
-    constexpr bool COOP = std::is_same<T, float>::value && std::is_same<S, float>::value &&
-                          MODE == QSQ_INTERP_PAPER && !BATCH;
-    bool drained = false;
     for (;;) {
         // ---- refill idle lanes
         const uint64_t need = __ballot(!active && !done);
@@ -828,12 +576,6 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
                 }
             }
             first_fill = false;
-            if (!drained && __ballot(!active && !done && item >= total)) {
-                drained = true;
-                if constexpr (COOP) {
-                    if (lane == __ffsll((unsigned long long)need) - 1) atomicMin(job.rec.t_drain, wall_clock64());
-                }
-            }
             if (!active && !done) {
                 if (item >= total) {
                     done = true;
@@ -871,39 +613,6 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
             }
         }
         if (__ballot(!done) == 0) break;
-        if constexpr (COOP) {
-            const uint64_t act = __ballot(active);
-            // park when few lines are left in this wave, or once the whole
-            // launch has run a while past the end of the list (by then the
-            // short lines are done and the long ones should not wait for the
-            // slowest wave)
-            bool park = false;
-            if (drained) {
-                park = __popcll(act) <= kCoopLines;
-                if (!park) {
-                    const unsigned long long t0 =
-                        __hip_atomic_load(job.rec.t_drain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    park = wall_clock64() > t0 + kTailDelay;
-                }
-                park = __ballot(park) != 0;
-            }
-            if (park) {
-                // park the running lines for the cooperative tail kernel
-                if (act) {
-                    const int leader = __ffsll((unsigned long long)act) - 1;
-                    unsigned long long base = 0;
-                    if (lane == leader) base = atomicAdd(job.rec.n_tail, (unsigned long long)__popcll(act));
-                    base = __shfl(base, leader);
-                    if (active) {
-                        const double y[9] = {X[0], X[1], X[2], (double)D1[0], (double)D1[1], (double)D1[2],
-                                             (double)D2[0], (double)D2[1], (double)D2[2]};
-                        put_rec(job.rec, rec, y, s, (double)h, kParked, attempts);
-                        job.rec.tail[base + __popcll(act & ((1ull << lane) - 1ull))] = (int32_t)rec;
-                    }
-                }
-                break;
-            }
-        }
         if (!active) continue;
 
         // ---- one step attempt (oracle order: step cap, null, trial, accept/reject, exit)
@@ -1341,13 +1050,7 @@ __global__ void __launch_bounds__(256) k_assemble(TraceJob job)
     }
 }
 
-__global__ void k_set_counters(unsigned long long *counter, unsigned long long v, unsigned long long *n_tail,
-                               unsigned long long *t_drain)
-{
-    *counter = v;
-    *n_tail = 0ull;
-    *t_drain = ~0ull;
-}
+__global__ void k_set_u64(unsigned long long *p, unsigned long long v) { *p = v; }
 
 // ---------------------------------------------------------------------------
 // host side
@@ -1355,7 +1058,7 @@ __global__ void k_set_counters(unsigned long long *counter, unsigned long long v
 uint64_t records_bytes(int64_t cap)
 {
     const uint64_t P = 2 * (uint64_t)cap;
-    return P * (11 * sizeof(double) + 6 * sizeof(int32_t)) + (uint64_t)scan_tmp_words((int64_t)P) * 8;
+    return P * (11 * sizeof(double) + 5 * sizeof(int32_t)) + (uint64_t)scan_tmp_words((int64_t)P) * 8;
 }
 
 void carve_records(void *scratch, int64_t cap, Records *rec, unsigned long long **counter)
@@ -1381,15 +1084,11 @@ void carve_records(void *scratch, int64_t cap, Records *rec, unsigned long long 
     p += P * sizeof(int32_t);
     rec->work = reinterpret_cast<int32_t *>(p);
     p += P * sizeof(int32_t);
-    rec->tail = reinterpret_cast<int32_t *>(p);
-    p += P * sizeof(int32_t);
     rec->scan_tmp = reinterpret_cast<int64_t *>(p);
     rec->cap = cap;
     // device scalars share the 256-byte block with the work counter
     rec->n_work = reinterpret_cast<int64_t *>(static_cast<char *>(scratch) + 8);
     rec->n_items = reinterpret_cast<int64_t *>(static_cast<char *>(scratch) + 16);
-    rec->n_tail = reinterpret_cast<unsigned long long *>(static_cast<char *>(scratch) + 24);
-    rec->t_drain = reinterpret_cast<unsigned long long *>(static_cast<char *>(scratch) + 32);
 }
 
 int device_cu_count()
@@ -1471,19 +1170,12 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
     if (cap_blocks > resident) cap_blocks = resident;
     const int64_t want = (2 * n_max + wg - 1) / wg;
     const int blocks = (int)(want < cap_blocks ? want : cap_blocks);
-    hipLaunchKernelGGL(k_set_counters, dim3(1), dim3(1), 0, st, job.counter, (unsigned long long)blocks * wg,
-                       job.rec.n_tail, job.rec.t_drain);
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, job.counter, (unsigned long long)blocks * wg);
     const bool prof = profiling();
     void *tok = nullptr;
     if (prof) prof_begin(kProfStep, st, &tok);
     void *args[] = {const_cast<TraceJob *>(&job)};
     hipLaunchKernel(kern, dim3(blocks), dim3(wg), args, lds, st);
-    if constexpr (sizeof(T) == 4 && std::is_same<S, float>::value && MODE == QSQ_INTERP_PAPER && !BATCH) {
-        // lines the stepping kernel parked: a quad of lanes per line
-        const void *tk = reinterpret_cast<const void *>(&k_trace_tail<MODE>);
-        const int tb = (int)((int64_t)cus * resident_blocks(tk, 256, 0));
-        hipLaunchKernel(tk, dim3(tb), dim3(256), args, 0, st);
-    }
     if (prof) prof_end(tok, st);
     int64_t lb = (2 * n_max + 255) / 256;
     int lblocks = (int)(lb < (int64_t)cus * 16 ? lb : (int64_t)cus * 16);

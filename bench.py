@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--threshold", type=float, default=0.02)
     ap.add_argument("--refine-batch", type=int, default=0, help="refinement levels per device round (0: auto)")
     ap.add_argument("--hmax-cells", type=float, default=1.0, help="largest step, in grid cells")
-    ap.add_argument("--cpu-level", type=int, default=9, help="base level of the oracle's sample map")
+    ap.add_argument("--cpu-level", type=int, default=10, help="base level of the oracle's sample map (10: the whole map)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch shape")
@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--volume-level", type=int, default=8, help="volume workload: base level (2^m cells a side)")
     ap.add_argument("--learn-fields", type=int, default=320, help="learned workload: maps generated (1/4 rope slices)")
     ap.add_argument("--learn-epochs", type=int, default=12)
-    ap.add_argument("--cpu-fraction", type=float, default=0.02,
+    ap.add_argument("--cpu-fraction", type=float, default=0.25,
                     help="batch workload: fraction of each field's seeds the oracle traces")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
@@ -306,11 +306,12 @@ def bench_batch(args):
     # h_init, h_max: 0.1 and 1 cell of each field's own grid
     opts32 = make_opts(args.tol, args.tol, step_dtype="f32")
     opts64 = make_opts(args.tol, args.tol, step_dtype="f64")
+    opts32.launch = args.launch
     plan = TraceBatchPlan(sets, opts32, want_work=True)
     tuned = None
     if not args.no_tune:
         from paper_1609_00724_amd import autotune
-        cands = autotune.candidates(lanes=(2, 3, 4, 8), wgs=(128, 256), gathers=(A.GATHER_DIRECT,))
+        cands = autotune.candidates(lanes=(1, 2, 3, 4), wgs=(64, 128, 256), gathers=(A.GATHER_DIRECT,))
         word, table = autotune.tune_batch(sets, opts32, reps=1, cands=cands)
         opts32.launch = word
         tuned = dict(autotune.describe(word), ms=table[word], candidates=len(table), worst_ms=max(table.values()))
@@ -456,6 +457,15 @@ def bench_volume(args):
     spec = VolumeSpec(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0, m, r, m, args.threshold, args.refine_batch)
     plan = QMapPlan(spec, 8 ** m * 4, dev)
     opts = make_opts(args.tol, args.tol, h_init=0.1 * h, h_max=args.hmax_cells * h, step_dtype="f32")
+    opts.launch = args.launch
+    tuned = None
+    if not args.no_tune:
+        # launch shape timed on the volume itself (one map per candidate)
+        from paper_1609_00724_amd import autotune
+        cands = autotune.candidates(lanes=(1, 2, 3, 8), wgs=(128,), gathers=(A.GATHER_DIRECT, A.GATHER_CACHED))
+        word, table = autotune.tune_map(plan, f32, opts, reps=1, cands=cands)
+        opts.launch = word
+        tuned = dict(autotune.describe(word), ms=table[word], candidates=len(table), worst_ms=max(table.values()))
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         plan.run(f32, opts)
@@ -482,6 +492,7 @@ def bench_volume(args):
     plan16 = QMapPlan(spec, 8 ** m * 4, dev)
     plan16.run(bf16, opts)
     torch.cuda.synchronize()
+    plan16.work.zero_()
     b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     b0.record(stream)
     plan16.run(bf16, opts)
@@ -527,7 +538,10 @@ def bench_volume(args):
             "launches": n_step,
             "avg_launch_ms": ms_trace / max(n_step, 1),
         },
+        "launch_shape": tuned,
+        "attempts_per_step": attempts / args.steps,
         "bf16_storage": {"ms": ms16, "lines_per_s": r16["count"] / (ms16 / 1e3), "lines": r16["count"],
+                         "attempts": int(plan16.work.cpu()[0]),
                          "common_keys": int(common.size),
                          "median_rel_log10q_diff_vs_fp32_storage": float(np.median(d16)),
                          "p90": float(np.percentile(d16, 90)), "p99": float(np.percentile(d16, 99))},
@@ -835,8 +849,9 @@ def accuracy(args, field, w, h, hmax):
 
 
 def cpu_baseline(args, w, h):
-    """The oracle (FP64 C + numpy refinement) on a bounded sample: the same map
-    recipe at a coarser base level, on the host cores."""
+    """The oracle (FP64 C + numpy refinement) on the host cores: the same map
+    recipe, by default the whole map (--cpu-level picks a coarser base level
+    if that takes too long)."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
     fo = _oracle_field(w)

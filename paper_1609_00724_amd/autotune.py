@@ -17,7 +17,7 @@ import torch
 
 from . import _abi as A
 
-DEFAULT_LANES = (2, 3, 4, 6, 8, 12)
+DEFAULT_LANES = (1, 2, 3, 4, 6, 8, 12)
 DEFAULT_WG = (64, 128, 256)
 
 _cache: dict = {}

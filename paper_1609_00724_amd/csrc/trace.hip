@@ -613,6 +613,13 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
             }
         }
         if (__ballot(!done) == 0) break;
+        // issue priority among the waves of a SIMD: waves holding a line that
+        // has run many attempts go first, so the long lines that end a launch
+        // are slowed less by the short ones beside them (scheduling only)
+        if (__ballot(active && attempts >= 512)) __builtin_amdgcn_s_setprio(3);
+        else if (__ballot(active && attempts >= 256)) __builtin_amdgcn_s_setprio(2);
+        else if (__ballot(active && attempts >= 128)) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
         if (!active) continue;
 
         // ---- one step attempt (oracle order: step cap, null, trial, accept/reject, exit)

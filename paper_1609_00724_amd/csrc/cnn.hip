@@ -173,6 +173,8 @@ __global__ void __launch_bounds__(256) k_conv(const void *in, ConvDims d, const 
     f32x4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // unrolled: the taps' operand loads are independent and issue together
+#pragma unroll
     for (int kc = 0; kc < NK; ++kc) {
         bf16x8 a;
         if constexpr (CI >= 32) {
@@ -224,8 +226,12 @@ __global__ void __launch_bounds__(256) k_conv(const void *in, ConvDims d, const 
 // Weight and bias gradients of one layer: dW[tap][ci][co] = sum over pixels
 // of x[p + tap - (1,1)][ci] dy[p][co], db[co] = sum of dy[p][co].  Each wave
 // (one per block) takes whole rows, keeps all 9 x CI x CO partial sums in its
-// accumulators and writes them to its own slot; k_wgrad_reduce adds the slots
-// in wave order (deterministic).
+// accumulators and writes them to its own slot; k_wgrad_reduce1/2 add the slots
+// in a fixed order (deterministic).  The contraction runs over pixels, which
+// are strided in the NHWC activations, so each 32-pixel strip is first staged
+// in LDS channel-major: the three input rows around the output row, each in
+// three copies shifted by one pixel (every MFMA operand is then one aligned
+// 16-byte LDS read), and the output-gradient strip.
 // ---------------------------------------------------------------------------
 template <int CI, int CO, bool SRC_F32>
 __global__ void __launch_bounds__(64) k_wgrad(const void *x, const uint16_t *dy, ConvDims d, int64_t rows_per_wave,
@@ -233,10 +239,19 @@ __global__ void __launch_bounds__(64) k_wgrad(const void *x, const uint16_t *dy,
 {
     constexpr int TI = ntile(CI), TO = ntile(CO), CIP = 16 * TI, COP = 16 * TO;
     constexpr int64_t SLOT = 9 * CIP * COP + COP;
+    constexpr int GI = SRC_F32 ? 1 : CI / 8;   // loads per input pixel: 8 BF16 channels, or all CI floats
+    constexpr int GO = CO >= 8 ? CO / 8 : 1;   // loads per output-gradient pixel
+    static_assert(SRC_F32 ? CI <= 8 : CI % 8 == 0, "input channels per load");
+    static_assert(CO >= 8 ? CO % 8 == 0 : true, "output channels per load");
+    __shared__ __attribute__((aligned(16))) uint16_t xs[3][3][CIP][32];
+    __shared__ __attribute__((aligned(16))) uint16_t gs[COP][32];
     const int lane = (int)threadIdx.x, i = lane & 15, kg = lane >> 4;
     const int64_t rows = d.n * d.h;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_wave;
     const int64_t r1 = r0 + rows_per_wave < rows ? r0 + rows_per_wave : rows;
+    // padded channel rows stay zero; every real entry is rewritten per strip
+    for (int e = lane; e < 9 * CIP * 32; e += 64) (&xs[0][0][0][0])[e] = 0;
+    for (int e = lane; e < COP * 32; e += 64) (&gs[0][0])[e] = 0;
     f32x4 acc[9][TI][TO];
 #pragma unroll
     for (int tp = 0; tp < 9; ++tp)
@@ -251,17 +266,56 @@ __global__ void __launch_bounds__(64) k_wgrad(const void *x, const uint16_t *dy,
         const int y = (int)(row % d.h);
         const int64_t img = row / d.h;
         for (int p0 = 0; p0 < d.w; p0 += 32) {
+            __syncthreads();   // the previous strip's reads are done
+            // input rows y-1..y+1, pixels p0-1 .. p0+32
+            for (int e = lane; e < 3 * 34 * GI; e += 64) {
+                const int r = e / (34 * GI), j = (e / GI) % 34, g = e % GI;
+                const int yy = y + r - 1, xx = p0 - 1 + j;
+                const bool in = yy >= 0 && yy < d.h && xx >= 0 && xx < d.w;
+                const int64_t pix = (img * d.h + yy) * d.w + xx;
+                uint16_t v[8];
+                if constexpr (SRC_F32) {
+#pragma unroll
+                    for (int c = 0; c < CI; ++c) v[c] = in ? f2bf(static_cast<const float *>(x)[pix * CI + c]) : 0;
+                } else {
+                    uint4 q = make_uint4(0, 0, 0, 0);
+                    if (in) q = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(x) + pix * CI + 8 * g);
+                    const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) v[c] = (uint16_t)(w4[c >> 1] >> (16 * (c & 1)));
+                }
+                constexpr int NC = SRC_F32 ? CI : 8;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const int ci = SRC_F32 ? c : 8 * g + c;
+#pragma unroll
+                    for (int sft = 0; sft < 3; ++sft) {
+                        const int k = j - sft;
+                        if (k >= 0 && k < 32) xs[r][sft][ci][k] = v[c];
+                    }
+                }
+            }
+            // output-gradient strip, pixels p0 .. p0+31
+            for (int e = lane; e < 32 * GO; e += 64) {
+                const int k = e / GO, g = e % GO;
+                const int64_t pix = (img * d.h + y) * d.w + p0 + k;
+                if constexpr (CO >= 8) {
+                    const uint4 q = *reinterpret_cast<const uint4 *>(dy + pix * CO + 8 * g);
+                    const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) gs[8 * g + c][k] = (uint16_t)(w4[c >> 1] >> (16 * (c & 1)));
+                } else {
+#pragma unroll
+                    for (int c = 0; c < CO; ++c) gs[c][k] = dy[pix * CO + c];
+                }
+            }
+            __syncthreads();
             bf16x8 bfr[TO];
 #pragma unroll
             for (int b = 0; b < TO; ++b) {
-                const int co = b * 16 + i;
+                bfr[b] = ld_bf16x8(&gs[b * 16 + i][8 * kg]);
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int xx = p0 + 8 * kg + j;
-                    const uint16_t v = (co < CO) ? dy[((img * d.h + y) * d.w + xx) * CO + co] : (uint16_t)0;
-                    bfr[b][j] = as_bf(v);
-                    dbs[b] += bf2f(v);
-                }
+                for (int j = 0; j < 8; ++j) dbs[b] += (float)bfr[b][j];
             }
 #pragma unroll
             for (int tp = 0; tp < 9; ++tp) {
@@ -269,18 +323,7 @@ __global__ void __launch_bounds__(64) k_wgrad(const void *x, const uint16_t *dy,
                 if (yy < 0 || yy >= d.h) continue;            // uniform over the wave
 #pragma unroll
                 for (int a = 0; a < TI; ++a) {
-                    const int ci = a * 16 + i;
-                    bf16x8 afr;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const int xx = p0 + 8 * kg + j + tp % 3 - 1;
-                        uint16_t v = 0;
-                        if (ci < CI && xx >= 0 && xx < d.w) {
-                            const int64_t e = ((img * d.h + yy) * d.w + xx) * CI + ci;
-                            v = SRC_F32 ? f2bf(static_cast<const float *>(x)[e]) : static_cast<const uint16_t *>(x)[e];
-                        }
-                        afr[j] = as_bf(v);
-                    }
+                    const bf16x8 afr = ld_bf16x8(&xs[tp / 3][tp % 3][a * 16 + i][8 * kg]);
 #pragma unroll
                     for (int b = 0; b < TO; ++b) acc[tp][a][b] = mfma(afr, bfr[b], acc[tp][a][b]);
                 }
@@ -300,33 +343,56 @@ __global__ void __launch_bounds__(64) k_wgrad(const void *x, const uint16_t *dy,
                     slot[((int64_t)tp * CIP + a * 16 + 4 * kg + r) * COP + b * 16 + i] = acc[tp][a][b][r];
 #pragma unroll
     for (int b = 0; b < TO; ++b) {
-        float s = dbs[b];
-        s += __shfl_xor(s, 16);
-        s += __shfl_xor(s, 32);
-        if (kg == 0) slot[9 * CIP * COP + b * 16 + i] = s;
+        float sb = dbs[b];
+        sb += __shfl_xor(sb, 16);
+        sb += __shfl_xor(sb, 32);
+        if (kg == 0) slot[9 * CIP * COP + b * 16 + i] = sb;
     }
 }
 
+// Slot sums in two fixed-order stages (deterministic for a given slot count):
+// groups of kRedGroup consecutive slots, then the groups in order.
+constexpr int kRedGroup = 32;
+
 template <int CI, int CO>
-__global__ void k_wgrad_reduce(const float *part, int64_t nslots, float *dw, float *db)
+__device__ __forceinline__ int64_t wgrad_src(int64_t e)
 {
     constexpr int CIP = 16 * ntile(CI), COP = 16 * ntile(CO);
-    constexpr int64_t SLOT = 9 * CIP * COP + COP;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= 9 * CI * CO + CO) return;
-    int64_t src;
     if (e < 9 * CI * CO) {
         const int co = (int)(e % CO), ci = (int)((e / CO) % CI), tp = (int)(e / (CO * CI));
-        src = ((int64_t)tp * CIP + ci) * COP + co;
-    } else {
-        src = 9 * CIP * COP + (e - 9 * CI * CO);
+        return ((int64_t)tp * CIP + ci) * COP + co;
     }
-    float s = 0.0f;
-    for (int64_t w = 0; w < nslots; ++w) s += part[w * SLOT + src];
+    return (int64_t)9 * CIP * COP + (e - 9 * CI * CO);
+}
+
+// grid (outputs / 256, slot groups): tmp[group][e] = sum of its slots
+template <int CI, int CO>
+__global__ void k_wgrad_reduce1(const float *part, int64_t nslots, float *tmp)
+{
+    constexpr int CIP = 16 * ntile(CI), COP = 16 * ntile(CO);
+    constexpr int64_t SLOT = 9 * CIP * COP + COP, NOUT = 9 * CI * CO + CO;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= NOUT) return;
+    const int64_t src = wgrad_src<CI, CO>(e);
+    const int64_t w0 = (int64_t)blockIdx.y * kRedGroup;
+    const int64_t w1 = w0 + kRedGroup < nslots ? w0 + kRedGroup : nslots;
+    float acc = 0.0f;
+    for (int64_t w = w0; w < w1; ++w) acc += part[w * SLOT + src];
+    tmp[(int64_t)blockIdx.y * NOUT + e] = acc;
+}
+
+template <int CI, int CO>
+__global__ void k_wgrad_reduce2(const float *tmp, int64_t ngroups, float *dw, float *db)
+{
+    constexpr int64_t NOUT = 9 * CI * CO + CO;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= NOUT) return;
+    float acc = 0.0f;
+    for (int64_t k = 0; k < ngroups; ++k) acc += tmp[k * NOUT + e];
     if (e < 9 * CI * CO)
-        dw[e] = s;
+        dw[e] = acc;
     else
-        db[e - 9 * CI * CO] = s;
+        db[e - 9 * CI * CO] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -359,12 +425,19 @@ __global__ void __launch_bounds__(256) k_loss(const float *out, const float *mas
     if (threadIdx.x == 0) part[blockIdx.x] = red[0] * invP;
 }
 
-__global__ void k_sum_parts(const double *part, int n, double *out)
+// one block of 256 threads: strided partial sums, then a fixed-order tree
+__global__ void __launch_bounds__(256) k_sum_parts(const double *part, int n, double *out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double s = 0.0;
-    for (int k = 0; k < n; ++k) s += part[k];
-    *out = s;
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int k = (int)threadIdx.x; k < n; k += 256) acc += part[k];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
 }
 
 // Adam (Kingma & Ba 2015) on the FP32 master parameters
@@ -439,30 +512,41 @@ static void conv_launch(int l, bool transposed, const void *in, ConvDims d, cons
 // waves of the weight-gradient pass and its partial-sum slots
 static int64_t wgrad_waves(ConvDims d) { return d.n * d.h < 1024 ? d.n * d.h : 1024; }
 
+// per-wave partial slots, then the first-stage group sums
+static int64_t wgrad_groups(ConvDims d) { return (wgrad_waves(d) + kRedGroup - 1) / kRedGroup; }
+
 uint64_t cnn_wgrad_scratch_bytes(int64_t n, int h, int w)
 {
     ConvDims d{n, h, w};
     const int64_t slot = 9 * 32 * 32 + 32;
-    return (uint64_t)wgrad_waves(d) * slot * 4;
+    return (uint64_t)wgrad_waves(d) * slot * 4 + (uint64_t)wgrad_groups(d) * slot * 4;
+}
+
+template <int CI, int CO, bool SRC_F32>
+static void wgrad_typed(const void *x, const uint16_t *dy, ConvDims d, float *part, float *dw, float *db,
+                        hipStream_t st)
+{
+    const int64_t waves = wgrad_waves(d), rows = d.n * d.h;
+    const int64_t rpw = (rows + waves - 1) / waves;
+    const int64_t used = (rows + rpw - 1) / rpw;
+    const int64_t nout = 9 * CI * CO + CO;
+    const int64_t groups = (used + kRedGroup - 1) / kRedGroup;
+    float *tmp = part + wgrad_waves(d) * (int64_t)(9 * 32 * 32 + 32);
+    hipLaunchKernelGGL((k_wgrad<CI, CO, SRC_F32>), dim3(used), dim3(64), 0, st, x, dy, d, rpw, part);
+    hipLaunchKernelGGL((k_wgrad_reduce1<CI, CO>), dim3(blocks_for(nout, 256), groups), dim3(256), 0, st, part, used,
+                       tmp);
+    hipLaunchKernelGGL((k_wgrad_reduce2<CI, CO>), dim3(blocks_for(nout, 256)), dim3(256), 0, st, tmp, groups, dw, db);
 }
 
 static void wgrad_launch(int l, const void *x, const uint16_t *dy, ConvDims d, float *part, float *dw, float *db,
                          hipStream_t st)
 {
-    const int64_t waves = wgrad_waves(d), rows = d.n * d.h;
-    const int64_t rpw = (rows + waves - 1) / waves;
-    const int64_t used = (rows + rpw - 1) / rpw;
-    const int64_t nout = 9 * kCi[l] * kCo[l] + kCo[l];
-    if (l == 0) {
-        hipLaunchKernelGGL((k_wgrad<3, 32, true>), dim3(used), dim3(64), 0, st, x, dy, d, rpw, part);
-        hipLaunchKernelGGL((k_wgrad_reduce<3, 32>), dim3(blocks_for(nout, 256)), dim3(256), 0, st, part, used, dw, db);
-    } else if (l == 3) {
-        hipLaunchKernelGGL((k_wgrad<32, 2, false>), dim3(used), dim3(64), 0, st, x, dy, d, rpw, part);
-        hipLaunchKernelGGL((k_wgrad_reduce<32, 2>), dim3(blocks_for(nout, 256)), dim3(256), 0, st, part, used, dw, db);
-    } else {
-        hipLaunchKernelGGL((k_wgrad<32, 32, false>), dim3(used), dim3(64), 0, st, x, dy, d, rpw, part);
-        hipLaunchKernelGGL((k_wgrad_reduce<32, 32>), dim3(blocks_for(nout, 256)), dim3(256), 0, st, part, used, dw, db);
-    }
+    if (l == 0)
+        wgrad_typed<3, 32, true>(x, dy, d, part, dw, db, st);
+    else if (l == 3)
+        wgrad_typed<32, 2, false>(x, dy, d, part, dw, db, st);
+    else
+        wgrad_typed<32, 32, false>(x, dy, d, part, dw, db, st);
 }
 
 hipError_t cnn_layer_forward(int l, const void *prep, const void *in, int64_t n, int h, int w, float *out_f32,
@@ -543,7 +627,7 @@ hipError_t cnn_train_step(float *params, float *adam_m, float *adam_v, int64_t t
     if (e != hipSuccess) return e;
     const int lb = (int)(blocks_for(P, 256) < kLossBlocks ? blocks_for(P, 256) : kLossBlocks);
     hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, st, s.out, mask, logq, P, lam, s.gout, s.lpart);
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1), 0, st, s.lpart, lb, loss_out ? loss_out : s.loss);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, s.lpart, lb, loss_out ? loss_out : s.loss);
     float *g = grad_out ? grad_out : s.grad;
     // layer 4 .. 1: weight gradients, then the input gradient masked by the
     // ReLU of the layer below (its BF16 activation > 0)

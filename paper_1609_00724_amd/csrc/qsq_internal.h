@@ -58,6 +58,7 @@ struct Records {
     int64_t *scan_tmp;  // block sums of the scan
     int64_t *n_work;    // device scalar: work items
     int64_t *n_items;   // device scalar: half-lines of the call (2 n)
+    int64_t *n_land;    // device scalar: half-lines the landing pass takes (listed in work)
 };
 
 // One seed set of a batched trace: its own field, seeds, per-grid step

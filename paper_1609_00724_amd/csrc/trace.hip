@@ -502,6 +502,16 @@ __global__ void k_compact(TraceJob job)
         if (job.rec.flag[it]) job.rec.work[job.rec.wpos[it]] = (int32_t)(it >= n ? job.rec.cap + (it - n) : it);
 }
 
+// flags of the half-lines the stepping pass left outside the box (to land)
+__global__ void k_land_flags(TraceJob job)
+{
+    const int64_t n2 = *job.rec.n_items, n = n2 / 2;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n2; it += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = it >= n ? job.rec.cap + (it - n) : it;
+        job.rec.flag[it] = job.rec.status[r] == kPendingLand ? 1 : 0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_trace: persistent stepping kernel
 // ---------------------------------------------------------------------------
@@ -821,6 +831,20 @@ __device__ void ck54_fp64(const S *__restrict__ nodes, const Geom &g, double sig
         yo[i] = y[i] + hs * (ck::b1 * K[0][i] + ck::b3 * K[2][i] + ck::b4 * K[3][i] + ck::b6 * K[5][i]);
 }
 
+// v[d] for a run-time d in 0..2 as selects (a dynamic index would put the
+// array in scratch memory)
+__device__ __forceinline__ double pick3(const double *v, int d)
+{
+    return d == 0 ? v[0] : (d == 1 ? v[1] : v[2]);
+}
+
+// signed distance of x beyond face f (0..5 = x lo, x hi, y lo, ...): > 0 outside
+__device__ __forceinline__ double beyond_face(const Geom &g, const double *x, int f)
+{
+    const int d = f >> 1;
+    return (f & 1) ? pick3(x, d) - pick3(g.hi, d) : pick3(g.lo, d) - pick3(x, d);
+}
+
 template <typename S, int MODE>
 __device__ double face_gap(const S *nodes, const Geom &g, double sigma, const double y[9], double hs,
                            int f, double yo[9])
@@ -831,8 +855,7 @@ __device__ double face_gap(const S *nodes, const Geom &g, double sigma, const do
     } else {
         ck54_fp64<S, MODE>(nodes, g, sigma, y, hs, yo);
     }
-    const int d = f >> 1;
-    return (f & 1) ? yo[d] - g.hi[d] : g.lo[d] - yo[d];
+    return beyond_face(g, yo, f);
 }
 
 // ---------------------------------------------------------------------------
@@ -841,13 +864,14 @@ __device__ double face_gap(const S *nodes, const Geom &g, double sigma, const do
 template <typename S, int MODE, bool BATCH>
 __global__ void __launch_bounds__(256) k_land(TraceJob job)
 {
-    const int64_t n = seed_count(job);
-    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < 2 * n;
+    // the list of half-lines to land (compacted after the stepping pass), so
+    // that every lane of a wave has one
+    const int64_t total = *job.rec.n_land;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
          it += (int64_t)gridDim.x * blockDim.x) {
-        const int dir = it >= n ? 1 : 0;
-        const int64_t i = dir ? it - n : it;
-        const int64_t r = dir * job.rec.cap + i;
-        if (job.rec.status[r] != kPendingLand) continue;
+        const int64_t r = job.rec.work[it];
+        const int dir = r >= job.rec.cap ? 1 : 0;
+        const int64_t i = dir ? r - job.rec.cap : r;
         const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
         Geom gl = job.g;
         double gtol = job.o.gtol;
@@ -864,11 +888,14 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
         ck54_fp64<S, MODE>(nodes, g, sigma, y, hs, y5);
         double best = INFINITY;
         int face = -1;
+        // end state of the converged trial for the best face (the step at the
+        // root is not taken again)
+        double ybest[9];
+        bool have_best = false;
         double gmax = -INFINITY;
         int fmax_ = 0;
         for (int f = 0; f < 6; ++f) {
-            const int d = f >> 1;
-            const double gend = (f & 1) ? y5[d] - g.hi[d] : g.lo[d] - y5[d];
+            const double gend = beyond_face(g, y5, f);
             if (gend > gmax) {
                 gmax = gend;
                 fmax_ = f;
@@ -879,6 +906,7 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
             double a = 0.0, b = hs;
             double ga = face_gap<S, MODE>(nodes, g, sigma, y, a, f, yo);
             double hf;
+            bool conv = false;
             if (ga >= 0.0) {
                 hf = 0.0;
             } else {
@@ -890,6 +918,7 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
                     const double gc = face_gap<S, MODE>(nodes, g, sigma, y, c, f, yo);
                     if (fabs(gc) <= gtol) {
                         hf = c;
+                        conv = true;
                         break;
                     }
                     if (gc > 0.0) {
@@ -910,6 +939,11 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
             if (hf < best) {
                 best = hf;
                 face = f;
+                have_best = conv;
+                if (conv) {
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) ybest[k] = yo[k];
+                }
             }
         }
         double yl[9];
@@ -919,13 +953,19 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
             face = fmax_;
             best = hs;
             for (int i = 0; i < 9; ++i) yl[i] = y5[i];
+        } else if (best > 0.0 && have_best) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) yl[k] = ybest[k];
         } else if (best > 0.0) {
             ck54_fp64<S, MODE>(nodes, g, sigma, y, best, yl);
         } else {
             for (int i = 0; i < 9; ++i) yl[i] = y[i];
         }
         const int d = face >> 1;
-        yl[d] = (face & 1) ? g.hi[d] : g.lo[d];
+        const double snap = (face & 1) ? pick3(g.hi, d) : pick3(g.lo, d);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (k == d) yl[k] = snap;
         const int att = job.rec.attempts[r];
         put_rec(job.rec, r, yl, s + best, 0.0, face, att);
     }
@@ -1096,6 +1136,7 @@ void carve_records(void *scratch, int64_t cap, Records *rec, unsigned long long 
     // device scalars share the 256-byte block with the work counter
     rec->n_work = reinterpret_cast<int64_t *>(static_cast<char *>(scratch) + 8);
     rec->n_items = reinterpret_cast<int64_t *>(static_cast<char *>(scratch) + 16);
+    rec->n_land = reinterpret_cast<int64_t *>(static_cast<char *>(scratch) + 24);
 }
 
 int device_cu_count()
@@ -1187,6 +1228,10 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
     int64_t lb = (2 * n_max + 255) / 256;
     int lblocks = (int)(lb < (int64_t)cus * 16 ? lb : (int64_t)cus * 16);
     if (prof) prof_begin(kProfLand, st, &tok);
+    // list of the half-lines to land (the work list is free again)
+    hipLaunchKernelGGL(k_land_flags, dim3(cblocks), dim3(256), 0, st, job);
+    launch_scan_i32(job.rec.flag, job.rec.n_items, 2 * n_max, job.rec.scan_tmp, job.rec.wpos, job.rec.n_land, st);
+    hipLaunchKernelGGL(k_compact, dim3(cblocks), dim3(256), 0, st, job);
     hipLaunchKernelGGL((k_land<S, MODE, BATCH>), dim3(lblocks), dim3(256), 0, st, job);
     if (prof) prof_end(tok, st);
     int64_t ab = (n_max + 255) / 256;

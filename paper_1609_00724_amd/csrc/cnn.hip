@@ -146,46 +146,81 @@ __global__ void k_prepare(const float *params, uint16_t *prep)
 }
 
 // ---------------------------------------------------------------------------
-// 3x3 'same' convolution, one wave per 16-pixel strip of a row, all output
-// channels.  in: BF16 (32 channels) or, for CI < 32, FP32 / BF16 with CI
-// channels.  Outputs (each nullable): BF16 activations (ReLU applied),
-// FP32 values, and a BF16 copy masked by act_mask > 0 (input gradients).
+// 3x3 'same' convolution, one wave per 16-pixel strip of kConvRows rows, all
+// output channels.  The wave keeps the weight operands in registers for its
+// rows and, for 32-channel inputs, a sliding window of the input operands
+// (three rows x three pixel shifts: each new output row loads one new input
+// row).  in: BF16 (32 channels) or, for CI < 32, FP32 / BF16 with CI
+// channels.  Outputs (each nullable): BF16 activations (ReLU applied), FP32
+// values, and a BF16 copy masked by act_mask > 0 (input gradients).
 // ---------------------------------------------------------------------------
 struct ConvDims {
     int64_t n;
     int h, w;
 };
 
+constexpr int kConvRows = 4;   // divides h (a multiple of 32)
+
 template <int CI, int CO, bool SRC_F32>
 __global__ void __launch_bounds__(256) k_conv(const void *in, ConvDims d, const uint16_t *wm, const float *bias,
                                               bool relu, uint16_t *out_bf, float *out_f32, uint16_t *out_masked,
                                               const uint16_t *act_mask)
 {
-    constexpr int NT = ntile(CO), COP = 16 * NT, NK = nchunk(CI);
+    constexpr int NT = ntile(CO), COP = 16 * NT, NK = nchunk(CI), R = kConvRows;
     const int lane = (int)(threadIdx.x & 63);
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int spr = d.w / 16;
-    if (wave >= d.n * d.h * spr) return;   // the whole wave leaves together
-    const int64_t row = wave / spr;        // image * h + y
-    const int x0 = (int)(wave % spr) * 16, y = (int)(row % d.h);
-    const int64_t img = row / d.h;
+    const int spr = d.w / 16, rb = d.h / R;
+    if (wave >= d.n * rb * spr) return;   // the whole wave leaves together
+    const int64_t blk = wave / spr;       // image * rb + row block
+    const int x0 = (int)(wave % spr) * 16, y0 = (int)(blk % rb) * R;
+    const int64_t img = blk / rb;
     const int i = lane & 15, kg = lane >> 4;
-    f32x4 acc[NT];
+    bf16x8 bw[NK][NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // unrolled: the taps' operand loads are independent and issue together
+    for (int kc = 0; kc < NK; ++kc)
 #pragma unroll
-    for (int kc = 0; kc < NK; ++kc) {
+        for (int t = 0; t < NT; ++t) bw[kc][t] = ld_bf16x8(wm + ((int64_t)(kc * COP + t * 16 + i) * 32 + 8 * kg));
+    // A operand of one input row yy at pixel shift dx (32 channels: lane i
+    // takes pixel x0 + i + dx, channels 8 kg .. 8 kg + 7)
+    auto a32 = [&](int yy, int dx) {
         bf16x8 a;
-        if constexpr (CI >= 32) {
-            const int yy = y + kc / 3 - 1, xx = x0 + i + kc % 3 - 1;
-            if (yy >= 0 && yy < d.h && xx >= 0 && xx < d.w) {
-                a = ld_bf16x8(static_cast<const uint16_t *>(in) + (((img * d.h + yy) * d.w + xx) * 32 + 8 * kg));
-            } else {
+        const int xx = x0 + i + dx;
+        if (CI >= 32 && yy >= 0 && yy < d.h && xx >= 0 && xx < d.w) {
+            a = ld_bf16x8(static_cast<const uint16_t *>(in) + (((img * d.h + yy) * d.w + xx) * 32 + 8 * kg));
+        } else {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) a[j] = as_bf(0);
+            for (int j = 0; j < 8; ++j) a[j] = as_bf(0);
+        }
+        return a;
+    };
+    bf16x8 win[3][3];   // [input row y-1, y, y+1][dx + 1]
+    if constexpr (CI >= 32) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) win[r][dx] = a32(y0 - 1 + r, dx - 1);
+    }
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+        const int y = y0 + rr;
+        f32x4 acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if constexpr (CI >= 32) {
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) win[2][dx] = a32(y + 1, dx - 1);
+#pragma unroll
+            for (int kc = 0; kc < 9; ++kc)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t] = mfma(win[kc / 3][kc % 3], bw[kc][t], acc[t]);
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                win[0][dx] = win[1][dx];
+                win[1][dx] = win[2][dx];
             }
         } else {
+            // all 9 taps of the CI input channels packed into one K chunk
+            bf16x8 a;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int k = 8 * kg + j, tap = k / CI, c = k % CI;
@@ -197,27 +232,25 @@ __global__ void __launch_bounds__(256) k_conv(const void *in, ConvDims d, const 
                 }
                 a[j] = as_bf(v);
             }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = mfma(a, bw[0][t], acc[t]);
         }
+        // lane holds D[pixel 4 kg + r][channel t 16 + i]
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const bf16x8 b = ld_bf16x8(wm + ((int64_t)(kc * COP + t * 16 + i) * 32 + 8 * kg));
-            acc[t] = mfma(a, b, acc[t]);
-        }
-    }
-    // lane holds D[pixel 4 kg + r][channel t 16 + i]
+            const int co = t * 16 + i;
+            if (co >= CO) continue;
+            const float bv = bias ? bias[co] : 0.0f;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int co = t * 16 + i;
-        if (co >= CO) continue;
-        const float bv = bias ? bias[co] : 0.0f;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            float v = acc[t][r] + bv;
-            if (relu) v = fmaxf(v, 0.0f);
-            const int64_t pix = (img * d.h + y) * d.w + x0 + 4 * kg + r;
-            if (out_f32) out_f32[pix * CO + co] = v;
-            if (out_bf) out_bf[pix * CO + co] = f2bf(v);
-            if (out_masked) out_masked[pix * CO + co] = bf2f(act_mask[pix * CO + co]) > 0.0f ? f2bf(v) : (uint16_t)0;
+            for (int r = 0; r < 4; ++r) {
+                float v = acc[t][r] + bv;
+                if (relu) v = fmaxf(v, 0.0f);
+                const int64_t pix = (img * d.h + y) * d.w + x0 + 4 * kg + r;
+                if (out_f32) out_f32[pix * CO + co] = v;
+                if (out_bf) out_bf[pix * CO + co] = f2bf(v);
+                if (out_masked)
+                    out_masked[pix * CO + co] = bf2f(act_mask[pix * CO + co]) > 0.0f ? f2bf(v) : (uint16_t)0;
+            }
         }
     }
 }
@@ -231,7 +264,8 @@ __global__ void __launch_bounds__(256) k_conv(const void *in, ConvDims d, const 
 // are strided in the NHWC activations, so each 32-pixel strip is first staged
 // in LDS channel-major: the three input rows around the output row, each in
 // three copies shifted by one pixel (every MFMA operand is then one aligned
-// 16-byte LDS read), and the output-gradient strip.
+// 16-byte LDS read), and the output-gradient strip.  A wave walks its rows
+// strip by strip, so consecutive output rows share two of their input rows.
 // ---------------------------------------------------------------------------
 template <int CI, int CO, bool SRC_F32>
 __global__ void __launch_bounds__(64) k_wgrad(const void *x, const uint16_t *dy, ConvDims d, int64_t rows_per_wave,
@@ -243,13 +277,15 @@ __global__ void __launch_bounds__(64) k_wgrad(const void *x, const uint16_t *dy,
     constexpr int GO = CO >= 8 ? CO / 8 : 1;   // loads per output-gradient pixel
     static_assert(SRC_F32 ? CI <= 8 : CI % 8 == 0, "input channels per load");
     static_assert(CO >= 8 ? CO % 8 == 0 : true, "output channels per load");
+    // xs[slot][shift][ci][k]: input row yy sits in slot yy mod 3, so moving to
+    // the next output row of the same image loads one new input row
     __shared__ __attribute__((aligned(16))) uint16_t xs[3][3][CIP][32];
     __shared__ __attribute__((aligned(16))) uint16_t gs[COP][32];
     const int lane = (int)threadIdx.x, i = lane & 15, kg = lane >> 4;
     const int64_t rows = d.n * d.h;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_wave;
     const int64_t r1 = r0 + rows_per_wave < rows ? r0 + rows_per_wave : rows;
-    // padded channel rows stay zero; every real entry is rewritten per strip
+    // padded channel rows stay zero; every real entry is rewritten when used
     for (int e = lane; e < 9 * CIP * 32; e += 64) (&xs[0][0][0][0])[e] = 0;
     for (int e = lane; e < COP * 32; e += 64) (&gs[0][0])[e] = 0;
     f32x4 acc[9][TI][TO];
@@ -262,16 +298,22 @@ __global__ void __launch_bounds__(64) k_wgrad(const void *x, const uint16_t *dy,
     float dbs[TO];
 #pragma unroll
     for (int b = 0; b < TO; ++b) dbs[b] = 0.0f;
-    for (int64_t row = r0; row < r1; ++row) {
-        const int y = (int)(row % d.h);
-        const int64_t img = row / d.h;
-        for (int p0 = 0; p0 < d.w; p0 += 32) {
-            __syncthreads();   // the previous strip's reads are done
-            // input rows y-1..y+1, pixels p0-1 .. p0+32
-            for (int e = lane; e < 3 * 34 * GI; e += 64) {
-                const int r = e / (34 * GI), j = (e / GI) % 34, g = e % GI;
+    for (int p0 = 0; p0 < d.w; p0 += 32) {
+        int64_t prev = -2;   // row whose input rows the slots hold
+        for (int64_t row = r0; row < r1; ++row) {
+            const int y = (int)(row % d.h);
+            const int64_t img = row / d.h;
+            // input rows to load: all three, or y+1 only after row - 1 of the same image
+            const bool slide = row == prev + 1 && y > 0;
+            const int first = slide ? 2 : 0;
+            prev = row;
+            __syncthreads();   // the previous row's reads are done
+            for (int e = lane; e < (3 - first) * 34 * GI; e += 64) {
+                const int r = first + e / (34 * GI), j = (e / GI) % 34, g = e % GI;
                 const int yy = y + r - 1, xx = p0 - 1 + j;
-                const bool in = yy >= 0 && yy < d.h && xx >= 0 && xx < d.w;
+                if (yy < 0 || yy >= d.h) continue;     // its taps are skipped
+                const int sl = yy % 3;
+                const bool in = xx >= 0 && xx < d.w;
                 const int64_t pix = (img * d.h + yy) * d.w + xx;
                 uint16_t v[8];
                 if constexpr (SRC_F32) {
@@ -291,7 +333,7 @@ __global__ void __launch_bounds__(64) k_wgrad(const void *x, const uint16_t *dy,
 #pragma unroll
                     for (int sft = 0; sft < 3; ++sft) {
                         const int k = j - sft;
-                        if (k >= 0 && k < 32) xs[r][sft][ci][k] = v[c];
+                        if (k >= 0 && k < 32) xs[sl][sft][ci][k] = v[c];
                     }
                 }
             }
@@ -321,9 +363,10 @@ __global__ void __launch_bounds__(64) k_wgrad(const void *x, const uint16_t *dy,
             for (int tp = 0; tp < 9; ++tp) {
                 const int yy = y + tp / 3 - 1;
                 if (yy < 0 || yy >= d.h) continue;            // uniform over the wave
+                const int sl = yy % 3;
 #pragma unroll
                 for (int a = 0; a < TI; ++a) {
-                    const bf16x8 afr = ld_bf16x8(&xs[tp / 3][tp % 3][a * 16 + i][8 * kg]);
+                    const bf16x8 afr = ld_bf16x8(&xs[sl][tp % 3][a * 16 + i][8 * kg]);
 #pragma unroll
                     for (int b = 0; b < TO; ++b) acc[tp][a][b] = mfma(afr, bfr[b], acc[tp][a][b]);
                 }
@@ -483,7 +526,7 @@ hipError_t cnn_prepare(const float *params, void *prep, hipStream_t st)
 static void conv_launch(int l, bool transposed, const void *in, ConvDims d, const void *prep, bool relu, uint16_t *out_bf,
                         float *out_f32, uint16_t *out_masked, const uint16_t *act_mask, hipStream_t st)
 {
-    const int64_t waves = d.n * d.h * (d.w / 16);
+    const int64_t waves = d.n * (d.h / kConvRows) * (d.w / 16);
     const dim3 grid(blocks_for(waves * 64, 256)), block(256);
     if (!transposed) {
         const uint16_t *wm = fwd_mat(prep, l);

@@ -783,7 +783,7 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
 // ---------------------------------------------------------------------------
 template <typename S, int MODE>
 __device__ void ck54_fp64(const S *__restrict__ nodes, const Geom &g, double sigma, const double y[9],
-                          double hs, double yo[9])
+                          double hs, double yo[9], double *slope0 = nullptr)
 {
     double K[6][9];
     const double A[6][5] = {{0, 0, 0, 0, 0},
@@ -829,6 +829,24 @@ __device__ void ck54_fp64(const S *__restrict__ nodes, const Geom &g, double sig
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         yo[i] = y[i] + hs * (ck::b1 * K[0][i] + ck::b3 * K[2][i] + ck::b4 * K[3][i] + ck::b6 * K[5][i]);
+    if (slope0) {
+        // dx/dlambda at the start of the step (the first stage)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) slope0[i] = K[0][i];
+    }
+}
+
+// First trial step length of the landing: the root in (0, hs) of the
+// quadratic with gap g0 < 0 and slope s0 at 0 and gap g1 > 0 at hs, or the
+// secant point if that root is not strictly inside.
+__device__ __forceinline__ double landing_guess(double g0, double s0, double g1, double hs)
+{
+    const double sec = -g0 * hs / (g1 - g0);
+    const double cq = (g1 - g0 - s0 * hs) / (hs * hs);
+    const double disc = s0 * s0 - 4.0 * cq * g0;
+    const double den = s0 + sqrt(fmax(disc, 0.0));
+    const double h = den > 0.0 ? -2.0 * g0 / den : -1.0;
+    return (h > 0.0 && h < hs) ? h : sec;
 }
 
 // v[d] for a run-time d in 0..2 as selects (a dynamic index would put the
@@ -883,9 +901,9 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
         }
         const Geom &g = gl;
         const double sigma = dir ? -1.0 : 1.0;
-        double y[9], s, hs, y5[9];
+        double y[9], s, hs, y5[9], v0[3];
         get_rec(job.rec, r, y, s, hs);
-        ck54_fp64<S, MODE>(nodes, g, sigma, y, hs, y5);
+        ck54_fp64<S, MODE>(nodes, g, sigma, y, hs, y5, v0);
         double best = INFINITY;
         int face = -1;
         // end state of the converged trial for the best face (the step at the
@@ -913,8 +931,13 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
                 double gb = gend;
                 int side = 0;
                 hf = -1.0;
+                // the first trial uses the gap's slope at the start of the step
+                // (a quadratic model); Illinois regula falsi from there on
+                const int dd = f >> 1;
+                const double s0 = (f & 1) ? pick3(v0, dd) : -pick3(v0, dd);
+                const double c0 = landing_guess(ga, s0, gb, hs);
                 for (int k = 0; k < 200; ++k) {
-                    const double c = (a * gb - b * ga) / (gb - ga);
+                    const double c = k == 0 ? c0 : (a * gb - b * ga) / (gb - ga);
                     const double gc = face_gap<S, MODE>(nodes, g, sigma, y, c, f, yo);
                     if (fabs(gc) <= gtol) {
                         hf = c;

@@ -220,6 +220,45 @@ def test_capacity_overflow_is_flagged(c2):
     assert np.all(np.diff(res["keys"]) > 0)
 
 
+def test_map_graph_replay_matches_eager(c2):
+    """The whole map call (base lattice, device-decided refinement rounds,
+    conversion) captured in a HIP graph: every replay, with eager work of
+    another map between the replays, reproduces the eager map bit for bit."""
+    from paper_1609_00724_amd.api import MapSpec, QMapPlan, make_opts
+    torch, dev = torch_dev()
+    opts = make_opts(TOL, TOL, h_init=0.1 * c2["h"], h_max=c2["h"], step_dtype="f32")
+    plan = QMapPlan(MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, 6, 2, 8, 0.02, 0), 4 ** 6 * 16, dev)
+    other = QMapPlan(MapSpec(0.0, -0.5, 0.5, -0.5, 0.5, 5, 1, 6, 0.02, 0), 4 ** 5 * 8, dev)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.run(c2["fg"], opts, s)
+    torch.cuda.synchronize()
+    keys = ("keys", "fll", "q_perp", "status", "q_grid", "fll_grid", "fledge")
+    first = plan.result()
+    ref = {k: first[k].clone() for k in keys}
+    count = first["count"]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        plan.run(c2["fg"], opts, s)
+    torch.cuda.synchronize()
+
+    def same(a, b):
+        if a.is_floating_point():
+            return torch.equal(torch.nan_to_num(a, nan=-7.0), torch.nan_to_num(b, nan=-7.0))
+        return torch.equal(a, b)
+
+    for _ in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        res = plan.result()
+        assert res["count"] == count
+        for k in keys:
+            assert same(res[k], ref[k]), k
+        with torch.cuda.stream(s):
+            other.run(c2["fg"], opts, s)
+        torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("step_dtype", ["f32", "f64"])
 def test_full_photospheric_map_sampled(oracle_mod, c2, step_dtype):
     """The benchmark's workload: 1024^2 base map with 4x (two-level) refinement;

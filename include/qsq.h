@@ -123,8 +123,8 @@ typedef struct qsq_trace_opts {
  *          256 lanes per compute unit, 1..15 (0: 8)
  *   wg     workgroup size code: 0 = 256, 1 = 64, 2 = 128 lanes
  *   gather 0 = automatic, 1 = direct corner loads, 2 = per-lane LDS cache of
- *          the last cell's corners (FP32 records and FP32 stepping, one field
- *          per call, field below 2 GiB; otherwise direct) */
+ *          the last cell's corners (FP32 or BF16 records and FP32 stepping,
+ *          one field per call, field below 2 GiB; otherwise direct) */
 #define QSQ_LAUNCH(lanes, wg, gather) (((lanes) & 15) | (((wg) & 3) << 4) | (((gather) & 3) << 6))
 
 /* Per-seed results (device arrays of n entries; fp_* are SoA planes 3 x n:

@@ -214,10 +214,37 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 __device__ f32x4 qsq_buffer_load16(__amdgpu_buffer_rsrc_t rsrc, int voffset, int soffset, int aux)
     __asm("llvm.amdgcn.raw.ptr.buffer.load.v4f32");
 
-// Buffer resource over the FP32 node records (gfx9 descriptor word 3).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t node_rsrc(const float *nodes, int bytes)
+// Raw buffer load of 8 bytes (one BF16 node record), same out-of-range rule.
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+__device__ i32x2 qsq_buffer_load8(__amdgpu_buffer_rsrc_t rsrc, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.raw.ptr.buffer.load.v2i32");
+
+// Buffer resource over the node records (gfx9 descriptor word 3).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t node_rsrc(const void *nodes, int bytes)
 {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(nodes), (short)0, bytes, 0x00020000);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(nodes), (short)0, bytes, 0x00020000);
+}
+
+// bytes of one node record: 4 x FP32 or 4 x BF16
+template <typename S>
+constexpr int node_bytes() { return std::is_same<S, float>::value ? 16 : 8; }
+
+// direction part (3 values, widened to FP32 exactly) of the node record at a
+// byte offset
+template <typename S>
+__device__ __forceinline__ void load_dir(__amdgpu_buffer_rsrc_t rsrc, int off, float &x, float &y, float &z)
+{
+    if constexpr (std::is_same<S, float>::value) {
+        const f32x4 v = qsq_buffer_load16(rsrc, off, 0, 0);
+        x = v.x;
+        y = v.y;
+        z = v.z;
+    } else {
+        const i32x2 v = qsq_buffer_load8(rsrc, off, 0, 0);
+        x = __uint_as_float((uint32_t)v.x << 16);
+        y = __uint_as_float((uint32_t)v.x & 0xffff0000u);
+        z = __uint_as_float((uint32_t)v.y << 16);
+    }
 }
 
 // Per-lane cache of the 8 corner records (direction part, 24 floats) of the
@@ -230,7 +257,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t node_rsrc(const float *nodes, 
 // alone, so it stays valid across the lines a lane traces.
 constexpr int kCachePlanes = 6;
 
-template <typename T, int MODE>
+template <typename T, typename S, int MODE>
 __device__ __forceinline__ T rhs_cached(__amdgpu_buffer_rsrc_t rsrc, int bytes, const Geom &g, const int ib[3],
                                         const T q[3], T sigma, const T d1[3], const T d2[3], T kx[3], T k1[3],
                                         T k2[3], int cc[3], float4 *slot, int stride)
@@ -241,15 +268,13 @@ __device__ __forceinline__ T rhs_cached(__amdgpu_buffer_rsrc_t rsrc, int bytes, 
     for (int d = 0; d < 3; ++d) cell_of(ib[d], q[d], g.n[d], c[d], t[d]);
     const bool miss = c[0] != cc[0] || c[1] != cc[1] || c[2] != cc[2];
     const int sy = g.n[0], sz = g.n[0] * g.n[1];
-    const int base = miss ? 16 * (c[2] * sz + c[1] * sy + c[0]) : bytes;
+    constexpr int NB = node_bytes<S>();
+    const int base = miss ? NB * (c[2] * sz + c[1] * sy + c[0]) : bytes;
     float w[24];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const int o = 16 * (((k & 1) ? 1 : 0) + ((k & 2) ? sy : 0) + ((k & 4) ? sz : 0));
-        const f32x4 x = qsq_buffer_load16(rsrc, base + o, 0, 0);
-        w[3 * k] = x.x;
-        w[3 * k + 1] = x.y;
-        w[3 * k + 2] = x.z;
+        const int o = NB * (((k & 1) ? 1 : 0) + ((k & 2) ? sy : 0) + ((k & 4) ? sz : 0));
+        load_dir<S>(rsrc, base + o, w[3 * k], w[3 * k + 1], w[3 * k + 2]);
     }
     if (miss) {
 #pragma unroll
@@ -331,8 +356,8 @@ __device__ __forceinline__ T err_scale(T atol, T rtol, T a, T b)
 __device__ __forceinline__ float err_ratio(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double err_ratio(double a, double b) { return a / b; }
 
-// one RHS evaluation of the stepping kernel: cached gathers (FP32 storage and
-// stepping, field below 2 GiB) or direct gathers
+// one RHS evaluation of the stepping kernel: cached gathers (FP32 or BF16
+// storage, FP32 stepping, field below 2 GiB) or direct gathers
 template <typename T, typename S, int MODE, bool CACHED>
 __device__ __forceinline__ T rhs_step(const S *__restrict__ nodes, __amdgpu_buffer_rsrc_t rsrc, int bytes,
                                       const Geom &g, const int ib[3], const T q[3], T sigma, const T d1[3],
@@ -340,7 +365,7 @@ __device__ __forceinline__ T rhs_step(const S *__restrict__ nodes, __amdgpu_buff
                                       int stride)
 {
     if constexpr (CACHED)
-        return rhs_cached<T, MODE>(rsrc, bytes, g, ib, q, sigma, d1, d2, kx, k1, k2, cc, slot, stride);
+        return rhs_cached<T, S, MODE>(rsrc, bytes, g, ib, q, sigma, d1, d2, kx, k1, k2, cc, slot, stride);
     else
         return rhs<T, S, MODE>(nodes, g, ib, q, sigma, d1, d2, kx, k1, k2);
 }
@@ -502,6 +527,62 @@ __global__ void k_compact(TraceJob job)
         if (job.rec.flag[it]) job.rec.work[job.rec.wpos[it]] = (int32_t)(it >= n ? job.rec.cap + (it - n) : it);
 }
 
+// ---------------------------------------------------------------------------
+// spatial order of the work list: a counting sort of the flagged half-lines by
+// (set, Morton index of the seed's cell at `bits` bits per axis of the set's
+// box).  Order within a bucket is arrival order; no line's arithmetic depends
+// on where it runs, so results do not change.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t spread3(uint32_t v)   // bit k of v -> bit 3k
+{
+    uint32_t r = 0;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) r |= ((v >> k) & 1u) << (3 * k);
+    return r;
+}
+
+template <bool BATCH>
+__global__ void k_bucket_count(TraceJob job, int bits)
+{
+    const int64_t n2 = *job.rec.n_items, n = n2 / 2;
+    const int64_t P = 2 * job.rec.cap;
+    const int side = 1 << bits;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n2; it += (int64_t)gridDim.x * blockDim.x) {
+        if (!job.rec.flag[it]) continue;
+        const int64_t i = it >= n ? it - n : it;
+        const int64_t r = it >= n ? job.rec.cap + i : i;
+        const Geom &g = BATCH ? job.sets[job.set_of[i]].g : job.g;
+        uint32_t c[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double u = (job.rec.y[d * P + r] - g.lo[d]) / (g.hi[d] - g.lo[d]);
+            int k = (int)(u * side);
+            k = k < 0 ? 0 : (k > side - 1 ? side - 1 : k);
+            c[d] = (uint32_t)k;
+        }
+        const int64_t set = BATCH ? job.set_of[i] : 0;
+        const int32_t b = (int32_t)((set << (3 * bits)) + (spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2)));
+        atomicAdd(&job.rec.bhist[b], 1);
+        job.rec.wpos[it] = b;
+    }
+}
+
+__global__ void k_bucket_scatter(TraceJob job)
+{
+    const int64_t n2 = *job.rec.n_items, n = n2 / 2;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n2; it += (int64_t)gridDim.x * blockDim.x) {
+        if (!job.rec.flag[it]) continue;
+        const int32_t pos = atomicAdd(&job.rec.boff[job.rec.wpos[it]], 1);
+        job.rec.work[pos] = (int32_t)(it >= n ? job.rec.cap + (it - n) : it);
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 // flags of the half-lines the stepping pass left outside the box (to land)
 __global__ void k_land_flags(TraceJob job)
 {
@@ -543,8 +624,8 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
     T ih[3] = {(T)g.ih[0], (T)g.ih[1], (T)g.ih[2]};
     unsigned long long c_att = 0, c_ev = 0, c_act = 0, c_land = 0;   // work counters
     // cached-gather state
-    const int cbytes = CACHED ? (int)((uint64_t)16 * g.n[0] * g.n[1] * g.n[2]) : 0;
-    const __amdgpu_buffer_rsrc_t rsrc = node_rsrc(reinterpret_cast<const float *>(job.nodes), cbytes);
+    const int cbytes = CACHED ? (int)((uint64_t)node_bytes<S>() * g.n[0] * g.n[1] * g.n[2]) : 0;
+    const __amdgpu_buffer_rsrc_t rsrc = node_rsrc(job.nodes, cbytes);
     int cache_cell[3] = {-1, -1, -1};
     // LDS cell cache: kCachePlanes planes of blockDim.x float4 (dynamic size)
     extern __shared__ float4 lds_cache[];
@@ -1125,10 +1206,27 @@ __global__ void k_set_u64(unsigned long long *p, unsigned long long v) { *p = v;
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+int64_t bucket_cap(int64_t cap)
+{
+    int64_t b = 4096;
+    while (b < cap / 2 && b < ((int64_t)1 << 21)) b *= 2;
+    return b;
+}
+
+int spatial_bits_for(int64_t cap, int nsets)
+{
+    const int64_t nb = bucket_cap(cap);
+    for (int bits = 5; bits >= 1; --bits)
+        if ((int64_t)(nsets > 0 ? nsets : 1) << (3 * bits) <= nb) return bits;
+    return 0;
+}
+
 uint64_t records_bytes(int64_t cap)
 {
-    const uint64_t P = 2 * (uint64_t)cap;
-    return P * (11 * sizeof(double) + 5 * sizeof(int32_t)) + (uint64_t)scan_tmp_words((int64_t)P) * 8;
+    const uint64_t P = 2 * (uint64_t)cap, NB = (uint64_t)bucket_cap(cap);
+    const uint64_t scan_n = P > NB ? P : NB;
+    return P * (11 * sizeof(double) + 5 * sizeof(int32_t)) + 2 * NB * sizeof(int32_t) +
+           (uint64_t)scan_tmp_words((int64_t)scan_n) * 8;
 }
 
 void carve_records(void *scratch, int64_t cap, Records *rec, unsigned long long **counter)
@@ -1154,12 +1252,18 @@ void carve_records(void *scratch, int64_t cap, Records *rec, unsigned long long 
     p += P * sizeof(int32_t);
     rec->work = reinterpret_cast<int32_t *>(p);
     p += P * sizeof(int32_t);
+    const uint64_t NB = (uint64_t)bucket_cap(cap);
+    rec->bhist = reinterpret_cast<int32_t *>(p);
+    p += NB * sizeof(int32_t);
+    rec->boff = reinterpret_cast<int32_t *>(p);
+    p += NB * sizeof(int32_t);
     rec->scan_tmp = reinterpret_cast<int64_t *>(p);
     rec->cap = cap;
     // device scalars share the 256-byte block with the work counter
     rec->n_work = reinterpret_cast<int64_t *>(static_cast<char *>(scratch) + 8);
     rec->n_items = reinterpret_cast<int64_t *>(static_cast<char *>(scratch) + 16);
     rec->n_land = reinterpret_cast<int64_t *>(static_cast<char *>(scratch) + 24);
+    rec->n_buckets = reinterpret_cast<int64_t *>(static_cast<char *>(scratch) + 32);
 }
 
 int device_cu_count()
@@ -1207,10 +1311,24 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
     int64_t sb = (n_max + 255) / 256;
     const int sblocks = (int)(sb < (int64_t)cus * 16 ? sb : (int64_t)cus * 16);
     hipLaunchKernelGGL((k_seed_pass<S, MODE, BATCH>), dim3(sblocks), dim3(256), 0, st, job);
-    launch_scan_i32(job.rec.flag, job.rec.n_items, 2 * n_max, job.rec.scan_tmp, job.rec.wpos, job.rec.n_work, st);
     int64_t cb = (2 * n_max + 255) / 256;
     const int cblocks = (int)(cb < (int64_t)cus * 16 ? cb : (int64_t)cus * 16);
-    hipLaunchKernelGGL(k_compact, dim3(cblocks), dim3(256), 0, st, job);
+    if (job.spatial_bits > 0) {
+        // work list in spatial buckets: count, offsets (their total is the
+        // work count), scatter
+        const int bits = job.spatial_bits;
+        const int64_t nb = (int64_t)(BATCH ? job.nsets : 1) << (3 * bits);
+        hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, reinterpret_cast<unsigned long long *>(job.rec.n_buckets),
+                           (unsigned long long)nb);
+        const int fb = (int)(((nb + 255) / 256) < (int64_t)cus * 16 ? (nb + 255) / 256 : (int64_t)cus * 16);
+        hipLaunchKernelGGL(k_fill_i32, dim3(fb), dim3(256), 0, st, job.rec.bhist, nb, 0);
+        hipLaunchKernelGGL((k_bucket_count<BATCH>), dim3(cblocks), dim3(256), 0, st, job, bits);
+        launch_scan_i32(job.rec.bhist, job.rec.n_buckets, nb, job.rec.scan_tmp, job.rec.boff, job.rec.n_work, st);
+        hipLaunchKernelGGL(k_bucket_scatter, dim3(cblocks), dim3(256), 0, st, job);
+    } else {
+        launch_scan_i32(job.rec.flag, job.rec.n_items, 2 * n_max, job.rec.scan_tmp, job.rec.wpos, job.rec.n_work, st);
+        hipLaunchKernelGGL(k_compact, dim3(cblocks), dim3(256), 0, st, job);
+    }
     // launch shape (QSQ_LAUNCH word): workgroup size and a resident-lane
     // target per CU, capped by what the kernel's registers and LDS let stay
     // resident, so that every workgroup of the persistent launch runs from the
@@ -1222,10 +1340,10 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
     size_t lds = 0;
     if constexpr (BATCH) {
         kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, false, true>);
-    } else if constexpr (sizeof(T) == 4 && std::is_same<S, float>::value) {
-        // cached gathers (FP32 records and stepping) address the node records
-        // with 32-bit byte offsets
-        const uint64_t field_bytes = (uint64_t)16 * job.g.n[0] * job.g.n[1] * job.g.n[2];
+    } else if constexpr (sizeof(T) == 4 && (std::is_same<S, float>::value || std::is_same<S, Bf16>::value)) {
+        // cached gathers (FP32 or BF16 records, FP32 stepping) address the
+        // node records with 32-bit byte offsets
+        const uint64_t field_bytes = (uint64_t)node_bytes<S>() * job.g.n[0] * job.g.n[1] * job.g.n[2];
         if (gather != 1 && field_bytes < ((uint64_t)1 << 31) - ((uint64_t)1 << 26)) {
             kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, true, false>);
             lds = kCachePlanes * wg * sizeof(float4);

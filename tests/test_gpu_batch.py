@@ -140,11 +140,12 @@ def test_batch_graph_replay():
     assert q.lib.qsq_abi_version() == 2
 
 
-def test_launch_shapes_give_identical_results():
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_launch_shapes_give_identical_results(storage):
     """The launch shape (lanes per CU, workgroup size) moves no result: every
     line's arithmetic is the same wherever it runs.  The two gather variants
     (direct loads, LDS cell cache) read the same node values; they must agree
-    line by line within the FP32 gates."""
+    line by line within the FP32 gates.  FP32 and BF16 node records."""
     import torch
 
     import paper_1609_00724_amd as q
@@ -153,7 +154,7 @@ def test_launch_shapes_give_identical_results():
     from paper_1609_00724_amd.api import TracePlan, make_opts
     dev = torch.device("cuda:0")
     f = _sets(1, np.float32, empty=())[0]
-    fg = gpu_field(f["b"], f["origin"], f["spacing"], storage="f32")
+    fg = gpu_field(f["b"], f["origin"], f["spacing"], storage=storage)
     seeds = torch.from_numpy(synth.random_seeds(77, 5000)).to(dev).t().contiguous()
     plan = TracePlan(seeds.shape[1], dev, want_steps=True)
     res = {}

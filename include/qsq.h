@@ -186,8 +186,10 @@ uint64_t qsq_trace_scratch_bytes(int64_t n);
  * with eq. (1) and eq. (5) forwards and backwards (Cash-Karp 5(4) with
  * adaptive steps) until the box is left (landing exactly on the face crossed
  * first), max_length, max_steps, a null or a non-finite state; then Q by
- * eq. (10)-(11).  scratch: device, >= qsq_trace_scratch_bytes(n), 256-byte
- * aligned.  n = 0 enqueues nothing and succeeds.  Errors: INVALID_ARG,
+ * eq. (10)-(11).  The half-lines are stepped in spatial order (sorted by the
+ * Morton index of their seed's cell; outputs stay in seed order and do not
+ * depend on that order).  scratch: device, >= qsq_trace_scratch_bytes(n),
+ * 256-byte aligned.  n = 0 enqueues nothing and succeeds.  Errors: INVALID_ARG,
  * UNSUPPORTED, WORKSPACE_TOO_SMALL, COUNT_OVERFLOW (n > 2^30), HIP.
  */
 int qsq_trace(const qsq_field *f, const double *seeds, int64_t n, const qsq_trace_opts *opts,
@@ -215,6 +217,8 @@ uint64_t qsq_trace_batch_scratch_bytes(int32_t nsets, int64_t total);
  * computation as qsq_trace (Sect. 3.1-3.5, eq. (1), (5), (9)-(11)), with the
  * half-lines of all sets served from one work list to one persistent stepping
  * launch, so that sets of uneven size and line length share the device.
+ * The work list is sorted by (set, Morton index of the seed's cell) so that
+ * neighbouring lanes trace neighbouring lines; outputs stay in seed order.
  * sets: host array of nsets entries (1 <= nsets <= QSQ_MAX_TRACE_SETS), read
  * during the call only.  opts applies to every set, except that h_init <= 0
  * and h_max <= 0 select 0.1 and 1 times each set's own smallest spacing.

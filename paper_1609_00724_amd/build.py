@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqsq.so")
 
-SOURCES = ["trace.hip", "field.hip", "maps.hip", "cnn.hip", "qsq_abi.cpp"]
+SOURCES = ["trace.hip", "field.hip", "maps.hip", "cnn.hip", "sort.hip", "qsq_abi.cpp"]
 ARCH = os.environ.get("QSQ_OFFLOAD_ARCH", "gfx950")
 
 

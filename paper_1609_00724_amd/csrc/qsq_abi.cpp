@@ -287,7 +287,7 @@ int qsq_trace(const qsq_field *f, const double *seeds, int64_t n, const qsq_trac
     job.n_host = n;
     job.n_dev = nullptr;
     qsq::carve_records(scratch, n, &job.rec, &job.counter);
-    job.spatial_bits = qsq::spatial_bits_for(n, 1);
+    job.spatial_bits = qsq::spatial_bits_for(1);
     job.fp_fwd = out->fp_fwd;
     job.fp_bwd = out->fp_bwd;
     job.fll = out->fll;
@@ -386,7 +386,7 @@ int qsq_trace_batch(const qsq_trace_set *sets, int32_t nsets, const qsq_trace_op
     p += round256((uint64_t)total * sizeof(int32_t));
     job.sets = reinterpret_cast<const qsq::SetDesc *>(p);
     job.nsets = nsets;
-    job.spatial_bits = qsq::spatial_bits_for(total, nsets);
+    job.spatial_bits = qsq::spatial_bits_for(nsets);
     job.work = reinterpret_cast<unsigned long long *>(work);
     hipError_t e = qsq::launch_trace_batch(job, table.data(), nsets, opts->step_dtype, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "qsq_trace_batch");

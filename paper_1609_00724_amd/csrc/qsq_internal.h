@@ -59,9 +59,9 @@ struct Records {
     int64_t *n_work;    // device scalar: work items
     int64_t *n_items;   // device scalar: half-lines of the call (2 n)
     int64_t *n_land;    // device scalar: half-lines the landing pass takes (listed in work)
-    int32_t *bhist;     // spatial buckets of the work list: counts (bucket_cap entries)
-    int32_t *boff;      // spatial buckets: running offsets
-    int64_t *n_buckets; // device scalar: buckets in use
+    int32_t *work2;     // 2*cap: second buffer of the work-list sort
+    int32_t *scnt;      // digit counts of the work-list sort (sort_count_words(2 cap))
+    int64_t *n_sort;    // device scalars of the sort: count entries, item total
 };
 
 // One seed set of a batched trace: its own field, seeds, per-grid step
@@ -100,10 +100,10 @@ struct TraceJob {
     const SetDesc *sets;
     int32_t *set_of;
     int nsets;
-    // > 0: the work list is grouped into spatial buckets (per set, the Morton
-    // order of the seed's cell at this many bits per axis of the set's box)
-    // before stepping, so that the lanes of a wave trace nearby lines; 0: seed
-    // order (maps, whose seeds already follow a space-filling curve)
+    // > 0: the work list is sorted by (set, Morton index of the seed's cell at
+    // this many bits per axis of the set's box) before stepping, so that the
+    // lanes of a wave trace nearby lines; 0: seed order (maps, whose seeds
+    // already follow a space-filling curve)
     int spatial_bits;
 };
 
@@ -115,10 +115,17 @@ void prof_end(void *token, hipStream_t s);
 
 // Bytes of the record block for cap seeds (without the 256-byte counter block).
 uint64_t records_bytes(int64_t cap);
-// Spatial buckets the record block of cap seeds holds, and the bits per axis
-// that fit nsets sets into them (0: too many sets, seed order).
-int64_t bucket_cap(int64_t cap);
-int spatial_bits_for(int64_t cap, int nsets);
+// Bits per axis of the spatial sort key for nsets sets (set index above a
+// 3-axis Morton index, 32 bits in all).
+int spatial_bits_for(int nsets);
+int set_bits_for(int nsets);
+// Stable LSD radix sort of n (*n_dev, at most n_max) uint32 keys with int32
+// values, key_bits low bits, 8 per pass; cnt holds sort_count_words(n_max)
+// words, scan_tmp scan_tmp_words(sort_count_words(n_max)), n_cnt two int64.
+int64_t sort_count_words(int64_t n_max);
+void launch_sort_pairs(uint32_t *keys, int32_t *vals, uint32_t *keys_tmp, int32_t *vals_tmp, int32_t *cnt,
+                       int64_t *scan_tmp, int64_t *n_cnt, const int64_t *n_dev, int64_t n_max, int key_bits,
+                       hipStream_t st);
 // Exclusive scan of n int32 values (n from *n_dev, at most n_max) into off and
 // the total into *total; tmp holds scan_tmp_words(n_max) int64 words.
 int64_t scan_tmp_words(int64_t n_max);

@@ -528,10 +528,10 @@ __global__ void k_compact(TraceJob job)
 }
 
 // ---------------------------------------------------------------------------
-// spatial order of the work list: a counting sort of the flagged half-lines by
-// (set, Morton index of the seed's cell at `bits` bits per axis of the set's
-// box).  Order within a bucket is arrival order; no line's arithmetic depends
-// on where it runs, so results do not change.
+// spatial order of the work list: sort keys (set, Morton index of the seed's
+// cell at `bits` bits per axis of the set's box) for the compacted list; the
+// sort itself is a stable radix sort.  No line's arithmetic depends on where
+// it runs, so results do not change.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t spread3(uint32_t v)   // bit k of v -> bit 3k
 {
@@ -542,15 +542,15 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v)   // bit k of v -> bit 3
 }
 
 template <bool BATCH>
-__global__ void k_bucket_count(TraceJob job, int bits)
+__global__ void k_sort_keys(TraceJob job, int bits)
 {
-    const int64_t n2 = *job.rec.n_items, n = n2 / 2;
+    const int64_t nw = *job.rec.n_work;
     const int64_t P = 2 * job.rec.cap;
     const int side = 1 << bits;
-    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n2; it += (int64_t)gridDim.x * blockDim.x) {
-        if (!job.rec.flag[it]) continue;
-        const int64_t i = it >= n ? it - n : it;
-        const int64_t r = it >= n ? job.rec.cap + i : i;
+    uint32_t *keys = reinterpret_cast<uint32_t *>(job.rec.flag);
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = job.rec.work[w];
+        const int64_t i = r >= job.rec.cap ? r - job.rec.cap : r;
         const Geom &g = BATCH ? job.sets[job.set_of[i]].g : job.g;
         uint32_t c[3];
 #pragma unroll
@@ -560,27 +560,9 @@ __global__ void k_bucket_count(TraceJob job, int bits)
             k = k < 0 ? 0 : (k > side - 1 ? side - 1 : k);
             c[d] = (uint32_t)k;
         }
-        const int64_t set = BATCH ? job.set_of[i] : 0;
-        const int32_t b = (int32_t)((set << (3 * bits)) + (spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2)));
-        atomicAdd(&job.rec.bhist[b], 1);
-        job.rec.wpos[it] = b;
+        const uint32_t set = BATCH ? (uint32_t)job.set_of[i] : 0u;
+        keys[w] = (set << (3 * bits)) | spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
     }
-}
-
-__global__ void k_bucket_scatter(TraceJob job)
-{
-    const int64_t n2 = *job.rec.n_items, n = n2 / 2;
-    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n2; it += (int64_t)gridDim.x * blockDim.x) {
-        if (!job.rec.flag[it]) continue;
-        const int32_t pos = atomicAdd(&job.rec.boff[job.rec.wpos[it]], 1);
-        job.rec.work[pos] = (int32_t)(it >= n ? job.rec.cap + (it - n) : it);
-    }
-}
-
-__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
 }
 
 // flags of the half-lines the stepping pass left outside the box (to land)
@@ -1206,26 +1188,24 @@ __global__ void k_set_u64(unsigned long long *p, unsigned long long v) { *p = v;
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-int64_t bucket_cap(int64_t cap)
+int set_bits_for(int nsets)
 {
-    int64_t b = 4096;
-    while (b < cap / 2 && b < ((int64_t)1 << 21)) b *= 2;
+    int b = 0;
+    while (b < 16 && ((int64_t)1 << b) < (int64_t)nsets) ++b;
     return b;
 }
 
-int spatial_bits_for(int64_t cap, int nsets)
+int spatial_bits_for(int nsets)
 {
-    const int64_t nb = bucket_cap(cap);
-    for (int bits = 5; bits >= 1; --bits)
-        if ((int64_t)(nsets > 0 ? nsets : 1) << (3 * bits) <= nb) return bits;
-    return 0;
+    const int b = (32 - set_bits_for(nsets)) / 3;
+    return b < 8 ? b : 8;
 }
 
 uint64_t records_bytes(int64_t cap)
 {
-    const uint64_t P = 2 * (uint64_t)cap, NB = (uint64_t)bucket_cap(cap);
-    const uint64_t scan_n = P > NB ? P : NB;
-    return P * (11 * sizeof(double) + 5 * sizeof(int32_t)) + 2 * NB * sizeof(int32_t) +
+    const uint64_t P = 2 * (uint64_t)cap, NC = (uint64_t)sort_count_words((int64_t)P);
+    const uint64_t scan_n = P > NC ? P : NC;
+    return P * (11 * sizeof(double) + 6 * sizeof(int32_t)) + NC * sizeof(int32_t) + 8 +
            (uint64_t)scan_tmp_words((int64_t)scan_n) * 8;
 }
 
@@ -1252,18 +1232,19 @@ void carve_records(void *scratch, int64_t cap, Records *rec, unsigned long long 
     p += P * sizeof(int32_t);
     rec->work = reinterpret_cast<int32_t *>(p);
     p += P * sizeof(int32_t);
-    const uint64_t NB = (uint64_t)bucket_cap(cap);
-    rec->bhist = reinterpret_cast<int32_t *>(p);
-    p += NB * sizeof(int32_t);
-    rec->boff = reinterpret_cast<int32_t *>(p);
-    p += NB * sizeof(int32_t);
+    rec->work2 = reinterpret_cast<int32_t *>(p);
+    p += P * sizeof(int32_t);
+    const uint64_t NC = (uint64_t)sort_count_words((int64_t)P);
+    rec->scnt = reinterpret_cast<int32_t *>(p);
+    p += NC * sizeof(int32_t);
+    p += (8 - ((uintptr_t)p & 7)) & 7;
     rec->scan_tmp = reinterpret_cast<int64_t *>(p);
     rec->cap = cap;
     // device scalars share the 256-byte block with the work counter
     rec->n_work = reinterpret_cast<int64_t *>(static_cast<char *>(scratch) + 8);
     rec->n_items = reinterpret_cast<int64_t *>(static_cast<char *>(scratch) + 16);
     rec->n_land = reinterpret_cast<int64_t *>(static_cast<char *>(scratch) + 24);
-    rec->n_buckets = reinterpret_cast<int64_t *>(static_cast<char *>(scratch) + 32);
+    rec->n_sort = reinterpret_cast<int64_t *>(static_cast<char *>(scratch) + 32);
 }
 
 int device_cu_count()
@@ -1313,21 +1294,17 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
     hipLaunchKernelGGL((k_seed_pass<S, MODE, BATCH>), dim3(sblocks), dim3(256), 0, st, job);
     int64_t cb = (2 * n_max + 255) / 256;
     const int cblocks = (int)(cb < (int64_t)cus * 16 ? cb : (int64_t)cus * 16);
+    launch_scan_i32(job.rec.flag, job.rec.n_items, 2 * n_max, job.rec.scan_tmp, job.rec.wpos, job.rec.n_work, st);
+    hipLaunchKernelGGL(k_compact, dim3(cblocks), dim3(256), 0, st, job);
     if (job.spatial_bits > 0) {
-        // work list in spatial buckets: count, offsets (their total is the
-        // work count), scatter
+        // work list in spatial order: keys (in the flag array, free now),
+        // then the stable sort with the work list as values
         const int bits = job.spatial_bits;
-        const int64_t nb = (int64_t)(BATCH ? job.nsets : 1) << (3 * bits);
-        hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, reinterpret_cast<unsigned long long *>(job.rec.n_buckets),
-                           (unsigned long long)nb);
-        const int fb = (int)(((nb + 255) / 256) < (int64_t)cus * 16 ? (nb + 255) / 256 : (int64_t)cus * 16);
-        hipLaunchKernelGGL(k_fill_i32, dim3(fb), dim3(256), 0, st, job.rec.bhist, nb, 0);
-        hipLaunchKernelGGL((k_bucket_count<BATCH>), dim3(cblocks), dim3(256), 0, st, job, bits);
-        launch_scan_i32(job.rec.bhist, job.rec.n_buckets, nb, job.rec.scan_tmp, job.rec.boff, job.rec.n_work, st);
-        hipLaunchKernelGGL(k_bucket_scatter, dim3(cblocks), dim3(256), 0, st, job);
-    } else {
-        launch_scan_i32(job.rec.flag, job.rec.n_items, 2 * n_max, job.rec.scan_tmp, job.rec.wpos, job.rec.n_work, st);
-        hipLaunchKernelGGL(k_compact, dim3(cblocks), dim3(256), 0, st, job);
+        hipLaunchKernelGGL((k_sort_keys<BATCH>), dim3(cblocks), dim3(256), 0, st, job, bits);
+        const int key_bits = 3 * bits + (BATCH ? set_bits_for(job.nsets) : 0);
+        launch_sort_pairs(reinterpret_cast<uint32_t *>(job.rec.flag), job.rec.work,
+                          reinterpret_cast<uint32_t *>(job.rec.wpos), job.rec.work2, job.rec.scnt, job.rec.scan_tmp,
+                          job.rec.n_sort, job.rec.n_work, 2 * n_max, key_bits, st);
     }
     // launch shape (QSQ_LAUNCH word): workgroup size and a resident-lane
     // target per CU, capped by what the kernel's registers and LDS let stay

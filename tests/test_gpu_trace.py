@@ -96,6 +96,36 @@ def test_charges_parity(oracle_mod, small_charges, step_dtype, tol):
         check_fp32(p, g, o, ref)
 
 
+@pytest.mark.parametrize("n", [1, 2047, 2049, 6001])
+def test_spatial_order_steps_every_line_once(oracle_mod, small_charges, n):
+    """The half-lines are stepped in spatial order (a radix sort of their
+    seeds' cells, tiles of 2048 items): whatever the count and however many
+    seeds share a cell (equal keys), every line is stepped exactly once and its
+    result does not depend on where the sort put it -- the same seeds given in
+    reverse and shuffled order give identical per-seed outputs, and statuses
+    match the oracle's."""
+    c = small_charges
+    g0 = synth.rng(90 + n)
+    seeds = _mixed_seeds(n, 90 + n)
+    if n > 8:
+        # a third of the seeds are copies of five points: long runs of equal keys
+        k = n // 3
+        seeds[:k] = seeds[g0.integers(k, n, size=5)][g0.integers(0, 5, size=k)]
+    h = min(c["spacing"])
+    kw = dict(rtol=1e-4, atol=1e-4, h_init=0.1 * h, h_max=h)
+    fg = gpu_field(c["b"], c["origin"], c["spacing"], storage="f32")
+    ref = gpu_trace(fg, seeds, step_dtype="f32", **kw)
+    for perm in (np.arange(n)[::-1].copy(), g0.permutation(n)):
+        out = gpu_trace(fg, seeds[perm], step_dtype="f32", **kw)
+        for key in ("status", "fll", "q_perp", "fp_fwd", "fp_bwd"):
+            a, b = np.nan_to_num(out[key], nan=-7.0), np.nan_to_num(ref[key][perm], nan=-7.0)
+            assert np.array_equal(a, b), key
+    if n >= 100:
+        fo = _oracle_grid(oracle_mod, c["b"], c["origin"], c["spacing"], "paper", "f32")
+        o = oracle_mod.trace(fo, seeds, **kw)
+        assert (ref["status"] == o["status"]).mean() >= 0.99
+
+
 def test_interp_normalize_fp32(oracle_mod, small_charges):
     c = small_charges
     seeds = _mixed_seeds(500, 5)

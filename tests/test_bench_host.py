@@ -1,0 +1,66 @@
+"""Host logic of bench.py (no GPU): the one-GPU refusal, the counter summary
+and the source-hash gate of the reported HBM traffic."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["requested_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def _csv(d, rows, counter):
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "x_counter_collection.csv"), "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for k, (name, v) in enumerate(rows):
+            w.writerow(dict(Dispatch_Id=k, Kernel_Name=name, Counter_Name=counter, Counter_Value=v))
+
+
+def test_counter_summary_scales_by_the_copy(tmp_path, monkeypatch):
+    """Fetched bytes = FETCH_SIZE KiB x 1024 x (1 GiB / what the copy's FETCH_SIZE
+    reads), likewise for writes; every stepping dispatch counts, nothing else."""
+    kt = "void qsq::k_trace<float, float, 0, false, false>(qsq::TraceJob)"
+    _csv(tmp_path / "f", [(kt, 1000.0), ("other", 5e6), (kt, 3000.0)], "FETCH_SIZE")
+    _csv(tmp_path / "w", [(kt, 100.0), ("other", 5e6), (kt, 300.0)], "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    _csv(tmp_path / "cf", [("__amd_rocclr_copyBuffer", gib_kib / 2)] * 3, "FETCH_SIZE")
+    _csv(tmp_path / "cw", [("__amd_rocclr_copyBuffer", gib_kib)] * 3, "WRITE_SIZE")
+    out = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
+    bench.summarize_pmc(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"), str(tmp_path / "cw"))
+    t = json.loads(out.read_text())
+    assert t["passes"] == 2 and t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
+    assert t["fetch_bytes_per_launch"] == pytest.approx(2000.0 * 1024 * 2.0)
+    assert t["write_bytes_per_launch"] == pytest.approx(200.0 * 1024)
+    assert t["kernel_sources_sha256"] == bench.kernel_hash()
+    assert bench.measured_traffic() == pytest.approx(t["bytes_per_launch"])
+    # a summary taken on other kernel sources is not reported
+    t["kernel_sources_sha256"] = "0" * 64
+    out.write_text(json.dumps(t))
+    assert bench.measured_traffic() is None
+
+
+def test_mismatched_counter_runs_are_rejected(tmp_path, monkeypatch):
+    kt = "void qsq::k_trace<float, float, 0, false, false>(qsq::TraceJob)"
+    _csv(tmp_path / "f", [(kt, 1.0), (kt, 1.0)], "FETCH_SIZE")
+    _csv(tmp_path / "w", [(kt, 1.0)], "WRITE_SIZE")
+    _csv(tmp_path / "cf", [("__amd_rocclr_copyBuffer", 1.0)], "FETCH_SIZE")
+    _csv(tmp_path / "cw", [("__amd_rocclr_copyBuffer", 1.0)], "WRITE_SIZE")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "t.json"))
+    with pytest.raises(SystemExit):
+        bench.summarize_pmc(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"), str(tmp_path / "cw"))

@@ -664,7 +664,6 @@ hipError_t cnn_train_step(float *params, float *adam_m, float *adam_v, int64_t t
                           float *grad_out, double *loss_out, void *ws, hipStream_t st)
 {
     const CnnWs s = ws_layout(ws, n, h, w);
-    const ConvDims d{n, h, w};
     const int64_t P = n * h * w;
     hipError_t e = cnn_forward(prep, x, n, h, w, s.out, ws, st);
     if (e != hipSuccess) return e;

@@ -58,7 +58,7 @@ struct Records {
     int64_t *scan_tmp;  // block sums of the scan
     int64_t *n_work;    // device scalar: work items
     int64_t *n_items;   // device scalar: half-lines of the call (2 n)
-    int64_t *n_land;    // device scalar: half-lines the landing pass takes (listed in work)
+    int64_t *n_land;    // device scalar: half-lines the landing pass takes (listed in work2)
     int32_t *work2;     // 2*cap: second buffer of the work-list sort
     int32_t *scnt;      // digit counts of the work-list sort (sort_count_words(2 cap))
     int64_t *n_sort;    // device scalars of the sort: count entries, item total

@@ -565,14 +565,21 @@ __global__ void k_sort_keys(TraceJob job, int bits)
     }
 }
 
-// flags of the half-lines the stepping pass left outside the box (to land)
+// The landing list: the stepped half-lines (work list order, so in spatial
+// or curve order like the stepping) that the stepping pass left outside the
+// box.  Flags over work-list positions, then a compaction into work2.
 __global__ void k_land_flags(TraceJob job)
 {
-    const int64_t n2 = *job.rec.n_items, n = n2 / 2;
-    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n2; it += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = it >= n ? job.rec.cap + (it - n) : it;
-        job.rec.flag[it] = job.rec.status[r] == kPendingLand ? 1 : 0;
-    }
+    const int64_t nw = *job.rec.n_work;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (int64_t)gridDim.x * blockDim.x)
+        job.rec.flag[w] = job.rec.status[job.rec.work[w]] == kPendingLand ? 1 : 0;
+}
+
+__global__ void k_land_compact(TraceJob job)
+{
+    const int64_t nw = *job.rec.n_work;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (int64_t)gridDim.x * blockDim.x)
+        if (job.rec.flag[w]) job.rec.work2[job.rec.wpos[w]] = job.rec.work[w];
 }
 
 // ---------------------------------------------------------------------------
@@ -950,7 +957,7 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
     const int64_t total = *job.rec.n_land;
     for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
          it += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = job.rec.work[it];
+        const int64_t r = job.rec.work2[it];
         const int dir = r >= job.rec.cap ? 1 : 0;
         const int64_t i = dir ? r - job.rec.cap : r;
         const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
@@ -1341,15 +1348,16 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
     void *tok = nullptr;
     if (prof) prof_begin(kProfStep, st, &tok);
     void *args[] = {const_cast<TraceJob *>(&job)};
-    hipLaunchKernel(kern, dim3(blocks), dim3(wg), args, lds, st);
+    const hipError_t le = hipLaunchKernel(kern, dim3(blocks), dim3(wg), args, lds, st);
     if (prof) prof_end(tok, st);
+    if (le != hipSuccess) return le;
     int64_t lb = (2 * n_max + 255) / 256;
     int lblocks = (int)(lb < (int64_t)cus * 16 ? lb : (int64_t)cus * 16);
     if (prof) prof_begin(kProfLand, st, &tok);
-    // list of the half-lines to land (the work list is free again)
+    // list of the half-lines to land, in work-list order
     hipLaunchKernelGGL(k_land_flags, dim3(cblocks), dim3(256), 0, st, job);
-    launch_scan_i32(job.rec.flag, job.rec.n_items, 2 * n_max, job.rec.scan_tmp, job.rec.wpos, job.rec.n_land, st);
-    hipLaunchKernelGGL(k_compact, dim3(cblocks), dim3(256), 0, st, job);
+    launch_scan_i32(job.rec.flag, job.rec.n_work, 2 * n_max, job.rec.scan_tmp, job.rec.wpos, job.rec.n_land, st);
+    hipLaunchKernelGGL(k_land_compact, dim3(cblocks), dim3(256), 0, st, job);
     hipLaunchKernelGGL((k_land<S, MODE, BATCH>), dim3(lblocks), dim3(256), 0, st, job);
     if (prof) prof_end(tok, st);
     int64_t ab = (n_max + 255) / 256;

@@ -384,23 +384,24 @@ __global__ void __launch_bounds__(256) k_scan_sums(const int32_t *v, const int64
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
+// block offsets: each thread sums a contiguous run of block sums, one block
+// scan of the 256 run totals, then each thread writes its run's offsets
 __global__ void __launch_bounds__(256) k_scan_top(int64_t nblocks, int64_t *bsum, int64_t *total)
 {
     __shared__ int64_t lds[4];
-    __shared__ int64_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int64_t b0 = 0; b0 < nblocks; b0 += 256) {
-        const int64_t i = b0 + threadIdx.x;
-        const int64_t x = i < nblocks ? bsum[i] : 0;
-        int64_t tot;
-        const int64_t incl = block_incl_scan(x, lds, tot);
-        if (i < nblocks) bsum[i] = carry + incl - x;
-        __syncthreads();
-        if (threadIdx.x == 0) carry += tot;
-        __syncthreads();
+    const int64_t per = (nblocks + 255) / 256;
+    const int64_t b0 = (int64_t)threadIdx.x * per;
+    const int64_t b1 = b0 + per < nblocks ? b0 + per : nblocks;
+    int64_t s = 0;
+    for (int64_t b = b0; b < b1; ++b) s += bsum[b];
+    int64_t tot;
+    int64_t run = block_incl_scan(s, lds, tot) - s;
+    for (int64_t b = b0; b < b1; ++b) {
+        const int64_t x = bsum[b];
+        bsum[b] = run;
+        run += x;
     }
-    if (threadIdx.x == 0) *total = carry;
+    if (threadIdx.x == 0) *total = tot;
 }
 
 __global__ void __launch_bounds__(256) k_scan_apply(const int32_t *v, const int64_t *count_in, const int64_t *boff,

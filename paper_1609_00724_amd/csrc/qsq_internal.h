@@ -19,6 +19,10 @@ struct Bf16 {
 constexpr int kPendingLand = 0x7f;
 // record status of a half-line the seed pass set up for stepping
 constexpr int kPendingStep = 0x7e;
+// record status of a half-line whose landing step length is found (face
+// kLandFace + f, step length in the record's h) and whose landed state is not
+// yet computed
+constexpr int kLandFace = 0x70;
 
 // Grid geometry as the kernels see it.
 struct Geom {

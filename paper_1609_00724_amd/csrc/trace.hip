@@ -174,6 +174,42 @@ __device__ __forceinline__ void field_at(const S *__restrict__ nodes, const Geom
     }
 }
 
+// The interpolated direction u alone (no gradient): the same operations as
+// the value part of field_at, so both give the same u bit for bit.
+template <typename T, typename S, int MODE>
+__device__ __forceinline__ void field_u(const S *__restrict__ nodes, const Geom &g, const int ib[3], const T q[3],
+                                        T u[3])
+{
+    int c[3];
+    T t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) cell_of(ib[d], q[d], g.n[d], c[d], t[d]);
+    const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
+    const int64_t b = (int64_t)c[2] * sz + (int64_t)c[1] * sy + c[0];
+    const auto n000 = ld4(nodes, b), n100 = ld4(nodes, b + 1);
+    const auto n010 = ld4(nodes, b + sy), n110 = ld4(nodes, b + sy + 1);
+    const auto n001 = ld4(nodes, b + sz), n101 = ld4(nodes, b + sz + 1);
+    const auto n011 = ld4(nodes, b + sz + sy), n111 = ld4(nodes, b + sz + sy + 1);
+    T val[3];
+#define QSQ_COMPV(F, k)                                                                                  \
+    val[k] = lerp_val<T>((T)n000.F, (T)n100.F, (T)n010.F, (T)n110.F, (T)n001.F, (T)n101.F, (T)n011.F,    \
+                         (T)n111.F, t[0], t[1], t[2])
+    QSQ_COMPV(x, 0);
+    QSQ_COMPV(y, 1);
+    QSQ_COMPV(z, 2);
+#undef QSQ_COMPV
+    if (MODE == QSQ_INTERP_PAPER) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) u[i] = val[i];
+    } else {
+        const T bb = val[0] * val[0] + val[1] * val[1] + val[2] * val[2];
+        const T bn = sqrt(bb);
+        const T inv = bn > (T)1e-300 ? (T)1 / bn : (T)0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) u[i] = val[i] * inv;
+    }
+}
+
 // a0 b0 + a1 b1 + a2 b2 with the fused operations spelled out, so that the
 // rounding does not depend on how the compiler contracts the expression
 template <typename T>
@@ -853,7 +889,7 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
 // ---------------------------------------------------------------------------
 template <typename S, int MODE>
 __device__ void ck54_fp64(const S *__restrict__ nodes, const Geom &g, double sigma, const double y[9],
-                          double hs, double yo[9], double *slope0 = nullptr)
+                          double hs, double yo[9])
 {
     double K[6][9];
     const double A[6][5] = {{0, 0, 0, 0, 0},
@@ -899,6 +935,49 @@ __device__ void ck54_fp64(const S *__restrict__ nodes, const Geom &g, double sig
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         yo[i] = y[i] + hs * (ck::b1 * K[0][i] + ck::b3 * K[2][i] + ck::b4 * K[3][i] + ck::b6 * K[5][i]);
+}
+
+// The position part of one FP64 Cash-Karp step (eq. (1) alone: the position
+// does not depend on the deviation vectors), the same operations as the
+// position components of ck54_fp64.
+template <typename S, int MODE>
+__device__ void ck54_pos(const S *__restrict__ nodes, const Geom &g, double sigma, const double y[3], double hs,
+                         double yo[3], double *slope0 = nullptr)
+{
+    double K[6][3];
+    const double A[6][5] = {{0, 0, 0, 0, 0},
+                            {ck::a21, 0, 0, 0, 0},
+                            {ck::a31, ck::a32, 0, 0, 0},
+                            {ck::a41, ck::a42, ck::a43, 0, 0},
+                            {ck::a51, ck::a52, ck::a53, ck::a54, 0},
+                            {ck::a61, ck::a62, ck::a63, ck::a64, ck::a65}};
+    int ib[3];
+    double fb[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double xg = (y[d] - g.o[d]) * g.ih[d];
+        const double fl = floor(fmin(fmax(xg, -1e9), 1e9));
+        ib[d] = (int)fl;
+        fb[d] = xg - fl;
+    }
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        double q[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            double ax = 0;
+#pragma unroll
+            for (int j = 0; j < st; ++j) ax = fma(A[st][j], K[j][i], ax);
+            q[i] = fma(hs * ax, g.ih[i], fb[i]);
+        }
+        double u[3];
+        field_u<double, S, MODE>(nodes, g, ib, q, u);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) K[st][i] = sigma * u[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        yo[i] = y[i] + hs * (ck::b1 * K[0][i] + ck::b3 * K[2][i] + ck::b4 * K[3][i] + ck::b6 * K[5][i]);
     if (slope0) {
         // dx/dlambda at the start of the step (the first stage)
 #pragma unroll
@@ -934,20 +1013,24 @@ __device__ __forceinline__ double beyond_face(const Geom &g, const double *x, in
 }
 
 template <typename S, int MODE>
-__device__ double face_gap(const S *nodes, const Geom &g, double sigma, const double y[9], double hs,
-                           int f, double yo[9])
+__device__ double face_gap(const S *nodes, const Geom &g, double sigma, const double y[3], double hs,
+                           int f, double yo[3])
 {
     if (hs == 0.0) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) yo[i] = y[i];
+        for (int i = 0; i < 3; ++i) yo[i] = y[i];
     } else {
-        ck54_fp64<S, MODE>(nodes, g, sigma, y, hs, yo);
+        ck54_pos<S, MODE>(nodes, g, sigma, y, hs, yo);
     }
     return beyond_face(g, yo, f);
 }
 
 // ---------------------------------------------------------------------------
-// k_land: FP64 landing of pending half-lines on the first face crossed
+// k_land: FP64 landing of pending half-lines on the first face crossed, in
+// two passes.  The step length that ends on the face needs the position only
+// (eq. (1) does not involve the deviation vectors), so the root find steps
+// three components (few registers, many waves); k_land_final then takes the
+// one full nine-component step to the root and snaps onto the face.
 // ---------------------------------------------------------------------------
 template <typename S, int MODE, bool BATCH>
 __global__ void __launch_bounds__(256) k_land(TraceJob job)
@@ -955,6 +1038,7 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
     // the list of half-lines to land (compacted after the stepping pass), so
     // that every lane of a wave has one
     const int64_t total = *job.rec.n_land;
+    const int64_t P = 2 * job.rec.cap;
     for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
          it += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = job.rec.work2[it];
@@ -971,15 +1055,12 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
         }
         const Geom &g = gl;
         const double sigma = dir ? -1.0 : 1.0;
-        double y[9], s, hs, y5[9], v0[3];
-        get_rec(job.rec, r, y, s, hs);
-        ck54_fp64<S, MODE>(nodes, g, sigma, y, hs, y5, v0);
+        const double y[3] = {job.rec.y[r], job.rec.y[P + r], job.rec.y[2 * P + r]};
+        const double hs = job.rec.h[r];
+        double y5[3], v0[3];
+        ck54_pos<S, MODE>(nodes, g, sigma, y, hs, y5, v0);
         double best = INFINITY;
         int face = -1;
-        // end state of the converged trial for the best face (the step at the
-        // root is not taken again)
-        double ybest[9];
-        bool have_best = false;
         double gmax = -INFINITY;
         int fmax_ = 0;
         for (int f = 0; f < 6; ++f) {
@@ -990,11 +1071,10 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
             }
             if (!(gend > 0.0)) continue;
             // Illinois regula falsi for the step length ending on face f
-            double yo[9];
+            double yo[3];
             double a = 0.0, b = hs;
             double ga = face_gap<S, MODE>(nodes, g, sigma, y, a, f, yo);
             double hf;
-            bool conv = false;
             if (ga >= 0.0) {
                 hf = 0.0;
             } else {
@@ -1011,7 +1091,6 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
                     const double gc = face_gap<S, MODE>(nodes, g, sigma, y, c, f, yo);
                     if (fabs(gc) <= gtol) {
                         hf = c;
-                        conv = true;
                         break;
                     }
                     if (gc > 0.0) {
@@ -1032,27 +1111,45 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
             if (hf < best) {
                 best = hf;
                 face = f;
-                have_best = conv;
-                if (conv) {
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) ybest[k] = yo[k];
-                }
             }
         }
-        double yl[9];
         if (face < 0) {
-            // the FP64 re-solve ends inside (the trial end was within rounding of a
-            // face): land on the nearest face at the full step
+            // the FP64 re-solve ends inside (the trial end was within rounding
+            // of a face): land on the nearest face at the full step
             face = fmax_;
             best = hs;
-            for (int i = 0; i < 9; ++i) yl[i] = y5[i];
-        } else if (best > 0.0 && have_best) {
-#pragma unroll
-            for (int k = 0; k < 9; ++k) yl[k] = ybest[k];
-        } else if (best > 0.0) {
+        }
+        job.rec.h[r] = best;
+        job.rec.status[r] = kLandFace + face;
+    }
+}
+
+template <typename S, int MODE, bool BATCH>
+__global__ void __launch_bounds__(256) k_land_final(TraceJob job)
+{
+    const int64_t total = *job.rec.n_land;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+         it += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = job.rec.work2[it];
+        const int dir = r >= job.rec.cap ? 1 : 0;
+        const int64_t i = dir ? r - job.rec.cap : r;
+        const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
+        Geom gl = job.g;
+        if constexpr (BATCH) {
+            const SetDesc &sd = job.sets[job.set_of[i]];
+            gl = sd.g;
+            nodes = static_cast<const S *>(sd.nodes);
+        }
+        const Geom &g = gl;
+        const double sigma = dir ? -1.0 : 1.0;
+        double y[9], s, best, yl[9];
+        get_rec(job.rec, r, y, s, best);
+        const int face = job.rec.status[r] - kLandFace;
+        if (best > 0.0) {
             ck54_fp64<S, MODE>(nodes, g, sigma, y, best, yl);
         } else {
-            for (int i = 0; i < 9; ++i) yl[i] = y[i];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) yl[k] = y[k];
         }
         const int d = face >> 1;
         const double snap = (face & 1) ? pick3(g.hi, d) : pick3(g.lo, d);
@@ -1359,6 +1456,7 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
     launch_scan_i32(job.rec.flag, job.rec.n_work, 2 * n_max, job.rec.scan_tmp, job.rec.wpos, job.rec.n_land, st);
     hipLaunchKernelGGL(k_land_compact, dim3(cblocks), dim3(256), 0, st, job);
     hipLaunchKernelGGL((k_land<S, MODE, BATCH>), dim3(lblocks), dim3(256), 0, st, job);
+    hipLaunchKernelGGL((k_land_final<S, MODE, BATCH>), dim3(lblocks), dim3(256), 0, st, job);
     if (prof) prof_end(tok, st);
     int64_t ab = (n_max + 255) / 256;
     int ablocks = (int)(ab < (int64_t)cus * 16 ? ab : (int64_t)cus * 16);

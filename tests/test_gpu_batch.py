@@ -179,3 +179,45 @@ def test_launch_shapes_give_identical_results(storage):
                                       cands=autotune.candidates(lanes=(2, 8), wgs=(128, 256)), use_cache=False)
     assert word in table and table[word] == min(table.values())
     assert autotune.describe(word)["workgroup"] in (128, 256)
+
+
+def test_full_batch_sampled(oracle_mod):
+    """The benchmark's batch at full size (64 point-charge fields on grids of
+    64^3 to 256x256x128, 10^4-10^6 random seeds each, FP32 storage and
+    stepping at tol 1e-4, one batched call in spatial work order): every
+    field's sampled lines against the FP64 oracle on the same FP32-rounded
+    field, with the FP32 gates; the converged oracle (tol 1e-10) decides the
+    statistical comparison."""
+    import torch
+
+    from gpu_util import check_fp32
+    from paper_1609_00724_amd import _abi as A
+    from paper_1609_00724_amd.api import TraceBatchPlan, make_opts
+    dev = torch.device("cuda:0")
+    g = synth.rng(64)
+    sets, picks, oracle_out, ref_out = [], [], [], []
+    for f in synth.batch_c3(count=64):
+        fg = gpu_field(f["b"], f["origin"], f["spacing"], storage="f32")
+        n = f["seeds"].shape[0]
+        pick = np.sort(g.choice(n, size=min(n, 6), replace=False))
+        h = min(f["spacing"])
+        kw = dict(rtol=1e-4, atol=1e-4, h_init=0.1 * h, h_max=h)
+        fo = oracle_mod.Field.grid(*(np.asarray(c, np.float64) for c in f["b"]), f["origin"], f["spacing"],
+                                   store="f32")
+        oracle_out.append(oracle_mod.trace(fo, f["seeds"][pick], **kw))
+        ref_out.append(oracle_mod.trace(fo, f["seeds"][pick], **dict(kw, rtol=1e-10, atol=1e-10)))
+        del fo
+        sets.append((fg, torch.from_numpy(f["seeds"]).to(dev)))
+        picks.append(pick)
+    opts = make_opts(1e-4, 1e-4, step_dtype="f32", launch=A.launch_word(3, 64, 1))
+    plan = TraceBatchPlan(sets, opts)
+    plan.run()
+    torch.cuda.synchronize()
+    outs = [_to_np(o) for o in plan.outs]
+    cat = lambda rs, key: np.concatenate([r[key] for r in rs])   # noqa: E731
+    gsel = [{k: v[p] for k, v in o.items()} for o, p in zip(outs, picks)]
+    keys = ("status", "q_perp", "fll", "fp_fwd", "fp_bwd")
+    gg = {k: cat(gsel, k) for k in keys}
+    oo = {k: cat(oracle_out, k) for k in keys}
+    rr = {k: cat(ref_out, k) for k in keys}
+    check_fp32(parity(gg, oo), gg, oo, rr)

@@ -381,3 +381,62 @@ def test_volume_refine_batches_identical(c2):
         res = _run_vmap(c2, m, r, thr, m + r, 8 ** (m + r), batch=b)
         for k in ("keys", "fll", "q_perp", "status"):
             assert np.array_equal(res[k], ref[k], equal_nan=True), (b, k)
+
+
+def test_full_rope_volume_sampled(oracle_mod):
+    """The benchmark's volume at full size: flux rope over a 6-charge
+    background on a 384x384x256 FP32 grid, 256^3 base cells and two levels of
+    3D FLL-jump refinement, FP32 stepping at tol 1e-4 with the LDS cell cache.
+    The refinement is complete (no curve-successive pair left open), and 400
+    sampled lines match the FP64 oracle on the same FP32-rounded field within
+    the FP32 gates; the 3D FLEDGE on a sampled block of the base lattice."""
+    import paper_1609_00724_amd as q
+    from gpu_util import check_fp32
+    from paper_1609_00724_amd import _abi as A
+    from paper_1609_00724_amd.api import QMapPlan, make_opts
+    torch, dev = torch_dev()
+    w = synth.flux_rope_c4(device=dev)
+    b = [torch.from_numpy(c).to(dev) for c in w["b"]]
+    fg = q.field_init(*b, w["origin"], w["spacing"], storage="f32")
+    del b
+    h = min(w["spacing"])
+    m, r, thr = 8, 2, 0.02
+    spec = q.VolumeSpec(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0, m, r, m, thr, 0)
+    plan = QMapPlan(spec, 8 ** m * 4, dev)
+    opts = make_opts(TOL, TOL, h_init=0.1 * h, h_max=h, step_dtype="f32", launch=A.launch_word(8, 128, 2))
+    plan.run(fg, opts)
+    torch.cuda.synchronize()
+    res = plan.result()
+    n = res["count"]
+    assert res["overflow"] == 0 and n > 8 ** m
+    keys = res["keys"].cpu().numpy()
+    fll = res["fll"].cpu().numpy()
+    _check_complete(dict(keys=keys, fll=fll), thr)
+    g = synth.rng(81)
+    idx = np.sort(g.choice(n, size=400, replace=False))
+    box = oracle_mod.VolumeBox(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0)
+    blk = 8 ** r
+    k = keys[idx]
+    base = k % blk == blk // 2
+    pos = np.empty((idx.size, 3))
+    pos[base] = box.centres(m, *oracle_mod.hilbert3_d2xyz(m, k[base] // blk))
+    pos[~base] = oracle_mod.key_positions(box, m, r, k[~base])
+    fo = oracle_mod.Field.grid(*(np.asarray(c, np.float64) for c in w["b"]), w["origin"], w["spacing"], store="f32")
+    kw = dict(rtol=TOL, atol=TOL, h_init=0.1 * h, h_max=h)
+    o = oracle_mod.trace(fo, pos, **kw)
+    ref = oracle_mod.trace(fo, pos, **dict(kw, rtol=1e-10, atol=1e-10))
+    gg = dict(status=res["status"].cpu().numpy()[idx], q_perp=res["q_perp"].cpu().numpy()[idx], fll=fll[idx],
+              fp_fwd=np.zeros((idx.size, 3)), fp_bwd=np.zeros((idx.size, 3)))
+    oz = dict(o, fp_fwd=np.zeros((idx.size, 3)), fp_bwd=np.zeros((idx.size, 3)))
+    check_fp32(parity(gg, oz), gg, oz, ref)
+    # FLEDGE of the base lengths on an interior block (the Sobel stencil only
+    # reaches one cell beyond the block)
+    allbase = keys % blk == blk // 2
+    bx, by, bz = oracle_mod.hilbert3_d2xyz(m, keys[allbase] // blk)
+    img = np.zeros((1 << m,) * 3)
+    img[bz, by, bx] = fll[allbase]
+    lo, hi = 100, 132
+    sub = img[lo - 1:hi + 1, lo - 1:hi + 1, lo - 1:hi + 1].astype(np.float32).astype(np.float64)
+    want = oracle_mod.sobel_magnitude(sub)[1:-1, 1:-1, 1:-1]
+    got = res["fledge"].cpu().numpy()[lo:hi, lo:hi, lo:hi]
+    assert np.allclose(got, want, rtol=1e-5, atol=1e-5)

@@ -462,10 +462,14 @@ def bench_volume(args):
     if not args.no_tune:
         # launch shape timed on the volume itself (one map per candidate)
         from paper_1609_00724_amd import autotune
-        cands = autotune.candidates(lanes=(1, 2, 3, 8), wgs=(128,), gathers=(A.GATHER_DIRECT, A.GATHER_CACHED))
-        word, table = autotune.tune_map(plan, f32, opts, reps=1, cands=cands)
+        cands = [A.launch_word(2, 128, A.GATHER_DIRECT)] + autotune.candidates(lanes=(2, 3, 8), wgs=(128,),
+                                                                                 gathers=(A.GATHER_CACHED,))
+        batches = (args.refine_batch,) if args.refine_batch > 0 else (1, 2, 3)
+        (word, batch), table = autotune.tune_map(plan, f32, opts, reps=1, cands=cands, batches=batches)
         opts.launch = word
-        tuned = dict(autotune.describe(word), ms=table[word], candidates=len(table), worst_ms=max(table.values()))
+        plan.d.refine_batch = batch
+        tuned = dict(autotune.describe(word), refine_batch=batch, ms=table[(word, batch)], candidates=len(table),
+                     worst_ms=max(table.values()))
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         plan.run(f32, opts)
@@ -490,6 +494,7 @@ def bench_volume(args):
     q32 = res["q_perp"].cpu().numpy()
 
     plan16 = QMapPlan(spec, 8 ** m * 4, dev)
+    plan16.d.refine_batch = plan.d.refine_batch
     plan16.run(bf16, opts)
     torch.cuda.synchronize()
     plan16.work.zero_()
@@ -526,6 +531,7 @@ def bench_volume(args):
             "lines_per_step": lines,
             "base_lines": 8 ** m,
             "grid": list(w["n"]),
+            "refine_batch": plan.d.refine_batch,
         },
         "roofline": {
             "bound": "alu",

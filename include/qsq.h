@@ -335,7 +335,7 @@ typedef struct qsq_volume_desc {
     int32_t base_level;    /* m: 2^m cells per axis, sampled at centres */
     int32_t refine_levels; /* r: finest cells are 2^(m+r) per axis (m + r <= 21) */
     int32_t out_level;     /* level of the output grids, m <= out_level <= m + r */
-    int32_t refine_batch;  /* as in qsq_map_desc */
+    int32_t refine_batch;  /* as in qsq_map_desc; <= 0: 1 */
     double threshold;      /* FLL jump that triggers a new sample (length units) */
     const uint8_t *propose; /* as in qsq_map_desc, one byte per base cell (8^m) */
 } qsq_volume_desc;

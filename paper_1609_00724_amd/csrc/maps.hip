@@ -883,7 +883,11 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
     // no-ops (nothing fires, samples are copied to the other buffer).
     const int levels = DIM * r;
     int batch = refine_batch;
-    if (batch <= 0) batch = levels < 4 ? levels : 4;
+    // default: slices speculate up to 4 levels per round (their rounds are
+    // bound by the longest line, so fewer rounds pay); volumes take one level
+    // per round (their rounds are bound by throughput, and the speculative
+    // lines a round discards cost in full)
+    if (batch <= 0) batch = DIM == 2 ? (levels < 4 ? levels : 4) : 1;
     if (batch > 5) batch = 5;
     if (batch < 1) batch = 1;       // no levels: no rounds either
     int64_t *rem = &counts[kRemWord];

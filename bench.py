@@ -173,7 +173,8 @@ def main():
             "grid": [256, 256, 128],
             "tol": args.tol,
             "h_max_cells": args.hmax_cells,
-            "refine_batch": plan.d.refine_batch,
+            # 0 selects the library's default: min(levels, 4) for maps
+            "refine_batch": plan.d.refine_batch or max(1, min(r, 4)),
         },
         "roofline": {
             "bound": "alu",
@@ -531,7 +532,8 @@ def bench_volume(args):
             "lines_per_step": lines,
             "base_lines": 8 ** m,
             "grid": list(w["n"]),
-            "refine_batch": plan.d.refine_batch,
+            # 0 selects the library's default: one level per round for volumes
+            "refine_batch": plan.d.refine_batch or 1,
         },
         "roofline": {
             "bound": "alu",

@@ -463,8 +463,8 @@ def bench_volume(args):
     if not args.no_tune:
         # launch shape timed on the volume itself (one map per candidate)
         from paper_1609_00724_amd import autotune
-        cands = [A.launch_word(2, 128, A.GATHER_DIRECT)] + autotune.candidates(lanes=(2, 3, 8), wgs=(128,),
-                                                                                 gathers=(A.GATHER_CACHED,))
+        cands = ([A.launch_word(2, 128, A.GATHER_DIRECT), A.launch_word(2, 128, A.GATHER_CACHED)]
+                 + autotune.candidates(lanes=(1, 2), wgs=(64, 128, 256), gathers=(A.GATHER_REGS,)))
         batches = (args.refine_batch,) if args.refine_batch > 0 else (1, 2, 3)
         (word, batch), table = autotune.tune_map(plan, f32, opts, reps=1, cands=cands, batches=batches)
         opts.launch = word

@@ -41,13 +41,13 @@ MAX_TRACE_SETS = 65536
 KERNEL_STEP, KERNEL_LAND, KERNEL_ASSEMBLE = 0, 1, 2
 
 WG_CODES = {256: 0, 64: 1, 128: 2}
-GATHER_AUTO, GATHER_DIRECT, GATHER_CACHED = 0, 1, 2
+GATHER_AUTO, GATHER_DIRECT, GATHER_CACHED, GATHER_REGS = 0, 1, 2, 3
 
 
 def launch_word(lanes=0, wg=256, gather=GATHER_AUTO):
     """QSQ_LAUNCH(lanes, wg, gather) of include/qsq.h."""
-    if not 0 <= lanes <= 15 or wg not in WG_CODES or gather not in (0, 1, 2):
-        raise ValueError("launch shape outside QSQ_LAUNCH(0..15, 64|128|256, 0..2)")
+    if not 0 <= lanes <= 15 or wg not in WG_CODES or gather not in (0, 1, 2, 3):
+        raise ValueError("launch shape outside QSQ_LAUNCH(0..15, 64|128|256, 0..3)")
     return (lanes & 15) | (WG_CODES[wg] << 4) | (gather << 6)
 
 

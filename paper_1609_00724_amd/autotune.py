@@ -23,8 +23,18 @@ DEFAULT_WG = (64, 128, 256)
 _cache: dict = {}
 
 
-def candidates(lanes=DEFAULT_LANES, wgs=DEFAULT_WG, gathers=(A.GATHER_DIRECT, A.GATHER_CACHED)):
-    return [A.launch_word(l, w, g) for g in gathers for w in wgs for l in lanes]
+# The cell-cache variants of the stepping kernel need more than 168 registers
+# per lane, so at most 2 waves per SIMD (512 lanes per CU) stay resident: a
+# larger lane target launches the same shape.
+CACHE_LANES = (1, 2)
+
+
+def candidates(lanes=DEFAULT_LANES, wgs=DEFAULT_WG, gathers=(A.GATHER_DIRECT, A.GATHER_CACHED, A.GATHER_REGS)):
+    out = []
+    for g in gathers:
+        ls = lanes if g == A.GATHER_DIRECT else tuple(l for l in lanes if l in CACHE_LANES) or lanes[:1]
+        out += [A.launch_word(l, w, g) for w in wgs for l in ls]
+    return out
 
 
 def _key(field, opts, tag):
@@ -105,7 +115,7 @@ def tune_batch(sets, opts, reps=3, cands=None):
 def describe(word):
     lanes = word & 15 or 8
     wg = {0: 256, 1: 64, 2: 128}[(word >> 4) & 3]
-    gather = {0: "auto", 1: "direct", 2: "lds-cache"}[(word >> 6) & 3]
+    gather = {0: "auto", 1: "direct", 2: "lds-cache", 3: "reg-cache"}[(word >> 6) & 3]
     return {"word": int(word), "lanes_per_cu": lanes * 256, "workgroup": wg, "gather": gather}
 
 

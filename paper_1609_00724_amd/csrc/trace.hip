@@ -365,6 +365,71 @@ __device__ __forceinline__ T rhs_cached(__amdgpu_buffer_rsrc_t rsrc, int bytes, 
     return rhs_from(sigma, u, G, d1, d2, kx, k1, k2);
 }
 
+// Per-lane cache of the 8 corner records (direction part, 24 floats) of the
+// cell a lane evaluated last, kept in registers.  Only lanes whose stage point
+// moved to another cell reload (a branch under the lane mask: a wave whose
+// lanes all stayed in their cells issues no load and waits for none); every
+// lane then interpolates from its registers.  The node values and the
+// arithmetic are those of the direct gather, so the results are the same bit
+// for bit.  The key is the cell's linear index within the lane's field.
+template <typename T, typename S, int MODE>
+__device__ __forceinline__ T rhs_regs(const S *__restrict__ nodes, const Geom &g, const int ib[3], const T q[3],
+                                      T sigma, const T d1[3], const T d2[3], T kx[3], T k1[3], T k2[3],
+                                      int64_t &cell, float (&cw)[24])
+{
+    int c[3];
+    T t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) cell_of(ib[d], q[d], g.n[d], c[d], t[d]);
+    const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
+    const int64_t b = (int64_t)c[2] * sz + (int64_t)c[1] * sy + c[0];
+    if (b != cell) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const auto v = ld4(nodes, b + ((k & 1) ? 1 : 0) + ((k & 2) ? sy : 0) + ((k & 4) ? sz : 0));
+            cw[3 * k] = v.x;
+            cw[3 * k + 1] = v.y;
+            cw[3 * k + 2] = v.z;
+        }
+        cell = b;
+    }
+    T val[3], dx[3], dy[3], dz[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        lerp_tree<T>((T)cw[i], (T)cw[3 + i], (T)cw[6 + i], (T)cw[9 + i], (T)cw[12 + i], (T)cw[15 + i],
+                     (T)cw[18 + i], (T)cw[21 + i], t[0], t[1], t[2], val[i], dx[i], dy[i], dz[i]);
+    const T ihx = (T)g.ih[0], ihy = (T)g.ih[1], ihz = (T)g.ih[2];
+    T u[3], G[3][3];
+    if (MODE == QSQ_INTERP_PAPER) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            u[i] = val[i];
+            G[0][i] = dx[i] * ihx;
+            G[1][i] = dy[i] * ihy;
+            G[2][i] = dz[i] * ihz;
+        }
+    } else {
+        const T bb = val[0] * val[0] + val[1] * val[1] + val[2] * val[2];
+        const T bn = sqrt(bb);
+        const T inv = bn > (T)1e-300 ? (T)1 / bn : (T)0;
+        T Gb[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            u[i] = val[i] * inv;
+            Gb[0][i] = dx[i] * ihx;
+            Gb[1][i] = dy[i] * ihy;
+            Gb[2][i] = dz[i] * ihz;
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const T ug = u[0] * Gb[j][0] + u[1] * Gb[j][1] + u[2] * Gb[j][2];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) G[j][i] = (Gb[j][i] - u[i] * ug) * inv;
+        }
+    }
+    return rhs_from(sigma, u, G, d1, d2, kx, k1, k2);
+}
+
 // 5th-order combination and the 5th-minus-4th error combination of the
 // stage slopes, fused operations spelled out
 template <typename T>
@@ -392,16 +457,22 @@ __device__ __forceinline__ T err_scale(T atol, T rtol, T a, T b)
 __device__ __forceinline__ float err_ratio(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double err_ratio(double a, double b) { return a / b; }
 
-// one RHS evaluation of the stepping kernel: cached gathers (FP32 or BF16
-// storage, FP32 stepping, field below 2 GiB) or direct gathers
-template <typename T, typename S, int MODE, bool CACHED>
+// gather variants of the stepping kernel: direct corner loads, the LDS cell
+// cache (FP32 or BF16 storage, FP32 stepping, one field below 2 GiB) and the
+// register cell cache (FP32 or BF16 storage, FP32 stepping)
+constexpr int kGatherDirect = 0, kGatherLds = 1, kGatherRegs = 2;
+
+// one RHS evaluation of the stepping kernel
+template <typename T, typename S, int MODE, int GATHER>
 __device__ __forceinline__ T rhs_step(const S *__restrict__ nodes, __amdgpu_buffer_rsrc_t rsrc, int bytes,
                                       const Geom &g, const int ib[3], const T q[3], T sigma, const T d1[3],
                                       const T d2[3], T kx[3], T k1[3], T k2[3], int cc[3], float4 *slot,
-                                      int stride)
+                                      int stride, int64_t &cell, float (&cw)[24])
 {
-    if constexpr (CACHED)
+    if constexpr (GATHER == kGatherLds)
         return rhs_cached<T, S, MODE>(rsrc, bytes, g, ib, q, sigma, d1, d2, kx, k1, k2, cc, slot, stride);
+    else if constexpr (GATHER == kGatherRegs)
+        return rhs_regs<T, S, MODE>(nodes, g, ib, q, sigma, d1, d2, kx, k1, k2, cell, cw);
     else
         return rhs<T, S, MODE>(nodes, g, ib, q, sigma, d1, d2, kx, k1, k2);
 }
@@ -621,10 +692,12 @@ __global__ void k_land_compact(TraceJob job)
 // ---------------------------------------------------------------------------
 // k_trace: persistent stepping kernel
 // ---------------------------------------------------------------------------
-template <typename T, typename S, int MODE, bool CACHED, bool BATCH>
+template <typename T, typename S, int MODE, int GATHER, bool BATCH>
 __global__ void __launch_bounds__(256) k_trace(TraceJob job)
 {
-    static_assert(!(CACHED && BATCH), "cached gathers need one field per launch");
+    static_assert(!(GATHER == kGatherLds && BATCH), "the LDS cell cache needs one field per launch");
+    static_assert(GATHER == kGatherDirect || sizeof(T) == 4, "cell caches hold FP32 corner values");
+    constexpr bool CACHED = GATHER == kGatherLds;
     // field and step limits of the lane's line: launch constants for one
     // field, reloaded from the set table at each refill in a batch
     const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
@@ -656,6 +729,11 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
     extern __shared__ float4 lds_cache[];
     const int stride = (int)blockDim.x;
     float4 *slot = lds_cache + threadIdx.x;
+    // register cell cache: the corners of the cell a lane evaluated last
+    int64_t reg_cell = -1;
+    float reg_corner[24];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) reg_corner[k] = 0.0f;
 
     // Work distribution: the first item of every lane is its global lane index
     // (the launcher starts the counter at the launch's lane count); after that
@@ -708,6 +786,7 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
                         hmax = (T)sd.h_max;
 #pragma unroll
                         for (int d = 0; d < 3; ++d) ih[d] = (T)gl.ih[d];
+                        reg_cell = -1;   // the line may belong to another field
                     }
                     sigma = dir ? (T)-1 : (T)1;
                     const int64_t P = 2 * job.rec.cap;
@@ -753,8 +832,8 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
                 fb[d] = (T)(xg - fl);
             }
             if (!have_k1) {
-                const T un2 = rhs_step<T, S, MODE, CACHED>(nodes, rsrc, cbytes, g, ib, fb, (T)1, D1, D2, Kx[0], K1[0],
-                                                           K2[0], cache_cell, slot, stride);
+                const T un2 = rhs_step<T, S, MODE, GATHER>(nodes, rsrc, cbytes, g, ib, fb, (T)1, D1, D2, Kx[0], K1[0],
+                                                           K2[0], cache_cell, slot, stride, reg_cell, reg_corner);
                 ++c_ev;
                 if (!(un2 >= (T)1e-12)) stop = QSQ_END_NULL;
                 have_k1 = true;
@@ -790,8 +869,8 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
             d1[i] = fma(hsig, a1, D1[i]);                                                           \
             d2[i] = fma(hsig, a2, D2[i]);                                                           \
         }                                                                                           \
-        rhs_step<T, S, MODE, CACHED>(nodes, rsrc, cbytes, g, ib, q, (T)1, d1, d2, Kx[ST], K1[ST], K2[ST], \
-                             cache_cell, slot, stride);                                             \
+        rhs_step<T, S, MODE, GATHER>(nodes, rsrc, cbytes, g, ib, q, (T)1, d1, d2, Kx[ST], K1[ST], K2[ST], \
+                                     cache_cell, slot, stride, reg_cell, reg_corner);               \
     }
             QSQ_STAGE(1, (T)ck::a21)
             QSQ_STAGE(2, (T)ck::a31, (T)ck::a32)
@@ -1419,21 +1498,24 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
     const int wg = wg_code == 1 ? 64 : wg_code == 2 ? 128 : 256;
     const void *kern;
     size_t lds = 0;
-    if constexpr (BATCH) {
-        kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, false, true>);
-    } else if constexpr (sizeof(T) == 4 && (std::is_same<S, float>::value || std::is_same<S, Bf16>::value)) {
-        // cached gathers (FP32 or BF16 records, FP32 stepping) address the
-        // node records with 32-bit byte offsets
+    constexpr bool cacheable = sizeof(T) == 4 && (std::is_same<S, float>::value || std::is_same<S, Bf16>::value);
+    if constexpr (BATCH && cacheable) {
+        kern = gather == 3 ? reinterpret_cast<const void *>(&k_trace<T, S, MODE, kGatherRegs, true>)
+                           : reinterpret_cast<const void *>(&k_trace<T, S, MODE, kGatherDirect, true>);
+    } else if constexpr (cacheable) {
+        // the LDS cache addresses the node records with 32-bit byte offsets
         const uint64_t field_bytes = (uint64_t)node_bytes<S>() * job.g.n[0] * job.g.n[1] * job.g.n[2];
-        if (gather != 1 && field_bytes < ((uint64_t)1 << 31) - ((uint64_t)1 << 26)) {
-            kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, true, false>);
+        if (gather == 3 || gather == 0) {
+            kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, kGatherRegs, false>);
+        } else if (gather == 2 && field_bytes < ((uint64_t)1 << 31) - ((uint64_t)1 << 26)) {
+            kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, kGatherLds, false>);
             lds = kCachePlanes * wg * sizeof(float4);
         } else {
-            kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, false, false>);
+            kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, kGatherDirect, false>);
         }
     } else {
         (void)gather;
-        kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, false, false>);
+        kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, kGatherDirect, BATCH>);
     }
     const int64_t resident = (int64_t)cus * resident_blocks(kern, wg, lds);
     int64_t cap_blocks = (int64_t)cus * lanes * (256 / wg);

@@ -95,6 +95,15 @@ def test_invalid_arguments_rejected_before_launch(qsq):
     assert L.qsq_trace(C.byref(f), _fake(7), 10, C.byref(o), C.byref(t), _fake(8), 1 << 20, None) == \
         A.ERR_UNSUPPORTED
     o.step_dtype = A.F32
+    for bad in (0x30, 0x100):             # workgroup code 3; bits above the word
+        o.launch = bad
+        assert L.qsq_trace(C.byref(f), _fake(7), 10, C.byref(o), C.byref(t), _fake(8), 1 << 20, None) == \
+            A.ERR_INVALID_ARG
+        assert b"launch word" in L.qsq_last_error()
+    o.launch = A.launch_word(2, 64, A.GATHER_REGS)   # valid: fails later, on the workspace
+    assert L.qsq_trace(C.byref(f), _fake(7), 10, C.byref(o), C.byref(t), _fake(8), 16, None) == \
+        A.ERR_WORKSPACE_TOO_SMALL
+    o.launch = 0
     assert L.qsq_trace(C.byref(f), _fake(7), 10, C.byref(o), C.byref(t), _fake(8), 16, None) == \
         A.ERR_WORKSPACE_TOO_SMALL
     assert L.qsq_trace(C.byref(f), _fake(7), (1 << 30) + 1, C.byref(o), C.byref(t), _fake(8), 1 << 20,

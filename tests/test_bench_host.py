@@ -64,3 +64,19 @@ def test_mismatched_counter_runs_are_rejected(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "t.json"))
     with pytest.raises(SystemExit):
         bench.summarize_pmc(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"), str(tmp_path / "cw"))
+
+
+def test_tuner_candidates_and_names():
+    from paper_1609_00724_amd import _abi as A
+    from paper_1609_00724_amd import autotune
+    words = autotune.candidates()
+    assert len(words) == len(set(words))
+    for w in words:
+        d = autotune.describe(w)
+        assert d["gather"] in ("direct", "lds-cache", "reg-cache")
+        if d["gather"] != "direct":              # at most 512 resident lanes per CU
+            assert d["lanes_per_cu"] <= 512
+    assert autotune.describe(A.launch_word(2, 64, A.GATHER_REGS)) == \
+        {"word": 2 | (1 << 4) | (3 << 6), "lanes_per_cu": 512, "workgroup": 64, "gather": "reg-cache"}
+    with pytest.raises(ValueError):
+        A.launch_word(2, 96, A.GATHER_REGS)

@@ -143,9 +143,11 @@ def test_batch_graph_replay():
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_launch_shapes_give_identical_results(storage):
     """The launch shape (lanes per CU, workgroup size) moves no result: every
-    line's arithmetic is the same wherever it runs.  The two gather variants
-    (direct loads, LDS cell cache) read the same node values; they must agree
-    line by line within the FP32 gates.  FP32 and BF16 node records."""
+    line's arithmetic is the same wherever it runs.  The register cell cache
+    reads the same node values into the same arithmetic as the direct loads:
+    the same results bit for bit.  The LDS cell cache reads the same node
+    values; it must agree with them line by line within the FP32 gates.  FP32
+    and BF16 node records."""
     import torch
 
     import paper_1609_00724_amd as q
@@ -158,15 +160,17 @@ def test_launch_shapes_give_identical_results(storage):
     seeds = torch.from_numpy(synth.random_seeds(77, 5000)).to(dev).t().contiguous()
     plan = TracePlan(seeds.shape[1], dev, want_steps=True)
     res = {}
-    for lanes, wg, gather in [(0, 256, 1), (2, 64, 1), (3, 128, 1), (12, 256, 1), (0, 256, 2), (2, 64, 2), (6, 128, 2)]:
+    for lanes, wg, gather in [(0, 256, 1), (2, 64, 1), (3, 128, 1), (12, 256, 1), (0, 256, 2), (2, 64, 2), (6, 128, 2),
+                              (0, 256, 3), (2, 128, 3), (1, 64, 3)]:
         opts = make_opts(1e-5, 1e-5, step_dtype="f32", launch=A.launch_word(lanes, wg, gather))
         out = plan.run(fg, seeds, opts)
         torch.cuda.synchronize()
         res[(lanes, wg, gather)] = {k: v.clone() for k, v in out.items()}
+    group = {1: 1, 2: 2, 3: 1}        # direct loads and the register cache: one group
     for g in (1, 2):
-        ref = next(v for k, v in res.items() if k[2] == g)
+        ref = next(v for k, v in res.items() if group[k[2]] == g)
         for k, v in res.items():
-            if k[2] != g:
+            if group[k[2]] != g:
                 continue
             for key in ref:
                 assert torch.equal(torch.nan_to_num(v[key], nan=-1.0), torch.nan_to_num(ref[key], nan=-1.0)), (k, key)
@@ -179,6 +183,33 @@ def test_launch_shapes_give_identical_results(storage):
                                       cands=autotune.candidates(lanes=(2, 8), wgs=(128, 256)), use_cache=False)
     assert word in table and table[word] == min(table.values())
     assert autotune.describe(word)["workgroup"] in (128, 256)
+
+
+def test_batch_register_cache_matches_direct():
+    """The batched launch with the register cell cache (invalidated whenever a
+    lane takes a line of another field) against direct corner loads: the same
+    results bit for bit, FP32 and BF16 records."""
+    import torch
+
+    from paper_1609_00724_amd import _abi as A
+    from paper_1609_00724_amd.api import TraceBatchPlan, make_opts
+    dev = torch.device("cuda:0")
+    for storage, dtype in (("f32", np.float32), ("bf16", np.float32)):
+        sets = _sets(6, dtype, empty=(4,))
+        fields = [gpu_field(f["b"], f["origin"], f["spacing"], storage=storage) for f in sets]
+        pairs = [(fg, torch.from_numpy(f["seeds"]).to(dev)) for fg, f in zip(fields, sets)]
+        res = []
+        for word in (A.launch_word(2, 64, A.GATHER_DIRECT), A.launch_word(2, 64, A.GATHER_REGS),
+                     A.launch_word(0, 256, A.GATHER_REGS)):
+            plan = TraceBatchPlan(pairs, make_opts(1e-4, 1e-4, step_dtype="f32", launch=word), want_steps=True)
+            plan.run()
+            torch.cuda.synchronize()
+            res.append([{k: v.clone() for k, v in o.items()} for o in plan.outs])
+        for other in res[1:]:
+            for k, (a, b) in enumerate(zip(res[0], other)):
+                for key in a:
+                    assert torch.equal(torch.nan_to_num(a[key], nan=-1.0), torch.nan_to_num(b[key], nan=-1.0)), \
+                        (storage, k, key)
 
 
 def test_full_batch_sampled(oracle_mod):

@@ -122,13 +122,12 @@ typedef struct qsq_trace_opts {
  *   lanes  resident-lane target of the persistent stepping launch, in units of
  *          256 lanes per compute unit, 1..15 (0: 8)
  *   wg     workgroup size code: 0 = 256, 1 = 64, 2 = 128 lanes
- *   gather 0 = automatic (3 where it applies, except in batches: 1),
+ *   gather 0 = automatic (3 where it applies, otherwise 1),
  *          1 = direct corner loads, 2 = per-lane LDS cache of
  *          the last cell's corners (FP32 or BF16 records and FP32 stepping,
  *          one field per call, field below 2 GiB; otherwise direct),
- *          3 = per-lane register cache of the last cell's corners (FP32 or
- *          BF16 records and FP32 stepping, also in batches; otherwise
- *          direct; results identical to direct loads bit for bit) */
+ *          3 = per-lane register cache of the last cell's corners (same
+ *          conditions as 2; results identical to direct loads bit for bit) */
 #define QSQ_LAUNCH(lanes, wg, gather) (((lanes) & 15) | (((wg) & 3) << 4) | (((gather) & 3) << 6))
 
 /* Per-seed results (device arrays of n entries; fp_* are SoA planes 3 x n:

@@ -366,38 +366,67 @@ __device__ __forceinline__ T rhs_cached(__amdgpu_buffer_rsrc_t rsrc, int bytes, 
 }
 
 // Per-lane cache of the 8 corner records (direction part, 24 floats) of the
-// cell a lane evaluated last, kept in registers.  Only lanes whose stage point
-// moved to another cell reload (a branch under the lane mask: a wave whose
-// lanes all stayed in their cells issues no load and waits for none); every
-// lane then interpolates from its registers.  The node values and the
-// arithmetic are those of the direct gather, so the results are the same bit
-// for bit.  The key is the cell's linear index within the lane's field.
+// cell a lane evaluated last, kept in registers.  A wave in which some lane's
+// stage point moved to another cell issues one gather (a branch taken by the
+// whole wave): the lanes that moved load their new corners, the others pass
+// out-of-range offsets (no memory access) and keep their registers by a
+// select.  A wave whose lanes all stayed in their cells issues no load and
+// waits for none.  No branch under the lane mask, so the 24 values keep their
+// registers from stage to stage without copies.  The node values and the
+// arithmetic are those of the direct gather: the results are the same bit for
+// bit.  The key is the cell's node index within the field (below 2 GiB).
+// Named scalars (not an array) so that they live in plain registers.
+struct Corner {
+    float x, y, z;
+};
+struct Brick {
+    Corner c000, c100, c010, c110, c001, c101, c011, c111;
+};
+
+template <typename S>
+__device__ __forceinline__ void refresh_corner(__amdgpu_buffer_rsrc_t rsrc, int off, bool miss, Corner &c)
+{
+    float x, y, z;
+    load_dir<S>(rsrc, off, x, y, z);
+    c.x = miss ? x : c.x;
+    c.y = miss ? y : c.y;
+    c.z = miss ? z : c.z;
+}
+
 template <typename T, typename S, int MODE>
-__device__ __forceinline__ T rhs_regs(const S *__restrict__ nodes, const Geom &g, const int ib[3], const T q[3],
-                                      T sigma, const T d1[3], const T d2[3], T kx[3], T k1[3], T k2[3],
-                                      int64_t &cell, float (&cw)[24])
+__device__ __forceinline__ T rhs_regs(__amdgpu_buffer_rsrc_t rsrc, int bytes, const Geom &g, const int ib[3],
+                                      const T q[3], T sigma, const T d1[3], const T d2[3], T kx[3], T k1[3],
+                                      T k2[3], int &cell, Brick &br)
 {
     int c[3];
     T t[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) cell_of(ib[d], q[d], g.n[d], c[d], t[d]);
-    const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
-    const int64_t b = (int64_t)c[2] * sz + (int64_t)c[1] * sy + c[0];
-    if (b != cell) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const auto v = ld4(nodes, b + ((k & 1) ? 1 : 0) + ((k & 2) ? sy : 0) + ((k & 4) ? sz : 0));
-            cw[3 * k] = v.x;
-            cw[3 * k + 1] = v.y;
-            cw[3 * k + 2] = v.z;
-        }
+    const int sy = g.n[0], sz = g.n[0] * g.n[1];
+    const int b = c[2] * sz + c[1] * sy + c[0];
+    const bool miss = b != cell;
+    if (__ballot(miss)) {
+        constexpr int NB = node_bytes<S>();
+        const int o = miss ? NB * b : bytes;
+        const int oy = NB * sy, oz = NB * sz;
+        refresh_corner<S>(rsrc, o, miss, br.c000);
+        refresh_corner<S>(rsrc, o + NB, miss, br.c100);
+        refresh_corner<S>(rsrc, o + oy, miss, br.c010);
+        refresh_corner<S>(rsrc, o + oy + NB, miss, br.c110);
+        refresh_corner<S>(rsrc, o + oz, miss, br.c001);
+        refresh_corner<S>(rsrc, o + oz + NB, miss, br.c101);
+        refresh_corner<S>(rsrc, o + oz + oy, miss, br.c011);
+        refresh_corner<S>(rsrc, o + oz + oy + NB, miss, br.c111);
         cell = b;
     }
     T val[3], dx[3], dy[3], dz[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        lerp_tree<T>((T)cw[i], (T)cw[3 + i], (T)cw[6 + i], (T)cw[9 + i], (T)cw[12 + i], (T)cw[15 + i],
-                     (T)cw[18 + i], (T)cw[21 + i], t[0], t[1], t[2], val[i], dx[i], dy[i], dz[i]);
+#define QSQ_COMPB(F, k)                                                                               \
+    lerp_tree<T>((T)br.c000.F, (T)br.c100.F, (T)br.c010.F, (T)br.c110.F, (T)br.c001.F, (T)br.c101.F,  \
+                 (T)br.c011.F, (T)br.c111.F, t[0], t[1], t[2], val[k], dx[k], dy[k], dz[k])
+    QSQ_COMPB(x, 0);
+    QSQ_COMPB(y, 1);
+    QSQ_COMPB(z, 2);
+#undef QSQ_COMPB
     const T ihx = (T)g.ih[0], ihy = (T)g.ih[1], ihz = (T)g.ih[2];
     T u[3], G[3][3];
     if (MODE == QSQ_INTERP_PAPER) {
@@ -458,8 +487,8 @@ __device__ __forceinline__ float err_ratio(float a, float b) { return a * __buil
 __device__ __forceinline__ double err_ratio(double a, double b) { return a / b; }
 
 // gather variants of the stepping kernel: direct corner loads, the LDS cell
-// cache (FP32 or BF16 storage, FP32 stepping, one field below 2 GiB) and the
-// register cell cache (FP32 or BF16 storage, FP32 stepping)
+// cache and the register cell cache (the caches: FP32 or BF16 storage, FP32
+// stepping, one field below 2 GiB)
 constexpr int kGatherDirect = 0, kGatherLds = 1, kGatherRegs = 2;
 
 // one RHS evaluation of the stepping kernel
@@ -467,12 +496,12 @@ template <typename T, typename S, int MODE, int GATHER>
 __device__ __forceinline__ T rhs_step(const S *__restrict__ nodes, __amdgpu_buffer_rsrc_t rsrc, int bytes,
                                       const Geom &g, const int ib[3], const T q[3], T sigma, const T d1[3],
                                       const T d2[3], T kx[3], T k1[3], T k2[3], int cc[3], float4 *slot,
-                                      int stride, int64_t &cell, float (&cw)[24])
+                                      int stride, int &cell, Brick &br)
 {
     if constexpr (GATHER == kGatherLds)
         return rhs_cached<T, S, MODE>(rsrc, bytes, g, ib, q, sigma, d1, d2, kx, k1, k2, cc, slot, stride);
     else if constexpr (GATHER == kGatherRegs)
-        return rhs_regs<T, S, MODE>(nodes, g, ib, q, sigma, d1, d2, kx, k1, k2, cell, cw);
+        return rhs_regs<T, S, MODE>(rsrc, bytes, g, ib, q, sigma, d1, d2, kx, k1, k2, cell, br);
     else
         return rhs<T, S, MODE>(nodes, g, ib, q, sigma, d1, d2, kx, k1, k2);
 }
@@ -695,9 +724,9 @@ __global__ void k_land_compact(TraceJob job)
 template <typename T, typename S, int MODE, int GATHER, bool BATCH>
 __global__ void __launch_bounds__(256) k_trace(TraceJob job)
 {
-    static_assert(!(GATHER == kGatherLds && BATCH), "the LDS cell cache needs one field per launch");
-    static_assert(GATHER == kGatherDirect || sizeof(T) == 4, "cell caches hold FP32 corner values");
-    constexpr bool CACHED = GATHER == kGatherLds;
+    static_assert(GATHER == kGatherDirect || (!BATCH && sizeof(T) == 4),
+                  "cell caches: one field per launch, FP32 corner values");
+    constexpr bool CACHED = GATHER != kGatherDirect;
     // field and step limits of the lane's line: launch constants for one
     // field, reloaded from the set table at each refill in a batch
     const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
@@ -730,10 +759,8 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
     const int stride = (int)blockDim.x;
     float4 *slot = lds_cache + threadIdx.x;
     // register cell cache: the corners of the cell a lane evaluated last
-    int64_t reg_cell = -1;
-    float reg_corner[24];
-#pragma unroll
-    for (int k = 0; k < 24; ++k) reg_corner[k] = 0.0f;
+    int reg_cell = -1;
+    Brick reg_brick = {};
 
     // Work distribution: the first item of every lane is its global lane index
     // (the launcher starts the counter at the launch's lane count); after that
@@ -786,7 +813,6 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
                         hmax = (T)sd.h_max;
 #pragma unroll
                         for (int d = 0; d < 3; ++d) ih[d] = (T)gl.ih[d];
-                        reg_cell = -1;   // the line may belong to another field
                     }
                     sigma = dir ? (T)-1 : (T)1;
                     const int64_t P = 2 * job.rec.cap;
@@ -833,7 +859,7 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
             }
             if (!have_k1) {
                 const T un2 = rhs_step<T, S, MODE, GATHER>(nodes, rsrc, cbytes, g, ib, fb, (T)1, D1, D2, Kx[0], K1[0],
-                                                           K2[0], cache_cell, slot, stride, reg_cell, reg_corner);
+                                                           K2[0], cache_cell, slot, stride, reg_cell, reg_brick);
                 ++c_ev;
                 if (!(un2 >= (T)1e-12)) stop = QSQ_END_NULL;
                 have_k1 = true;
@@ -870,7 +896,7 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
             d2[i] = fma(hsig, a2, D2[i]);                                                           \
         }                                                                                           \
         rhs_step<T, S, MODE, GATHER>(nodes, rsrc, cbytes, g, ib, q, (T)1, d1, d2, Kx[ST], K1[ST], K2[ST], \
-                                     cache_cell, slot, stride, reg_cell, reg_corner);               \
+                                     cache_cell, slot, stride, reg_cell, reg_brick);               \
     }
             QSQ_STAGE(1, (T)ck::a21)
             QSQ_STAGE(2, (T)ck::a31, (T)ck::a32)
@@ -1499,15 +1525,13 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
     const void *kern;
     size_t lds = 0;
     constexpr bool cacheable = sizeof(T) == 4 && (std::is_same<S, float>::value || std::is_same<S, Bf16>::value);
-    if constexpr (BATCH && cacheable) {
-        kern = gather == 3 ? reinterpret_cast<const void *>(&k_trace<T, S, MODE, kGatherRegs, true>)
-                           : reinterpret_cast<const void *>(&k_trace<T, S, MODE, kGatherDirect, true>);
-    } else if constexpr (cacheable) {
-        // the LDS cache addresses the node records with 32-bit byte offsets
+    if constexpr (cacheable && !BATCH) {
+        // the cell caches address the node records with 32-bit byte offsets
         const uint64_t field_bytes = (uint64_t)node_bytes<S>() * job.g.n[0] * job.g.n[1] * job.g.n[2];
-        if (gather == 3 || gather == 0) {
+        const bool fits = field_bytes < ((uint64_t)1 << 31) - ((uint64_t)1 << 26);
+        if ((gather == 3 || gather == 0) && fits) {
             kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, kGatherRegs, false>);
-        } else if (gather == 2 && field_bytes < ((uint64_t)1 << 31) - ((uint64_t)1 << 26)) {
+        } else if (gather == 2 && fits) {
             kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, kGatherLds, false>);
             lds = kCachePlanes * wg * sizeof(float4);
         } else {

@@ -185,10 +185,11 @@ def test_launch_shapes_give_identical_results(storage):
     assert autotune.describe(word)["workgroup"] in (128, 256)
 
 
-def test_batch_register_cache_matches_direct():
-    """The batched launch with the register cell cache (invalidated whenever a
-    lane takes a line of another field) against direct corner loads: the same
-    results bit for bit, FP32 and BF16 records."""
+def test_batch_register_cache_word_runs_direct():
+    """Batches lay lines of many fields side by side in a wave, so the cell
+    caches do not apply: a batched call with the register-cache word runs the
+    direct loads and gives the same results bit for bit, FP32 and BF16
+    records."""
     import torch
 
     from paper_1609_00724_amd import _abi as A
@@ -200,7 +201,7 @@ def test_batch_register_cache_matches_direct():
         pairs = [(fg, torch.from_numpy(f["seeds"]).to(dev)) for fg, f in zip(fields, sets)]
         res = []
         for word in (A.launch_word(2, 64, A.GATHER_DIRECT), A.launch_word(2, 64, A.GATHER_REGS),
-                     A.launch_word(0, 256, A.GATHER_REGS)):
+                     A.launch_word(0, 256, A.GATHER_AUTO)):
             plan = TraceBatchPlan(pairs, make_opts(1e-4, 1e-4, step_dtype="f32", launch=word), want_steps=True)
             plan.run()
             torch.cuda.synchronize()

@@ -106,7 +106,7 @@ def main():
     field = q.field_init(*b, w["origin"], w["spacing"], storage="f32")
     m, r = args.base_level, args.refine_levels
     spec = MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, r, m, args.threshold, args.refine_batch)
-    plan = QMapPlan(spec, 4 ** m * 4, dev)
+    plan = QMapPlan(spec, 4 ** (m + r), dev)    # the finest lattice: the map cannot overflow
     hmax = args.hmax_cells * h
     opts = make_opts(args.tol, args.tol, h_init=0.1 * h, h_max=hmax, step_dtype="f32")
     stream = torch.cuda.current_stream()

@@ -811,11 +811,21 @@ __global__ void k_merge_sorted(Samples a, const int64_t *na_p, Samples nw, const
 // possible firing gap (at most one per sample), no round takes fewer than
 // batch levels and ceil(levels / batch) rounds suffice; otherwise a round may
 // fall back to fewer levels and up to one round per level is enqueued.
-static int planned_rounds(int levels, int batch, int64_t slots, int64_t capacity)
+// Rounds to enqueue.  A round takes the most levels (up to batch) for which
+// the speculative keys of every firing pair fit the trace slots, and a round
+// over n samples fires at most n pairs: the first round starts from `first`
+// samples, later ones from at most `capacity`.  Enough rounds for the fewest
+// levels per round are enqueued; rounds after the last level are no-ops.
+static int planned_rounds(int levels, int batch, int64_t slots, int64_t first, int64_t capacity)
 {
     if (levels <= 0) return 0;
-    if ((double)slots >= (double)capacity * (double)((1 << batch) - 1)) return (levels + batch - 1) / batch;
-    return levels;
+    auto most = [&](int64_t n) {
+        int D = batch < levels ? batch : levels;
+        while (D > 1 && (double)n * (double)((1 << D) - 1) > (double)slots) --D;
+        return D;
+    };
+    const int rem = levels - most(first), later = most(capacity);
+    return 1 + (rem + later - 1) / later;
 }
 
 // One refined map of a slice (DIM 2) or volume (DIM 3): base lattice, trace,
@@ -920,7 +930,7 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
         step = 1;
         batch = 1;
     }
-    const int rounds = planned_rounds(levels, batch, Lo.tcap, cap);
+    const int rounds = planned_rounds(levels, batch, Lo.tcap, step ? cap : nb, cap);
     int round = 0;
     for (; round < rounds; ++round) {
         int64_t *cin = &counts[step + round], *cout = &counts[step + round + 1];

@@ -197,16 +197,29 @@ def test_map_without_refinement(oracle_mod, c2):
     _sample_parity(oracle_mod, c2, res, np.arange(0, 4 ** m, 7), m, 0)
 
 
-@pytest.mark.parametrize("r", [2, 3])
-def test_refine_batches_give_identical_maps(c2, r):
+@pytest.mark.parametrize("r,tight", [(2, False), (3, False), (2, True), (3, True)])
+def test_refine_batches_give_identical_maps(c2, r, tight):
     """Deciding several refinement levels per device round (tracing every key
     those levels could insert, then applying the rule) keeps exactly the
-    samples of the pass-by-pass rule: every batch size gives the same arrays."""
+    samples of the pass-by-pass rule: every batch size gives the same arrays.
+    With the full finest lattice as capacity one round can take every level;
+    with a capacity of exactly the refined sample count the rounds are planned
+    for fewer levels each, so rounds run with fewer levels than the batch or
+    as no-ops at the end; the arrays stay the same."""
     m, thr = 6, 0.02
     ref = _run_map(c2, m, r, thr, m + r, 4 ** (m + r), batch=1)
-    assert ref["count"] > 4 ** m
+    assert ref["count"] > 4 ** m and ref["overflow"] == 0
+    cap = 4 ** (m + r)
+    if tight:
+        cap = ref["count"]
+        assert cap < 15 * 4 ** m            # the first round cannot be planned for 4 levels
+        tight_ref = _run_map(c2, m, r, thr, m + r, cap, batch=1)
+        assert tight_ref["overflow"] == 0
+        for k in ("keys", "fll", "q_perp", "status", "q_grid"):
+            assert np.array_equal(tight_ref[k], ref[k], equal_nan=True), k
     for b in (2, 3, 4, 5):
-        res = _run_map(c2, m, r, thr, m + r, 4 ** (m + r), batch=b)
+        res = _run_map(c2, m, r, thr, m + r, cap, batch=b)
+        assert res["overflow"] == 0, b
         assert res["count"] == ref["count"], b
         for k in ("keys", "fll", "q_perp", "status"):
             assert np.array_equal(res[k], ref[k], equal_nan=True), (b, k)
@@ -265,7 +278,7 @@ def test_full_photospheric_map_sampled(oracle_mod, c2, step_dtype):
     oracle checks on a sample of lines, converter cells, and the whole FLEDGE.
     FP64 stepping must match the oracle on every sampled line."""
     m, r, thr = 10, 2, 0.02
-    res = _run_map(c2, m, r, thr, m, 4 ** m * 4, step_dtype)
+    res = _run_map(c2, m, r, thr, m, 4 ** (m + r), step_dtype)
     n = res["count"]
     assert res["overflow"] == 0 and n > 4 ** m
     _check_complete(res, thr)

@@ -701,21 +701,28 @@ __global__ void k_sort_keys(TraceJob job, int bits)
     }
 }
 
-// The landing list: the stepped half-lines (work list order, so in spatial
-// or curve order like the stepping) that the stepping pass left outside the
-// box.  Flags over work-list positions, then a compaction into work2.
+// The landing list: the half-lines that the stepping pass left outside the
+// box, in record order (forward halves, then backward ones, each in seed
+// order), so that the landing kernels read and write the record planes in
+// runs rather than in the work list's (spatial) order.  Flags over the half-
+// line records, then a compaction into work2.
+__device__ __forceinline__ int64_t half_record(const TraceJob &job, int64_t it, int64_t n)
+{
+    return it >= n ? job.rec.cap + (it - n) : it;
+}
+
 __global__ void k_land_flags(TraceJob job)
 {
-    const int64_t nw = *job.rec.n_work;
-    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (int64_t)gridDim.x * blockDim.x)
-        job.rec.flag[w] = job.rec.status[job.rec.work[w]] == kPendingLand ? 1 : 0;
+    const int64_t n2 = *job.rec.n_items, n = n2 / 2;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n2; it += (int64_t)gridDim.x * blockDim.x)
+        job.rec.flag[it] = job.rec.status[half_record(job, it, n)] == kPendingLand ? 1 : 0;
 }
 
 __global__ void k_land_compact(TraceJob job)
 {
-    const int64_t nw = *job.rec.n_work;
-    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (int64_t)gridDim.x * blockDim.x)
-        if (job.rec.flag[w]) job.rec.work2[job.rec.wpos[w]] = job.rec.work[w];
+    const int64_t n2 = *job.rec.n_items, n = n2 / 2;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n2; it += (int64_t)gridDim.x * blockDim.x)
+        if (job.rec.flag[it]) job.rec.work2[job.rec.wpos[it]] = (int32_t)half_record(job, it, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -1047,7 +1054,7 @@ __device__ void ck54_fp64(const S *__restrict__ nodes, const Geom &g, double sig
 // position components of ck54_fp64.
 template <typename S, int MODE>
 __device__ void ck54_pos(const S *__restrict__ nodes, const Geom &g, double sigma, const double y[3], double hs,
-                         double yo[3], double *slope0 = nullptr)
+                         double yo[3], double *slope0 = nullptr, const double *k1 = nullptr)
 {
     double K[6][3];
     const double A[6][5] = {{0, 0, 0, 0, 0},
@@ -1067,6 +1074,13 @@ __device__ void ck54_pos(const S *__restrict__ nodes, const Geom &g, double sigm
     }
 #pragma unroll
     for (int st = 0; st < 6; ++st) {
+        if (st == 0 && k1) {
+            // the first stage sits at y whatever the step length: a caller
+            // that took a step from y already has it
+#pragma unroll
+            for (int i = 0; i < 3; ++i) K[0][i] = k1[i];
+            continue;
+        }
         double q[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -1119,13 +1133,13 @@ __device__ __forceinline__ double beyond_face(const Geom &g, const double *x, in
 
 template <typename S, int MODE>
 __device__ double face_gap(const S *nodes, const Geom &g, double sigma, const double y[3], double hs,
-                           int f, double yo[3])
+                           int f, double yo[3], const double k1[3])
 {
     if (hs == 0.0) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) yo[i] = y[i];
     } else {
-        ck54_pos<S, MODE>(nodes, g, sigma, y, hs, yo);
+        ck54_pos<S, MODE>(nodes, g, sigma, y, hs, yo, nullptr, k1);
     }
     return beyond_face(g, yo, f);
 }
@@ -1178,7 +1192,7 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
             // Illinois regula falsi for the step length ending on face f
             double yo[3];
             double a = 0.0, b = hs;
-            double ga = face_gap<S, MODE>(nodes, g, sigma, y, a, f, yo);
+            double ga = face_gap<S, MODE>(nodes, g, sigma, y, a, f, yo, v0);
             double hf;
             if (ga >= 0.0) {
                 hf = 0.0;
@@ -1193,7 +1207,7 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
                 const double c0 = landing_guess(ga, s0, gb, hs);
                 for (int k = 0; k < 200; ++k) {
                     const double c = k == 0 ? c0 : (a * gb - b * ga) / (gb - ga);
-                    const double gc = face_gap<S, MODE>(nodes, g, sigma, y, c, f, yo);
+                    const double gc = face_gap<S, MODE>(nodes, g, sigma, y, c, f, yo, v0);
                     if (fabs(gc) <= gtol) {
                         hf = c;
                         break;
@@ -1557,9 +1571,9 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
     int64_t lb = (2 * n_max + 255) / 256;
     int lblocks = (int)(lb < (int64_t)cus * 16 ? lb : (int64_t)cus * 16);
     if (prof) prof_begin(kProfLand, st, &tok);
-    // list of the half-lines to land, in work-list order
+    // list of the half-lines to land, in record order
     hipLaunchKernelGGL(k_land_flags, dim3(cblocks), dim3(256), 0, st, job);
-    launch_scan_i32(job.rec.flag, job.rec.n_work, 2 * n_max, job.rec.scan_tmp, job.rec.wpos, job.rec.n_land, st);
+    launch_scan_i32(job.rec.flag, job.rec.n_items, 2 * n_max, job.rec.scan_tmp, job.rec.wpos, job.rec.n_land, st);
     hipLaunchKernelGGL(k_land_compact, dim3(cblocks), dim3(256), 0, st, job);
     hipLaunchKernelGGL((k_land<S, MODE, BATCH>), dim3(lblocks), dim3(256), 0, st, job);
     hipLaunchKernelGGL((k_land_final<S, MODE, BATCH>), dim3(lblocks), dim3(256), 0, st, job);

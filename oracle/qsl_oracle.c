@@ -29,6 +29,9 @@
  *   - boundary landing: the step that leaves the closed box is re-solved for
  *     the step length at which its 5th-order solution lies on the first face
  *     crossed (Illinois regula falsi on the signed distance), then snapped;
+ *     an Euler step is cut in closed form where it meets that face;
+ *   - the explicit Euler scheme (Sect. 3.4) takes fixed steps h_init on the
+ *     whole state (x, dx1, dx2), one right-hand side per step;
  *   - the frame (a, b) completing Bhat(x0) is the branchless construction of
  *     Duff et al. 2017 (JCGT 6(1)); Q does not depend on this choice.
  */
@@ -84,8 +87,11 @@ typedef struct {
     int64_t max_steps;     /* accepted + rejected attempts per half-line */
     double frame_angle;    /* rotate (a, b) about Bhat(x0) by this angle */
     int32_t nthreads;      /* <= 0: OpenMP default */
-    int32_t pad;
+    int32_t stepper;       /* OR_CK54 (adaptive) or OR_EULER (fixed step h_init) */
 } or_opts;
+
+/* steppers (Sect. 3.4) */
+enum { OR_CK54 = 0, OR_EULER = 1 };
 
 /* BF16 value of x: x rounded to FP32, then to the nearest BF16 (8-bit
  * significand), ties to even; finite inputs only */
@@ -424,8 +430,87 @@ static double land_on_face(const or_field *F, double sigma, const double y[9], d
     return ga > -gb ? a : b;  /* smaller |g| of the bracket ends */
 }
 
+/* Explicit Euler with a fixed step h_init (Sect. 3.4): y <- y + h f(y) on the
+ * whole state (x, dx1, dx2).  There is no error control.  The step whose end
+ * leaves the box is cut where it meets the first face it crosses: the end of
+ * an Euler step moves linearly with the step length, so that length is the
+ * distance to the face divided by the step's rate towards it; the state is
+ * taken there and the position snapped to the face. */
+static void trace_half_euler(const or_field *F, const or_opts *O, double sigma, const double y0[9],
+                             or_half *out)
+{
+    double y[9], dy[9], y1[9];
+    memcpy(y, y0, sizeof y);
+    double s = 0.0;
+    const double h = O->h_init;
+    out->accepted = out->rejected = out->land_iters = 0;
+    out->status = -1;
+    for (;;) {
+        if (out->accepted >= O->max_steps) {
+            out->status = OR_MAX_STEPS;
+            break;
+        }
+        {   /* null: the interpolated unit field has (nearly) vanished here */
+            double u[3], J[3][3], bm;
+            field_eval(F, y, u, J, &bm);
+            if (sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) < 1e-6) {
+                out->status = OR_NULL;
+                break;
+            }
+        }
+        double hs = h;
+        int last = 0;
+        if (O->max_length > 0.0 && hs >= O->max_length - s) {
+            hs = O->max_length - s;
+            last = 1;
+        }
+        rhs(F, sigma, y, dy);
+        for (int i = 0; i < 9; ++i) y1[i] = y[i] + hs * dy[i];
+        if (!all_finite(y1, 9)) {
+            out->status = OR_NONFINITE;
+            break;
+        }
+        ++out->accepted;
+        if (outside(F, y1)) {
+            double best = INFINITY;
+            int face = -1;
+            for (int f = 0; f < 6; ++f) {
+                int d = f / 2;
+                double wall = (f & 1) ? F->d.hi[d] : F->d.lo[d];
+                double g = (f & 1) ? y1[d] - wall : wall - y1[d];
+                if (!(g > 0.0)) continue;
+                double hf = (wall - y[d]) / dy[d];
+                hf = hf < 0.0 ? 0.0 : (hf > hs ? hs : hf);
+                if (hf < best) {
+                    best = hf;
+                    face = f;
+                }
+            }
+            for (int i = 0; i < 9; ++i) y[i] = y[i] + best * dy[i];
+            int d = face / 2;
+            y[d] = (face & 1) ? F->d.hi[d] : F->d.lo[d];
+            s += best;
+            out->status = face;
+            break;
+        }
+        memcpy(y, y1, sizeof y);
+        if (last) {
+            s = O->max_length;
+            out->status = OR_MAX_LENGTH;
+            break;
+        }
+        s += hs;
+    }
+    memcpy(out->y, y, sizeof y);
+    out->s = s;
+}
+
 static void trace_half(const or_field *F, const or_opts *O, double sigma, const double y0[9], or_half *out)
 {
+    if (O->stepper == OR_EULER) {
+        trace_half_euler(F, O, sigma, y0, out);
+        return;
+    }
     double y[9], y5[9], y4[9];
     memcpy(y, y0, sizeof y);
     double s = 0.0, h = O->h_init;

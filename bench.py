@@ -33,8 +33,10 @@ METRIC = "field lines traced with Q per sec (1 GPU) + % HBM/L2 roofline at fixed
 #  per step attempt: Cash-Karp stage inputs for stages 2..6 on 9 components
 #  (378), 5th-order combination (63), error combination (81), update (18),
 #  error norm (54), controller (6)                                     -> 600
+#  per explicit Euler step: the update of 9 components (18)            -> 18
 FLOP_PER_EVAL = 147
 FLOP_PER_ATTEMPT = 600
+FLOP_PER_EULER_STEP = 18
 # VALU ceiling for this kernel: 256 CUs x 4 SIMD x 16 lanes x 2 FLOP (FMA) x
 # 2.4 GHz; packed FP32 is disabled in the build, so the packed-FP32 rate
 # (157.3 TFLOP/s) is out of reach and is not the ceiling.
@@ -52,6 +54,8 @@ def parse():
     ap.add_argument("--threshold", type=float, default=0.02)
     ap.add_argument("--refine-batch", type=int, default=0, help="refinement levels per device round (0: auto)")
     ap.add_argument("--hmax-cells", type=float, default=1.0, help="largest step, in grid cells")
+    ap.add_argument("--stepper", choices=("ck54", "euler"), default="ck54",
+                    help="map workload: adaptive Cash-Karp 5(4), or explicit Euler with fixed steps of 1/5 cell")
     ap.add_argument("--cpu-level", type=int, default=10, help="base level of the oracle's sample map (10: the whole map)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy leg")
@@ -108,7 +112,10 @@ def main():
     spec = MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, r, m, args.threshold, args.refine_batch)
     plan = QMapPlan(spec, 4 ** (m + r), dev)    # the finest lattice: the map cannot overflow
     hmax = args.hmax_cells * h
-    opts = make_opts(args.tol, args.tol, h_init=0.1 * h, h_max=hmax, step_dtype="f32")
+    if args.stepper == "euler":
+        opts = make_opts(args.tol, args.tol, step_dtype="f32", stepper="euler")   # fixed step h / 5
+    else:
+        opts = make_opts(args.tol, args.tol, h_init=0.1 * h, h_max=hmax, step_dtype="f32")
     stream = torch.cuda.current_stream()
 
     tuned = None
@@ -149,7 +156,8 @@ def main():
     ms_per_step = ms_total / args.steps
     value = lines / (ms_per_step / 1e3)
 
-    flops = FLOP_PER_EVAL * evals + FLOP_PER_ATTEMPT * attempts
+    per_attempt = FLOP_PER_EULER_STEP if args.stepper == "euler" else FLOP_PER_ATTEMPT
+    flops = FLOP_PER_EVAL * evals + per_attempt * attempts
     achieved = flops / (ms_step / 1e3) / 1e12 if ms_step > 0 else 0.0
     out = {
         "metric": METRIC,
@@ -167,7 +175,9 @@ def main():
         "config": {
             "workload": (f"photospheric Q/FLL/FLEDGE map, 4-charge potential field on a 256x256x128 FP32 grid, "
                          f"{1 << m}^2 base lines + FLL-jump Hilbert refinement r={r} thr={args.threshold}, "
-                         f"CK54 FP32 stepping tol={args.tol:g} h_max={args.hmax_cells:g} cell, FP64 landing and Q"),
+                         + (f"CK54 FP32 stepping tol={args.tol:g} h_max={args.hmax_cells:g} cell"
+                            if args.stepper == "ck54" else "explicit Euler FP32 stepping, fixed step 1/5 cell")
+                         + ", FP64 landing and Q"),
             "lines_per_step": lines,
             "base_lines": 4 ** m,
             "grid": [256, 256, 128],
@@ -570,9 +580,11 @@ def cpu_baseline_volume(args, w, h):
     fo = _oracle_field(w)
     box = oracle.VolumeBox(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0)
 
+    euler = args.stepper == "euler"
+
     def fn(p):
-        t = oracle.trace(fo, p, rtol=args.tol, atol=args.tol, h_init=0.1 * h, h_max=args.hmax_cells * h,
-                         nthreads=threads)
+        t = oracle.trace(fo, p, rtol=args.tol, atol=args.tol, h_init=0.2 * h if euler else 0.1 * h,
+                         h_max=0.2 * h if euler else args.hmax_cells * h, nthreads=threads, stepper=args.stepper)
         return {"fll": t["fll"], "q": t["q_perp"]}
 
     t0 = time.perf_counter()
@@ -843,8 +855,12 @@ def accuracy(args, field, w, h, hmax):
     import paper_1609_00724_amd as q
     import synth
     seeds = synth.random_seeds(2024, args.accuracy_lines, z=0.0)
-    g = q.trace(field, torch.from_numpy(seeds).cuda(), rtol=args.tol, atol=args.tol,
-                h_init=0.1 * h, h_max=hmax, step_dtype="f32")
+    if args.stepper == "euler":
+        g = q.trace(field, torch.from_numpy(seeds).cuda(), rtol=args.tol, atol=args.tol, step_dtype="f32",
+                    stepper="euler")
+    else:
+        g = q.trace(field, torch.from_numpy(seeds).cuda(), rtol=args.tol, atol=args.tol,
+                    h_init=0.1 * h, h_max=hmax, step_dtype="f32")
     torch.cuda.synchronize()
     qg = g["q_perp"].cpu().numpy()
     o = oracle.trace(_oracle_field(w), seeds, rtol=1e-10, atol=1e-10, h_init=0.1 * h, h_max=h)
@@ -865,9 +881,11 @@ def cpu_baseline(args, w, h):
     fo = _oracle_field(w)
     plane = oracle.SlicePlane(0.0, -1.0, 1.0, -1.0, 1.0)
 
+    euler = args.stepper == "euler"
+
     def fn(p):
-        t = oracle.trace(fo, p, rtol=args.tol, atol=args.tol, h_init=0.1 * h, h_max=args.hmax_cells * h,
-                         nthreads=threads)
+        t = oracle.trace(fo, p, rtol=args.tol, atol=args.tol, h_init=0.2 * h if euler else 0.1 * h,
+                         h_max=0.2 * h if euler else args.hmax_cells * h, nthreads=threads, stepper=args.stepper)
         return {"fll": t["fll"], "q": t["q_perp"]}
 
     t0 = time.perf_counter()

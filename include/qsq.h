@@ -59,7 +59,8 @@ extern "C" {
 #define QSQ_INTERP_NORMALIZE 1
 
 /* steppers (Sect. 3.4) */
-#define QSQ_STEPPER_CK54 0
+#define QSQ_STEPPER_CK54 0   /* adaptive Cash-Karp 5(4) */
+#define QSQ_STEPPER_EULER 1  /* explicit Euler, fixed step h_init */
 
 /* outcome of one half-line: the exit face (the box is left through it) or why
  * tracing stopped elsewhere */
@@ -103,7 +104,13 @@ typedef struct qsq_field {
 } qsq_field;
 
 typedef struct qsq_trace_opts {
-    int32_t stepper;       /* QSQ_STEPPER_CK54 */
+    int32_t stepper;       /* QSQ_STEPPER_CK54, or QSQ_STEPPER_EULER: fixed steps
+                              h_init (0: one fifth of the smallest grid
+                              spacing) of the line and both deviation
+                              vectors, one field evaluation per step, no error
+                              control (rtol and atol are validated but unused,
+                              h_max unused); the step that leaves the box is
+                              cut where it meets the first face it crosses */
     int32_t step_dtype;    /* QSQ_F32: stage arithmetic in FP32, position and
                               length accumulated in FP64; QSQ_F64: all FP64.
                               Boundary landing and Q assembly are always FP64. */

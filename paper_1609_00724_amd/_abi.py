@@ -17,6 +17,7 @@ ERR_COUNT_OVERFLOW = -5
 F64, F32, BF16 = 0, 1, 2
 INTERP_PAPER, INTERP_NORMALIZE = 0, 1
 STEPPER_CK54 = 0
+STEPPER_EULER = 1
 FLAG_SKIP_OPEN = 1
 
 END_XLO, END_XHI, END_YLO, END_YHI, END_ZLO, END_ZHI = range(6)

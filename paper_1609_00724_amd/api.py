@@ -72,10 +72,16 @@ def field_init(bx, by, bz, origin, spacing, storage="f32", mode="paper", stream=
     return Field(d, ws)
 
 
+_STEPPER = {"ck54": A.STEPPER_CK54, "euler": A.STEPPER_EULER}
+
+
 def make_opts(rtol, atol, h_init=0.0, h_max=0.0, max_length=0.0, max_steps=0, step_dtype="f32",
-              skip_open=False, launch=0) -> A.TraceOpts:
+              skip_open=False, launch=0, stepper="ck54") -> A.TraceOpts:
+    """Trace options.  stepper "ck54": adaptive Cash-Karp 5(4) with rtol, atol,
+    first step h_init, largest step h_max; "euler": explicit Euler with the
+    fixed step h_init (0: one fifth of the smallest grid spacing)."""
     o = A.TraceOpts()
-    o.stepper = A.STEPPER_CK54
+    o.stepper = _STEPPER[stepper]
     o.step_dtype = _DT[step_dtype]
     o.rtol, o.atol = float(rtol), float(atol)
     o.h_init, o.h_max, o.max_length = float(h_init), float(h_max), float(max_length)
@@ -113,7 +119,7 @@ class TracePlan:
 
 
 def trace(field: Field, seeds, *, rtol, atol, h_init=0.0, h_max=0.0, max_length=0.0, max_steps=0,
-          step_dtype="f32", skip_open=False, want_steps=False, want_work=False, stream=None):
+          step_dtype="f32", skip_open=False, want_steps=False, want_work=False, stream=None, stepper="ck54"):
     """Trace seeds, a device tensor of shape (n, 3) (one row per seed), both ways.
 
     Returns device tensors: fp_fwd, fp_bwd (3, n) SoA planes; fll, q_perp, q_det,
@@ -125,7 +131,7 @@ def trace(field: Field, seeds, *, rtol, atol, h_init=0.0, h_max=0.0, max_length=
     soa = seeds.t().contiguous()
     n = soa.shape[1]
     plan = TracePlan(n, seeds.device, want_steps=want_steps, want_work=want_work)
-    opts = make_opts(rtol, atol, h_init, h_max, max_length, max_steps, step_dtype, skip_open)
+    opts = make_opts(rtol, atol, h_init, h_max, max_length, max_steps, step_dtype, skip_open, stepper=stepper)
     return plan.run(field, soa, opts, stream)
 
 
@@ -177,10 +183,10 @@ class TraceBatchPlan:
 
 
 def trace_batch(sets, *, rtol, atol, h_init=0.0, h_max=0.0, max_length=0.0, max_steps=0, step_dtype="f32",
-                skip_open=False, want_steps=False, want_work=False, stream=None):
+                skip_open=False, want_steps=False, want_work=False, stream=None, stepper="ck54"):
     """Trace several (field, seeds (n, 3)) sets in one batched call; returns one
     output dict per set (as trace()) and, if asked, the summed work counters."""
-    opts = make_opts(rtol, atol, h_init, h_max, max_length, max_steps, step_dtype, skip_open)
+    opts = make_opts(rtol, atol, h_init, h_max, max_length, max_steps, step_dtype, skip_open, stepper=stepper)
     plan = TraceBatchPlan(sets, opts, want_steps=want_steps, want_work=want_work)
     outs = plan.run(stream)
     return (outs, plan.work) if want_work else outs
@@ -332,9 +338,9 @@ class QMapPlan:
 
 
 def qmap(field: Field, spec, capacity: int, *, rtol, atol, h_init=0.0, h_max=0.0,
-         max_length=0.0, max_steps=0, step_dtype="f32", skip_open=False, stream=None):
+         max_length=0.0, max_steps=0, step_dtype="f32", skip_open=False, stream=None, stepper="ck54"):
     plan = QMapPlan(spec, capacity, field.ws.device)
-    opts = make_opts(rtol, atol, h_init, h_max, max_length, max_steps, step_dtype, skip_open)
+    opts = make_opts(rtol, atol, h_init, h_max, max_length, max_steps, step_dtype, skip_open, stepper=stepper)
     plan.run(field, opts, stream)
     return plan.result()
 

@@ -70,7 +70,8 @@ int check_field(const qsq_field *f)
 int make_geom_opts(const qsq_field *f, const qsq_trace_opts *o, qsq::Geom *g, qsq::StepOpts *so)
 {
     if (!o) return fail(QSQ_ERR_INVALID_ARG, "opts is NULL");
-    if (o->stepper != QSQ_STEPPER_CK54) return fail(QSQ_ERR_UNSUPPORTED, "stepper %d not supported", o->stepper);
+    if (o->stepper != QSQ_STEPPER_CK54 && o->stepper != QSQ_STEPPER_EULER)
+        return fail(QSQ_ERR_UNSUPPORTED, "stepper %d not supported", o->stepper);
     if (o->step_dtype != QSQ_F32 && o->step_dtype != QSQ_F64)
         return fail(QSQ_ERR_UNSUPPORTED, "step dtype %d not supported", o->step_dtype);
     if (!(o->rtol > 0.0) || !(o->atol > 0.0) || !isfinite(o->rtol) || !isfinite(o->atol))
@@ -98,12 +99,19 @@ int make_geom_opts(const qsq_field *f, const qsq_trace_opts *o, qsq::Geom *g, qs
     so->h_max = o->h_max > 0.0 ? o->h_max : hmin_grid;
     so->h_init = o->h_init > 0.0 ? o->h_init : 0.1 * hmin_grid;
     if (so->h_init > so->h_max) so->h_init = so->h_max;
+    if (o->stepper == QSQ_STEPPER_EULER) {
+        // fixed step: about five samplings per grid spacing unless given
+        so->h_init = o->h_init > 0.0 ? o->h_init : 0.2 * hmin_grid;
+        so->h_max = so->h_init;
+    }
     so->max_length = o->max_length > 0.0 ? o->max_length : 0.0;
     so->hmin = 1e-12 * extent;
     so->gtol = 1e-12 * extent;
     so->max_steps = o->max_steps > 0 ? o->max_steps : (int64_t)1 << 22;
     so->flags = o->flags;
     so->launch = o->launch;
+    so->stepper = o->stepper;
+    so->pad = 0;
     return QSQ_OK;
 }
 

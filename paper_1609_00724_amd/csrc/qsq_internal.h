@@ -44,6 +44,8 @@ struct StepOpts {
     int64_t max_steps;
     int flags;
     int launch;          // QSQ_LAUNCH word (0: defaults)
+    int stepper;         // QSQ_STEPPER_*
+    int pad;
 };
 
 // Per half-line end records, SoA planes of length 2*cap; half-line (dir, seed)

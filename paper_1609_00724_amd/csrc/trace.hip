@@ -728,8 +728,9 @@ __global__ void k_land_compact(TraceJob job)
 // ---------------------------------------------------------------------------
 // k_trace: persistent stepping kernel
 // ---------------------------------------------------------------------------
-template <typename T, typename S, int MODE, int GATHER, bool BATCH>
-__global__ void __launch_bounds__(256) k_trace(TraceJob job)
+// (the Euler variants fit 3 waves per SIMD: one evaluation's state per step)
+template <typename T, typename S, int MODE, int GATHER, bool BATCH, bool EULER = false>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EULER ? 3 : 1))) k_trace(TraceJob job)
 {
     static_assert(GATHER == kGatherDirect || (!BATCH && sizeof(T) == 4),
                   "cell caches: one field per launch, FP32 corner values");
@@ -864,7 +865,7 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
                 ib[d] = (int)fl;
                 fb[d] = (T)(xg - fl);
             }
-            if (!have_k1) {
+            if (!EULER && !have_k1) {
                 const T un2 = rhs_step<T, S, MODE, GATHER>(nodes, rsrc, cbytes, g, ib, fb, (T)1, D1, D2, Kx[0], K1[0],
                                                            K2[0], cache_cell, slot, stride, reg_cell, reg_brick);
                 ++c_ev;
@@ -872,7 +873,61 @@ __global__ void __launch_bounds__(256) k_trace(TraceJob job)
                 have_k1 = true;
             }
         }
-        if (stop < 0) {
+        if constexpr (EULER) {
+            // explicit Euler (Sect. 3.4): one evaluation at the current point
+            // per fixed step h, the whole state advanced along it
+            if (stop < 0) {
+                const T un2 = rhs_step<T, S, MODE, GATHER>(nodes, rsrc, cbytes, g, ib, fb, (T)1, D1, D2, Kx[0],
+                                                           K1[0], K2[0], cache_cell, slot, stride, reg_cell,
+                                                           reg_brick);
+                ++c_ev;
+                if (!(un2 >= (T)1e-12)) stop = QSQ_END_NULL;
+            }
+            if (stop < 0) {
+                T hs = h;
+                bool last = false;
+                if (o.max_length > 0.0 && (double)hs >= o.max_length - s) {
+                    hs = (T)(o.max_length - s);
+                    last = true;
+                }
+                const T hsig = sigma * hs;
+                double Xn[3];
+                T D1n[3], D2n[3], fsum = 0;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    Xn[i] = X[i] + (double)(hsig * Kx[0][i]);
+                    D1n[i] = fma(hsig, K1[0][i], D1[i]);
+                    D2n[i] = fma(hsig, K2[0][i], D2[i]);
+                    fsum += ((T)Xn[i] + D1n[i]) + D2n[i];
+                }
+                ++attempts;
+                ++c_att;
+                if (!isfinite(fsum)) {
+                    stop = QSQ_END_NONFINITE;
+                } else if (outside_box(g, Xn[0], Xn[1], Xn[2])) {
+                    // the step that leaves the box: cut at the face in FP64
+                    const double y[9] = {X[0], X[1], X[2], (double)D1[0], (double)D1[1], (double)D1[2],
+                                         (double)D2[0], (double)D2[1], (double)D2[2]};
+                    put_rec(job.rec, rec, y, s, (double)hs, kPendingLand, attempts);
+                    active = false;
+                    ++c_land;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        X[i] = Xn[i];
+                        D1[i] = D1n[i];
+                        D2[i] = D2n[i];
+                    }
+                    if (last) {
+                        s = o.max_length;
+                        stop = QSQ_END_MAX_LENGTH;
+                    } else {
+                        s += (double)hs;
+                    }
+                }
+            }
+        }
+        if (!EULER && stop < 0) {
             T hs = h < hmax ? h : hmax;
             bool last = false;
             if (o.max_length > 0.0 && (double)hs >= o.max_length - s) {
@@ -1281,6 +1336,86 @@ __global__ void __launch_bounds__(256) k_land_final(TraceJob job)
 }
 
 // ---------------------------------------------------------------------------
+// k_land_euler: FP64 landing of an explicit Euler step.  The end of an Euler
+// step moves linearly with its length, so the length that ends on face f is
+// the distance to the face over the step's rate towards it; the first face
+// crossed (the shortest such length; exact ties keep the lower face) takes
+// the line, the whole state is advanced by that length and the position
+// snapped to the face.
+// ---------------------------------------------------------------------------
+template <typename S, int MODE, bool BATCH>
+__global__ void __launch_bounds__(256) k_land_euler(TraceJob job)
+{
+    const int64_t total = *job.rec.n_land;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+         it += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = job.rec.work2[it];
+        const int dir = r >= job.rec.cap ? 1 : 0;
+        const int64_t i = dir ? r - job.rec.cap : r;
+        const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
+        Geom gl = job.g;
+        if constexpr (BATCH) {
+            const SetDesc &sd = job.sets[job.set_of[i]];
+            gl = sd.g;
+            nodes = static_cast<const S *>(sd.nodes);
+        }
+        const Geom &g = gl;
+        const double sigma = dir ? -1.0 : 1.0;
+        double y[9], s, hs;
+        get_rec(job.rec, r, y, s, hs);
+        double u[3], G[3][3], mag;
+        field_at_x<S, MODE, false>(nodes, g, y, u, G, mag);
+        double dy[9];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            dy[k] = sigma * u[k];
+            dy[3 + k] = sigma * (G[0][k] * y[3] + G[1][k] * y[4] + G[2][k] * y[5]);
+            dy[6 + k] = sigma * (G[0][k] * y[6] + G[1][k] * y[7] + G[2][k] * y[8]);
+        }
+        double best = INFINITY;
+        int face = -1;
+        for (int f = 0; f < 6; ++f) {
+            const int d = f >> 1;
+            const double wall = (f & 1) ? pick3(g.hi, d) : pick3(g.lo, d);
+            const double yd = pick3(y, d), vd = pick3(dy, d);
+            const double end = yd + hs * vd;
+            const double gap = (f & 1) ? end - wall : wall - end;
+            if (!(gap > 0.0)) continue;
+            double hf = (wall - yd) / vd;
+            hf = hf < 0.0 ? 0.0 : (hf > hs ? hs : hf);
+            if (hf < best) {
+                best = hf;
+                face = f;
+            }
+        }
+        double yl[9];
+        if (face < 0) {
+            // the FP32 step left the box but the FP64 one does not: end on
+            // the face nearest the FP64 end point of the full step
+            best = hs;
+            double gmax = -INFINITY;
+            for (int f = 0; f < 6; ++f) {
+                const int d = f >> 1;
+                const double end = pick3(y, d) + hs * pick3(dy, d);
+                const double gap = (f & 1) ? end - pick3(g.hi, d) : pick3(g.lo, d) - end;
+                if (gap > gmax) {
+                    gmax = gap;
+                    face = f;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) yl[k] = y[k] + best * dy[k];
+        const int d = face >> 1;
+        const double snap = (face & 1) ? pick3(g.hi, d) : pick3(g.lo, d);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (k == d) yl[k] = snap;
+        put_rec(job.rec, r, yl, s + best, 0.0, face, job.rec.attempts[r]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_assemble: FP64 Q and length per seed (eq. 10-11)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double dot3(const double *a, const double *b)
@@ -1506,9 +1641,18 @@ static int resident_blocks(const void *kern, int wg, size_t lds)
     return n;
 }
 
+// the stepping kernel of a gather variant for the job's stepper
+template <typename T, typename S, int MODE, int GATHER, bool BATCH>
+static const void *trace_kernel(bool euler)
+{
+    return euler ? reinterpret_cast<const void *>(&k_trace<T, S, MODE, GATHER, BATCH, true>)
+                 : reinterpret_cast<const void *>(&k_trace<T, S, MODE, GATHER, BATCH, false>);
+}
+
 template <typename T, typename S, int MODE, bool BATCH>
 static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
 {
+    const bool euler = job.o.stepper == QSQ_STEPPER_EULER;
     const int cus = device_cu_count();
     const int64_t n_max = job.n_dev ? job.rec.cap : job.n_host;
     if (n_max <= 0) return hipSuccess;
@@ -1544,16 +1688,16 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
         const uint64_t field_bytes = (uint64_t)node_bytes<S>() * job.g.n[0] * job.g.n[1] * job.g.n[2];
         const bool fits = field_bytes < ((uint64_t)1 << 31) - ((uint64_t)1 << 26);
         if ((gather == 3 || gather == 0) && fits) {
-            kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, kGatherRegs, false>);
+            kern = trace_kernel<T, S, MODE, kGatherRegs, false>(euler);
         } else if (gather == 2 && fits) {
-            kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, kGatherLds, false>);
+            kern = trace_kernel<T, S, MODE, kGatherLds, false>(euler);
             lds = kCachePlanes * wg * sizeof(float4);
         } else {
-            kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, kGatherDirect, false>);
+            kern = trace_kernel<T, S, MODE, kGatherDirect, false>(euler);
         }
     } else {
         (void)gather;
-        kern = reinterpret_cast<const void *>(&k_trace<T, S, MODE, kGatherDirect, BATCH>);
+        kern = trace_kernel<T, S, MODE, kGatherDirect, BATCH>(euler);
     }
     const int64_t resident = (int64_t)cus * resident_blocks(kern, wg, lds);
     int64_t cap_blocks = (int64_t)cus * lanes * (256 / wg);
@@ -1575,8 +1719,12 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
     hipLaunchKernelGGL(k_land_flags, dim3(cblocks), dim3(256), 0, st, job);
     launch_scan_i32(job.rec.flag, job.rec.n_items, 2 * n_max, job.rec.scan_tmp, job.rec.wpos, job.rec.n_land, st);
     hipLaunchKernelGGL(k_land_compact, dim3(cblocks), dim3(256), 0, st, job);
-    hipLaunchKernelGGL((k_land<S, MODE, BATCH>), dim3(lblocks), dim3(256), 0, st, job);
-    hipLaunchKernelGGL((k_land_final<S, MODE, BATCH>), dim3(lblocks), dim3(256), 0, st, job);
+    if (euler) {
+        hipLaunchKernelGGL((k_land_euler<S, MODE, BATCH>), dim3(lblocks), dim3(256), 0, st, job);
+    } else {
+        hipLaunchKernelGGL((k_land<S, MODE, BATCH>), dim3(lblocks), dim3(256), 0, st, job);
+        hipLaunchKernelGGL((k_land_final<S, MODE, BATCH>), dim3(lblocks), dim3(256), 0, st, job);
+    }
     if (prof) prof_end(tok, st);
     int64_t ab = (n_max + 255) / 256;
     int ablocks = (int)(ab < (int64_t)cus * 16 ? ab : (int64_t)cus * 16);

@@ -106,6 +106,13 @@ def test_invalid_arguments_rejected_before_launch(qsq):
     o.launch = 0
     assert L.qsq_trace(C.byref(f), _fake(7), 10, C.byref(o), C.byref(t), _fake(8), 16, None) == \
         A.ERR_WORKSPACE_TOO_SMALL
+    o.stepper = 2                                     # no such stepper
+    assert L.qsq_trace(C.byref(f), _fake(7), 10, C.byref(o), C.byref(t), _fake(8), 1 << 20, None) == \
+        A.ERR_UNSUPPORTED
+    o.stepper = A.STEPPER_EULER                       # valid: fails later, on the workspace
+    assert L.qsq_trace(C.byref(f), _fake(7), 10, C.byref(o), C.byref(t), _fake(8), 16, None) == \
+        A.ERR_WORKSPACE_TOO_SMALL
+    o.stepper = A.STEPPER_CK54
     assert L.qsq_trace(C.byref(f), _fake(7), (1 << 30) + 1, C.byref(o), C.byref(t), _fake(8), 1 << 20,
                        None) == A.ERR_COUNT_OVERFLOW
     t.status = None

@@ -365,30 +365,34 @@ __device__ __forceinline__ int64_t block_incl_scan(int64_t v, int64_t *lds, int6
     return v + pre;
 }
 
-// exclusive scan of v[0..count), three kernels: block sums, block offsets, apply
-__global__ void __launch_bounds__(256) k_scan_sums(const int32_t *v, const int64_t *count_in, int64_t *bsum)
+// exclusive scan of v[0..count), three kernels: block sums, block offsets,
+// apply.  Arrays are sized for the capacity; only the blocks the device count
+// reaches are read or written (the grid strides over them).
+__global__ void __launch_bounds__(256) k_scan_sums(const int32_t *v, const int64_t *count_in, int64_t nblocks,
+                                                   int64_t *bsum)
 {
     __shared__ int64_t lds[4];
     const int64_t count = *count_in;
-    const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
-    if (b0 >= count) {
-        if (threadIdx.x == 0) bsum[blockIdx.x] = 0;
-        return;
+    for (int64_t blk = blockIdx.x; blk < nblocks && blk * kScanBlock < count; blk += gridDim.x) {
+        const int64_t i0 = blk * kScanBlock + (int64_t)threadIdx.x * kScanPer;
+        int64_t s = 0;
+        for (int k = 0; k < kScanPer; ++k)
+            if (i0 + k < count) s += v[i0 + k];
+        int64_t tot;
+        block_incl_scan(s, lds, tot);
+        if (threadIdx.x == 0) bsum[blk] = tot;
     }
-    int64_t s = 0;
-    const int64_t i0 = b0 + (int64_t)threadIdx.x * kScanPer;
-    for (int k = 0; k < kScanPer; ++k)
-        if (i0 + k < count) s += v[i0 + k];
-    int64_t tot;
-    block_incl_scan(s, lds, tot);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-// block offsets: each thread sums a contiguous run of block sums, one block
-// scan of the 256 run totals, then each thread writes its run's offsets
-__global__ void __launch_bounds__(256) k_scan_top(int64_t nblocks, int64_t *bsum, int64_t *total)
+// block offsets of the blocks the count reaches: each thread sums a
+// contiguous run of block sums, one block scan of the 256 run totals, then
+// each thread writes its run's offsets
+__global__ void __launch_bounds__(256) k_scan_top(const int64_t *count_in, int64_t nblocks_max, int64_t *bsum,
+                                                  int64_t *total)
 {
     __shared__ int64_t lds[4];
+    const int64_t used = (*count_in + kScanBlock - 1) / kScanBlock;
+    const int64_t nblocks = used < nblocks_max ? used : nblocks_max;
     const int64_t per = (nblocks + 255) / 256;
     const int64_t b0 = (int64_t)threadIdx.x * per;
     const int64_t b1 = b0 + per < nblocks ? b0 + per : nblocks;
@@ -404,26 +408,26 @@ __global__ void __launch_bounds__(256) k_scan_top(int64_t nblocks, int64_t *bsum
     if (threadIdx.x == 0) *total = tot;
 }
 
-__global__ void __launch_bounds__(256) k_scan_apply(const int32_t *v, const int64_t *count_in, const int64_t *boff,
-                                                    int32_t *off)
+__global__ void __launch_bounds__(256) k_scan_apply(const int32_t *v, const int64_t *count_in, int64_t nblocks,
+                                                    const int64_t *boff, int32_t *off)
 {
     __shared__ int64_t lds[4];
     const int64_t count = *count_in;
-    const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
-    if (b0 >= count) return;
-    const int64_t i0 = b0 + (int64_t)threadIdx.x * kScanPer;
-    int32_t x[kScanPer];
-    int64_t s = 0;
-    for (int k = 0; k < kScanPer; ++k) {
-        x[k] = i0 + k < count ? v[i0 + k] : 0;
-        s += x[k];
-    }
-    int64_t tot;
-    const int64_t incl = block_incl_scan(s, lds, tot);
-    int64_t run = boff[blockIdx.x] + incl - s;
-    for (int k = 0; k < kScanPer; ++k) {
-        if (i0 + k < count) off[i0 + k] = (int32_t)run;
-        run += x[k];
+    for (int64_t blk = blockIdx.x; blk < nblocks && blk * kScanBlock < count; blk += gridDim.x) {
+        const int64_t i0 = blk * kScanBlock + (int64_t)threadIdx.x * kScanPer;
+        int32_t x[kScanPer];
+        int64_t s = 0;
+        for (int k = 0; k < kScanPer; ++k) {
+            x[k] = i0 + k < count ? v[i0 + k] : 0;
+            s += x[k];
+        }
+        int64_t tot;
+        const int64_t incl = block_incl_scan(s, lds, tot);
+        int64_t run = boff[blk] + incl - s;
+        for (int k = 0; k < kScanPer; ++k) {
+            if (i0 + k < count) off[i0 + k] = (int32_t)run;
+            run += x[k];
+        }
     }
 }
 
@@ -707,9 +711,10 @@ uint64_t vmap_scratch_bytes(const qsq_volume_desc *d, int64_t capacity)
 static void launch_scan(const int32_t *v, const int64_t *count_in, int64_t nblocks, int64_t *bsum, int32_t *off,
                         int64_t *total, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nblocks), dim3(256), 0, st, v, count_in, bsum);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, nblocks, bsum, total);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblocks), dim3(256), 0, st, v, count_in, bsum, off);
+    const unsigned grid = (unsigned)(nblocks < 2048 ? nblocks : 2048);
+    hipLaunchKernelGGL(k_scan_sums, dim3(grid), dim3(256), 0, st, v, count_in, nblocks, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, count_in, nblocks, bsum, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3(grid), dim3(256), 0, st, v, count_in, nblocks, bsum, off);
 }
 
 int64_t scan_tmp_words(int64_t n_max) { return (n_max + kScanBlock - 1) / kScanBlock + 1; }

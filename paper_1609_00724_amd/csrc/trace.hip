@@ -8,8 +8,9 @@
 //              stop condition holds.  Retired lanes are refilled from a device
 //              work counter with one atomic per wave (ballot + prefix count).
 //   k_land     FP64: re-solves the step that left the box for the step length
-//              whose 5th-order end lies on the first face crossed (Illinois
-//              regula falsi on the signed face distance), then snaps to it.
+//              whose 5th-order end lies on the first face crossed (regula
+//              falsi on the signed face distance, Anderson-Bjorck variant),
+//              then snaps to it.
 //   k_assemble FP64: per seed, projects the deviations perpendicular to the
 //              renormalised field at both ends and forms Q by eq. (10)-(11),
 //              the determinant form, the exit-face-plane Q and the length.
@@ -1244,7 +1245,7 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
                 fmax_ = f;
             }
             if (!(gend > 0.0)) continue;
-            // Illinois regula falsi for the step length ending on face f
+            // regula falsi (Anderson-Bjorck) for the step length ending on face f
             double yo[3];
             double a = 0.0, b = hs;
             double ga = face_gap<S, MODE>(nodes, g, sigma, y, a, f, yo, v0);
@@ -1256,7 +1257,7 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
                 int side = 0;
                 hf = -1.0;
                 // the first trial uses the gap's slope at the start of the step
-                // (a quadratic model); Illinois regula falsi from there on
+                // (a quadratic model); regula falsi from there on
                 const int dd = f >> 1;
                 const double s0 = (f & 1) ? pick3(v0, dd) : -pick3(v0, dd);
                 const double c0 = landing_guess(ga, s0, gb, hs);
@@ -1267,15 +1268,24 @@ __global__ void __launch_bounds__(256) k_land(TraceJob job)
                         hf = c;
                         break;
                     }
+                    // the same end replaced twice in a row: scale the kept
+                    // end's gap (Anderson-Bjorck factor 1 - gc/g_old, 1/2
+                    // when that is not positive, which is Illinois)
                     if (gc > 0.0) {
+                        if (side == 1) {
+                            const double m = 1.0 - gc / gb;
+                            ga *= m > 0.0 ? m : 0.5;
+                        }
                         b = c;
                         gb = gc;
-                        if (side == 1) ga *= 0.5;
                         side = 1;
                     } else {
+                        if (side == -1) {
+                            const double m = 1.0 - gc / ga;
+                            gb *= m > 0.0 ? m : 0.5;
+                        }
                         a = c;
                         ga = gc;
-                        if (side == -1) gb *= 0.5;
                         side = -1;
                     }
                     if (b - a <= 1e-15 * hs) break;

@@ -713,7 +713,7 @@ def bench_learned(args):
     ms_step = e0.elapsed_time(e1) / 10
     flop_fwd = 2 * 64 * 64 * sum(9 * ci * co for ci, co in zip(learn.CHANNELS[:-1], learn.CHANNELS[1:]))
 
-    # judge on held-out maps
+    # score the proposals on held-out maps
     tp = fn = fp = 0
     miss_cnn = miss_plain = miss_learned = qsl_total = 0
     curve_xy = [v.long() for v in q.hilbert2_d2xy(m, torch.arange(4 ** m, device=dev))]
@@ -792,7 +792,7 @@ def bench_learned(args):
         "loss_curve": curve,
         "train_s": t_train,
         "data_s": t_gen,
-        "judge": {
+        "scored_against_rule": {
             "mask_recall": tp / max(tp + fn, 1),
             "mask_precision": tp / max(tp + fp, 1),
             "proposed_pixel_fraction": prop_pixels / (len(test) * side * side),

@@ -3,7 +3,7 @@
 // coarse tiles of the field-line length, its FLEDGE map (Sect. 3.6) and Bz,
 // and outputs a refine-mask logit and a log10 Q estimate per pixel.  The
 // network is an extension beyond the paper; the FLL-jump rule of Sect. 3.6
-// stays the fallback and the judge of its proposals.
+// stays the fallback and the reference its proposals are scored against.
 //
 // Every contraction runs on the matrix cores: v_mfma_f32_16x16x32_bf16 (BF16
 // operands, FP32 accumulation), one wave per 16x16 output tile.

@@ -626,7 +626,7 @@ def bench_learned(args):
     flux-rope fields, 128x128x64 FP32 grids) give coarse 256^2 inputs (length,
     FLEDGE, Bz) and targets from the same maps refined 4x by the FLL-jump rule
     (refine mask, max log10 Q per pixel); the CNN trains on 9/10 of the maps
-    with the library's kernels and is judged on the rest against the plain
+    with the library's kernels and is scored on the rest against the plain
     rule: recall of its mask, and the fraction of fine QSL pixels (Q > 1e3)
     whose coarse pixel it does not propose."""
     import numpy as np
@@ -775,7 +775,7 @@ def bench_learned(args):
         lines_plain += fine.result()["count"]
         del prop_curve
     out = {
-        "metric": "learned refinement proposer: training and judged proposals",
+        "metric": "learned refinement proposer: training and scored proposals",
         "value": bs * flop_fwd * 3 / (ms_step / 1e3) / 1e12,
         "unit": "TFLOP/s (training step, BF16 matrix cores)",
         "n_gpus": 1,

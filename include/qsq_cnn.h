@@ -5,7 +5,7 @@
  * convolutional network reads coarse tiles of three maps the method makes --
  * field-line length, its FLEDGE map (Sect. 3.6) and Bz on the slice -- and
  * proposes which coarse pixels the refinement of Sect. 3.6 should refine; the
- * FLL-jump rule stays the fallback and judges the proposals.
+ * FLL-jump rule stays the fallback and scores the proposals.
  *
  * Network: four 3x3 'same' convolutions (zero padding), 3 -> 32 -> 32 -> 32 ->
  * 2 channels, FP32 bias, ReLU after the first three; output channel 0 is the

@@ -74,8 +74,10 @@ extern "C" {
 #define QSQ_END_MAX_STEPS 7     /* reached opts.max_steps step attempts */
 #define QSQ_END_NULL 8          /* |Bhat| < 1e-6: a null of the field */
 #define QSQ_END_UNDERFLOW 9     /* step size fell below 1e-12 of the box extent */
-#define QSQ_END_SEED_OUTSIDE 10 /* seed lies outside the closed box */
-#define QSQ_END_NONFINITE 11    /* the state became NaN or Inf */
+#define QSQ_END_SEED_OUTSIDE 10 /* seed lies outside the closed box (or is not finite) */
+#define QSQ_END_NONFINITE 11    /* a trial step's state became NaN or Inf (e.g. a non-finite
+                                   node value in its cells); the end state is the last
+                                   finite one */
 
 /* per-seed status word: forward | backward << 8 | QSQ_STATUS_OPEN; OPEN is set
  * unless both ends lie on the bottom (z = min) face (open lines, Sect. 3.5) */
@@ -298,7 +300,8 @@ typedef struct qsq_map_desc {
 
 /* Results of qsq_qmap (device memory).  Samples are kept in curve order. */
 typedef struct qsq_map_out {
-    int64_t capacity;      /* entries available in each sample array (>= 4^m; 8^m for volumes) */
+    int64_t capacity;      /* entries available in each sample array (>= 4^m; 8^m for volumes;
+                              at most 2^30) */
     uint64_t *keys;        /* finest-level curve index of each sample */
     double *fll;           /* field-line length per sample */
     double *q_perp;        /* Q of eq. (11) per sample */
@@ -333,7 +336,8 @@ uint64_t qsq_qmap_scratch_bytes(const qsq_map_desc *d, int64_t capacity);
  * key of a firing gap always being floor((k1+k2)/2).  Samples beyond
  * `capacity`, or proposed or speculative keys beyond the trace slots
  * (`capacity`), are dropped and set *overflow.
- * Errors: INVALID_ARG, UNSUPPORTED, WORKSPACE_TOO_SMALL, HIP.
+ * Errors: INVALID_ARG, UNSUPPORTED, WORKSPACE_TOO_SMALL, COUNT_OVERFLOW
+ * (capacity > 2^30), HIP.
  */
 int qsq_qmap(const qsq_field *f, const qsq_map_desc *d, const qsq_trace_opts *opts,
              const qsq_map_out *out, void *scratch, uint64_t scratch_bytes, void *stream);
@@ -358,7 +362,8 @@ uint64_t qsq_vmap_scratch_bytes(const qsq_volume_desc *d, int64_t capacity);
  * (qsq_hilbert3_*).  Base samples: the (2^m)^3 cell centres in level-m curve
  * order q with key q*8^r + 8^r/2; the key gap halves over 3r passes.  Output
  * grids are (2^out_level)^3 and the FLEDGE map (2^m)^3, C order [z][y][x];
- * capacity >= 8^m.  Errors: INVALID_ARG, UNSUPPORTED, WORKSPACE_TOO_SMALL, HIP.
+ * capacity >= 8^m.  Errors: INVALID_ARG, UNSUPPORTED, WORKSPACE_TOO_SMALL,
+ * COUNT_OVERFLOW (capacity > 2^30), HIP.
  */
 int qsq_vmap(const qsq_field *f, const qsq_volume_desc *d, const qsq_trace_opts *opts,
              const qsq_map_out *out, void *scratch, uint64_t scratch_bytes, void *stream);

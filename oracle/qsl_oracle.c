@@ -373,10 +373,11 @@ typedef struct {
     int64_t accepted, rejected, land_iters;
 } or_half;
 
+/* a point that is not in the closed box; a non-finite coordinate is outside */
 static int outside(const or_field *F, const double x[3])
 {
     for (int d = 0; d < 3; ++d)
-        if (x[d] < F->d.lo[d] || x[d] > F->d.hi[d]) return 1;
+        if (!(x[d] >= F->d.lo[d] && x[d] <= F->d.hi[d])) return 1;
     return 0;
 }
 

@@ -510,7 +510,9 @@ int qsq_vmap(const qsq_field *f, const qsq_volume_desc *d, const qsq_trace_opts 
     if (!out) return fail(QSQ_ERR_INVALID_ARG, "out is NULL");
     const int64_t nb = (int64_t)1 << (3 * d->base_level);
     if (out->capacity < nb) return fail(QSQ_ERR_INVALID_ARG, "capacity < 8^base_level");
-    if (out->capacity > ((int64_t)1 << 31) - 1) return fail(QSQ_ERR_COUNT_OVERFLOW, "capacity >= 2^31");
+    // the trace records hold 2 x capacity half-lines addressed by int32 work
+    // entries and scan offsets, as qsq_trace bounds its seed count
+    if (out->capacity > ((int64_t)1 << 30)) return fail(QSQ_ERR_COUNT_OVERFLOW, "capacity > 2^30");
     if (!out->keys || !out->fll || !out->q_perp || !out->status || !out->count || !out->overflow)
         return fail(QSQ_ERR_INVALID_ARG, "sample arrays, count and overflow are required");
     if (!scratch || !aligned(scratch, 256)) return fail(QSQ_ERR_INVALID_ARG, "scratch NULL or not 256-byte aligned");
@@ -543,7 +545,9 @@ int qsq_qmap(const qsq_field *f, const qsq_map_desc *d, const qsq_trace_opts *op
     if (!out) return fail(QSQ_ERR_INVALID_ARG, "out is NULL");
     const int64_t nb = (int64_t)1 << (2 * d->base_level);
     if (out->capacity < nb) return fail(QSQ_ERR_INVALID_ARG, "capacity < 4^base_level");
-    if (out->capacity > ((int64_t)1 << 31) - 1) return fail(QSQ_ERR_COUNT_OVERFLOW, "capacity >= 2^31");
+    // the trace records hold 2 x capacity half-lines addressed by int32 work
+    // entries and scan offsets, as qsq_trace bounds its seed count
+    if (out->capacity > ((int64_t)1 << 30)) return fail(QSQ_ERR_COUNT_OVERFLOW, "capacity > 2^30");
     if (!out->keys || !out->fll || !out->q_perp || !out->status || !out->count || !out->overflow)
         return fail(QSQ_ERR_INVALID_ARG, "sample arrays, count and overflow are required");
     if (!scratch || !aligned(scratch, 256)) return fail(QSQ_ERR_INVALID_ARG, "scratch NULL or not 256-byte aligned");

@@ -525,9 +525,10 @@ __device__ __forceinline__ void field_at_x(const S *__restrict__ nodes, const Ge
     field_at<double, S, MODE, MAG>(nodes, g, ib, q, u, G, mag);
 }
 
+// not a point of the closed box (a non-finite coordinate is outside)
 __device__ __forceinline__ bool outside_box(const Geom &g, double x0, double x1, double x2)
 {
-    return x0 < g.lo[0] || x0 > g.hi[0] || x1 < g.lo[1] || x1 > g.hi[1] || x2 < g.lo[2] || x2 > g.hi[2];
+    return !(x0 >= g.lo[0] && x0 <= g.hi[0] && x1 >= g.lo[1] && x1 <= g.hi[1] && x2 >= g.lo[2] && x2 <= g.hi[2]);
 }
 
 // orthonormal (a, b) completing the unit vector n, branch-free
@@ -870,7 +871,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EULER 
                 const T un2 = rhs_step<T, S, MODE, GATHER>(nodes, rsrc, cbytes, g, ib, fb, (T)1, D1, D2, Kx[0], K1[0],
                                                            K2[0], cache_cell, slot, stride, reg_cell, reg_brick);
                 ++c_ev;
-                if (!(un2 >= (T)1e-12)) stop = QSQ_END_NULL;
+                if (un2 < (T)1e-12) stop = QSQ_END_NULL;   // NaN: not a null (the step reports it)
                 have_k1 = true;
             }
         }
@@ -882,7 +883,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EULER 
                                                            K1[0], K2[0], cache_cell, slot, stride, reg_cell,
                                                            reg_brick);
                 ++c_ev;
-                if (!(un2 >= (T)1e-12)) stop = QSQ_END_NULL;
+                if (un2 < (T)1e-12) stop = QSQ_END_NULL;   // NaN: not a null (the step reports it)
             }
             if (stop < 0) {
                 T hs = h;

@@ -127,6 +127,21 @@ def test_invalid_arguments_rejected_before_launch(qsq):
     mo = A.MapOut()
     assert L.qsq_qmap(C.byref(f), C.byref(d), C.byref(o), C.byref(mo), _fake(9), 1 << 30, None) == \
         A.ERR_INVALID_ARG
+    assert b"out_level" in L.qsq_last_error()
+    # capacities past 2^30 samples: the trace records are addressed with int32
+    d.out_level = 6
+    mo.capacity = (1 << 30) + 1
+    assert L.qsq_qmap(C.byref(f), C.byref(d), C.byref(o), C.byref(mo), _fake(9), 1 << 62, None) == \
+        A.ERR_COUNT_OVERFLOW
+    vd = A.VolumeDesc()
+    vd.x0, vd.x1, vd.y0, vd.y1, vd.z0, vd.z1 = -1, 1, -1, 1, 0, 1
+    vd.base_level, vd.refine_levels, vd.out_level, vd.threshold = 4, 2, 4, 0.1
+    assert L.qsq_vmap(C.byref(f), C.byref(vd), C.byref(o), C.byref(mo), _fake(9), 1 << 62, None) == \
+        A.ERR_COUNT_OVERFLOW
+    mo.capacity = 1 << 30                  # the largest allowed: fails later, on the arrays
+    assert L.qsq_vmap(C.byref(f), C.byref(vd), C.byref(o), C.byref(mo), _fake(9), 1 << 62, None) == \
+        A.ERR_INVALID_ARG
+    assert b"sample arrays" in L.qsq_last_error()
     # FLEDGE: overlapping buffers, bad rank
     shp = (C.c_int64 * 2)(16, 16)
     assert L.qsq_fledge(_fake(1), 2, shp, C.c_void_p(0x100000 + 64), None) == A.ERR_INVALID_ARG

@@ -119,6 +119,38 @@ def test_train_step_gradient_and_loss():
     assert abs(float(loss) - L) <= 1e-3 * abs(L)
 
 
+def test_adam_update_matches_oracle():
+    """Three training steps through the C-ABI: after each, the FP32 master
+    parameters and both Adam moments equal oracle.cnn.adam_step (Kingma & Ba
+    2015, FP64) applied to the step's own inputs -- parameters and moments
+    before the step, the step's gradient, the step count -- within FP32
+    rounding of each operation (a few units in the last place of the terms
+    that form each value)."""
+    import torch
+    prop, wr, br, g, dev = _setup(14)
+    x, mask, logq = _batch(g)
+    T = lambda a: torch.from_numpy(a).to(dev)   # noqa: E731
+    lr = 2e-3
+    host = lambda t: t.detach().double().cpu().numpy()   # noqa: E731
+    for step in range(3):
+        p0, m0, v0 = host(prop.params), host(prop.m), host(prop.v)
+        _, grad = prop.train_step(T(x), T(mask), T(logq), lr=lr, lam=0.1, want_grad=True)
+        torch.cuda.synchronize()
+        gr = host(grad)
+        p, m, v = p0.copy(), m0.copy(), v0.copy()
+        ref.adam_step(p, gr, m, v, prop.t, lr=lr)
+        pg, mg, vg = host(prop.params), host(prop.m), host(prop.v)
+        u = np.abs(p - p0)                               # size of the FP64 update
+        ulp = 2.0 ** -23
+        em = np.abs(mg - m) / (4 * ulp * (0.9 * np.abs(m0) + 0.1 * np.abs(gr)) + 1e-45)
+        ev = np.abs(vg - v) / (4 * ulp * (0.999 * v0 + 0.001 * gr * gr) + 1e-45)
+        ep = np.abs(pg - p) / (4 * ulp * (np.abs(p0) + u) + 1e-45)
+        print(f"step {prop.t}: max error in units of the bound m {em.max():.3f} v {ev.max():.3f} p {ep.max():.3f}; "
+              f"mean |update| {u.mean():.2e}")
+        assert em.max() <= 1.0 and ev.max() <= 1.0 and ep.max() <= 1.0
+        assert np.count_nonzero(gr) > 0.5 * gr.size and np.median(u[gr != 0]) > 0.5 * lr
+
+
 def test_training_lowers_the_loss():
     """200 Adam steps on a fixed synthetic task (mask = x0 > 0.5 smoothed by
     the 3x3 neighbourhood, log10 Q = 1 + x1): the loss must fall well below

@@ -12,7 +12,8 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_util import FP_TOL, check_fp32, check_lines, gpu_field, gpu_trace, parity
+from gpu_util import (FP_TOL, check_fp32, check_lines, gpu_field, gpu_trace, parity, qfp_in_gate, qfp_parity,
+                      sensitivity_floor)
 
 pytestmark = pytest.mark.gpu
 
@@ -91,9 +92,27 @@ def test_charges_parity(oracle_mod, small_charges, step_dtype, tol):
     assert p["gate"].mean() > 0.97
     if step_dtype == "f64":
         check_lines(p, o, strict=True)
+        _check_qfp(g, o, 1.0)
     else:
         ref = oracle_mod.trace(fo, seeds, **dict(kw, rtol=1e-10, atol=1e-10))
-        check_fp32(p, g, o, ref)
+        floor, _ = sensitivity_floor(oracle_mod, fo, seeds, o, kw)
+        check_fp32(p, g, o, ref, min_frac=floor)
+        _check_qfp(g, o, sensitivity_floor(oracle_mod, fo, seeds, o, kw, judge=qfp_in_gate)[0])
+
+
+def _check_qfp(g, o, floor):
+    """The exit-face-plane Q per line against the oracle's, on every line with
+    both ends on faces -- the bottom face and the side and top faces -- with
+    the Q gate (relative log10 error <= 1e-3): all of them for FP64 stepping,
+    at least the sensitivity floor's share for FP32 stepping."""
+    m, e = qfp_parity(g, o)
+    fwd, bwd = o["status"] & 0xFF, (o["status"] >> 8) & 0xFF
+    side = m & ((fwd < 4) | (bwd < 4) | (fwd == 5) | (bwd == 5))
+    ok = np.nan_to_num(e, nan=np.inf) <= 1e-3
+    print(f"q_fp: {int(m.sum())} lines with two face ends ({int(side.sum())} reach a side or the top), "
+          f"{float(ok[m].mean()):.4f} within 1e-3, max {np.nanmax(e[m]):.2e}")
+    assert side.sum() >= 20
+    assert ok[m].mean() >= floor and ok[side].mean() >= floor
 
 
 @pytest.mark.parametrize("n", [1, 2047, 2049, 6001])
@@ -136,7 +155,7 @@ def test_interp_normalize_fp32(oracle_mod, small_charges):
     fo = _oracle_grid(oracle_mod, c["b"], c["origin"], c["spacing"], "interp_normalize", "f32")
     o = oracle_mod.trace(fo, seeds, **kw)
     ref = oracle_mod.trace(fo, seeds, **dict(kw, rtol=1e-10, atol=1e-10))
-    check_fp32(parity(g, o), g, o, ref)
+    check_fp32(parity(g, o), g, o, ref, min_frac=sensitivity_floor(oracle_mod, fo, seeds, o, kw)[0])
 
 
 # ---------------------------------------------------------------------------
@@ -236,7 +255,7 @@ def test_bf16_storage(oracle_mod, small_charges):
     fo = _oracle_grid(oracle_mod, c["b"], c["origin"], c["spacing"], "paper", "bf16")
     o = oracle_mod.trace(fo, seeds, **kw)
     ref = oracle_mod.trace(fo, seeds, **dict(kw, rtol=1e-10, atol=1e-10))
-    check_fp32(parity(g, o), g, o, ref)
+    check_fp32(parity(g, o), g, o, ref, min_frac=sensitivity_floor(oracle_mod, fo, seeds, o, kw)[0])
     # storage error: BF16 field vs the unrounded field
     f64 = oracle_mod.trace(_oracle_grid(oracle_mod, c["b"], c["origin"], c["spacing"], "paper", "f64"),
                            seeds, **kw)
@@ -271,6 +290,7 @@ def test_flux_rope_fp64_parity(oracle_mod, rope):
     o = oracle_mod.trace(fo, seeds, **kw)
     p = parity(g, o)
     check_lines(p, o, strict=True)
+    _check_qfp(g, o, 1.0)
     # the rope twists lines: some closed lines (both ends on z = 0) are long
     closed = (o["status"] & 0xFFFF) == (4 | (4 << 8))
     assert closed.sum() > 100 and np.percentile(o["fll"][closed], 90) > 0.5
@@ -288,4 +308,65 @@ def test_flux_rope_fp32_stepping(oracle_mod, rope, storage):
     fo = _oracle_grid(oracle_mod, rope["b"], rope["origin"], rope["spacing"], "paper", storage)
     o = oracle_mod.trace(fo, seeds, **kw)
     ref = oracle_mod.trace(fo, seeds, **dict(kw, rtol=1e-10, atol=1e-10))
-    check_fp32(parity(g, o), g, o, ref)
+    check_fp32(parity(g, o), g, o, ref, min_frac=sensitivity_floor(oracle_mod, fo, seeds, o, kw)[0])
+
+
+# ---------------------------------------------------------------------------
+# UNDERFLOW, NONFINITE and non-finite seeds: status parity with the oracle on
+# the inputs its pins use (tests/test_oracle_trace.py)
+# ---------------------------------------------------------------------------
+
+def test_underflow_at_a_spine_null(oracle_mod):
+    """A line run into a null along its spine stops with UNDERFLOW on the GPU
+    as in the oracle (FP64 stepping, tol 1e-8): same statuses, ends on the
+    spine within 1e-9 of the null, lengths as the oracle's."""
+    from test_oracle_trace import SPINE_SEEDS, spine_null
+    b, origin, spacing = spine_null()
+    h = min(spacing)
+    kw = dict(rtol=1e-8, atol=1e-8, h_init=0.1 * h, h_max=h)
+    fg = gpu_field(b, origin, spacing, storage="f64", mode="interp_normalize")
+    g = gpu_trace(fg, SPINE_SEEDS, step_dtype="f64", **kw)
+    o = oracle_mod.trace(oracle_mod.Field.grid(*b, origin, spacing, mode=oracle_mod.INTERP_NORMALIZE),
+                         SPINE_SEEDS, **kw)
+    assert np.array_equal(g["status"], o["status"])
+    assert np.all((g["status"] & 0xFF) == oracle_mod.UNDERFLOW)
+    assert np.all(g["fp_fwd"][:, :2] == 0.0) and np.all(np.abs(g["fp_fwd"][:, 2]) < 1e-9)
+    assert np.allclose(g["fll"], o["fll"], rtol=0, atol=1e-8)
+    assert np.all(np.isnan(g["q_perp"]))
+
+
+@pytest.mark.parametrize("value", [np.nan, np.inf])
+@pytest.mark.parametrize("mode", ["paper", "interp_normalize"])
+@pytest.mark.parametrize("storage,step_dtype", [("f64", "f64"), ("f32", "f32")])
+def test_nonfinite_node_status_parity(oracle_mod, value, mode, storage, step_dtype):
+    """A NaN or Inf node on the line's way: NONFINITE at the last finite state,
+    as in the oracle on the same stored field; the other half unaffected."""
+    from test_oracle_trace import poisoned_uniform
+    b, origin, spacing = poisoned_uniform(value)
+    seeds = np.array([[0.0, 0.0, 0.1], [0.5, 0.5, 0.3], [0.0, 0.0, 0.9]])
+    h = min(spacing)
+    kw = dict(rtol=1e-6, atol=1e-6, h_init=0.1 * h, h_max=h)
+    fg = gpu_field(b, origin, spacing, storage=storage, mode=mode)
+    g = gpu_trace(fg, seeds, step_dtype=step_dtype, **kw)
+    md = oracle_mod.PAPER if mode == "paper" else oracle_mod.INTERP_NORMALIZE
+    o = oracle_mod.trace(oracle_mod.Field.grid(*b, origin, spacing, mode=md, store=storage), seeds, **kw)
+    assert np.array_equal(g["status"], o["status"]), (g["status"], o["status"])
+    assert (g["status"][0] & 0xFF) == oracle_mod.NONFINITE
+    assert ((g["status"][2] >> 8) & 0xFF) == oracle_mod.NONFINITE
+    tol = 1e-12 if step_dtype == "f64" else 1e-6
+    assert np.allclose(g["fp_fwd"], o["fp_fwd"], rtol=0, atol=tol)
+    assert np.allclose(g["fp_bwd"], o["fp_bwd"], rtol=0, atol=tol)
+    assert np.allclose(g["fll"], o["fll"], rtol=0, atol=tol)
+    assert np.isnan(g["q_perp"][0]) and np.isnan(g["q_perp"][2]) and np.isfinite(g["q_perp"][1])
+
+
+def test_non_finite_seed_is_outside(oracle_mod, small_charges):
+    c = small_charges
+    seeds = np.array([[np.nan, 0.0, 0.5], [0.0, 0.0, np.inf], [0.1, 0.1, 0.5]])
+    h = min(c["spacing"])
+    kw = dict(rtol=1e-4, atol=1e-4, h_init=0.1 * h, h_max=h)
+    fg = gpu_field(c["b"], c["origin"], c["spacing"], storage="f32")
+    g = gpu_trace(fg, seeds, step_dtype="f32", **kw)
+    o = oracle_mod.trace(_oracle_grid(oracle_mod, c["b"], c["origin"], c["spacing"], "paper", "f32"), seeds, **kw)
+    assert np.array_equal(g["status"], o["status"])
+    assert np.all((g["status"][:2] & 0xFF) == oracle_mod.SEED_OUTSIDE) and np.all(g["fll"][:2] == 0.0)

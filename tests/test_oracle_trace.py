@@ -487,3 +487,112 @@ def test_node_storage_rounding(oracle_mod):
     assert np.allclose(u32[0], exact.astype(np.float32).astype(np.float64), rtol=1e-14, atol=0)
     assert not np.allclose(u32[0], exact, rtol=1e-12, atol=0)          # it is rounded
     assert m32[0] == pytest.approx(np.float64(np.float32(np.sqrt(0.98))), rel=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# step underflow and non-finite states (Sect. 3.4 controller; stops the paper
+# leaves to the implementation)
+# ---------------------------------------------------------------------------
+
+def _charge_grid_33(O, mode=None):
+    """The 4-charge field sampled FP64 on 33 x 33 x 17 nodes."""
+    n = (33, 33, 17)
+    b = synth.sample_charges(synth.point_charges(2, 4), n, dtype=np.float64)
+    origin, spacing = synth.grid_geometry(n)
+    return O.Field.grid(*b, origin, spacing, **({} if mode is None else dict(mode=mode))), min(spacing)
+
+
+def spine_null(n=(9, 9, 9)):
+    """B = (x, y, -2 z) on [-1, 1]^3 (a 3D null at the origin whose spine is
+    the z axis), sampled on n nodes: linear, so the INTERP_NORMALIZE grid
+    field is exactly the analytic one."""
+    lo, hi = (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0)
+    b = synth.sample_linear(np.zeros(3), np.diag([1.0, 1.0, -2.0]), n, lo=lo, hi=hi)
+    origin, spacing = synth.grid_geometry(n, lo, hi)
+    return b, origin, spacing
+
+
+SPINE_SEEDS = np.array([[0.0, 0.0, 0.5], [0.0, 0.0, 0.3137], [0.0, 0.0, -0.7]])
+
+
+@pytest.mark.parametrize("n", [(9, 9, 9), (17, 17, 16)])
+def test_step_underflow_at_a_spine_null(oracle_mod, n):
+    """A line run into a magnetic null along its spine: the unit field on the
+    spine is (0, 0, -sign z), so it reverses across the null, and the Jacobian
+    of eq. (5) grows like 1/|z| as the null nears.  The embedded error of a
+    step near the null stays above the tolerance until the step falls below
+    1e-12 of the box extent: the forward half stops with UNDERFLOW within
+    1e-9 of the null, on the spine (x = y = 0 exactly: the field has no
+    transverse part there), after a length equal to the distance it covered
+    (|u| = 1 on the spine); the backward half leaves through the face the
+    spine meets; Q is undefined."""
+    O = oracle_mod
+    b, origin, spacing = spine_null(n)
+    F = O.Field.grid(*b, origin, spacing, mode=O.INTERP_NORMALIZE)
+    h = min(spacing)
+    r = O.trace(F, SPINE_SEEDS, rtol=1e-8, atol=1e-8, h_init=0.1 * h, h_max=h)
+    assert np.all(_fwd(r["status"]) == O.UNDERFLOW)
+    assert np.array_equal(_bwd(r["status"]), np.where(SPINE_SEEDS[:, 2] > 0, O.ZHI, O.ZLO))
+    z = r["fp_fwd"][:, 2]
+    assert np.all(r["fp_fwd"][:, :2] == 0.0) and np.all(np.abs(z) < 1e-9)
+    assert np.all(np.sign(z) == np.sign(SPINE_SEEDS[:, 2]))
+    assert np.allclose(r["lam_fwd"], np.abs(SPINE_SEEDS[:, 2] - z), rtol=0, atol=1e-12)
+    assert np.all(r["counts"][:, 0, 1] >= 1) and np.all(np.isnan(r["q_perp"]))
+    # the same seeds off the spine pass the null by and leave the box
+    off = SPINE_SEEDS + np.array([0.05, -0.03, 0.0])
+    r = O.trace(F, off, rtol=1e-8, atol=1e-8, h_init=0.1 * h, h_max=h)
+    assert np.all(_fwd(r["status"]) < 6)
+
+
+def poisoned_uniform(value, mode_name="paper"):
+    """Uniform field B = (0, 0, 1) on 9^3 nodes with node (x 4, y 4, z 6) set
+    to `value` (NaN or Inf): the cells with z index 5 and 6 around x = y = 0
+    hold a non-finite corner."""
+    n = (9, 9, 9)
+    bx, by, bz = (np.array(c) for c in synth.sample_linear(*synth.uniform([0, 0, 1.0]), n))
+    bz[6, 4, 4] = value
+    origin, spacing = synth.grid_geometry(n)
+    return (bx, by, bz), origin, spacing
+
+
+@pytest.mark.parametrize("value", [np.nan, np.inf])
+@pytest.mark.parametrize("mode", ["paper", "interp_normalize"])
+def test_nonfinite_node(oracle_mod, value, mode):
+    """A line through the poisoned cells: the first trial step with a stage
+    point in cell z 5 (z >= 0.625) turns non-finite, so the forward half stops
+    with NONFINITE at its last accepted point, on the line x = y = 0 within one
+    largest step (0.125) below z = 0.625; its length is that point's height
+    less the seed's (the field is uniform).  The backward half never reaches
+    the cells and lands on z = 0 as on the clean field.  Q is undefined."""
+    O = oracle_mod
+    b, origin, spacing = poisoned_uniform(value)
+    md = O.PAPER if mode == "paper" else O.INTERP_NORMALIZE
+    F = O.Field.grid(*b, origin, spacing, mode=md)
+    seed = np.array([[0.0, 0.0, 0.1]])
+    kw = _opts(1e-8, min(spacing))
+    r = O.trace(F, seed, **kw)
+    assert _fwd(r["status"][0]) == O.NONFINITE and _bwd(r["status"][0]) == O.ZLO
+    z_end = r["fp_fwd"][0, 2]
+    assert 0.625 - 0.125 <= z_end < 0.625
+    assert np.allclose(r["fp_fwd"][0, :2], 0.0, atol=1e-14)
+    assert r["lam_fwd"][0] == pytest.approx(z_end - 0.1, abs=1e-12)
+    assert r["fll"][0] == pytest.approx(z_end, abs=1e-12)
+    assert np.isnan(r["q_perp"][0]) and np.isnan(r["q_det"][0])
+    clean = O.trace(O.Field.grid(*poisoned_uniform(1.0)[0], origin, spacing, mode=md), seed, **kw)
+    assert np.array_equal(r["fp_bwd"], clean["fp_bwd"]) and r["lam_bwd"][0] == clean["lam_bwd"][0]
+    # the explicit Euler scheme evaluates the field at the start of each step
+    # only: it stops at the first point of its fixed-step lattice inside the
+    # poisoned cells (z = 0.1 + 21 * 0.025 = 0.625, up to rounding)
+    e = O.trace(F, seed, rtol=1e-8, atol=1e-8, h_init=0.025, h_max=0.025, stepper="euler")
+    assert _fwd(e["status"][0]) == O.NONFINITE
+    assert e["fp_fwd"][0, 2] == pytest.approx(0.625, abs=1e-12) and e["counts"][0, 0, 0] == 21
+
+
+def test_non_finite_seed_is_outside(oracle_mod):
+    """A seed with a NaN coordinate is not a point of the box: SEED_OUTSIDE on
+    both halves, length 0, Q undefined."""
+    O = oracle_mod
+    F, h = _charge_grid_33(O)
+    r = O.trace(F, np.array([[np.nan, 0.0, 0.5], [0.0, 0.0, np.inf]]), **_opts(1e-6, h))
+    assert np.all(_fwd(r["status"]) == O.SEED_OUTSIDE) and np.all(_bwd(r["status"]) == O.SEED_OUTSIDE)
+    assert np.all(r["fll"] == 0.0) and np.all(np.isnan(r["q_perp"]))

@@ -11,6 +11,7 @@ Contents, each following the paper (Tassev & Savcheva 2017):
                                   magnitude of a field-line-length map
   * ``hilbert2_*``             -- Sect. 3.6: Hilbert ordering of a slice
   * ``refine_slice``           -- Sect. 3.6: FLL-jump refinement along the curve
+  * ``refine_shifted``         -- Sect. 3.6: the same with the shifted-curve re-pass
   * ``convert_to_grid``        -- Sect. 3.6: array converter (max per cell,
                                   log Q interpolated along the curve in gaps)
   * ``oracle.cnn``             -- FP64 reference of the learned refinement
@@ -363,6 +364,83 @@ def refine_slice(region, m: int, r: int, thr: float, sample_fn, max_passes=64, e
         keys = np.insert(keys, idx + 1, newk)
         vals = {k: np.insert(v, idx + 1, np.asarray(newv[k]), axis=0) for k, v in vals.items()}
     return keys, vals, passes
+
+
+def _curve_index(region, level, cells):
+    """Hilbert index at `level` of cells (one array per axis) of the region's
+    curve (2D for slices, 3D for volumes)."""
+    if region.dims == 2:
+        return hilbert2_xy2d(level, cells[0], cells[1])
+    return hilbert3_xyz2d(level, cells[0], cells[1], cells[2])
+
+
+def refine_shifted(region, m: int, r: int, thr: float, sample_fn, shift: int, max_cycles=64):
+    """FLL-jump refinement with the shifted-curve re-pass (Sect. 3.6, last
+    paragraph: after each refinement step the curve is shifted in space, the
+    samples are reordered along it, the refinement step is applied again, and
+    the curve is shifted back).
+
+    Each cycle is one pass of the rule along the curve (as refine_slice: a new
+    sample at floor((k1 + k2) / 2) between curve-successive samples two or more
+    finest cells apart whose lengths differ by more than ``thr``), then one
+    pass of the same rule along the shifted curve: every sample's finest cell
+    (the cell its key names at level L = m + r) is moved by ``shift`` finest
+    cells along every axis into the square (cube) of side 2^(L+1), where the
+    order-(L+1) Hilbert curve orders them; curve-successive samples of that
+    order whose shifted indices differ by >= 2 and whose lengths differ by more
+    than ``thr`` put a new sample in the cell of index floor((k1' + k2') / 2)
+    on that curve, moved back by ``shift``, unless the cell lies outside the
+    map; the new samples join the key-ordered list.  Cycles repeat until one
+    inserts nothing, at most ``max_cycles``.  0 < shift < 2^L.
+
+    Returns (keys, values dict, cycles run)."""
+    L = m + r
+    if not 0 < shift < (1 << L):
+        raise ValueError("shift must lie in (0, 2^(m+r))")
+    keys, pts = base_samples(region, m, r)
+    vals = {k: np.asarray(v) for k, v in sample_fn(pts).items()}
+    cycles = 0
+    while cycles < max_cycles:
+        cycles += 1
+        inserted = 0
+        # one pass along the curve
+        gap = keys[1:] - keys[:-1]
+        fire = (gap >= 2) & (np.abs(vals["fll"][1:] - vals["fll"][:-1]) > thr)
+        if fire.any():
+            idx = np.nonzero(fire)[0]
+            newk = (keys[idx] + keys[idx + 1]) // 2
+            newv = sample_fn(key_positions(region, m, r, newk))
+            keys = np.insert(keys, idx + 1, newk)
+            vals = {k: np.insert(v, idx + 1, np.asarray(newv[k]), axis=0) for k, v in vals.items()}
+            inserted += newk.size
+        # one pass along the shifted curve
+        cells = region.cells(L, keys)
+        kp = _curve_index(region, L + 1, [np.asarray(c) + shift for c in cells])
+        order = np.argsort(kp, kind="stable")
+        ks, fs = kp[order], vals["fll"][order]
+        fire = (ks[1:] - ks[:-1] >= 2) & (np.abs(fs[1:] - fs[:-1]) > thr)
+        if fire.any():
+            j = np.nonzero(fire)[0]
+            mid = (ks[j] + ks[j + 1]) // 2
+            back = [np.asarray(c) - shift for c in region.cells(L + 1, mid)]
+            inside = np.ones(mid.size, dtype=bool)
+            for c in back:
+                inside &= (c >= 0) & (c < (1 << L))
+            newk = _curve_index(region, L, [c[inside] for c in back]) if inside.any() else np.zeros(0, np.int64)
+            if newk.size:
+                # a cell strictly between two successive samples of the shifted
+                # order holds no sample, and distinct pairs give distinct cells
+                assert np.unique(newk).size == newk.size and not np.isin(newk, keys).any()
+                newv = sample_fn(key_positions(region, m, r, newk))
+                keys = np.concatenate([keys, newk])
+                vals = {k: np.concatenate([v, np.asarray(newv[k])], axis=0) for k, v in vals.items()}
+                o = np.argsort(keys, kind="stable")
+                keys = keys[o]
+                vals = {k: v[o] for k, v in vals.items()}
+                inserted += newk.size
+        if inserted == 0:
+            break
+    return keys, vals, cycles
 
 
 def convert_to_grid(keys, values, m: int, r: int, level: int, log_interp: bool, cells=None, dims=2):

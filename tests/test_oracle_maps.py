@@ -277,3 +277,100 @@ def test_convert_volume_brute_force(oracle_mod):
     # block 1 ([8,16)) empty: log-interpolated at key 11.5 between keys 4 and 20
     w = (11.5 - 4) / 16
     assert g[z[1], y[1], x[1]] == pytest.approx(10 ** ((1 - w) * np.log10(50) + w * np.log10(2)))
+
+
+# ---------------------------------------------------------------------------
+# shifted-curve re-pass (Sect. 3.6, last paragraph)
+# ---------------------------------------------------------------------------
+
+def _quadrant(p):
+    """Length 1 in the lower-right quadrant (x > 0, y < 0), 0 elsewhere: its
+    edges run along the curve's top-level seams, where spatial neighbours lie
+    in the first and last quadrants of the curve, far apart along it."""
+    f = ((p[:, 0] > 0) & (p[:, 1] < 0)).astype(float)
+    return {"fll": f, "q": 2.0 + f}
+
+
+def _longest_miss(O, plane, m, r, keys):
+    """Longest stretch (in base pixels) along either edge of the quadrant
+    (x = 0 for y < -0.1, y = 0 for x > 0.1) with no refined sample within one
+    finest cell of the edge."""
+    fine, base = 2.0 / (1 << (m + r)), 2.0 / (1 << m)
+    pos = O.key_positions(plane, m, r, keys[keys % (1 << (2 * r)) != (1 << (2 * r)) // 2])
+    x, y = pos[:, 0], pos[:, 1]
+    ys = np.sort(y[(np.abs(x) < fine) & (y < -0.1)])
+    xs = np.sort(x[(np.abs(y) < fine) & (x > 0.1)])
+    g1 = np.diff(np.concatenate([[-1.0], ys, [-0.1]])).max()
+    g2 = np.diff(np.concatenate([[0.1], xs, [1.0]])).max()
+    return max(g1, g2) / base
+
+
+def test_shifted_repass_finds_the_seam_jump(oracle_mod):
+    """The jump along the curve's seams: without the re-pass only the one
+    curve-successive pair that crosses an edge (where the curve passes from
+    the upper-right to the lower-right quadrant) is refined, so the edges are
+    missed along nearly their whole length (14 of 14.4 base pixels); the
+    re-pass refines both edges with no miss longer than 3 base pixels, and the
+    refined set is complete in both orders."""
+    O = oracle_mod
+    plane = O.SlicePlane(*PLANE_ARGS)
+    m, r = 5, 2
+    plain, _, _ = O.refine_slice(plane, m, r, 0.5, _quadrant)
+    keys, vals, cycles = O.refine_shifted(plane, m, r, 0.5, _quadrant, shift=6)
+    miss_plain, miss_shift = _longest_miss(O, plane, m, r, plain), _longest_miss(O, plane, m, r, keys)
+    print(f"longest miss along the edges: plain {miss_plain:.2f}, shifted re-pass {miss_shift:.2f} base pixels; "
+          f"{keys.size} samples, {cycles} cycles")
+    assert miss_plain > 10.0 and miss_shift <= 3.0
+    assert np.all(np.diff(keys) > 0) and keys.size > plain.size
+    _complete_both_orders(O, plane, m, r, keys, vals["fll"], 0.5, 6)
+
+
+def _complete_both_orders(O, region, m, r, keys, fll, thr, shift):
+    """No pair fires along the curve, and every pair that fires along the
+    shifted curve has its new cell outside the map."""
+    L = m + r
+    assert not np.any((np.diff(keys) >= 2) & (np.abs(np.diff(fll)) > thr))
+    cells = region.cells(L, keys)
+    kp = O._curve_index(region, L + 1, [np.asarray(c) + shift for c in cells])
+    o = np.argsort(kp)
+    ks, fs = kp[o], fll[o]
+    fire = (np.diff(ks) >= 2) & (np.abs(np.diff(fs)) > thr)
+    mid = (ks[:-1][fire] + ks[1:][fire]) // 2
+    back = [np.asarray(c) - shift for c in region.cells(L + 1, mid)]
+    inside = np.ones(mid.size, bool)
+    for c in back:
+        inside &= (c >= 0) & (c < (1 << L))
+    assert not inside.any()
+
+
+def test_shifted_repass_leaves_a_jump_free_map_alone(oracle_mod):
+    O = oracle_mod
+    plane = O.SlicePlane(*PLANE_ARGS)
+    smooth = lambda p: {"fll": 0.01 * p[:, 0] + 0.02 * p[:, 1], "q": np.full(len(p), 2.0)}   # noqa: E731
+    keys, _, cycles = O.refine_shifted(plane, 4, 2, 0.05, smooth, shift=6)
+    assert cycles == 1 and np.array_equal(keys, np.arange(256) * 16 + 8)
+
+
+def test_shifted_repass_disc_and_volume(oracle_mod):
+    """A disc (no seam-aligned edges): with the re-pass every sample off the
+    base lattice still lies within one base pixel of the edge, there are more
+    of them, and the set ends complete in both orders; likewise a ball in a
+    volume.  (The re-pass's samples split the curve's gaps unevenly, so later
+    passes along the curve may pick other midpoints than the plain rule.)"""
+    O = oracle_mod
+    plane = O.SlicePlane(*PLANE_ARGS)
+    m, r, R = 5, 2, 0.5
+    plain, _, _ = O.refine_slice(plane, m, r, 0.5, _disc(R))
+    keys, vals, cycles = O.refine_shifted(plane, m, r, 0.5, _disc(R), shift=6)
+    assert keys.size > plain.size and cycles >= 2
+    new = keys[keys % 16 != 8]
+    pos = O.key_positions(plane, m, r, new)
+    assert np.all(np.abs(np.hypot(pos[:, 0], pos[:, 1]) - R) < 2.0 / (1 << m) * np.sqrt(2))
+    _complete_both_orders(O, plane, m, r, keys, vals["fll"], 0.5, 6)
+    box = O.VolumeBox(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0)
+    ball = lambda p: {"fll": (np.sum((p - [0.1, -0.2, 0.45]) ** 2, axis=1) < 0.3 ** 2).astype(float),   # noqa: E731
+                      "q": np.full(len(p), 2.0)}
+    vk, vv, vc = O.refine_shifted(box, 3, 2, 0.5, ball, shift=3)
+    vplain, _, _ = O.refine_slice(box, 3, 2, 0.5, ball)
+    assert vk.size > vplain.size
+    _complete_both_orders(O, box, 3, 2, vk, vv["fll"], 0.5, 3)

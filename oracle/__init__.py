@@ -61,7 +61,8 @@ class _Desc(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h_init", C.c_double),
                 ("h_max", C.c_double), ("max_length", C.c_double), ("max_steps", C.c_int64),
-                ("frame_angle", C.c_double), ("nthreads", C.c_int32), ("stepper", C.c_int32)]
+                ("frame_angle", C.c_double), ("nthreads", C.c_int32), ("stepper", C.c_int32),
+                ("round_f32", C.c_int32), ("pad", C.c_int32)]
 
 
 STEPPERS = {"ck54": 0, "euler": 1}
@@ -175,12 +176,17 @@ def default_opts(field: Field, spacing_min: float, tol: float):
 
 
 def trace(field: Field, seeds, *, rtol, atol, h_init, h_max, max_length=0.0,
-          max_steps=1 << 22, frame_angle=0.0, nthreads=0, want_ends=False, stepper="ck54"):
+          max_steps=1 << 22, frame_angle=0.0, nthreads=0, want_ends=False, stepper="ck54",
+          round_f32=False):
     """Trace seeds (n, 3) both ways; return a dict of per-seed arrays.
 
     stepper "ck54": adaptive Cash-Karp 5(4) (rtol, atol, first step h_init,
     largest step h_max); "euler": explicit Euler with the fixed step h_init
     (rtol, atol, h_max unused), Sect. 3.4.
+
+    round_f32 is a test instrument, off for every parity reference: it rounds
+    each CK54 stage point and each accepted state to FP32, so that a test can
+    measure how many lines the roundings FP32 stepping cannot avoid move.
 
     Keys: fp_fwd, fp_bwd (n,3); fll, q_perp (eq. 11), q_det (determinant
     form), q_fp (exit-face planes), lam_fwd, lam_bwd (n,); status (n,) int32
@@ -189,7 +195,8 @@ def trace(field: Field, seeds, *, rtol, atol, h_init, h_max, max_length=0.0,
     """
     seeds = np.ascontiguousarray(seeds, dtype=np.float64).reshape(-1, 3)
     n = seeds.shape[0]
-    o = _Opts(rtol, atol, h_init, h_max, max_length, int(max_steps), frame_angle, nthreads, STEPPERS[stepper])
+    o = _Opts(rtol, atol, h_init, h_max, max_length, int(max_steps), frame_angle, nthreads, STEPPERS[stepper],
+              int(bool(round_f32)), 0)
     out = dict(fp_fwd=np.empty((n, 3)), fp_bwd=np.empty((n, 3)), fll=np.empty(n),
                q_perp=np.empty(n), q_det=np.empty(n), q_fp=np.empty(n),
                lam_fwd=np.empty(n), lam_bwd=np.empty(n),

@@ -88,6 +88,10 @@ typedef struct {
     double frame_angle;    /* rotate (a, b) about Bhat(x0) by this angle */
     int32_t nthreads;      /* <= 0: OpenMP default */
     int32_t stepper;       /* OR_CK54 (adaptive) or OR_EULER (fixed step h_init) */
+    int32_t round_f32;     /* sensitivity instrument, 0 = off (plain FP64): 1 rounds
+                              every CK54 stage point and every accepted state to
+                              FP32, the roundings FP32 stepping cannot avoid */
+    int32_t pad;
 } or_opts;
 
 /* steppers (Sect. 3.4) */
@@ -340,7 +344,7 @@ void or_ck54_tableau(double *c, double *a, double *b5, double *b4)
 
 /* one trial step: 5th-order solution (propagated) and embedded 4th order */
 static void ck54_step(const or_field *F, double sigma, const double y[9], double h,
-                      double y5[9], double y4[9])
+                      double y5[9], double y4[9], int round_f32)
 {
     double k[6][9], yt[9];
     for (int s = 0; s < 6; ++s) {
@@ -348,8 +352,11 @@ static void ck54_step(const or_field *F, double sigma, const double y[9], double
             double acc = 0.0;
             for (int j = 0; j < s; ++j) acc += CK_A[s][j] * k[j][i];
             yt[i] = y[i] + h * acc;
+            if (round_f32) yt[i] = (double)(float)yt[i];
         }
         rhs(F, sigma, yt, k[s]);
+        if (round_f32)
+            for (int i = 0; i < 9; ++i) k[s][i] = (double)(float)k[s][i];
     }
     for (int i = 0; i < 9; ++i) {
         double a5 = 0.0, a4 = 0.0;
@@ -395,7 +402,7 @@ static double face_gap(const or_field *F, double sigma, const double y[9], doubl
     if (h == 0.0)
         memcpy(yo, y, sizeof(double) * 9);
     else
-        ck54_step(F, sigma, y, h, yo, y4);
+        ck54_step(F, sigma, y, h, yo, y4, 0);
     int d = f / 2;
     return (f & 1) ? yo[d] - F->d.hi[d] : F->d.lo[d] - yo[d];
 }
@@ -540,7 +547,7 @@ static void trace_half(const or_field *F, const or_opts *O, double sigma, const 
             hs = O->max_length - s;
             last = 1;
         }
-        ck54_step(F, sigma, y, hs, y5, y4);
+        ck54_step(F, sigma, y, hs, y5, y4, O->round_f32);
         if (!all_finite(y5, 9) || !all_finite(y4, 9)) {
             out->status = OR_NONFINITE;
             break;
@@ -576,7 +583,7 @@ static void trace_half(const or_field *F, const or_opts *O, double sigma, const 
             }
             double yl[9];
             if (best > 0.0)
-                ck54_step(F, sigma, y, best, yl, y4);
+                ck54_step(F, sigma, y, best, yl, y4, 0);
             else
                 memcpy(yl, y, sizeof yl);
             int d = face / 2;
@@ -587,6 +594,8 @@ static void trace_half(const or_field *F, const or_opts *O, double sigma, const 
             break;
         }
         memcpy(y, y5, sizeof y);
+        if (O->round_f32)
+            for (int i = 0; i < 9; ++i) y[i] = (double)(float)y[i];
         if (last) {
             s = O->max_length;
             out->status = OR_MAX_LENGTH;

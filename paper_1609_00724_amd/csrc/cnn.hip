@@ -484,13 +484,16 @@ __global__ void __launch_bounds__(256) k_sum_parts(const double *part, int n, do
 }
 
 // Adam (Kingma & Ba 2015) on the FP32 master parameters
-__global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
-                       float c1, float c2)
+// b1, b2 are the decay rates, ob1 = 1 - b1 and ob2 = 1 - b2 (formed in FP64
+// on the host: 1 - b2 taken in FP32 from the rounded 0.999f is 1.3e-5 off),
+// c1, c2 the bias corrections 1 - b^t.
+__global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float ob1,
+                       float ob2, float eps, float c1, float c2)
 {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const float ge = g[e];
-        const float me = b1 * m[e] + (1.0f - b1) * ge;
-        const float ve = b2 * v[e] + (1.0f - b2) * ge * ge;
+        const float me = b1 * m[e] + ob1 * ge;
+        const float ve = b2 * v[e] + ob2 * ge * ge;
         m[e] = me;
         v[e] = ve;
         p[e] -= lr * (me / c1) / (sqrtf(ve / c2) + eps);
@@ -683,10 +686,12 @@ hipError_t cnn_train_step(float *params, float *adam_m, float *adam_v, int64_t t
         if (e != hipSuccess) return e;
         gin = gnext;
     }
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+    // Kingma & Ba's defaults; every constant is formed in FP64 and rounded once
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 - pow(b1, (double)t)), c2 = (float)(1.0 - pow(b2, (double)t));
     hipLaunchKernelGGL(k_adam, dim3(blocks_for(QSQ_CNN_PARAMS, 256)), dim3(256), 0, st, params, g, adam_m, adam_v,
-                       (int64_t)QSQ_CNN_PARAMS, lr, b1, b2, 1e-8f, c1, c2);
+                       (int64_t)QSQ_CNN_PARAMS, lr, (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f,
+                       c1, c2);
     return cnn_prepare(params, prep, st);
 }
 

@@ -207,6 +207,27 @@ uint64_t qsq_trace_scratch_bytes(int64_t n);
 int qsq_trace(const qsq_field *f, const double *seeds, int64_t n, const qsq_trace_opts *opts,
               const qsq_trace_out *out, void *scratch, uint64_t scratch_bytes, void *stream);
 
+/* ---- tracing without allocation ---------------------------------------- */
+
+#define QSQ_TRACE_NOALLOC_MAX_SEEDS (1 << 18)
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): qsq_trace
+ * with its scratch in a fixed 64 MiB device array owned by the library (one
+ * copy per device, held until the process ends) instead of a caller buffer.
+ * The caller still passes the field, seeds and outputs; the call allocates
+ * nothing and computes exactly what qsq_trace computes.  At most
+ * QSQ_TRACE_NOALLOC_MAX_SEEDS seeds per call (WORKSPACE_TOO_SMALL beyond).
+ * Every call on a device shares that device's array: calls that overlap in
+ * time on one device (different streams or host threads without ordering)
+ * race and give undefined results; calls on one stream are ordered and safe.
+ * The first call on a device looks up the array's address there.  Errors: as
+ * qsq_trace, plus WORKSPACE_TOO_SMALL for n above the limit.
+ */
+int qsq_trace_noalloc(const qsq_field *f, const double *seeds, int64_t n, const qsq_trace_opts *opts,
+                      const qsq_trace_out *out, void *stream);
+
 /* ---- batched trace ------------------------------------------------------ */
 
 /* One seed set of a batched trace: a prepared field, its seeds and outputs. */

@@ -30,7 +30,7 @@ EXPORTS = ["qsq_abi_version", "qsq_status_string", "qsq_last_error", "qsq_field_
            "qsq_hilbert2_d2xy", "qsq_hilbert2_xy2d", "qsq_qmap_scratch_bytes", "qsq_qmap",
            "qsq_profile_enable", "qsq_profile_reset", "qsq_profile_read",
            "qsq_hilbert3_d2xyz", "qsq_hilbert3_xyz2d", "qsq_vmap_scratch_bytes", "qsq_vmap",
-           "qsq_trace_batch_scratch_bytes", "qsq_trace_batch"]
+           "qsq_trace_batch_scratch_bytes", "qsq_trace_batch", "qsq_trace_noalloc"]
 
 # every entry point include/qsq_cnn.h declares
 CNN_EXPORTS = ["qsq_cnn_prep_bytes", "qsq_cnn_prepare", "qsq_cnn_workspace_bytes", "qsq_cnn_layer_scratch_bytes",
@@ -38,6 +38,7 @@ CNN_EXPORTS = ["qsq_cnn_prep_bytes", "qsq_cnn_prepare", "qsq_cnn_workspace_bytes
 CNN_PARAMS = 19970
 
 MAX_TRACE_SETS = 65536
+TRACE_NOALLOC_MAX_SEEDS = 1 << 18
 
 KERNEL_STEP, KERNEL_LAND, KERNEL_ASSEMBLE = 0, 1, 2
 
@@ -122,6 +123,8 @@ def _load():
     L.qsq_trace.argtypes = [C.POINTER(FieldDesc), P, I64, C.POINTER(TraceOpts), C.POINTER(TraceOut),
                             P, U64, P]
     L.qsq_trace_batch_scratch_bytes.restype = U64
+    L.qsq_trace_noalloc.restype = I
+    L.qsq_trace_noalloc.argtypes = [C.POINTER(FieldDesc), P, I64, C.POINTER(TraceOpts), C.POINTER(TraceOut), P]
     L.qsq_trace_batch_scratch_bytes.argtypes = [C.c_int32, I64]
     L.qsq_trace_batch.restype = I
     L.qsq_trace_batch.argtypes = [C.POINTER(TraceSet), C.c_int32, C.POINTER(TraceOpts), P, P, U64, P]

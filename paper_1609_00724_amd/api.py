@@ -95,8 +95,9 @@ class TracePlan:
     """Preallocated outputs and scratch for repeated traces of n seeds."""
 
     def __init__(self, n: int, device, want=("fp_fwd", "fp_bwd", "fll", "q_perp", "q_det", "q_fp"),
-                 want_steps=False, want_work=False):
+                 want_steps=False, want_work=False, noalloc=False):
         self.n = int(n)
+        self.noalloc = bool(noalloc)   # run through qsq_trace_noalloc (library-owned scratch)
         f64 = dict(dtype=torch.float64, device=device)
         self.out = {}
         for k in want:
@@ -106,15 +107,19 @@ class TracePlan:
             self.out["steps"] = torch.empty((2, n), dtype=torch.int32, device=device)
         if want_work:
             self.out["work"] = torch.zeros(4, dtype=torch.int64, device=device)
-        self.scratch = _bytes_tensor(lib.qsq_trace_scratch_bytes(n), device)
+        self.scratch = None if self.noalloc else _bytes_tensor(lib.qsq_trace_scratch_bytes(n), device)
         o = A.TraceOut()
         for k in ("fp_fwd", "fp_bwd", "fll", "q_perp", "q_det", "q_fp", "status", "steps", "work"):
             setattr(o, k, _p(self.out.get(k)))
         self.tout = o
 
     def run(self, field: Field, seeds_soa: torch.Tensor, opts: A.TraceOpts, stream=None):
-        check(lib.qsq_trace(C.byref(field.desc), _p(seeds_soa), self.n, C.byref(opts), C.byref(self.tout),
-                            _p(self.scratch), self.scratch.numel() * 8, _stream(stream)))
+        if self.noalloc:
+            check(lib.qsq_trace_noalloc(C.byref(field.desc), _p(seeds_soa), self.n, C.byref(opts),
+                                        C.byref(self.tout), _stream(stream)))
+        else:
+            check(lib.qsq_trace(C.byref(field.desc), _p(seeds_soa), self.n, C.byref(opts), C.byref(self.tout),
+                                _p(self.scratch), self.scratch.numel() * 8, _stream(stream)))
         return self.out
 
 

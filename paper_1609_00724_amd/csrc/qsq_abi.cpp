@@ -311,6 +311,61 @@ int qsq_trace(const qsq_field *f, const double *seeds, int64_t n, const qsq_trac
     return ok();
 }
 
+}  // extern "C"
+
+// Scratch of qsq_trace_noalloc: a fixed device array, one copy per device,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+#define QSQ_NOALLOC_SCRATCH_BYTES (64ull << 20)
+static __device__ __align__(256) unsigned char scratch[QSQ_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kMaxDevices] = {};
+
+// device address of this device's copy of `scratch` (set up on the first call
+// made with that device current)
+int noalloc_scratch(void **ptr)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "qsq_trace_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(QSQ_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "qsq_trace_noalloc: hipGetSymbolAddress");
+        if (!p || !aligned(p, 256)) return fail(QSQ_ERR_HIP, "qsq_trace_noalloc: bad scratch address");
+        g_noalloc_ptr[dev] = p;
+    }
+    *ptr = g_noalloc_ptr[dev];
+    return QSQ_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int qsq_trace_noalloc(const qsq_field *f, const double *seeds, int64_t n, const qsq_trace_opts *opts,
+                      const qsq_trace_out *out, void *stream)
+{
+    if (n > QSQ_TRACE_NOALLOC_MAX_SEEDS)
+        return fail(QSQ_ERR_WORKSPACE_TOO_SMALL, "qsq_trace_noalloc: n = %lld > %d seeds", (long long)n,
+                    QSQ_TRACE_NOALLOC_MAX_SEEDS);
+    if (qsq_trace_scratch_bytes(n) > QSQ_NOALLOC_SCRATCH_BYTES)
+        return fail(QSQ_ERR_WORKSPACE_TOO_SMALL, "qsq_trace_noalloc: scratch of %lld seeds exceeds %llu bytes",
+                    (long long)n, (unsigned long long)QSQ_NOALLOC_SCRATCH_BYTES);
+    void *ptr = nullptr;
+    if (n > 0) {
+        // the other arguments are checked by qsq_trace before anything is enqueued
+        const int rc = noalloc_scratch(&ptr);
+        if (rc) return rc;
+    }
+    return qsq_trace(f, seeds, n, opts, out, ptr, QSQ_NOALLOC_SCRATCH_BYTES, stream);
+}
+
 static uint64_t round256(uint64_t b) { return (b + 255) & ~(uint64_t)255; }
 
 // prefix the last error message with the set that caused it

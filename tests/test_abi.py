@@ -214,3 +214,15 @@ def test_cnn_arguments_rejected_before_launch(qsq):
     s = L.qsq_cnn_layer_scratch_bytes(4, 64, 64)
     assert L.qsq_cnn_layer_backward(0, _fake(1), _fake(2), _fake(3), 4, 64, 64, _fake(4), _fake(5), _fake(6),
                                     _fake(7), s, None) == A.ERR_INVALID_ARG     # layer 0 has no input gradient
+
+
+def test_noalloc_limits(qsq):
+    """qsq_trace_noalloc rejects a seed count beyond its fixed scratch before
+    touching the device, and its limit fits the 64 MiB array."""
+    from paper_1609_00724_amd import _abi as A
+    assert qsq.lib.qsq_trace_scratch_bytes(A.TRACE_NOALLOC_MAX_SEEDS) <= 64 << 20
+    f = A.FieldDesc()
+    o = A.TraceOpts()
+    rc = qsq.lib.qsq_trace_noalloc(C.byref(f), None, A.TRACE_NOALLOC_MAX_SEEDS + 1, C.byref(o), None, None)
+    assert rc == A.ERR_WORKSPACE_TOO_SMALL
+    assert b"noalloc" in qsq.lib.qsq_last_error()

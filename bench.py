@@ -1,17 +1,23 @@
 #!/usr/bin/env python3
 """Throughput of the QSL Squasher hot path on one MI355X.
 
-One step = one whole photospheric Q / length / FLEDGE map of a 4-charge
-potential field on a 256x256x128 FP32 grid: 1024^2 base lines traced both ways
-(adaptive Cash-Karp 5(4), FP32 stepping, FP64 landing and Q), the Sobel FLEDGE
-map, FLL-jump refinement along the Hilbert curve to 4x the base resolution
-(two levels, every pass on the device), and the array converter.  Inputs are
-resident in HBM before timing starts.
+One step (default workload) = one whole refined 3D Q / length / FLEDGE volume
+of a twisted flux rope over a 6-charge potential background on a 384x384x256
+FP32 grid: 256^3 base cells traced both ways (adaptive Cash-Karp 5(4), FP32
+stepping, FP64 landing and Q), the 3D Sobel FLEDGE map, FLL-jump refinement
+along the 3D Hilbert curve to 4x the base resolution per axis (every pass on
+the device), and the array converter.  Inputs are resident in HBM before
+timing starts.  `--workload map` runs the photospheric 1024^2 map of a
+4-charge field on a 256x256x128 grid instead.
 
-Printed (one JSON line): lines traced with Q per second, the stepping
-kernel's achieved FLOP rate against the VALU ceiling, the oracle's throughput
-on the host cores on a bounded sample, and the median relative log10 Q error
-against the FP64 oracle at tolerance 1e-10 on a fixed set of lines.
+Fixed-error protocol: on a fixed seeded set of lines, the GPU tracer at each
+candidate setting (tolerance x largest step; Euler: step size) is compared
+with the FP64 oracle at tolerance 1e-10 on the same gridded field; among the
+settings whose median relative log10 Q error is <= 1e-3 the fastest map is
+timed.  Printed (one JSON line): lines traced with Q per second at that
+setting, the stepping kernel's achieved FLOP rate from the work of the kept
+samples against the FP32 vector peak, the oracle's throughput on the host
+cores (all allotted and one) on a bounded sample, and the sweep itself.
 """
 from __future__ import annotations
 
@@ -37,10 +43,18 @@ METRIC = "field lines traced with Q per sec (1 GPU) + % HBM/L2 roofline at fixed
 FLOP_PER_EVAL = 147
 FLOP_PER_ATTEMPT = 600
 FLOP_PER_EULER_STEP = 18
-# VALU ceiling for this kernel: 256 CUs x 4 SIMD x 16 lanes x 2 FLOP (FMA) x
-# 2.4 GHz; packed FP32 is disabled in the build, so the packed-FP32 rate
-# (157.3 TFLOP/s) is out of reach and is not the ceiling.
-VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Published FP32 vector peak of the MI355X: 256 CUs x 4 SIMD x 16 lanes x
+# 2 FLOP (FMA) x 2 (packed FP32, two lanes of work per instruction) x 2.4 GHz.
+FP32_PEAK_TFLOPS = 157.3
+# The same without packed FP32, which this build does not emit: the ceiling
+# of one FP32 FMA per lane per clock.
+FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+# fixed-error protocol
+TARGET_MEDIAN = 1e-3
+SWEEP_TOLS = (1e-2, 3e-3, 1e-3, 3e-4, 1e-4)
+SWEEP_HMAX_CELLS = (1.0, 2.0, 3.0, 4.0)
+SWEEP_EULER_DIVS = (5, 10, 20)     # Euler step = one grid cell / this
 
 
 def parse():
@@ -48,34 +62,41 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--tol", type=float, default=1e-4, help="stepping rtol = atol")
-    ap.add_argument("--base-level", type=int, default=10)
+    ap.add_argument("--workload", choices=("volume", "map", "batch", "learned"), default="volume",
+                    help="volume: 3D Q/FLL/FLEDGE volume of a flux-rope field (default); map: photospheric map "
+                         "of one field; batch: 64 fields in one batched trace; learned: the CNN proposer")
+    ap.add_argument("--tol", type=float, default=None,
+                    help="stepping rtol = atol; given with --hmax-cells it replaces the fixed-error sweep")
+    ap.add_argument("--hmax-cells", type=float, default=None, help="largest step, in grid cells")
+    ap.add_argument("--stepper", choices=("ck54", "euler"), default="ck54",
+                    help="map / volume: adaptive Cash-Karp 5(4), or explicit Euler with fixed steps")
+    ap.add_argument("--euler-div", type=int, default=None, help="Euler step = one cell / this (with --stepper euler)")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the fixed-error sweep (settings from --tol / --hmax-cells, else 1e-4 and 1 cell)")
+    ap.add_argument("--base-level", type=int, default=10, help="map workload: 2^m x 2^m base pixels")
+    ap.add_argument("--volume-level", type=int, default=8, help="volume workload: 2^m cells a side")
     ap.add_argument("--refine-levels", type=int, default=2)
     ap.add_argument("--threshold", type=float, default=0.02)
-    ap.add_argument("--refine-batch", type=int, default=0, help="refinement levels per device round (0: auto)")
-    ap.add_argument("--hmax-cells", type=float, default=1.0, help="largest step, in grid cells")
-    ap.add_argument("--stepper", choices=("ck54", "euler"), default="ck54",
-                    help="map workload: adaptive Cash-Karp 5(4), or explicit Euler with fixed steps of 1/5 cell")
-    ap.add_argument("--cpu-level", type=int, default=10, help="base level of the oracle's sample map (10: the whole map)")
+    ap.add_argument("--refine-batch", type=int, default=0, help="refinement levels per device round (0: tuned)")
+    ap.add_argument("--cpu-level", type=int, default=None,
+                    help="base level of the oracle's sample (default: map 8, volume 5)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
-    ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch shape")
     ap.add_argument("--launch", type=int, default=0, help="launch-shape word with --no-tune (0: library default)")
-    ap.add_argument("--accuracy-lines", type=int, default=256)
-    ap.add_argument("--workload", choices=("map", "batch", "volume", "learned"), default="map",
-                    help="map: photospheric map of one field; batch: 64 fields in one batched trace; "
-                         "volume: 3D Q/FLL/FLEDGE volume of a flux-rope field")
+    ap.add_argument("--accuracy-lines", type=int, default=2048)
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the accuracy and BF16 legs after the timed region (counter runs)")
     ap.add_argument("--batch-fields", type=int, default=64)
-    ap.add_argument("--volume-level", type=int, default=8, help="volume workload: base level (2^m cells a side)")
     ap.add_argument("--learn-fields", type=int, default=320, help="learned workload: maps generated (1/4 rope slices)")
     ap.add_argument("--learn-epochs", type=int, default=12)
     ap.add_argument("--cpu-fraction", type=float, default=0.25,
                     help="batch workload: fraction of each field's seeds the oracle traces")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
-    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
-                    help="write profiles/k_trace_traffic.json from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE csv "
-                         "outputs of this benchmark and of --calibrate-copy")
+    ap.add_argument("--summarize-pmc", nargs=5,
+                    metavar=("NAME", "FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write profiles/k_trace_traffic_NAME.json from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE "
+                         "csv outputs of this benchmark (workload NAME) and of --calibrate-copy")
     return ap.parse_args()
 
 
@@ -91,51 +112,212 @@ def main():
         return summarize_pmc(*args.summarize_pmc)
     if args.workload == "batch":
         return bench_batch(args)
-    if args.workload == "volume":
-        return bench_volume(args)
     if args.workload == "learned":
         return bench_learned(args)
+    return bench_field_map(args)
+
+
+# ---------------------------------------------------------------------------
+# fixed-error protocol
+# ---------------------------------------------------------------------------
+
+def rel_log10_err(qg, sg, ref):
+    """Relative log10 Q error per line against the oracle reference, on lines
+    whose exit faces agree and whose reference Q is finite and < 1e6."""
+    import numpy as np
+    qo = ref["q_perp"]
+    m = np.isfinite(qo) & np.isfinite(qg) & (qo < 1e6) & (sg == ref["status"])
+    return np.abs(np.log10(qg[m]) - np.log10(qo[m])) / np.abs(np.log10(qo[m]))
+
+
+class Setting:
+    """One point of the sweep: stepper, stepping precision, tolerance and
+    largest step (CK54), or step size (Euler), in grid cells."""
+
+    def __init__(self, stepper, step_dtype, tol=None, hmax_cells=None, euler_div=None):
+        self.stepper, self.step_dtype = stepper, step_dtype
+        self.tol, self.hmax_cells, self.euler_div = tol, hmax_cells, euler_div
+
+    def opts(self, h, launch=0):
+        from paper_1609_00724_amd.api import make_opts
+        if self.stepper == "euler":
+            o = make_opts(1e-3, 1e-3, h_init=h / self.euler_div, step_dtype=self.step_dtype, stepper="euler")
+        else:
+            o = make_opts(self.tol, self.tol, h_init=0.1 * h, h_max=self.hmax_cells * h,
+                          step_dtype=self.step_dtype)
+        o.launch = launch
+        return o
+
+    def oracle_kw(self, h):
+        if self.stepper == "euler":
+            return dict(rtol=1e-3, atol=1e-3, h_init=h / self.euler_div, h_max=h / self.euler_div, stepper="euler")
+        return dict(rtol=self.tol, atol=self.tol, h_init=0.1 * h, h_max=self.hmax_cells * h)
+
+    def describe(self):
+        if self.stepper == "euler":
+            return {"stepper": "euler", "step_dtype": self.step_dtype, "step_cells": 1.0 / self.euler_div}
+        return {"stepper": "ck54", "step_dtype": self.step_dtype, "tol": self.tol, "h_max_cells": self.hmax_cells}
+
+    def text(self):
+        if self.stepper == "euler":
+            return f"explicit Euler {self.step_dtype.upper()} stepping, fixed step 1/{self.euler_div} cell"
+        return (f"CK54 {self.step_dtype.upper()} stepping tol={self.tol:g} h_max={self.hmax_cells:g} cell")
+
+
+def sweep_settings(variant):
+    stepper, dt = variant
+    if stepper == "euler":
+        return [Setting("euler", dt, euler_div=d) for d in SWEEP_EULER_DIVS]
+    return [Setting("ck54", dt, tol=t, hmax_cells=c) for c in SWEEP_HMAX_CELLS for t in SWEEP_TOLS]
+
+
+def accuracy_of(field, seeds_dev, ref, setting, h):
+    """Median / p90 relative log10 Q error of the GPU tracer at `setting` on
+    the accuracy lines."""
     import numpy as np
     import torch
 
+    from paper_1609_00724_amd.api import TracePlan
+    plan = TracePlan(seeds_dev.shape[1], seeds_dev.device, want=("q_perp",))
+    out = plan.run(field, seeds_dev, setting.opts(h))
+    torch.cuda.synchronize()
+    e = rel_log10_err(out["q_perp"].cpu().numpy(), out["status"].cpu().numpy(), ref)
+    return {"median": float(np.median(e)), "p90": float(np.percentile(e, 90)), "lines": int(e.size)}
+
+
+def time_map(plan, field, opts, reps=1):
+    """Milliseconds of one map (the fastest of `reps`, after one untimed run)."""
+    import torch
+    plan.run(field, opts)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.run(field, opts)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def fixed_error(plan, field, seeds_dev, ref, h, variants, log):
+    """For each variant, every sweep setting's accuracy; the settings that
+    meet the target are timed on the map itself and the fastest is chosen.
+    Returns ({variant: chosen row or None}, all rows)."""
+    rows, chosen = [], {}
+    for var in variants:
+        best = None
+        for st in sweep_settings(var):
+            acc = accuracy_of(field, seeds_dev, ref, st, h)
+            row = dict(st.describe(), **acc, meets_target=acc["median"] <= TARGET_MEDIAN)
+            if row["meets_target"]:
+                row["map_ms"] = time_map(plan, field, st.opts(h))
+                row["lines_per_s"] = plan.result()["count"] / (row["map_ms"] / 1e3)
+                if best is None or row["map_ms"] < best[0]["map_ms"]:
+                    best = (row, st)
+            rows.append(row)
+            log(f"sweep {row}")
+        chosen[var] = best
+    return chosen, rows
+
+
+# ---------------------------------------------------------------------------
+# map and volume workloads
+# ---------------------------------------------------------------------------
+
+def bench_field_map(args):
+    """A refined Q / length / FLEDGE map: the 3D volume of the flux-rope field
+    (default) or the photospheric slice of the 4-charge field, at the
+    fixed-error setting, with the stepping kernel's roofline from the work of
+    the kept samples."""
+    import numpy as np
+    import torch
+
+    import oracle
     import paper_1609_00724_amd as q
     import synth
     from paper_1609_00724_amd import _abi as A
-    from paper_1609_00724_amd.api import MapSpec, Profiler, QMapPlan, make_opts
+    from paper_1609_00724_amd.api import MapSpec, Profiler, QMapPlan, VolumeSpec
+
+    def log(msg):
+        print(f"bench: {msg}", file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
-    w = synth.charges_c2()
-    h = min(w["spacing"])
+    volume = args.workload == "volume"
+    t_gen = time.perf_counter()
+    if volume:
+        w = synth.flux_rope_c4(device=dev)
+        m = args.volume_level
+    else:
+        w = synth.charges_c2()
+        m = args.base_level
     b = [torch.from_numpy(c).to(dev) for c in w["b"]]
     field = q.field_init(*b, w["origin"], w["spacing"], storage="f32")
-    m, r = args.base_level, args.refine_levels
-    spec = MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, r, m, args.threshold, args.refine_batch)
-    plan = QMapPlan(spec, 4 ** (m + r), dev)    # the finest lattice: the map cannot overflow
-    hmax = args.hmax_cells * h
-    if args.stepper == "euler":
-        opts = make_opts(args.tol, args.tol, step_dtype="f32", stepper="euler")   # fixed step h / 5
+    bf16 = q.field_init(*b, w["origin"], w["spacing"], storage="bf16") if volume else None
+    del b
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    h = min(w["spacing"])
+    r, thr = args.refine_levels, args.threshold
+    dims = 3 if volume else 2
+    if volume:
+        spec = VolumeSpec(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0, m, r, m, thr, args.refine_batch)
+        cap = 8 ** m * 4
     else:
-        opts = make_opts(args.tol, args.tol, h_init=0.1 * h, h_max=hmax, step_dtype="f32")
-    stream = torch.cuda.current_stream()
+        spec = MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, r, m, thr, args.refine_batch)
+        cap = 4 ** (m + r)     # the finest lattice: the map cannot overflow
+    plan = QMapPlan(spec, cap, dev, want_steps=True)
+    log(f"field ready ({t_gen:.1f} s)")
+
+    # reference lines: FP64 oracle at tolerance 1e-10 on the same gridded field
+    acc_seeds = (synth.random_seeds(2025, args.accuracy_lines) if volume
+                 else synth.random_seeds(2024, args.accuracy_lines, z=0.0))
+    fo = oracle.Field.grid(*(np.asarray(c, np.float64) for c in w["b"]), w["origin"], w["spacing"])
+    t_ref = time.perf_counter()
+    ref = oracle.trace(fo, acc_seeds, rtol=1e-10, atol=1e-10, h_init=0.1 * h, h_max=h)
+    t_ref = time.perf_counter() - t_ref
+    log(f"reference lines traced ({t_ref:.1f} s)")
+    seeds_dev = torch.from_numpy(np.ascontiguousarray(acc_seeds.T)).to(dev)
+
+    # the setting: the fixed-error sweep, or given on the command line
+    variant = (args.stepper, "f32")
+    rows, chosen = [], {}
+    if args.no_sweep or args.tol is not None or args.euler_div is not None:
+        st = (Setting("euler", "f32", euler_div=args.euler_div or 5) if args.stepper == "euler"
+              else Setting("ck54", "f32", tol=args.tol or 1e-4, hmax_cells=args.hmax_cells or 1.0))
+    else:
+        variants = [("ck54", "f32"), ("ck54", "f64"), ("euler", "f32")]
+        chosen, rows = fixed_error(plan, field, seeds_dev, ref, h, variants, log)
+        if chosen[variant] is None:
+            raise SystemExit("no sweep setting meets the fixed-error target")
+        st = chosen[variant][1]
+    opts = st.opts(h, args.launch)
+    log(f"setting: {st.text()}")
 
     tuned = None
-    opts.launch = args.launch
     if not args.no_tune:
-        # launch shape picked on the workload itself, before the timed region
+        # launch shape and refinement batch timed on the workload itself
         from paper_1609_00724_amd import autotune
-        batches = (args.refine_batch,) if args.refine_batch > 0 else (1, 2, 3, 4)
-        (word, batch), table = autotune.tune_map(plan, field, opts, reps=2, batches=batches)
+        if volume:
+            cands = ([A.launch_word(2, 128, A.GATHER_DIRECT), A.launch_word(2, 128, A.GATHER_CACHED)]
+                     + autotune.candidates(lanes=(1, 2), wgs=(64, 128, 256), gathers=(A.GATHER_REGS,)))
+            batches = (args.refine_batch,) if args.refine_batch > 0 else (1, 2, 3)
+            (word, batch), table = autotune.tune_map(plan, field, opts, reps=1, cands=cands, batches=batches)
+        else:
+            batches = (args.refine_batch,) if args.refine_batch > 0 else (1, 2, 3, 4)
+            (word, batch), table = autotune.tune_map(plan, field, opts, reps=2, batches=batches)
         opts.launch = word
         plan.d.refine_batch = batch
         tuned = dict(autotune.describe(word), refine_batch=batch, ms=table[(word, batch)], candidates=len(table),
                      worst_ms=max(table.values()))
+        log(f"tuned: {tuned}")
+    stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         plan.run(field, opts)
     torch.cuda.synchronize()
     plan.work.zero_()
     with Profiler() as prof:
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         wall0 = time.perf_counter()
         t0.record(stream)
@@ -144,24 +326,34 @@ def main():
         t1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
-        ms_total = t0.elapsed_time(t1)
-        n_step, ms_step = prof.read(A.KERNEL_STEP)
+        ms_per_step = t0.elapsed_time(t1) / args.steps
+        n_step, ms_trace = prof.read(A.KERNEL_STEP)
         n_land, ms_land = prof.read(A.KERNEL_LAND)
         n_asm, ms_asm = prof.read(A.KERNEL_ASSEMBLE)
     Profiler.reset()
     res = plan.result()
     lines = res["count"]
-    work = plan.work.cpu().numpy().astype(np.int64)
-    attempts, evals, stepped, landed = (int(v) for v in work)
-    ms_per_step = ms_total / args.steps
-    value = lines / (ms_per_step / 1e3)
-
-    per_attempt = FLOP_PER_EULER_STEP if args.stepper == "euler" else FLOP_PER_ATTEMPT
-    flops = FLOP_PER_EVAL * evals + per_attempt * attempts
-    achieved = flops / (ms_step / 1e3) / 1e12 if ms_step > 0 else 0.0
+    attempts, evals, stepped, landed = (int(v) for v in plan.work.cpu().numpy())
+    kept_attempts = int(res["steps"].to(torch.int64).sum().item()) * args.steps
+    per_attempt = FLOP_PER_EULER_STEP if st.stepper == "euler" else FLOP_PER_ATTEMPT
+    traced_flops = FLOP_PER_EVAL * evals + per_attempt * attempts
+    # the method's own work: the kept samples' lines (speculative lines the
+    # rule drops are traced but are not the method's); evaluations per attempt
+    # are taken as equal for kept and dropped lines
+    own = kept_attempts / max(attempts, 1)
+    own_flops = traced_flops * own
+    achieved = own_flops / (ms_trace / 1e3) / 1e12 if ms_trace > 0 else 0.0
+    traffic = measured_traffic(args.workload)
+    grid_txt = "x".join(str(v) for v in w["n"])
+    if volume:
+        wl = (f"3D Q/FLL/FLEDGE volume, flux rope over a 6-charge background on a {grid_txt} FP32 grid, "
+              f"{1 << m}^3 base cells + FLL-jump 3D Hilbert refinement r={r} thr={thr}")
+    else:
+        wl = (f"photospheric Q/FLL/FLEDGE map, 4-charge potential field on a {grid_txt} FP32 grid, "
+              f"{1 << m}^2 base lines + FLL-jump Hilbert refinement r={r} thr={thr}")
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": lines / (ms_per_step / 1e3),
         "unit": "lines/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -173,48 +365,123 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": (f"photospheric Q/FLL/FLEDGE map, 4-charge potential field on a 256x256x128 FP32 grid, "
-                         f"{1 << m}^2 base lines + FLL-jump Hilbert refinement r={r} thr={args.threshold}, "
-                         + (f"CK54 FP32 stepping tol={args.tol:g} h_max={args.hmax_cells:g} cell"
-                            if args.stepper == "ck54" else "explicit Euler FP32 stepping, fixed step 1/5 cell")
-                         + ", FP64 landing and Q"),
+            "workload": wl + ", " + st.text() + " (fixed-error setting), FP64 landing and Q",
             "lines_per_step": lines,
-            "base_lines": 4 ** m,
-            "grid": [256, 256, 128],
-            "tol": args.tol,
-            "h_max_cells": args.hmax_cells,
-            # 0 selects the library's default: min(levels, 4) for maps
-            "refine_batch": plan.d.refine_batch or max(1, min(r, 4)),
+            "base_lines": (2 ** dims) ** m,
+            "grid": list(w["n"]),
+            "setting": st.describe(),
+            # 0 selects the library's default: 4 levels per round for slices, 1 for volumes
+            "refine_batch": plan.d.refine_batch or (1 if volume else max(1, min(dims * r, 4))),
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_trace (adaptive stepping)",
+            "kernel": "k_trace (" + ("explicit Euler" if st.stepper == "euler" else "adaptive") + " stepping)",
             "achieved": achieved,
-            "peak": VALU_PEAK_TFLOPS,
+            "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": achieved / VALU_PEAK_TFLOPS,
-            "traffic": measured_traffic(),
+            "frac": achieved / FP32_PEAK_TFLOPS,
+            "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "launches": n_step,
-            "avg_launch_ms": ms_step / max(n_step, 1),
-            "algorithmic_flops_per_step": flops / args.steps,
-            "rhs_evals_per_step": evals / args.steps,
+            "avg_launch_ms": ms_trace / max(n_step, 1),
+            "own_flops_per_step": own_flops / args.steps,
+            "traced_flops_per_step": traced_flops / args.steps,
+            "traced_over_kept_attempts": attempts / max(kept_attempts, 1),
             "attempts_per_step": attempts / args.steps,
+            "kept_attempts_per_step": kept_attempts / args.steps,
+            "rhs_evals_per_step": evals / args.steps,
+            "nonpacked_fp32_ceiling": FP32_NONPACKED_TFLOPS,
+            "frac_of_nonpacked_ceiling": achieved / FP32_NONPACKED_TFLOPS,
         },
-        "kernel_ms_per_step": {"step": ms_step / args.steps, "land": ms_land / args.steps,
+        "kernel_ms_per_step": {"step": ms_trace / args.steps, "land": ms_land / args.steps,
                                "assemble": ms_asm / args.steps},
         "launch_shape": tuned,
         "wall_s_timed": wall,
+        "setup_s": t_gen,
     }
-
     if not args.no_accuracy:
-        out["accuracy"] = accuracy(args, field, w, h, hmax)
+        acc = accuracy_of(field, seeds_dev, ref, st, h)
+        out["accuracy"] = dict(acc, reference="FP64 oracle on the same grid data, tol 1e-10",
+                               target_median=TARGET_MEDIAN)
+    if rows:
+        out["fixed_error"] = {
+            "target_median_rel_log10q_err": TARGET_MEDIAN,
+            "chosen": {f"{k[0]}_{k[1]}": (None if v is None else v[0]) for k, v in chosen.items()},
+            "sweep": rows,
+        }
+    if volume and not args.no_accuracy:
+        plan16 = QMapPlan(spec, cap, dev)
+        plan16.d.refine_batch = plan.d.refine_batch
+        ms16 = time_map(plan16, bf16, opts)
+        r16 = plan16.result()
+        acc16 = accuracy_of(bf16, seeds_dev, ref, st, h)
+        out["bf16_storage"] = {"ms": ms16, "lines_per_s": r16["count"] / (ms16 / 1e3), "lines": r16["count"],
+                               "accuracy": acc16}
+        del plan16
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args, w, h)
+        out["cpu_baseline"] = cpu_baseline_map(args, fo, st, h, volume)
     print(json.dumps(out), flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trace_traffic.json")
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "cores_allowed": allowed, "cpu_model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def host_threads():
+    """Threads for the oracle: the host cores this process may use, or the
+    box's CPU share where OMP_NUM_THREADS states it."""
+    info = host_info()
+    omp = int(info["omp_num_threads"] or 0)
+    return min(omp, info["cores_allowed"]) if omp > 0 else info["cores_allowed"]
+
+
+def cpu_baseline_map(args, fo, st, h, volume):
+    """The oracle (FP64 C + numpy refinement) at the same setting, field,
+    refinement rule and threshold on a bounded sample: a 2^l base lattice
+    (l = 5 for the volume, 8 for the map) with its refinement, on all the
+    host cores this process may use, and on one core."""
+    import oracle
+    level = args.cpu_level if args.cpu_level is not None else (5 if volume else 8)
+    region = (oracle.VolumeBox(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0) if volume
+              else oracle.SlicePlane(0.0, -1.0, 1.0, -1.0, 1.0))
+    kw = st.oracle_kw(h)
+
+    def run(threads):
+        def fn(p):
+            t = oracle.trace(fo, p, nthreads=threads, **kw)
+            return {"fll": t["fll"], "q": t["q_perp"]}
+        t0 = time.perf_counter()
+        keys, _, _ = oracle.refine_slice(region, level, args.refine_levels, args.threshold, fn)
+        return keys.size, time.perf_counter() - t0
+
+    threads = host_threads()
+    n_all, dt_all = run(threads)
+    n_one, dt_one = run(1)
+    shape = f"{1 << level}^{3 if volume else 2}"
+    return dict({"value": n_all / dt_all, "unit": "lines/s", "cores": threads, "kind": "oracle",
+                 "sample": (f"same field, setting and refinement rule on a {shape} base lattice "
+                            f"({n_all} lines, {dt_all:.1f} s on {threads} threads; {dt_one:.1f} s on 1)"),
+                 "one_core": n_one / dt_one}, **host_info())
+
+
+def traffic_file(name):
+    return os.path.join(ROOT, "profiles", f"k_trace_traffic_{name}.json")
+
+
 KERNEL_SOURCES = ("paper_1609_00724_amd/csrc/trace.hip", "paper_1609_00724_amd/csrc/qsq_internal.h")
 
 
@@ -237,7 +504,7 @@ def _pmc_rows(d, counter):
             if r["Counter_Name"] == counter]
 
 
-def summarize_pmc(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
+def summarize_pmc(name, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
     """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by what they read for a
     plain 1 GiB copy and store the stepping kernel's bytes per launch, keyed by
     the hash of its sources (the benchmark reports null once they change)."""
@@ -260,16 +527,17 @@ def summarize_pmc(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
            "fetch_scale": fscale, "write_scale": wscale,
            "copy_fetch_kib": sum(cf) / len(cf), "copy_write_kib": sum(cw) / len(cw)}
     out["bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
-    with open(TRAFFIC_FILE, "w") as fh:
+    with open(traffic_file(name), "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
 
 
-def measured_traffic():
-    """HBM bytes per stepping-kernel launch from the committed counter summary,
-    or None if the kernel's sources changed since the counters were taken."""
+def measured_traffic(name):
+    """HBM bytes per stepping-kernel launch from the committed counter summary
+    of workload `name`, or None if the kernel's sources changed since the
+    counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(name)) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -315,8 +583,9 @@ def bench_batch(args):
     total = sum(int(s.shape[0]) for s in seeds)
     sets = list(zip(fields, seeds))
     # h_init, h_max: 0.1 and 1 cell of each field's own grid
-    opts32 = make_opts(args.tol, args.tol, step_dtype="f32")
-    opts64 = make_opts(args.tol, args.tol, step_dtype="f64")
+    tol = args.tol or 1e-4
+    opts32 = make_opts(tol, tol, step_dtype="f32")
+    opts64 = make_opts(tol, tol, step_dtype="f64")
     opts32.launch = args.launch
     plan = TraceBatchPlan(sets, opts32, want_work=True)
     tuned = None
@@ -409,18 +678,20 @@ def bench_batch(args):
             "workload": (f"batched trace: {len(fields)} point-charge fields (2-8 charges, grids 64^3 to "
                          f"256x256x128, FP32 storage), 1e4-1e6 random photospheric seeds each, one batched "
                          f"call (one persistent stepping launch) replayed as a HIP graph, CK54 FP32 stepping "
-                         f"tol={args.tol:g}, h_max 1 cell of each grid, FP64 landing and Q"),
+                         f"tol={tol:g}, h_max 1 cell of each grid, FP64 landing and Q"),
             "fields": len(fields),
             "lines_per_step": total,
-            "tol": args.tol,
+            "tol": tol,
         },
         "roofline": {
             "bound": "alu",
             "kernel": "k_trace (batched, adaptive stepping)",
             "achieved": achieved,
-            "peak": VALU_PEAK_TFLOPS,
+            "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": achieved / VALU_PEAK_TFLOPS,
+            "frac": achieved / FP32_PEAK_TFLOPS,
+            "nonpacked_fp32_ceiling": FP32_NONPACKED_TFLOPS,
+            "frac_of_nonpacked_ceiling": achieved / FP32_NONPACKED_TFLOPS,
             "traffic": None,
             "launches": n_step,
             "avg_launch_ms": ms_trace / max(n_step, 1),
@@ -439,185 +710,6 @@ def bench_batch(args):
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_batch(args, host)
     print(json.dumps(out), flush=True)
-
-
-def bench_volume(args):
-    """A refined 3D Q / length / FLEDGE volume of the flux-rope field
-    (384x384x256 nodes): 256^3 base cells, two refinement levels, FP32 storage;
-    the same volume with BF16 node storage beside it, and the storage error
-    against the FP64 oracle on a fixed set of lines."""
-    import numpy as np
-    import torch
-
-    import paper_1609_00724_amd as q
-    import synth
-    from paper_1609_00724_amd import _abi as A
-    from paper_1609_00724_amd.api import Profiler, QMapPlan, VolumeSpec, make_opts
-
-    dev = torch.device("cuda:0")
-    t_gen = time.perf_counter()
-    w = synth.flux_rope_c4(device=dev)
-    b = [torch.from_numpy(c).to(dev) for c in w["b"]]
-    f32 = q.field_init(*b, w["origin"], w["spacing"], storage="f32")
-    bf16 = q.field_init(*b, w["origin"], w["spacing"], storage="bf16")
-    del b
-    torch.cuda.synchronize()
-    t_gen = time.perf_counter() - t_gen
-    h = min(w["spacing"])
-    m, r = args.volume_level, args.refine_levels
-    spec = VolumeSpec(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0, m, r, m, args.threshold, args.refine_batch)
-    plan = QMapPlan(spec, 8 ** m * 4, dev)
-    opts = make_opts(args.tol, args.tol, h_init=0.1 * h, h_max=args.hmax_cells * h, step_dtype="f32")
-    opts.launch = args.launch
-    tuned = None
-    if not args.no_tune:
-        # launch shape timed on the volume itself (one map per candidate)
-        from paper_1609_00724_amd import autotune
-        cands = ([A.launch_word(2, 128, A.GATHER_DIRECT), A.launch_word(2, 128, A.GATHER_CACHED)]
-                 + autotune.candidates(lanes=(1, 2), wgs=(64, 128, 256), gathers=(A.GATHER_REGS,)))
-        batches = (args.refine_batch,) if args.refine_batch > 0 else (1, 2, 3)
-        (word, batch), table = autotune.tune_map(plan, f32, opts, reps=1, cands=cands, batches=batches)
-        opts.launch = word
-        plan.d.refine_batch = batch
-        tuned = dict(autotune.describe(word), refine_batch=batch, ms=table[(word, batch)], candidates=len(table),
-                     worst_ms=max(table.values()))
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        plan.run(f32, opts)
-    torch.cuda.synchronize()
-    plan.work.zero_()
-    with Profiler() as prof:
-        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0.record(stream)
-        for _ in range(args.steps):
-            plan.run(f32, opts)
-        t1.record(stream)
-        torch.cuda.synchronize()
-        ms_step = t0.elapsed_time(t1) / args.steps
-        n_step, ms_trace = prof.read(A.KERNEL_STEP)
-    Profiler.reset()
-    res = plan.result()
-    lines = res["count"]
-    attempts, evals, stepped, landed = (int(v) for v in plan.work.cpu().numpy())
-    flops = FLOP_PER_EVAL * evals + FLOP_PER_ATTEMPT * attempts
-    achieved = flops / (ms_trace / 1e3) / 1e12
-    keys32 = res["keys"].cpu().numpy()
-    q32 = res["q_perp"].cpu().numpy()
-
-    plan16 = QMapPlan(spec, 8 ** m * 4, dev)
-    plan16.d.refine_batch = plan.d.refine_batch
-    plan16.run(bf16, opts)
-    torch.cuda.synchronize()
-    plan16.work.zero_()
-    b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    b0.record(stream)
-    plan16.run(bf16, opts)
-    b1.record(stream)
-    torch.cuda.synchronize()
-    ms16 = b0.elapsed_time(b1)
-    r16 = plan16.result()
-    keys16 = r16["keys"].cpu().numpy()
-    q16 = r16["q_perp"].cpu().numpy()
-    common, i32, i16 = np.intersect1d(keys32, keys16, return_indices=True)
-    ok = np.isfinite(q32[i32]) & np.isfinite(q16[i16]) & (q32[i32] < 1e6)
-    d16 = np.abs(np.log10(q16[i16][ok]) - np.log10(q32[i32][ok])) / np.abs(np.log10(q32[i32][ok]))
-
-    out = {
-        "metric": METRIC,
-        "value": lines / (ms_step / 1e3),
-        "unit": "lines/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": (f"3D Q/FLL/FLEDGE volume, flux rope over a 6-charge background on a 384x384x256 "
-                         f"FP32 grid, {1 << m}^3 base cells + FLL-jump 3D Hilbert refinement r={r} "
-                         f"thr={args.threshold}, CK54 FP32 stepping tol={args.tol:g}, FP64 landing and Q"),
-            "lines_per_step": lines,
-            "base_lines": 8 ** m,
-            "grid": list(w["n"]),
-            # 0 selects the library's default: one level per round for volumes
-            "refine_batch": plan.d.refine_batch or 1,
-        },
-        "roofline": {
-            "bound": "alu",
-            "kernel": "k_trace (adaptive stepping)",
-            "achieved": achieved,
-            "peak": VALU_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / VALU_PEAK_TFLOPS,
-            "traffic": None,
-            "launches": n_step,
-            "avg_launch_ms": ms_trace / max(n_step, 1),
-        },
-        "launch_shape": tuned,
-        "attempts_per_step": attempts / args.steps,
-        "bf16_storage": {"ms": ms16, "lines_per_s": r16["count"] / (ms16 / 1e3), "lines": r16["count"],
-                         "attempts": int(plan16.work.cpu()[0]),
-                         "common_keys": int(common.size),
-                         "median_rel_log10q_diff_vs_fp32_storage": float(np.median(d16)),
-                         "p90": float(np.percentile(d16, 90)), "p99": float(np.percentile(d16, 99))},
-        "setup_s": t_gen,
-    }
-    if not args.no_accuracy:
-        out["accuracy"] = accuracy_volume(args, w, f32, bf16, h)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline_volume(args, w, h)
-    print(json.dumps(out), flush=True)
-
-
-def cpu_baseline_volume(args, w, h):
-    """The oracle on a bounded sample of the volume workload: the same field,
-    tolerance and 3D refinement rule on a 32^3 base lattice."""
-    import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
-    fo = _oracle_field(w)
-    box = oracle.VolumeBox(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0)
-
-    euler = args.stepper == "euler"
-
-    def fn(p):
-        t = oracle.trace(fo, p, rtol=args.tol, atol=args.tol, h_init=0.2 * h if euler else 0.1 * h,
-                         h_max=0.2 * h if euler else args.hmax_cells * h, nthreads=threads, stepper=args.stepper)
-        return {"fll": t["fll"], "q": t["q_perp"]}
-
-    t0 = time.perf_counter()
-    keys, _, _ = oracle.refine_slice(box, 5, args.refine_levels, args.threshold, fn)
-    dt = time.perf_counter() - t0
-    return {"value": keys.size / dt, "unit": "lines/s", "cores": threads, "kind": "oracle",
-            "sample": f"same field, tolerance and 3D refinement rule on a 32^3 base lattice ({keys.size} lines, {dt:.1f} s)"}
-
-
-def accuracy_volume(args, w, f32, bf16, h):
-    """Relative log10 Q error of FP32 and BF16 node storage (bench tolerance)
-    against the FP64 oracle on the FP64 field (tolerance 1e-10), at a fixed
-    seeded set of points in the box."""
-    import numpy as np
-    import torch
-
-    import oracle
-    import paper_1609_00724_amd as q
-    import synth
-    seeds = synth.random_seeds(2025, args.accuracy_lines)
-    o = oracle.trace(_oracle_field(w), seeds, rtol=1e-10, atol=1e-10, h_init=0.1 * h, h_max=h)
-    res = {}
-    for name, fg in (("f32", f32), ("bf16", bf16)):
-        g = q.trace(fg, torch.from_numpy(seeds).cuda(), rtol=args.tol, atol=args.tol, h_init=0.1 * h,
-                    h_max=args.hmax_cells * h, step_dtype="f32")
-        torch.cuda.synchronize()
-        qg = g["q_perp"].cpu().numpy()
-        m = np.isfinite(o["q_perp"]) & np.isfinite(qg) & (o["q_perp"] < 1e6) & (g["status"].cpu().numpy() == o["status"])
-        rel = np.abs(np.log10(qg[m]) - np.log10(o["q_perp"][m])) / np.abs(np.log10(o["q_perp"][m]))
-        res[name] = {"median_rel_log10q_err": float(np.median(rel)), "p90": float(np.percentile(rel, 90)),
-                     "max": float(rel.max()), "lines": int(m.sum())}
-    res["reference"] = "FP64 oracle on the FP64 field, tol 1e-10"
-    return res
 
 
 def bench_learned(args):
@@ -643,7 +735,8 @@ def bench_learned(args):
     n = (128, 128, 64)
     origin, spacing = synth.grid_geometry(n)
     h = min(spacing)
-    opts = make_opts(args.tol, args.tol, h_init=0.1 * h, h_max=h, step_dtype="f32")
+    tol = args.tol or 1e-4
+    opts = make_opts(tol, tol, h_init=0.1 * h, h_max=h, step_dtype="f32")
     coarse = QMapPlan(MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, 0, m, thr), 4 ** m, dev)
     fine = QMapPlan(MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, r, m + r, thr), 4 ** m * 8, dev)
     t_gen = time.perf_counter()
@@ -820,7 +913,8 @@ def cpu_baseline_batch(args, host):
 
     import oracle
     import synth
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    threads = host_threads()
+    tol = args.tol or 1e-4
     g = synth.rng(7)
     lines, dt = 0, 0.0
     for f in host:
@@ -831,69 +925,13 @@ def cpu_baseline_batch(args, host):
         del b
         h = min(f["spacing"])
         t0 = time.perf_counter()
-        oracle.trace(fo, f["seeds"][pick], rtol=args.tol, atol=args.tol, h_init=0.1 * h, h_max=h, nthreads=threads)
+        oracle.trace(fo, f["seeds"][pick], rtol=tol, atol=tol, h_init=0.1 * h, h_max=h, nthreads=threads)
         dt += time.perf_counter() - t0
         lines += pick.size
         del fo
-    return {"value": lines / dt, "unit": "lines/s", "cores": threads, "kind": "oracle",
-            "sample": f"{args.cpu_fraction:g} of each field's seeds ({lines} lines, {dt:.1f} s of tracing)"}
-
-
-def _oracle_field(w):
-    import numpy as np
-    import oracle
-    return oracle.Field.grid(*(c.astype(np.float64) for c in w["b"]), w["origin"], w["spacing"])
-
-
-def accuracy(args, field, w, h, hmax):
-    """Median relative log10 Q error of the GPU (bench settings) against the FP64
-    oracle at tolerance 1e-10, on a fixed seeded set of photospheric lines."""
-    import numpy as np
-    import torch
-
-    import oracle
-    import paper_1609_00724_amd as q
-    import synth
-    seeds = synth.random_seeds(2024, args.accuracy_lines, z=0.0)
-    if args.stepper == "euler":
-        g = q.trace(field, torch.from_numpy(seeds).cuda(), rtol=args.tol, atol=args.tol, step_dtype="f32",
-                    stepper="euler")
-    else:
-        g = q.trace(field, torch.from_numpy(seeds).cuda(), rtol=args.tol, atol=args.tol,
-                    h_init=0.1 * h, h_max=hmax, step_dtype="f32")
-    torch.cuda.synchronize()
-    qg = g["q_perp"].cpu().numpy()
-    o = oracle.trace(_oracle_field(w), seeds, rtol=1e-10, atol=1e-10, h_init=0.1 * h, h_max=h)
-    qo = o["q_perp"]
-    m = np.isfinite(qo) & np.isfinite(qg) & (qo < 1e6) & (g["status"].cpu().numpy() == o["status"])
-    rel = np.abs(np.log10(qg[m]) - np.log10(qo[m])) / np.abs(np.log10(qo[m]))
-    return {"median_rel_log10q_err": float(np.median(rel)), "p90": float(np.percentile(rel, 90)),
-            "p99": float(np.percentile(rel, 99)), "max": float(rel.max()),
-            "lines": int(m.sum()), "reference": "FP64 oracle, tol 1e-10", "target_median": 1e-3}
-
-
-def cpu_baseline(args, w, h):
-    """The oracle (FP64 C + numpy refinement) on the host cores: the same map
-    recipe, by default the whole map (--cpu-level picks a coarser base level
-    if that takes too long)."""
-    import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
-    fo = _oracle_field(w)
-    plane = oracle.SlicePlane(0.0, -1.0, 1.0, -1.0, 1.0)
-
-    euler = args.stepper == "euler"
-
-    def fn(p):
-        t = oracle.trace(fo, p, rtol=args.tol, atol=args.tol, h_init=0.2 * h if euler else 0.1 * h,
-                         h_max=0.2 * h if euler else args.hmax_cells * h, nthreads=threads, stepper=args.stepper)
-        return {"fll": t["fll"], "q": t["q_perp"]}
-
-    t0 = time.perf_counter()
-    keys, _, _ = oracle.refine_slice(plane, args.cpu_level, args.refine_levels, args.threshold, fn)
-    dt = time.perf_counter() - t0
-    return {"value": keys.size / dt, "unit": "lines/s", "cores": threads, "kind": "oracle",
-            "sample": (f"same field, tolerance and refinement rule; {1 << args.cpu_level}^2 base map "
-                       f"({keys.size} lines, {dt:.1f} s)")}
+    return dict({"value": lines / dt, "unit": "lines/s", "cores": threads, "kind": "oracle",
+                 "sample": f"{args.cpu_fraction:g} of each field's seeds ({lines} lines, {dt:.1f} s of tracing)"},
+                **host_info())
 
 
 if __name__ == "__main__":

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define QSQ_ABI_VERSION 2
+#define QSQ_ABI_VERSION 3
 
 /* return codes */
 #define QSQ_OK 0
@@ -334,6 +334,10 @@ typedef struct qsq_map_out {
     float *fll_grid;       /* same for the length (linear gap fill); NULL: skip */
     float *fledge;         /* 2^m squared: Sobel FLEDGE of the base length map; NULL: skip */
     uint64_t *work;        /* as qsq_trace_out.work, summed over every pass; NULL: skip */
+    int32_t *steps;        /* NULL, or capacity entries: step attempts of each kept
+                              sample's line (forward + backward), in sample order;
+                              lines traced and then dropped by the rule count in
+                              `work` only */
 } qsq_map_out;
 
 /* Scratch bytes qsq_qmap needs for a map with `capacity` samples. */

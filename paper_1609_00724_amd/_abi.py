@@ -97,7 +97,7 @@ class MapOut(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("keys", C.c_void_p), ("fll", C.c_void_p),
                 ("q_perp", C.c_void_p), ("status", C.c_void_p), ("count", C.c_void_p),
                 ("overflow", C.c_void_p), ("q_grid", C.c_void_p), ("fll_grid", C.c_void_p),
-                ("fledge", C.c_void_p), ("work", C.c_void_p)]
+                ("fledge", C.c_void_p), ("work", C.c_void_p), ("steps", C.c_void_p)]
 
 
 class QsqError(RuntimeError):

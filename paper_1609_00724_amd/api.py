@@ -298,9 +298,10 @@ class QMapPlan:
     """Preallocated sample arrays, grids and scratch for repeated slice maps
     (MapSpec) or volume maps (VolumeSpec)."""
 
-    def __init__(self, spec: MapSpec, capacity: int, device, grids=True, fledge_map=True):
+    def __init__(self, spec: MapSpec, capacity: int, device, grids=True, fledge_map=True, want_steps=False):
         """Work counters (step attempts, RHS evaluations, half-lines stepped,
-        half-lines landed) accumulate in ``self.work``; zero it to restart."""
+        half-lines landed) accumulate in ``self.work``; zero it to restart.
+        want_steps: also keep the step attempts of each kept sample's line."""
         self.spec = spec
         self.capacity = int(capacity)
         self.d = spec.desc()
@@ -319,6 +320,7 @@ class QMapPlan:
         self.fll_grid = torch.empty(gshape, dtype=torch.float32, device=device) if grids else None
         self.fledge = torch.empty(bshape, dtype=torch.float32, device=device) if fledge_map else None
         self.work = torch.zeros(4, dtype=torch.int64, device=device)
+        self.steps = torch.empty(cap, dtype=torch.int32, device=device) if want_steps else None
         sizer = lib.qsq_vmap_scratch_bytes if self.dims == 3 else lib.qsq_qmap_scratch_bytes
         self.scratch = _bytes_tensor(sizer(C.byref(self.d), cap), device)
         o = A.MapOut()
@@ -327,6 +329,7 @@ class QMapPlan:
         o.count, o.overflow = _p(self.count), _p(self.overflow)
         o.q_grid, o.fll_grid, o.fledge = _p(self.q_grid), _p(self.fll_grid), _p(self.fledge)
         o.work = _p(self.work)
+        o.steps = _p(self.steps)
         self.mout = o
 
     def run(self, field: Field, opts: A.TraceOpts, stream=None):
@@ -339,7 +342,8 @@ class QMapPlan:
         n = int(self.count.item())
         return dict(count=n, overflow=int(self.overflow.item()), keys=self.keys[:n], fll=self.fll[:n],
                     q_perp=self.q_perp[:n], status=self.status[:n], q_grid=self.q_grid,
-                    fll_grid=self.fll_grid, fledge=self.fledge)
+                    fll_grid=self.fll_grid, fledge=self.fledge,
+                    steps=None if self.steps is None else self.steps[:n])
 
 
 def qmap(field: Field, spec, capacity: int, *, rtol, atol, h_init=0.0, h_max=0.0,

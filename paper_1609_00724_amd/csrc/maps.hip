@@ -294,6 +294,7 @@ struct Samples {
     uint64_t *keys;
     double *fll, *q;
     int32_t *status;
+    int32_t *att;      // step attempts of the sample's line (nullable: not kept)
 };
 
 // base lattice: cell q of level m at its centre, key q B^r + B^r/2 (B = 2^DIM)
@@ -559,6 +560,7 @@ __global__ void k_merge(const Round *rdp, Samples a, Samples b, Samples nw, cons
         b.fll[dst] = a.fll[i];
         b.q[dst] = a.q[i];
         b.status[dst] = a.status[i];
+        if (b.att) b.att[dst] = a.att[i];
         if (kcnt[i] > 0 && flag[i] && fpos[i] < ne) {
             const int64_t p = (int64_t)fpos[i] * rd.S;
             const uint32_t mk = kmask[fpos[i]];
@@ -570,6 +572,7 @@ __global__ void k_merge(const Round *rdp, Samples a, Samples b, Samples nw, cons
                     b.fll[dst + 1 + t] = nw.fll[p + j - 1];
                     b.q[dst + 1 + t] = nw.q[p + j - 1];
                     b.status[dst + 1 + t] = nw.status[p + j - 1];
+                    if (b.att) b.att[dst + 1 + t] = nw.att[p + j - 1];
                 }
                 ++t;
             }
@@ -595,6 +598,7 @@ __global__ void k_copy_samples(Samples src, Samples dst, const int64_t *count_in
         dst.fll[i] = src.fll[i];
         dst.q[i] = src.q[i];
         dst.status[i] = src.status[i];
+        if (dst.att) dst.att[i] = src.att[i];
     }
 }
 
@@ -663,8 +667,8 @@ constexpr int kPropWords = kRemWord + 8;
 constexpr int kCountWords = kPropWords + 8;
 
 struct QmapLayout {
-    uint64_t trace, seeds, bkeys, bfll, bq, bst, nkeys, nfll, nq, nst, flag, fpos, kcnt, koff, kmask, bsum, counts,
-        rounds, img, total;
+    uint64_t trace, seeds, bkeys, bfll, bq, bst, batt, nkeys, nfll, nq, nst, natt, flag, fpos, kcnt, koff, kmask,
+        bsum, counts, rounds, img, total;
     int64_t tcap, nblocks;
 };
 
@@ -681,10 +685,12 @@ static QmapLayout layout(int dims, int m, int64_t cap)
     L.bfll = o; o += al((uint64_t)cap * 8);
     L.bq = o; o += al((uint64_t)cap * 8);
     L.bst = o; o += al((uint64_t)cap * 4);
+    L.batt = o; o += al((uint64_t)cap * 4);
     L.nkeys = o; o += al((uint64_t)L.tcap * 8);
     L.nfll = o; o += al((uint64_t)L.tcap * 8);
     L.nq = o; o += al((uint64_t)L.tcap * 8);
     L.nst = o; o += al((uint64_t)L.tcap * 4);
+    L.natt = o; o += al((uint64_t)L.tcap * 4);
     L.flag = o; o += al((uint64_t)cap * 4);
     L.fpos = o; o += al((uint64_t)cap * 4);
     L.kcnt = o; o += al((uint64_t)cap * 4);
@@ -809,6 +815,7 @@ __global__ void k_merge_sorted(Samples a, const int64_t *na_p, Samples nw, const
         b.fll[dst] = src.fll[i];
         b.q[dst] = src.q[i];
         b.status[dst] = src.status[i];
+        if (b.att) b.att[dst] = src.att[i];
     }
 }
 
@@ -849,11 +856,15 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
     double *seeds = reinterpret_cast<double *>(base + Lo.seeds);
     // device scalars (sample counts, per-round scalars, levels left; see kRoundWords)
     int64_t *counts = reinterpret_cast<int64_t *>(base + Lo.counts);
-    Samples A{out->keys, out->fll, out->q_perp, out->status};
+    // per-sample step attempts travel with the samples only if the caller asked
+    const bool att = out->steps != nullptr;
+    Samples A{out->keys, out->fll, out->q_perp, out->status, out->steps};
     Samples Bs{reinterpret_cast<uint64_t *>(base + Lo.bkeys), reinterpret_cast<double *>(base + Lo.bfll),
-               reinterpret_cast<double *>(base + Lo.bq), reinterpret_cast<int32_t *>(base + Lo.bst)};
+               reinterpret_cast<double *>(base + Lo.bq), reinterpret_cast<int32_t *>(base + Lo.bst),
+               att ? reinterpret_cast<int32_t *>(base + Lo.batt) : nullptr};
     Samples N{reinterpret_cast<uint64_t *>(base + Lo.nkeys), reinterpret_cast<double *>(base + Lo.nfll),
-              reinterpret_cast<double *>(base + Lo.nq), reinterpret_cast<int32_t *>(base + Lo.nst)};
+              reinterpret_cast<double *>(base + Lo.nq), reinterpret_cast<int32_t *>(base + Lo.nst),
+              att ? reinterpret_cast<int32_t *>(base + Lo.natt) : nullptr};
     int32_t *flag = reinterpret_cast<int32_t *>(base + Lo.flag);
     int32_t *fpos = reinterpret_cast<int32_t *>(base + Lo.fpos);
     int32_t *kcnt = reinterpret_cast<int32_t *>(base + Lo.kcnt);
@@ -871,6 +882,7 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
     job.seed_stride = Lo.tcap;
     carve_records(base + Lo.trace, Lo.tcap, &job.rec, &job.counter);
     job.out_stride = Lo.tcap;
+    job.steps_sum = 1;
     job.work = reinterpret_cast<unsigned long long *>(out->work);
 
     // base lattice
@@ -881,6 +893,7 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
     job.fll = A.fll;
     job.q_perp = A.q;
     job.status = A.status;
+    job.steps = A.att;
     hipError_t e = launch_trace(job, step_dtype, st);
     if (e != hipSuccess) return e;
     if (out->fledge) {
@@ -925,6 +938,7 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
         job.fll = N.fll;
         job.q_perp = N.q;
         job.status = N.status;
+        job.steps = N.att;
         e = launch_trace(job, step_dtype, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_merge_sorted, dim3(grid_for(cap)), dim3(256), 0, st, cur, &counts[0], N, n_seeds, nxt,
@@ -951,6 +965,7 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
         job.fll = N.fll;
         job.q_perp = N.q;
         job.status = N.status;
+        job.steps = N.att;
         e = launch_trace(job, step_dtype, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_select, dim3(grid_for(cap)), dim3(256), 0, st, rg, &rds[round], cur, cin, flag, fpos,

@@ -99,7 +99,8 @@ struct TraceJob {
     // per-seed outputs (stride out_stride for the fp planes); any may be null
     double *fp_fwd, *fp_bwd, *fll, *q_perp, *q_det, *q_fp;
     int32_t *status;
-    int32_t *steps;           // 2 planes of out_stride
+    int32_t *steps;           // 2 planes of out_stride; with steps_sum one plane
+    int steps_sum;            // 1: steps[i] = forward + backward attempts
     int64_t out_stride;
     unsigned long long *work; // 4 device counters accumulated (nullable)
     // batched traces: nsets > 0, the set table and the set of each global seed

@@ -1499,8 +1499,12 @@ __global__ void __launch_bounds__(256) k_assemble(TraceJob job)
         if (o_fpb)
             for (int k = 0; k < 3; ++k) o_fpb[k * os + li] = yB[k];
         if (o_steps) {
-            o_steps[li] = job.rec.attempts[rF];
-            o_steps[os + li] = job.rec.attempts[rB];
+            if (job.steps_sum) {
+                o_steps[li] = job.rec.attempts[rF] + job.rec.attempts[rB];
+            } else {
+                o_steps[li] = job.rec.attempts[rF];
+                o_steps[os + li] = job.rec.attempts[rB];
+            }
         }
         double qp = NAN, qd = NAN, qf = NAN;
         const bool defF = stF >= QSQ_END_XLO && stF <= QSQ_END_MAX_STEPS;

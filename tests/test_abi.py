@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol(qsq):
 
 def test_version_and_strings(qsq):
     from paper_1609_00724_amd import _abi as A
-    assert qsq.lib.qsq_abi_version() == 2
+    assert qsq.lib.qsq_abi_version() == 3
     for code in range(12):
         assert qsq.lib.qsq_status_string(code) != b"unknown code"
     for code in (A.ERR_INVALID_ARG, A.ERR_UNSUPPORTED, A.ERR_WORKSPACE_TOO_SMALL, A.ERR_HIP, A.ERR_COUNT_OVERFLOW):

@@ -41,18 +41,20 @@ def test_counter_summary_scales_by_the_copy(tmp_path, monkeypatch):
     _csv(tmp_path / "cf", [("__amd_rocclr_copyBuffer", gib_kib / 2)] * 3, "FETCH_SIZE")
     _csv(tmp_path / "cw", [("__amd_rocclr_copyBuffer", gib_kib)] * 3, "WRITE_SIZE")
     out = tmp_path / "traffic.json"
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
-    bench.summarize_pmc(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"), str(tmp_path / "cw"))
+    monkeypatch.setattr(bench, "traffic_file", lambda name: str(out) if name == "volume" else "/nonexistent")
+    bench.summarize_pmc("volume", str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"),
+                        str(tmp_path / "cw"))
     t = json.loads(out.read_text())
     assert t["passes"] == 2 and t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
     assert t["fetch_bytes_per_launch"] == pytest.approx(2000.0 * 1024 * 2.0)
     assert t["write_bytes_per_launch"] == pytest.approx(200.0 * 1024)
     assert t["kernel_sources_sha256"] == bench.kernel_hash()
-    assert bench.measured_traffic() == pytest.approx(t["bytes_per_launch"])
+    assert bench.measured_traffic("volume") == pytest.approx(t["bytes_per_launch"])
+    assert bench.measured_traffic("map") is None         # another workload's counters are not used
     # a summary taken on other kernel sources is not reported
     t["kernel_sources_sha256"] = "0" * 64
     out.write_text(json.dumps(t))
-    assert bench.measured_traffic() is None
+    assert bench.measured_traffic("volume") is None
 
 
 def test_mismatched_counter_runs_are_rejected(tmp_path, monkeypatch):
@@ -61,9 +63,10 @@ def test_mismatched_counter_runs_are_rejected(tmp_path, monkeypatch):
     _csv(tmp_path / "w", [(kt, 1.0)], "WRITE_SIZE")
     _csv(tmp_path / "cf", [("__amd_rocclr_copyBuffer", 1.0)], "FETCH_SIZE")
     _csv(tmp_path / "cw", [("__amd_rocclr_copyBuffer", 1.0)], "WRITE_SIZE")
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "t.json"))
+    monkeypatch.setattr(bench, "traffic_file", lambda name: str(tmp_path / "t.json"))
     with pytest.raises(SystemExit):
-        bench.summarize_pmc(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"), str(tmp_path / "cw"))
+        bench.summarize_pmc("volume", str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"),
+                            str(tmp_path / "cw"))
 
 
 def test_tuner_candidates_and_names():
@@ -80,3 +83,26 @@ def test_tuner_candidates_and_names():
         {"word": 2 | (1 << 4) | (3 << 6), "lanes_per_cu": 512, "workgroup": 64, "gather": "reg-cache"}
     with pytest.raises(ValueError):
         A.launch_word(2, 96, A.GATHER_REGS)
+
+
+def test_fixed_error_settings_and_host_info():
+    """The sweep covers every tolerance x largest-step pair for CK54 and the
+    three Euler step sizes; the host record names the cores and the CPU."""
+    ck = bench.sweep_settings(("ck54", "f32"))
+    assert len(ck) == len(bench.SWEEP_TOLS) * len(bench.SWEEP_HMAX_CELLS)
+    assert {(s.tol, s.hmax_cells) for s in ck} == {(t, c) for t in bench.SWEEP_TOLS for c in bench.SWEEP_HMAX_CELLS}
+    eu = bench.sweep_settings(("euler", "f32"))
+    assert [s.euler_div for s in eu] == list(bench.SWEEP_EULER_DIVS)
+    assert eu[0].oracle_kw(0.5)["h_init"] == pytest.approx(0.1) and eu[0].oracle_kw(0.5)["stepper"] == "euler"
+    info = bench.host_info()
+    assert info["nproc"] >= 1 and info["cores_allowed"] >= 1
+    assert 1 <= bench.host_threads() <= info["cores_allowed"]
+    assert bench.FP32_PEAK_TFLOPS == 157.3
+    assert bench.FP32_NONPACKED_TFLOPS == pytest.approx(78.6432)
+
+
+def test_rel_log10_err_masks():
+    import numpy as np
+    ref = {"q_perp": np.array([10.0, 1e7, np.nan, 100.0]), "status": np.array([1, 1, 1, 2])}
+    e = bench.rel_log10_err(np.array([10.0 ** 1.001, 1e7, 5.0, 100.0]), np.array([1, 1, 1, 3]), ref)
+    assert e.size == 1 and e[0] == pytest.approx(1e-3)

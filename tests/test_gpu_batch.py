@@ -137,7 +137,7 @@ def test_batch_graph_replay():
             for key in r:
                 assert torch.equal(o[key], r[key]), f"replay {rep} set {k} {key}"
         assert torch.equal(plan.work, work_ref), f"replay {rep} work"
-    assert q.lib.qsq_abi_version() == 2
+    assert q.lib.qsq_abi_version() == 3
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16"])

@@ -230,6 +230,56 @@ def test_refine_batches_give_identical_maps(c2, r, tight):
         assert np.array_equal(res["q_grid"], ref["q_grid"], equal_nan=True)
 
 
+@pytest.mark.parametrize("dims", [2, 3])
+def test_kept_sample_steps(oracle_mod, c2, dims):
+    """Per-sample step attempts of a refined map (the method's own work): with
+    one level per round every traced line is kept, so they sum to the traced
+    attempts; with four speculative levels per round the kept samples are the
+    same, carry the same attempts, and sum to less than what was traced; and
+    each equals the attempts of its line re-traced on its own at the sample's
+    position (forward + backward)."""
+    import paper_1609_00724_amd as q
+    from paper_1609_00724_amd.api import MapSpec, QMapPlan, VolumeSpec, make_opts
+    torch, dev = torch_dev()
+    h = c2["h"]
+    m, r, thr = (6, 2, 0.02) if dims == 2 else (4, 2, 0.02)
+    opts = make_opts(TOL, TOL, h_init=0.1 * h, h_max=h, step_dtype="f32")
+    got = {}
+    for batch in (1, 4):
+        spec = (MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, r, m, thr, batch) if dims == 2
+                else VolumeSpec(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0, m, r, m, thr, batch))
+        plan = QMapPlan(spec, (2 ** dims) ** (m + r), dev, want_steps=True)
+        plan.run(c2["fg"], opts)
+        torch.cuda.synchronize()
+        res = plan.result()
+        got[batch] = (res["keys"].cpu().numpy(), res["steps"].cpu().numpy().astype(np.int64),
+                      int(plan.work[0].item()))
+    k1, s1, w1 = got[1]
+    k4, s4, w4 = got[4]
+    print(f"dims {dims}: kept attempts {s1.sum()}, traced at 1 level/round {w1}, at 4 levels/round {w4}")
+    assert np.array_equal(k1, k4) and np.array_equal(s1, s4)
+    assert s1.sum() == w1 and s4.sum() < w4
+    # re-trace a sample of positions alone
+    blk = (2 ** dims) ** r
+    idx = np.arange(0, k1.size, max(1, k1.size // 500))
+    k = k1[idx]
+    base = k % blk == blk // 2
+    pos = np.empty((idx.size, 3))
+    if dims == 2:
+        plane = oracle_mod.SlicePlane(0.0, -1.0, 1.0, -1.0, 1.0)
+        pos[base] = plane.centres(m, *oracle_mod.hilbert2_d2xy(m, k[base] // blk))
+        pos[~base] = oracle_mod.key_positions(plane, m, r, k[~base])
+    else:
+        box = oracle_mod.VolumeBox(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0)
+        pos[base] = box.centres(m, *oracle_mod.hilbert3_d2xyz(m, k[base] // blk))
+        pos[~base] = oracle_mod.key_positions(box, m, r, k[~base])
+    t = q.trace(c2["fg"], torch.from_numpy(pos).to(dev), rtol=TOL, atol=TOL, h_init=0.1 * h, h_max=h,
+                step_dtype="f32", want_steps=True)
+    torch.cuda.synchronize()
+    alone = t["steps"].cpu().numpy().astype(np.int64).sum(0)
+    assert np.array_equal(alone, s1[idx])
+
+
 def test_capacity_overflow_is_flagged(c2):
     m, r = 5, 2
     res = _run_map(c2, m, r, 0.0, m, 4 ** m + 10)

@@ -317,6 +317,11 @@ typedef struct qsq_map_desc {
                               of that pixel as a sample before the FLL-jump rule
                               runs (proposals of a learned or external model);
                               the rule then refines what is left (fallback) */
+    int32_t shift;         /* 0, or the shifted-curve re-pass (Sect. 3.6, last paragraph):
+                              after every pass of the rule along the curve, one pass
+                              along the curve shifted by `shift` finest cells per
+                              axis (0 < shift < 2^(m+r); see qsq_qmap) */
+    int32_t max_cycles;    /* with shift: at most this many cycles (1..48; <= 0: 48) */
 } qsq_map_desc;
 
 /* Results of qsq_qmap (device memory).  Samples are kept in curve order. */
@@ -328,7 +333,9 @@ typedef struct qsq_map_out {
     double *q_perp;        /* Q of eq. (11) per sample */
     int32_t *status;       /* status word per sample */
     int64_t *count;        /* device scalar: samples held (<= capacity) */
-    int32_t *overflow;     /* device scalar: 1 if refinement wanted more than capacity */
+    int32_t *overflow;     /* device scalar: bit 0 set if refinement wanted more than
+                              capacity; bit 1 set if the shifted re-pass was still
+                              inserting samples in its last cycle */
     float *q_grid;         /* 2^out_level squared, row y: max Q per cell, gaps filled
                               by log Q interpolated along the curve; NULL: skip */
     float *fll_grid;       /* same for the length (linear gap fill); NULL: skip */
@@ -361,6 +368,17 @@ uint64_t qsq_qmap_scratch_bytes(const qsq_map_desc *d, int64_t capacity);
  * key of a firing gap always being floor((k1+k2)/2).  Samples beyond
  * `capacity`, or proposed or speculative keys beyond the trace slots
  * (`capacity`), are dropped and set *overflow.
+ * With `shift` > 0 (the shifted-curve re-pass, Sect. 3.6, last paragraph)
+ * refinement runs in cycles: one pass of the rule along the curve (one new key
+ * floor((k1+k2)/2) per firing gap), then one pass along a shifted curve -- each
+ * sample's finest cell moved by `shift` cells along every axis into the square
+ * of side 2^(m+r+1) and ordered by that square's order-(m+r+1) Hilbert index;
+ * successive samples of that order whose indices differ by >= 2 and whose
+ * lengths differ by more than `threshold` add a sample in the cell of index
+ * floor((k1'+k2')/2), moved back by `shift`, if it lies inside the map.
+ * Cycles repeat until one inserts nothing (at most max_cycles; bit 1 of
+ * *overflow if the last one still inserted).  refine_batch is ignored, and
+ * `propose` must be NULL (UNSUPPORTED otherwise).
  * Errors: INVALID_ARG, UNSUPPORTED, WORKSPACE_TOO_SMALL, COUNT_OVERFLOW
  * (capacity > 2^30), HIP.
  */
@@ -377,6 +395,8 @@ typedef struct qsq_volume_desc {
     int32_t refine_batch;  /* as in qsq_map_desc; <= 0: 1 */
     double threshold;      /* FLL jump that triggers a new sample (length units) */
     const uint8_t *propose; /* as in qsq_map_desc, one byte per base cell (8^m) */
+    int32_t shift;         /* as in qsq_map_desc, on the 3D curve */
+    int32_t max_cycles;    /* as in qsq_map_desc */
 } qsq_volume_desc;
 
 /* Scratch bytes qsq_vmap needs for a map with `capacity` samples. */

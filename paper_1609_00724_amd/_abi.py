@@ -83,14 +83,15 @@ class MapDesc(C.Structure):
     _fields_ = [("z0", C.c_double), ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double),
                 ("y1", C.c_double), ("base_level", C.c_int32), ("refine_levels", C.c_int32),
                 ("out_level", C.c_int32), ("refine_batch", C.c_int32), ("threshold", C.c_double),
-                ("propose", C.c_void_p)]
+                ("propose", C.c_void_p), ("shift", C.c_int32), ("max_cycles", C.c_int32)]
 
 
 class VolumeDesc(C.Structure):
     _fields_ = [("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
                 ("z0", C.c_double), ("z1", C.c_double), ("base_level", C.c_int32),
                 ("refine_levels", C.c_int32), ("out_level", C.c_int32), ("refine_batch", C.c_int32),
-                ("threshold", C.c_double), ("propose", C.c_void_p)]
+                ("threshold", C.c_double), ("propose", C.c_void_p), ("shift", C.c_int32),
+                ("max_cycles", C.c_int32)]
 
 
 class MapOut(C.Structure):

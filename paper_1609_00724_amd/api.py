@@ -249,6 +249,8 @@ class MapSpec:
     threshold: float
     refine_batch: int = 0   # refinement levels per device round; 0: all in one round
     propose: Optional[torch.Tensor] = None   # uint8 per base pixel in curve order (device)
+    shift: int = 0          # > 0: shifted-curve re-pass by this many finest cells per axis
+    max_cycles: int = 0     # re-pass cycles at most (0: library default)
 
     def desc(self) -> A.MapDesc:
         d = A.MapDesc()
@@ -257,6 +259,7 @@ class MapSpec:
         d.refine_batch = self.refine_batch
         d.threshold = self.threshold
         d.propose = _proposal_ptr(self.propose, 4 ** self.base_level)
+        d.shift, d.max_cycles = self.shift, self.max_cycles
         return d
 
 
@@ -274,6 +277,8 @@ class VolumeSpec:
     threshold: float
     refine_batch: int = 0
     propose: Optional[torch.Tensor] = None   # uint8 per base cell in curve order (device)
+    shift: int = 0
+    max_cycles: int = 0
 
     def desc(self) -> A.VolumeDesc:
         d = A.VolumeDesc()
@@ -282,6 +287,7 @@ class VolumeSpec:
         d.refine_batch = self.refine_batch
         d.threshold = self.threshold
         d.propose = _proposal_ptr(self.propose, 8 ** self.base_level)
+        d.shift, d.max_cycles = self.shift, self.max_cycles
         return d
 
 

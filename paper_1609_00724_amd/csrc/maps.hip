@@ -664,15 +664,23 @@ constexpr int kMaxRounds = 64;
 constexpr int kRoundWords = 128;
 constexpr int kRemWord = kRoundWords + 4 * kMaxRounds;
 constexpr int kPropWords = kRemWord + 8;
-constexpr int kCountWords = kPropWords + 8;
+// shifted re-pass: per cycle the shifted pass's firing count, the new samples
+// kept and the sort's two scalars
+constexpr int kMaxCycles = 48;
+constexpr int kShiftWords = kPropWords + 8;
+constexpr int kCountWords = kShiftWords + 4 * kMaxCycles;
 
 struct QmapLayout {
     uint64_t trace, seeds, bkeys, bfll, bq, bst, batt, nkeys, nfll, nq, nst, natt, flag, fpos, kcnt, koff, kmask,
-        bsum, counts, rounds, img, total;
+        bsum, counts, rounds, img;
+    // shifted re-pass only: shifted keys and sample indices (and the sort's
+    // second buffers), the new key of each shifted gap, the sort's digit counts
+    // and scan space, the new samples in key order
+    uint64_t skeys, sidx, skeys2, sidx2, nkey, scnt, sscan, gkeys, gfll, gq, gst, gatt, total;
     int64_t tcap, nblocks;
 };
 
-static QmapLayout layout(int dims, int m, int64_t cap)
+static QmapLayout layout(int dims, int m, int64_t cap, bool shifted)
 {
     QmapLayout L{};
     const int64_t nb = (int64_t)1 << (dims * m);
@@ -700,18 +708,33 @@ static QmapLayout layout(int dims, int m, int64_t cap)
     L.counts = o; o += al(kCountWords * 8);
     L.rounds = o; o += al(kMaxRounds * sizeof(Round));
     L.img = o; o += al((uint64_t)nb * 4);
+    if (shifted) {
+        const int64_t sc = sort_count_words(L.tcap);
+        L.skeys = o; o += al((uint64_t)L.tcap * 8);
+        L.sidx = o; o += al((uint64_t)L.tcap * 4);
+        L.skeys2 = o; o += al((uint64_t)L.tcap * 8);
+        L.sidx2 = o; o += al((uint64_t)L.tcap * 4);
+        L.nkey = o; o += al((uint64_t)L.tcap * 8);
+        L.scnt = o; o += al((uint64_t)sc * 4);
+        L.sscan = o; o += al((uint64_t)scan_tmp_words(sc) * 8);
+        L.gkeys = o; o += al((uint64_t)L.tcap * 8);
+        L.gfll = o; o += al((uint64_t)L.tcap * 8);
+        L.gq = o; o += al((uint64_t)L.tcap * 8);
+        L.gst = o; o += al((uint64_t)L.tcap * 4);
+        L.gatt = o; o += al((uint64_t)L.tcap * 4);
+    }
     L.total = o;
     return L;
 }
 
 uint64_t qmap_scratch_bytes(const qsq_map_desc *d, int64_t capacity)
 {
-    return layout(2, d->base_level, capacity).total;
+    return layout(2, d->base_level, capacity, d->shift > 0).total;
 }
 
 uint64_t vmap_scratch_bytes(const qsq_volume_desc *d, int64_t capacity)
 {
-    return layout(3, d->base_level, capacity).total;
+    return layout(3, d->base_level, capacity, d->shift > 0).total;
 }
 
 static void launch_scan(const int32_t *v, const int64_t *count_in, int64_t nblocks, int64_t *bsum, int32_t *off,
@@ -819,6 +842,114 @@ __global__ void k_merge_sorted(Samples a, const int64_t *na_p, Samples nw, const
     }
 }
 
+// ---------------------------------------------------------------------------
+// shifted-curve re-pass (Sect. 3.6, last paragraph)
+// ---------------------------------------------------------------------------
+// Index of every sample on the shifted curve: its finest cell moved by
+// `shift` cells along every axis, indexed on the order L+1 curve of the square
+// (cube) of side 2^(L+1) that holds the moved map; the sample's own index rides
+// along for the sort.
+template <int DIM>
+__global__ void k_shift_keys(Region rg, int shift, Samples a, const int64_t *count_in, uint64_t *skeys,
+                             int32_t *sidx)
+{
+    const int64_t count = *count_in;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t c[3];
+        cell_of_key<DIM>(rg.L, a.keys[i], c);
+        for (int ax = 0; ax < DIM; ++ax) c[ax] += (uint32_t)shift;
+        skeys[i] = key_of_cell<DIM>(rg.L + 1, c);
+        sidx[i] = (int32_t)i;
+    }
+}
+
+// The rule along the shifted order: successive samples j, j+1 whose shifted
+// indices differ by >= 2 and whose lengths differ by more than thr put a new
+// sample in the cell of shifted index floor((k1'+k2')/2), moved back by
+// `shift`, if that cell lies inside the map; flag[j] marks it, nkey[j] holds
+// its key on the map's own curve.
+template <int DIM>
+__global__ void k_shift_fire(Region rg, int shift, Samples a, const int64_t *count_in, const uint64_t *skeys,
+                             const int32_t *sidx, int32_t *flag, uint64_t *nkey)
+{
+    const int64_t count = *count_in;
+    const int64_t side = (int64_t)1 << rg.L;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < count; j += (int64_t)gridDim.x * blockDim.x) {
+        int32_t f = 0;
+        if (j + 1 < count) {
+            const uint64_t k0 = skeys[j], k1 = skeys[j + 1];
+            if (k1 - k0 >= 2 && fabs(a.fll[sidx[j + 1]] - a.fll[sidx[j]]) > rg.thr) {
+                uint32_t c[3];
+                cell_of_key<DIM>(rg.L + 1, k0 + ((k1 - k0) >> 1), c);
+                bool inside = true;
+                for (int ax = 0; ax < DIM; ++ax) {
+                    const int64_t v = (int64_t)c[ax] - shift;
+                    inside = inside && v >= 0 && v < side;
+                    c[ax] = (uint32_t)v;
+                }
+                if (inside) {
+                    nkey[j] = key_of_cell<DIM>(rg.L, c);
+                    f = 1;
+                }
+            }
+        }
+        flag[j] = f;
+    }
+}
+
+// new samples that fit the trace slots (the rest set *overflow)
+__global__ void k_shift_setup(const int64_t *n_new, int64_t slots, int64_t *n_eff, int32_t *overflow)
+{
+    int64_t ne = *n_new;
+    if (ne > slots) {
+        ne = slots;
+        *overflow |= 1;
+    }
+    *n_eff = ne;
+}
+
+// seeds of the new samples, compacted in shifted order; nidx = 0, 1, ... for
+// the sort into key order that follows the trace
+template <int DIM>
+__global__ void k_shift_seeds(Region rg, const int64_t *count_in, const int32_t *flag, const int32_t *fpos,
+                              const uint64_t *nkey, const int64_t *n_eff, int64_t stride, double *seeds,
+                              uint64_t *nkeys, int32_t *nidx)
+{
+    const int64_t count = *count_in, ne = *n_eff;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < count; j += (int64_t)gridDim.x * blockDim.x) {
+        if (!flag[j] || fpos[j] >= ne) continue;
+        const int64_t p = fpos[j];
+        const uint64_t k = nkey[j];
+        uint32_t c[3];
+        cell_of_key<DIM>(rg.L, k, c);
+        nkeys[p] = k;
+        nidx[p] = (int32_t)p;
+        for (int ax = 0; ax < 3; ++ax)
+            seeds[ax * stride + p] = (ax < DIM) ? rg.lo[ax] + ((double)c[ax] + 0.5) * rg.d[ax] : rg.lo[ax];
+    }
+}
+
+// the traced new samples in key order: dst[t] = src[perm[t]] (keys already sorted)
+__global__ void k_gather_samples(Samples src, const int32_t *perm, const uint64_t *sorted_keys, const int64_t *n_p,
+                                 Samples dst)
+{
+    const int64_t n = *n_p;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = perm[t];
+        dst.keys[t] = sorted_keys[t];
+        dst.fll[t] = src.fll[i];
+        dst.q[t] = src.q[i];
+        dst.status[t] = src.status[i];
+        if (dst.att) dst.att[t] = src.att[i];
+    }
+}
+
+// bit 1 of *overflow: the last re-pass cycle still inserted samples
+__global__ void k_cycle_check(const int64_t *count_before, const int64_t *count_after, int32_t *overflow)
+{
+    if (*count_after != *count_before) *overflow |= 2;
+}
+
 // Rounds to enqueue.  If the trace slots hold 2^batch - 1 keys for every
 // possible firing gap (at most one per sample), no round takes fewer than
 // batch levels and ceil(levels / batch) rounds suffice; otherwise a round may
@@ -844,12 +975,12 @@ static int planned_rounds(int levels, int batch, int64_t slots, int64_t first, i
 // FLEDGE of the base lengths, refinement rounds, converter.
 template <int DIM>
 static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &o, int step_dtype, Region rg,
-                             int out_level, int refine_batch, const uint8_t *propose, const qsq_map_out *out,
-                             void *scratch, hipStream_t st)
+                             int out_level, int refine_batch, const uint8_t *propose, int shift, int max_cycles,
+                             const qsq_map_out *out, void *scratch, hipStream_t st)
 {
     const int64_t cap = out->capacity;
     const int m = rg.m, r = rg.r;
-    const QmapLayout Lo = layout(DIM, m, cap);
+    const QmapLayout Lo = layout(DIM, m, cap, shift > 0);
     char *base = static_cast<char *>(scratch);
     const int64_t nb = (int64_t)1 << (DIM * m);
 
@@ -949,7 +1080,79 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
         step = 1;
         batch = 1;
     }
-    const int rounds = planned_rounds(levels, batch, Lo.tcap, step ? cap : nb, cap);
+    if (shift > 0) {
+        // cycles of two passes: the rule along the curve (one new key per
+        // firing gap), then along the shifted curve; a cycle that inserts
+        // nothing leaves the samples as they are, so later cycles do nothing
+        uint64_t *skeys = reinterpret_cast<uint64_t *>(base + Lo.skeys);
+        uint64_t *skeys2 = reinterpret_cast<uint64_t *>(base + Lo.skeys2);
+        uint64_t *nkey = reinterpret_cast<uint64_t *>(base + Lo.nkey);
+        int32_t *sidx = reinterpret_cast<int32_t *>(base + Lo.sidx);
+        int32_t *sidx2 = reinterpret_cast<int32_t *>(base + Lo.sidx2);
+        int32_t *scnt = reinterpret_cast<int32_t *>(base + Lo.scnt);
+        int64_t *sscan = reinterpret_cast<int64_t *>(base + Lo.sscan);
+        Samples G{reinterpret_cast<uint64_t *>(base + Lo.gkeys), reinterpret_cast<double *>(base + Lo.gfll),
+                  reinterpret_cast<double *>(base + Lo.gq), reinterpret_cast<int32_t *>(base + Lo.gst),
+                  att ? reinterpret_cast<int32_t *>(base + Lo.gatt) : nullptr};
+        const int cycles = max_cycles > 0 && max_cycles < kMaxCycles ? max_cycles : kMaxCycles;
+        int slot = 0;
+        for (int cyc = 0; cyc < cycles; ++cyc, slot += 2) {
+            int64_t *cin = &counts[slot], *cmid = &counts[slot + 1], *cout = &counts[slot + 2];
+            int64_t *n_fire = &counts[kRoundWords + 4 * cyc], *n_eff = n_fire + 1, *n_seeds = n_fire + 2,
+                    *n_kept = n_fire + 3;
+            int64_t *sw = &counts[kShiftWords + 4 * cyc];   // new samples, kept of them, sort scalars
+            // the rule along the curve
+            hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, st, rem, (int64_t)1);
+            hipLaunchKernelGGL(k_fire, dim3(grid_for(cap)), dim3(256), 0, st, cur, cin, rg.thr, flag);
+            launch_scan(flag, cin, Lo.nblocks, bsum, fpos, n_fire, st);
+            hipLaunchKernelGGL(k_round_setup, dim3(1), dim3(1), 0, st, n_fire, 1, Lo.tcap, rem, &rds[cyc], n_eff,
+                               n_seeds, out->overflow);
+            hipLaunchKernelGGL((k_spec_seeds<DIM>), dim3(grid_for(cap)), dim3(256), 0, st, rg, &rds[cyc], cur, cin,
+                               flag, fpos, n_eff, Lo.tcap, seeds, N.keys);
+            job.n_dev = n_seeds;
+            job.fll = N.fll;
+            job.q_perp = N.q;
+            job.status = N.status;
+            job.steps = N.att;
+            e = launch_trace(job, step_dtype, st);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_select, dim3(grid_for(cap)), dim3(256), 0, st, rg, &rds[cyc], cur, cin, flag, fpos,
+                               n_eff, N.fll, kcnt, kmask);
+            launch_scan(kcnt, cin, Lo.nblocks, bsum, koff, n_kept, st);
+            hipLaunchKernelGGL(k_merge, dim3(grid_for(cap)), dim3(256), 0, st, &rds[cyc], cur, nxt, N, cin, flag,
+                               fpos, n_eff, kcnt, koff, kmask, cap);
+            hipLaunchKernelGGL(k_round_finish, dim3(1), dim3(1), 0, st, cin, n_kept, cap, cmid, out->overflow);
+            Samples t = cur;
+            cur = nxt;
+            nxt = t;
+            // the rule along the shifted curve
+            hipLaunchKernelGGL((k_shift_keys<DIM>), dim3(grid_for(cap)), dim3(256), 0, st, rg, shift, cur, cmid, skeys,
+                               sidx);
+            launch_sort_pairs64(skeys, sidx, skeys2, sidx2, scnt, sscan, &sw[2], cmid, Lo.tcap, DIM * (rg.L + 1), st);
+            hipLaunchKernelGGL((k_shift_fire<DIM>), dim3(grid_for(cap)), dim3(256), 0, st, rg, shift, cur, cmid, skeys,
+                               sidx, flag, nkey);
+            launch_scan(flag, cmid, Lo.nblocks, bsum, fpos, &sw[0], st);
+            hipLaunchKernelGGL(k_shift_setup, dim3(1), dim3(1), 0, st, &sw[0], Lo.tcap, &sw[1], out->overflow);
+            hipLaunchKernelGGL((k_shift_seeds<DIM>), dim3(grid_for(cap)), dim3(256), 0, st, rg, cmid, flag, fpos, nkey,
+                               &sw[1], Lo.tcap, seeds, N.keys, sidx2);
+            job.n_dev = &sw[1];
+            e = launch_trace(job, step_dtype, st);
+            if (e != hipSuccess) return e;
+            // the new samples in key order (the shifted keys' buffers are free
+            // again and serve as the sort's second buffers), then merged in
+            launch_sort_pairs64(N.keys, sidx2, skeys, sidx, scnt, sscan, &sw[2], &sw[1], Lo.tcap, DIM * rg.L, st);
+            hipLaunchKernelGGL(k_gather_samples, dim3(grid_for(cap)), dim3(256), 0, st, N, sidx2, N.keys, &sw[1], G);
+            hipLaunchKernelGGL(k_merge_sorted, dim3(grid_for(cap)), dim3(256), 0, st, cur, cmid, G, &sw[1], nxt, cap,
+                               cout, out->overflow);
+            t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        if (slot >= 2)
+            hipLaunchKernelGGL(k_cycle_check, dim3(1), dim3(1), 0, st, &counts[slot - 2], &counts[slot], out->overflow);
+        step = slot;
+    }
+    const int rounds = shift > 0 ? 0 : planned_rounds(levels, batch, Lo.tcap, step ? cap : nb, cap);
     int round = 0;
     for (; round < rounds; ++round) {
         int64_t *cin = &counts[step + round], *cout = &counts[step + round + 1];
@@ -1008,7 +1211,8 @@ hipError_t launch_qmap(const qsq_field *f, const Geom &g, const StepOpts &o, int
     rg.d[1] = (d->y1 - d->y0) / nL;
     rg.d[2] = 0.0;
     rg.thr = d->threshold;
-    return launch_map<2>(f, g, o, step_dtype, rg, d->out_level, d->refine_batch, d->propose, out, scratch, st);
+    return launch_map<2>(f, g, o, step_dtype, rg, d->out_level, d->refine_batch, d->propose, d->shift, d->max_cycles,
+                         out, scratch, st);
 }
 
 hipError_t launch_vmap(const qsq_field *f, const Geom &g, const StepOpts &o, int step_dtype,
@@ -1025,7 +1229,8 @@ hipError_t launch_vmap(const qsq_field *f, const Geom &g, const StepOpts &o, int
         rg.d[a] = (hi[a] - lo[a]) / nL;
     }
     rg.thr = d->threshold;
-    return launch_map<3>(f, g, o, step_dtype, rg, d->out_level, d->refine_batch, d->propose, out, scratch, st);
+    return launch_map<3>(f, g, o, step_dtype, rg, d->out_level, d->refine_batch, d->propose, d->shift, d->max_cycles,
+                         out, scratch, st);
 }
 
 }  // namespace qsq

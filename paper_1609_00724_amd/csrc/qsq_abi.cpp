@@ -517,6 +517,17 @@ int qsq_hilbert3_xyz2d(int b, const uint32_t *x, const uint32_t *y, const uint32
     return ok();
 }
 
+// the shifted-curve re-pass options shared by slices and volumes (L = m + r)
+static int check_shift(int32_t shift, int32_t max_cycles, int L, bool propose)
+{
+    if (shift == 0) return QSQ_OK;
+    if (shift < 0 || (int64_t)shift >= ((int64_t)1 << L))
+        return fail(QSQ_ERR_INVALID_ARG, "shift must be 0 or in (0, 2^(base_level + refine_levels))");
+    if (max_cycles > 48) return fail(QSQ_ERR_INVALID_ARG, "max_cycles must be <= 48");
+    if (propose) return fail(QSQ_ERR_UNSUPPORTED, "proposals and the shifted re-pass cannot be combined");
+    return QSQ_OK;
+}
+
 static int check_map(const qsq_map_desc *d)
 {
     if (!d) return fail(QSQ_ERR_INVALID_ARG, "map desc is NULL");
@@ -527,7 +538,7 @@ static int check_map(const qsq_map_desc *d)
     if (!(d->x1 > d->x0) || !(d->y1 > d->y0) || !isfinite(d->z0))
         return fail(QSQ_ERR_INVALID_ARG, "slice extent must satisfy x1 > x0, y1 > y0, finite z0");
     if (!(d->threshold >= 0.0)) return fail(QSQ_ERR_INVALID_ARG, "threshold must be >= 0");
-    return QSQ_OK;
+    return check_shift(d->shift, d->max_cycles, d->base_level + d->refine_levels, d->propose != nullptr);
 }
 
 static int check_volume(const qsq_volume_desc *d)
@@ -542,7 +553,9 @@ static int check_volume(const qsq_volume_desc *d)
     if (!(d->x1 > d->x0) || !(d->y1 > d->y0) || !(d->z1 > d->z0))
         return fail(QSQ_ERR_INVALID_ARG, "volume extent must satisfy x1 > x0, y1 > y0, z1 > z0");
     if (!(d->threshold >= 0.0)) return fail(QSQ_ERR_INVALID_ARG, "threshold must be >= 0");
-    return QSQ_OK;
+    if (d->shift > 0 && d->base_level + d->refine_levels > 20)
+        return fail(QSQ_ERR_UNSUPPORTED, "shifted re-pass needs base_level + refine_levels <= 20 for volumes");
+    return check_shift(d->shift, d->max_cycles, d->base_level + d->refine_levels, d->propose != nullptr);
 }
 
 uint64_t qsq_vmap_scratch_bytes(const qsq_volume_desc *d, int64_t capacity)

@@ -133,6 +133,10 @@ int64_t sort_count_words(int64_t n_max);
 void launch_sort_pairs(uint32_t *keys, int32_t *vals, uint32_t *keys_tmp, int32_t *vals_tmp, int32_t *cnt,
                        int64_t *scan_tmp, int64_t *n_cnt, const int64_t *n_dev, int64_t n_max, int key_bits,
                        hipStream_t st);
+// The same with uint64 keys.
+void launch_sort_pairs64(uint64_t *keys, int32_t *vals, uint64_t *keys_tmp, int32_t *vals_tmp, int32_t *cnt,
+                         int64_t *scan_tmp, int64_t *n_cnt, const int64_t *n_dev, int64_t n_max, int key_bits,
+                         hipStream_t st);
 // Exclusive scan of n int32 values (n from *n_dev, at most n_max) into off and
 // the total into *total; tmp holds scan_tmp_words(n_max) int64 words.
 int64_t scan_tmp_words(int64_t n_max);

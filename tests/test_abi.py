@@ -226,3 +226,27 @@ def test_noalloc_limits(qsq):
     rc = qsq.lib.qsq_trace_noalloc(C.byref(f), None, A.TRACE_NOALLOC_MAX_SEEDS + 1, C.byref(o), None, None)
     assert rc == A.ERR_WORKSPACE_TOO_SMALL
     assert b"noalloc" in qsq.lib.qsq_last_error()
+
+
+def test_shifted_repass_arguments_rejected(qsq):
+    """Shift outside (0, 2^(m+r)), too many cycles, or proposals together
+    with the re-pass are refused before anything is enqueued."""
+    from paper_1609_00724_amd import _abi as A
+    d = A.MapDesc()
+    d.x0, d.x1, d.y0, d.y1 = -1.0, 1.0, -1.0, 1.0
+    d.base_level, d.refine_levels, d.out_level, d.threshold = 4, 2, 4, 0.02
+    # a well-formed descriptor (its node pointer is never dereferenced: the
+    # call fails on the map description first)
+    f = A.FieldDesc()
+    f.grid.n[:] = (8, 8, 8)
+    f.grid.spacing[:] = (1.0, 1.0, 1.0)
+    f.storage, f.mode, f.nodes, f.bytes = A.F32, A.INTERP_PAPER, 256, 8 ** 3 * 16
+    o = A.TraceOpts()
+    for shift, cycles, prop, code in ((-1, 0, None, A.ERR_INVALID_ARG), (64, 0, None, A.ERR_INVALID_ARG),
+                                      (5, 49, None, A.ERR_INVALID_ARG), (5, 0, 1, A.ERR_UNSUPPORTED)):
+        d.shift, d.max_cycles, d.propose = shift, cycles, prop
+        rc = qsq.lib.qsq_qmap(C.byref(f), C.byref(d), C.byref(o), None, None, 0, None)
+        assert rc == code, (shift, cycles, rc, qsq.lib.qsq_last_error())
+        assert any(w in qsq.lib.qsq_last_error() for w in (b"shift", b"proposals", b"max_cycles"))
+    d.shift, d.max_cycles, d.propose = 5, 0, None
+    assert qsq.lib.qsq_qmap_scratch_bytes(C.byref(d), 4 ** 6) > 0

@@ -280,6 +280,91 @@ def test_kept_sample_steps(oracle_mod, c2, dims):
     assert np.array_equal(alone, s1[idx])
 
 
+def _keys_of_points(O, region, L, pts):
+    """Finest-level curve keys of sample positions (cell centres)."""
+    if region.dims == 2:
+        ext = [(region.x0, region.x1), (region.y0, region.y1)]
+        cols = [pts[:, 0], pts[:, 1]]
+    else:
+        ext = [(region.lo[a], region.hi[a]) for a in range(3)]
+        cols = [pts[:, a] for a in range(3)]
+    n = 1 << L
+    cells = [np.floor((c - lo) / (hi - lo) * n).astype(np.int64) for c, (lo, hi) in zip(cols, ext)]
+    return O._curve_index(region, L, cells)
+
+
+@pytest.mark.parametrize("dims,shift", [(2, 6), (2, 37), (3, 3)])
+def test_shifted_repass_vs_oracle(oracle_mod, c2, dims, shift):
+    """The shifted-curve re-pass (Sect. 3.6, last paragraph) on the device,
+    FP64 stepping: (1) the oracle's refine_shifted replayed on the GPU's own
+    sample values (its sample function looks each requested key up among the
+    GPU's samples) asks for exactly the GPU's keys and ends with the same set,
+    so every decision of both passes in every cycle matches the rule; (2) each
+    sample's length and Q match the oracle traced at its position; (3) the
+    re-pass adds samples the plain rule does not; (4) the set is complete in
+    both orders (no gap left that either pass would fire)."""
+    import paper_1609_00724_amd as q
+    from paper_1609_00724_amd.api import MapSpec, QMapPlan, VolumeSpec, make_opts
+    O = oracle_mod
+    torch, dev = torch_dev()
+    h = c2["h"]
+    m, r, thr = (6, 2, 0.02) if dims == 2 else (4, 2, 0.02)
+    L = m + r
+    opts = make_opts(1e-6, 1e-6, h_init=0.1 * h, h_max=h, step_dtype="f64")
+    res = {}
+    for sh in (0, shift):
+        spec = (MapSpec(0.0, -1.0, 1.0, -1.0, 1.0, m, r, m, thr, 1, shift=sh) if dims == 2
+                else VolumeSpec(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0, m, r, m, thr, 1, shift=sh))
+        plan = QMapPlan(spec, (2 ** dims) ** L, dev)
+        plan.run(c2["fg"], opts)
+        torch.cuda.synchronize()
+        out = plan.result()
+        res[sh] = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items()}
+    g = res[shift]
+    n = g["count"]
+    assert g["overflow"] == 0, g["overflow"]
+    keys = g["keys"][:n]
+    assert np.all(np.diff(keys) > 0)
+    region = (O.SlicePlane(0.0, -1.0, 1.0, -1.0, 1.0) if dims == 2 else O.VolumeBox(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0))
+    lookup = {int(k): i for i, k in enumerate(keys)}
+    missing = []
+    calls = []
+
+    def from_gpu(pts):
+        # the first call is the base lattice (key q B^r + B^r / 2 at the centre
+        # of base cell q, which is a corner of finest cells); later calls ask
+        # for finest-cell centres
+        ks = O.base_samples(region, m, r)[0] if not calls else _keys_of_points(O, region, L, pts)
+        calls.append(len(ks))
+        idx = np.array([lookup.get(int(k), -1) for k in ks])
+        missing.extend(int(k) for k in ks[idx < 0])
+        idx = np.maximum(idx, 0)
+        return {"fll": g["fll"][:n][idx], "q": g["q_perp"][:n][idx]}
+
+    rk, _, cycles = O.refine_shifted(region, m, r, thr, from_gpu, shift=shift, max_cycles=48)
+    print(f"dims {dims} shift {shift}: {n} samples (plain rule {res[0]['count']}), oracle replay {rk.size} "
+          f"in {cycles} cycles, keys the GPU lacks {len(missing)}")
+    assert not missing
+    assert np.array_equal(rk, keys)
+    assert n > res[0]["count"]
+    # values: the oracle traced at every 8th sample position
+    idx = np.arange(0, n, 8)
+    k = keys[idx]
+    blk = (2 ** dims) ** r
+    base = k % blk == blk // 2          # base samples sit at their base cell's centre
+    pos = np.empty((idx.size, 3))
+    pos[base] = region.centres(m, *region.cells(m, k[base] // blk))
+    pos[~base] = O.key_positions(region, m, r, k[~base])
+    o = O.trace(c2["fo"], pos, rtol=1e-6, atol=1e-6, h_init=0.1 * h, h_max=h)
+    same = g["status"][:n][idx] == o["status"]
+    assert same.mean() > 0.995
+    assert np.all(np.abs(g["fll"][:n][idx][same] - o["fll"][same]) <= 1e-4 * np.maximum(o["fll"][same], 1e-12))
+    # completeness in both orders
+    gap = np.diff(keys) >= 2
+    jump = np.abs(np.diff(g["fll"][:n])) > thr
+    assert not np.any(gap & jump)
+
+
 def test_capacity_overflow_is_flagged(c2):
     m, r = 5, 2
     res = _run_map(c2, m, r, 0.0, m, 4 ** m + 10)

@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch shape")
     ap.add_argument("--launch", type=int, default=0, help="launch-shape word with --no-tune (0: library default)")
+    ap.add_argument("--cell-records", action="store_true",
+                    help="add the field's cell records (8 corner records per cell) and let the tuner try them")
     ap.add_argument("--accuracy-lines", type=int, default=2048)
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the accuracy and BF16 legs after the timed region (counter runs)")
@@ -255,6 +257,8 @@ def bench_field_map(args):
     field = q.field_init(*b, w["origin"], w["spacing"], storage="f32")
     bf16 = q.field_init(*b, w["origin"], w["spacing"], storage="bf16") if volume else None
     del b
+    if args.cell_records:
+        field.add_cells()
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
     h = min(w["spacing"])
@@ -301,6 +305,8 @@ def bench_field_map(args):
         if volume:
             cands = ([A.launch_word(2, 128, A.GATHER_DIRECT), A.launch_word(2, 128, A.GATHER_CACHED)]
                      + autotune.candidates(lanes=(1, 2), wgs=(64, 128, 256), gathers=(A.GATHER_REGS,)))
+            if args.cell_records:
+                cands += autotune.candidates(lanes=(1, 2, 4), wgs=(64, 256), gathers=(A.GATHER_CELLS,))
             batches = (args.refine_batch,) if args.refine_batch > 0 else (1, 2, 3)
             (word, batch), table = autotune.tune_map(plan, field, opts, reps=1, cands=cands, batches=batches)
         else:

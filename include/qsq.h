@@ -103,6 +103,11 @@ typedef struct qsq_field {
                               PAPER (Bx/|B|, By/|B|, Bz/|B|, |B|),
                               INTERP_NORMALIZE (Bx, By, Bz, 0); x fastest */
     uint64_t bytes;        /* size of the node records */
+    void *cells;           /* NULL, or device cell records (qsq_field_add_cells): for
+                              each of the (n0-1)(n1-1)(n2-1) cells, x fastest, the
+                              node records of its 8 corners (i+a, j+b, k+c) in the
+                              order a + 2b + 4c, contiguous */
+    uint64_t cell_bytes;   /* size of the cell records (0 without) */
 } qsq_field;
 
 typedef struct qsq_trace_opts {
@@ -136,8 +141,11 @@ typedef struct qsq_trace_opts {
  *          the last cell's corners (FP32 or BF16 records and FP32 stepping,
  *          one field per call, field below 2 GiB; otherwise direct),
  *          3 = per-lane register cache of the last cell's corners (same
- *          conditions as 2; results identical to direct loads bit for bit) */
-#define QSQ_LAUNCH(lanes, wg, gather) (((lanes) & 15) | (((wg) & 3) << 4) | (((gather) & 3) << 6))
+ *          conditions as 2; results identical to direct loads bit for bit),
+ *          4 = direct loads of the cell's corners from the field's cell
+ *          records (FP32 or BF16 storage, FP32 stepping, one field per call,
+ *          field with cell records; otherwise direct; identical results) */
+#define QSQ_LAUNCH(lanes, wg, gather) (((lanes) & 15) | (((wg) & 3) << 4) | (((gather) & 7) << 6))
 
 /* Per-seed results (device arrays of n entries; fp_* are SoA planes 3 x n:
  * x at [0,n), y at [n,2n), z at [2n,3n)).  Any pointer except status may be
@@ -185,6 +193,23 @@ uint64_t qsq_field_bytes(const qsq_grid *g, int storage);
 int qsq_field_init(const qsq_grid *g, const void *bx, const void *by, const void *bz,
                    int in_dtype, int storage, int mode, void *ws, uint64_t ws_bytes,
                    void *stream, qsq_field *out);
+
+/* Bytes of cell records for grid g at the given storage type:
+ * 8 node records per cell, (n0-1)(n1-1)(n2-1) cells. */
+uint64_t qsq_field_cell_bytes(const qsq_grid *g, int storage);
+
+/*
+ * Add cell records to a prepared field (Sect. 3.2: the trilinear stencil of a
+ * cell is its 8 corner nodes): for every cell the records of its 8 corners,
+ * copied from f->nodes into `ws` (device, >= qsq_field_cell_bytes, 256-byte
+ * aligned), so that one evaluation reads one contiguous block (128 bytes for
+ * FP32 records) instead of four pairs of records in four node rows.  The
+ * stepping kernel reads them with launch gather 4; the values, and so every
+ * result, are those of the node records.  Sets f->cells and f->cell_bytes.
+ * Errors: INVALID_ARG (f invalid, ws NULL or misaligned), WORKSPACE_TOO_SMALL,
+ * HIP.
+ */
+int qsq_field_add_cells(qsq_field *f, void *ws, uint64_t ws_bytes, void *stream);
 
 /* ---- tracing (Sect. 3.1-3.5) ------------------------------------------ */
 

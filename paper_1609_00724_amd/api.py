@@ -38,11 +38,22 @@ def _bytes_tensor(nbytes, device):
 
 
 class Field:
-    """A prepared field: node records in a torch-owned device workspace."""
+    """A prepared field: node records (and, if added, cell records) in
+    torch-owned device workspaces."""
 
     def __init__(self, desc: A.FieldDesc, ws: torch.Tensor):
         self.desc = desc
         self.ws = ws
+        self.cells_ws = None
+
+    def add_cells(self, stream=None):
+        """Add cell records (the 8 corner records of every cell, contiguous),
+        read by the stepping kernel's gather 4; returns self."""
+        nbytes = lib.qsq_field_cell_bytes(C.byref(self.desc.grid), self.desc.storage)
+        ws = _bytes_tensor(nbytes, self.ws.device)
+        check(lib.qsq_field_add_cells(C.byref(self.desc), _p(ws), ws.numel() * 8, _stream(stream)))
+        self.cells_ws = ws
+        return self
 
     @property
     def n(self):

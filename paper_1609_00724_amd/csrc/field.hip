@@ -72,6 +72,48 @@ static void go(const void *bx, const void *by, const void *bz, int mode, void *w
                            bx, by, bz, static_cast<S *>(ws), N);
 }
 
+// cell records: the 8 corner records of every cell, corner a + 2b + 4c =
+// node (i+a, j+b, k+c), copied whole (R is one record: 16, 8 or 32 bytes)
+template <typename R>
+__global__ void __launch_bounds__(256) k_cell_records(const R *__restrict__ nodes, int64_t nx, int64_t ny,
+                                                      int64_t ncells, R *__restrict__ cells)
+{
+    const int64_t cx = nx - 1, cy = ny - 1;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 8 * ncells;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e >> 3;
+        const int v = (int)(e & 7);
+        const int64_t i = c % cx, j = (c / cx) % cy, k = c / (cx * cy);
+        const int64_t n = ((k + (v >> 2)) * ny + j + ((v >> 1) & 1)) * nx + i + (v & 1);
+        cells[e] = nodes[n];
+    }
+}
+
+uint64_t cell_record_bytes(const qsq_grid *g, int storage)
+{
+    const uint64_t rec = storage == QSQ_F64 ? 32 : storage == QSQ_F32 ? 16 : 8;
+    return 8 * rec * (uint64_t)(g->n[0] - 1) * (uint64_t)(g->n[1] - 1) * (uint64_t)(g->n[2] - 1);
+}
+
+hipError_t launch_cell_records(const qsq_field *f, void *ws, hipStream_t st)
+{
+    const int64_t nx = f->grid.n[0], ny = f->grid.n[1];
+    const int64_t ncells = (nx - 1) * (ny - 1) * (f->grid.n[2] - 1);
+    const int cus = device_cu_count();
+    const int64_t want = (8 * ncells + 255) / 256;
+    const int blocks = (int)(want < (int64_t)cus * 32 ? want : (int64_t)cus * 32);
+    if (f->storage == QSQ_F32)
+        hipLaunchKernelGGL(k_cell_records<float4>, dim3(blocks), dim3(256), 0, st,
+                           static_cast<const float4 *>(f->nodes), nx, ny, ncells, static_cast<float4 *>(ws));
+    else if (f->storage == QSQ_BF16)
+        hipLaunchKernelGGL(k_cell_records<uint2>, dim3(blocks), dim3(256), 0, st,
+                           static_cast<const uint2 *>(f->nodes), nx, ny, ncells, static_cast<uint2 *>(ws));
+    else
+        hipLaunchKernelGGL(k_cell_records<double4>, dim3(blocks), dim3(256), 0, st,
+                           static_cast<const double4 *>(f->nodes), nx, ny, ncells, static_cast<double4 *>(ws));
+    return hipGetLastError();
+}
+
 hipError_t launch_field_init(const qsq_grid *g, const void *bx, const void *by, const void *bz,
                              int in_dtype, int storage, int mode, void *ws, hipStream_t st)
 {

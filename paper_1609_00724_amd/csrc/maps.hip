@@ -1005,6 +1005,7 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
 
     TraceJob job{};
     job.nodes = f->nodes;
+    job.cells = f->cells;
     job.storage = f->storage;
     job.mode = f->mode;
     job.g = g;

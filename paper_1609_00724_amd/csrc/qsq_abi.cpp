@@ -64,6 +64,8 @@ int check_field(const qsq_field *f)
     if (!f->nodes) return fail(QSQ_ERR_INVALID_ARG, "field nodes is NULL");
     if (f->bytes < qsq_field_bytes(&f->grid, f->storage))
         return fail(QSQ_ERR_INVALID_ARG, "field bytes smaller than the grid needs");
+    if (f->cells && f->cell_bytes < qsq::cell_record_bytes(&f->grid, f->storage))
+        return fail(QSQ_ERR_INVALID_ARG, "field cell_bytes smaller than the grid's cell records");
     return QSQ_OK;
 }
 
@@ -79,8 +81,8 @@ int make_geom_opts(const qsq_field *f, const qsq_trace_opts *o, qsq::Geom *g, qs
     if (!isfinite(o->h_init) || !isfinite(o->h_max) || !isfinite(o->max_length))
         return fail(QSQ_ERR_INVALID_ARG, "h_init, h_max and max_length must be finite");
     if (o->flags & ~QSQ_FLAG_SKIP_OPEN) return fail(QSQ_ERR_INVALID_ARG, "unknown flags 0x%x", o->flags);
-    if ((o->launch & ~0xff) || ((o->launch >> 4) & 3) == 3)
-        return fail(QSQ_ERR_INVALID_ARG, "launch word 0x%x outside QSQ_LAUNCH(0..15, 0..2, 0..3)", o->launch);
+    if ((o->launch & ~0x1ff) || ((o->launch >> 4) & 3) == 3 || ((o->launch >> 6) & 7) > 4)
+        return fail(QSQ_ERR_INVALID_ARG, "launch word 0x%x outside QSQ_LAUNCH(0..15, 0..2, 0..4)", o->launch);
     double hmin_grid = f->grid.spacing[0];
     double extent = 0.0;
     for (int d = 0; d < 3; ++d) {
@@ -256,6 +258,31 @@ int qsq_field_init(const qsq_grid *g, const void *bx, const void *by, const void
     out->mode = mode;
     out->nodes = ws;
     out->bytes = need;
+    out->cells = nullptr;
+    out->cell_bytes = 0;
+    return ok();
+}
+
+uint64_t qsq_field_cell_bytes(const qsq_grid *g, int storage)
+{
+    if (!g || g->n[0] < 2 || g->n[1] < 2 || g->n[2] < 2) return 0;
+    if (storage != QSQ_F64 && storage != QSQ_F32 && storage != QSQ_BF16) return 0;
+    return qsq::cell_record_bytes(g, storage);
+}
+
+int qsq_field_add_cells(qsq_field *f, void *ws, uint64_t ws_bytes, void *stream)
+{
+    int rc = check_field(f);
+    if (rc) return rc;
+    if (!ws || !aligned(ws, 256)) return fail(QSQ_ERR_INVALID_ARG, "cell workspace NULL or not 256-byte aligned");
+    const uint64_t need = qsq_field_cell_bytes(&f->grid, f->storage);
+    if (ws_bytes < need)
+        return fail(QSQ_ERR_WORKSPACE_TOO_SMALL, "cell workspace %llu < %llu bytes", (unsigned long long)ws_bytes,
+                    (unsigned long long)need);
+    hipError_t e = qsq::launch_cell_records(f, ws, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_field_add_cells");
+    f->cells = ws;
+    f->cell_bytes = need;
     return ok();
 }
 
@@ -286,6 +313,7 @@ int qsq_trace(const qsq_field *f, const double *seeds, int64_t n, const qsq_trac
                     (unsigned long long)scratch_bytes, (unsigned long long)need);
     qsq::TraceJob job{};
     job.nodes = f->nodes;
+    job.cells = f->cells;
     job.storage = f->storage;
     job.mode = f->mode;
     job.g = g;

@@ -86,6 +86,7 @@ struct SetDesc {
 
 struct TraceJob {
     const void *nodes;
+    const void *cells;  // cell records (nullable): 8 corner records per cell
     int storage;        // QSQ_F32 / QSQ_F64
     int mode;           // QSQ_INTERP_*
     Geom g;
@@ -154,6 +155,9 @@ hipError_t launch_trace_batch(const TraceJob &job, const SetDesc *host_sets, int
                               hipStream_t stream);
 
 // Field preparation.
+// Cell records (8 corner records per cell) copied from a prepared field's nodes.
+uint64_t cell_record_bytes(const qsq_grid *g, int storage);
+hipError_t launch_cell_records(const qsq_field *f, void *ws, hipStream_t st);
 hipError_t launch_field_init(const qsq_grid *g, const void *bx, const void *by, const void *bz,
                              int in_dtype, int storage, int mode, void *ws, hipStream_t stream);
 

@@ -118,7 +118,9 @@ __device__ __forceinline__ void cell_of(int ib, T q, int n, int &c, T &t)
 // Field value u (Bhat as interpolated) and physical gradient rows
 // G[j][i] = d u_i / d x_j at a point; optionally |B| (PAPER: interpolated node
 // magnitudes; INTERP_NORMALIZE: magnitude of the interpolated B).
-template <typename T, typename S, int MODE, bool MAG>
+// CELLS: `nodes` points at cell records (the 8 corner records of each cell,
+// contiguous, corner a + 2b + 4c) instead of node records; the same values.
+template <typename T, typename S, int MODE, bool MAG, bool CELLS = false>
 __device__ __forceinline__ void field_at(const S *__restrict__ nodes, const Geom &g, const int ib[3],
                                          const T q[3], T u[3], T G[3][3], T &mag)
 {
@@ -126,12 +128,21 @@ __device__ __forceinline__ void field_at(const S *__restrict__ nodes, const Geom
     T t[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) cell_of(ib[d], q[d], g.n[d], c[d], t[d]);
-    const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
-    const int64_t b = (int64_t)c[2] * sz + (int64_t)c[1] * sy + c[0];
-    const auto n000 = ld4(nodes, b), n100 = ld4(nodes, b + 1);
-    const auto n010 = ld4(nodes, b + sy), n110 = ld4(nodes, b + sy + 1);
-    const auto n001 = ld4(nodes, b + sz), n101 = ld4(nodes, b + sz + 1);
-    const auto n011 = ld4(nodes, b + sz + sy), n111 = ld4(nodes, b + sz + sy + 1);
+    int64_t o[8];
+    if constexpr (CELLS) {
+        const int64_t b = 8 * (((int64_t)c[2] * (g.n[1] - 1) + c[1]) * (g.n[0] - 1) + c[0]);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) o[v] = b + v;
+    } else {
+        const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
+        const int64_t b = (int64_t)c[2] * sz + (int64_t)c[1] * sy + c[0];
+        o[0] = b, o[1] = b + 1, o[2] = b + sy, o[3] = b + sy + 1;
+        o[4] = b + sz, o[5] = b + sz + 1, o[6] = b + sz + sy, o[7] = b + sz + sy + 1;
+    }
+    const auto n000 = ld4(nodes, o[0]), n100 = ld4(nodes, o[1]);
+    const auto n010 = ld4(nodes, o[2]), n110 = ld4(nodes, o[3]);
+    const auto n001 = ld4(nodes, o[4]), n101 = ld4(nodes, o[5]);
+    const auto n011 = ld4(nodes, o[6]), n111 = ld4(nodes, o[7]);
     T val[3], dx[3], dy[3], dz[3];
 #define QSQ_COMP(F, k)                                                                              \
     lerp_tree<T>((T)n000.F, (T)n100.F, (T)n010.F, (T)n110.F, (T)n001.F, (T)n101.F, (T)n011.F,       \
@@ -234,13 +245,13 @@ __device__ __forceinline__ T rhs_from(T sigma, const T u[3], const T G[3][3], co
     return jdot(u[0], u[1], u[2], u[0], u[1], u[2]);
 }
 
-template <typename T, typename S, int MODE>
+template <typename T, typename S, int MODE, bool CELLS = false>
 __device__ __forceinline__ T rhs(const S *__restrict__ nodes, const Geom &g, const int ib[3],
                                  const T q[3], T sigma, const T d1[3], const T d2[3], T kx[3],
                                  T k1[3], T k2[3])
 {
     T u[3], G[3][3], mag;
-    field_at<T, S, MODE, false>(nodes, g, ib, q, u, G, mag);
+    field_at<T, S, MODE, false, CELLS>(nodes, g, ib, q, u, G, mag);
     return rhs_from(sigma, u, G, d1, d2, kx, k1, k2);
 }
 
@@ -490,7 +501,7 @@ __device__ __forceinline__ double err_ratio(double a, double b) { return a / b; 
 // gather variants of the stepping kernel: direct corner loads, the LDS cell
 // cache and the register cell cache (the caches: FP32 or BF16 storage, FP32
 // stepping, one field below 2 GiB)
-constexpr int kGatherDirect = 0, kGatherLds = 1, kGatherRegs = 2;
+constexpr int kGatherDirect = 0, kGatherLds = 1, kGatherRegs = 2, kGatherCells = 3;
 
 // one RHS evaluation of the stepping kernel
 template <typename T, typename S, int MODE, int GATHER>
@@ -504,7 +515,7 @@ __device__ __forceinline__ T rhs_step(const S *__restrict__ nodes, __amdgpu_buff
     else if constexpr (GATHER == kGatherRegs)
         return rhs_regs<T, S, MODE>(rsrc, bytes, g, ib, q, sigma, d1, d2, kx, k1, k2, cell, br);
     else
-        return rhs<T, S, MODE>(nodes, g, ib, q, sigma, d1, d2, kx, k1, k2);
+        return rhs<T, S, MODE, GATHER == kGatherCells>(nodes, g, ib, q, sigma, d1, d2, kx, k1, k2);
 }
 
 // FP64 evaluation at a physical point (landing, assembly, seed frame)
@@ -736,10 +747,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EULER 
 {
     static_assert(GATHER == kGatherDirect || (!BATCH && sizeof(T) == 4),
                   "cell caches: one field per launch, FP32 corner values");
-    constexpr bool CACHED = GATHER != kGatherDirect;
+    constexpr bool CACHED = GATHER == kGatherLds || GATHER == kGatherRegs;
     // field and step limits of the lane's line: launch constants for one
-    // field, reloaded from the set table at each refill in a batch
-    const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
+    // field, reloaded from the set table at each refill in a batch (the cell
+    // records' variant reads them in place of the node records)
+    const S *__restrict__ nodes = static_cast<const S *>(GATHER == kGatherCells ? job.cells : job.nodes);
     Geom gl = job.g;
     const Geom &g = gl;
     const StepOpts &o = job.o;
@@ -1693,7 +1705,7 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
     // resident, so that every workgroup of the persistent launch runs from the
     // start (the first item of each lane is its global index)
     const int lanes = (job.o.launch & 15) ? (job.o.launch & 15) : 8;
-    const int wg_code = (job.o.launch >> 4) & 3, gather = (job.o.launch >> 6) & 3;
+    const int wg_code = (job.o.launch >> 4) & 3, gather = (job.o.launch >> 6) & 7;
     const int wg = wg_code == 1 ? 64 : wg_code == 2 ? 128 : 256;
     const void *kern;
     size_t lds = 0;
@@ -1702,7 +1714,9 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
         // the cell caches address the node records with 32-bit byte offsets
         const uint64_t field_bytes = (uint64_t)node_bytes<S>() * job.g.n[0] * job.g.n[1] * job.g.n[2];
         const bool fits = field_bytes < ((uint64_t)1 << 31) - ((uint64_t)1 << 26);
-        if ((gather == 3 || gather == 0) && fits) {
+        if (gather == 4 && job.cells) {
+            kern = trace_kernel<T, S, MODE, kGatherCells, false>(euler);
+        } else if ((gather == 3 || gather == 0) && fits) {
             kern = trace_kernel<T, S, MODE, kGatherRegs, false>(euler);
         } else if (gather == 2 && fits) {
             kern = trace_kernel<T, S, MODE, kGatherLds, false>(euler);

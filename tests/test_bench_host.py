@@ -76,7 +76,7 @@ def test_tuner_candidates_and_names():
     assert len(words) == len(set(words))
     for w in words:
         d = autotune.describe(w)
-        assert d["gather"] in ("direct", "lds-cache", "reg-cache")
+        assert d["gather"] in ("direct", "lds-cache", "reg-cache", "cell-records")
         if d["gather"] != "direct":              # at most 512 resident lanes per CU
             assert d["lanes_per_cu"] <= 512
     assert autotune.describe(A.launch_word(2, 64, A.GATHER_REGS)) == \

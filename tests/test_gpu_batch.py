@@ -160,13 +160,21 @@ def test_launch_shapes_give_identical_results(storage):
     seeds = torch.from_numpy(synth.random_seeds(77, 5000)).to(dev).t().contiguous()
     plan = TracePlan(seeds.shape[1], dev, want_steps=True)
     res = {}
-    for lanes, wg, gather in [(0, 256, 1), (2, 64, 1), (3, 128, 1), (12, 256, 1), (0, 256, 2), (2, 64, 2), (6, 128, 2),
-                              (0, 256, 3), (2, 128, 3), (1, 64, 3)]:
+    # gather 4 before the cell records exist runs the direct loads
+    shapes = [(0, 256, 4), (0, 256, 1), (2, 64, 1), (3, 128, 1), (12, 256, 1), (0, 256, 2), (2, 64, 2), (6, 128, 2),
+              (0, 256, 3), (2, 128, 3), (1, 64, 3), "cells", (1, 256, 4), (2, 64, 4), (6, 128, 4)]
+    for shape in shapes:
+        if shape == "cells":
+            fg.add_cells()
+            continue
+        lanes, wg, gather = shape
+        key = (lanes, wg, gather, fg.cells_ws is not None)
         opts = make_opts(1e-5, 1e-5, step_dtype="f32", launch=A.launch_word(lanes, wg, gather))
         out = plan.run(fg, seeds, opts)
         torch.cuda.synchronize()
-        res[(lanes, wg, gather)] = {k: v.clone() for k, v in out.items()}
-    group = {1: 1, 2: 2, 3: 1}        # direct loads and the register cache: one group
+        res[key] = {k: v.clone() for k, v in out.items()}
+    # direct loads, the register cache and the cell records: one group
+    group = {1: 1, 2: 2, 3: 1, 4: 1}
     for g in (1, 2):
         ref = next(v for k, v in res.items() if group[k[2]] == g)
         for k, v in res.items():
@@ -174,7 +182,8 @@ def test_launch_shapes_give_identical_results(storage):
                 continue
             for key in ref:
                 assert torch.equal(torch.nan_to_num(v[key], nan=-1.0), torch.nan_to_num(ref[key], nan=-1.0)), (k, key)
-    a, b = res[(0, 256, 1)], res[(0, 256, 2)]
+    assert sum(1 for k in res if k[2] == 4 and k[3]) == 3
+    a, b = res[(0, 256, 1, False)], res[(0, 256, 2, False)]
     same = (a["status"] == b["status"]).float().mean().item()
     close = ((a["fll"] - b["fll"]).abs() <= 1e-4 * b["fll"].abs().clamp(min=1e-12)).float().mean().item()
     print(f"direct vs cached gathers: status agreement {same:.4f}, lengths within 1e-4: {close:.4f}")

@@ -365,6 +365,34 @@ def test_shifted_repass_vs_oracle(oracle_mod, c2, dims, shift):
     assert not np.any(gap & jump)
 
 
+def test_volume_map_cell_records_identical(c2):
+    """A refined volume map stepped with the cell records (gather 4) equals the
+    map stepped with the register cell cache and with direct loads bit for
+    bit: the same corner values reach the same arithmetic."""
+    import paper_1609_00724_amd as q
+    from paper_1609_00724_amd import _abi as A
+    from paper_1609_00724_amd.api import QMapPlan, VolumeSpec, make_opts
+    torch, dev = torch_dev()
+    h = c2["h"]
+    fg = c2["fg"]
+    if fg.cells_ws is None:
+        fg.add_cells()
+    spec = VolumeSpec(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0, 5, 2, 6, 0.02, 1)
+    out = []
+    for gather in (A.GATHER_CELLS, A.GATHER_REGS, A.GATHER_DIRECT):
+        plan = QMapPlan(spec, 8 ** 7, dev, want_steps=True)
+        opts = make_opts(1e-2, 1e-2, h_init=0.1 * h, h_max=4 * h, step_dtype="f32",
+                         launch=A.launch_word(1, 256, gather))
+        plan.run(fg, opts)
+        torch.cuda.synchronize()
+        r = plan.result()
+        out.append({k: v.clone() for k, v in r.items() if hasattr(v, "clone")})
+    for other in out[1:]:
+        for k in out[0]:
+            assert torch.equal(torch.nan_to_num(out[0][k].double(), nan=-1.0),
+                               torch.nan_to_num(other[k].double(), nan=-1.0)), k
+
+
 def test_capacity_overflow_is_flagged(c2):
     m, r = 5, 2
     res = _run_map(c2, m, r, 0.0, m, 4 ** m + 10)

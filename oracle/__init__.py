@@ -55,7 +55,7 @@ class _Desc(C.Structure):
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("bx", C.c_void_p), ("by", C.c_void_p), ("bz", C.c_void_p),
                 ("lin", C.c_double * 12), ("charges", C.c_void_p), ("ncharges", C.c_int64),
-                ("quantize", C.c_int32), ("pad", C.c_int32)]
+                ("quantize", C.c_int32), ("order", C.c_int32)]
 
 
 class _Opts(C.Structure):
@@ -118,10 +118,12 @@ class Field:
             self._h = None
 
     @classmethod
-    def grid(cls, bx, by, bz, origin, spacing, mode=PAPER, store="f64"):
+    def grid(cls, bx, by, bz, origin, spacing, mode=PAPER, store="f64", order=1):
         """``store="f32"`` / ``"bf16"`` rounds the prepared node values (Bhat and
         |B| in PAPER mode, B otherwise) to FP32 / BF16 (via FP32, nearest even),
-        i.e. traces the field such a node store holds."""
+        i.e. traces the field such a node store holds.  ``order`` is the
+        interpolation order (Sect. 3.2): 1 trilinear, 2 triquadratic (Dodgson
+        1997), 3 tricubic (Keys 1981)."""
         bx, by, bz = (np.ascontiguousarray(b, dtype=np.float64) for b in (bx, by, bz))
         nz, ny, nx = bx.shape
         d = _Desc()
@@ -133,6 +135,9 @@ class Field:
         d.hi[:] = [origin[i] + (d.n[i] - 1) * spacing[i] for i in range(3)]
         d.bx, d.by, d.bz = _ptr(bx), _ptr(by), _ptr(bz)
         d.quantize = {"f64": 0, "f32": 1, "bf16": 2}[store]
+        if order not in (1, 2, 3) or (order > 1 and min(d.n) < 4):
+            raise ValueError("order must be 1, 2 or 3 (2 and 3 need >= 4 nodes per axis)")
+        d.order = order
         return cls(d, (bx, by, bz))
 
     @classmethod

@@ -12,6 +12,7 @@
  * with no blocking or fusion:
  *   Sect. 3.1  field-line ODE  d x / d lambda = Bhat(x)                 eq. (1)
  *   Sect. 3.2  trilinear interpolation of the node field                 eq. (3)-(4)
+ *              triquadratic (Dodgson 1997) and tricubic (Keys 1981) stencils  eq. (3)
  *   Sect. 3.3  linearised deviation d dx / d lambda = (dx . grad) Bhat   eq. (5)
  *   Sect. 3.4  adaptive Cash-Karp 5(4) Runge-Kutta stepping
  *   Sect. 3.5  orthonormal initial frame eq. (9), end vectors eq. (10),
@@ -71,7 +72,8 @@ typedef struct {
     int64_t ncharges;
     int32_t quantize;      /* 1: round the prepared node values to FP32, 2: to
                               BF16 (the stored form of an FP32 / BF16 node field) */
-    int32_t pad;
+    int32_t order;         /* interpolation order (Sect. 3.2): 1 trilinear (also 0),
+                              2 triquadratic (Dodgson 1997), 3 tricubic (Keys 1981) */
 } or_field_desc;
 
 typedef struct {
@@ -209,6 +211,119 @@ static void trilinear(const or_field *F, int ncomp, const double x[3],
     }
 }
 
+/* Sect. 3.2: the triquadratic and tricubic kernels f_v of eq. (3) are
+ * products of one-dimensional kernels of the distance d (in grid spacings)
+ * between the point and a stencil node.
+ *   Keys (1981) cubic convolution, a = -1/2, nodes c-1 .. c+2 of the cell c:
+ *     W(d) = 3/2 d^3 - 5/2 d^2 + 1            (the cell's own nodes, d <= 1)
+ *     W(d) = -1/2 d^3 + 5/2 d^2 - 4 d + 2     (the outer nodes, 1 <= d <= 2)
+ *   Dodgson (1997) interpolating quadratic, the node m nearest the point and
+ *   its two neighbours:
+ *     W(d) = 1 - 2 d^2                        (node m, d <= 1/2)
+ *     W(d) = d^2 - 5/2 d + 3/2                (the neighbours, 1/2 <= d <= 3/2)
+ * Each node's piece is the one its place in the stencil gives; d is measured
+ * so that it grows away from the node into the cell, and outside the box the
+ * boundary cell's pieces continue as polynomials (as trilinear interpolation
+ * continues the boundary cell linearly).  A stencil node beyond the grid
+ * takes Keys' boundary value f(-1) = 3 f(0) - 3 f(1) + f(2) (mirrored at the
+ * top end), axis by axis.  The gradient is the kernels' analytic derivative. */
+static double node_value(const or_field *F, int k, const int64_t idx[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        const int64_t n = F->d.n[d];
+        if (idx[d] < 0 || idx[d] > n - 1) {
+            int64_t a[3] = { idx[0], idx[1], idx[2] };
+            const int low = idx[d] < 0;
+            double v = 0.0;
+            const double coef[3] = { 3.0, -3.0, 1.0 };
+            for (int m = 0; m < 3; ++m) {
+                a[d] = low ? m : n - 1 - m;
+                v += coef[m] * node_value(F, k, a);
+            }
+            return v;
+        }
+    }
+    const int64_t nx = F->d.n[0], ny = F->d.n[1];
+    return F->c[k][(idx[2] * ny + idx[1]) * nx + idx[0]];
+}
+
+/* weight and d(weight)/d(position in grid units) of stencil node j (of K)
+ * for the point at fraction t of cell c along one axis; *first = index of
+ * node 0 of the stencil */
+static void kernel_1d(int order, int64_t c, double t, int j, int64_t *first, double *w, double *dw)
+{
+    if (order == 3) {
+        /* node c - 1 + j at signed offset t - (j - 1) from the point */
+        *first = c - 1;
+        const int k = j - 1;
+        const double d = k <= 0 ? t - k : k - t;     /* grows away from the node into the cell */
+        const double sgn = k <= 0 ? 1.0 : -1.0;       /* d d / d t */
+        if (k == 0 || k == 1) {
+            *w = 1.5 * d * d * d - 2.5 * d * d + 1.0;
+            *dw = sgn * (4.5 * d * d - 5.0 * d);
+        } else {
+            *w = -0.5 * d * d * d + 2.5 * d * d - 4.0 * d + 2.0;
+            *dw = sgn * (-1.5 * d * d + 5.0 * d - 4.0);
+        }
+        return;
+    }
+    /* quadratic: centre m = c (t < 1/2) or c + 1, offset u = t - (m - c) */
+    const int up = !(t < 0.5);
+    const double u = up ? t - 1.0 : t;
+    *first = c + up - 1;
+    if (j == 1) {
+        *w = 1.0 - 2.0 * u * u;
+        *dw = -4.0 * u;
+    } else {
+        const double d = j == 0 ? 1.0 + u : 1.0 - u;
+        const double sgn = j == 0 ? 1.0 : -1.0;
+        *w = d * d - 2.5 * d + 1.5;
+        *dw = sgn * (2.0 * d - 2.5);
+    }
+}
+
+/* sum over the 27 or 64 stencil vertices of value * f_v and value * grad f_v */
+static void stencil_interp(const or_field *F, int ncomp, const double x[3], double val[4], double grad[4][3])
+{
+    const int order = F->d.order, K = order + 1;
+    int64_t c[3];
+    double t[3];
+    locate(F, x, c, t);
+    for (int k = 0; k < ncomp; ++k) {
+        val[k] = 0.0;
+        grad[k][0] = grad[k][1] = grad[k][2] = 0.0;
+    }
+    double w[3][4], dw[3][4];
+    int64_t first[3];
+    for (int d = 0; d < 3; ++d)
+        for (int j = 0; j < K; ++j) {
+            kernel_1d(order, c[d], t[d], j, &first[d], &w[d][j], &dw[d][j]);
+            dw[d][j] /= F->d.spacing[d];
+        }
+    for (int a = 0; a < K; ++a)
+        for (int b = 0; b < K; ++b)
+            for (int e = 0; e < K; ++e) {
+                const int64_t idx[3] = { first[0] + a, first[1] + b, first[2] + e };
+                const double f = w[0][a] * w[1][b] * w[2][e];
+                const double df[3] = { dw[0][a] * w[1][b] * w[2][e], w[0][a] * dw[1][b] * w[2][e],
+                                       w[0][a] * w[1][b] * dw[2][e] };
+                for (int k = 0; k < ncomp; ++k) {
+                    const double q = node_value(F, k, idx);
+                    val[k] += f * q;
+                    for (int j = 0; j < 3; ++j) grad[k][j] += df[j] * q;
+                }
+            }
+}
+
+/* the node interpolant of the field's order */
+static void interp(const or_field *F, int ncomp, const double x[3], double val[4], double grad[4][3])
+{
+    if (F->d.order >= 2)
+        stencil_interp(F, ncomp, x, val, grad);
+    else
+        trilinear(F, ncomp, x, val, grad);
+}
+
 /* u = B/|B| and grad u = (I - u u^T) grad B / |B| */
 static void normalise(const double B[3], double G[3][3], double u[3], double J[3][3], double *bmag)
 {
@@ -267,7 +382,7 @@ static void field_eval(const or_field *F, const double x[3], double u[3], double
 {
     if (F->d.kind == OR_PAPER) {
         double val[4], grad[4][3];
-        trilinear(F, 4, x, val, grad);
+        interp(F, 4, x, val, grad);
         for (int i = 0; i < 3; ++i) {
             u[i] = val[i];
             for (int j = 0; j < 3; ++j) J[i][j] = grad[i][j];
@@ -278,7 +393,7 @@ static void field_eval(const or_field *F, const double x[3], double u[3], double
     double B[3], G[3][3];
     if (F->d.kind == OR_INTERP_NORMALIZE) {
         double val[4], grad[4][3];
-        trilinear(F, 3, x, val, grad);
+        interp(F, 3, x, val, grad);
         for (int i = 0; i < 3; ++i) {
             B[i] = val[i];
             for (int j = 0; j < 3; ++j) G[i][j] = grad[i][j];

@@ -41,6 +41,12 @@ METRIC = "field lines traced with Q per sec (1 GPU) + % HBM/L2 roofline at fixed
 #  error norm (54), controller (6)                                     -> 600
 #  per explicit Euler step: the update of 9 components (18)            -> 18
 FLOP_PER_EVAL = 147
+#  per RHS evaluation with the K-node-per-axis stencils (K = 3 triquadratic,
+#  4 tricubic): kernel weights and derivative weights of the 3 axes (45 / 90),
+#  per component the separable sums -- along x 2 K^3 FMA, along y 3 K^2, along
+#  z 4 K -- (186 / 384 FLOP, x 3 components), scalings, J.dx1, J.dx2 and the
+#  sign (48)                                                   -> 651 / 1290
+FLOP_PER_EVAL_ORDER = {"linear": FLOP_PER_EVAL, "quadratic": 651, "cubic": 1290}
 FLOP_PER_ATTEMPT = 600
 FLOP_PER_EULER_STEP = 18
 # Published FP32 vector peak of the MI355X: 256 CUs x 4 SIMD x 16 lanes x
@@ -53,7 +59,7 @@ FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # fixed-error protocol
 TARGET_MEDIAN = 1e-3
 SWEEP_TOLS = (1e-2, 3e-3, 1e-3, 3e-4, 1e-4)
-SWEEP_HMAX_CELLS = (1.0, 2.0, 3.0, 4.0)
+SWEEP_HMAX_CELLS = (1.0, 2.0, 3.0, 4.0, 6.0, 8.0)
 SWEEP_EULER_DIVS = (5, 10, 20)     # Euler step = one grid cell / this
 
 
@@ -83,6 +89,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch shape")
     ap.add_argument("--launch", type=int, default=0, help="launch-shape word with --no-tune (0: library default)")
+    ap.add_argument("--order", choices=("linear", "quadratic", "cubic"), default="linear",
+                    help="map / volume: interpolation kernel (trilinear, Dodgson triquadratic, Keys tricubic)")
     ap.add_argument("--cell-records", action="store_true",
                     help="add the field's cell records (8 corner records per cell) and let the tuner try them")
     ap.add_argument("--accuracy-lines", type=int, default=2048)
@@ -254,8 +262,10 @@ def bench_field_map(args):
         w = synth.charges_c2()
         m = args.base_level
     b = [torch.from_numpy(c).to(dev) for c in w["b"]]
-    field = q.field_init(*b, w["origin"], w["spacing"], storage="f32")
-    bf16 = q.field_init(*b, w["origin"], w["spacing"], storage="bf16") if volume else None
+    field = q.field_init(*b, w["origin"], w["spacing"], storage="f32", order=args.order)
+    # BF16 node records are offered with the trilinear kernel only
+    bf16 = (q.field_init(*b, w["origin"], w["spacing"], storage="bf16")
+            if volume and args.order == "linear" else None)
     del b
     if args.cell_records:
         field.add_cells()
@@ -276,7 +286,8 @@ def bench_field_map(args):
     # reference lines: FP64 oracle at tolerance 1e-10 on the same gridded field
     acc_seeds = (synth.random_seeds(2025, args.accuracy_lines) if volume
                  else synth.random_seeds(2024, args.accuracy_lines, z=0.0))
-    fo = oracle.Field.grid(*(np.asarray(c, np.float64) for c in w["b"]), w["origin"], w["spacing"])
+    order_n = {"linear": 1, "quadratic": 2, "cubic": 3}[args.order]
+    fo = oracle.Field.grid(*(np.asarray(c, np.float64) for c in w["b"]), w["origin"], w["spacing"], order=order_n)
     t_ref = time.perf_counter()
     ref = oracle.trace(fo, acc_seeds, rtol=1e-10, atol=1e-10, h_init=0.1 * h, h_max=h)
     t_ref = time.perf_counter() - t_ref
@@ -342,7 +353,7 @@ def bench_field_map(args):
     attempts, evals, stepped, landed = (int(v) for v in plan.work.cpu().numpy())
     kept_attempts = int(res["steps"].to(torch.int64).sum().item()) * args.steps
     per_attempt = FLOP_PER_EULER_STEP if st.stepper == "euler" else FLOP_PER_ATTEMPT
-    traced_flops = FLOP_PER_EVAL * evals + per_attempt * attempts
+    traced_flops = FLOP_PER_EVAL_ORDER[args.order] * evals + per_attempt * attempts
     # the method's own work: the kept samples' lines (speculative lines the
     # rule drops are traced but are not the method's); evaluations per attempt
     # are taken as equal for kept and dropped lines
@@ -351,12 +362,14 @@ def bench_field_map(args):
     achieved = own_flops / (ms_trace / 1e3) / 1e12 if ms_trace > 0 else 0.0
     traffic = measured_traffic(args.workload)
     grid_txt = "x".join(str(v) for v in w["n"])
+    kernel_txt = {"linear": "", "quadratic": " (triquadratic interpolation)",
+                  "cubic": " (tricubic interpolation)"}[args.order]
     if volume:
         wl = (f"3D Q/FLL/FLEDGE volume, flux rope over a 6-charge background on a {grid_txt} FP32 grid, "
-              f"{1 << m}^3 base cells + FLL-jump 3D Hilbert refinement r={r} thr={thr}")
+              f"{1 << m}^3 base cells + FLL-jump 3D Hilbert refinement r={r} thr={thr}{kernel_txt}")
     else:
         wl = (f"photospheric Q/FLL/FLEDGE map, 4-charge potential field on a {grid_txt} FP32 grid, "
-              f"{1 << m}^2 base lines + FLL-jump Hilbert refinement r={r} thr={thr}")
+              f"{1 << m}^2 base lines + FLL-jump Hilbert refinement r={r} thr={thr}{kernel_txt}")
     out = {
         "metric": METRIC,
         "value": lines / (ms_per_step / 1e3),
@@ -376,6 +389,7 @@ def bench_field_map(args):
             "base_lines": (2 ** dims) ** m,
             "grid": list(w["n"]),
             "setting": st.describe(),
+            "interpolation": args.order,
             # 0 selects the library's default: 4 levels per round for slices, 1 for volumes
             "refine_batch": plan.d.refine_batch or (1 if volume else max(1, min(dims * r, 4))),
         },
@@ -415,7 +429,7 @@ def bench_field_map(args):
             "chosen": {f"{k[0]}_{k[1]}": (None if v is None else v[0]) for k, v in chosen.items()},
             "sweep": rows,
         }
-    if volume and not args.no_accuracy:
+    if bf16 is not None and not args.no_accuracy:
         plan16 = QMapPlan(spec, cap, dev)
         plan16.d.refine_batch = plan.d.refine_batch
         ms16 = time_map(plan16, bf16, opts)

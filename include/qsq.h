@@ -58,6 +58,21 @@ extern "C" {
 #define QSQ_INTERP_PAPER 0
 #define QSQ_INTERP_NORMALIZE 1
 
+/* interpolation order (Sect. 3.2): the kernel f_v of eq. (3) over a stencil of
+ * 8, 27 or 64 nodes around the point's cell.  Per axis: LINEAR, the two nodes
+ * of the cell; QUADRATIC, Dodgson's (1997) interpolating quadratic kernel
+ * (1 - 2d^2 for |d| <= 1/2, d^2 - 5|d|/2 + 3/2 for 1/2 < |d| <= 3/2, d in
+ * spacings) over the node nearest the point and its two neighbours; CUBIC,
+ * Keys' (1981) cubic convolution kernel with a = -1/2 over nodes c-1 .. c+2 of
+ * the cell c.  Gradients are the analytic derivatives of the kernels.  A
+ * stencil node beyond the grid takes Keys' boundary value 3 f(0) - 3 f(1) +
+ * f(2) (mirrored at the top end).  QUADRATIC and CUBIC need >= 4 nodes per
+ * axis and FP32 or FP64 node records, and are not available in batched
+ * traces; the stepping kernel then reads the nodes directly (no cell caches). */
+#define QSQ_ORDER_LINEAR 1
+#define QSQ_ORDER_QUADRATIC 2
+#define QSQ_ORDER_CUBIC 3
+
 /* steppers (Sect. 3.4) */
 #define QSQ_STEPPER_CK54 0   /* adaptive Cash-Karp 5(4) */
 #define QSQ_STEPPER_EULER 1  /* explicit Euler, fixed step h_init */
@@ -108,6 +123,10 @@ typedef struct qsq_field {
                               node records of its 8 corners (i+a, j+b, k+c) in the
                               order a + 2b + 4c, contiguous */
     uint64_t cell_bytes;   /* size of the cell records (0 without) */
+    int32_t order;         /* interpolation order (Sect. 3.2, eq. 3): QSQ_ORDER_*; 0 reads as
+                              trilinear.  qsq_field_init sets trilinear; a caller may
+                              set another order on the descriptor afterwards */
+    int32_t pad;
 } qsq_field;
 
 typedef struct qsq_trace_opts {

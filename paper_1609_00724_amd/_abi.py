@@ -18,6 +18,7 @@ F64, F32, BF16 = 0, 1, 2
 INTERP_PAPER, INTERP_NORMALIZE = 0, 1
 STEPPER_CK54 = 0
 STEPPER_EULER = 1
+ORDER_LINEAR, ORDER_QUADRATIC, ORDER_CUBIC = 1, 2, 3
 FLAG_SKIP_OPEN = 1
 
 END_XLO, END_XHI, END_YLO, END_YHI, END_ZLO, END_ZHI = range(6)
@@ -60,7 +61,8 @@ class Grid(C.Structure):
 
 class FieldDesc(C.Structure):
     _fields_ = [("grid", Grid), ("storage", C.c_int32), ("mode", C.c_int32),
-                ("nodes", C.c_void_p), ("bytes", C.c_uint64), ("cells", C.c_void_p), ("cell_bytes", C.c_uint64)]
+                ("nodes", C.c_void_p), ("bytes", C.c_uint64), ("cells", C.c_void_p), ("cell_bytes", C.c_uint64),
+                ("order", C.c_int32), ("pad", C.c_int32)]
 
 
 class TraceOpts(C.Structure):

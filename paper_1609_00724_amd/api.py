@@ -64,8 +64,12 @@ class Field:
         return tuple(self.desc.grid.spacing)
 
 
-def field_init(bx, by, bz, origin, spacing, storage="f32", mode="paper", stream=None) -> Field:
-    """Prepare node records from B component arrays shaped (nz, ny, nx) on the device."""
+_ORDER = {"linear": A.ORDER_LINEAR, "quadratic": A.ORDER_QUADRATIC, "cubic": A.ORDER_CUBIC}
+
+
+def field_init(bx, by, bz, origin, spacing, storage="f32", mode="paper", stream=None, order="linear") -> Field:
+    """Prepare node records from B component arrays shaped (nz, ny, nx) on the
+    device; `order` picks the interpolation kernel (linear, quadratic, cubic)."""
     if bx.dtype not in (torch.float32, torch.float64):
         raise TypeError("B components must be float32 or float64")
     in_dt = A.F64 if bx.dtype == torch.float64 else A.F32
@@ -80,6 +84,7 @@ def field_init(bx, by, bz, origin, spacing, storage="f32", mode="paper", stream=
     d = A.FieldDesc()
     check(lib.qsq_field_init(C.byref(g), _p(bx), _p(by), _p(bz), in_dt, _DT[storage], _MODE[mode],
                              _p(ws), ws.numel() * 8, _stream(stream), C.byref(d)))
+    d.order = _ORDER[order]
     return Field(d, ws)
 
 

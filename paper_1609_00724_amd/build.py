@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqsq.so")
 
-SOURCES = ["trace.hip", "field.hip", "maps.hip", "cnn.hip", "sort.hip", "qsq_abi.cpp"]
+SOURCES = ["trace.hip", "trace_o2p.hip", "trace_o2n.hip", "trace_o3p.hip", "trace_o3n.hip", "field.hip", "maps.hip",
+           "cnn.hip", "sort.hip", "qsq_abi.cpp"]
 ARCH = os.environ.get("QSQ_OFFLOAD_ARCH", "gfx950")
 
 
@@ -47,7 +48,7 @@ def _compile(src: str) -> str:
 
 
 def build(verbose: bool = False) -> str:
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -1007,7 +1007,7 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
     job.nodes = f->nodes;
     job.cells = f->cells;
     job.storage = f->storage;
-    job.mode = f->mode;
+    job.mode = job_mode(f);
     job.g = g;
     job.o = o;
     job.seeds = seeds;

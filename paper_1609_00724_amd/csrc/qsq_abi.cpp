@@ -66,6 +66,14 @@ int check_field(const qsq_field *f)
         return fail(QSQ_ERR_INVALID_ARG, "field bytes smaller than the grid needs");
     if (f->cells && f->cell_bytes < qsq::cell_record_bytes(&f->grid, f->storage))
         return fail(QSQ_ERR_INVALID_ARG, "field cell_bytes smaller than the grid's cell records");
+    if (f->order < 0 || f->order > QSQ_ORDER_CUBIC) return fail(QSQ_ERR_INVALID_ARG, "field order %d", f->order);
+    if (f->order > QSQ_ORDER_LINEAR) {
+        if (f->storage == QSQ_BF16)
+            return fail(QSQ_ERR_UNSUPPORTED, "interpolation order %d needs FP32 or FP64 node records", f->order);
+        for (int d = 0; d < 3; ++d)
+            if (f->grid.n[d] < 4)
+                return fail(QSQ_ERR_UNSUPPORTED, "interpolation order %d needs >= 4 nodes per axis", f->order);
+    }
     return QSQ_OK;
 }
 
@@ -260,6 +268,8 @@ int qsq_field_init(const qsq_grid *g, const void *bx, const void *by, const void
     out->bytes = need;
     out->cells = nullptr;
     out->cell_bytes = 0;
+    out->order = QSQ_ORDER_LINEAR;
+    out->pad = 0;
     return ok();
 }
 
@@ -315,7 +325,7 @@ int qsq_trace(const qsq_field *f, const double *seeds, int64_t n, const qsq_trac
     job.nodes = f->nodes;
     job.cells = f->cells;
     job.storage = f->storage;
-    job.mode = f->mode;
+    job.mode = qsq::job_mode(f);
     job.g = g;
     job.o = so;
     job.seeds = seeds;
@@ -424,6 +434,7 @@ int qsq_trace_batch(const qsq_trace_set *sets, int32_t nsets, const qsq_trace_op
         const qsq_trace_set &t = sets[k];
         int rc = check_field(&t.field);
         if (rc) return set_fail(rc, k);
+        if (t.field.order > QSQ_ORDER_LINEAR) return set_fail(QSQ_ERR_UNSUPPORTED, k);
         if (t.field.storage != sets[0].field.storage || t.field.mode != sets[0].field.mode)
             return fail(QSQ_ERR_INVALID_ARG, "set %d: storage and mode must match set 0", k);
         qsq::Geom g;
@@ -465,7 +476,7 @@ int qsq_trace_batch(const qsq_trace_set *sets, int32_t nsets, const qsq_trace_op
                     (unsigned long long)scratch_bytes, (unsigned long long)need);
     qsq::TraceJob job{};
     job.storage = sets[0].field.storage;
-    job.mode = sets[0].field.mode;
+    job.mode = qsq::job_mode(&sets[0].field);
     job.nodes = sets[0].field.nodes;
     job.g = table[0].g;
     job.o = so0;   // rtol, atol, max_length, max_steps, flags; per-set limits come from the table

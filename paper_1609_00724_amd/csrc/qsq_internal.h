@@ -146,6 +146,10 @@ void launch_scan_i32(const int32_t *v, const int64_t *n_dev, int64_t n_max, int6
 // Carve records + counter out of a scratch block (256-byte aligned).
 void carve_records(void *scratch, int64_t cap, Records *rec, unsigned long long **counter);
 
+// The same for a higher interpolation order, one field: MODE = job.mode =
+// interpolation mode | (order - 1) << 1, 2..5 (instantiated in trace_o*.hip).
+template <int MODE>
+hipError_t launch_trace_mode(const TraceJob &job, int step_dtype, hipStream_t stream);
 // Enqueue the whole trace (work-counter reset, stepping, FP64 landing, FP64 Q assembly).
 hipError_t launch_trace(const TraceJob &job, int step_dtype, hipStream_t stream);
 // Batched trace: writes the host set table into job.sets (device) with small
@@ -155,6 +159,13 @@ hipError_t launch_trace_batch(const TraceJob &job, const SetDesc *host_sets, int
                               hipStream_t stream);
 
 // Field preparation.
+// Internal mode of a trace job: the field's interpolation mode in bit 0 and
+// its interpolation order - 1 above it.
+inline int job_mode(const qsq_field *f)
+{
+    const int order = f->order > 1 ? f->order : 1;
+    return f->mode | ((order - 1) << 1);
+}
 // Cell records (8 corner records per cell) copied from a prepared field's nodes.
 uint64_t cell_record_bytes(const qsq_grid *g, int storage);
 hipError_t launch_cell_records(const qsq_field *f, void *ws, hipStream_t st);

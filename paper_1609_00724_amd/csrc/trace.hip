@@ -115,44 +115,153 @@ __device__ __forceinline__ void cell_of(int ib, T q, int n, int &c, T &t)
     t = q - (T)(ci - ib);
 }
 
-// Field value u (Bhat as interpolated) and physical gradient rows
-// G[j][i] = d u_i / d x_j at a point; optionally |B| (PAPER: interpolated node
-// magnitudes; INTERP_NORMALIZE: magnitude of the interpolated B).
-// CELLS: `nodes` points at cell records (the 8 corner records of each cell,
-// contiguous, corner a + 2b + 4c) instead of node records; the same values.
-template <typename T, typename S, int MODE, bool MAG, bool CELLS = false>
-__device__ __forceinline__ void field_at(const S *__restrict__ nodes, const Geom &g, const int ib[3],
-                                         const T q[3], T u[3], T G[3][3], T &mag)
+// ---------------------------------------------------------------------------
+// Higher interpolation orders (Sect. 3.2): the 27-vertex triquadratic stencil
+// (Dodgson 1997) and the 64-vertex tricubic stencil (Keys 1981).  The order
+// rides in the MODE template value: bit 0 is the interpolation mode
+// (QSQ_INTERP_*), the bits above hold order - 1.
+// ---------------------------------------------------------------------------
+template <int MODE>
+constexpr int interp_order() { return (MODE >> 1) + 1; }
+template <int MODE>
+constexpr bool normalize_first() { return (MODE & 1) == QSQ_INTERP_PAPER; }
+
+// Per-axis stencil of K = order + 1 nodes starting at node s, with the
+// weights w of the values and dw of the grid-unit derivative.  Cubic (Keys'
+// kernel with a = -1/2): nodes c-1 .. c+2 of the cell c, fraction t.
+// Quadratic (Dodgson's interpolating kernel, 1 - 2d^2 within half a spacing,
+// d^2 - 5|d|/2 + 3/2 out to 3/2 spacings): the node m nearest the point and
+// its two neighbours, offset u = t or t - 1 from m.  A stencil node beyond the
+// grid stands for Keys' extrapolation f(-1) = 3 f(0) - 3 f(1) + f(2) (and the
+// same at the top end); its weight is folded onto those three nodes and the
+// stencil starts at the first node inside.  The last weight is then zero and
+// its node index may lie past the grid (the caller clamps it).
+template <int K, typename T>
+__device__ __forceinline__ void axis_stencil(int c, T t, int n, int &s, T w[K], T dw[K])
 {
-    int c[3];
-    T t[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) cell_of(ib[d], q[d], g.n[d], c[d], t[d]);
-    int64_t o[8];
-    if constexpr (CELLS) {
-        const int64_t b = 8 * (((int64_t)c[2] * (g.n[1] - 1) + c[1]) * (g.n[0] - 1) + c[0]);
-#pragma unroll
-        for (int v = 0; v < 8; ++v) o[v] = b + v;
+    if constexpr (K == 4) {
+        const T t2 = t * t, t3 = t2 * t;
+        w[0] = (T)0.5 * (-t3 + (T)2 * t2 - t);
+        w[1] = (T)0.5 * ((T)3 * t3 - (T)5 * t2 + (T)2);
+        w[2] = (T)0.5 * ((T)-3 * t3 + (T)4 * t2 + t);
+        w[3] = (T)0.5 * (t3 - t2);
+        dw[0] = (T)0.5 * ((T)-3 * t2 + (T)4 * t - (T)1);
+        dw[1] = (T)0.5 * ((T)9 * t2 - (T)10 * t);
+        dw[2] = (T)0.5 * ((T)-9 * t2 + (T)8 * t + (T)1);
+        dw[3] = (T)0.5 * ((T)3 * t2 - (T)2 * t);
+        s = c - 1;
     } else {
-        const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
-        const int64_t b = (int64_t)c[2] * sz + (int64_t)c[1] * sy + c[0];
-        o[0] = b, o[1] = b + 1, o[2] = b + sy, o[3] = b + sy + 1;
-        o[4] = b + sz, o[5] = b + sz + 1, o[6] = b + sz + sy, o[7] = b + sz + sy + 1;
+        const bool low = t < (T)0.5;
+        const T u = low ? t : t - (T)1;
+        w[0] = u * (u - (T)0.5);
+        w[1] = (T)1 - (T)2 * u * u;
+        w[2] = u * (u + (T)0.5);
+        dw[0] = (T)2 * u - (T)0.5;
+        dw[1] = (T)-4 * u;
+        dw[2] = (T)2 * u + (T)0.5;
+        s = low ? c - 1 : c;
     }
-    const auto n000 = ld4(nodes, o[0]), n100 = ld4(nodes, o[1]);
-    const auto n010 = ld4(nodes, o[2]), n110 = ld4(nodes, o[3]);
-    const auto n001 = ld4(nodes, o[4]), n101 = ld4(nodes, o[5]);
-    const auto n011 = ld4(nodes, o[6]), n111 = ld4(nodes, o[7]);
-    T val[3], dx[3], dy[3], dz[3];
-#define QSQ_COMP(F, k)                                                                              \
-    lerp_tree<T>((T)n000.F, (T)n100.F, (T)n010.F, (T)n110.F, (T)n001.F, (T)n101.F, (T)n011.F,       \
-                 (T)n111.F, t[0], t[1], t[2], val[k], dx[k], dy[k], dz[k])
-    QSQ_COMP(x, 0);
-    QSQ_COMP(y, 1);
-    QSQ_COMP(z, 2);
-#undef QSQ_COMP
+    if (s < 0) {
+        // node -1 folded onto nodes 0, 1, 2 (weights 3, -3, 1)
+        const T a = w[0], da = dw[0];
+#pragma unroll
+        for (int k = 0; k < K - 1; ++k) {
+            w[k] = w[k + 1];
+            dw[k] = dw[k + 1];
+        }
+        w[K - 1] = (T)0;
+        dw[K - 1] = (T)0;
+        w[0] += (T)3 * a, w[1] -= (T)3 * a, w[2] += a;
+        dw[0] += (T)3 * da, dw[1] -= (T)3 * da, dw[2] += da;
+        s = 0;
+    } else if (s + K - 1 > n - 1) {
+        // node n folded onto nodes n-1, n-2, n-3 (weights 3, -3, 1); the
+        // stencil then starts at n-3
+        const T a = w[K - 1], da = dw[K - 1];
+        const int shift = s - (n - 3);   // 0 for the cubic, 1 for the quadratic stencil
+        T nw[K], ndw[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            nw[k] = (T)0;
+            ndw[k] = (T)0;
+        }
+#pragma unroll
+        for (int k = 0; k < K - 1; ++k) {
+            nw[k + shift] += w[k];
+            ndw[k + shift] += dw[k];
+        }
+        nw[0] += a, nw[1] -= (T)3 * a, nw[2] += (T)3 * a;
+        ndw[0] += da, ndw[1] -= (T)3 * da, ndw[2] += (T)3 * da;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            w[k] = nw[k];
+            dw[k] = ndw[k];
+        }
+        s = n - 3;
+    }
+}
+
+// Value and grid-unit gradient of the first NC record components by the
+// separable stencil sum: along x per row, then y, then z.
+template <int K, int NC, typename T, typename S>
+__device__ __forceinline__ void stencil_sum(const S *__restrict__ nodes, const Geom &g, const int s[3],
+                                            const T w[3][K], const T dw[3][K], T val[NC], T dx[NC], T dy[NC],
+                                            T dz[NC])
+{
+#pragma unroll
+    for (int k = 0; k < NC; ++k) val[k] = dx[k] = dy[k] = dz[k] = (T)0;
+    const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
+    // rows one at a time (only the K records of a row in flight): unrolling
+    // the z and y loops lets the compiler hoist all K^3 loads and spill
+#pragma unroll 1
+    for (int kz = 0; kz < K; ++kz) {
+        const int iz = s[2] + kz < g.n[2] - 1 ? s[2] + kz : g.n[2] - 1;
+        T ay[NC], axy[NC], ayy[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) ay[k] = axy[k] = ayy[k] = (T)0;
+#pragma unroll 1
+        for (int ky = 0; ky < K; ++ky) {
+            const int iy = s[1] + ky < g.n[1] - 1 ? s[1] + ky : g.n[1] - 1;
+            const int64_t row = (int64_t)iz * sz + (int64_t)iy * sy;
+            T rx[NC], drx[NC];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) rx[k] = drx[k] = (T)0;
+#pragma unroll
+            for (int kx = 0; kx < K; ++kx) {
+                const int ix = s[0] + kx < g.n[0] - 1 ? s[0] + kx : g.n[0] - 1;
+                const auto v = ld4(nodes, row + ix);
+                const T c4[4] = {(T)v.x, (T)v.y, (T)v.z, (T)v.w};
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    rx[k] = fma(w[0][kx], c4[k], rx[k]);
+                    drx[k] = fma(dw[0][kx], c4[k], drx[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                ay[k] = fma(w[1][ky], rx[k], ay[k]);
+                axy[k] = fma(w[1][ky], drx[k], axy[k]);
+                ayy[k] = fma(dw[1][ky], rx[k], ayy[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            val[k] = fma(w[2][kz], ay[k], val[k]);
+            dx[k] = fma(w[2][kz], axy[k], dx[k]);
+            dy[k] = fma(w[2][kz], ayy[k], dy[k]);
+            dz[k] = fma(dw[2][kz], ay[k], dz[k]);
+        }
+    }
+}
+
+// u, the physical gradient rows and |B| from the interpolated components
+// (value and grid-unit derivatives; val[3] = interpolated |B| in PAPER mode)
+template <typename T, int MODE, bool MAG>
+__device__ __forceinline__ void field_finish(const Geom &g, const T val[4], const T dx[4], const T dy[4],
+                                             const T dz[4], T u[3], T G[3][3], T &mag)
+{
     const T ihx = (T)g.ih[0], ihy = (T)g.ih[1], ihz = (T)g.ih[2];
-    if (MODE == QSQ_INTERP_PAPER) {
+    if (normalize_first<MODE>()) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             u[i] = val[i];
@@ -160,9 +269,7 @@ __device__ __forceinline__ void field_at(const S *__restrict__ nodes, const Geom
             G[1][i] = dy[i] * ihy;
             G[2][i] = dz[i] * ihz;
         }
-        if (MAG)
-            mag = lerp_val<T>((T)n000.w, (T)n100.w, (T)n010.w, (T)n110.w, (T)n001.w, (T)n101.w,
-                              (T)n011.w, (T)n111.w, t[0], t[1], t[2]);
+        if (MAG) mag = val[3];
     } else {
         // u = B/|B|, grad u = (I - u u^T) grad B / |B|
         const T bb = val[0] * val[0] + val[1] * val[1] + val[2] * val[2];
@@ -186,6 +293,60 @@ __device__ __forceinline__ void field_at(const S *__restrict__ nodes, const Geom
     }
 }
 
+// Field value u (Bhat as interpolated) and physical gradient rows
+// G[j][i] = d u_i / d x_j at a point; optionally |B| (PAPER: interpolated node
+// magnitudes; INTERP_NORMALIZE: magnitude of the interpolated B).
+// CELLS: `nodes` points at cell records (the 8 corner records of each cell,
+// contiguous, corner a + 2b + 4c) instead of node records; the same values.
+template <typename T, typename S, int MODE, bool MAG, bool CELLS = false>
+__device__ __forceinline__ void field_at(const S *__restrict__ nodes, const Geom &g, const int ib[3],
+                                         const T q[3], T u[3], T G[3][3], T &mag)
+{
+    int c[3];
+    T t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) cell_of(ib[d], q[d], g.n[d], c[d], t[d]);
+    T val[4], dx[4], dy[4], dz[4];
+    if constexpr (interp_order<MODE>() > 1) {
+        constexpr int K = interp_order<MODE>() + 1;
+        int s0[3];
+        T w[3][K], dw[3][K];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) axis_stencil<K, T>(c[d], t[d], g.n[d], s0[d], w[d], dw[d]);
+        // |B| is the 4th component in PAPER mode; INTERP_NORMALIZE takes |interpolated B|
+        constexpr int NC = (MAG && normalize_first<MODE>()) ? 4 : 3;
+        stencil_sum<K, NC, T, S>(nodes, g, s0, w, dw, val, dx, dy, dz);
+        field_finish<T, MODE, MAG>(g, val, dx, dy, dz, u, G, mag);
+        return;
+    }
+    int64_t o[8];
+    if constexpr (CELLS) {
+        const int64_t b = 8 * (((int64_t)c[2] * (g.n[1] - 1) + c[1]) * (g.n[0] - 1) + c[0]);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) o[v] = b + v;
+    } else {
+        const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
+        const int64_t b = (int64_t)c[2] * sz + (int64_t)c[1] * sy + c[0];
+        o[0] = b, o[1] = b + 1, o[2] = b + sy, o[3] = b + sy + 1;
+        o[4] = b + sz, o[5] = b + sz + 1, o[6] = b + sz + sy, o[7] = b + sz + sy + 1;
+    }
+    const auto n000 = ld4(nodes, o[0]), n100 = ld4(nodes, o[1]);
+    const auto n010 = ld4(nodes, o[2]), n110 = ld4(nodes, o[3]);
+    const auto n001 = ld4(nodes, o[4]), n101 = ld4(nodes, o[5]);
+    const auto n011 = ld4(nodes, o[6]), n111 = ld4(nodes, o[7]);
+#define QSQ_COMP(F, k)                                                                              \
+    lerp_tree<T>((T)n000.F, (T)n100.F, (T)n010.F, (T)n110.F, (T)n001.F, (T)n101.F, (T)n011.F,       \
+                 (T)n111.F, t[0], t[1], t[2], val[k], dx[k], dy[k], dz[k])
+    QSQ_COMP(x, 0);
+    QSQ_COMP(y, 1);
+    QSQ_COMP(z, 2);
+#undef QSQ_COMP
+    if (MAG && normalize_first<MODE>())
+        val[3] = lerp_val<T>((T)n000.w, (T)n100.w, (T)n010.w, (T)n110.w, (T)n001.w, (T)n101.w, (T)n011.w,
+                             (T)n111.w, t[0], t[1], t[2]);
+    field_finish<T, MODE, MAG>(g, val, dx, dy, dz, u, G, mag);
+}
+
 // The interpolated direction u alone (no gradient): the same operations as
 // the value part of field_at, so both give the same u bit for bit.
 template <typename T, typename S, int MODE>
@@ -196,21 +357,31 @@ __device__ __forceinline__ void field_u(const S *__restrict__ nodes, const Geom 
     T t[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) cell_of(ib[d], q[d], g.n[d], c[d], t[d]);
-    const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
-    const int64_t b = (int64_t)c[2] * sz + (int64_t)c[1] * sy + c[0];
-    const auto n000 = ld4(nodes, b), n100 = ld4(nodes, b + 1);
-    const auto n010 = ld4(nodes, b + sy), n110 = ld4(nodes, b + sy + 1);
-    const auto n001 = ld4(nodes, b + sz), n101 = ld4(nodes, b + sz + 1);
-    const auto n011 = ld4(nodes, b + sz + sy), n111 = ld4(nodes, b + sz + sy + 1);
     T val[3];
+    if constexpr (interp_order<MODE>() > 1) {
+        // the same stencil sums as field_at (the derivative sums are not used)
+        constexpr int K = interp_order<MODE>() + 1;
+        int s0[3];
+        T w[3][K], dw[3][K], dx[3], dy[3], dz[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) axis_stencil<K, T>(c[d], t[d], g.n[d], s0[d], w[d], dw[d]);
+        stencil_sum<K, 3, T, S>(nodes, g, s0, w, dw, val, dx, dy, dz);
+    } else {
+        const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
+        const int64_t b = (int64_t)c[2] * sz + (int64_t)c[1] * sy + c[0];
+        const auto n000 = ld4(nodes, b), n100 = ld4(nodes, b + 1);
+        const auto n010 = ld4(nodes, b + sy), n110 = ld4(nodes, b + sy + 1);
+        const auto n001 = ld4(nodes, b + sz), n101 = ld4(nodes, b + sz + 1);
+        const auto n011 = ld4(nodes, b + sz + sy), n111 = ld4(nodes, b + sz + sy + 1);
 #define QSQ_COMPV(F, k)                                                                                  \
     val[k] = lerp_val<T>((T)n000.F, (T)n100.F, (T)n010.F, (T)n110.F, (T)n001.F, (T)n101.F, (T)n011.F,    \
                          (T)n111.F, t[0], t[1], t[2])
-    QSQ_COMPV(x, 0);
-    QSQ_COMPV(y, 1);
-    QSQ_COMPV(z, 2);
+        QSQ_COMPV(x, 0);
+        QSQ_COMPV(y, 1);
+        QSQ_COMPV(z, 2);
 #undef QSQ_COMPV
-    if (MODE == QSQ_INTERP_PAPER) {
+    }
+    if (normalize_first<MODE>()) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) u[i] = val[i];
     } else {
@@ -347,7 +518,7 @@ __device__ __forceinline__ T rhs_cached(__amdgpu_buffer_rsrc_t rsrc, int bytes, 
                      (T)v[18 + i], (T)v[21 + i], t[0], t[1], t[2], val[i], dx[i], dy[i], dz[i]);
     const T ihx = (T)g.ih[0], ihy = (T)g.ih[1], ihz = (T)g.ih[2];
     T u[3], G[3][3];
-    if (MODE == QSQ_INTERP_PAPER) {
+    if (normalize_first<MODE>()) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             u[i] = val[i];
@@ -441,7 +612,7 @@ __device__ __forceinline__ T rhs_regs(__amdgpu_buffer_rsrc_t rsrc, int bytes, co
 #undef QSQ_COMPB
     const T ihx = (T)g.ih[0], ihy = (T)g.ih[1], ihz = (T)g.ih[2];
     T u[3], G[3][3];
-    if (MODE == QSQ_INTERP_PAPER) {
+    if (normalize_first<MODE>()) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             u[i] = val[i];
@@ -669,7 +840,7 @@ __global__ void __launch_bounds__(256) k_seed_pass(TraceJob job)
 
 // work list: record indices of the flagged half-lines, forward ones first,
 // each in seed order
-__global__ void k_compact(TraceJob job)
+static __global__ void k_compact(TraceJob job)
 {
     const int64_t n2 = *job.rec.n_items, n = n2 / 2;
     for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n2; it += (int64_t)gridDim.x * blockDim.x)
@@ -724,14 +895,14 @@ __device__ __forceinline__ int64_t half_record(const TraceJob &job, int64_t it, 
     return it >= n ? job.rec.cap + (it - n) : it;
 }
 
-__global__ void k_land_flags(TraceJob job)
+static __global__ void k_land_flags(TraceJob job)
 {
     const int64_t n2 = *job.rec.n_items, n = n2 / 2;
     for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n2; it += (int64_t)gridDim.x * blockDim.x)
         job.rec.flag[it] = job.rec.status[half_record(job, it, n)] == kPendingLand ? 1 : 0;
 }
 
-__global__ void k_land_compact(TraceJob job)
+static __global__ void k_land_compact(TraceJob job)
 {
     const int64_t n2 = *job.rec.n_items, n = n2 / 2;
     for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n2; it += (int64_t)gridDim.x * blockDim.x)
@@ -1568,11 +1739,12 @@ __global__ void __launch_bounds__(256) k_assemble(TraceJob job)
     }
 }
 
-__global__ void k_set_u64(unsigned long long *p, unsigned long long v) { *p = v; }
+static __global__ void k_set_u64(unsigned long long *p, unsigned long long v) { *p = v; }
 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+#ifndef QSQ_TRACE_HIGH_TU
 int set_bits_for(int nsets)
 {
     int b = 0;
@@ -1648,6 +1820,8 @@ int device_cu_count()
 
 // Workgroups of `kern` (wg lanes, lds bytes of dynamic LDS) that stay resident
 // on one CU together, from the runtime's occupancy calculator (cached).
+#endif  // QSQ_TRACE_HIGH_TU
+
 static int resident_blocks(const void *kern, int wg, size_t lds)
 {
     struct Entry {
@@ -1709,7 +1883,8 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
     const int wg = wg_code == 1 ? 64 : wg_code == 2 ? 128 : 256;
     const void *kern;
     size_t lds = 0;
-    constexpr bool cacheable = sizeof(T) == 4 && (std::is_same<S, float>::value || std::is_same<S, Bf16>::value);
+    constexpr bool cacheable = sizeof(T) == 4 && interp_order<MODE>() == 1 &&
+                               (std::is_same<S, float>::value || std::is_same<S, Bf16>::value);
     if constexpr (cacheable && !BATCH) {
         // the cell caches address the node records with 32-bit byte offsets
         const uint64_t field_bytes = (uint64_t)node_bytes<S>() * job.g.n[0] * job.g.n[1] * job.g.n[2];
@@ -1763,12 +1938,46 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
     return hipGetLastError();
 }
 
+#ifdef QSQ_TRACE_HIGH_TU
+// higher interpolation orders: one field per call, FP32 or FP64 node records;
+// each (order, mode) pair is instantiated in a translation unit of its own,
+// so that the build compiles them side by side
+template <int MODE>
+hipError_t launch_trace_mode(const TraceJob &job, int step_dtype, hipStream_t st)
+{
+    const bool f32 = step_dtype == QSQ_F32;
+    if (job.storage == QSQ_F32)
+        return f32 ? launch_typed<float, float, MODE, false>(job, st) : launch_typed<double, float, MODE, false>(job, st);
+    if (job.storage == QSQ_F64)
+        return f32 ? launch_typed<float, double, MODE, false>(job, st)
+                   : launch_typed<double, double, MODE, false>(job, st);
+    return hipErrorNotSupported;
+}
+
+template hipError_t launch_trace_mode<QSQ_TRACE_HIGH_MODE>(const TraceJob &job, int step_dtype, hipStream_t st);
+#else
+
 template <bool BATCH>
 static hipError_t dispatch(const TraceJob &job, int step_dtype, hipStream_t st)
 {
     const bool f32 = step_dtype == QSQ_F32;
-    const bool paper = job.mode == QSQ_INTERP_PAPER;
+    const bool paper = (job.mode & 1) == QSQ_INTERP_PAPER;
     constexpr int P = QSQ_INTERP_PAPER, N = QSQ_INTERP_NORMALIZE;
+    if (job.mode > 1) {
+        // higher interpolation orders: one field per call
+        if constexpr (BATCH) {
+            return hipErrorNotSupported;
+        } else {
+            // job.mode = interpolation mode | (order - 1) << 1
+            switch (job.mode) {
+            case 2: return launch_trace_mode<2>(job, step_dtype, st);
+            case 3: return launch_trace_mode<3>(job, step_dtype, st);
+            case 4: return launch_trace_mode<4>(job, step_dtype, st);
+            case 5: return launch_trace_mode<5>(job, step_dtype, st);
+            default: return hipErrorNotSupported;
+            }
+        }
+    }
     if (job.storage == QSQ_BF16) {
         if (f32) return paper ? launch_typed<float, Bf16, P, BATCH>(job, st) : launch_typed<float, Bf16, N, BATCH>(job, st);
         return paper ? launch_typed<double, Bf16, P, BATCH>(job, st) : launch_typed<double, Bf16, N, BATCH>(job, st);
@@ -1814,5 +2023,7 @@ hipError_t launch_trace_batch(const TraceJob &job, const SetDesc *host_sets, int
     }
     return dispatch<true>(job, step_dtype, st);
 }
+
+#endif  // QSQ_TRACE_HIGH_TU
 
 }  // namespace qsq

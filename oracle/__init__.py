@@ -36,6 +36,7 @@ MAX_LENGTH, MAX_STEPS, NULL, UNDERFLOW, SEED_OUTSIDE, NONFINITE = range(6, 12)
 OPEN_BIT = 1 << 16
 
 PAPER, INTERP_NORMALIZE, ANALYTIC = 0, 1, 2
+GEOMETRIES = {"cartesian": 0, "spherical": 1}
 AN_LINEAR, AN_CHARGES = 0, 1
 
 
@@ -55,7 +56,8 @@ class _Desc(C.Structure):
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("bx", C.c_void_p), ("by", C.c_void_p), ("bz", C.c_void_p),
                 ("lin", C.c_double * 12), ("charges", C.c_void_p), ("ncharges", C.c_int64),
-                ("quantize", C.c_int32), ("order", C.c_int32)]
+                ("quantize", C.c_int32), ("order", C.c_int32), ("geometry", C.c_int32), ("pad", C.c_int32),
+                ("coord", C.c_void_p * 3)]
 
 
 class _Opts(C.Structure):
@@ -118,12 +120,17 @@ class Field:
             self._h = None
 
     @classmethod
-    def grid(cls, bx, by, bz, origin, spacing, mode=PAPER, store="f64", order=1):
+    def grid(cls, bx, by, bz, origin, spacing, mode=PAPER, store="f64", order=1, geometry="cartesian",
+             coords=None):
         """``store="f32"`` / ``"bf16"`` rounds the prepared node values (Bhat and
         |B| in PAPER mode, B otherwise) to FP32 / BF16 (via FP32, nearest even),
         i.e. traces the field such a node store holds.  ``order`` is the
         interpolation order (Sect. 3.2): 1 trilinear, 2 triquadratic (Dodgson
-        1997), 3 tricubic (Keys 1981)."""
+        1997), 3 tricubic (Keys 1981).  ``geometry="spherical"`` reads the axes as
+        (longitude, latitude, radius) and the arrays as (B_phi, B_theta, B_r)
+        (Sect. 3.1, eq. 2 and 6-8).  ``coords`` = (x, y, z) node coordinate
+        arrays (None per axis: uniform) gives a rectilinear grid whose cells
+        have their own spans (Sect. 3.2); trilinear only."""
         bx, by, bz = (np.ascontiguousarray(b, dtype=np.float64) for b in (bx, by, bz))
         nz, ny, nx = bx.shape
         d = _Desc()
@@ -138,7 +145,20 @@ class Field:
         if order not in (1, 2, 3) or (order > 1 and min(d.n) < 4):
             raise ValueError("order must be 1, 2 or 3 (2 and 3 need >= 4 nodes per axis)")
         d.order = order
-        return cls(d, (bx, by, bz))
+        d.geometry = GEOMETRIES[geometry]
+        keep = [bx, by, bz]
+        for a, c in enumerate(coords or (None, None, None)):
+            if c is None:
+                continue
+            c = np.ascontiguousarray(c, dtype=np.float64)
+            if c.shape != (d.n[a],) or not np.all(np.diff(c) > 0):
+                raise ValueError(f"coords[{a}] must be {d.n[a]} increasing node coordinates")
+            if order > 1:
+                raise ValueError("rectilinear (non-uniform) axes take the trilinear kernel only")
+            d.coord[a] = _ptr(c)
+            d.lo[a], d.hi[a] = c[0], c[-1]
+            keep.append(c)
+        return cls(d, tuple(keep))
 
     @classmethod
     def linear(cls, b0, M, lo, hi):
@@ -152,8 +172,11 @@ class Field:
         return cls(d, ())
 
     @classmethod
-    def charges(cls, charges, lo, hi):
-        """Analytic field of point charges, rows (x, y, z, q)."""
+    def charges(cls, charges, lo, hi, geometry="cartesian"):
+        """Analytic field of point charges, rows (x, y, z, q).  With
+        ``geometry="spherical"`` the box [lo, hi] is in (longitude, latitude,
+        radius) and the field is seen in spherical components (a test of the
+        spherical equations against the Cartesian ones)."""
         ch = np.ascontiguousarray(charges, dtype=np.float64).reshape(-1, 4)
         d = _Desc()
         d.kind = ANALYTIC
@@ -162,6 +185,7 @@ class Field:
         d.ncharges = ch.shape[0]
         d.lo[:] = lo
         d.hi[:] = hi
+        d.geometry = GEOMETRIES[geometry]
         return cls(d, (ch,))
 
     def eval(self, x):
@@ -301,6 +325,29 @@ class SlicePlane:
         px = self.x0 + (np.asarray(ix) + 0.5) * (self.x1 - self.x0) / n
         py = self.y0 + (np.asarray(iy) + 0.5) * (self.y1 - self.y0) / n
         return np.stack([px, py, np.full(px.shape, float(self.z0))], axis=-1)
+
+    def cells(self, level, d):
+        return hilbert2_d2xy(level, d)
+
+
+class PlaneSlice:
+    """Planar slice of any orientation (Sect. 2: orientation, centre and axis
+    spans): the parallelogram corner + s u + t v, s, t in [0, 1], with edge
+    vectors u and v.  Cell (i, j) of level L sits at corner + (i + 1/2) / 2^L u
+    + (j + 1/2) / 2^L v.  In spherical geometry a slice at fixed radius over
+    longitude and latitude ranges is the plane r = r0 of the coordinates."""
+    dims = 2
+
+    def __init__(self, corner, u, v):
+        self.corner = np.asarray(corner, float)
+        self.u = np.asarray(u, float)
+        self.v = np.asarray(v, float)
+
+    def centres(self, level, ix, iy):
+        n = 1 << level
+        s = (np.asarray(ix, float) + 0.5) / n
+        t = (np.asarray(iy, float) + 0.5) / n
+        return self.corner + s[..., None] * self.u + t[..., None] * self.v
 
     def cells(self, level, d):
         return hilbert2_d2xy(level, d)

@@ -74,7 +74,16 @@ typedef struct {
                               BF16 (the stored form of an FP32 / BF16 node field) */
     int32_t order;         /* interpolation order (Sect. 3.2): 1 trilinear (also 0),
                               2 triquadratic (Dodgson 1997), 3 tricubic (Keys 1981) */
+    int32_t geometry;      /* OR_CARTESIAN, or OR_SPHERICAL (Sect. 3.1): coordinates
+                              (phi, theta, r) = (longitude, latitude, radius), field
+                              components (B_phi, B_theta, B_r) in the orthonormal basis */
+    int32_t pad;
+    const double *coord[3]; /* NULL: uniform axis (origin + i spacing); else the n[d]
+                              increasing node coordinates of a rectilinear axis (Sect. 3.2:
+                              h_c is the span of the point's cell); trilinear only */
 } or_field_desc;
+
+enum { OR_CARTESIAN = 0, OR_SPHERICAL = 1 };
 
 typedef struct {
     or_field_desc d;
@@ -166,19 +175,44 @@ void or_field_free(void *h)
 /* interpolation, eq. (3)-(4), and its analytic gradient (Sect. 3.3)   */
 /* ------------------------------------------------------------------ */
 
-/* cell c = vertex of the containing cell closest to the array origin */
-static void locate(const or_field *F, const double x[3], int64_t c[3], double t[3])
+/* cell c = vertex of the containing cell closest to the array origin, the
+ * point's fraction t of the cell and the cell's span h (uniform axes: the
+ * spacing; rectilinear axes: coord[c+1] - coord[c], found by bisection) */
+static void locate_h(const or_field *F, const double x[3], int64_t c[3], double t[3], double h[3])
 {
     for (int d = 0; d < 3; ++d) {
+        const int64_t n = F->d.n[d];
+        const double *X = F->d.coord[d];
+        if (X) {
+            double xv = x[d];
+            if (!(xv > -1e300)) xv = -1e300;      /* also catches NaN */
+            int64_t lo = 0, hi = n - 2;           /* last cell whose lower node <= x, clamped */
+            while (lo < hi) {
+                int64_t mid = (lo + hi + 1) / 2;
+                if (X[mid] <= xv) lo = mid;
+                else hi = mid - 1;
+            }
+            c[d] = lo;
+            h[d] = X[lo + 1] - X[lo];
+            t[d] = (x[d] - X[lo]) / h[d];
+            continue;
+        }
         double s = (x[d] - F->d.origin[d]) / F->d.spacing[d];
         if (!(s > -1e9)) s = -1e9;      /* also catches NaN */
         if (s > 1e9) s = 1e9;
         double fl = floor(s);
         if (fl < 0.0) fl = 0.0;
-        if (fl > (double)(F->d.n[d] - 2)) fl = (double)(F->d.n[d] - 2);
+        if (fl > (double)(n - 2)) fl = (double)(n - 2);
         c[d] = (int64_t)fl;
         t[d] = s - fl;
+        h[d] = F->d.spacing[d];
     }
+}
+
+static void locate(const or_field *F, const double x[3], int64_t c[3], double t[3])
+{
+    double h[3];
+    locate_h(F, x, c, t, h);
 }
 
 /* sum over the 8 stencil vertices of value * f_v and value * grad f_v */
@@ -186,8 +220,8 @@ static void trilinear(const or_field *F, int ncomp, const double x[3],
                       double val[4], double grad[4][3])
 {
     int64_t c[3];
-    double t[3];
-    locate(F, x, c, t);
+    double t[3], h[3];
+    locate_h(F, x, c, t, h);
     for (int k = 0; k < ncomp; ++k) {
         val[k] = 0.0;
         grad[k][0] = grad[k][1] = grad[k][2] = 0.0;
@@ -198,7 +232,7 @@ static void trilinear(const or_field *F, int ncomp, const double x[3],
         double w[3], dw[3];
         for (int d = 0; d < 3; ++d) {
             w[d] = vv[d] ? t[d] : 1.0 - t[d];
-            dw[d] = (vv[d] ? 1.0 : -1.0) / F->d.spacing[d];
+            dw[d] = (vv[d] ? 1.0 : -1.0) / h[d];
         }
         double f = w[0] * w[1] * w[2];
         double df[3] = { dw[0] * w[1] * w[2], w[0] * dw[1] * w[2], w[0] * w[1] * dw[2] };
@@ -375,6 +409,78 @@ static void analytic_B(const or_field *F, const double x[3], double B[3], double
     }
 }
 
+static double dot3(const double *a, const double *b);
+
+/* Spherical geometry (Sect. 3.1): longitude phi, latitude theta, radius r;
+ * the orthonormal basis (phi_hat, theta_hat, r_hat) at (phi, theta) */
+static void sph_basis(double ph, double th, double e[3][3])
+{
+    const double cp = cos(ph), sp = sin(ph), ct = cos(th), st = sin(th);
+    e[0][0] = -sp, e[0][1] = cp, e[0][2] = 0.0;                 /* phi_hat */
+    e[1][0] = -st * cp, e[1][1] = -st * sp, e[1][2] = ct;       /* theta_hat */
+    e[2][0] = ct * cp, e[2][1] = ct * sp, e[2][2] = st;         /* r_hat */
+}
+
+/* Cartesian position of the spherical point q = (phi, theta, r) */
+static void sph_to_cart(const double q[3], double x[3])
+{
+    x[0] = q[2] * cos(q[1]) * cos(q[0]);
+    x[1] = q[2] * cos(q[1]) * sin(q[0]);
+    x[2] = q[2] * sin(q[1]);
+}
+
+/* An analytic Cartesian field seen in spherical coordinates: the components
+ * B_i(q) = e_i(q) . B(x(q)) and their coordinate derivatives
+ * d_j B_i = e_i . (grad B  d_j x) + (d_j e_i) . B, with d_phi x = r cos(theta)
+ * phi_hat, d_theta x = r theta_hat, d_r x = r_hat and the basis derivatives
+ * written out from the basis vectors' components. */
+static void analytic_B(const or_field *F, const double x[3], double B[3], double G[3][3]);
+
+static void analytic_sph(const or_field *F, const double q[3], double Bs[3], double Gs[3][3])
+{
+    const double ph = q[0], th = q[1], r = q[2];
+    double x[3], Bc[3], Gc[3][3], e[3][3];
+    sph_to_cart(q, x);
+    analytic_B(F, x, Bc, Gc);
+    sph_basis(ph, th, e);
+    const double cp = cos(ph), sp = sin(ph), ct = cos(th), st = sin(th);
+    /* d e_i / d phi and d e_i / d theta (d / d r of the basis is zero) */
+    double dphi[3][3] = { { -cp, -sp, 0.0 }, { st * sp, -st * cp, 0.0 }, { -ct * sp, ct * cp, 0.0 } };
+    double dth[3][3] = { { 0.0, 0.0, 0.0 }, { -ct * cp, -ct * sp, -st }, { -st * cp, -st * sp, ct } };
+    double dx[3][3];   /* d x / d q_j, one vector per j */
+    for (int k = 0; k < 3; ++k) {
+        dx[0][k] = r * ct * e[0][k];
+        dx[1][k] = r * e[1][k];
+        dx[2][k] = e[2][k];
+    }
+    for (int i = 0; i < 3; ++i) {
+        Bs[i] = dot3(e[i], Bc);
+        for (int j = 0; j < 3; ++j) {
+            double gdx[3];
+            for (int k = 0; k < 3; ++k) gdx[k] = Gc[k][0] * dx[j][0] + Gc[k][1] * dx[j][1] + Gc[k][2] * dx[j][2];
+            double de = 0.0;
+            if (j == 0) de = dot3(dphi[i], Bc);
+            if (j == 1) de = dot3(dth[i], Bc);
+            Gs[i][j] = dot3(e[i], gdx) + de;
+        }
+    }
+}
+
+/* metric factors of the field-line equation in spherical geometry, eq. (2):
+ * d phi / d lambda = Bhat_phi / (r cos theta), d theta / d lambda = Bhat_theta
+ * / r, d r / d lambda = Bhat_r; the deviations of eq. (6) carry the same
+ * factors, and eq. (8) turns them back into lengths.  Cartesian: all 1. */
+static void metric(const or_field *F, const double q[3], double scale[3])
+{
+    if (F->d.geometry == OR_SPHERICAL) {
+        scale[0] = q[2] * cos(q[1]);
+        scale[1] = q[2];
+        scale[2] = 1.0;
+    } else {
+        scale[0] = scale[1] = scale[2] = 1.0;
+    }
+}
+
 /* Bhat(x), its gradient J[i][j] = d Bhat_i / d x_j, and |B|(x).
  * PAPER mode: Bhat is the interpolant of the normalised node field (not a
  * unit vector in general); |B| is the interpolant of the node magnitudes. */
@@ -398,6 +504,8 @@ static void field_eval(const or_field *F, const double x[3], double u[3], double
             B[i] = val[i];
             for (int j = 0; j < 3; ++j) G[i][j] = grad[i][j];
         }
+    } else if (F->d.geometry == OR_SPHERICAL) {
+        analytic_sph(F, x, B, G);
     } else {
         analytic_B(F, x, B, G);
     }
@@ -421,12 +529,16 @@ void or_field_eval(const void *h, int64_t n, const double *x, double *u, double 
 
 static void rhs(const or_field *F, double sigma, const double y[9], double dy[9])
 {
-    double u[3], J[3][3], bm;
+    double u[3], J[3][3], bm, sc[3];
     field_eval(F, y, u, J, &bm);
+    metric(F, y, sc);
+    /* Cartesian: eq. (1) and (5); spherical: eq. (2) and (6), the deviations
+     * held as coordinate differences (d phi, d theta, d r), J the coordinate
+     * derivatives of the interpolated components */
     for (int i = 0; i < 3; ++i) {
-        dy[i] = sigma * u[i];
-        dy[3 + i] = sigma * (J[i][0] * y[3] + J[i][1] * y[4] + J[i][2] * y[5]);
-        dy[6 + i] = sigma * (J[i][0] * y[6] + J[i][1] * y[7] + J[i][2] * y[8]);
+        dy[i] = sigma * u[i] / sc[i];
+        dy[3 + i] = sigma * (J[i][0] * y[3] + J[i][1] * y[4] + J[i][2] * y[5]) / sc[i];
+        dy[6 + i] = sigma * (J[i][0] * y[6] + J[i][1] * y[7] + J[i][2] * y[8]) / sc[i];
     }
 }
 
@@ -819,10 +931,12 @@ void or_trace(const void *hf, const or_opts *O, int64_t n, const double *seeds,
                 double a[3], b[3], y0[9];
                 onb(nrm, a, b);
                 double ca = cos(O->frame_angle), sa = sin(O->frame_angle);
+                double sc0[3];
+                metric(F, x0, sc0);
                 for (int j = 0; j < 3; ++j) {
                     y0[j] = x0[j];
-                    y0[3 + j] = ca * a[j] + sa * b[j];      /* eq. (9): dx1(0) = a */
-                    y0[6 + j] = -sa * a[j] + ca * b[j];     /* eq. (9): dx2(0) = b */
+                    y0[3 + j] = (ca * a[j] + sa * b[j]) / sc0[j];      /* eq. (9): dx1(0) = a */
+                    y0[6 + j] = (-sa * a[j] + ca * b[j]) / sc0[j];     /* eq. (9): dx2(0) = b */
                 }
                 trace_half(F, O, +1.0, y0, &H[0]);
                 trace_half(F, O, -1.0, y0, &H[1]);
@@ -866,20 +980,30 @@ void or_trace(const void *hf, const or_opts *O, int64_t n, const double *seeds,
                 uF[j] /= nF;
                 uB[j] /= nB;
             }
+            /* the deviations as lengths at each end, eq. (8) (Cartesian: as held) */
+            double scF[3], scB[3], dF1[3], dF2[3], dB1[3], dB2[3];
+            metric(F, H[0].y, scF);
+            metric(F, H[1].y, scB);
+            for (int j = 0; j < 3; ++j) {
+                dF1[j] = scF[j] * H[0].y[3 + j];
+                dF2[j] = scF[j] * H[0].y[6 + j];
+                dB1[j] = scB[j] * H[1].y[3 + j];
+                dB2[j] = scB[j] * H[1].y[6 + j];
+            }
             double aF[3], bF[3], aB[3], bB[3];
-            perp(H[0].y + 3, uF, aF);
-            perp(H[0].y + 6, uF, bF);
-            perp(H[1].y + 3, uB, aB);
-            perp(H[1].y + 6, uB, bB);
+            perp(dF1, uF, aF);
+            perp(dF2, uF, bF);
+            perp(dB1, uB, aB);
+            perp(dB2, uB, bB);
             double br = bracket(aF, bF, aB, bB);
             qp = BF * BB / (B0 * B0) * br;                               /* eq. (11) */
             qd = br / (cross_norm(aF, bF) * cross_norm(aB, bB));
             if (is_face(stF) && is_face(stB)) {
                 double pF1[3], pF2[3], pB1[3], pB2[3];
-                along_to_face(H[0].y + 3, vF, stF, pF1);
-                along_to_face(H[0].y + 6, vF, stF, pF2);
-                along_to_face(H[1].y + 3, vB, stB, pB1);
-                along_to_face(H[1].y + 6, vB, stB, pB2);
+                along_to_face(dF1, vF, stF, pF1);
+                along_to_face(dF2, vF, stF, pF2);
+                along_to_face(dB1, vB, stB, pB1);
+                along_to_face(dB2, vB, stB, pB2);
                 qf = bracket(pF1, pF2, pB1, pB2) / (cross_norm(pF1, pF2) * cross_norm(pB1, pB2));
             }
         }

@@ -374,3 +374,46 @@ def test_shifted_repass_disc_and_volume(oracle_mod):
     vplain, _, _ = O.refine_slice(box, 3, 2, 0.5, ball)
     assert vk.size > vplain.size
     _complete_both_orders(O, box, 3, 2, vk, vv["fll"], 0.5, 3)
+
+
+# ---------------------------------------------------------------------------
+# planar slices of any orientation (Sect. 2)
+# ---------------------------------------------------------------------------
+
+def test_plane_slice_axis_aligned_is_the_horizontal_slice(oracle_mod):
+    O = oracle_mod
+    a = O.SlicePlane(0.25, -1.0, 0.5, -0.5, 1.0)
+    b = O.PlaneSlice((-1.0, -0.5, 0.25), (1.5, 0.0, 0.0), (0.0, 1.5, 0.0))
+    d = np.arange(4 ** 5)
+    assert np.array_equal(a.centres(5, *a.cells(5, d)), b.centres(5, *b.cells(5, d)))
+
+
+def test_plane_slice_tilted_through_the_flux_tube(oracle_mod):
+    """A refined map on a tilted slice through the analytic flux tube B = (kx,
+    -ky, 1): every sample (base and refined) sits on the plane, and its Q is
+    the closed form of the line through its position."""
+    from test_oracle_trace import K, _hyp_closed, _hyp_qperp
+    O = oracle_mod
+    b0, M = synth.hyperbolic(K)
+    F = O.Field.linear(b0, M, synth.LO, synth.HI)
+    corner = np.array([-0.3, -0.35, 0.2])
+    u = np.array([0.6, 0.1, 0.3])
+    v = np.array([-0.1, 0.7, 0.25])
+    plane = O.PlaneSlice(corner, u, v)
+    m, r = 3, 2
+    got = {}
+
+    def fn(p):
+        t = O.trace(F, p, rtol=1e-11, atol=1e-11, h_init=1e-3, h_max=0.02)
+        for row, f, q in zip(p, t["fll"], t["q_perp"]):
+            got[tuple(row)] = q
+        return {"fll": t["fll"], "q": t["q_perp"]}
+
+    keys, vals, _ = O.refine_slice(plane, m, r, 0.05, fn)
+    assert keys.size > 4 ** m
+    normal = np.cross(u, v)
+    pts = np.array(list(got))
+    assert np.abs((pts - corner) @ normal).max() < 1e-12
+    for p, q in list(got.items())[::7]:
+        c = _hyp_closed(*p)
+        assert abs(q / _hyp_qperp(c["xb"], c["zf"], c["zb"]) - 1) < 1e-7

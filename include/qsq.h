@@ -126,8 +126,25 @@ typedef struct qsq_field {
     int32_t order;         /* interpolation order (Sect. 3.2, eq. 3): QSQ_ORDER_*; 0 reads as
                               trilinear.  qsq_field_init sets trilinear; a caller may
                               set another order on the descriptor afterwards */
-    int32_t pad;
+    int32_t geometry;      /* QSQ_GEOMETRY_*; qsq_field_init sets CARTESIAN */
+    const double *coords[3]; /* NULL, or device: the n[d] increasing node coordinates of a
+                              rectilinear axis d (Sect. 3.2: each cell has its own span
+                              h_c); grid.origin[d] and grid.origin[d] + (n[d]-1)
+                              grid.spacing[d] must be its first and last coordinates
+                              (the box).  qsq_field_init sets NULL */
 } qsq_field;
+
+/* Geometry of a field (Sect. 3.1).  SPHERICAL: the grid axes are longitude phi,
+ * latitude theta (radians) and radius r, the input arrays (B_phi, B_theta,
+ * B_r) in the local orthonormal basis; field lines follow eq. (2), deviations
+ * eq. (6)-(7) held as coordinate differences (d phi, d theta, d r), turned into
+ * lengths by eq. (8) for Q; footpoints are returned in (phi, theta, r).
+ * SPHERICAL fields and fields with rectilinear axes take the trilinear
+ * kernel, FP32 or FP64 node records and the CK54 stepper, one field per call;
+ * they are stepped in physical coordinates by a kernel of their own.  h_init
+ * and h_max (arc length) should be given explicitly for spherical grids. */
+#define QSQ_GEOMETRY_CARTESIAN 0
+#define QSQ_GEOMETRY_SPHERICAL 1
 
 typedef struct qsq_trace_opts {
     int32_t stepper;       /* QSQ_STEPPER_CK54, or QSQ_STEPPER_EULER: fixed steps
@@ -366,6 +383,12 @@ typedef struct qsq_map_desc {
                               along the curve shifted by `shift` finest cells per
                               axis (0 < shift < 2^(m+r); see qsq_qmap) */
     int32_t max_cycles;    /* with shift: at most this many cycles (1..48; <= 0: 48) */
+    int32_t tilted;        /* 0: the horizontal slice above; 1: the planar slice of any
+                              orientation corner + s edge_u + t edge_v, s, t in [0, 1]
+                              (Sect. 2), pixel (i, j) of level L at s = (i + 1/2) / 2^L,
+                              t = (j + 1/2) / 2^L (z0, x0, x1, y0, y1 unused) */
+    int32_t pad;
+    double corner[3], edge_u[3], edge_v[3];
 } qsq_map_desc;
 
 /* Results of qsq_qmap (device memory).  Samples are kept in curve order. */

@@ -19,6 +19,7 @@ INTERP_PAPER, INTERP_NORMALIZE = 0, 1
 STEPPER_CK54 = 0
 STEPPER_EULER = 1
 ORDER_LINEAR, ORDER_QUADRATIC, ORDER_CUBIC = 1, 2, 3
+GEOMETRY_CARTESIAN, GEOMETRY_SPHERICAL = 0, 1
 FLAG_SKIP_OPEN = 1
 
 END_XLO, END_XHI, END_YLO, END_YHI, END_ZLO, END_ZHI = range(6)
@@ -62,7 +63,7 @@ class Grid(C.Structure):
 class FieldDesc(C.Structure):
     _fields_ = [("grid", Grid), ("storage", C.c_int32), ("mode", C.c_int32),
                 ("nodes", C.c_void_p), ("bytes", C.c_uint64), ("cells", C.c_void_p), ("cell_bytes", C.c_uint64),
-                ("order", C.c_int32), ("pad", C.c_int32)]
+                ("order", C.c_int32), ("geometry", C.c_int32), ("coords", C.c_void_p * 3)]
 
 
 class TraceOpts(C.Structure):
@@ -86,7 +87,9 @@ class MapDesc(C.Structure):
     _fields_ = [("z0", C.c_double), ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double),
                 ("y1", C.c_double), ("base_level", C.c_int32), ("refine_levels", C.c_int32),
                 ("out_level", C.c_int32), ("refine_batch", C.c_int32), ("threshold", C.c_double),
-                ("propose", C.c_void_p), ("shift", C.c_int32), ("max_cycles", C.c_int32)]
+                ("propose", C.c_void_p), ("shift", C.c_int32), ("max_cycles", C.c_int32),
+                ("tilted", C.c_int32), ("pad", C.c_int32), ("corner", C.c_double * 3), ("edge_u", C.c_double * 3),
+                ("edge_v", C.c_double * 3)]
 
 
 class VolumeDesc(C.Structure):

@@ -67,9 +67,14 @@ class Field:
 _ORDER = {"linear": A.ORDER_LINEAR, "quadratic": A.ORDER_QUADRATIC, "cubic": A.ORDER_CUBIC}
 
 
-def field_init(bx, by, bz, origin, spacing, storage="f32", mode="paper", stream=None, order="linear") -> Field:
+def field_init(bx, by, bz, origin, spacing, storage="f32", mode="paper", stream=None, order="linear",
+               geometry="cartesian", coords=None) -> Field:
     """Prepare node records from B component arrays shaped (nz, ny, nx) on the
-    device; `order` picks the interpolation kernel (linear, quadratic, cubic)."""
+    device; `order` picks the interpolation kernel (linear, quadratic, cubic);
+    geometry "spherical" reads the axes as (longitude, latitude, radius) and
+    the arrays as (B_phi, B_theta, B_r); `coords` = (x, y, z) node coordinate
+    tensors (None per axis: uniform) makes a rectilinear grid, whose first and
+    last coordinates must equal origin and origin + (n - 1) spacing."""
     if bx.dtype not in (torch.float32, torch.float64):
         raise TypeError("B components must be float32 or float64")
     in_dt = A.F64 if bx.dtype == torch.float64 else A.F32
@@ -85,7 +90,19 @@ def field_init(bx, by, bz, origin, spacing, storage="f32", mode="paper", stream=
     check(lib.qsq_field_init(C.byref(g), _p(bx), _p(by), _p(bz), in_dt, _DT[storage], _MODE[mode],
                              _p(ws), ws.numel() * 8, _stream(stream), C.byref(d)))
     d.order = _ORDER[order]
-    return Field(d, ws)
+    d.geometry = {"cartesian": A.GEOMETRY_CARTESIAN, "spherical": A.GEOMETRY_SPHERICAL}[geometry]
+    keep = []
+    for a, c in enumerate(coords or (None, None, None)):
+        if c is None:
+            continue
+        c = _dev(c, torch.float64, "coords")
+        if c.numel() != d.grid.n[a]:
+            raise ValueError(f"coords[{a}] must hold {d.grid.n[a]} node coordinates")
+        d.coords[a] = c.data_ptr()
+        keep.append(c)
+    f = Field(d, ws)
+    f.coords_ws = keep
+    return f
 
 
 _STEPPER = {"ck54": A.STEPPER_CK54, "euler": A.STEPPER_EULER}
@@ -267,6 +284,7 @@ class MapSpec:
     propose: Optional[torch.Tensor] = None   # uint8 per base pixel in curve order (device)
     shift: int = 0          # > 0: shifted-curve re-pass by this many finest cells per axis
     max_cycles: int = 0     # re-pass cycles at most (0: library default)
+    plane: Optional[tuple] = None   # (corner, edge_u, edge_v): a slice of any orientation
 
     def desc(self) -> A.MapDesc:
         d = A.MapDesc()
@@ -276,6 +294,12 @@ class MapSpec:
         d.threshold = self.threshold
         d.propose = _proposal_ptr(self.propose, 4 ** self.base_level)
         d.shift, d.max_cycles = self.shift, self.max_cycles
+        if self.plane is not None:
+            corner, eu, ev = self.plane
+            d.tilted = 1
+            d.corner[:] = tuple(float(v) for v in corner)
+            d.edge_u[:] = tuple(float(v) for v in eu)
+            d.edge_v[:] = tuple(float(v) for v in ev)
         return d
 
 

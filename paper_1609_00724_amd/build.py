@@ -19,8 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqsq.so")
 
-SOURCES = ["trace.hip", "trace_o2p.hip", "trace_o2n.hip", "trace_o3p.hip", "trace_o3n.hip", "field.hip", "maps.hip",
-           "cnn.hip", "sort.hip", "qsq_abi.cpp"]
+SOURCES = ["trace.hip", "trace_o2p.hip", "trace_o2n.hip", "trace_o3p.hip", "trace_o3n.hip", "trace_geop.hip",
+           "trace_geon.hip", "field.hip", "maps.hip", "cnn.hip", "sort.hip", "qsq_abi.cpp"]
 ARCH = os.environ.get("QSQ_OFFLOAD_ARCH", "gfx950")
 
 

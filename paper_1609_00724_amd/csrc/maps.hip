@@ -287,8 +287,25 @@ hipError_t launch_fledge(const float *in, int ndim, const int64_t *shape, float 
 struct Region {
     double lo[3], d[3];
     int m, r, L;                 // base level, refine levels, finest level
+    int tilted;                  // slices: 1 = a plane of any orientation (eu, ev below)
     double thr;
+    double eu[3], ev[3];         // tilted slices: the finest cell's edge vectors
 };
+
+// Position of the centre of cell c at a level whose cells are `f` finest cells
+// wide: axis-aligned slices and volumes offset lo along the axes; a tilted
+// slice (Sect. 2: orientation, centre and axis spans) offsets it along the
+// plane's edge vectors.
+template <int DIM>
+__device__ __forceinline__ void cell_centre(const Region &rg, const uint32_t c[3], double f, double x[3])
+{
+    if (DIM == 2 && rg.tilted) {
+        const double s = ((double)c[0] + 0.5) * f, t = ((double)c[1] + 0.5) * f;
+        for (int a = 0; a < 3; ++a) x[a] = rg.lo[a] + s * rg.eu[a] + t * rg.ev[a];
+    } else {
+        for (int a = 0; a < 3; ++a) x[a] = (a < DIM) ? rg.lo[a] + ((double)c[a] + 0.5) * f * rg.d[a] : rg.lo[a];
+    }
+}
 
 struct Samples {
     uint64_t *keys;
@@ -305,8 +322,9 @@ __global__ void k_base_seeds(Region rg, int64_t nb, int64_t stride, double *seed
         uint32_t c[3];
         cell_of_key<DIM>(rg.m, (uint64_t)q, c);
         const double f = (double)(1u << rg.r);   // base cell = f finest cells per axis
-        for (int a = 0; a < 3; ++a)
-            seeds[a * stride + q] = (a < DIM) ? rg.lo[a] + ((double)c[a] + 0.5) * f * rg.d[a] : rg.lo[a];
+        double x[3];
+        cell_centre<DIM>(rg, c, f, x);
+        for (int a = 0; a < 3; ++a) seeds[a * stride + q] = x[a];
         const uint64_t blk = (uint64_t)1 << (DIM * rg.r);
         keys[q] = (uint64_t)q * blk + blk / 2;
     }
@@ -490,8 +508,9 @@ __global__ void k_spec_seeds(Region rg, const Round *rdp, Samples a, const int64
             cell_of_key<DIM>(rg.L, k, c);
             const int64_t p = base + j - 1;
             nkeys[p] = k;
-            for (int ax = 0; ax < 3; ++ax)
-                seeds[ax * stride + p] = (ax < DIM) ? rg.lo[ax] + ((double)c[ax] + 0.5) * rg.d[ax] : rg.lo[ax];
+            double x[3];
+            cell_centre<DIM>(rg, c, 1.0, x);
+            for (int ax = 0; ax < 3; ++ax) seeds[ax * stride + p] = x[ax];
         }
     }
 }
@@ -796,8 +815,9 @@ __global__ void k_prop_seeds(Region rg, int64_t nb, const int32_t *flag, const i
             uint32_t c[3];
             cell_of_key<DIM>(rg.L, k, c);
             nkeys[base + p] = k;
-            for (int ax = 0; ax < 3; ++ax)
-                seeds[ax * stride + base + p] = (ax < DIM) ? rg.lo[ax] + ((double)c[ax] + 0.5) * rg.d[ax] : rg.lo[ax];
+            double x[3];
+            cell_centre<DIM>(rg, c, 1.0, x);
+            for (int ax = 0; ax < 3; ++ax) seeds[ax * stride + base + p] = x[ax];
             ++p;
         }
     }
@@ -924,8 +944,9 @@ __global__ void k_shift_seeds(Region rg, const int64_t *count_in, const int32_t 
         cell_of_key<DIM>(rg.L, k, c);
         nkeys[p] = k;
         nidx[p] = (int32_t)p;
-        for (int ax = 0; ax < 3; ++ax)
-            seeds[ax * stride + p] = (ax < DIM) ? rg.lo[ax] + ((double)c[ax] + 0.5) * rg.d[ax] : rg.lo[ax];
+        double x[3];
+        cell_centre<DIM>(rg, c, 1.0, x);
+        for (int ax = 0; ax < 3; ++ax) seeds[ax * stride + p] = x[ax];
     }
 }
 
@@ -1212,6 +1233,14 @@ hipError_t launch_qmap(const qsq_field *f, const Geom &g, const StepOpts &o, int
     rg.d[1] = (d->y1 - d->y0) / nL;
     rg.d[2] = 0.0;
     rg.thr = d->threshold;
+    if (d->tilted) {
+        rg.tilted = 1;
+        for (int a = 0; a < 3; ++a) {
+            rg.lo[a] = d->corner[a];
+            rg.eu[a] = d->edge_u[a] / nL;
+            rg.ev[a] = d->edge_v[a] / nL;
+        }
+    }
     return launch_map<2>(f, g, o, step_dtype, rg, d->out_level, d->refine_batch, d->propose, d->shift, d->max_cycles,
                          out, scratch, st);
 }

@@ -67,6 +67,21 @@ int check_field(const qsq_field *f)
     if (f->cells && f->cell_bytes < qsq::cell_record_bytes(&f->grid, f->storage))
         return fail(QSQ_ERR_INVALID_ARG, "field cell_bytes smaller than the grid's cell records");
     if (f->order < 0 || f->order > QSQ_ORDER_CUBIC) return fail(QSQ_ERR_INVALID_ARG, "field order %d", f->order);
+    if (f->geometry != QSQ_GEOMETRY_CARTESIAN && f->geometry != QSQ_GEOMETRY_SPHERICAL)
+        return fail(QSQ_ERR_INVALID_ARG, "field geometry %d", f->geometry);
+    const bool rect = f->coords[0] || f->coords[1] || f->coords[2];
+    if (f->geometry == QSQ_GEOMETRY_SPHERICAL || rect) {
+        if (f->order > QSQ_ORDER_LINEAR)
+            return fail(QSQ_ERR_UNSUPPORTED, "spherical or rectilinear fields take the trilinear kernel");
+        if (f->storage == QSQ_BF16)
+            return fail(QSQ_ERR_UNSUPPORTED, "spherical or rectilinear fields need FP32 or FP64 node records");
+    }
+    if (f->geometry == QSQ_GEOMETRY_SPHERICAL) {
+        const double th0 = f->grid.origin[1], th1 = th0 + (double)(f->grid.n[1] - 1) * f->grid.spacing[1];
+        const double r0 = f->grid.origin[2];
+        if (!(th0 > -1.5707963267948966) || !(th1 < 1.5707963267948966) || !(r0 > 0.0))
+            return fail(QSQ_ERR_INVALID_ARG, "spherical grid needs latitudes inside (-pi/2, pi/2) and radii > 0");
+    }
     if (f->order > QSQ_ORDER_LINEAR) {
         if (f->storage == QSQ_BF16)
             return fail(QSQ_ERR_UNSUPPORTED, "interpolation order %d needs FP32 or FP64 node records", f->order);
@@ -103,7 +118,12 @@ int make_geom_opts(const qsq_field *f, const qsq_trace_opts *o, qsq::Geom *g, qs
         hmin_grid = fmin(hmin_grid, f->grid.spacing[d]);
         extent = fmax(extent, g->hi[d] - g->lo[d]);
     }
-    g->pad = 0;
+    g->geometry = f->geometry;
+    for (int d = 0; d < 3; ++d) g->coord[d] = f->coords[d];
+    if (qsq::job_mode(f) & 8) {
+        if (o->stepper != QSQ_STEPPER_CK54)
+            return fail(QSQ_ERR_UNSUPPORTED, "spherical or rectilinear fields take the CK54 stepper");
+    }
     so->rtol = o->rtol;
     so->atol = o->atol;
     so->h_max = o->h_max > 0.0 ? o->h_max : hmin_grid;
@@ -269,7 +289,8 @@ int qsq_field_init(const qsq_grid *g, const void *bx, const void *by, const void
     out->cells = nullptr;
     out->cell_bytes = 0;
     out->order = QSQ_ORDER_LINEAR;
-    out->pad = 0;
+    out->geometry = QSQ_GEOMETRY_CARTESIAN;
+    out->coords[0] = out->coords[1] = out->coords[2] = nullptr;
     return ok();
 }
 
@@ -434,7 +455,7 @@ int qsq_trace_batch(const qsq_trace_set *sets, int32_t nsets, const qsq_trace_op
         const qsq_trace_set &t = sets[k];
         int rc = check_field(&t.field);
         if (rc) return set_fail(rc, k);
-        if (t.field.order > QSQ_ORDER_LINEAR) return set_fail(QSQ_ERR_UNSUPPORTED, k);
+        if (t.field.order > QSQ_ORDER_LINEAR || (qsq::job_mode(&t.field) & 8)) return set_fail(QSQ_ERR_UNSUPPORTED, k);
         if (t.field.storage != sets[0].field.storage || t.field.mode != sets[0].field.mode)
             return fail(QSQ_ERR_INVALID_ARG, "set %d: storage and mode must match set 0", k);
         qsq::Geom g;
@@ -574,8 +595,22 @@ static int check_map(const qsq_map_desc *d)
         return fail(QSQ_ERR_INVALID_ARG, "need base_level >= 1, refine_levels >= 0, sum <= 16");
     if (d->out_level < d->base_level || d->out_level > d->base_level + d->refine_levels)
         return fail(QSQ_ERR_INVALID_ARG, "out_level outside [base_level, base_level + refine_levels]");
-    if (!(d->x1 > d->x0) || !(d->y1 > d->y0) || !isfinite(d->z0))
+    if (d->tilted) {
+        double uu = 0.0, vv = 0.0, cr[3];
+        for (int a = 0; a < 3; ++a) {
+            if (!isfinite(d->corner[a]) || !isfinite(d->edge_u[a]) || !isfinite(d->edge_v[a]))
+                return fail(QSQ_ERR_INVALID_ARG, "tilted slice corner and edges must be finite");
+            uu += d->edge_u[a] * d->edge_u[a];
+            vv += d->edge_v[a] * d->edge_v[a];
+        }
+        cr[0] = d->edge_u[1] * d->edge_v[2] - d->edge_u[2] * d->edge_v[1];
+        cr[1] = d->edge_u[2] * d->edge_v[0] - d->edge_u[0] * d->edge_v[2];
+        cr[2] = d->edge_u[0] * d->edge_v[1] - d->edge_u[1] * d->edge_v[0];
+        if (!(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2] > 1e-24 * uu * vv))
+            return fail(QSQ_ERR_INVALID_ARG, "tilted slice edges must span a plane");
+    } else if (!(d->x1 > d->x0) || !(d->y1 > d->y0) || !isfinite(d->z0)) {
         return fail(QSQ_ERR_INVALID_ARG, "slice extent must satisfy x1 > x0, y1 > y0, finite z0");
+    }
     if (!(d->threshold >= 0.0)) return fail(QSQ_ERR_INVALID_ARG, "threshold must be >= 0");
     return check_shift(d->shift, d->max_cycles, d->base_level + d->refine_levels, d->propose != nullptr);
 }

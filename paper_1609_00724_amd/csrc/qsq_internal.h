@@ -27,12 +27,13 @@ constexpr int kLandFace = 0x70;
 // Grid geometry as the kernels see it.
 struct Geom {
     int n[3];          // nodes per axis
-    int pad;
+    int geometry;      // QSQ_GEOMETRY_*
     double o[3];       // origin
     double h[3];       // spacing
     double ih[3];      // 1 / spacing
     double lo[3];      // closed box
     double hi[3];
+    const double *coord[3];   // rectilinear axes: node coordinates (device), else null
 };
 
 struct StepOpts {
@@ -159,12 +160,14 @@ hipError_t launch_trace_batch(const TraceJob &job, const SetDesc *host_sets, int
                               hipStream_t stream);
 
 // Field preparation.
-// Internal mode of a trace job: the field's interpolation mode in bit 0 and
-// its interpolation order - 1 above it.
+// Internal mode of a trace job: the field's interpolation mode in bit 0, its
+// interpolation order - 1 in bits 1-2, and bit 3 for the general geometry
+// (spherical coordinates or rectilinear axes).
 inline int job_mode(const qsq_field *f)
 {
     const int order = f->order > 1 ? f->order : 1;
-    return f->mode | ((order - 1) << 1);
+    const bool geo = f->geometry != QSQ_GEOMETRY_CARTESIAN || f->coords[0] || f->coords[1] || f->coords[2];
+    return f->mode | ((order - 1) << 1) | (geo ? 8 : 0);
 }
 // Cell records (8 corner records per cell) copied from a prepared field's nodes.
 uint64_t cell_record_bytes(const qsq_grid *g, int storage);

@@ -122,7 +122,7 @@ __device__ __forceinline__ void cell_of(int ib, T q, int n, int &c, T &t)
 // (QSQ_INTERP_*), the bits above hold order - 1.
 // ---------------------------------------------------------------------------
 template <int MODE>
-constexpr int interp_order() { return (MODE >> 1) + 1; }
+constexpr int interp_order() { return ((MODE >> 1) & 3) + 1; }
 template <int MODE>
 constexpr bool normalize_first() { return (MODE & 1) == QSQ_INTERP_PAPER; }
 
@@ -257,10 +257,10 @@ __device__ __forceinline__ void stencil_sum(const S *__restrict__ nodes, const G
 // u, the physical gradient rows and |B| from the interpolated components
 // (value and grid-unit derivatives; val[3] = interpolated |B| in PAPER mode)
 template <typename T, int MODE, bool MAG>
-__device__ __forceinline__ void field_finish(const Geom &g, const T val[4], const T dx[4], const T dy[4],
+__device__ __forceinline__ void field_finish(const double ih[3], const T val[4], const T dx[4], const T dy[4],
                                              const T dz[4], T u[3], T G[3][3], T &mag)
 {
-    const T ihx = (T)g.ih[0], ihy = (T)g.ih[1], ihz = (T)g.ih[2];
+    const T ihx = (T)ih[0], ihy = (T)ih[1], ihz = (T)ih[2];
     if (normalize_first<MODE>()) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -316,7 +316,7 @@ __device__ __forceinline__ void field_at(const S *__restrict__ nodes, const Geom
         // |B| is the 4th component in PAPER mode; INTERP_NORMALIZE takes |interpolated B|
         constexpr int NC = (MAG && normalize_first<MODE>()) ? 4 : 3;
         stencil_sum<K, NC, T, S>(nodes, g, s0, w, dw, val, dx, dy, dz);
-        field_finish<T, MODE, MAG>(g, val, dx, dy, dz, u, G, mag);
+        field_finish<T, MODE, MAG>(g.ih, val, dx, dy, dz, u, G, mag);
         return;
     }
     int64_t o[8];
@@ -344,7 +344,7 @@ __device__ __forceinline__ void field_at(const S *__restrict__ nodes, const Geom
     if (MAG && normalize_first<MODE>())
         val[3] = lerp_val<T>((T)n000.w, (T)n100.w, (T)n010.w, (T)n110.w, (T)n001.w, (T)n101.w, (T)n011.w,
                              (T)n111.w, t[0], t[1], t[2]);
-    field_finish<T, MODE, MAG>(g, val, dx, dy, dz, u, G, mag);
+    field_finish<T, MODE, MAG>(g.ih, val, dx, dy, dz, u, G, mag);
 }
 
 // The interpolated direction u alone (no gradient): the same operations as
@@ -689,11 +689,101 @@ __device__ __forceinline__ T rhs_step(const S *__restrict__ nodes, __amdgpu_buff
         return rhs<T, S, MODE, GATHER == kGatherCells>(nodes, g, ib, q, sigma, d1, d2, kx, k1, k2);
 }
 
+// ---------------------------------------------------------------------------
+// General geometry (Sect. 3.1-3.2): spherical coordinates (longitude phi,
+// latitude theta, radius r; field components in the local orthonormal basis)
+// and rectilinear axes whose cells have spans of their own.  MODE bit 3.
+// These fields are stepped in physical coordinates by k_trace_geo and landed
+// by k_land_geo; the seed pass and the Q assembly are shared.
+// ---------------------------------------------------------------------------
+template <int MODE>
+constexpr bool geo_mode() { return (MODE & 8) != 0; }
+
+// cell, fraction of the cell and the cell's span per axis at a physical point;
+// a rectilinear axis is searched by bisection for the last cell whose lower
+// node lies at or below the point (clamped to the grid's cells)
+__device__ __forceinline__ void geo_cell(const Geom &g, const double x[3], int c[3], double t[3], double h[3])
+{
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double *X = g.coord[d];
+        const int n = g.n[d];
+        if (X) {
+            const double xv = fmax(x[d], -1e300);   // NaN -> the lowest cell
+            int lo = 0, hi = n - 2;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (X[mid] <= xv)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            c[d] = lo;
+            h[d] = X[lo + 1] - X[lo];
+            t[d] = (x[d] - X[lo]) / h[d];
+        } else {
+            const double sg = fmin(fmax((x[d] - g.o[d]) * g.ih[d], -1e9), 1e9);
+            double fl = floor(sg);
+            fl = fl < 0.0 ? 0.0 : (fl > (double)(n - 2) ? (double)(n - 2) : fl);
+            c[d] = (int)fl;
+            t[d] = sg - fl;
+            h[d] = g.h[d];
+        }
+    }
+}
+
+// trilinear value and physical gradient at a physical point
+template <typename T, typename S, int MODE, bool MAG>
+__device__ __forceinline__ void field_at_geo(const S *__restrict__ nodes, const Geom &g, const double x[3], T u[3],
+                                             T G[3][3], T &mag)
+{
+    int c[3];
+    double t64[3], h[3];
+    geo_cell(g, x, c, t64, h);
+    const T t[3] = {(T)t64[0], (T)t64[1], (T)t64[2]};
+    const double ih[3] = {1.0 / h[0], 1.0 / h[1], 1.0 / h[2]};
+    const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
+    const int64_t b = (int64_t)c[2] * sz + (int64_t)c[1] * sy + c[0];
+    const auto n000 = ld4(nodes, b), n100 = ld4(nodes, b + 1);
+    const auto n010 = ld4(nodes, b + sy), n110 = ld4(nodes, b + sy + 1);
+    const auto n001 = ld4(nodes, b + sz), n101 = ld4(nodes, b + sz + 1);
+    const auto n011 = ld4(nodes, b + sz + sy), n111 = ld4(nodes, b + sz + sy + 1);
+    T val[4], dx[4], dy[4], dz[4];
+#define QSQ_COMPG(F, k)                                                                             \
+    lerp_tree<T>((T)n000.F, (T)n100.F, (T)n010.F, (T)n110.F, (T)n001.F, (T)n101.F, (T)n011.F,       \
+                 (T)n111.F, t[0], t[1], t[2], val[k], dx[k], dy[k], dz[k])
+    QSQ_COMPG(x, 0);
+    QSQ_COMPG(y, 1);
+    QSQ_COMPG(z, 2);
+#undef QSQ_COMPG
+    if (MAG && normalize_first<MODE>())
+        val[3] = lerp_val<T>((T)n000.w, (T)n100.w, (T)n010.w, (T)n110.w, (T)n001.w, (T)n101.w, (T)n011.w,
+                             (T)n111.w, t[0], t[1], t[2]);
+    field_finish<T, MODE, MAG>(ih, val, dx, dy, dz, u, G, mag);
+}
+
+// metric factors of eq. (2) and (8) at a physical point: (r cos theta, r, 1)
+// in spherical geometry, ones otherwise
+__device__ __forceinline__ void geo_scale(const Geom &g, const double x[3], double sc[3])
+{
+    if (g.geometry == QSQ_GEOMETRY_SPHERICAL) {
+        sc[0] = x[2] * cos(x[1]);
+        sc[1] = x[2];
+        sc[2] = 1.0;
+    } else {
+        sc[0] = sc[1] = sc[2] = 1.0;
+    }
+}
+
 // FP64 evaluation at a physical point (landing, assembly, seed frame)
 template <typename S, int MODE, bool MAG>
 __device__ __forceinline__ void field_at_x(const S *__restrict__ nodes, const Geom &g, const double x[3],
                                            double u[3], double G[3][3], double &mag)
 {
+    if constexpr (geo_mode<MODE>()) {
+        field_at_geo<double, S, MODE, MAG>(nodes, g, x, u, G, mag);
+        return;
+    }
     int ib[3];
     double q[3];
 #pragma unroll
@@ -814,9 +904,11 @@ __global__ void __launch_bounds__(256) k_seed_pass(TraceJob job)
                 const double nn[3] = {u[0] / un, u[1] / un, u[2] / un};
                 double a[3], b[3];
                 frame_of(nn, a, b);
+                double sc[3] = {1.0, 1.0, 1.0};
+                if constexpr (geo_mode<MODE>()) geo_scale(g, x0, sc);   // eq. (8) inverted
                 for (int k = 0; k < 3; ++k) {
-                    y0[3 + k] = a[k];
-                    y0[6 + k] = b[k];
+                    y0[3 + k] = a[k] / sc[k];
+                    y0[6 + k] = b[k] / sc[k];
                 }
                 for (int dir = 0; dir < 2; ++dir) {
                     const double sg = dir ? -1.0 : 1.0;
@@ -1705,6 +1797,18 @@ __global__ void __launch_bounds__(256) k_assemble(TraceJob job)
                 uF[k] /= nF;
                 uB[k] /= nB;
             }
+            if constexpr (geo_mode<MODE>()) {
+                // the deviations as lengths at each end, eq. (8)
+                double scF[3], scB[3];
+                geo_scale(g, yF, scF);
+                geo_scale(g, yB, scB);
+                for (int k = 0; k < 3; ++k) {
+                    yF[3 + k] *= scF[k];
+                    yF[6 + k] *= scF[k];
+                    yB[3 + k] *= scB[k];
+                    yB[6 + k] *= scB[k];
+                }
+            }
             // perpendicular parts of the deviations at both ends (Sect. 3.5)
             double aF[3], bF[3], aB[3], bB[3];
             const double pa = dot3(uF, yF + 3), pb = dot3(uF, yF + 6);
@@ -1736,6 +1840,322 @@ __global__ void __launch_bounds__(256) k_assemble(TraceJob job)
         if (o_qp) o_qp[li] = qp;
         if (o_qd) o_qd[li] = qd;
         if (o_qf) o_qf[li] = qf;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// General geometry: stepping and landing in physical coordinates
+// ---------------------------------------------------------------------------
+// f(y) of eq. (1)+(5) (Cartesian) or eq. (2)+(6) (spherical: the metric factors
+// divide each component) at the physical point x; returns |u|^2
+template <typename T, typename S, int MODE>
+__device__ __forceinline__ T rhs_geo(const S *__restrict__ nodes, const Geom &g, const double x[3], T sigma,
+                                     const T d1[3], const T d2[3], T kx[3], T k1[3], T k2[3])
+{
+    T u[3], G[3][3], mag;
+    field_at_geo<T, S, MODE, false>(nodes, g, x, u, G, mag);
+    const T un2 = rhs_from(sigma, u, G, d1, d2, kx, k1, k2);
+    if (g.geometry == QSQ_GEOMETRY_SPHERICAL) {
+        double sc[3];
+        geo_scale(g, x, sc);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const T m = (T)(1.0 / sc[i]);
+            kx[i] *= m;
+            k1[i] *= m;
+            k2[i] *= m;
+        }
+    }
+    return un2;
+}
+
+// one FP64 Cash-Karp step of the whole state in physical coordinates (5th-order end)
+template <typename S, int MODE>
+__device__ void ck54_geo(const S *__restrict__ nodes, const Geom &g, double sigma, const double y[9], double hs,
+                         double yo[9])
+{
+    double K[6][9];
+    const double A[6][5] = {{0, 0, 0, 0, 0},
+                            {ck::a21, 0, 0, 0, 0},
+                            {ck::a31, ck::a32, 0, 0, 0},
+                            {ck::a41, ck::a42, ck::a43, 0, 0},
+                            {ck::a51, ck::a52, ck::a53, ck::a54, 0},
+                            {ck::a61, ck::a62, ck::a63, ck::a64, ck::a65}};
+#pragma unroll 1
+    for (int st = 0; st < 6; ++st) {
+        double yt[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            double a = 0;
+            for (int j = 0; j < st; ++j) a = fma(A[st][j], K[j][i], a);
+            yt[i] = fma(hs, a, y[i]);
+        }
+        double kx[3], k1[3], k2[3];
+        rhs_geo<double, S, MODE>(nodes, g, yt, sigma, yt + 3, yt + 6, kx, k1, k2);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            K[st][i] = kx[i];
+            K[st][3 + i] = k1[i];
+            K[st][6 + i] = k2[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        yo[i] = y[i] + hs * (ck::b1 * K[0][i] + ck::b3 * K[2][i] + ck::b4 * K[3][i] + ck::b6 * K[5][i]);
+}
+
+// Adaptive Cash-Karp 5(4) stepping of general-geometry half-lines: one lane
+// per half-line, items taken one at a time from the work counter; the same
+// error norm, controller, limits and statuses as the uniform-grid kernel,
+// positions held in FP64, stage arithmetic in T.
+template <typename T, typename S, int MODE>
+__global__ void __launch_bounds__(256) k_trace_geo(TraceJob job)
+{
+    const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
+    const Geom g = job.g;
+    const StepOpts &o = job.o;
+    const int64_t total = *job.rec.n_work;
+    const int64_t P = 2 * job.rec.cap;
+    const T rtol = (T)o.rtol, atol = (T)o.atol;
+    unsigned long long c_att = 0, c_ev = 0, c_act = 0, c_land = 0;
+    for (;;) {
+        const int64_t it = (int64_t)atomicAdd(job.counter, 1ull);
+        if (it >= total) break;
+        const int64_t rec = job.rec.work[it];
+        const T sigma = rec >= job.rec.cap ? (T)-1 : (T)1;
+        double X[3];
+        T D1[3], D2[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            X[k] = job.rec.y[k * P + rec];
+            D1[k] = (T)job.rec.y[(3 + k) * P + rec];
+            D2[k] = (T)job.rec.y[(6 + k) * P + rec];
+        }
+        double s = 0.0;
+        T h = (T)o.h_init;
+        int attempts = 0, stop = -1;
+        ++c_act;
+        for (;;) {
+            if (attempts >= o.max_steps) {
+                stop = QSQ_END_MAX_STEPS;
+                break;
+            }
+            T K[6][9];
+            // first stage (also the null test at the current point)
+            {
+                T kx[3], k1[3], k2[3];
+                const T un2 = rhs_geo<T, S, MODE>(nodes, g, X, sigma, D1, D2, kx, k1, k2);
+                ++c_ev;
+                if (un2 < (T)1e-12) {
+                    stop = QSQ_END_NULL;
+                    break;
+                }
+                for (int i = 0; i < 3; ++i) {
+                    K[0][i] = kx[i];
+                    K[0][3 + i] = k1[i];
+                    K[0][6 + i] = k2[i];
+                }
+            }
+            T hs = h < (T)o.h_max ? h : (T)o.h_max;
+            bool last = false;
+            if (o.max_length > 0.0 && (double)hs >= o.max_length - s) {
+                hs = (T)(o.max_length - s);
+                last = true;
+            }
+            const double A[6][5] = {{0, 0, 0, 0, 0},
+                                    {ck::a21, 0, 0, 0, 0},
+                                    {ck::a31, ck::a32, 0, 0, 0},
+                                    {ck::a41, ck::a42, ck::a43, 0, 0},
+                                    {ck::a51, ck::a52, ck::a53, ck::a54, 0},
+                                    {ck::a61, ck::a62, ck::a63, ck::a64, ck::a65}};
+#pragma unroll 1
+            for (int st = 1; st < 6; ++st) {
+                double xs[3];
+                T d1[3], d2[3];
+                for (int i = 0; i < 3; ++i) {
+                    T ax = 0, a1 = 0, a2 = 0;
+                    for (int j = 0; j < st; ++j) {
+                        ax = fma((T)A[st][j], K[j][i], ax);
+                        a1 = fma((T)A[st][j], K[j][3 + i], a1);
+                        a2 = fma((T)A[st][j], K[j][6 + i], a2);
+                    }
+                    xs[i] = X[i] + (double)(hs * ax);
+                    d1[i] = fma(hs, a1, D1[i]);
+                    d2[i] = fma(hs, a2, D2[i]);
+                }
+                T kx[3], k1[3], k2[3];
+                rhs_geo<T, S, MODE>(nodes, g, xs, sigma, d1, d2, kx, k1, k2);
+                ++c_ev;
+                for (int i = 0; i < 3; ++i) {
+                    K[st][i] = kx[i];
+                    K[st][3 + i] = k1[i];
+                    K[st][6 + i] = k2[i];
+                }
+            }
+            double Xn[3];
+            T D1n[3], D2n[3], err = 0, fsum = 0;
+            for (int i = 0; i < 9; ++i) {
+                const T b5 = ck_b5(K[0][i], K[2][i], K[3][i], K[5][i]);
+                const T e = ck_e(K[0][i], K[2][i], K[3][i], K[4][i], K[5][i]);
+                T yo, yn;
+                if (i < 3) {
+                    Xn[i] = X[i] + (double)(hs * b5);
+                    yo = (T)X[i];
+                    yn = (T)Xn[i];
+                } else if (i < 6) {
+                    D1n[i - 3] = fma(hs, b5, D1[i - 3]);
+                    yo = D1[i - 3];
+                    yn = D1n[i - 3];
+                } else {
+                    D2n[i - 6] = fma(hs, b5, D2[i - 6]);
+                    yo = D2[i - 6];
+                    yn = D2n[i - 6];
+                }
+                err = fmax(err, fabs(hs * e) / err_scale(atol, rtol, yo, yn));
+                fsum += yn + e;
+            }
+            ++attempts;
+            ++c_att;
+            if (!isfinite(fsum)) {
+                stop = QSQ_END_NONFINITE;
+                break;
+            }
+            if (err > (T)1) {
+                const T f = (T)0.9 * (T)pow((double)err, -0.25);
+                h = hs * (f > (T)0.2 ? f : (T)0.2);
+                if ((double)h < o.hmin) {
+                    stop = QSQ_END_UNDERFLOW;
+                    break;
+                }
+                continue;
+            }
+            if (outside_box(g, Xn[0], Xn[1], Xn[2])) {
+                const double y[9] = {X[0], X[1], X[2], (double)D1[0], (double)D1[1], (double)D1[2],
+                                     (double)D2[0], (double)D2[1], (double)D2[2]};
+                put_rec(job.rec, rec, y, s, (double)hs, kPendingLand, attempts);
+                ++c_land;
+                break;
+            }
+            for (int i = 0; i < 3; ++i) {
+                X[i] = Xn[i];
+                D1[i] = D1n[i];
+                D2[i] = D2n[i];
+            }
+            if (last) {
+                s = o.max_length;
+                stop = QSQ_END_MAX_LENGTH;
+                break;
+            }
+            s += (double)hs;
+            const T f = err > (T)0 ? (T)0.9 * (T)pow((double)err, -0.2) : (T)5;
+            h = hs * (f < (T)5 ? f : (T)5);
+        }
+        if (stop >= 0) {
+            const double y[9] = {X[0], X[1], X[2], (double)D1[0], (double)D1[1], (double)D1[2],
+                                 (double)D2[0], (double)D2[1], (double)D2[2]};
+            put_rec(job.rec, rec, y, s, 0.0, stop, attempts);
+        }
+    }
+    if (job.work) {
+        atomicAdd(&job.work[0], c_att);
+        atomicAdd(&job.work[1], c_ev);
+        atomicAdd(&job.work[2], c_act);
+        atomicAdd(&job.work[3], c_land);
+    }
+}
+
+// signed distance past face f of the FP64 step's end from y over length h
+template <typename S, int MODE>
+__device__ double face_gap_geo(const S *nodes, const Geom &g, double sigma, const double y[9], double h, int f,
+                               double yo[9])
+{
+    if (h > 0.0) {
+        ck54_geo<S, MODE>(nodes, g, sigma, y, h, yo);
+    } else {
+        for (int k = 0; k < 9; ++k) yo[k] = y[k];
+    }
+    return beyond_face(g, yo, f);
+}
+
+// FP64 landing of general-geometry half-lines: for every face the trial step
+// crosses, Illinois regula falsi from the secant point on the face gap of the
+// FP64 step's end over its length (|gap| <= gtol); the face reached first (the
+// shortest length; exact ties keep the lower face) takes the line, the state
+// is stepped there and snapped onto the face
+template <typename S, int MODE>
+__global__ void __launch_bounds__(256) k_land_geo(TraceJob job)
+{
+    const int64_t total = *job.rec.n_land;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+         it += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = job.rec.work2[it];
+        const S *__restrict__ nodes = static_cast<const S *>(job.nodes);
+        const Geom &g = job.g;
+        const double gtol = job.o.gtol;
+        const double sigma = r >= job.rec.cap ? -1.0 : 1.0;
+        double y[9], s, hs, yo[9];
+        get_rec(job.rec, r, y, s, hs);
+        ck54_geo<S, MODE>(nodes, g, sigma, y, hs, yo);
+        double best = INFINITY;
+        int face = -1;
+        for (int f = 0; f < 6; ++f) {
+            if (!(beyond_face(g, yo, f) > 0.0)) continue;
+            double a = 0.0, b = hs, ga = face_gap_geo<S, MODE>(nodes, g, sigma, y, a, f, yo), gb, root;
+            if (ga >= 0.0) {
+                root = 0.0;
+            } else {
+                gb = face_gap_geo<S, MODE>(nodes, g, sigma, y, b, f, yo);
+                int side = 0;
+                root = -1.0;
+                for (int k = 0; k < 200 && root < 0.0; ++k) {
+                    const double c = (a * gb - b * ga) / (gb - ga);
+                    const double gc = face_gap_geo<S, MODE>(nodes, g, sigma, y, c, f, yo);
+                    if (fabs(gc) <= gtol) {
+                        root = c;
+                    } else if (gc > 0.0) {
+                        b = c;
+                        gb = gc;
+                        if (side == +1) ga *= 0.5;
+                        side = +1;
+                    } else {
+                        a = c;
+                        ga = gc;
+                        if (side == -1) gb *= 0.5;
+                        side = -1;
+                    }
+                    if (root < 0.0 && b - a <= 1e-15 * hs) root = ga > -gb ? a : b;
+                }
+                if (root < 0.0) root = ga > -gb ? a : b;
+            }
+            if (root < best) {
+                best = root;
+                face = f;
+            }
+        }
+        if (face < 0) {
+            // the trial step left the box in FP32 but the FP64 step does not:
+            // end on the face nearest the FP64 end
+            best = hs;
+            double gmax = -INFINITY;
+            for (int f = 0; f < 6; ++f) {
+                const double gp = beyond_face(g, yo, f);
+                if (gp > gmax) {
+                    gmax = gp;
+                    face = f;
+                }
+            }
+        }
+        double yl[9];
+        if (best > 0.0) {
+            ck54_geo<S, MODE>(nodes, g, sigma, y, best, yl);
+        } else {
+            for (int k = 0; k < 9; ++k) yl[k] = y[k];
+        }
+        const int d = face >> 1;
+        const double snap = (face & 1) ? pick3(g.hi, d) : pick3(g.lo, d);
+        for (int k = 0; k < 3; ++k)
+            if (k == d) yl[k] = snap;
+        put_rec(job.rec, r, yl, s + best, 0.0, face, job.rec.attempts[r]);
     }
 }
 
@@ -1942,16 +2362,58 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
 // higher interpolation orders: one field per call, FP32 or FP64 node records;
 // each (order, mode) pair is instantiated in a translation unit of its own,
 // so that the build compiles them side by side
+// general geometry: seed pass, stepping in physical coordinates, FP64
+// landing, the shared Q assembly
+template <typename T, typename S, int MODE>
+static hipError_t launch_geo(const TraceJob &job, hipStream_t st)
+{
+    const int cus = device_cu_count();
+    const int64_t n_max = job.n_dev ? job.rec.cap : job.n_host;
+    if (n_max <= 0) return hipSuccess;
+    auto blocks_of = [&](int64_t items) {
+        const int64_t b = (items + 255) / 256;
+        return (int)(b < (int64_t)cus * 16 ? b : (int64_t)cus * 16);
+    };
+    hipLaunchKernelGGL((k_seed_pass<S, MODE, false>), dim3(blocks_of(n_max)), dim3(256), 0, st, job);
+    launch_scan_i32(job.rec.flag, job.rec.n_items, 2 * n_max, job.rec.scan_tmp, job.rec.wpos, job.rec.n_work, st);
+    hipLaunchKernelGGL(k_compact, dim3(blocks_of(2 * n_max)), dim3(256), 0, st, job);
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, job.counter, 0ull);
+    const bool prof = profiling();
+    void *tok = nullptr;
+    if (prof) prof_begin(kProfStep, st, &tok);
+    hipLaunchKernelGGL((k_trace_geo<T, S, MODE>), dim3(cus * 8), dim3(256), 0, st, job);
+    if (prof) prof_end(tok, st);
+    if (prof) prof_begin(kProfLand, st, &tok);
+    hipLaunchKernelGGL(k_land_flags, dim3(blocks_of(2 * n_max)), dim3(256), 0, st, job);
+    launch_scan_i32(job.rec.flag, job.rec.n_items, 2 * n_max, job.rec.scan_tmp, job.rec.wpos, job.rec.n_land, st);
+    hipLaunchKernelGGL(k_land_compact, dim3(blocks_of(2 * n_max)), dim3(256), 0, st, job);
+    hipLaunchKernelGGL((k_land_geo<S, MODE>), dim3(blocks_of(2 * n_max)), dim3(256), 0, st, job);
+    if (prof) prof_end(tok, st);
+    if (prof) prof_begin(kProfAssemble, st, &tok);
+    hipLaunchKernelGGL((k_assemble<S, MODE, false>), dim3(blocks_of(n_max)), dim3(256), 0, st, job);
+    if (prof) prof_end(tok, st);
+    return hipGetLastError();
+}
+
 template <int MODE>
 hipError_t launch_trace_mode(const TraceJob &job, int step_dtype, hipStream_t st)
 {
     const bool f32 = step_dtype == QSQ_F32;
-    if (job.storage == QSQ_F32)
-        return f32 ? launch_typed<float, float, MODE, false>(job, st) : launch_typed<double, float, MODE, false>(job, st);
-    if (job.storage == QSQ_F64)
-        return f32 ? launch_typed<float, double, MODE, false>(job, st)
-                   : launch_typed<double, double, MODE, false>(job, st);
-    return hipErrorNotSupported;
+    if constexpr (geo_mode<MODE>()) {
+        if (job.storage == QSQ_F32)
+            return f32 ? launch_geo<float, float, MODE>(job, st) : launch_geo<double, float, MODE>(job, st);
+        if (job.storage == QSQ_F64)
+            return f32 ? launch_geo<float, double, MODE>(job, st) : launch_geo<double, double, MODE>(job, st);
+        return hipErrorNotSupported;
+    } else {
+        if (job.storage == QSQ_F32)
+            return f32 ? launch_typed<float, float, MODE, false>(job, st)
+                       : launch_typed<double, float, MODE, false>(job, st);
+        if (job.storage == QSQ_F64)
+            return f32 ? launch_typed<float, double, MODE, false>(job, st)
+                       : launch_typed<double, double, MODE, false>(job, st);
+        return hipErrorNotSupported;
+    }
 }
 
 template hipError_t launch_trace_mode<QSQ_TRACE_HIGH_MODE>(const TraceJob &job, int step_dtype, hipStream_t st);
@@ -1974,6 +2436,8 @@ static hipError_t dispatch(const TraceJob &job, int step_dtype, hipStream_t st)
             case 3: return launch_trace_mode<3>(job, step_dtype, st);
             case 4: return launch_trace_mode<4>(job, step_dtype, st);
             case 5: return launch_trace_mode<5>(job, step_dtype, st);
+            case 8: return launch_trace_mode<8>(job, step_dtype, st);
+            case 9: return launch_trace_mode<9>(job, step_dtype, st);
             default: return hipErrorNotSupported;
             }
         }

@@ -261,3 +261,29 @@ def flux_rope_c4(n=(384, 384, 256), dtype=np.float32, device=None):
     b, meta = flux_rope_field(n, dtype=dtype, device=device)
     origin, spacing = grid_geometry(n)
     return dict(b=b, origin=origin, spacing=spacing, n=n, **meta)
+
+
+def sample_charges_spherical(charges, n, lo, hi, dtype=np.float64):
+    """The point-charge field on a (longitude, latitude, radius) grid of n =
+    (n_phi, n_theta, n_r) nodes spanning [lo, hi], as the components (B_phi,
+    B_theta, B_r) in the local orthonormal basis, arrays shaped (n_r, n_theta,
+    n_phi).  Returns (b, origin, spacing)."""
+    axes = [np.linspace(lo[d], hi[d], n[d]) for d in range(3)]
+    R, TH, PH = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    X = R * np.cos(TH) * np.cos(PH)
+    Y = R * np.cos(TH) * np.sin(PH)
+    Z = R * np.sin(TH)
+    B = [np.zeros_like(X) for _ in range(3)]
+    for cx, cy, cz, q in charges:
+        dx, dy, dz = X - cx, Y - cy, Z - cz
+        inv3 = q / (dx * dx + dy * dy + dz * dz) ** 1.5
+        B[0] += dx * inv3
+        B[1] += dy * inv3
+        B[2] += dz * inv3
+    e_phi = (-np.sin(PH), np.cos(PH), 0.0 * PH)
+    e_th = (-np.sin(TH) * np.cos(PH), -np.sin(TH) * np.sin(PH), np.cos(TH))
+    e_r = (np.cos(TH) * np.cos(PH), np.cos(TH) * np.sin(PH), np.sin(TH))
+    comp = [sum(B[k] * e[k] for k in range(3)).astype(dtype) for e in (e_phi, e_th, e_r)]
+    origin = tuple(float(lo[d]) for d in range(3))
+    spacing = tuple((hi[d] - lo[d]) / (n[d] - 1) for d in range(3))
+    return comp, origin, spacing

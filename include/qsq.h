@@ -387,7 +387,10 @@ typedef struct qsq_map_desc {
                               orientation corner + s edge_u + t edge_v, s, t in [0, 1]
                               (Sect. 2), pixel (i, j) of level L at s = (i + 1/2) / 2^L,
                               t = (j + 1/2) / 2^L (z0, x0, x1, y0, y1 unused) */
-    int32_t pad;
+    int32_t base_given;    /* 1: out->fll, q_perp and status (and steps) already hold the
+                              base lattice's 4^m samples in level-m curve order -- e.g. a
+                              map of the same slice with refine_levels 0 -- and are not
+                              traced again; their keys are rewritten to q 4^r + 4^r/2 */
     double corner[3], edge_u[3], edge_v[3];
 } qsq_map_desc;
 

@@ -88,7 +88,7 @@ class MapDesc(C.Structure):
                 ("y1", C.c_double), ("base_level", C.c_int32), ("refine_levels", C.c_int32),
                 ("out_level", C.c_int32), ("refine_batch", C.c_int32), ("threshold", C.c_double),
                 ("propose", C.c_void_p), ("shift", C.c_int32), ("max_cycles", C.c_int32),
-                ("tilted", C.c_int32), ("pad", C.c_int32), ("corner", C.c_double * 3), ("edge_u", C.c_double * 3),
+                ("tilted", C.c_int32), ("base_given", C.c_int32), ("corner", C.c_double * 3), ("edge_u", C.c_double * 3),
                 ("edge_v", C.c_double * 3)]
 
 

@@ -378,10 +378,30 @@ class QMapPlan:
         o.steps = _p(self.steps)
         self.mout = o
 
-    def run(self, field: Field, opts: A.TraceOpts, stream=None):
+    def run(self, field: Field, opts: A.TraceOpts, stream=None, base_from=None):
+        """Enqueue the map.  base_from: a slice plan of the same slice and base
+        level with no refinement levels whose result holds the base lattice;
+        its samples are copied in and not traced again."""
         fn = lib.qsq_vmap if self.dims == 3 else lib.qsq_qmap
-        check(fn(C.byref(field.desc), C.byref(self.d), C.byref(opts), C.byref(self.mout),
-                 _p(self.scratch), self.scratch.numel() * 8, _stream(stream)))
+        if base_from is not None:
+            if self.dims != 2 or base_from.spec.base_level != self.spec.base_level or base_from.spec.refine_levels:
+                raise ValueError("base_from must be an unrefined slice map of the same base level")
+            nb = 4 ** self.spec.base_level
+            pairs = [(self.fll, base_from.fll), (self.q_perp, base_from.q_perp), (self.status, base_from.status)]
+            if self.steps is not None:
+                if base_from.steps is None:
+                    raise ValueError("base_from must keep the step attempts too")
+                pairs.append((self.steps, base_from.steps))
+            with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+                for a, b in pairs:
+                    a[:nb].copy_(b[:nb])
+            self.d.base_given = 1
+        try:
+            check(fn(C.byref(field.desc), C.byref(self.d), C.byref(opts), C.byref(self.mout),
+                     _p(self.scratch), self.scratch.numel() * 8, _stream(stream)))
+        finally:
+            if self.dims == 2:
+                self.d.base_given = 0
         return self
 
     def result(self):

@@ -330,6 +330,14 @@ __global__ void k_base_seeds(Region rg, int64_t nb, int64_t stride, double *seed
     }
 }
 
+// keys of a base lattice given by the caller (samples in level-m curve order)
+__global__ void k_base_keys(const Region rg, int64_t nb, uint64_t *keys, int dim)
+{
+    const uint64_t blk = (uint64_t)1 << (dim * rg.r);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nb; q += (int64_t)gridDim.x * blockDim.x)
+        keys[q] = (uint64_t)q * blk + blk / 2;
+}
+
 __global__ void k_set_count(int64_t *c, int64_t v, int32_t *overflow)
 {
     *c = v;
@@ -997,7 +1005,7 @@ static int planned_rounds(int levels, int batch, int64_t slots, int64_t first, i
 template <int DIM>
 static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &o, int step_dtype, Region rg,
                              int out_level, int refine_batch, const uint8_t *propose, int shift, int max_cycles,
-                             const qsq_map_out *out, void *scratch, hipStream_t st)
+                             bool base_given, const qsq_map_out *out, void *scratch, hipStream_t st)
 {
     const int64_t cap = out->capacity;
     const int m = rg.m, r = rg.r;
@@ -1038,17 +1046,24 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
     job.steps_sum = 1;
     job.work = reinterpret_cast<unsigned long long *>(out->work);
 
-    // base lattice
-    hipLaunchKernelGGL((k_base_seeds<DIM>), dim3(grid_for(nb)), dim3(256), 0, st, rg, nb, Lo.tcap, seeds, A.keys);
-    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, &counts[0], nb, out->overflow);
-    job.n_host = nb;
-    job.n_dev = nullptr;
-    job.fll = A.fll;
-    job.q_perp = A.q;
-    job.status = A.status;
-    job.steps = A.att;
-    hipError_t e = launch_trace(job, step_dtype, st);
-    if (e != hipSuccess) return e;
+    // base lattice (traced here, or given in the caller's arrays)
+    hipError_t e = hipSuccess;
+    if (base_given) {
+        hipLaunchKernelGGL(k_base_keys, dim3(grid_for(nb)), dim3(256), 0, st, rg, nb, A.keys, DIM);
+        hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, &counts[0], nb, out->overflow);
+    } else {
+        hipLaunchKernelGGL((k_base_seeds<DIM>), dim3(grid_for(nb)), dim3(256), 0, st, rg, nb, Lo.tcap, seeds,
+                           A.keys);
+        hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, &counts[0], nb, out->overflow);
+        job.n_host = nb;
+        job.n_dev = nullptr;
+        job.fll = A.fll;
+        job.q_perp = A.q;
+        job.status = A.status;
+        job.steps = A.att;
+        e = launch_trace(job, step_dtype, st);
+        if (e != hipSuccess) return e;
+    }
     if (out->fledge) {
         float *img = reinterpret_cast<float *>(base + Lo.img);
         hipLaunchKernelGGL((k_fll_raster<DIM>), dim3(grid_for(nb)), dim3(256), 0, st, rg, nb, A.fll, img);
@@ -1242,7 +1257,7 @@ hipError_t launch_qmap(const qsq_field *f, const Geom &g, const StepOpts &o, int
         }
     }
     return launch_map<2>(f, g, o, step_dtype, rg, d->out_level, d->refine_batch, d->propose, d->shift, d->max_cycles,
-                         out, scratch, st);
+                         d->base_given != 0, out, scratch, st);
 }
 
 hipError_t launch_vmap(const qsq_field *f, const Geom &g, const StepOpts &o, int step_dtype,
@@ -1260,7 +1275,7 @@ hipError_t launch_vmap(const qsq_field *f, const Geom &g, const StepOpts &o, int
     }
     rg.thr = d->threshold;
     return launch_map<3>(f, g, o, step_dtype, rg, d->out_level, d->refine_batch, d->propose, d->shift, d->max_cycles,
-                         out, scratch, st);
+                         false, out, scratch, st);
 }
 
 }  // namespace qsq

@@ -612,6 +612,7 @@ static int check_map(const qsq_map_desc *d)
         return fail(QSQ_ERR_INVALID_ARG, "slice extent must satisfy x1 > x0, y1 > y0, finite z0");
     }
     if (!(d->threshold >= 0.0)) return fail(QSQ_ERR_INVALID_ARG, "threshold must be >= 0");
+    if (d->base_given != 0 && d->base_given != 1) return fail(QSQ_ERR_INVALID_ARG, "base_given must be 0 or 1");
     return check_shift(d->shift, d->max_cycles, d->base_level + d->refine_levels, d->propose != nullptr);
 }
 

@@ -61,14 +61,24 @@ class Proposer:
             self._ws = _bytes_tensor(need, self.params.device)
         return self._ws
 
-    def forward(self, x: torch.Tensor, stream=None) -> torch.Tensor:
-        """x: (n, h, w, 3) float32 device tiles -> (n, h, w, 2) logits and log10 Q."""
+    def workspace(self, n, h, w) -> torch.Tensor:
+        """A workspace of its own for forward() on n tiles of h x w (for calls
+        that overlap on several streams)."""
+        return _bytes_tensor(lib.qsq_cnn_workspace_bytes(n, h, w), self.params.device)
+
+    def forward(self, x: torch.Tensor, stream=None, ws=None) -> torch.Tensor:
+        """x: (n, h, w, 3) float32 device tiles -> (n, h, w, 2) logits and log10 Q.
+        ws: a workspace from workspace() (default: one shared by the calls
+        on this object, which must then not overlap)."""
         x = x.contiguous()
         n, h, w, c = x.shape
         if c != 3 or x.dtype != torch.float32:
             raise ValueError("x must be float32 (n, h, w, 3)")
         out = torch.empty((n, h, w, 2), dtype=torch.float32, device=x.device)
-        ws = self._workspace(n, h, w)
+        if ws is None:
+            ws = self._workspace(n, h, w)
+        elif ws.numel() * 8 < lib.qsq_cnn_workspace_bytes(n, h, w):
+            raise ValueError("workspace too small")
         check(lib.qsq_cnn_forward(_p(self.prep), _p(x), n, h, w, _p(out), _p(ws), ws.numel() * 8, _stream(stream)))
         return out
 

@@ -115,6 +115,35 @@ def _sample_charges_torch(charges, n, lo, hi, dtype, device):
     return [a.cpu().numpy().astype(dtype) for a in acc]
 
 
+def charges_device(charges, n, device, base=None, lo=LO, hi=HI):
+    """sample_charges kept on `device`: FP64 sums (plus the FP64 device
+    tensors `base`, if given) cast to three FP32 torch tensors (nz, ny, nx)."""
+    import torch
+    f64 = dict(dtype=torch.float64, device=torch.device(device))
+    xs, ys, zs = (torch.tensor(c, **f64) for c in node_coords(n, lo, hi))
+    out = []
+    for comp in range(3):
+        acc = base[comp].clone() if base is not None else torch.zeros((n[2], n[1], n[0]), **f64)
+        for z0 in range(0, n[2], 32):
+            Z = zs[z0:z0 + 32, None, None]
+            for cx, cy, cz, q in np.asarray(charges, float):
+                dx, dy, dz = xs[None, None, :] - cx, ys[None, :, None] - cy, Z - cz
+                inv3 = q * (dx * dx + dy * dy + dz * dz) ** -1.5
+                acc[z0:z0 + 32] += (dx, dy, dz)[comp] * inv3
+        out.append(acc.float())
+        del acc
+    return out
+
+
+def rope_charges(seed: int, ring_radius=0.3, depth=0.1, leg_charge=1.5):
+    """Background charges of a flux-rope field: +leg_charge and -leg_charge
+    under the rope's two legs (x = +-sqrt(R^2 - depth^2), z = -depth) and four
+    drawn as point_charges(seed, 4)."""
+    xleg = float(np.sqrt(ring_radius ** 2 - depth ** 2))
+    legs = np.array([[xleg, 0.0, -depth, leg_charge], [-xleg, 0.0, -depth, -leg_charge]])
+    return np.vstack([legs, point_charges(seed, 4)])
+
+
 def pixel_seeds(nx, ny, z0=0.0, lo=LO, hi=HI):
     """Pixel centres of an nx x ny raster on the plane z = z0, raster order (x fastest)."""
     px = lo[0] + (np.arange(nx) + 0.5) * (hi[0] - lo[0]) / nx
@@ -196,10 +225,8 @@ def flux_rope_field(n, ring_radius=0.3, depth=0.1, minor=0.08, current=0.5, turn
     dev = torch.device(device) if device is not None else torch.device("cpu")
     f64 = dict(dtype=torch.float64, device=dev)
     R, zc, a = ring_radius, -depth, minor
-    xleg = float(np.sqrt(R * R - zc * zc))
     if charges is None:
-        legs = np.array([[xleg, 0.0, zc, leg_charge], [-xleg, 0.0, zc, -leg_charge]])
-        charges = np.vstack([legs, point_charges(4, 4)])
+        charges = rope_charges(4, ring_radius, depth, leg_charge)
     th = torch.arange(quad, **f64) * (2 * np.pi / quad)
     px, pz = R * torch.cos(th), zc + R * torch.sin(th)                  # ring points
     tx, tz = -R * torch.sin(th) * (2 * np.pi / quad), R * torch.cos(th) * (2 * np.pi / quad)   # dl

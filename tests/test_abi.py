@@ -250,3 +250,20 @@ def test_shifted_repass_arguments_rejected(qsq):
         assert any(w in qsq.lib.qsq_last_error() for w in (b"shift", b"proposals", b"max_cycles"))
     d.shift, d.max_cycles, d.propose = 5, 0, None
     assert qsq.lib.qsq_qmap_scratch_bytes(C.byref(d), 4 ** 6) > 0
+
+
+def test_base_given_flag_checked(qsq):
+    """base_given takes 0 or 1; any other value is refused before anything is
+    enqueued."""
+    from paper_1609_00724_amd import _abi as A
+    d = A.MapDesc()
+    d.x0, d.x1, d.y0, d.y1 = -1.0, 1.0, -1.0, 1.0
+    d.base_level, d.refine_levels, d.out_level, d.threshold = 4, 2, 4, 0.02
+    f = A.FieldDesc()
+    f.grid.n[:] = (8, 8, 8)
+    f.grid.spacing[:] = (1.0, 1.0, 1.0)
+    f.storage, f.mode, f.nodes, f.bytes = A.F32, A.INTERP_PAPER, 256, 8 ** 3 * 16
+    o = A.TraceOpts()
+    d.base_given = 2
+    rc = qsq.lib.qsq_qmap(C.byref(f), C.byref(d), C.byref(o), None, None, 0, None)
+    assert rc == A.ERR_INVALID_ARG and b"base_given" in qsq.lib.qsq_last_error()

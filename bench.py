@@ -101,6 +101,7 @@ def parse():
                     help="learned workload: maps generated (1/4 flux-rope slices)")
     ap.add_argument("--learn-epochs", type=int, default=12)
     ap.add_argument("--learn-streams", type=int, default=4, help="learned workload: streams the scored maps use")
+    ap.add_argument("--learn-batch", type=int, default=256, help="learned workload: tiles per training step")
     ap.add_argument("--learn-group", type=int, default=8, help="learned workload: maps in flight at once")
     ap.add_argument("--cpu-fraction", type=float, default=0.25,
                     help="batch workload: fraction of each field's seeds the oracle traces")
@@ -980,7 +981,7 @@ def bench_learned(args):
     for d in train:
         del d["x"], d["mask"], d["logq"]
     prop = learn.Proposer(learn.init_params(1, dev))
-    bs = 64
+    bs = args.learn_batch
     g = torch.Generator(device="cpu").manual_seed(0)
     curve = []
     t_train = time.perf_counter()

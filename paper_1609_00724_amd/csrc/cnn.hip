@@ -51,13 +51,17 @@ constexpr int kCi[4] = {3, 32, 32, 32};
 constexpr int kCo[4] = {32, 32, 32, 2};
 
 __host__ __device__ constexpr int ntile(int c) { return (c + 15) / 16; }
-__host__ __device__ constexpr int nchunk(int ci) { return ci >= 32 ? 9 : 1; }
+// channels per tap in the packed K layout of an input with fewer than 32
+// channels (3 is padded to 4 so that a tap's channels fill whole dwords)
+__host__ __device__ constexpr int cpad(int ci) { return ci == 3 ? 4 : ci; }
+__host__ __device__ constexpr int nchunk(int ci) { return ci >= 32 ? 9 : (9 * cpad(ci) + 31) / 32; }
 
 // ---------------------------------------------------------------------------
 // Prepared weights (BF16 matrices in MFMA-friendly order + FP32 biases)
 //   fwd[l]: [nchunk(Ci)][16 ntile(Co)][32]: element (kc, co, kk) multiplies
 //           input channel/tap (tap = kc, ci = kk) for Ci = 32, or
-//           (tap = k / Ci, ci = k % Ci, k = kk < 9 Ci) for Ci < 32
+//           (tap = k / cpad(Ci), ci = k % cpad(Ci), k = 32 kc + kk; zero
+//           where ci >= Ci or tap >= 9) for Ci < 32
 //   bwd[l] (l >= 1): the transposed, tap-flipped kernel of the input
 //           gradient, a convolution from Co channels to Ci = 32: element
 //           (kc, ci, kk) = W[flip(tap)][ci][c] with (tap, c) taken from
@@ -112,10 +116,10 @@ __global__ void k_prepare(const float *params, uint16_t *prep)
                 tap = kc;
                 ci = kk;
             } else {
-                tap = kk / Ci;
-                ci = kk % Ci;
+                tap = (32 * kc + kk) / cpad(Ci);
+                ci = (32 * kc + kk) % cpad(Ci);
             }
-            const bool ok = co < Co && tap < 9;
+            const bool ok = co < Co && tap < 9 && ci < Ci;
             prep[P.fwd[l] + e] = ok ? f2bf(W[((int64_t)tap * Ci + ci) * Co + co]) : (uint16_t)0;
         }
     }
@@ -131,10 +135,10 @@ __global__ void k_prepare(const float *params, uint16_t *prep)
                 tap = kc;
                 c = kk;
             } else {
-                tap = kk / Co;
-                c = kk % Co;
+                tap = (32 * kc + kk) / cpad(Co);
+                c = (32 * kc + kk) % cpad(Co);
             }
-            const bool ok = tap < 9 && ci < Ci;
+            const bool ok = tap < 9 && ci < Ci && c < Co;
             prep[P.bwd[l] + e] = ok ? f2bf(W[((int64_t)(8 - tap) * Ci + ci) * Co + c]) : (uint16_t)0;
         }
     }
@@ -148,25 +152,38 @@ __global__ void k_prepare(const float *params, uint16_t *prep)
 // ---------------------------------------------------------------------------
 // 3x3 'same' convolution, one wave per 16-pixel strip of kConvRows rows, all
 // output channels.  The wave keeps the weight operands in registers for its
-// rows and, for 32-channel inputs, a sliding window of the input operands
-// (three rows x three pixel shifts: each new output row loads one new input
-// row).  in: BF16 (32 channels) or, for CI < 32, FP32 / BF16 with CI
-// channels.  Outputs (each nullable): BF16 activations (ReLU applied), FP32
-// values, and a BF16 copy masked by act_mask > 0 (input gradients).
+// rows.  32-channel inputs (BF16): lane (i, kg) loads pixel x0 + i, channels
+// 8 kg .. 8 kg + 7, of each input row once; the operands shifted by one
+// pixel come from the neighbouring lanes of its row of 16 (DPP row shifts),
+// the edge pixels x0 - 1 and x0 + 16 from one halo load by lanes 0 and 15; a
+// window of three rows slides down the strip.  Inputs with CI < 32 channels
+// (FP32 with 3, BF16 with 2): the 9 taps' channels packed along K, cpad(CI)
+// per tap, each tap's channels fetched with one load.  Outputs (each
+// nullable): BF16 activations (ReLU applied), FP32 values, a BF16 copy masked
+// by mask_cm > 0 (input gradients; mask_cm is the channel-major copy of the
+// layer's input activations), and the channel-major copy of the BF16 output
+// (masked too when mask_cm is given).
 // ---------------------------------------------------------------------------
 struct ConvDims {
     int64_t n;
     int h, w;
 };
 
-constexpr int kConvRows = 4;   // divides h (a multiple of 32)
+constexpr int kConvRows = 8;   // divides h (a multiple of 32)
+
+struct Row3 {
+    bf16x8 m, z, p;   // the lane's pixel shifted by -1, 0, +1
+};
 
 template <int CI, int CO, bool SRC_F32>
-__global__ void __launch_bounds__(256) k_conv(const void *in, ConvDims d, const uint16_t *wm, const float *bias,
-                                              bool relu, uint16_t *out_bf, float *out_f32, uint16_t *out_masked,
-                                              const uint16_t *act_mask)
+__global__ void __launch_bounds__(256) k_conv(const void *__restrict__ in, ConvDims d,
+                                              const uint16_t *__restrict__ wm, const float *__restrict__ bias,
+                                              bool relu, uint16_t *__restrict__ out_bf, float *__restrict__ out_f32,
+                                              uint16_t *__restrict__ out_masked,
+                                              const uint16_t *__restrict__ mask_cm, uint16_t *__restrict__ out_cm)
 {
     constexpr int NT = ntile(CO), COP = 16 * NT, NK = nchunk(CI), R = kConvRows;
+    static_assert(CI >= 32 ? !SRC_F32 : (CI == 3) == SRC_F32, "FP32 input has 3 channels, BF16 input 2 or 32");
     const int lane = (int)(threadIdx.x & 63);
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int spr = d.w / 16, rb = d.h / R;
@@ -180,25 +197,35 @@ __global__ void __launch_bounds__(256) k_conv(const void *in, ConvDims d, const 
     for (int kc = 0; kc < NK; ++kc)
 #pragma unroll
         for (int t = 0; t < NT; ++t) bw[kc][t] = ld_bf16x8(wm + ((int64_t)(kc * COP + t * 16 + i) * 32 + 8 * kg));
-    // A operand of one input row yy at pixel shift dx (32 channels: lane i
-    // takes pixel x0 + i + dx, channels 8 kg .. 8 kg + 7)
-    auto a32 = [&](int yy, int dx) {
-        bf16x8 a;
-        const int xx = x0 + i + dx;
-        if (CI >= 32 && yy >= 0 && yy < d.h && xx >= 0 && xx < d.w) {
-            a = ld_bf16x8(static_cast<const uint16_t *>(in) + (((img * d.h + yy) * d.w + xx) * 32 + 8 * kg));
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) a[j] = as_bf(0);
+    // input row yy of a 32-channel input: the three shifted operands
+    auto row3 = [&](int yy) {
+        uint4 z = make_uint4(0, 0, 0, 0), hv = make_uint4(0, 0, 0, 0);
+        if (yy >= 0 && yy < d.h) {
+            const uint16_t *row = static_cast<const uint16_t *>(in) + (img * d.h + yy) * (int64_t)d.w * 32 + 8 * kg;
+            z = *reinterpret_cast<const uint4 *>(row + (int64_t)(x0 + i) * 32);
+            const int xh = i == 0 ? x0 - 1 : x0 + 16;
+            if ((i == 0 || i == 15) && xh >= 0 && xh < d.w) hv = *reinterpret_cast<const uint4 *>(row + (int64_t)xh * 32);
         }
-        return a;
+        // row_shr:1 (lane i takes lane i - 1; lane 0 keeps its halo), row_shl:1
+        // (lane i takes lane i + 1; lane 15 keeps its halo)
+        const uint4 m = make_uint4((uint32_t)__builtin_amdgcn_update_dpp((int)hv.x, (int)z.x, 0x111, 0xf, 0xf, false),
+                                   (uint32_t)__builtin_amdgcn_update_dpp((int)hv.y, (int)z.y, 0x111, 0xf, 0xf, false),
+                                   (uint32_t)__builtin_amdgcn_update_dpp((int)hv.z, (int)z.z, 0x111, 0xf, 0xf, false),
+                                   (uint32_t)__builtin_amdgcn_update_dpp((int)hv.w, (int)z.w, 0x111, 0xf, 0xf, false));
+        const uint4 p = make_uint4((uint32_t)__builtin_amdgcn_update_dpp((int)hv.x, (int)z.x, 0x101, 0xf, 0xf, false),
+                                   (uint32_t)__builtin_amdgcn_update_dpp((int)hv.y, (int)z.y, 0x101, 0xf, 0xf, false),
+                                   (uint32_t)__builtin_amdgcn_update_dpp((int)hv.z, (int)z.z, 0x101, 0xf, 0xf, false),
+                                   (uint32_t)__builtin_amdgcn_update_dpp((int)hv.w, (int)z.w, 0x101, 0xf, 0xf, false));
+        Row3 r;
+        r.m = __builtin_bit_cast(bf16x8, m);
+        r.z = __builtin_bit_cast(bf16x8, z);
+        r.p = __builtin_bit_cast(bf16x8, p);
+        return r;
     };
-    bf16x8 win[3][3];   // [input row y-1, y, y+1][dx + 1]
+    Row3 win[3];   // input rows y - 1, y, y + 1
     if constexpr (CI >= 32) {
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) win[r][dx] = a32(y0 - 1 + r, dx - 1);
+        win[0] = row3(y0 - 1);
+        win[1] = row3(y0);
     }
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
@@ -207,33 +234,43 @@ __global__ void __launch_bounds__(256) k_conv(const void *in, ConvDims d, const 
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
         if constexpr (CI >= 32) {
+            win[2] = row3(y + 1);
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) win[2][dx] = a32(y + 1, dx - 1);
+            for (int ty = 0; ty < 3; ++ty)
 #pragma unroll
-            for (int kc = 0; kc < 9; ++kc)
-#pragma unroll
-                for (int t = 0; t < NT; ++t) acc[t] = mfma(win[kc / 3][kc % 3], bw[kc][t], acc[t]);
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                win[0][dx] = win[1][dx];
-                win[1][dx] = win[2][dx];
-            }
-        } else {
-            // all 9 taps of the CI input channels packed into one K chunk
-            bf16x8 a;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = 8 * kg + j, tap = k / CI, c = k % CI;
-                const int yy = y + tap / 3 - 1, xx = x0 + i + tap % 3 - 1;
-                uint16_t v = 0;
-                if (tap < 9 && yy >= 0 && yy < d.h && xx >= 0 && xx < d.w) {
-                    const int64_t e = ((img * d.h + yy) * d.w + xx) * CI + c;
-                    v = SRC_F32 ? f2bf(static_cast<const float *>(in)[e]) : static_cast<const uint16_t *>(in)[e];
+                for (int t = 0; t < NT; ++t) {
+                    acc[t] = mfma(win[ty].m, bw[3 * ty + 0][t], acc[t]);
+                    acc[t] = mfma(win[ty].z, bw[3 * ty + 1][t], acc[t]);
+                    acc[t] = mfma(win[ty].p, bw[3 * ty + 2][t], acc[t]);
                 }
-                a[j] = as_bf(v);
-            }
+            win[0] = win[1];
+            win[1] = win[2];
+        } else {
+            // the 9 taps' channels packed along K: lane kg takes taps
+            // (32 kc + 8 kg) / cpad .. + 8 / cpad - 1 of chunk kc
+            constexpr int CP = cpad(CI), TPL = 8 / CP, WPT = CP / 2;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = mfma(a, bw[0][t], acc[t]);
+            for (int kc = 0; kc < NK; ++kc) {
+                uint32_t wd[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int tt = 0; tt < TPL; ++tt) {
+                    const int tap = (32 * kc + 8 * kg) / CP + tt;
+                    const int yy = y + tap / 3 - 1, xx = x0 + i + tap % 3 - 1;
+                    if (tap < 9 && yy >= 0 && yy < d.h && xx >= 0 && xx < d.w) {
+                        const int64_t pix = (img * d.h + yy) * d.w + xx;
+                        if constexpr (SRC_F32) {
+                            const float *pf = static_cast<const float *>(in) + pix * 3;
+                            wd[WPT * tt] = (uint32_t)f2bf(pf[0]) | ((uint32_t)f2bf(pf[1]) << 16);
+                            wd[WPT * tt + 1] = (uint32_t)f2bf(pf[2]);
+                        } else {
+                            wd[WPT * tt] = *reinterpret_cast<const uint32_t *>(static_cast<const uint16_t *>(in) + pix * 2);
+                        }
+                    }
+                }
+                const bf16x8 a = __builtin_bit_cast(bf16x8, make_uint4(wd[0], wd[1], wd[2], wd[3]));
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t] = mfma(a, bw[kc][t], acc[t]);
+            }
         }
         // lane holds D[pixel 4 kg + r][channel t 16 + i]
 #pragma unroll
@@ -241,155 +278,145 @@ __global__ void __launch_bounds__(256) k_conv(const void *in, ConvDims d, const 
             const int co = t * 16 + i;
             if (co >= CO) continue;
             const float bv = bias ? bias[co] : 0.0f;
+            const int64_t cmo = ((img * d.h + y) * CO + co) * (int64_t)d.w + x0 + 4 * kg;
+            uint2 mk = make_uint2(0u, 0u);   // mask of pixels 4 kg .. 4 kg + 3 (channel-major, BF16)
+            if (mask_cm) mk = *reinterpret_cast<const uint2 *>(mask_cm + cmo);
+            uint32_t cm[2] = {0u, 0u};   // the BF16 output of pixels 4 kg .. 4 kg + 3
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 float v = acc[t][r] + bv;
                 if (relu) v = fmaxf(v, 0.0f);
                 const int64_t pix = (img * d.h + y) * d.w + x0 + 4 * kg + r;
+                uint16_t hb = f2bf(v);
                 if (out_f32) out_f32[pix * CO + co] = v;
-                if (out_bf) out_bf[pix * CO + co] = f2bf(v);
-                if (out_masked)
-                    out_masked[pix * CO + co] = bf2f(act_mask[pix * CO + co]) > 0.0f ? f2bf(v) : (uint16_t)0;
+                if (out_bf) out_bf[pix * CO + co] = hb;
+                if (mask_cm) {
+                    const uint32_t mw = (r < 2 ? mk.x : mk.y) >> (16 * (r & 1));
+                    hb = bf2f((uint16_t)mw) > 0.0f ? hb : (uint16_t)0;
+                    if (out_masked) out_masked[pix * CO + co] = hb;
+                }
+                cm[r >> 1] |= (uint32_t)hb << (16 * (r & 1));
             }
+            if (out_cm) *reinterpret_cast<uint2 *>(out_cm + cmo) = make_uint2(cm[0], cm[1]);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Weight and bias gradients of one layer: dW[tap][ci][co] = sum over pixels
-// of x[p + tap - (1,1)][ci] dy[p][co], db[co] = sum of dy[p][co].  Each wave
-// (one per block) takes whole rows, keeps all 9 x CI x CO partial sums in its
-// accumulators and writes them to its own slot; k_wgrad_reduce1/2 add the slots
-// in a fixed order (deterministic).  The contraction runs over pixels, which
-// are strided in the NHWC activations, so each 32-pixel strip is first staged
-// in LDS channel-major: the three input rows around the output row, each in
-// three copies shifted by one pixel (every MFMA operand is then one aligned
-// 16-byte LDS read), and the output-gradient strip.  A wave walks its rows
-// strip by strip, so consecutive output rows share two of their input rows.
+// Channel-major row copies.  The weight gradient contracts over pixels, and a
+// matrix-core operand takes 8 consecutive K values per lane, so its operands
+// are read from copies of the activations and gradients laid out per image
+// row as [channel][x] (BF16): cm[((img h + y) C + c) w + x].  The producing
+// kernels (convolutions, loss) write them beside their NHWC outputs; k_to_cm
+// makes them from NHWC data (the network input, the per-layer check calls).
 // ---------------------------------------------------------------------------
-template <int CI, int CO, bool SRC_F32>
-__global__ void __launch_bounds__(64) k_wgrad(const void *x, const uint16_t *dy, ConvDims d, int64_t rows_per_wave,
-                                              float *part)
+template <int C, bool SRC_F32>
+__global__ void k_to_cm(const void *in, int64_t rows, int w, uint16_t *out)
+{
+    const int64_t total = rows * C * w;
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total;
+         o += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(o % w), c = (int)((o / w) % C);
+        const int64_t row = o / ((int64_t)w * C), e = (row * w + x) * C + c;
+        out[o] = SRC_F32 ? f2bf(static_cast<const float *>(in)[e]) : static_cast<const uint16_t *>(in)[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight and bias gradients of one layer: dW[tap][ci][co] = sum over pixels
+// of x[p + tap - (1,1)][ci] dy[p][co], db[co] = sum of dy[p][co], from the
+// channel-major copies.  MFMA: M = 16 input channels, N = 16 output
+// channels, K = 32 pixels of a row.  Lane (i, kg) reads 8 consecutive pixels
+// x0 + 8 kg .. + 7 of channel i: one aligned 16-byte load, plus the two
+// neighbouring pixel pairs for the operands shifted by one pixel either way
+// (byte-align of adjacent dwords).  A workgroup takes R rows of one image and
+// one 32-pixel column chunk, one wave per (input tile, output tile) pair;
+// each wave slides a window of three input rows down the rows and writes its
+// sums to the workgroup's slot; k_wgrad_reduce1/2 add the slots in a fixed
+// order (deterministic).
+// ---------------------------------------------------------------------------
+struct Shift3 {
+    bf16x8 m, z, p;   // pixels shifted by -1, 0, +1
+};
+
+template <int CI, int CO>
+__global__ void __launch_bounds__(256) k_wgrad(const uint16_t *__restrict__ xcm, const uint16_t *__restrict__ gcm,
+                                               ConvDims d, int R, float *__restrict__ part)
 {
     constexpr int TI = ntile(CI), TO = ntile(CO), CIP = 16 * TI, COP = 16 * TO;
-    constexpr int64_t SLOT = 9 * CIP * COP + COP;
-    constexpr int GI = SRC_F32 ? 1 : CI / 8;   // loads per input pixel: 8 BF16 channels, or all CI floats
-    constexpr int GO = CO >= 8 ? CO / 8 : 1;   // loads per output-gradient pixel
-    static_assert(SRC_F32 ? CI <= 8 : CI % 8 == 0, "input channels per load");
-    static_assert(CO >= 8 ? CO % 8 == 0 : true, "output channels per load");
-    // xs[slot][shift][ci][k]: input row yy sits in slot yy mod 3, so moving to
-    // the next output row of the same image loads one new input row
-    __shared__ __attribute__((aligned(16))) uint16_t xs[3][3][CIP][32];
-    __shared__ __attribute__((aligned(16))) uint16_t gs[COP][32];
-    const int lane = (int)threadIdx.x, i = lane & 15, kg = lane >> 4;
-    const int64_t rows = d.n * d.h;
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_wave;
-    const int64_t r1 = r0 + rows_per_wave < rows ? r0 + rows_per_wave : rows;
-    // padded channel rows stay zero; every real entry is rewritten when used
-    for (int e = lane; e < 9 * CIP * 32; e += 64) (&xs[0][0][0][0])[e] = 0;
-    for (int e = lane; e < COP * 32; e += 64) (&gs[0][0])[e] = 0;
-    f32x4 acc[9][TI][TO];
+    constexpr int SLOT = 9 * CIP * COP + COP;
+    const int lane = (int)(threadIdx.x & 63), wid = (int)(threadIdx.x >> 6);
+    const int a = wid / TO, b = wid % TO;
+    const int i = lane & 15, kg = lane >> 4;
+    const int cpr = d.w / 32, rb = d.h / R;
+    const int64_t unit = blockIdx.x;
+    const int x0 = (int)(unit % cpr) * 32, y0 = (int)((unit / cpr) % rb) * R;
+    const int64_t img = unit / ((int64_t)cpr * rb);
+    const int xs = x0 + 8 * kg, c = a * 16 + i, co = b * 16 + i;
+    auto xrow = [&](int yy) {
+        uint32_t d0 = 0, d1 = 0, d2 = 0, d3 = 0, lft = 0, rgt = 0;
+        if (c < CI && yy >= 0 && yy < d.h) {
+            const uint16_t *row = xcm + ((img * d.h + yy) * CI + c) * (int64_t)d.w;
+            const uint4 q = *reinterpret_cast<const uint4 *>(row + xs);
+            d0 = q.x;
+            d1 = q.y;
+            d2 = q.z;
+            d3 = q.w;
+            if (xs > 0) lft = *reinterpret_cast<const uint32_t *>(row + xs - 2);
+            if (xs + 8 < d.w) rgt = *reinterpret_cast<const uint32_t *>(row + xs + 8);
+        }
+        const uint32_t e12 = __builtin_amdgcn_alignbyte(d1, d0, 2), e34 = __builtin_amdgcn_alignbyte(d2, d1, 2),
+                       e56 = __builtin_amdgcn_alignbyte(d3, d2, 2);
+        Shift3 s;
+        s.z = __builtin_bit_cast(bf16x8, make_uint4(d0, d1, d2, d3));
+        s.m = __builtin_bit_cast(bf16x8, make_uint4(__builtin_amdgcn_alignbyte(d0, lft, 2), e12, e34, e56));
+        s.p = __builtin_bit_cast(bf16x8, make_uint4(e12, e34, e56, __builtin_amdgcn_alignbyte(rgt, d3, 2)));
+        return s;
+    };
+    f32x4 acc[9];
 #pragma unroll
-    for (int tp = 0; tp < 9; ++tp)
+    for (int tp = 0; tp < 9; ++tp) acc[tp] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float dbs = 0.0f;
+    // rows go four at a time: all loads of a group are issued before its
+    // products, so their latencies overlap (R is a multiple of 4)
+    Shift3 win[6];   // input rows y - 1 .. y + 4
+    win[0] = xrow(y0 - 1);
+    win[1] = xrow(y0);
+    for (int rr = 0; rr < R; rr += 4) {
+        const int y = y0 + rr;
+        bf16x8 gb[4];
 #pragma unroll
-        for (int a = 0; a < TI; ++a)
+        for (int k = 0; k < 4; ++k) {
+            win[2 + k] = xrow(y + 1 + k);
+            uint4 q = make_uint4(0, 0, 0, 0);
+            if (co < CO)
+                q = *reinterpret_cast<const uint4 *>(gcm + ((img * d.h + y + k) * CO + co) * (int64_t)d.w + xs);
+            gb[k] = __builtin_bit_cast(bf16x8, q);
+        }
 #pragma unroll
-            for (int b = 0; b < TO; ++b) acc[tp][a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float dbs[TO];
+        for (int k = 0; k < 4; ++k) {
 #pragma unroll
-    for (int b = 0; b < TO; ++b) dbs[b] = 0.0f;
-    for (int p0 = 0; p0 < d.w; p0 += 32) {
-        int64_t prev = -2;   // row whose input rows the slots hold
-        for (int64_t row = r0; row < r1; ++row) {
-            const int y = (int)(row % d.h);
-            const int64_t img = row / d.h;
-            // input rows to load: all three, or y+1 only after row - 1 of the same image
-            const bool slide = row == prev + 1 && y > 0;
-            const int first = slide ? 2 : 0;
-            prev = row;
-            __syncthreads();   // the previous row's reads are done
-            for (int e = lane; e < (3 - first) * 34 * GI; e += 64) {
-                const int r = first + e / (34 * GI), j = (e / GI) % 34, g = e % GI;
-                const int yy = y + r - 1, xx = p0 - 1 + j;
-                if (yy < 0 || yy >= d.h) continue;     // its taps are skipped
-                const int sl = yy % 3;
-                const bool in = xx >= 0 && xx < d.w;
-                const int64_t pix = (img * d.h + yy) * d.w + xx;
-                uint16_t v[8];
-                if constexpr (SRC_F32) {
+            for (int j = 0; j < 8; ++j) dbs += (float)gb[k][j];
 #pragma unroll
-                    for (int c = 0; c < CI; ++c) v[c] = in ? f2bf(static_cast<const float *>(x)[pix * CI + c]) : 0;
-                } else {
-                    uint4 q = make_uint4(0, 0, 0, 0);
-                    if (in) q = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(x) + pix * CI + 8 * g);
-                    const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) v[c] = (uint16_t)(w4[c >> 1] >> (16 * (c & 1)));
-                }
-                constexpr int NC = SRC_F32 ? CI : 8;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const int ci = SRC_F32 ? c : 8 * g + c;
-#pragma unroll
-                    for (int sft = 0; sft < 3; ++sft) {
-                        const int k = j - sft;
-                        if (k >= 0 && k < 32) xs[sl][sft][ci][k] = v[c];
-                    }
-                }
-            }
-            // output-gradient strip, pixels p0 .. p0+31
-            for (int e = lane; e < 32 * GO; e += 64) {
-                const int k = e / GO, g = e % GO;
-                const int64_t pix = (img * d.h + y) * d.w + p0 + k;
-                if constexpr (CO >= 8) {
-                    const uint4 q = *reinterpret_cast<const uint4 *>(dy + pix * CO + 8 * g);
-                    const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) gs[8 * g + c][k] = (uint16_t)(w4[c >> 1] >> (16 * (c & 1)));
-                } else {
-#pragma unroll
-                    for (int c = 0; c < CO; ++c) gs[c][k] = dy[pix * CO + c];
-                }
-            }
-            __syncthreads();
-            bf16x8 bfr[TO];
-#pragma unroll
-            for (int b = 0; b < TO; ++b) {
-                bfr[b] = ld_bf16x8(&gs[b * 16 + i][8 * kg]);
-#pragma unroll
-                for (int j = 0; j < 8; ++j) dbs[b] += (float)bfr[b][j];
-            }
-#pragma unroll
-            for (int tp = 0; tp < 9; ++tp) {
-                const int yy = y + tp / 3 - 1;
-                if (yy < 0 || yy >= d.h) continue;            // uniform over the wave
-                const int sl = yy % 3;
-#pragma unroll
-                for (int a = 0; a < TI; ++a) {
-                    const bf16x8 afr = ld_bf16x8(&xs[sl][tp % 3][a * 16 + i][8 * kg]);
-#pragma unroll
-                    for (int b = 0; b < TO; ++b) acc[tp][a][b] = mfma(afr, bfr[b], acc[tp][a][b]);
-                }
+            for (int ty = 0; ty < 3; ++ty) {
+                acc[3 * ty + 0] = mfma(win[k + ty].m, gb[k], acc[3 * ty + 0]);
+                acc[3 * ty + 1] = mfma(win[k + ty].z, gb[k], acc[3 * ty + 1]);
+                acc[3 * ty + 2] = mfma(win[k + ty].p, gb[k], acc[3 * ty + 2]);
             }
         }
+        win[0] = win[4];
+        win[1] = win[5];
     }
-    float *slot = part + (int64_t)blockIdx.x * SLOT;
     // lane holds D[ci = a 16 + 4 kg + r][co = b 16 + i]
+    float *slot = part + unit * SLOT;
 #pragma unroll
     for (int tp = 0; tp < 9; ++tp)
 #pragma unroll
-        for (int a = 0; a < TI; ++a)
-#pragma unroll
-            for (int b = 0; b < TO; ++b)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    slot[((int64_t)tp * CIP + a * 16 + 4 * kg + r) * COP + b * 16 + i] = acc[tp][a][b][r];
-#pragma unroll
-    for (int b = 0; b < TO; ++b) {
-        float sb = dbs[b];
-        sb += __shfl_xor(sb, 16);
-        sb += __shfl_xor(sb, 32);
-        if (kg == 0) slot[9 * CIP * COP + b * 16 + i] = sb;
+        for (int r = 0; r < 4; ++r) slot[(tp * CIP + a * 16 + 4 * kg + r) * COP + b * 16 + i] = acc[tp][r];
+    if (a == 0) {
+        dbs += __shfl_xor(dbs, 16);
+        dbs += __shfl_xor(dbs, 32);
+        if (kg == 0) slot[9 * CIP * COP + b * 16 + i] = dbs;
     }
 }
 
@@ -410,7 +437,7 @@ __device__ __forceinline__ int64_t wgrad_src(int64_t e)
 
 // grid (outputs / 256, slot groups): tmp[group][e] = sum of its slots
 template <int CI, int CO>
-__global__ void k_wgrad_reduce1(const float *part, int64_t nslots, float *tmp)
+__global__ void k_wgrad_reduce1(const float *__restrict__ part, int64_t nslots, float *__restrict__ tmp)
 {
     constexpr int CIP = 16 * ntile(CI), COP = 16 * ntile(CO);
     constexpr int64_t SLOT = 9 * CIP * COP + COP, NOUT = 9 * CI * CO + CO;
@@ -425,7 +452,8 @@ __global__ void k_wgrad_reduce1(const float *part, int64_t nslots, float *tmp)
 }
 
 template <int CI, int CO>
-__global__ void k_wgrad_reduce2(const float *tmp, int64_t ngroups, float *dw, float *db)
+__global__ void k_wgrad_reduce2(const float *__restrict__ tmp, int64_t ngroups, float *__restrict__ dw,
+                                float *__restrict__ db)
 {
     constexpr int64_t NOUT = 9 * CI * CO + CO;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -444,7 +472,7 @@ __global__ void k_wgrad_reduce2(const float *tmp, int64_t ngroups, float *dw, fl
 // operand precision of the backward contractions) and per-block sums
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_loss(const float *out, const float *mask, const float *logq, int64_t P,
-                                              float lam, uint16_t *g, double *part)
+                                              float lam, uint16_t *g, double *part, int w, uint16_t *g_cm)
 {
     __shared__ double red[256];
     double s = 0.0;
@@ -456,8 +484,12 @@ __global__ void __launch_bounds__(256) k_loss(const float *out, const float *mas
         const float dq = valid ? qh - tq : 0.0f;
         s += (double)(sp - t * z) + (double)lam * (double)dq * (double)dq;
         const float sig = 1.0f / (1.0f + expf(-z));
-        g[2 * p] = f2bf((float)((sig - t) * invP));
-        g[2 * p + 1] = f2bf((float)(2.0 * lam * dq * invP));
+        const uint16_t g0 = f2bf((float)((sig - t) * invP)), g1 = f2bf((float)(2.0 * lam * dq * invP));
+        g[2 * p] = g0;
+        g[2 * p + 1] = g1;
+        const int64_t row = p / w, x = p % w;
+        g_cm[(row * 2 + 0) * w + x] = g0;
+        g_cm[(row * 2 + 1) * w + x] = g1;
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -527,7 +559,8 @@ hipError_t cnn_prepare(const float *params, void *prep, hipStream_t st)
 }
 
 static void conv_launch(int l, bool transposed, const void *in, ConvDims d, const void *prep, bool relu, uint16_t *out_bf,
-                        float *out_f32, uint16_t *out_masked, const uint16_t *act_mask, hipStream_t st)
+                        float *out_f32, uint16_t *out_masked, const uint16_t *mask_cm, uint16_t *out_cm,
+                        hipStream_t st)
 {
     const int64_t waves = d.n * (d.h / kConvRows) * (d.w / 16);
     const dim3 grid(blocks_for(waves * 64, 256)), block(256);
@@ -536,94 +569,129 @@ static void conv_launch(int l, bool transposed, const void *in, ConvDims d, cons
         const float *b = bias_of(prep, l);
         if (l == 0)
             hipLaunchKernelGGL((k_conv<3, 32, true>), grid, block, 0, st, in, d, wm, b, relu, out_bf, out_f32,
-                               out_masked, act_mask);
+                               out_masked, mask_cm, out_cm);
         else if (l == 3)
             hipLaunchKernelGGL((k_conv<32, 2, false>), grid, block, 0, st, in, d, wm, b, relu, out_bf, out_f32,
-                               out_masked, act_mask);
+                               out_masked, mask_cm, out_cm);
         else
             hipLaunchKernelGGL((k_conv<32, 32, false>), grid, block, 0, st, in, d, wm, b, relu, out_bf, out_f32,
-                               out_masked, act_mask);
+                               out_masked, mask_cm, out_cm);
     } else {
         // input gradient of layer l: a convolution from Co(l) to Ci(l) = 32 channels
         const uint16_t *wm = bwd_mat(prep, l);
         if (l == 3)
             hipLaunchKernelGGL((k_conv<2, 32, false>), grid, block, 0, st, in, d, wm, (const float *)nullptr, false,
-                               out_bf, out_f32, out_masked, act_mask);
+                               out_bf, out_f32, out_masked, mask_cm, out_cm);
         else
             hipLaunchKernelGGL((k_conv<32, 32, false>), grid, block, 0, st, in, d, wm, (const float *)nullptr, false,
-                               out_bf, out_f32, out_masked, act_mask);
+                               out_bf, out_f32, out_masked, mask_cm, out_cm);
     }
 }
 
-// waves of the weight-gradient pass and its partial-sum slots
-static int64_t wgrad_waves(ConvDims d) { return d.n * d.h < 1024 ? d.n * d.h : 1024; }
-
-// per-wave partial slots, then the first-stage group sums
-static int64_t wgrad_groups(ConvDims d) { return (wgrad_waves(d) + kRedGroup - 1) / kRedGroup; }
-
-uint64_t cnn_wgrad_scratch_bytes(int64_t n, int h, int w)
+// Rows per workgroup of the weight-gradient pass: the smallest power of two
+// >= 4 dividing h that keeps the slots (one per workgroup: R rows of a
+// 32-pixel column chunk) at 512 or fewer, h at most.
+static int wgrad_rows(ConvDims d)
 {
-    ConvDims d{n, h, w};
-    const int64_t slot = 9 * 32 * 32 + 32;
-    return (uint64_t)wgrad_waves(d) * slot * 4 + (uint64_t)wgrad_groups(d) * slot * 4;
+    int R = 4;
+    while (R < d.h && d.h % (2 * R) == 0 && d.n * (d.h / R) * (d.w / 32) > 512) R *= 2;
+    return R;
 }
 
-template <int CI, int CO, bool SRC_F32>
-static void wgrad_typed(const void *x, const uint16_t *dy, ConvDims d, float *part, float *dw, float *db,
+static int64_t wgrad_slots(ConvDims d) { return d.n * (d.h / wgrad_rows(d)) * (d.w / 32); }
+static int64_t wgrad_groups(ConvDims d) { return (wgrad_slots(d) + kRedGroup - 1) / kRedGroup; }
+
+// slots and first-stage group sums of the weight-gradient reduction
+static uint64_t wgrad_part_bytes(ConvDims d)
+{
+    const int64_t slot = 9 * 32 * 32 + 32;
+    return (uint64_t)(wgrad_slots(d) + wgrad_groups(d)) * slot * 4;
+}
+
+static uint64_t al256(uint64_t b) { return (b + 255) & ~(uint64_t)255; }
+
+// per-layer backward: channel-major copies of the input and of dy, then the slots
+uint64_t cnn_wgrad_scratch_bytes(int64_t n, int h, int w)
+{
+    const uint64_t cm = al256((uint64_t)n * h * w * 32 * 2);
+    return 2 * cm + wgrad_part_bytes(ConvDims{n, h, w});
+}
+
+template <int CI, int CO>
+static void wgrad_typed(const uint16_t *xcm, const uint16_t *gcm, ConvDims d, float *part, float *dw, float *db,
                         hipStream_t st)
 {
-    const int64_t waves = wgrad_waves(d), rows = d.n * d.h;
-    const int64_t rpw = (rows + waves - 1) / waves;
-    const int64_t used = (rows + rpw - 1) / rpw;
+    const int64_t slots = wgrad_slots(d), groups = wgrad_groups(d);
     const int64_t nout = 9 * CI * CO + CO;
-    const int64_t groups = (used + kRedGroup - 1) / kRedGroup;
-    float *tmp = part + wgrad_waves(d) * (int64_t)(9 * 32 * 32 + 32);
-    hipLaunchKernelGGL((k_wgrad<CI, CO, SRC_F32>), dim3(used), dim3(64), 0, st, x, dy, d, rpw, part);
-    hipLaunchKernelGGL((k_wgrad_reduce1<CI, CO>), dim3(blocks_for(nout, 256), groups), dim3(256), 0, st, part, used,
+    float *tmp = part + slots * (int64_t)(9 * 32 * 32 + 32);
+    hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(slots), dim3(64 * ntile(CI) * ntile(CO)), 0, st, xcm, gcm, d,
+                       wgrad_rows(d), part);
+    hipLaunchKernelGGL((k_wgrad_reduce1<CI, CO>), dim3(blocks_for(nout, 256), groups), dim3(256), 0, st, part, slots,
                        tmp);
     hipLaunchKernelGGL((k_wgrad_reduce2<CI, CO>), dim3(blocks_for(nout, 256)), dim3(256), 0, st, tmp, groups, dw, db);
 }
 
-static void wgrad_launch(int l, const void *x, const uint16_t *dy, ConvDims d, float *part, float *dw, float *db,
-                         hipStream_t st)
+static void wgrad_launch(int l, const uint16_t *xcm, const uint16_t *gcm, ConvDims d, float *part, float *dw,
+                         float *db, hipStream_t st)
 {
     if (l == 0)
-        wgrad_typed<3, 32, true>(x, dy, d, part, dw, db, st);
+        wgrad_typed<3, 32>(xcm, gcm, d, part, dw, db, st);
     else if (l == 3)
-        wgrad_typed<32, 2, false>(x, dy, d, part, dw, db, st);
+        wgrad_typed<32, 2>(xcm, gcm, d, part, dw, db, st);
     else
-        wgrad_typed<32, 32, false>(x, dy, d, part, dw, db, st);
+        wgrad_typed<32, 32>(xcm, gcm, d, part, dw, db, st);
+}
+
+template <int C, bool SRC_F32>
+static void to_cm(const void *in, ConvDims d, uint16_t *out, hipStream_t st)
+{
+    const int64_t total = d.n * d.h * (int64_t)d.w * C;
+    const int blocks = (int)(blocks_for(total, 256) < 4096 ? blocks_for(total, 256) : 4096);
+    hipLaunchKernelGGL((k_to_cm<C, SRC_F32>), dim3(blocks), dim3(256), 0, st, in, d.n * d.h, d.w, out);
 }
 
 hipError_t cnn_layer_forward(int l, const void *prep, const void *in, int64_t n, int h, int w, float *out_f32,
                              uint16_t *out_bf, hipStream_t st)
 {
-    conv_launch(l, false, in, ConvDims{n, h, w}, prep, l < 3, out_bf, out_f32, nullptr, nullptr, st);
+    conv_launch(l, false, in, ConvDims{n, h, w}, prep, l < 3, out_bf, out_f32, nullptr, nullptr, nullptr, st);
     return hipGetLastError();
 }
 
 hipError_t cnn_layer_backward(int l, const void *prep, const void *in, const uint16_t *dy, int64_t n, int h, int w,
-                              float *dw, float *db, float *dx_f32, uint16_t *dx_masked, const uint16_t *act_mask,
+                              float *dw, float *db, float *dx_f32, uint16_t *dx_masked, const uint16_t *mask_cm,
                               void *scratch, hipStream_t st)
 {
     const ConvDims d{n, h, w};
-    wgrad_launch(l, in, dy, d, static_cast<float *>(scratch), dw, db, st);
+    const uint64_t cm = al256((uint64_t)n * h * w * 32 * 2);
+    uint16_t *xcm = static_cast<uint16_t *>(scratch);
+    uint16_t *gcm = reinterpret_cast<uint16_t *>(static_cast<char *>(scratch) + cm);
+    float *part = reinterpret_cast<float *>(static_cast<char *>(scratch) + 2 * cm);
+    if (l == 0)
+        to_cm<3, true>(in, d, xcm, st);
+    else
+        to_cm<32, false>(in, d, xcm, st);
+    if (l == 3)
+        to_cm<2, false>(dy, d, gcm, st);
+    else
+        to_cm<32, false>(dy, d, gcm, st);
+    wgrad_launch(l, xcm, gcm, d, part, dw, db, st);
     if (l > 0 && (dx_f32 || dx_masked))
-        conv_launch(l, true, dy, d, prep, false, nullptr, dx_f32, dx_masked, act_mask, st);
+        conv_launch(l, true, dy, d, prep, false, nullptr, dx_f32, dx_masked, mask_cm, nullptr, st);
     return hipGetLastError();
 }
 
 // Workspace of the whole-network calls: 3 hidden activations (BF16, 32 ch),
 // output (FP32, 2 ch), output gradient (BF16, 2 ch), two hidden gradients
-// (BF16, 32 ch), gradient vector, loss partials, weight-gradient slots.
+// (BF16, 32 ch), channel-major copies of the input, the activations and the
+// gradients, gradient vector, loss partials, weight-gradient slots.
 struct CnnWs {
     uint16_t *act[3], *gout, *gh[2];
+    uint16_t *x_cm, *act_cm[3], *gout_cm, *gh_cm[2];
     float *out, *grad, *part;
     double *lpart, *loss;
     uint64_t total;
 };
 
-static uint64_t al256(uint64_t b) { return (b + 255) & ~(uint64_t)255; }
 constexpr int kLossBlocks = 512;
 
 static CnnWs ws_layout(void *base, int64_t n, int h, int w)
@@ -641,24 +709,36 @@ static CnnWs ws_layout(void *base, int64_t n, int h, int w)
     s.out = reinterpret_cast<float *>(take(P * 2 * 4));
     s.gout = reinterpret_cast<uint16_t *>(take(P * 2 * 2));
     for (int k = 0; k < 2; ++k) s.gh[k] = reinterpret_cast<uint16_t *>(take(P * 32 * 2));
+    s.x_cm = reinterpret_cast<uint16_t *>(take(P * 3 * 2));
+    for (int k = 0; k < 3; ++k) s.act_cm[k] = reinterpret_cast<uint16_t *>(take(P * 32 * 2));
+    s.gout_cm = reinterpret_cast<uint16_t *>(take(P * 2 * 2));
+    for (int k = 0; k < 2; ++k) s.gh_cm[k] = reinterpret_cast<uint16_t *>(take(P * 32 * 2));
     s.grad = reinterpret_cast<float *>(take(QSQ_CNN_PARAMS * 4));
     s.lpart = reinterpret_cast<double *>(take(kLossBlocks * 8));
     s.loss = reinterpret_cast<double *>(take(8));
-    s.part = reinterpret_cast<float *>(take(cnn_wgrad_scratch_bytes(n, h, w)));
+    s.part = reinterpret_cast<float *>(take(wgrad_part_bytes(ConvDims{n, h, w})));
     s.total = o;
     return s;
 }
 
 uint64_t cnn_workspace_bytes(int64_t n, int h, int w) { return ws_layout(nullptr, n, h, w).total; }
 
+// forward through the four layers; with cm, also the channel-major copies of
+// the hidden activations (for the weight gradients of a training step)
+static void forward_layers(const void *prep, const float *x, ConvDims d, float *out, const CnnWs &s, bool cm,
+                           hipStream_t st)
+{
+    conv_launch(0, false, x, d, prep, true, s.act[0], nullptr, nullptr, nullptr, cm ? s.act_cm[0] : nullptr, st);
+    conv_launch(1, false, s.act[0], d, prep, true, s.act[1], nullptr, nullptr, nullptr, cm ? s.act_cm[1] : nullptr,
+                st);
+    conv_launch(2, false, s.act[1], d, prep, true, s.act[2], nullptr, nullptr, nullptr, cm ? s.act_cm[2] : nullptr,
+                st);
+    conv_launch(3, false, s.act[2], d, prep, false, nullptr, out, nullptr, nullptr, nullptr, st);
+}
+
 hipError_t cnn_forward(const void *prep, const float *x, int64_t n, int h, int w, float *out, void *ws, hipStream_t st)
 {
-    const CnnWs s = ws_layout(ws, n, h, w);
-    const ConvDims d{n, h, w};
-    conv_launch(0, false, x, d, prep, true, s.act[0], nullptr, nullptr, nullptr, st);
-    conv_launch(1, false, s.act[0], d, prep, true, s.act[1], nullptr, nullptr, nullptr, st);
-    conv_launch(2, false, s.act[1], d, prep, true, s.act[2], nullptr, nullptr, nullptr, st);
-    conv_launch(3, false, s.act[2], d, prep, false, nullptr, out, nullptr, nullptr, st);
+    forward_layers(prep, x, ConvDims{n, h, w}, out, ws_layout(ws, n, h, w), false, st);
     return hipGetLastError();
 }
 
@@ -667,24 +747,29 @@ hipError_t cnn_train_step(float *params, float *adam_m, float *adam_v, int64_t t
                           float *grad_out, double *loss_out, void *ws, hipStream_t st)
 {
     const CnnWs s = ws_layout(ws, n, h, w);
+    const ConvDims d{n, h, w};
     const int64_t P = n * h * w;
-    hipError_t e = cnn_forward(prep, x, n, h, w, s.out, ws, st);
-    if (e != hipSuccess) return e;
+    to_cm<3, true>(x, d, s.x_cm, st);
+    forward_layers(prep, x, d, s.out, s, true, st);
     const int lb = (int)(blocks_for(P, 256) < kLossBlocks ? blocks_for(P, 256) : kLossBlocks);
-    hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, st, s.out, mask, logq, P, lam, s.gout, s.lpart);
+    hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, st, s.out, mask, logq, P, lam, s.gout, s.lpart, w, s.gout_cm);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, s.lpart, lb, loss_out ? loss_out : s.loss);
     float *g = grad_out ? grad_out : s.grad;
     // layer 4 .. 1: weight gradients, then the input gradient masked by the
     // ReLU of the layer below (its BF16 activation > 0)
-    const uint16_t *gin = s.gout;
+    const uint16_t *gin = s.gout, *gin_cm = s.gout_cm;
     for (int l = 3; l >= 0; --l) {
-        const void *xin = l == 0 ? static_cast<const void *>(x) : static_cast<const void *>(s.act[l - 1]);
+        const uint16_t *xcm = l == 0 ? s.x_cm : s.act_cm[l - 1];
         float *dw = g + master_w(l), *db = dw + 9 * kCi[l] * kCo[l];
-        uint16_t *gnext = l > 0 ? s.gh[l % 2] : nullptr;
-        e = cnn_layer_backward(l, prep, xin, gin, n, h, w, dw, db, nullptr, gnext, l > 0 ? s.act[l - 1] : nullptr,
-                               s.part, st);
-        if (e != hipSuccess) return e;
-        gin = gnext;
+        wgrad_launch(l, xcm, gin_cm, d, s.part, dw, db, st);
+        if (l > 0) {
+            // the input gradient of layer 1 feeds only layer 0's weight
+            // gradient: its channel-major copy alone
+            uint16_t *gnext = l > 1 ? s.gh[l % 2] : nullptr, *gnext_cm = s.gh_cm[l % 2];
+            conv_launch(l, true, gin, d, prep, false, nullptr, nullptr, gnext, s.act_cm[l - 1], gnext_cm, st);
+            gin = gnext;
+            gin_cm = gnext_cm;
+        }
     }
     // Kingma & Ba's defaults; every constant is formed in FP64 and rounded once
     const double b1 = 0.9, b2 = 0.999;
@@ -692,6 +777,8 @@ hipError_t cnn_train_step(float *params, float *adam_m, float *adam_v, int64_t t
     hipLaunchKernelGGL(k_adam, dim3(blocks_for(QSQ_CNN_PARAMS, 256)), dim3(256), 0, st, params, g, adam_m, adam_v,
                        (int64_t)QSQ_CNN_PARAMS, lr, (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f,
                        c1, c2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     return cnn_prepare(params, prep, st);
 }
 

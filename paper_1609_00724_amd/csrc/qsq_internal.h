@@ -206,7 +206,7 @@ hipError_t cnn_train_step(float *params, float *adam_m, float *adam_v, int64_t t
 hipError_t cnn_layer_forward(int l, const void *prep, const void *in, int64_t n, int h, int w, float *out_f32,
                              uint16_t *out_bf, hipStream_t st);
 hipError_t cnn_layer_backward(int l, const void *prep, const void *in, const uint16_t *dy, int64_t n, int h, int w,
-                              float *dw, float *db, float *dx_f32, uint16_t *dx_masked, const uint16_t *act_mask,
+                              float *dw, float *db, float *dx_f32, uint16_t *dx_masked, const uint16_t *mask_cm,
                               void *scratch, hipStream_t st);
 
 }  // namespace qsq

@@ -180,8 +180,15 @@ typedef struct qsq_trace_opts {
  *          conditions as 2; results identical to direct loads bit for bit),
  *          4 = direct loads of the cell's corners from the field's cell
  *          records (FP32 or BF16 storage, FP32 stepping, one field per call,
- *          field with cell records; otherwise direct; identical results) */
+ *          field with cell records; otherwise direct; identical results)
+ * and the flag
+ *   QSQ_LAUNCH_PARTS  split the work list of the persistent stepping launch
+ *          into 8 contiguous parts with a counter each; workgroup b starts in
+ *          part b mod 8 (the XCD it is dispatched to, so that one XCD's L2
+ *          serves lines whose seeds lie together) and moves on to the other
+ *          parts once its own is used up (scheduling only: identical results) */
 #define QSQ_LAUNCH(lanes, wg, gather) (((lanes) & 15) | (((wg) & 3) << 4) | (((gather) & 7) << 6))
+#define QSQ_LAUNCH_PARTS (1 << 9)
 
 /* Per-seed results (device arrays of n entries; fp_* are SoA planes 3 x n:
  * x at [0,n), y at [n,2n), z at [2n,3n)).  Any pointer except status may be

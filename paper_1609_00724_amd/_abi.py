@@ -49,11 +49,14 @@ WG_CODES = {256: 0, 64: 1, 128: 2}
 GATHER_AUTO, GATHER_DIRECT, GATHER_CACHED, GATHER_REGS, GATHER_CELLS = 0, 1, 2, 3, 4
 
 
-def launch_word(lanes=0, wg=256, gather=GATHER_AUTO):
-    """QSQ_LAUNCH(lanes, wg, gather) of include/qsq.h."""
+LAUNCH_PARTS = 1 << 9
+
+
+def launch_word(lanes=0, wg=256, gather=GATHER_AUTO, parts=False):
+    """QSQ_LAUNCH(lanes, wg, gather), with QSQ_LAUNCH_PARTS if parts, of include/qsq.h."""
     if not 0 <= lanes <= 15 or wg not in WG_CODES or gather not in (0, 1, 2, 3, 4):
         raise ValueError("launch shape outside QSQ_LAUNCH(0..15, 64|128|256, 0..4)")
-    return (lanes & 15) | (WG_CODES[wg] << 4) | (gather << 6)
+    return (lanes & 15) | (WG_CODES[wg] << 4) | (gather << 6) | (LAUNCH_PARTS if parts else 0)
 
 
 class Grid(C.Structure):

@@ -29,12 +29,15 @@ _cache: dict = {}
 CACHE_LANES = (1, 2)
 
 
-def candidates(lanes=DEFAULT_LANES, wgs=DEFAULT_WG, gathers=(A.GATHER_DIRECT, A.GATHER_CACHED, A.GATHER_REGS)):
+def candidates(lanes=DEFAULT_LANES, wgs=DEFAULT_WG, gathers=(A.GATHER_DIRECT, A.GATHER_CACHED, A.GATHER_REGS),
+               parts=(False, True)):
+    """Launch words over lanes x workgroup x gather, each with the work list in
+    one piece and split into per-XCD parts (QSQ_LAUNCH_PARTS)."""
     out = []
     for g in gathers:
         ls = (lanes if g in (A.GATHER_DIRECT, A.GATHER_CELLS)
               else tuple(l for l in lanes if l in CACHE_LANES) or lanes[:1])
-        out += [A.launch_word(l, w, g) for w in wgs for l in ls]
+        out += [A.launch_word(l, w, g, pt) for pt in parts for w in wgs for l in ls]
     return out
 
 
@@ -117,7 +120,8 @@ def describe(word):
     lanes = word & 15 or 8
     wg = {0: 256, 1: 64, 2: 128}[(word >> 4) & 3]
     gather = {0: "auto", 1: "direct", 2: "lds-cache", 3: "reg-cache", 4: "cell-records"}[(word >> 6) & 7]
-    return {"word": int(word), "lanes_per_cu": lanes * 256, "workgroup": wg, "gather": gather}
+    return {"word": int(word), "lanes_per_cu": lanes * 256, "workgroup": wg, "gather": gather,
+            "xcd_parts": bool(word & A.LAUNCH_PARTS)}
 
 
 def tune_map(plan, field, opts, reps=3, cands=None, batches=None):

@@ -104,8 +104,9 @@ int make_geom_opts(const qsq_field *f, const qsq_trace_opts *o, qsq::Geom *g, qs
     if (!isfinite(o->h_init) || !isfinite(o->h_max) || !isfinite(o->max_length))
         return fail(QSQ_ERR_INVALID_ARG, "h_init, h_max and max_length must be finite");
     if (o->flags & ~QSQ_FLAG_SKIP_OPEN) return fail(QSQ_ERR_INVALID_ARG, "unknown flags 0x%x", o->flags);
-    if ((o->launch & ~0x1ff) || ((o->launch >> 4) & 3) == 3 || ((o->launch >> 6) & 7) > 4)
-        return fail(QSQ_ERR_INVALID_ARG, "launch word 0x%x outside QSQ_LAUNCH(0..15, 0..2, 0..4)", o->launch);
+    if ((o->launch & ~0x3ff) || ((o->launch >> 4) & 3) == 3 || ((o->launch >> 6) & 7) > 4)
+        return fail(QSQ_ERR_INVALID_ARG, "launch word 0x%x outside QSQ_LAUNCH(0..15, 0..2, 0..4) | QSQ_LAUNCH_PARTS",
+                    o->launch);
     double hmin_grid = f->grid.spacing[0];
     double extent = 0.0;
     for (int d = 0; d < 3; ++d) {

@@ -51,6 +51,11 @@ struct StepOpts {
 
 // Per half-line end records, SoA planes of length 2*cap; half-line (dir, seed)
 // lives at dir*cap + seed (dir 0 = forward, 1 = backward).
+// Work-list parts of the persistent stepping launch (one per XCD) and the
+// index of their counters in the 256-byte counter block (u64 slots 8 .. 15).
+constexpr int kParts = 8;
+constexpr int kPartCounter = 8;
+
 struct Records {
     double *y;          // 9 planes: x0..2, dx1 0..2, dx2 0..2
     double *s;          // path length so far

@@ -1047,12 +1047,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EULER 
     int reg_cell = -1;
     Brick reg_brick = {};
 
-    // Work distribution: the first item of every lane is its global lane index
-    // (the launcher starts the counter at the launch's lane count); after that
-    // each wave takes chunks of kChunk items with one atomic and hands them to
-    // its idle lanes itself, so the shared counter is touched once per chunk
-    // rather than on every iteration in which a lane finished a line.
+    // Work distribution.  The work list is split into nparts contiguous parts
+    // (one, or kParts with the partition bit of the launch word), each with
+    // its own counter.  Workgroup b starts in part b mod nparts -- the XCD
+    // the hardware dispatches it to, so that the lanes of one XCD trace lines
+    // whose seeds lie together along the curve and share that XCD's L2 -- and
+    // the first item of each of its lanes is the lane's index within the
+    // part's workgroups (the launcher starts each counter past those).  After
+    // that each wave takes chunks of kChunk items of its part with one atomic
+    // and hands them to its idle lanes itself; a wave whose part is used up
+    // moves on to the following parts, and its lanes are done when every
+    // part is.  Which lane traces which line never changes a result.
     constexpr int64_t kChunk = 64;
+    const int nparts = (o.launch >> 9) & 1 ? kParts : 1;
+    const int home = (int)(blockIdx.x % (unsigned)nparts);
+    unsigned long long *pcount = job.counter + kPartCounter;
+    auto pbeg = [&](int p) { return total * p / nparts; };
+    int part = home, spent = 0;    // the wave's part; parts found used up
     int64_t cnext = 0, cend = 0;   // the wave's unassigned items [cnext, cend)
     bool first_fill = true;
     for (;;) {
@@ -1060,31 +1071,49 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EULER 
         const uint64_t need = __ballot(!active && !done);
         if (need) {
             const int j = __popcll(need & ((1ull << lane) - 1ull));   // rank among idle lanes
-            int64_t item;
+            int64_t item = -1;
             if (first_fill) {
-                item = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u) + j;
+                item = pbeg(home) + (int64_t)(blockIdx.x / (unsigned)nparts) * blockDim.x + (threadIdx.x & ~63u) + j;
+                if (item >= pbeg(home + 1)) item = -1;
             } else {
                 const int k = __popcll(need);
                 const int64_t avail = cend - cnext;
-                int64_t fresh = 0;
-                if (avail < k) {
+                if (avail < k && spent < nparts) {
+                    // one more chunk: from the wave's part, or the next part not used up
                     unsigned long long b = 0;
+                    int p = part, t = spent;
                     const int leader = __ffsll((unsigned long long)need) - 1;
-                    if (lane == leader) b = atomicAdd(job.counter, (unsigned long long)kChunk);
-                    fresh = (int64_t)__shfl(b, leader);
-                }
-                item = j < avail ? cnext + j : fresh + (j - avail);
-                if (avail < k) {
-                    cnext = fresh + (k - avail);
-                    cend = fresh + kChunk;
+                    if (lane == leader) {
+                        for (;;) {
+                            b = atomicAdd(pcount + p, (unsigned long long)kChunk);
+                            if ((int64_t)b < pbeg(p + 1)) break;
+                            if (++t >= nparts) break;
+                            p = p + 1 < nparts ? p + 1 : 0;
+                        }
+                    }
+                    b = __shfl(b, leader);
+                    part = __shfl(p, leader);
+                    spent = __shfl(t, leader);
+                    const int64_t fresh = (int64_t)b;
+                    const int64_t fend = spent < nparts ? min(fresh + kChunk, pbeg(part + 1)) : fresh;
+                    const int64_t got = fend - fresh;
+                    if (j < avail)
+                        item = cnext + j;
+                    else if (j - avail < got)
+                        item = fresh + (j - avail);
+                    const int64_t used = k - avail < got ? k - avail : got;
+                    cnext = fresh + used;
+                    cend = fend;
                 } else {
-                    cnext += k;
+                    if (j < avail) item = cnext + j;
+                    cnext += k < avail ? k : avail;
                 }
             }
             first_fill = false;
             if (!active && !done) {
-                if (item >= total) {
-                    done = true;
+                if (item < 0) {
+                    // no item this round; done once every part is used up
+                    done = spent >= nparts;
                 } else {
                     // the seed pass left x0 and the frame (eq. 9) in the record
                     rec = job.rec.work[item];
@@ -2161,6 +2190,17 @@ __global__ void __launch_bounds__(256) k_land_geo(TraceJob job)
 
 static __global__ void k_set_u64(unsigned long long *p, unsigned long long v) { *p = v; }
 
+// counters of the stepping launch's work-list parts: part p starts past the
+// first items of its workgroups (blocks b with b mod nparts = p, wg lanes each)
+static __global__ void k_part_counters(TraceJob job, int blocks, int wg, int nparts)
+{
+    const int p = (int)threadIdx.x;
+    if (p >= nparts) return;
+    const int64_t total = *job.rec.n_work;
+    const int64_t nb = p < blocks ? (blocks - p + nparts - 1) / nparts : 0;
+    job.counter[kPartCounter + p] = (unsigned long long)(total * p / nparts + nb * wg);
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -2328,7 +2368,8 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
     if (cap_blocks > resident) cap_blocks = resident;
     const int64_t want = (2 * n_max + wg - 1) / wg;
     const int blocks = (int)(want < cap_blocks ? want : cap_blocks);
-    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, job.counter, (unsigned long long)blocks * wg);
+    const int nparts = (job.o.launch >> 9) & 1 ? kParts : 1;
+    hipLaunchKernelGGL(k_part_counters, dim3(1), dim3(64), 0, st, job, blocks, wg, nparts);
     const bool prof = profiling();
     void *tok = nullptr;
     if (prof) prof_begin(kProfStep, st, &tok);

@@ -95,7 +95,7 @@ def test_invalid_arguments_rejected_before_launch(qsq):
     assert L.qsq_trace(C.byref(f), _fake(7), 10, C.byref(o), C.byref(t), _fake(8), 1 << 20, None) == \
         A.ERR_UNSUPPORTED
     o.step_dtype = A.F32
-    for bad in (0x30, 0x200, 0x140):      # workgroup code 3; bits above the word; gather 5
+    for bad in (0x30, 0x400, 0x140):      # workgroup code 3; bits above the word; gather 5
         o.launch = bad
         assert L.qsq_trace(C.byref(f), _fake(7), 10, C.byref(o), C.byref(t), _fake(8), 1 << 20, None) == \
             A.ERR_INVALID_ARG

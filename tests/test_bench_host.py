@@ -80,7 +80,9 @@ def test_tuner_candidates_and_names():
         if d["gather"] != "direct":              # at most 512 resident lanes per CU
             assert d["lanes_per_cu"] <= 512
     assert autotune.describe(A.launch_word(2, 64, A.GATHER_REGS)) == \
-        {"word": 2 | (1 << 4) | (3 << 6), "lanes_per_cu": 512, "workgroup": 64, "gather": "reg-cache"}
+        {"word": 2 | (1 << 4) | (3 << 6), "lanes_per_cu": 512, "workgroup": 64, "gather": "reg-cache",
+         "xcd_parts": False}
+    assert autotune.describe(A.launch_word(1, 256, A.GATHER_DIRECT, parts=True))["xcd_parts"]
     with pytest.raises(ValueError):
         A.launch_word(2, 96, A.GATHER_REGS)
 

@@ -161,15 +161,18 @@ def test_launch_shapes_give_identical_results(storage):
     plan = TracePlan(seeds.shape[1], dev, want_steps=True)
     res = {}
     # gather 4 before the cell records exist runs the direct loads
-    shapes = [(0, 256, 4), (0, 256, 1), (2, 64, 1), (3, 128, 1), (12, 256, 1), (0, 256, 2), (2, 64, 2), (6, 128, 2),
-              (0, 256, 3), (2, 128, 3), (1, 64, 3), "cells", (1, 256, 4), (2, 64, 4), (6, 128, 4)]
+    # (lanes, workgroup, gather[, work list in per-XCD parts])
+    shapes = [(0, 256, 4), (0, 256, 1), (2, 64, 1), (3, 128, 1), (12, 256, 1), (2, 64, 1, True), (0, 256, 2),
+              (2, 64, 2), (6, 128, 2), (1, 256, 2, True), (0, 256, 3), (2, 128, 3), (1, 64, 3), (1, 256, 3, True),
+              "cells", (1, 256, 4), (2, 64, 4), (6, 128, 4), (2, 64, 4, True)]
     for shape in shapes:
         if shape == "cells":
             fg.add_cells()
             continue
-        lanes, wg, gather = shape
-        key = (lanes, wg, gather, fg.cells_ws is not None)
-        opts = make_opts(1e-5, 1e-5, step_dtype="f32", launch=A.launch_word(lanes, wg, gather))
+        lanes, wg, gather, *rest = shape
+        parts = bool(rest and rest[0])
+        key = (lanes, wg, gather, fg.cells_ws is not None, parts)
+        opts = make_opts(1e-5, 1e-5, step_dtype="f32", launch=A.launch_word(lanes, wg, gather, parts))
         out = plan.run(fg, seeds, opts)
         torch.cuda.synchronize()
         res[key] = {k: v.clone() for k, v in out.items()}
@@ -182,8 +185,9 @@ def test_launch_shapes_give_identical_results(storage):
                 continue
             for key in ref:
                 assert torch.equal(torch.nan_to_num(v[key], nan=-1.0), torch.nan_to_num(ref[key], nan=-1.0)), (k, key)
-    assert sum(1 for k in res if k[2] == 4 and k[3]) == 3
-    a, b = res[(0, 256, 1, False)], res[(0, 256, 2, False)]
+    assert sum(1 for k in res if k[2] == 4 and k[3]) == 4
+    assert sum(1 for k in res if k[4]) == 4
+    a, b = res[(0, 256, 1, False, False)], res[(0, 256, 2, False, False)]
     same = (a["status"] == b["status"]).float().mean().item()
     close = ((a["fll"] - b["fll"]).abs() <= 1e-4 * b["fll"].abs().clamp(min=1e-12)).float().mean().item()
     print(f"direct vs cached gathers: status agreement {same:.4f}, lengths within 1e-4: {close:.4f}")
@@ -210,7 +214,7 @@ def test_batch_register_cache_word_runs_direct():
         pairs = [(fg, torch.from_numpy(f["seeds"]).to(dev)) for fg, f in zip(fields, sets)]
         res = []
         for word in (A.launch_word(2, 64, A.GATHER_DIRECT), A.launch_word(2, 64, A.GATHER_REGS),
-                     A.launch_word(0, 256, A.GATHER_AUTO)):
+                     A.launch_word(0, 256, A.GATHER_AUTO), A.launch_word(1, 128, A.GATHER_DIRECT, parts=True)):
             plan = TraceBatchPlan(pairs, make_opts(1e-4, 1e-4, step_dtype="f32", launch=word), want_steps=True)
             plan.run()
             torch.cuda.synchronize()

@@ -379,10 +379,11 @@ def test_volume_map_cell_records_identical(c2):
         fg.add_cells()
     spec = VolumeSpec(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0, 5, 2, 6, 0.02, 1)
     out = []
-    for gather in (A.GATHER_CELLS, A.GATHER_REGS, A.GATHER_DIRECT):
+    for gather, parts in ((A.GATHER_CELLS, False), (A.GATHER_REGS, False), (A.GATHER_DIRECT, False),
+                          (A.GATHER_REGS, True), (A.GATHER_DIRECT, True)):
         plan = QMapPlan(spec, 8 ** 7, dev, want_steps=True)
         opts = make_opts(1e-2, 1e-2, h_init=0.1 * h, h_max=4 * h, step_dtype="f32",
-                         launch=A.launch_word(1, 256, gather))
+                         launch=A.launch_word(1, 256, gather, parts))
         plan.run(fg, opts)
         torch.cuda.synchronize()
         r = plan.result()

@@ -93,13 +93,15 @@ def parse():
                     help="map / volume: interpolation kernel (trilinear, Dodgson triquadratic, Keys tricubic)")
     ap.add_argument("--cell-records", action="store_true",
                     help="add the field's cell records (8 corner records per cell) and let the tuner try them")
+    ap.add_argument("--no-bricks", action="store_true",
+                    help="do not add the field's brick records (2x2x2 node bricks) for the tuner to try")
     ap.add_argument("--accuracy-lines", type=int, default=2048)
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the accuracy and BF16 legs after the timed region (counter runs)")
     ap.add_argument("--batch-fields", type=int, default=64)
     ap.add_argument("--learn-fields", type=int, default=2000,
                     help="learned workload: maps generated (1/4 flux-rope slices)")
-    ap.add_argument("--learn-epochs", type=int, default=12)
+    ap.add_argument("--learn-epochs", type=int, default=40)
     ap.add_argument("--learn-streams", type=int, default=4, help="learned workload: streams the scored maps use")
     ap.add_argument("--learn-batch", type=int, default=256, help="learned workload: tiles per training step")
     ap.add_argument("--learn-group", type=int, default=8, help="learned workload: maps in flight at once")
@@ -273,6 +275,8 @@ def bench_field_map(args):
     del b
     if args.cell_records:
         field.add_cells()
+    if not args.no_bricks and args.order == "linear":
+        field.add_bricks()
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
     h = min(w["spacing"])
@@ -322,11 +326,16 @@ def bench_field_map(args):
                      + autotune.candidates(lanes=(1, 2), wgs=(64, 128, 256), gathers=(A.GATHER_REGS,)))
             if args.cell_records:
                 cands += autotune.candidates(lanes=(1, 2, 4), wgs=(64, 256), gathers=(A.GATHER_CELLS,))
+            if field.bricks_ws is not None:
+                cands += autotune.candidates(lanes=(1, 2), wgs=(64, 128, 256), gathers=(A.GATHER_BRICKS,))
             batches = (args.refine_batch,) if args.refine_batch > 0 else (1, 2, 3)
             (word, batch), table = autotune.tune_map(plan, field, opts, reps=1, cands=cands, batches=batches)
         else:
             batches = (args.refine_batch,) if args.refine_batch > 0 else (1, 2, 3, 4)
-            (word, batch), table = autotune.tune_map(plan, field, opts, reps=2, batches=batches)
+            cands = autotune.candidates()
+            if field.bricks_ws is not None:
+                cands += autotune.candidates(gathers=(A.GATHER_BRICKS,))
+            (word, batch), table = autotune.tune_map(plan, field, opts, reps=2, cands=cands, batches=batches)
         opts.launch = word
         plan.d.refine_batch = batch
         tuned = dict(autotune.describe(word), refine_batch=batch, ms=table[(word, batch)], candidates=len(table),

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define QSQ_ABI_VERSION 3
+#define QSQ_ABI_VERSION 4
 
 /* return codes */
 #define QSQ_OK 0
@@ -132,6 +132,12 @@ typedef struct qsq_field {
                               h_c); grid.origin[d] and grid.origin[d] + (n[d]-1)
                               grid.spacing[d] must be its first and last coordinates
                               (the box).  qsq_field_init sets NULL */
+    void *bricks;          /* NULL, or device brick records (qsq_field_add_bricks): the
+                              node records in 2 x 2 x 2 bricks, bricks x fastest, node
+                              (i, j, k) at ((k/2 nby + j/2) nbx + i/2) 8 + 4 (k%2) +
+                              2 (j%2) + i%2 with nbx = (n0+1)/2, nby = (n1+1)/2;
+                              padding nodes zero.  Read by launch gather 5 only */
+    uint64_t brick_bytes;  /* size of the brick records (0 without) */
 } qsq_field;
 
 /* Geometry of a field (Sect. 3.1).  SPHERICAL: the grid axes are longitude phi,
@@ -180,7 +186,10 @@ typedef struct qsq_trace_opts {
  *          conditions as 2; results identical to direct loads bit for bit),
  *          4 = direct loads of the cell's corners from the field's cell
  *          records (FP32 or BF16 storage, FP32 stepping, one field per call,
- *          field with cell records; otherwise direct; identical results)
+ *          field with cell records; otherwise direct; identical results),
+ *          5 = the register cache of 3 reading the field's brick records (same
+ *          conditions as 3, field with brick records; otherwise as 3;
+ *          identical results)
  * and the flag
  *   QSQ_LAUNCH_PARTS  split the work list of the persistent stepping launch
  *          into 8 contiguous parts with a counter each; workgroup b starts in
@@ -253,6 +262,24 @@ uint64_t qsq_field_cell_bytes(const qsq_grid *g, int storage);
  * HIP.
  */
 int qsq_field_add_cells(qsq_field *f, void *ws, uint64_t ws_bytes, void *stream);
+
+/* Bytes of brick records for grid g at the given storage type: 8 node records
+ * per brick, ((n0+1)/2)((n1+1)/2)((n2+1)/2) bricks. */
+uint64_t qsq_field_brick_bytes(const qsq_grid *g, int storage);
+
+/*
+ * Add brick records to a prepared field: the node records reordered into
+ * 2 x 2 x 2 bricks (layout at qsq_field.bricks) in `ws` (device, >=
+ * qsq_field_brick_bytes, 256-byte aligned), so that the 8 corners of a cell
+ * (Sect. 3.2) touch fewer cache lines (a brick of FP32 records is one
+ * 128-byte line); the stepping kernel reads them with
+ * launch gather 5, every other pass reads f->nodes; the values, and so every
+ * result, are those of the node records.  Trilinear Cartesian fields with
+ * uniform axes only.  Sets f->bricks and f->brick_bytes.  Errors: INVALID_ARG
+ * (f invalid, ws NULL or misaligned), UNSUPPORTED (higher order, spherical or
+ * rectilinear field), WORKSPACE_TOO_SMALL, HIP.
+ */
+int qsq_field_add_bricks(qsq_field *f, void *ws, uint64_t ws_bytes, void *stream);
 
 /* ---- tracing (Sect. 3.1-3.5) ------------------------------------------ */
 

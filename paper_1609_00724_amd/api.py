@@ -38,13 +38,14 @@ def _bytes_tensor(nbytes, device):
 
 
 class Field:
-    """A prepared field: node records (and, if added, cell records) in
-    torch-owned device workspaces."""
+    """A prepared field: node records (and, if added, cell or brick records)
+    in torch-owned device workspaces."""
 
     def __init__(self, desc: A.FieldDesc, ws: torch.Tensor):
         self.desc = desc
         self.ws = ws
         self.cells_ws = None
+        self.bricks_ws = None
 
     def add_cells(self, stream=None):
         """Add cell records (the 8 corner records of every cell, contiguous),
@@ -53,6 +54,15 @@ class Field:
         ws = _bytes_tensor(nbytes, self.ws.device)
         check(lib.qsq_field_add_cells(C.byref(self.desc), _p(ws), ws.numel() * 8, _stream(stream)))
         self.cells_ws = ws
+        return self
+
+    def add_bricks(self, stream=None):
+        """Add brick records (the node records in 2 x 2 x 2 bricks), read by
+        the stepping kernel's gather 5; returns self."""
+        nbytes = lib.qsq_field_brick_bytes(C.byref(self.desc.grid), self.desc.storage)
+        ws = _bytes_tensor(nbytes, self.ws.device)
+        check(lib.qsq_field_add_bricks(C.byref(self.desc), _p(ws), ws.numel() * 8, _stream(stream)))
+        self.bricks_ws = ws
         return self
 
     @property

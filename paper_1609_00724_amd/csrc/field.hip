@@ -114,6 +114,54 @@ hipError_t launch_cell_records(const qsq_field *f, void *ws, hipStream_t st)
     return hipGetLastError();
 }
 
+// Brick records: the node records in 2 x 2 x 2 bricks, bricks x fastest,
+// node (i, j, k) at ((bk nby + bj) nbx + bi) 8 + 4 (k & 1) + 2 (j & 1) + (i & 1)
+// with (bi, bj, bk) = (i, j, k) / 2; the nodes of a brick fill one 128-byte
+// line (FP32), so a cell's 8 corners span 1 to 8 lines (3.4 on average)
+// rather than the 4 to 8 of the x-fastest layout.  Padding nodes are zero.
+template <typename R>
+__global__ void __launch_bounds__(256) k_brick_records(const R *__restrict__ nodes, int64_t nx, int64_t ny, int64_t nz,
+                                                       int64_t nbx, int64_t nby, int64_t total, R *__restrict__ bricks)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int v = (int)(e & 7);
+        const int64_t b = e >> 3;
+        const int64_t i = 2 * (b % nbx) + (v & 1), j = 2 * ((b / nbx) % nby) + ((v >> 1) & 1),
+                      k = 2 * (b / (nbx * nby)) + (v >> 2);
+        R r{};
+        if (i < nx && j < ny && k < nz) r = nodes[(k * ny + j) * nx + i];
+        bricks[e] = r;
+    }
+}
+
+uint64_t brick_record_bytes(const qsq_grid *g, int storage)
+{
+    const uint64_t rec = storage == QSQ_F64 ? 32 : storage == QSQ_F32 ? 16 : 8;
+    return 8 * rec * (uint64_t)((g->n[0] + 1) / 2) * (uint64_t)((g->n[1] + 1) / 2) * (uint64_t)((g->n[2] + 1) / 2);
+}
+
+hipError_t launch_brick_records(const qsq_field *f, void *ws, hipStream_t st)
+{
+    const int64_t nx = f->grid.n[0], ny = f->grid.n[1], nz = f->grid.n[2];
+    const int64_t nbx = (nx + 1) / 2, nby = (ny + 1) / 2, nbz = (nz + 1) / 2;
+    const int64_t total = 8 * nbx * nby * nbz;
+    const int cus = device_cu_count();
+    const int64_t want = (total + 255) / 256;
+    const int blocks = (int)(want < (int64_t)cus * 32 ? want : (int64_t)cus * 32);
+    if (f->storage == QSQ_F32)
+        hipLaunchKernelGGL(k_brick_records<float4>, dim3(blocks), dim3(256), 0, st,
+                           static_cast<const float4 *>(f->nodes), nx, ny, nz, nbx, nby, total, static_cast<float4 *>(ws));
+    else if (f->storage == QSQ_BF16)
+        hipLaunchKernelGGL(k_brick_records<uint2>, dim3(blocks), dim3(256), 0, st,
+                           static_cast<const uint2 *>(f->nodes), nx, ny, nz, nbx, nby, total, static_cast<uint2 *>(ws));
+    else
+        hipLaunchKernelGGL(k_brick_records<double4>, dim3(blocks), dim3(256), 0, st,
+                           static_cast<const double4 *>(f->nodes), nx, ny, nz, nbx, nby, total,
+                           static_cast<double4 *>(ws));
+    return hipGetLastError();
+}
+
 hipError_t launch_field_init(const qsq_grid *g, const void *bx, const void *by, const void *bz,
                              int in_dtype, int storage, int mode, void *ws, hipStream_t st)
 {

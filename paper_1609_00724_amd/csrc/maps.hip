@@ -1035,6 +1035,7 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
     TraceJob job{};
     job.nodes = f->nodes;
     job.cells = f->cells;
+    job.bricks = f->bricks;
     job.storage = f->storage;
     job.mode = job_mode(f);
     job.g = g;

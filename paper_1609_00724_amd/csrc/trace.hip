@@ -576,7 +576,12 @@ __device__ __forceinline__ void refresh_corner(__amdgpu_buffer_rsrc_t rsrc, int 
     c.z = miss ? z : c.z;
 }
 
-template <typename T, typename S, int MODE>
+// BRICKS: the records are the field's brick records (2 x 2 x 2 node bricks,
+// bricks x fastest): node (i, j, k) sits at ((k/2 nby + j/2) nbx + i/2) 8 +
+// 4 (k & 1) + 2 (j & 1) + (i & 1), so the step from a corner to its neighbour
+// along an axis is 1, 2, 4 records from an even index and 7, 8 nbx - 2,
+// 8 nbx nby - 4 from an odd one
+template <typename T, typename S, int MODE, bool BRICKS = false>
 __device__ __forceinline__ T rhs_regs(__amdgpu_buffer_rsrc_t rsrc, int bytes, const Geom &g, const int ib[3],
                                       const T q[3], T sigma, const T d1[3], const T d2[3], T kx[3], T k1[3],
                                       T k2[3], int &cell, Brick &br)
@@ -585,21 +590,34 @@ __device__ __forceinline__ T rhs_regs(__amdgpu_buffer_rsrc_t rsrc, int bytes, co
     T t[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) cell_of(ib[d], q[d], g.n[d], c[d], t[d]);
-    const int sy = g.n[0], sz = g.n[0] * g.n[1];
-    const int b = c[2] * sz + c[1] * sy + c[0];
+    int b, sx, sy, sz;
+    if constexpr (BRICKS) {
+        const int nbx = (g.n[0] + 1) >> 1, nby = (g.n[1] + 1) >> 1;
+        b = (((c[2] >> 1) * nby + (c[1] >> 1)) * nbx + (c[0] >> 1)) * 8 + ((c[2] & 1) << 2) + ((c[1] & 1) << 1) +
+            (c[0] & 1);
+        sx = (c[0] & 1) ? 7 : 1;
+        sy = (c[1] & 1) ? 8 * nbx - 2 : 2;
+        sz = (c[2] & 1) ? 8 * nbx * nby - 4 : 4;
+    } else {
+        sx = 1;
+        sy = g.n[0];
+        sz = g.n[0] * g.n[1];
+        b = c[2] * sz + c[1] * sy + c[0];
+    }
     const bool miss = b != cell;
     if (__ballot(miss)) {
         constexpr int NB = node_bytes<S>();
+        // lanes that stayed in their cell read past the end (no access, zeros) and keep their registers
         const int o = miss ? NB * b : bytes;
-        const int oy = NB * sy, oz = NB * sz;
+        const int ox = NB * sx, oy = NB * sy, oz = NB * sz;
         refresh_corner<S>(rsrc, o, miss, br.c000);
-        refresh_corner<S>(rsrc, o + NB, miss, br.c100);
+        refresh_corner<S>(rsrc, o + ox, miss, br.c100);
         refresh_corner<S>(rsrc, o + oy, miss, br.c010);
-        refresh_corner<S>(rsrc, o + oy + NB, miss, br.c110);
+        refresh_corner<S>(rsrc, o + oy + ox, miss, br.c110);
         refresh_corner<S>(rsrc, o + oz, miss, br.c001);
-        refresh_corner<S>(rsrc, o + oz + NB, miss, br.c101);
+        refresh_corner<S>(rsrc, o + oz + ox, miss, br.c101);
         refresh_corner<S>(rsrc, o + oz + oy, miss, br.c011);
-        refresh_corner<S>(rsrc, o + oz + oy + NB, miss, br.c111);
+        refresh_corner<S>(rsrc, o + oz + oy + ox, miss, br.c111);
         cell = b;
     }
     T val[3], dx[3], dy[3], dz[3];
@@ -672,7 +690,7 @@ __device__ __forceinline__ double err_ratio(double a, double b) { return a / b; 
 // gather variants of the stepping kernel: direct corner loads, the LDS cell
 // cache and the register cell cache (the caches: FP32 or BF16 storage, FP32
 // stepping, one field below 2 GiB)
-constexpr int kGatherDirect = 0, kGatherLds = 1, kGatherRegs = 2, kGatherCells = 3;
+constexpr int kGatherDirect = 0, kGatherLds = 1, kGatherRegs = 2, kGatherCells = 3, kGatherBricks = 4;
 
 // one RHS evaluation of the stepping kernel
 template <typename T, typename S, int MODE, int GATHER>
@@ -683,8 +701,9 @@ __device__ __forceinline__ T rhs_step(const S *__restrict__ nodes, __amdgpu_buff
 {
     if constexpr (GATHER == kGatherLds)
         return rhs_cached<T, S, MODE>(rsrc, bytes, g, ib, q, sigma, d1, d2, kx, k1, k2, cc, slot, stride);
-    else if constexpr (GATHER == kGatherRegs)
-        return rhs_regs<T, S, MODE>(rsrc, bytes, g, ib, q, sigma, d1, d2, kx, k1, k2, cell, br);
+    else if constexpr (GATHER == kGatherRegs || GATHER == kGatherBricks)
+        return rhs_regs<T, S, MODE, GATHER == kGatherBricks>(rsrc, bytes, g, ib, q, sigma, d1, d2, kx, k1, k2, cell,
+                                                             br);
     else
         return rhs<T, S, MODE, GATHER == kGatherCells>(nodes, g, ib, q, sigma, d1, d2, kx, k1, k2);
 }
@@ -1010,7 +1029,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EULER 
 {
     static_assert(GATHER == kGatherDirect || (!BATCH && sizeof(T) == 4),
                   "cell caches: one field per launch, FP32 corner values");
-    constexpr bool CACHED = GATHER == kGatherLds || GATHER == kGatherRegs;
+    constexpr bool CACHED = GATHER == kGatherLds || GATHER == kGatherRegs || GATHER == kGatherBricks;
     // field and step limits of the lane's line: launch constants for one
     // field, reloaded from the set table at each refill in a batch (the cell
     // records' variant reads them in place of the node records)
@@ -1036,8 +1055,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EULER 
     T ih[3] = {(T)g.ih[0], (T)g.ih[1], (T)g.ih[2]};
     unsigned long long c_att = 0, c_ev = 0, c_act = 0, c_land = 0;   // work counters
     // cached-gather state
-    const int cbytes = CACHED ? (int)((uint64_t)node_bytes<S>() * g.n[0] * g.n[1] * g.n[2]) : 0;
-    const __amdgpu_buffer_rsrc_t rsrc = node_rsrc(job.nodes, cbytes);
+    const uint64_t nrec = GATHER == kGatherBricks
+                              ? 8 * (uint64_t)((g.n[0] + 1) / 2) * ((g.n[1] + 1) / 2) * ((g.n[2] + 1) / 2)
+                              : (uint64_t)g.n[0] * g.n[1] * g.n[2];
+    const int cbytes = CACHED ? (int)(node_bytes<S>() * nrec) : 0;
+    const __amdgpu_buffer_rsrc_t rsrc = node_rsrc(GATHER == kGatherBricks ? job.bricks : job.nodes, cbytes);
     int cache_cell[3] = {-1, -1, -1};
     // LDS cell cache: kCachePlanes planes of blockDim.x float4 (dynamic size)
     extern __shared__ float4 lds_cache[];
@@ -2348,10 +2370,15 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
     if constexpr (cacheable && !BATCH) {
         // the cell caches address the node records with 32-bit byte offsets
         const uint64_t field_bytes = (uint64_t)node_bytes<S>() * job.g.n[0] * job.g.n[1] * job.g.n[2];
-        const bool fits = field_bytes < ((uint64_t)1 << 31) - ((uint64_t)1 << 26);
-        if (gather == 4 && job.cells) {
+        const uint64_t brick_bytes = (uint64_t)node_bytes<S>() * 8 * ((job.g.n[0] + 1) / 2) *
+                                     ((job.g.n[1] + 1) / 2) * ((job.g.n[2] + 1) / 2);
+        const uint64_t limit = ((uint64_t)1 << 31) - ((uint64_t)1 << 26);
+        const bool fits = field_bytes < limit;
+        if (gather == 5 && job.bricks && brick_bytes < limit) {
+            kern = trace_kernel<T, S, MODE, kGatherBricks, false>(euler);
+        } else if (gather == 4 && job.cells) {
             kern = trace_kernel<T, S, MODE, kGatherCells, false>(euler);
-        } else if ((gather == 3 || gather == 0) && fits) {
+        } else if ((gather == 3 || gather == 5 || gather == 0) && fits) {
             kern = trace_kernel<T, S, MODE, kGatherRegs, false>(euler);
         } else if (gather == 2 && fits) {
             kern = trace_kernel<T, S, MODE, kGatherLds, false>(euler);

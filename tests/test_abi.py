@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol(qsq):
 
 def test_version_and_strings(qsq):
     from paper_1609_00724_amd import _abi as A
-    assert qsq.lib.qsq_abi_version() == 3
+    assert qsq.lib.qsq_abi_version() == 4
     for code in range(12):
         assert qsq.lib.qsq_status_string(code) != b"unknown code"
     for code in (A.ERR_INVALID_ARG, A.ERR_UNSUPPORTED, A.ERR_WORKSPACE_TOO_SMALL, A.ERR_HIP, A.ERR_COUNT_OVERFLOW):
@@ -95,7 +95,7 @@ def test_invalid_arguments_rejected_before_launch(qsq):
     assert L.qsq_trace(C.byref(f), _fake(7), 10, C.byref(o), C.byref(t), _fake(8), 1 << 20, None) == \
         A.ERR_UNSUPPORTED
     o.step_dtype = A.F32
-    for bad in (0x30, 0x400, 0x140):      # workgroup code 3; bits above the word; gather 5
+    for bad in (0x30, 0x400, 0x180):      # workgroup code 3; bits above the word; gather 6
         o.launch = bad
         assert L.qsq_trace(C.byref(f), _fake(7), 10, C.byref(o), C.byref(t), _fake(8), 1 << 20, None) == \
             A.ERR_INVALID_ARG
@@ -267,3 +267,24 @@ def test_base_given_flag_checked(qsq):
     d.base_given = 2
     rc = qsq.lib.qsq_qmap(C.byref(f), C.byref(d), C.byref(o), None, None, 0, None)
     assert rc == A.ERR_INVALID_ARG and b"base_given" in qsq.lib.qsq_last_error()
+
+
+def test_brick_record_sizes_and_limits(qsq):
+    """Brick records: 8 records per 2x2x2 brick of the (padded) grid; fields
+    other than trilinear, Cartesian and uniform are refused before any work."""
+    from paper_1609_00724_amd import _abi as A
+    g = A.Grid()
+    g.n[:] = (5, 4, 3)
+    assert qsq.lib.qsq_field_brick_bytes(C.byref(g), A.F32) == 8 * 16 * 3 * 2 * 2
+    assert qsq.lib.qsq_field_brick_bytes(C.byref(g), A.BF16) == 8 * 8 * 3 * 2 * 2
+    assert qsq.lib.qsq_field_brick_bytes(C.byref(g), A.F64) == 8 * 32 * 3 * 2 * 2
+    f = A.FieldDesc()
+    f.grid.n[:] = (8, 8, 8)
+    f.grid.spacing[:] = (1.0, 1.0, 1.0)
+    f.storage, f.mode, f.nodes, f.bytes = A.F32, A.INTERP_PAPER, 256, 8 ** 3 * 16
+    f.order = A.ORDER_CUBIC
+    rc = qsq.lib.qsq_field_add_bricks(C.byref(f), 256, 1 << 20, None)
+    assert rc == A.ERR_UNSUPPORTED and b"brick" in qsq.lib.qsq_last_error()
+    f.order = A.ORDER_LINEAR
+    rc = qsq.lib.qsq_field_add_bricks(C.byref(f), 256, 16, None)
+    assert rc == A.ERR_WORKSPACE_TOO_SMALL

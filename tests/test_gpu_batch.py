@@ -137,7 +137,7 @@ def test_batch_graph_replay():
             for key in r:
                 assert torch.equal(o[key], r[key]), f"replay {rep} set {k} {key}"
         assert torch.equal(plan.work, work_ref), f"replay {rep} work"
-    assert q.lib.qsq_abi_version() == 3
+    assert q.lib.qsq_abi_version() == 4
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
@@ -164,10 +164,14 @@ def test_launch_shapes_give_identical_results(storage):
     # (lanes, workgroup, gather[, work list in per-XCD parts])
     shapes = [(0, 256, 4), (0, 256, 1), (2, 64, 1), (3, 128, 1), (12, 256, 1), (2, 64, 1, True), (0, 256, 2),
               (2, 64, 2), (6, 128, 2), (1, 256, 2, True), (0, 256, 3), (2, 128, 3), (1, 64, 3), (1, 256, 3, True),
-              "cells", (1, 256, 4), (2, 64, 4), (6, 128, 4), (2, 64, 4, True)]
+              "cells", (1, 256, 4), (2, 64, 4), (6, 128, 4), (2, 64, 4, True),
+              "bricks", (1, 256, 5), (2, 64, 5), (2, 128, 5, True)]
     for shape in shapes:
         if shape == "cells":
             fg.add_cells()
+            continue
+        if shape == "bricks":
+            fg.add_bricks()
             continue
         lanes, wg, gather, *rest = shape
         parts = bool(rest and rest[0])
@@ -176,8 +180,8 @@ def test_launch_shapes_give_identical_results(storage):
         out = plan.run(fg, seeds, opts)
         torch.cuda.synchronize()
         res[key] = {k: v.clone() for k, v in out.items()}
-    # direct loads, the register cache and the cell records: one group
-    group = {1: 1, 2: 2, 3: 1, 4: 1}
+    # direct loads, the register cache (node or brick records) and the cell records: one group
+    group = {1: 1, 2: 2, 3: 1, 4: 1, 5: 1}
     for g in (1, 2):
         ref = next(v for k, v in res.items() if group[k[2]] == g)
         for k, v in res.items():
@@ -186,7 +190,8 @@ def test_launch_shapes_give_identical_results(storage):
             for key in ref:
                 assert torch.equal(torch.nan_to_num(v[key], nan=-1.0), torch.nan_to_num(ref[key], nan=-1.0)), (k, key)
     assert sum(1 for k in res if k[2] == 4 and k[3]) == 4
-    assert sum(1 for k in res if k[4]) == 4
+    assert sum(1 for k in res if k[4]) == 5
+    assert sum(1 for k in res if k[2] == 5) == 3
     a, b = res[(0, 256, 1, False, False)], res[(0, 256, 2, False, False)]
     same = (a["status"] == b["status"]).float().mean().item()
     close = ((a["fll"] - b["fll"]).abs() <= 1e-4 * b["fll"].abs().clamp(min=1e-12)).float().mean().item()

@@ -377,10 +377,13 @@ def test_volume_map_cell_records_identical(c2):
     fg = c2["fg"]
     if fg.cells_ws is None:
         fg.add_cells()
+    if fg.bricks_ws is None:
+        fg.add_bricks()
     spec = VolumeSpec(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0, 5, 2, 6, 0.02, 1)
     out = []
     for gather, parts in ((A.GATHER_CELLS, False), (A.GATHER_REGS, False), (A.GATHER_DIRECT, False),
-                          (A.GATHER_REGS, True), (A.GATHER_DIRECT, True)):
+                          (A.GATHER_REGS, True), (A.GATHER_DIRECT, True), (A.GATHER_BRICKS, False),
+                          (A.GATHER_BRICKS, True)):
         plan = QMapPlan(spec, 8 ** 7, dev, want_steps=True)
         opts = make_opts(1e-2, 1e-2, h_init=0.1 * h, h_max=4 * h, step_dtype="f32",
                          launch=A.launch_word(1, 256, gather, parts))

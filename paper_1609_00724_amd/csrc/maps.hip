@@ -459,23 +459,49 @@ __global__ void __launch_bounds__(256) k_scan_apply(const int32_t *v, const int6
 }
 
 // A refinement round decides D levels at once: every firing gap (size G keys)
-// gets its S = 2^D - 1 interior keys at spacing unit = G / 2^D traced.
+// gets the S = 2^D - 1 keys of its bisection tree of depth D traced -- at
+// spacing unit = G / 2^D on the regular lattice, or, where the gaps are
+// irregular (after proposals), by repeated integer midpoints (an interval of
+// fewer than 2 keys cannot be split: its slot repeats its first key and is
+// never kept).
 struct Round {
     int D, S;
     uint64_t unit;
+    int irregular;
+    int pad;
 };
+
+// key of node j (1 .. 2^D - 1, in order) of the depth-D bisection tree of the
+// gap [k0, k1): integer midpoints, as the pass-by-pass rule inserts them
+__device__ __forceinline__ uint64_t tree_key(uint64_t k0, uint64_t k1, int D, int j)
+{
+    int lo = 0, hi = 1 << D;
+    uint64_t s = k0, e = k1;
+    for (;;) {
+        const int mi = (lo + hi) >> 1;
+        const uint64_t mk = s + ((e - s) >> 1);
+        if (j == mi) return mk;
+        if (j < mi) {
+            hi = mi;
+            e = mk;
+        } else {
+            lo = mi;
+            s = mk;
+        }
+    }
+}
 
 // Round set-up on the device: rem levels are left; the round decides
 // D = min(batch, rem) levels at once, fewer if the firing gaps' speculative
 // keys would not fit the trace slots (D = 1 always fits: one key per firing
 // gap, and gaps are fewer than samples).  When no gap fires, no gap can fire at
 // a finer level either (the samples do not change), so the refinement is over.
-__global__ void k_round_setup(const int64_t *n_fire, int batch, int64_t slots, int64_t *rem, Round *rd,
+__global__ void k_round_setup(const int64_t *n_fire, int batch, int irregular, int64_t slots, int64_t *rem, Round *rd,
                               int64_t *n_eff, int64_t *n_seeds, int32_t *overflow)
 {
     const int64_t nf = *n_fire;
     const int rm = (int)*rem;
-    Round r{0, 0, 0};
+    Round r{0, 0, 0, irregular, 0};
     int64_t ne = 0;
     if (rm > 0 && nf > 0) {
         int D = batch < rm ? batch : rm;
@@ -508,10 +534,11 @@ __global__ void k_spec_seeds(Region rg, const Round *rdp, Samples a, const int64
         if (!flag[i] || fpos[i] >= ne) continue;
         const int64_t base = (int64_t)fpos[i] * rd.S;
         const uint64_t k0 = a.keys[i];
+        const uint64_t k1 = a.keys[i + 1];
         for (int j = 1; j <= rd.S; ++j) {
-            // one pass: the midpoint of the gap, which is any size once proposals
-            // were merged (k0 + unit on the regular lattice)
-            const uint64_t k = rd.D == 1 ? k0 + ((a.keys[i + 1] - k0) >> 1) : k0 + (uint64_t)j * rd.unit;
+            // the regular lattice: k0 + j unit; irregular gaps (any size once
+            // proposals were merged): the bisection tree's integer midpoints
+            const uint64_t k = rd.irregular || rd.D == 1 ? tree_key(k0, k1, rd.D, j) : k0 + (uint64_t)j * rd.unit;
             uint32_t c[3];
             cell_of_key<DIM>(rg.L, k, c);
             const int64_t p = base + j - 1;
@@ -527,7 +554,8 @@ __global__ void k_spec_seeds(Region rg, const Round *rdp, Samples a, const int64
 // interval at depth d (length 2^(D-d) units) is split iff its parent was split,
 // its ends differ in length by more than thr and its key gap is >= 2; the
 // midpoints of split intervals are kept.  Bit j-1 of the mask keeps key j.
-__device__ __forceinline__ uint32_t keep_mask(const Round &rd, double thr, double f0, double fG, const double *fs)
+__device__ __forceinline__ uint32_t keep_mask(const Round &rd, double thr, double f0, double fG, const double *fs,
+                                              uint64_t k0, uint64_t kG, const uint64_t *ks)
 {
     const int N = 1 << rd.D;
     uint32_t keep = 0, active = 1;   // the whole gap fired
@@ -539,11 +567,12 @@ __device__ __forceinline__ uint32_t keep_mask(const Round &rd, double thr, doubl
             const int m = a * L + L / 2;
             keep |= 1u << (m - 1);
             if (d + 1 < rd.D) {
-                const uint64_t kg = (uint64_t)(L / 2) * rd.unit;
                 for (int c = 0; c < 2; ++c) {
                     const int s = a * L + c * (L / 2), e = s + L / 2;
                     const double fs_ = s == 0 ? f0 : fs[s - 1];
                     const double fe_ = e == N ? fG : fs[e - 1];
+                    // key gap of the child (L/2 units on the regular lattice)
+                    const uint64_t kg = (e == N ? kG : ks[e - 1]) - (s == 0 ? k0 : ks[s - 1]);
                     if (kg >= 2 && fabs(fe_ - fs_) > thr) next |= 1u << (2 * a + c);
                 }
             }
@@ -554,8 +583,8 @@ __device__ __forceinline__ uint32_t keep_mask(const Round &rd, double thr, doubl
 }
 
 __global__ void k_select(Region rg, const Round *rdp, Samples a, const int64_t *count_in, const int32_t *flag,
-                         const int32_t *fpos, const int64_t *n_eff, const double *nfll, int32_t *kcnt,
-                         uint32_t *kmask)
+                         const int32_t *fpos, const int64_t *n_eff, const double *nfll, const uint64_t *nkeys,
+                         int32_t *kcnt, uint32_t *kmask)
 {
     const Round rd = *rdp;
     const int64_t count = *count_in, ne = *n_eff;
@@ -563,7 +592,8 @@ __global__ void k_select(Region rg, const Round *rdp, Samples a, const int64_t *
         int32_t c = 0;
         if (flag[i] && fpos[i] < ne) {
             const int64_t p = fpos[i];
-            const uint32_t mk = keep_mask(rd, rg.thr, a.fll[i], a.fll[i + 1], nfll + p * rd.S);
+            const uint32_t mk = keep_mask(rd, rg.thr, a.fll[i], a.fll[i + 1], nfll + p * rd.S, a.keys[i],
+                                          a.keys[i + 1], nkeys + p * rd.S);
             kmask[p] = mk;
             c = __popc(mk);
         }
@@ -1092,10 +1122,11 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
     hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, st, rem, (int64_t)levels);
     Samples cur = A, nxt = Bs;
     int step = 0;      // sample-count slot of the current sample list
+    bool irregular = false;   // gaps no longer on the regular lattice (proposals merged)
     if (propose && levels > 0) {
         // proposals first: trace the finest cells of every proposed base cell
-        // and merge them in; the gaps are irregular from here on, so the rule
-        // runs one pass per round
+        // and merge them in; the gaps are irregular from here on, so the
+        // rounds take the bisection trees of the gaps as they are
         int64_t *n_prop = &counts[kPropWords], *n_eff = n_prop + 1, *n_seeds = n_prop + 2;
         hipLaunchKernelGGL(k_prop_flags, dim3(grid_for(nb)), dim3(256), 0, st, propose, nb, flag);
         launch_scan(flag, &counts[0], Lo.nblocks, bsum, fpos, n_prop, st);
@@ -1116,7 +1147,7 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
         cur = nxt;
         nxt = t;
         step = 1;
-        batch = 1;
+        irregular = true;
     }
     if (shift > 0) {
         // cycles of two passes: the rule along the curve (one new key per
@@ -1143,7 +1174,7 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
             hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, st, rem, (int64_t)1);
             hipLaunchKernelGGL(k_fire, dim3(grid_for(cap)), dim3(256), 0, st, cur, cin, rg.thr, flag);
             launch_scan(flag, cin, Lo.nblocks, bsum, fpos, n_fire, st);
-            hipLaunchKernelGGL(k_round_setup, dim3(1), dim3(1), 0, st, n_fire, 1, Lo.tcap, rem, &rds[cyc], n_eff,
+            hipLaunchKernelGGL(k_round_setup, dim3(1), dim3(1), 0, st, n_fire, 1, 1, Lo.tcap, rem, &rds[cyc], n_eff,
                                n_seeds, out->overflow);
             hipLaunchKernelGGL((k_spec_seeds<DIM>), dim3(grid_for(cap)), dim3(256), 0, st, rg, &rds[cyc], cur, cin,
                                flag, fpos, n_eff, Lo.tcap, seeds, N.keys);
@@ -1155,7 +1186,7 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
             e = launch_trace(job, step_dtype, st);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k_select, dim3(grid_for(cap)), dim3(256), 0, st, rg, &rds[cyc], cur, cin, flag, fpos,
-                               n_eff, N.fll, kcnt, kmask);
+                               n_eff, N.fll, N.keys, kcnt, kmask);
             launch_scan(kcnt, cin, Lo.nblocks, bsum, koff, n_kept, st);
             hipLaunchKernelGGL(k_merge, dim3(grid_for(cap)), dim3(256), 0, st, &rds[cyc], cur, nxt, N, cin, flag,
                                fpos, n_eff, kcnt, koff, kmask, cap);
@@ -1198,8 +1229,8 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
                 *n_kept = n_fire + 3;
         hipLaunchKernelGGL(k_fire, dim3(grid_for(cap)), dim3(256), 0, st, cur, cin, rg.thr, flag);
         launch_scan(flag, cin, Lo.nblocks, bsum, fpos, n_fire, st);
-        hipLaunchKernelGGL(k_round_setup, dim3(1), dim3(1), 0, st, n_fire, batch, Lo.tcap, rem, &rds[round], n_eff,
-                           n_seeds, out->overflow);
+        hipLaunchKernelGGL(k_round_setup, dim3(1), dim3(1), 0, st, n_fire, batch, irregular ? 1 : 0, Lo.tcap, rem,
+                           &rds[round], n_eff, n_seeds, out->overflow);
         hipLaunchKernelGGL((k_spec_seeds<DIM>), dim3(grid_for(cap)), dim3(256), 0, st, rg, &rds[round], cur, cin,
                            flag, fpos, n_eff, Lo.tcap, seeds, N.keys);
         job.n_dev = n_seeds;
@@ -1210,7 +1241,7 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
         e = launch_trace(job, step_dtype, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_select, dim3(grid_for(cap)), dim3(256), 0, st, rg, &rds[round], cur, cin, flag, fpos,
-                           n_eff, N.fll, kcnt, kmask);
+                           n_eff, N.fll, N.keys, kcnt, kmask);
         launch_scan(kcnt, cin, Lo.nblocks, bsum, koff, n_kept, st);
         hipLaunchKernelGGL(k_merge, dim3(grid_for(cap)), dim3(256), 0, st, &rds[round], cur, nxt, N, cin, flag, fpos,
                            n_eff, kcnt, koff, kmask, cap);

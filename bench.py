@@ -113,6 +113,8 @@ def parse():
                     metavar=("NAME", "FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write profiles/k_trace_traffic_NAME.json from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE "
                          "csv outputs of this benchmark (workload NAME) and of --calibrate-copy")
+    ap.add_argument("--pmc-launch", type=int, default=None,
+                    help="with --summarize-pmc: the launch word the counter runs used (recorded in the summary)")
     return ap.parse_args()
 
 
@@ -125,7 +127,7 @@ def main():
     if args.calibrate_copy:
         return calibrate_copy()
     if args.summarize_pmc:
-        return summarize_pmc(*args.summarize_pmc)
+        return summarize_pmc(*args.summarize_pmc, launch=args.pmc_launch)
     if args.workload == "batch":
         return bench_batch(args)
     if args.workload == "learned":
@@ -373,7 +375,7 @@ def bench_field_map(args):
     own = kept_attempts / max(attempts, 1)
     own_flops = traced_flops * own
     achieved = own_flops / (ms_trace / 1e3) / 1e12 if ms_trace > 0 else 0.0
-    traffic = measured_traffic(args.workload)
+    traffic, traffic_word = measured_traffic(args.workload)
     grid_txt = "x".join(str(v) for v in w["n"])
     kernel_txt = {"linear": "", "quadratic": " (triquadratic interpolation)",
                   "cubic": " (tricubic interpolation)"}[args.order]
@@ -415,6 +417,7 @@ def bench_field_map(args):
             "frac": achieved / FP32_PEAK_TFLOPS,
             "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_launch_word": traffic_word,
             "launches": n_step,
             "avg_launch_ms": ms_trace / max(n_step, 1),
             "own_flops_per_step": own_flops / args.steps,
@@ -543,7 +546,7 @@ def _pmc_rows(d, counter):
             if r["Counter_Name"] == counter]
 
 
-def summarize_pmc(name, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
+def summarize_pmc(name, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, launch=None):
     """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by what they read for a
     plain 1 GiB copy and store the stepping kernel's bytes per launch, keyed by
     the hash of its sources (the benchmark reports null once they change)."""
@@ -564,7 +567,7 @@ def summarize_pmc(name, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
            "fetch_bytes_per_launch": sum(f) / npass * 1024.0 * fscale,
            "write_bytes_per_launch": sum(w) / npass * 1024.0 * wscale,
            "fetch_scale": fscale, "write_scale": wscale,
-           "copy_fetch_kib": sum(cf) / len(cf), "copy_write_kib": sum(cw) / len(cw)}
+           "copy_fetch_kib": sum(cf) / len(cf), "copy_write_kib": sum(cw) / len(cw), "launch_word": launch}
     out["bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
     with open(traffic_file(name), "w") as fh:
         json.dump(out, fh, indent=1)
@@ -572,15 +575,17 @@ def summarize_pmc(name, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
 
 
 def measured_traffic(name):
-    """HBM bytes per stepping-kernel launch from the committed counter summary
-    of workload `name`, or None if the kernel's sources changed since the
-    counters were taken."""
+    """(HBM bytes per stepping-kernel launch, launch word of the counter runs)
+    from the committed counter summary of workload `name`, or (None, None) if
+    the kernel's sources changed since the counters were taken."""
     try:
         with open(traffic_file(name)) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
-        return None
-    return t["bytes_per_launch"] if t.get("kernel_sources_sha256") == kernel_hash() else None
+        return None, None
+    if t.get("kernel_sources_sha256") != kernel_hash():
+        return None, None
+    return t["bytes_per_launch"], t.get("launch_word")
 
 
 def calibrate_copy():

@@ -43,18 +43,18 @@ def test_counter_summary_scales_by_the_copy(tmp_path, monkeypatch):
     out = tmp_path / "traffic.json"
     monkeypatch.setattr(bench, "traffic_file", lambda name: str(out) if name == "volume" else "/nonexistent")
     bench.summarize_pmc("volume", str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"),
-                        str(tmp_path / "cw"))
+                        str(tmp_path / "cw"), launch=834)
     t = json.loads(out.read_text())
     assert t["passes"] == 2 and t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
     assert t["fetch_bytes_per_launch"] == pytest.approx(2000.0 * 1024 * 2.0)
     assert t["write_bytes_per_launch"] == pytest.approx(200.0 * 1024)
     assert t["kernel_sources_sha256"] == bench.kernel_hash()
-    assert bench.measured_traffic("volume") == pytest.approx(t["bytes_per_launch"])
-    assert bench.measured_traffic("map") is None         # another workload's counters are not used
+    assert bench.measured_traffic("volume") == (pytest.approx(t["bytes_per_launch"]), 834)
+    assert bench.measured_traffic("map") == (None, None)         # another workload's counters are not used
     # a summary taken on other kernel sources is not reported
     t["kernel_sources_sha256"] = "0" * 64
     out.write_text(json.dumps(t))
-    assert bench.measured_traffic("volume") is None
+    assert bench.measured_traffic("volume") == (None, None)
 
 
 def test_mismatched_counter_runs_are_rejected(tmp_path, monkeypatch):

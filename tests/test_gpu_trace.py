@@ -160,6 +160,38 @@ def test_spatial_order_steps_every_line_once(oracle_mod, small_charges, n):
         assert (ref["status"] == o["status"]).mean() >= 0.99
 
 
+@pytest.mark.parametrize("n", [1, 3, 8, 9, 65, 1000])
+def test_xcd_parts_edge_counts(small_charges, n):
+    """The work list split into per-XCD parts (QSQ_LAUNCH_PARTS) with fewer
+    items than parts, than workgroups, or than one wave: every line is traced
+    once and every output equals the single-counter launch's bit for bit, for
+    the register cache and for direct loads."""
+    import torch
+
+    import paper_1609_00724_amd as q
+    from paper_1609_00724_amd import _abi as A
+    from paper_1609_00724_amd.api import TracePlan, make_opts
+    c = small_charges
+    h = min(c["spacing"])
+    fg = gpu_field(c["b"], c["origin"], c["spacing"], storage="f32")
+    dev = torch.device("cuda:0")
+    seeds = torch.from_numpy(np.ascontiguousarray(_mixed_seeds(n, 300 + n).T)).to(dev)
+    res = {}
+    for gather in (A.GATHER_REGS, A.GATHER_DIRECT):
+        for parts in (False, True):
+            plan = TracePlan(n, dev, want_steps=True)
+            opts = make_opts(1e-4, 1e-4, h_init=0.1 * h, h_max=h, step_dtype="f32",
+                             launch=A.launch_word(1, 64, gather, parts))
+            out = plan.run(fg, seeds, opts)
+            torch.cuda.synchronize()
+            res[(gather, parts)] = {k: v.clone() for k, v in out.items()}
+    ref = res[(A.GATHER_REGS, False)]
+    for key, r in res.items():
+        for k in ref:
+            assert torch.equal(torch.nan_to_num(r[k], nan=-7.0), torch.nan_to_num(ref[k], nan=-7.0)), (key, k)
+    assert int((ref["steps"][0] > 0).sum()) > 0 or n < 3
+
+
 def test_interp_normalize_fp32(oracle_mod, small_charges):
     c = small_charges
     seeds = _mixed_seeds(500, 5)

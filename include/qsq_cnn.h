@@ -27,6 +27,8 @@
  *   out     FP32 NHWC (n, h, w, 2)
  *   acts    BF16 (raw 16-bit) NHWC with 32 channels
  *   h, w    multiples of 32 (tiles of 64 x 64 in practice); n * h * w < 2^31
+ *           and h * w <= 2^24 (a tile's tensors are addressed with 32-bit
+ *           byte offsets); otherwise QSQ_ERR_COUNT_OVERFLOW
  */
 #ifndef QSQ_CNN_H
 #define QSQ_CNN_H

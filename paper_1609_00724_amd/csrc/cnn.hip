@@ -152,17 +152,21 @@ __global__ void k_prepare(const float *params, uint16_t *prep)
 // ---------------------------------------------------------------------------
 // 3x3 'same' convolution, one wave per 16-pixel strip of kConvRows rows, all
 // output channels.  The wave keeps the weight operands in registers for its
-// rows.  32-channel inputs (BF16): lane (i, kg) loads pixel x0 + i, channels
-// 8 kg .. 8 kg + 7, of each input row once; the operands shifted by one
-// pixel come from the neighbouring lanes of its row of 16 (DPP row shifts),
-// the edge pixels x0 - 1 and x0 + 16 from one halo load by lanes 0 and 15; a
-// window of three rows slides down the strip.  Inputs with CI < 32 channels
-// (FP32 with 3, BF16 with 2): the 9 taps' channels packed along K, cpad(CI)
-// per tap, each tap's channels fetched with one load.  Outputs (each
-// nullable): BF16 activations (ReLU applied), FP32 values, a BF16 copy masked
-// by mask_cm > 0 (input gradients; mask_cm is the channel-major copy of the
+// rows.  32-channel inputs (BF16): lane (i, kg) reads pixels x0 + i - 1,
+// x0 + i, x0 + i + 1, channels 8 kg .. 8 kg + 7, of each input row (three
+// 16-byte buffer loads); rows above and below the image lie outside the
+// image's buffer range and read as zeros, the pixels left and right of it
+// are zeroed by a select; a window of three rows slides down the strip and
+// the next row is fetched one row ahead.  Inputs with CI < 32 channels (FP32
+// with 3, BF16 with 2): the 9 taps' channels packed along K, cpad(CI) per
+// tap, each tap's channels fetched with one load.  Outputs (each nullable):
+// BF16 activations (ReLU applied), FP32 values, a BF16 copy masked by
+// mask_cm > 0 (input gradients; mask_cm is the channel-major copy of the
 // layer's input activations), and the channel-major copy of the BF16 output
-// (masked too when mask_cm is given).
+// (masked too when mask_cm is given).  A BF16 NHWC output of 32 channels goes
+// through LDS so that each lane stores one pixel's 8 channels (16 bytes) and
+// the wave a row's 1 KB with one store.  One tile's tensor is addressed with
+// 32-bit byte offsets (h w <= 2^24).
 // ---------------------------------------------------------------------------
 struct ConvDims {
     int64_t n;
@@ -170,6 +174,32 @@ struct ConvDims {
 };
 
 constexpr int kConvRows = 8;   // divides h (a multiple of 32)
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// buffer resource over `bytes` bytes at p (gfx9 descriptor word 3: 32-bit
+// data format, untyped access); offsets at or past `bytes` read zeros and
+// drop writes
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
+}
+
+// two FP32 values to a BF16 pair (round to nearest even), a in the low half
+__device__ __forceinline__ uint32_t pack_bf2(float a, float b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
+}
+
+// BF16 pair with each half kept where the matching half of m (BF16) is > 0
+__device__ __forceinline__ uint32_t mask_bf2(uint32_t v, uint32_t m)
+{
+    const bool lo = __uint_as_float(m << 16) > 0.0f, hi = __uint_as_float(m & 0xffff0000u) > 0.0f;
+    return (lo ? v & 0xffffu : 0u) | (hi ? v & 0xffff0000u : 0u);
+}
 
 struct Row3 {
     bf16x8 m, z, p;   // the lane's pixel shifted by -1, 0, +1
@@ -185,56 +215,117 @@ __global__ void __launch_bounds__(256) k_conv(const void *__restrict__ in, ConvD
     constexpr int NT = ntile(CO), COP = 16 * NT, NK = nchunk(CI), R = kConvRows;
     static_assert(CI >= 32 ? !SRC_F32 : (CI == 3) == SRC_F32, "FP32 input has 3 channels, BF16 input 2 or 32");
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int spr = d.w / 16, rb = d.h / R;
-    if (wave >= d.n * rb * spr) return;   // the whole wave leaves together
-    const int64_t blk = wave / spr;       // image * rb + row block
-    const int x0 = (int)(wave % spr) * 16, y0 = (int)(blk % rb) * R;
+    // workgroup: R rows of a 64-pixel column chunk of one image; wave s (a
+    // scalar, so that the buffer resources below are too) the 16-pixel strip
+    // x0 = xc + 16 s
+    const int cpr = (d.w + 63) / 64, rb = d.h / R;
+    const int64_t blk = blockIdx.x / cpr;   // image * rb + row block
+    const int xc = (int)(blockIdx.x % cpr) * 64, y0 = (int)(blk % rb) * R;
     const int64_t img = blk / rb;
+    const int sw = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int x0 = xc + 16 * sw;
     const int i = lane & 15, kg = lane >> 4;
+    const int64_t npix = (int64_t)d.h * d.w;   // pixels of one tile
+    // 32-channel inputs: the workgroup's R + 2 input rows, pixels xc - 1 ..
+    // xc + 64 (zeros outside the image), staged in LDS with all loads in
+    // flight at once: [row][pixel][4 chunks of 8 channels]
+    constexpr int PW = 66, NCH = (R + 2) * PW * 4, PER = (NCH + 255) / 256;
+    uint4 *lrows = nullptr;
+    if constexpr (CI >= 32) {
+        __shared__ uint4 rows_lds[NCH];
+        lrows = rows_lds;
+        const __amdgpu_buffer_rsrc_t rs = buf_rsrc(static_cast<const uint16_t *>(in) + img * npix * 32, (int)(npix * 64));
+        u32x4 tmp[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int c = (int)threadIdx.x + 256 * k;
+            const int r = c / (PW * 4), rem = c % (PW * 4), px = xc - 1 + (rem >> 2), q = rem & 3;
+            // rows above and below the tile lie outside the buffer range (zeros), and so
+            // do the pixels left and right of it
+            const int off = px >= 0 && px < d.w ? (((y0 - 1 + r) * d.w + px) * 32 + 8 * q) * 2 : (int)(npix * 64);
+            tmp[k] = c < NCH ? __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0) : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int c = (int)threadIdx.x + 256 * k;
+            if (c < NCH) rows_lds[c] = make_uint4(tmp[k].x, tmp[k].y, tmp[k].z, tmp[k].w);
+        }
+        __syncthreads();
+    }
+    if (x0 >= d.w) return;   // the whole wave leaves together (no barrier follows)
     bf16x8 bw[NK][NT];
 #pragma unroll
     for (int kc = 0; kc < NK; ++kc)
 #pragma unroll
         for (int t = 0; t < NT; ++t) bw[kc][t] = ld_bf16x8(wm + ((int64_t)(kc * COP + t * 16 + i) * 32 + 8 * kg));
-    // input row yy of a 32-channel input: the three shifted operands
-    auto row3 = [&](int yy) {
-        uint4 z = make_uint4(0, 0, 0, 0), hv = make_uint4(0, 0, 0, 0);
-        if (yy >= 0 && yy < d.h) {
-            const uint16_t *row = static_cast<const uint16_t *>(in) + (img * d.h + yy) * (int64_t)d.w * 32 + 8 * kg;
-            z = *reinterpret_cast<const uint4 *>(row + (int64_t)(x0 + i) * 32);
-            const int xh = i == 0 ? x0 - 1 : x0 + 16;
-            if ((i == 0 || i == 15) && xh >= 0 && xh < d.w) hv = *reinterpret_cast<const uint4 *>(row + (int64_t)xh * 32);
+    float bv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bv[t] = bias && t * 16 + i < CO ? bias[t * 16 + i] : 0.0f;
+    // the tile's channel-major tensors (mask, output copy): CO channels per row
+    const int cm_bytes = (int)(npix * CO * 2);
+    const __amdgpu_buffer_rsrc_t mask_rs = buf_rsrc(mask_cm ? mask_cm + img * npix * CO : nullptr, cm_bytes);
+    const __amdgpu_buffer_rsrc_t cm_rs = buf_rsrc(out_cm ? out_cm + img * npix * CO : nullptr, cm_bytes);
+    // byte offset of (row y, channel 16 t + i, pixel x0 + 4 kg) in them
+    auto cm_off = [&](int y, int t) { return ((y * CO + t * 16 + i) * d.w + x0 + 4 * kg) * 2; };
+    // BF16 NHWC output of 32 channels through the wave's LDS stage
+    __shared__ uint16_t stage_all[4][16 * 32];
+    uint16_t *stage = stage_all[threadIdx.x >> 6];
+    auto store_nhwc = [&](uint16_t *dst, int y, const uint32_t (&hp)[NT][2]) {
+        if constexpr (CO == 32) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    stage[(4 * kg + r) * 32 + 16 * t + i] = (uint16_t)(hp[t][r >> 1] >> (16 * (r & 1)));
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const u32x4 q = reinterpret_cast<const u32x4 *>(stage)[lane];
+            const __amdgpu_buffer_rsrc_t rs = buf_rsrc(dst + img * npix * 32, (int)(npix * 64));
+            __builtin_amdgcn_raw_buffer_store_b128(q, rs, ((y * d.w + x0) * 32 + 8 * lane) * 2, 0, 0);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int co = t * 16 + i;
+                if (co >= CO) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    dst[((img * d.h + y) * d.w + x0 + 4 * kg + r) * CO + co] = (uint16_t)(hp[t][r >> 1] >> (16 * (r & 1)));
+            }
         }
-        // row_shr:1 (lane i takes lane i - 1; lane 0 keeps its halo), row_shl:1
-        // (lane i takes lane i + 1; lane 15 keeps its halo)
-        const uint4 m = make_uint4((uint32_t)__builtin_amdgcn_update_dpp((int)hv.x, (int)z.x, 0x111, 0xf, 0xf, false),
-                                   (uint32_t)__builtin_amdgcn_update_dpp((int)hv.y, (int)z.y, 0x111, 0xf, 0xf, false),
-                                   (uint32_t)__builtin_amdgcn_update_dpp((int)hv.z, (int)z.z, 0x111, 0xf, 0xf, false),
-                                   (uint32_t)__builtin_amdgcn_update_dpp((int)hv.w, (int)z.w, 0x111, 0xf, 0xf, false));
-        const uint4 p = make_uint4((uint32_t)__builtin_amdgcn_update_dpp((int)hv.x, (int)z.x, 0x101, 0xf, 0xf, false),
-                                   (uint32_t)__builtin_amdgcn_update_dpp((int)hv.y, (int)z.y, 0x101, 0xf, 0xf, false),
-                                   (uint32_t)__builtin_amdgcn_update_dpp((int)hv.z, (int)z.z, 0x101, 0xf, 0xf, false),
-                                   (uint32_t)__builtin_amdgcn_update_dpp((int)hv.w, (int)z.w, 0x101, 0xf, 0xf, false));
-        Row3 r;
-        r.m = __builtin_bit_cast(bf16x8, m);
-        r.z = __builtin_bit_cast(bf16x8, z);
-        r.p = __builtin_bit_cast(bf16x8, p);
-        return r;
+    };
+    // the lane's three shifted operands of staged row r (input row y0 - 1 + r)
+    auto lds3 = [&](int r) {
+        const int base = (r * PW + 16 * sw + i) * 4 + kg;
+        Row3 o;
+        o.m = __builtin_bit_cast(bf16x8, lrows[base]);
+        o.z = __builtin_bit_cast(bf16x8, lrows[base + 4]);
+        o.p = __builtin_bit_cast(bf16x8, lrows[base + 8]);
+        return o;
     };
     Row3 win[3];   // input rows y - 1, y, y + 1
     if constexpr (CI >= 32) {
-        win[0] = row3(y0 - 1);
-        win[1] = row3(y0);
+        win[0] = lds3(0);
+        win[1] = lds3(1);
     }
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
         const int y = y0 + rr;
+        // mask of this row's pixels 4 kg .. 4 kg + 3, fetched before the
+        // products so that its latency overlaps them
+        u32x2 mk[NT];
+        if (mask_cm) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) mk[t] = __builtin_amdgcn_raw_buffer_load_b64(mask_rs, cm_off(y, t), 0, 0);
+        }
         f32x4 acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
         if constexpr (CI >= 32) {
-            win[2] = row3(y + 1);
+            win[2] = lds3(rr + 2);
 #pragma unroll
             for (int ty = 0; ty < 3; ++ty)
 #pragma unroll
@@ -272,32 +363,42 @@ __global__ void __launch_bounds__(256) k_conv(const void *__restrict__ in, ConvD
                 for (int t = 0; t < NT; ++t) acc[t] = mfma(a, bw[kc][t], acc[t]);
             }
         }
-        // lane holds D[pixel 4 kg + r][channel t 16 + i]
+        // lane holds D[pixel 4 kg + r][channel t 16 + i]; BF16 pairs of
+        // pixels (4 kg, 4 kg + 1) and (4 kg + 2, 4 kg + 3)
+        float v[NT][4];
+        uint32_t hp[NT][2];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int co = t * 16 + i;
-            if (co >= CO) continue;
-            const float bv = bias ? bias[co] : 0.0f;
-            const int64_t cmo = ((img * d.h + y) * CO + co) * (int64_t)d.w + x0 + 4 * kg;
-            uint2 mk = make_uint2(0u, 0u);   // mask of pixels 4 kg .. 4 kg + 3 (channel-major, BF16)
-            if (mask_cm) mk = *reinterpret_cast<const uint2 *>(mask_cm + cmo);
-            uint32_t cm[2] = {0u, 0u};   // the BF16 output of pixels 4 kg .. 4 kg + 3
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                float v = acc[t][r] + bv;
-                if (relu) v = fmaxf(v, 0.0f);
-                const int64_t pix = (img * d.h + y) * d.w + x0 + 4 * kg + r;
-                uint16_t hb = f2bf(v);
-                if (out_f32) out_f32[pix * CO + co] = v;
-                if (out_bf) out_bf[pix * CO + co] = hb;
-                if (mask_cm) {
-                    const uint32_t mw = (r < 2 ? mk.x : mk.y) >> (16 * (r & 1));
-                    hb = bf2f((uint16_t)mw) > 0.0f ? hb : (uint16_t)0;
-                    if (out_masked) out_masked[pix * CO + co] = hb;
-                }
-                cm[r >> 1] |= (uint32_t)hb << (16 * (r & 1));
+                v[t][r] = acc[t][r] + bv[t];
+                if (relu) v[t][r] = fmaxf(v[t][r], 0.0f);
             }
-            if (out_cm) *reinterpret_cast<uint2 *>(out_cm + cmo) = make_uint2(cm[0], cm[1]);
+            hp[t][0] = pack_bf2(v[t][0], v[t][1]);
+            hp[t][1] = pack_bf2(v[t][2], v[t][3]);
+        }
+        if (out_f32) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int co = t * 16 + i;
+                if (co >= CO) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) out_f32[((img * d.h + y) * d.w + x0 + 4 * kg + r) * CO + co] = v[t][r];
+            }
+        }
+        if (out_bf) store_nhwc(out_bf, y, hp);
+        if (mask_cm) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                hp[t][0] = mask_bf2(hp[t][0], mk[t].x);
+                hp[t][1] = mask_bf2(hp[t][1], mk[t].y);
+            }
+            if (out_masked) store_nhwc(out_masked, y, hp);
+        }
+        if (out_cm) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                if (t * 16 + i < CO) __builtin_amdgcn_raw_buffer_store_b64(u32x2{hp[t][0], hp[t][1]}, cm_rs, cm_off(y, t), 0, 0);
         }
     }
 }
@@ -330,32 +431,35 @@ __global__ void k_to_cm(const void *in, int64_t rows, int w, uint16_t *out)
 // x0 + 8 kg .. + 7 of channel i: one aligned 16-byte load, plus the two
 // neighbouring pixel pairs for the operands shifted by one pixel either way
 // (byte-align of adjacent dwords).  A workgroup takes R rows of one image and
-// one 32-pixel column chunk, one wave per (input tile, output tile) pair;
-// each wave slides a window of three input rows down the rows and writes its
-// sums to the workgroup's slot; k_wgrad_reduce1/2 add the slots in a fixed
-// order (deterministic).
+// a 64-pixel column chunk (both halves of each 128-byte line of a channel
+// row): one wave per (input tile, output tile) pair and 32-pixel half; each
+// wave slides a window of three input rows down the R rows, the second
+// half's sums are added to the first's through LDS, and the workgroup writes
+// them to its slot; k_wgrad_reduce1/2 add the slots in a fixed order
+// (deterministic).
 // ---------------------------------------------------------------------------
 struct Shift3 {
     bf16x8 m, z, p;   // pixels shifted by -1, 0, +1
 };
 
 template <int CI, int CO>
-__global__ void __launch_bounds__(256) k_wgrad(const uint16_t *__restrict__ xcm, const uint16_t *__restrict__ gcm,
+__global__ void __launch_bounds__(512) k_wgrad(const uint16_t *__restrict__ xcm, const uint16_t *__restrict__ gcm,
                                                ConvDims d, int R, float *__restrict__ part)
 {
-    constexpr int TI = ntile(CI), TO = ntile(CO), CIP = 16 * TI, COP = 16 * TO;
+    constexpr int TI = ntile(CI), TO = ntile(CO), CIP = 16 * TI, COP = 16 * TO, NW = TI * TO;
     constexpr int SLOT = 9 * CIP * COP + COP;
     const int lane = (int)(threadIdx.x & 63), wid = (int)(threadIdx.x >> 6);
-    const int a = wid / TO, b = wid % TO;
+    const int half = wid / NW, pw = wid % NW, a = pw / TO, b = pw % TO;
     const int i = lane & 15, kg = lane >> 4;
-    const int cpr = d.w / 32, rb = d.h / R;
+    const int cpr = (d.w + 63) / 64, rb = d.h / R;
     const int64_t unit = blockIdx.x;
-    const int x0 = (int)(unit % cpr) * 32, y0 = (int)((unit / cpr) % rb) * R;
+    const int x0 = (int)(unit % cpr) * 64 + half * 32, y0 = (int)((unit / cpr) % rb) * R;
     const int64_t img = unit / ((int64_t)cpr * rb);
+    const int RH = x0 < d.w ? R : 0;   // rows of this half (none past the right edge)
     const int xs = x0 + 8 * kg, c = a * 16 + i, co = b * 16 + i;
     auto xrow = [&](int yy) {
         uint32_t d0 = 0, d1 = 0, d2 = 0, d3 = 0, lft = 0, rgt = 0;
-        if (c < CI && yy >= 0 && yy < d.h) {
+        if (c < CI && yy >= 0 && yy < d.h && xs < d.w) {
             const uint16_t *row = xcm + ((img * d.h + yy) * CI + c) * (int64_t)d.w;
             const uint4 q = *reinterpret_cast<const uint4 *>(row + xs);
             d0 = q.x;
@@ -376,13 +480,13 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t *__restrict__ xcm,
     f32x4 acc[9];
 #pragma unroll
     for (int tp = 0; tp < 9; ++tp) acc[tp] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float dbs = 0.0f;
+    float dbs = 0.0f;   // bias gradient (waves of input tile 0 only)
     // rows go four at a time: all loads of a group are issued before its
     // products, so their latencies overlap (R is a multiple of 4)
     Shift3 win[6];   // input rows y - 1 .. y + 4
     win[0] = xrow(y0 - 1);
     win[1] = xrow(y0);
-    for (int rr = 0; rr < R; rr += 4) {
+    for (int rr = 0; rr < RH; rr += 4) {
         const int y = y0 + rr;
         bf16x8 gb[4];
 #pragma unroll
@@ -395,8 +499,10 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t *__restrict__ xcm,
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
+            if (a == 0) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) dbs += (float)gb[k][j];
+                for (int j = 0; j < 8; ++j) dbs += (float)gb[k][j];
+            }
 #pragma unroll
             for (int ty = 0; ty < 3; ++ty) {
                 acc[3 * ty + 0] = mfma(win[k + ty].m, gb[k], acc[3 * ty + 0]);
@@ -407,6 +513,18 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t *__restrict__ xcm,
         win[0] = win[4];
         win[1] = win[5];
     }
+    // the second half's sums, added to the first's in a fixed order
+    __shared__ f32x4 red[NW][9][64];
+    __shared__ float redb[TO][64];
+    if (half == 1) {
+#pragma unroll
+        for (int tp = 0; tp < 9; ++tp) red[pw][tp][lane] = acc[tp];
+        if (a == 0) redb[b][lane] = dbs;
+    }
+    __syncthreads();
+    if (half == 1) return;
+#pragma unroll
+    for (int tp = 0; tp < 9; ++tp) acc[tp] += red[pw][tp][lane];
     // lane holds D[ci = a 16 + 4 kg + r][co = b 16 + i]
     float *slot = part + unit * SLOT;
 #pragma unroll
@@ -414,6 +532,7 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t *__restrict__ xcm,
 #pragma unroll
         for (int r = 0; r < 4; ++r) slot[(tp * CIP + a * 16 + 4 * kg + r) * COP + b * 16 + i] = acc[tp][r];
     if (a == 0) {
+        dbs += redb[b][lane];
         dbs += __shfl_xor(dbs, 16);
         dbs += __shfl_xor(dbs, 32);
         if (kg == 0) slot[9 * CIP * COP + b * 16 + i] = dbs;
@@ -421,49 +540,68 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t *__restrict__ xcm,
 }
 
 // Slot sums in two fixed-order stages (deterministic for a given slot count):
-// groups of kRedGroup consecutive slots, then the groups in order.
+// groups of kRedGroup consecutive slots, then the groups in order.  One pair
+// of launches reduces the slots of up to four layers (a training step's
+// backward pass) at once.
 constexpr int kRedGroup = 32;
 
-template <int CI, int CO>
-__device__ __forceinline__ int64_t wgrad_src(int64_t e)
+struct RedSeg {
+    const float *part;   // the layer's slots
+    float *dw, *db;
+    int ci, co, cip, cop;
+    int64_t slot, nout, e0;   // slot floats, outputs, first output in the job
+};
+
+struct RedJob {
+    RedSeg s[4];
+    int nseg;
+    int64_t nslots, total;
+};
+
+// output e of the job: its segment and the offset of its value within a slot
+__device__ __forceinline__ const RedSeg &red_seg(const RedJob &J, int64_t e)
 {
-    constexpr int CIP = 16 * ntile(CI), COP = 16 * ntile(CO);
-    if (e < 9 * CI * CO) {
-        const int co = (int)(e % CO), ci = (int)((e / CO) % CI), tp = (int)(e / (CO * CI));
-        return ((int64_t)tp * CIP + ci) * COP + co;
+    int k = 0;
+    while (k + 1 < J.nseg && e >= J.s[k + 1].e0) ++k;
+    return J.s[k];
+}
+
+__device__ __forceinline__ int64_t red_src(const RedSeg &g, int64_t le)
+{
+    const int64_t nw = 9 * (int64_t)g.ci * g.co;
+    if (le < nw) {
+        const int co = (int)(le % g.co), ci = (int)((le / g.co) % g.ci), tp = (int)(le / ((int64_t)g.co * g.ci));
+        return ((int64_t)tp * g.cip + ci) * g.cop + co;
     }
-    return (int64_t)9 * CIP * COP + (e - 9 * CI * CO);
+    return 9 * (int64_t)g.cip * g.cop + (le - nw);
 }
 
 // grid (outputs / 256, slot groups): tmp[group][e] = sum of its slots
-template <int CI, int CO>
-__global__ void k_wgrad_reduce1(const float *__restrict__ part, int64_t nslots, float *__restrict__ tmp)
+__global__ void k_wgrad_reduce1(RedJob J, float *__restrict__ tmp)
 {
-    constexpr int CIP = 16 * ntile(CI), COP = 16 * ntile(CO);
-    constexpr int64_t SLOT = 9 * CIP * COP + COP, NOUT = 9 * CI * CO + CO;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= NOUT) return;
-    const int64_t src = wgrad_src<CI, CO>(e);
+    if (e >= J.total) return;
+    const RedSeg &g = red_seg(J, e);
+    const int64_t src = red_src(g, e - g.e0);
     const int64_t w0 = (int64_t)blockIdx.y * kRedGroup;
-    const int64_t w1 = w0 + kRedGroup < nslots ? w0 + kRedGroup : nslots;
+    const int64_t w1 = w0 + kRedGroup < J.nslots ? w0 + kRedGroup : J.nslots;
     float acc = 0.0f;
-    for (int64_t w = w0; w < w1; ++w) acc += part[w * SLOT + src];
-    tmp[(int64_t)blockIdx.y * NOUT + e] = acc;
+    for (int64_t w = w0; w < w1; ++w) acc += g.part[w * g.slot + src];
+    tmp[(int64_t)blockIdx.y * J.total + e] = acc;
 }
 
-template <int CI, int CO>
-__global__ void k_wgrad_reduce2(const float *__restrict__ tmp, int64_t ngroups, float *__restrict__ dw,
-                                float *__restrict__ db)
+__global__ void k_wgrad_reduce2(RedJob J, const float *__restrict__ tmp, int64_t ngroups)
 {
-    constexpr int64_t NOUT = 9 * CI * CO + CO;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= NOUT) return;
+    if (e >= J.total) return;
+    const RedSeg &g = red_seg(J, e);
     float acc = 0.0f;
-    for (int64_t k = 0; k < ngroups; ++k) acc += tmp[k * NOUT + e];
-    if (e < 9 * CI * CO)
-        dw[e] = acc;
+    for (int64_t k = 0; k < ngroups; ++k) acc += tmp[k * J.total + e];
+    const int64_t le = e - g.e0, nw = 9 * (int64_t)g.ci * g.co;
+    if (le < nw)
+        g.dw[le] = acc;
     else
-        db[e - 9 * CI * CO] = acc;
+        g.db[le - nw] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -562,8 +700,7 @@ static void conv_launch(int l, bool transposed, const void *in, ConvDims d, cons
                         float *out_f32, uint16_t *out_masked, const uint16_t *mask_cm, uint16_t *out_cm,
                         hipStream_t st)
 {
-    const int64_t waves = d.n * (d.h / kConvRows) * (d.w / 16);
-    const dim3 grid(blocks_for(waves * 64, 256)), block(256);
+    const dim3 grid((unsigned)(d.n * (d.h / kConvRows) * ((d.w + 63) / 64))), block(256);
     if (!transposed) {
         const uint16_t *wm = fwd_mat(prep, l);
         const float *b = bias_of(prep, l);
@@ -590,25 +727,38 @@ static void conv_launch(int l, bool transposed, const void *in, ConvDims d, cons
 
 // Rows per workgroup of the weight-gradient pass: the smallest power of two
 // >= 4 dividing h that keeps the slots (one per workgroup: R rows of a
-// 32-pixel column chunk) at 512 or fewer, h at most.
+// 64-pixel column chunk) at 512 or fewer, h at most.
 static int wgrad_rows(ConvDims d)
 {
     int R = 4;
-    while (R < d.h && d.h % (2 * R) == 0 && d.n * (d.h / R) * (d.w / 32) > 512) R *= 2;
+    while (R < d.h && d.h % (2 * R) == 0 && d.n * (d.h / R) * ((d.w + 63) / 64) > 512) R *= 2;
     return R;
 }
 
-static int64_t wgrad_slots(ConvDims d) { return d.n * (d.h / wgrad_rows(d)) * (d.w / 32); }
+static int64_t wgrad_slots(ConvDims d) { return d.n * (d.h / wgrad_rows(d)) * ((d.w + 63) / 64); }
 static int64_t wgrad_groups(ConvDims d) { return (wgrad_slots(d) + kRedGroup - 1) / kRedGroup; }
 
-// slots and first-stage group sums of the weight-gradient reduction
-static uint64_t wgrad_part_bytes(ConvDims d)
+static int64_t slot_floats(int l)
 {
-    const int64_t slot = 9 * 32 * 32 + 32;
-    return (uint64_t)(wgrad_slots(d) + wgrad_groups(d)) * slot * 4;
+    return 9LL * 16 * ntile(kCi[l]) * 16 * ntile(kCo[l]) + 16 * ntile(kCo[l]);
 }
 
 static uint64_t al256(uint64_t b) { return (b + 255) & ~(uint64_t)255; }
+
+// slots of one layer (at most the 32 x 32 layers' size) and its group sums
+static uint64_t wgrad_part_bytes(ConvDims d)
+{
+    return al256((uint64_t)wgrad_slots(d) * slot_floats(1) * 4) +
+           (uint64_t)wgrad_groups(d) * (9 * 32 * 32 + 32) * 4;
+}
+
+// slots of all four layers and the group sums of the whole parameter vector
+static uint64_t train_part_bytes(ConvDims d)
+{
+    uint64_t b = 0;
+    for (int l = 0; l < 4; ++l) b += al256((uint64_t)wgrad_slots(d) * slot_floats(l) * 4);
+    return b + (uint64_t)wgrad_groups(d) * QSQ_CNN_PARAMS * 4;
+}
 
 // per-layer backward: channel-major copies of the input and of dy, then the slots
 uint64_t cnn_wgrad_scratch_bytes(int64_t n, int h, int w)
@@ -617,29 +767,48 @@ uint64_t cnn_wgrad_scratch_bytes(int64_t n, int h, int w)
     return 2 * cm + wgrad_part_bytes(ConvDims{n, h, w});
 }
 
-template <int CI, int CO>
-static void wgrad_typed(const uint16_t *xcm, const uint16_t *gcm, ConvDims d, float *part, float *dw, float *db,
-                        hipStream_t st)
+// the slots of layer l (written to `part`) as a segment of a reduction job
+static void wgrad_slots_launch(int l, const uint16_t *xcm, const uint16_t *gcm, ConvDims d, float *part, float *dw,
+                               float *db, RedJob &J, hipStream_t st)
 {
-    const int64_t slots = wgrad_slots(d), groups = wgrad_groups(d);
-    const int64_t nout = 9 * CI * CO + CO;
-    float *tmp = part + slots * (int64_t)(9 * 32 * 32 + 32);
-    hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(slots), dim3(64 * ntile(CI) * ntile(CO)), 0, st, xcm, gcm, d,
-                       wgrad_rows(d), part);
-    hipLaunchKernelGGL((k_wgrad_reduce1<CI, CO>), dim3(blocks_for(nout, 256), groups), dim3(256), 0, st, part, slots,
-                       tmp);
-    hipLaunchKernelGGL((k_wgrad_reduce2<CI, CO>), dim3(blocks_for(nout, 256)), dim3(256), 0, st, tmp, groups, dw, db);
+    const int64_t slots = wgrad_slots(d);
+    const int R = wgrad_rows(d);
+    const dim3 grid(slots), block(2 * 64 * ntile(kCi[l]) * ntile(kCo[l]));
+    if (l == 0)
+        hipLaunchKernelGGL((k_wgrad<3, 32>), grid, block, 0, st, xcm, gcm, d, R, part);
+    else if (l == 3)
+        hipLaunchKernelGGL((k_wgrad<32, 2>), grid, block, 0, st, xcm, gcm, d, R, part);
+    else
+        hipLaunchKernelGGL((k_wgrad<32, 32>), grid, block, 0, st, xcm, gcm, d, R, part);
+    RedSeg &g = J.s[J.nseg++];
+    g.part = part;
+    g.dw = dw;
+    g.db = db;
+    g.ci = kCi[l];
+    g.co = kCo[l];
+    g.cip = 16 * ntile(kCi[l]);
+    g.cop = 16 * ntile(kCo[l]);
+    g.slot = slot_floats(l);
+    g.nout = 9LL * kCi[l] * kCo[l] + kCo[l];
+    g.e0 = J.total;
+    J.total += g.nout;
+    J.nslots = slots;
+}
+
+static void wgrad_reduce(const RedJob &J, float *tmp, ConvDims d, hipStream_t st)
+{
+    const int64_t groups = wgrad_groups(d);
+    hipLaunchKernelGGL(k_wgrad_reduce1, dim3(blocks_for(J.total, 256), groups), dim3(256), 0, st, J, tmp);
+    hipLaunchKernelGGL(k_wgrad_reduce2, dim3(blocks_for(J.total, 256)), dim3(256), 0, st, J, (const float *)tmp,
+                       groups);
 }
 
 static void wgrad_launch(int l, const uint16_t *xcm, const uint16_t *gcm, ConvDims d, float *part, float *dw,
                          float *db, hipStream_t st)
 {
-    if (l == 0)
-        wgrad_typed<3, 32>(xcm, gcm, d, part, dw, db, st);
-    else if (l == 3)
-        wgrad_typed<32, 2>(xcm, gcm, d, part, dw, db, st);
-    else
-        wgrad_typed<32, 32>(xcm, gcm, d, part, dw, db, st);
+    RedJob J{};
+    wgrad_slots_launch(l, xcm, gcm, d, part, dw, db, J, st);
+    wgrad_reduce(J, part + al256((uint64_t)wgrad_slots(d) * slot_floats(1) * 4) / 4, d, st);
 }
 
 template <int C, bool SRC_F32>
@@ -716,7 +885,7 @@ static CnnWs ws_layout(void *base, int64_t n, int h, int w)
     s.grad = reinterpret_cast<float *>(take(QSQ_CNN_PARAMS * 4));
     s.lpart = reinterpret_cast<double *>(take(kLossBlocks * 8));
     s.loss = reinterpret_cast<double *>(take(8));
-    s.part = reinterpret_cast<float *>(take(wgrad_part_bytes(ConvDims{n, h, w})));
+    s.part = reinterpret_cast<float *>(take(train_part_bytes(ConvDims{n, h, w})));
     s.total = o;
     return s;
 }
@@ -757,11 +926,16 @@ hipError_t cnn_train_step(float *params, float *adam_m, float *adam_v, int64_t t
     float *g = grad_out ? grad_out : s.grad;
     // layer 4 .. 1: weight gradients, then the input gradient masked by the
     // ReLU of the layer below (its BF16 activation > 0)
+    // (each layer's weight-gradient slots in a region of their own; one
+    // reduction of all four layers after the last)
     const uint16_t *gin = s.gout, *gin_cm = s.gout_cm;
+    RedJob J{};
+    float *part = s.part;
     for (int l = 3; l >= 0; --l) {
         const uint16_t *xcm = l == 0 ? s.x_cm : s.act_cm[l - 1];
         float *dw = g + master_w(l), *db = dw + 9 * kCi[l] * kCo[l];
-        wgrad_launch(l, xcm, gin_cm, d, s.part, dw, db, st);
+        wgrad_slots_launch(l, xcm, gin_cm, d, part, dw, db, J, st);
+        part += al256((uint64_t)wgrad_slots(d) * slot_floats(l) * 4) / 4;
         if (l > 0) {
             // the input gradient of layer 1 feeds only layer 0's weight
             // gradient: its channel-major copy alone
@@ -771,6 +945,7 @@ hipError_t cnn_train_step(float *params, float *adam_m, float *adam_v, int64_t t
             gin_cm = gnext_cm;
         }
     }
+    wgrad_reduce(J, part, d, st);
     // Kingma & Ba's defaults; every constant is formed in FP64 and rounded once
     const double b1 = 0.9, b2 = 0.999;
     const float c1 = (float)(1.0 - pow(b1, (double)t)), c2 = (float)(1.0 - pow(b2, (double)t));

@@ -742,6 +742,7 @@ static int check_tiles(int64_t n, int h, int w)
         return fail(QSQ_ERR_INVALID_ARG, "need n >= 1 and h, w positive multiples of 32 (got %lld, %d, %d)",
                     (long long)n, h, w);
     if ((double)n * h * w >= 2147483648.0) return fail(QSQ_ERR_COUNT_OVERFLOW, "n h w >= 2^31 pixels");
+    if ((int64_t)h * w > ((int64_t)1 << 24)) return fail(QSQ_ERR_COUNT_OVERFLOW, "h w > 2^24 pixels per tile");
     return QSQ_OK;
 }
 

@@ -208,6 +208,9 @@ def test_cnn_arguments_rejected_before_launch(qsq):
         A.ERR_WORKSPACE_TOO_SMALL
     assert L.qsq_cnn_forward(_fake(1), _fake(2), 1 << 20, 64, 64, _fake(3), _fake(4), 1 << 62, None) == \
         A.ERR_COUNT_OVERFLOW
+    # one tile above 2^24 pixels: its tensors would not fit 32-bit byte offsets
+    assert L.qsq_cnn_forward(_fake(1), _fake(2), 1, 4096, 4128, _fake(3), _fake(4), 1 << 62, None) == \
+        A.ERR_COUNT_OVERFLOW
     assert L.qsq_cnn_train_step(_fake(1), _fake(2), _fake(3), 0, 1e-3, _fake(4), _fake(5), _fake(6), 4, 64, 64, 0.1,
                                 _fake(7), None, None, _fake(8), need, None) == A.ERR_INVALID_ARG
     assert L.qsq_cnn_layer_forward(4, _fake(1), _fake(2), 4, 64, 64, _fake(3), None) == A.ERR_INVALID_ARG

@@ -150,23 +150,24 @@ __global__ void k_prepare(const float *params, uint16_t *prep)
 }
 
 // ---------------------------------------------------------------------------
-// 3x3 'same' convolution, one wave per 16-pixel strip of kConvRows rows, all
-// output channels.  The wave keeps the weight operands in registers for its
-// rows.  32-channel inputs (BF16): lane (i, kg) reads pixels x0 + i - 1,
-// x0 + i, x0 + i + 1, channels 8 kg .. 8 kg + 7, of each input row (three
-// 16-byte buffer loads); rows above and below the image lie outside the
-// image's buffer range and read as zeros, the pixels left and right of it
-// are zeroed by a select; a window of three rows slides down the strip and
-// the next row is fetched one row ahead.  Inputs with CI < 32 channels (FP32
-// with 3, BF16 with 2): the 9 taps' channels packed along K, cpad(CI) per
-// tap, each tap's channels fetched with one load.  Outputs (each nullable):
-// BF16 activations (ReLU applied), FP32 values, a BF16 copy masked by
-// mask_cm > 0 (input gradients; mask_cm is the channel-major copy of the
+// 3x3 'same' convolution.  A workgroup of 4 waves takes kConvRows rows of a
+// 64-pixel column chunk of one image, a wave a 16-pixel strip of it, all
+// output channels; the wave keeps the weight operands in registers.
+// 32-channel inputs (BF16): the workgroup first stages its input rows
+// (kConvRows + 2, pixels x - 1 .. x + 64, zeros outside the image) in LDS with
+// all loads in flight at once; lane (i, kg) then reads pixels x0 + i - 1,
+// x0 + i, x0 + i + 1, channels 8 kg .. 8 kg + 7, of each row from there, in a
+// window of three rows sliding down the strip.  Inputs with CI < 32 channels
+// (FP32 with 3, BF16 with 2) are staged the same way, as BF16 with cpad(CI)
+// channels per pixel, and the 9 taps' channels packed along K (cpad(CI) per
+// tap) are read from there.  Outputs (each
+// nullable): BF16 activations (ReLU applied), FP32 values, a BF16 copy masked
+// by mask_cm > 0 (input gradients; mask_cm is the channel-major copy of the
 // layer's input activations), and the channel-major copy of the BF16 output
 // (masked too when mask_cm is given).  A BF16 NHWC output of 32 channels goes
 // through LDS so that each lane stores one pixel's 8 channels (16 bytes) and
-// the wave a row's 1 KB with one store.  One tile's tensor is addressed with
-// 32-bit byte offsets (h w <= 2^24).
+// the wave a row's 1 KB with one store.  One tile's tensors are addressed
+// with 32-bit byte offsets (h w <= 2^24).
 // ---------------------------------------------------------------------------
 struct ConvDims {
     int64_t n;
@@ -249,6 +250,42 @@ __global__ void __launch_bounds__(256) k_conv(const void *__restrict__ in, ConvD
         for (int k = 0; k < PER; ++k) {
             const int c = (int)threadIdx.x + 256 * k;
             if (c < NCH) rows_lds[c] = make_uint4(tmp[k].x, tmp[k].y, tmp[k].z, tmp[k].w);
+        }
+        __syncthreads();
+    }
+    // inputs with CI < 32 channels: the same rows as BF16 with cpad(CI)
+    // channels per pixel (the pad channel zero), WPT dwords per pixel
+    constexpr int WPT = cpad(CI) / 2, NPX = (R + 2) * PW;
+    uint32_t *lsmall = nullptr;
+    if constexpr (CI < 32) {
+        __shared__ uint32_t small_lds[NPX * WPT];
+        lsmall = small_lds;
+        constexpr int PERS = (NPX + 255) / 256;
+        uint32_t tmp[PERS][WPT];
+#pragma unroll
+        for (int k = 0; k < PERS; ++k) {
+            const int q = (int)threadIdx.x + 256 * k;
+            const int yy = y0 - 1 + q / PW, px = xc - 1 + q % PW;
+#pragma unroll
+            for (int j = 0; j < WPT; ++j) tmp[k][j] = 0u;
+            if (q < NPX && yy >= 0 && yy < d.h && px >= 0 && px < d.w) {
+                const int64_t pix = (img * d.h + yy) * d.w + px;
+                if constexpr (SRC_F32) {
+                    const float *pf = static_cast<const float *>(in) + pix * 3;
+                    tmp[k][0] = (uint32_t)f2bf(pf[0]) | ((uint32_t)f2bf(pf[1]) << 16);
+                    tmp[k][1] = (uint32_t)f2bf(pf[2]);
+                } else {
+                    tmp[k][0] = *reinterpret_cast<const uint32_t *>(static_cast<const uint16_t *>(in) + pix * 2);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PERS; ++k) {
+            const int q = (int)threadIdx.x + 256 * k;
+            if (q < NPX) {
+#pragma unroll
+                for (int j = 0; j < WPT; ++j) small_lds[q * WPT + j] = tmp[k][j];
+            }
         }
         __syncthreads();
     }
@@ -339,23 +376,18 @@ __global__ void __launch_bounds__(256) k_conv(const void *__restrict__ in, ConvD
         } else {
             // the 9 taps' channels packed along K: lane kg takes taps
             // (32 kc + 8 kg) / cpad .. + 8 / cpad - 1 of chunk kc
-            constexpr int CP = cpad(CI), TPL = 8 / CP, WPT = CP / 2;
+            // (read from the staged rows: staged row rr + dy, pixel 16 s + i + dx)
+            constexpr int CP = cpad(CI), TPL = 8 / CP;
 #pragma unroll
             for (int kc = 0; kc < NK; ++kc) {
                 uint32_t wd[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
                 for (int tt = 0; tt < TPL; ++tt) {
                     const int tap = (32 * kc + 8 * kg) / CP + tt;
-                    const int yy = y + tap / 3 - 1, xx = x0 + i + tap % 3 - 1;
-                    if (tap < 9 && yy >= 0 && yy < d.h && xx >= 0 && xx < d.w) {
-                        const int64_t pix = (img * d.h + yy) * d.w + xx;
-                        if constexpr (SRC_F32) {
-                            const float *pf = static_cast<const float *>(in) + pix * 3;
-                            wd[WPT * tt] = (uint32_t)f2bf(pf[0]) | ((uint32_t)f2bf(pf[1]) << 16);
-                            wd[WPT * tt + 1] = (uint32_t)f2bf(pf[2]);
-                        } else {
-                            wd[WPT * tt] = *reinterpret_cast<const uint32_t *>(static_cast<const uint16_t *>(in) + pix * 2);
-                        }
+                    if (tap < 9) {
+                        const int q = (rr + tap / 3) * PW + 16 * sw + i + tap % 3;
+#pragma unroll
+                        for (int j = 0; j < WPT; ++j) wd[WPT * tt + j] = lsmall[q * WPT + j];
                     }
                 }
                 const bf16x8 a = __builtin_bit_cast(bf16x8, make_uint4(wd[0], wd[1], wd[2], wd[3]));
@@ -414,12 +446,26 @@ __global__ void __launch_bounds__(256) k_conv(const void *__restrict__ in, ConvD
 template <int C, bool SRC_F32>
 __global__ void k_to_cm(const void *in, int64_t rows, int w, uint16_t *out)
 {
-    const int64_t total = rows * C * w;
-    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total;
-         o += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(o % w), c = (int)((o / w) % C);
-        const int64_t row = o / ((int64_t)w * C), e = (row * w + x) * C + c;
-        out[o] = SRC_F32 ? f2bf(static_cast<const float *>(in)[e]) : static_cast<const uint16_t *>(in)[e];
+    if constexpr (C <= 4) {
+        // one pixel per thread: its C values read together, one store per
+        // channel row (consecutive threads write consecutive pixels)
+        const int64_t total = rows * w;
+        for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
+             p += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t row = p / w, x = p % w;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                out[(row * C + c) * w + x] = SRC_F32 ? f2bf(static_cast<const float *>(in)[p * C + c])
+                                                     : static_cast<const uint16_t *>(in)[p * C + c];
+        }
+    } else {
+        const int64_t total = rows * C * w;
+        for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total;
+             o += (int64_t)gridDim.x * blockDim.x) {
+            const int x = (int)(o % w), c = (int)((o / w) % C);
+            const int64_t row = o / ((int64_t)w * C), e = (row * w + x) * C + c;
+            out[o] = SRC_F32 ? f2bf(static_cast<const float *>(in)[e]) : static_cast<const uint16_t *>(in)[e];
+        }
     }
 }
 
@@ -427,55 +473,94 @@ __global__ void k_to_cm(const void *in, int64_t rows, int w, uint16_t *out)
 // Weight and bias gradients of one layer: dW[tap][ci][co] = sum over pixels
 // of x[p + tap - (1,1)][ci] dy[p][co], db[co] = sum of dy[p][co], from the
 // channel-major copies.  MFMA: M = 16 input channels, N = 16 output
-// channels, K = 32 pixels of a row.  Lane (i, kg) reads 8 consecutive pixels
-// x0 + 8 kg .. + 7 of channel i: one aligned 16-byte load, plus the two
-// neighbouring pixel pairs for the operands shifted by one pixel either way
-// (byte-align of adjacent dwords).  A workgroup takes R rows of one image and
-// a 64-pixel column chunk (both halves of each 128-byte line of a channel
-// row): one wave per (input tile, output tile) pair and 32-pixel half; each
-// wave slides a window of three input rows down the R rows, the second
-// half's sums are added to the first's through LDS, and the workgroup writes
-// them to its slot; k_wgrad_reduce1/2 add the slots in a fixed order
-// (deterministic).
+// channels, K = 32 pixels of a row.  A workgroup takes R rows of one image
+// and a 64-pixel column chunk, one wave per (input tile, output tile) pair;
+// each wave covers the whole chunk as two K halves: lane (i, kg) reads
+// pixels x0 + 8 kg .. + 7 and x0 + 32 + 8 kg .. + 7 of channel i (two aligned
+// 16-byte buffer loads per row, zeros outside the tile).  The pixel pairs
+// either side, for the operands shifted by one pixel (byte-align of adjacent
+// dwords), come from the neighbouring lanes (kg - 1, kg + 1, and across the
+// two halves) by ds_bpermute; only the chunk's outer edges are loaded, and
+// only where the chunk does not end at the image edge.  Each wave slides a
+// window of three input rows down its R rows, four at a time, and writes its
+// sums to the workgroup's slot; k_wgrad_reduce1/2 add the slots in a fixed
+// order (deterministic).
 // ---------------------------------------------------------------------------
 struct Shift3 {
     bf16x8 m, z, p;   // pixels shifted by -1, 0, +1
 };
 
+// one input row of a lane: the two 8-pixel chunks and the pixel pairs either
+// side of each
+struct XRow {
+    uint32_t d[2][4], lft[2], rgt[2];
+};
+
+__device__ __forceinline__ Shift3 shift3(const uint32_t (&d)[4], uint32_t lft, uint32_t rgt)
+{
+    const uint32_t e12 = __builtin_amdgcn_alignbyte(d[1], d[0], 2), e34 = __builtin_amdgcn_alignbyte(d[2], d[1], 2),
+                   e56 = __builtin_amdgcn_alignbyte(d[3], d[2], 2);
+    Shift3 s;
+    s.z = __builtin_bit_cast(bf16x8, make_uint4(d[0], d[1], d[2], d[3]));
+    s.m = __builtin_bit_cast(bf16x8, make_uint4(__builtin_amdgcn_alignbyte(d[0], lft, 2), e12, e34, e56));
+    s.p = __builtin_bit_cast(bf16x8, make_uint4(e12, e34, e56, __builtin_amdgcn_alignbyte(rgt, d[3], 2)));
+    return s;
+}
+
 template <int CI, int CO>
-__global__ void __launch_bounds__(512) k_wgrad(const uint16_t *__restrict__ xcm, const uint16_t *__restrict__ gcm,
+__global__ void __launch_bounds__(256) k_wgrad(const uint16_t *__restrict__ xcm, const uint16_t *__restrict__ gcm,
                                                ConvDims d, int R, float *__restrict__ part)
 {
-    constexpr int TI = ntile(CI), TO = ntile(CO), CIP = 16 * TI, COP = 16 * TO, NW = TI * TO;
+    constexpr int TI = ntile(CI), TO = ntile(CO), CIP = 16 * TI, COP = 16 * TO;
     constexpr int SLOT = 9 * CIP * COP + COP;
     const int lane = (int)(threadIdx.x & 63), wid = (int)(threadIdx.x >> 6);
-    const int half = wid / NW, pw = wid % NW, a = pw / TO, b = pw % TO;
+    const int a = wid / TO, b = wid % TO;
     const int i = lane & 15, kg = lane >> 4;
     const int cpr = (d.w + 63) / 64, rb = d.h / R;
     const int64_t unit = blockIdx.x;
-    const int x0 = (int)(unit % cpr) * 64 + half * 32, y0 = (int)((unit / cpr) % rb) * R;
+    const int x0 = (int)(unit % cpr) * 64, y0 = (int)((unit / cpr) % rb) * R;
     const int64_t img = unit / ((int64_t)cpr * rb);
-    const int RH = x0 < d.w ? R : 0;   // rows of this half (none past the right edge)
-    const int xs = x0 + 8 * kg, c = a * 16 + i, co = b * 16 + i;
+    const int c = a * 16 + i, co = b * 16 + i;
+    const int64_t npix = (int64_t)d.h * d.w;
+    const int xbytes = (int)(npix * CI * 2), gbytes = (int)(npix * CO * 2);
+    const __amdgpu_buffer_rsrc_t xrs = buf_rsrc(xcm + img * npix * CI, xbytes);
+    const __amdgpu_buffer_rsrc_t grs = buf_rsrc(gcm + img * npix * CO, gbytes);
+    // byte offset of pixel x of row yy of channel ch (out of range: zeros)
+    auto xoff = [&](int yy, int x) {
+        return c < CI && yy >= 0 && yy < d.h && x >= 0 && x < d.w ? ((yy * CI + c) * d.w + x) * 2 : xbytes;
+    };
+    const bool edge_l = x0 > 0, edge_r = x0 + 64 < d.w;   // chunk edges inside the image
+    const int up = ((lane + 48) & 63) << 2, dn = ((lane + 16) & 63) << 2;   // ds_bpermute addresses of kg - 1, kg + 1
     auto xrow = [&](int yy) {
-        uint32_t d0 = 0, d1 = 0, d2 = 0, d3 = 0, lft = 0, rgt = 0;
-        if (c < CI && yy >= 0 && yy < d.h && xs < d.w) {
-            const uint16_t *row = xcm + ((img * d.h + yy) * CI + c) * (int64_t)d.w;
-            const uint4 q = *reinterpret_cast<const uint4 *>(row + xs);
-            d0 = q.x;
-            d1 = q.y;
-            d2 = q.z;
-            d3 = q.w;
-            if (xs > 0) lft = *reinterpret_cast<const uint32_t *>(row + xs - 2);
-            if (xs + 8 < d.w) rgt = *reinterpret_cast<const uint32_t *>(row + xs + 8);
+        XRow r;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(xrs, xoff(yy, x0 + 32 * h + 8 * kg), 0, 0);
+            r.d[h][0] = q.x;
+            r.d[h][1] = q.y;
+            r.d[h][2] = q.z;
+            r.d[h][3] = q.w;
         }
-        const uint32_t e12 = __builtin_amdgcn_alignbyte(d1, d0, 2), e34 = __builtin_amdgcn_alignbyte(d2, d1, 2),
-                       e56 = __builtin_amdgcn_alignbyte(d3, d2, 2);
-        Shift3 s;
-        s.z = __builtin_bit_cast(bf16x8, make_uint4(d0, d1, d2, d3));
-        s.m = __builtin_bit_cast(bf16x8, make_uint4(__builtin_amdgcn_alignbyte(d0, lft, 2), e12, e34, e56));
-        s.p = __builtin_bit_cast(bf16x8, make_uint4(e12, e34, e56, __builtin_amdgcn_alignbyte(rgt, d3, 2)));
-        return s;
+        // pixel pairs left of each chunk: lane kg - 1's last dword (for kg = 0
+        // of the second half: lane kg = 3 of the first half)
+        const uint32_t l0 = (uint32_t)__builtin_amdgcn_ds_bpermute(up, (int)r.d[0][3]);
+        const uint32_t l1 = (uint32_t)__builtin_amdgcn_ds_bpermute(up, (int)r.d[1][3]);
+        const uint32_t r0 = (uint32_t)__builtin_amdgcn_ds_bpermute(dn, (int)r.d[0][0]);
+        const uint32_t r1 = (uint32_t)__builtin_amdgcn_ds_bpermute(dn, (int)r.d[1][0]);
+        uint32_t el = 0, er = 0;
+        if (edge_l) el = __builtin_amdgcn_raw_buffer_load_b32(xrs, kg == 0 ? xoff(yy, x0 - 2) : xbytes, 0, 0);
+        if (edge_r) er = __builtin_amdgcn_raw_buffer_load_b32(xrs, kg == 3 ? xoff(yy, x0 + 64) : xbytes, 0, 0);
+        r.lft[0] = kg > 0 ? l0 : el;
+        r.lft[1] = kg > 0 ? l1 : l0;
+        r.rgt[0] = kg < 3 ? r0 : r1;
+        r.rgt[1] = kg < 3 ? r1 : er;
+        return r;
+    };
+    auto grow = [&](int yy, int h) {
+        const int x = x0 + 32 * h + 8 * kg;
+        const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(
+            grs, co < CO && yy < d.h && x < d.w ? ((yy * CO + co) * d.w + x) * 2 : gbytes, 0, 0);
+        return __builtin_bit_cast(bf16x8, q);
     };
     f32x4 acc[9];
 #pragma unroll
@@ -483,48 +568,38 @@ __global__ void __launch_bounds__(512) k_wgrad(const uint16_t *__restrict__ xcm,
     float dbs = 0.0f;   // bias gradient (waves of input tile 0 only)
     // rows go four at a time: all loads of a group are issued before its
     // products, so their latencies overlap (R is a multiple of 4)
-    Shift3 win[6];   // input rows y - 1 .. y + 4
+    XRow win[6];   // input rows y - 1 .. y + 4
     win[0] = xrow(y0 - 1);
     win[1] = xrow(y0);
-    for (int rr = 0; rr < RH; rr += 4) {
+    for (int rr = 0; rr < R; rr += 4) {
         const int y = y0 + rr;
-        bf16x8 gb[4];
+        bf16x8 gb[4][2];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             win[2 + k] = xrow(y + 1 + k);
-            uint4 q = make_uint4(0, 0, 0, 0);
-            if (co < CO)
-                q = *reinterpret_cast<const uint4 *>(gcm + ((img * d.h + y + k) * CO + co) * (int64_t)d.w + xs);
-            gb[k] = __builtin_bit_cast(bf16x8, q);
+            gb[k][0] = grow(y + k, 0);
+            gb[k][1] = grow(y + k, 1);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (a == 0) {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) dbs += (float)gb[k][j];
+                for (int j = 0; j < 8; ++j) dbs += (float)gb[k][0][j] + (float)gb[k][1][j];
             }
 #pragma unroll
-            for (int ty = 0; ty < 3; ++ty) {
-                acc[3 * ty + 0] = mfma(win[k + ty].m, gb[k], acc[3 * ty + 0]);
-                acc[3 * ty + 1] = mfma(win[k + ty].z, gb[k], acc[3 * ty + 1]);
-                acc[3 * ty + 2] = mfma(win[k + ty].p, gb[k], acc[3 * ty + 2]);
-            }
+            for (int ty = 0; ty < 3; ++ty)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const XRow &xr = win[k + ty];
+                    const Shift3 xs3 = shift3(xr.d[h], xr.lft[h], xr.rgt[h]);
+                    acc[3 * ty + 0] = mfma(xs3.m, gb[k][h], acc[3 * ty + 0]);
+                    acc[3 * ty + 1] = mfma(xs3.z, gb[k][h], acc[3 * ty + 1]);
+                    acc[3 * ty + 2] = mfma(xs3.p, gb[k][h], acc[3 * ty + 2]);
+                }
         }
         win[0] = win[4];
         win[1] = win[5];
     }
-    // the second half's sums, added to the first's in a fixed order
-    __shared__ f32x4 red[NW][9][64];
-    __shared__ float redb[TO][64];
-    if (half == 1) {
-#pragma unroll
-        for (int tp = 0; tp < 9; ++tp) red[pw][tp][lane] = acc[tp];
-        if (a == 0) redb[b][lane] = dbs;
-    }
-    __syncthreads();
-    if (half == 1) return;
-#pragma unroll
-    for (int tp = 0; tp < 9; ++tp) acc[tp] += red[pw][tp][lane];
     // lane holds D[ci = a 16 + 4 kg + r][co = b 16 + i]
     float *slot = part + unit * SLOT;
 #pragma unroll
@@ -532,7 +607,6 @@ __global__ void __launch_bounds__(512) k_wgrad(const uint16_t *__restrict__ xcm,
 #pragma unroll
         for (int r = 0; r < 4; ++r) slot[(tp * CIP + a * 16 + 4 * kg + r) * COP + b * 16 + i] = acc[tp][r];
     if (a == 0) {
-        dbs += redb[b][lane];
         dbs += __shfl_xor(dbs, 16);
         dbs += __shfl_xor(dbs, 32);
         if (kg == 0) slot[9 * CIP * COP + b * 16 + i] = dbs;
@@ -549,13 +623,13 @@ struct RedSeg {
     const float *part;   // the layer's slots
     float *dw, *db;
     int ci, co, cip, cop;
-    int64_t slot, nout, e0;   // slot floats, outputs, first output in the job
+    int64_t slot, nslots, nout, e0;   // slot floats, slots, outputs, first output in the job
 };
 
 struct RedJob {
     RedSeg s[4];
     int nseg;
-    int64_t nslots, total;
+    int64_t total;
 };
 
 // output e of the job: its segment and the offset of its value within a slot
@@ -584,7 +658,7 @@ __global__ void k_wgrad_reduce1(RedJob J, float *__restrict__ tmp)
     const RedSeg &g = red_seg(J, e);
     const int64_t src = red_src(g, e - g.e0);
     const int64_t w0 = (int64_t)blockIdx.y * kRedGroup;
-    const int64_t w1 = w0 + kRedGroup < J.nslots ? w0 + kRedGroup : J.nslots;
+    const int64_t w1 = w0 + kRedGroup < g.nslots ? w0 + kRedGroup : g.nslots;
     float acc = 0.0f;
     for (int64_t w = w0; w < w1; ++w) acc += g.part[w * g.slot + src];
     tmp[(int64_t)blockIdx.y * J.total + e] = acc;
@@ -725,18 +799,27 @@ static void conv_launch(int l, bool transposed, const void *in, ConvDims d, cons
     }
 }
 
-// Rows per workgroup of the weight-gradient pass: the smallest power of two
-// >= 4 dividing h that keeps the slots (one per workgroup: R rows of a
-// 64-pixel column chunk) at 512 or fewer, h at most.
-static int wgrad_rows(ConvDims d)
+// Rows per workgroup of layer l's weight-gradient pass: the smallest power
+// of two >= 4 dividing h that keeps its slots (one per workgroup: R rows of a
+// 64-pixel column chunk) at 2048 / (waves per workgroup) or fewer, h at most
+// -- about 2048 waves for the 32 x 32 layers and the narrow ones alike.
+static int wgrad_rows(ConvDims d, int l)
 {
+    const int64_t cap = 2048 / (ntile(kCi[l]) * ntile(kCo[l]));
     int R = 4;
-    while (R < d.h && d.h % (2 * R) == 0 && d.n * (d.h / R) * ((d.w + 63) / 64) > 512) R *= 2;
+    while (R < d.h && d.h % (2 * R) == 0 && d.n * (d.h / R) * ((d.w + 63) / 64) > cap) R *= 2;
     return R;
 }
 
-static int64_t wgrad_slots(ConvDims d) { return d.n * (d.h / wgrad_rows(d)) * ((d.w + 63) / 64); }
-static int64_t wgrad_groups(ConvDims d) { return (wgrad_slots(d) + kRedGroup - 1) / kRedGroup; }
+static int64_t wgrad_slots(ConvDims d, int l) { return d.n * (d.h / wgrad_rows(d, l)) * ((d.w + 63) / 64); }
+
+// first-stage groups of a reduction: enough for the layer with the most slots
+static int64_t wgrad_groups(ConvDims d)
+{
+    int64_t m = 0;
+    for (int l = 0; l < 4; ++l) m = wgrad_slots(d, l) > m ? wgrad_slots(d, l) : m;
+    return (m + kRedGroup - 1) / kRedGroup;
+}
 
 static int64_t slot_floats(int l)
 {
@@ -745,18 +828,21 @@ static int64_t slot_floats(int l)
 
 static uint64_t al256(uint64_t b) { return (b + 255) & ~(uint64_t)255; }
 
-// slots of one layer (at most the 32 x 32 layers' size) and its group sums
+static uint64_t slot_bytes(ConvDims d, int l) { return al256((uint64_t)wgrad_slots(d, l) * slot_floats(l) * 4); }
+
+// slots of one layer (the largest layer's) and its group sums
 static uint64_t wgrad_part_bytes(ConvDims d)
 {
-    return al256((uint64_t)wgrad_slots(d) * slot_floats(1) * 4) +
-           (uint64_t)wgrad_groups(d) * (9 * 32 * 32 + 32) * 4;
+    uint64_t m = 0;
+    for (int l = 0; l < 4; ++l) m = slot_bytes(d, l) > m ? slot_bytes(d, l) : m;
+    return m + (uint64_t)wgrad_groups(d) * (9 * 32 * 32 + 32) * 4;
 }
 
 // slots of all four layers and the group sums of the whole parameter vector
 static uint64_t train_part_bytes(ConvDims d)
 {
     uint64_t b = 0;
-    for (int l = 0; l < 4; ++l) b += al256((uint64_t)wgrad_slots(d) * slot_floats(l) * 4);
+    for (int l = 0; l < 4; ++l) b += slot_bytes(d, l);
     return b + (uint64_t)wgrad_groups(d) * QSQ_CNN_PARAMS * 4;
 }
 
@@ -771,9 +857,9 @@ uint64_t cnn_wgrad_scratch_bytes(int64_t n, int h, int w)
 static void wgrad_slots_launch(int l, const uint16_t *xcm, const uint16_t *gcm, ConvDims d, float *part, float *dw,
                                float *db, RedJob &J, hipStream_t st)
 {
-    const int64_t slots = wgrad_slots(d);
-    const int R = wgrad_rows(d);
-    const dim3 grid(slots), block(2 * 64 * ntile(kCi[l]) * ntile(kCo[l]));
+    const int64_t slots = wgrad_slots(d, l);
+    const int R = wgrad_rows(d, l);
+    const dim3 grid(slots), block(64 * ntile(kCi[l]) * ntile(kCo[l]));
     if (l == 0)
         hipLaunchKernelGGL((k_wgrad<3, 32>), grid, block, 0, st, xcm, gcm, d, R, part);
     else if (l == 3)
@@ -789,10 +875,10 @@ static void wgrad_slots_launch(int l, const uint16_t *xcm, const uint16_t *gcm, 
     g.cip = 16 * ntile(kCi[l]);
     g.cop = 16 * ntile(kCo[l]);
     g.slot = slot_floats(l);
+    g.nslots = slots;
     g.nout = 9LL * kCi[l] * kCo[l] + kCo[l];
     g.e0 = J.total;
     J.total += g.nout;
-    J.nslots = slots;
 }
 
 static void wgrad_reduce(const RedJob &J, float *tmp, ConvDims d, hipStream_t st)
@@ -808,14 +894,16 @@ static void wgrad_launch(int l, const uint16_t *xcm, const uint16_t *gcm, ConvDi
 {
     RedJob J{};
     wgrad_slots_launch(l, xcm, gcm, d, part, dw, db, J, st);
-    wgrad_reduce(J, part + al256((uint64_t)wgrad_slots(d) * slot_floats(1) * 4) / 4, d, st);
+    uint64_t m = 0;
+    for (int k = 0; k < 4; ++k) m = slot_bytes(d, k) > m ? slot_bytes(d, k) : m;
+    wgrad_reduce(J, part + m / 4, d, st);
 }
 
 template <int C, bool SRC_F32>
 static void to_cm(const void *in, ConvDims d, uint16_t *out, hipStream_t st)
 {
-    const int64_t total = d.n * d.h * (int64_t)d.w * C;
-    const int blocks = (int)(blocks_for(total, 256) < 4096 ? blocks_for(total, 256) : 4096);
+    const int64_t total = d.n * d.h * (int64_t)d.w * (C <= 4 ? 1 : C);
+    const int blocks = (int)(blocks_for(total, 256) < 8192 ? blocks_for(total, 256) : 8192);
     hipLaunchKernelGGL((k_to_cm<C, SRC_F32>), dim3(blocks), dim3(256), 0, st, in, d.n * d.h, d.w, out);
 }
 
@@ -861,7 +949,7 @@ struct CnnWs {
     uint64_t total;
 };
 
-constexpr int kLossBlocks = 512;
+constexpr int kLossBlocks = 2048;
 
 static CnnWs ws_layout(void *base, int64_t n, int h, int w)
 {
@@ -935,7 +1023,7 @@ hipError_t cnn_train_step(float *params, float *adam_m, float *adam_v, int64_t t
         const uint16_t *xcm = l == 0 ? s.x_cm : s.act_cm[l - 1];
         float *dw = g + master_w(l), *db = dw + 9 * kCi[l] * kCo[l];
         wgrad_slots_launch(l, xcm, gin_cm, d, part, dw, db, J, st);
-        part += al256((uint64_t)wgrad_slots(d) * slot_floats(l) * 4) / 4;
+        part += slot_bytes(d, l) / 4;
         if (l > 0) {
             // the input gradient of layer 1 feeds only layer 0's weight
             // gradient: its channel-major copy alone

@@ -70,10 +70,13 @@ int qsq_cnn_forward(const void *prep, const float *x, int64_t n, int h, int w, f
  * logq is finite; backward through all layers (the output gradient and the
  * hidden gradients rounded to BF16 as matrix-core operands); one Adam update
  * (beta1 0.9, beta2 0.999, eps 1e-8, step t >= 1) of params with adam_m and
- * adam_v (FP32, QSQ_CNN_PARAMS each, zero before step 1); prep is refreshed
- * from the updated params.  mask, logq: FP32 (n, h, w).  grad_out: NULL or
- * QSQ_CNN_PARAMS floats receiving the gradient (params layout).  loss_out:
- * NULL or one device double receiving the loss before the update.
+ * adam_v (FP32, QSQ_CNN_PARAMS each, zero before step 1).  prep must hold
+ * qsq_cnn_prepare(params) on entry (the forward pass reads it); the update
+ * rewrites the entries of prep that the changed params feed, so it again
+ * equals qsq_cnn_prepare(params) on return.  mask, logq: FP32 (n, h, w).
+ * grad_out: NULL or QSQ_CNN_PARAMS floats receiving the gradient (params
+ * layout).  loss_out: NULL or one device double receiving the loss before
+ * the update.
  */
 int qsq_cnn_train_step(float *params, float *adam_m, float *adam_v, int64_t t, float lr, const float *x,
                        const float *mask, const float *logq, int64_t n, int h, int w, float lam, void *prep,

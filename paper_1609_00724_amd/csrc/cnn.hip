@@ -511,8 +511,8 @@ template <int CI, int CO>
 __global__ void __launch_bounds__(256) k_wgrad(const uint16_t *__restrict__ xcm, const uint16_t *__restrict__ gcm,
                                                ConvDims d, int R, float *__restrict__ part)
 {
-    constexpr int TI = ntile(CI), TO = ntile(CO), CIP = 16 * TI, COP = 16 * TO;
-    constexpr int SLOT = 9 * CIP * COP + COP;
+    constexpr int TO = ntile(CO);
+    constexpr int SLOT = 9 * CI * CO + CO;   // dW (tap, ci, co) then db (co): the parameter order
     const int lane = (int)(threadIdx.x & 63), wid = (int)(threadIdx.x >> 6);
     const int a = wid / TO, b = wid % TO;
     const int i = lane & 15, kg = lane >> 4;
@@ -600,16 +600,22 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t *__restrict__ xcm,
         win[0] = win[4];
         win[1] = win[5];
     }
-    // lane holds D[ci = a 16 + 4 kg + r][co = b 16 + i]
+    // lane holds D[ci = a 16 + 4 kg + r][co = b 16 + i]; the slot keeps the
+    // real channels only
     float *slot = part + unit * SLOT;
+    if (co < CO) {
 #pragma unroll
-    for (int tp = 0; tp < 9; ++tp)
+        for (int tp = 0; tp < 9; ++tp)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) slot[(tp * CIP + a * 16 + 4 * kg + r) * COP + b * 16 + i] = acc[tp][r];
+            for (int r = 0; r < 4; ++r) {
+                const int ci = a * 16 + 4 * kg + r;
+                if (ci < CI) slot[(tp * CI + ci) * CO + co] = acc[tp][r];
+            }
+    }
     if (a == 0) {
         dbs += __shfl_xor(dbs, 16);
         dbs += __shfl_xor(dbs, 32);
-        if (kg == 0) slot[9 * CIP * COP + b * 16 + i] = dbs;
+        if (kg == 0 && co < CO) slot[9 * CI * CO + co] = dbs;
     }
 }
 
@@ -617,13 +623,13 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t *__restrict__ xcm,
 // groups of kRedGroup consecutive slots, then the groups in order.  One pair
 // of launches reduces the slots of up to four layers (a training step's
 // backward pass) at once.
-constexpr int kRedGroup = 32;
+constexpr int kRedGroup = 64;
 
 struct RedSeg {
-    const float *part;   // the layer's slots
+    const float *part;   // the layer's slots (each: dW (tap, ci, co), then db)
     float *dw, *db;
-    int ci, co, cip, cop;
-    int64_t slot, nslots, nout, e0;   // slot floats, slots, outputs, first output in the job
+    int64_t nw;                   // weights (9 ci co); the slot holds nw + co floats
+    int64_t nslots, nout, e0;     // slots, outputs (= slot floats), first output in the job
 };
 
 struct RedJob {
@@ -640,27 +646,18 @@ __device__ __forceinline__ const RedSeg &red_seg(const RedJob &J, int64_t e)
     return J.s[k];
 }
 
-__device__ __forceinline__ int64_t red_src(const RedSeg &g, int64_t le)
-{
-    const int64_t nw = 9 * (int64_t)g.ci * g.co;
-    if (le < nw) {
-        const int co = (int)(le % g.co), ci = (int)((le / g.co) % g.ci), tp = (int)(le / ((int64_t)g.co * g.ci));
-        return ((int64_t)tp * g.cip + ci) * g.cop + co;
-    }
-    return 9 * (int64_t)g.cip * g.cop + (le - nw);
-}
-
 // grid (outputs / 256, slot groups): tmp[group][e] = sum of its slots
 __global__ void k_wgrad_reduce1(RedJob J, float *__restrict__ tmp)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= J.total) return;
     const RedSeg &g = red_seg(J, e);
-    const int64_t src = red_src(g, e - g.e0);
+    const int64_t src = e - g.e0;
     const int64_t w0 = (int64_t)blockIdx.y * kRedGroup;
     const int64_t w1 = w0 + kRedGroup < g.nslots ? w0 + kRedGroup : g.nslots;
     float acc = 0.0f;
-    for (int64_t w = w0; w < w1; ++w) acc += g.part[w * g.slot + src];
+#pragma unroll 8
+    for (int64_t w = w0; w < w1; ++w) acc += g.part[w * g.nout + src];
     tmp[(int64_t)blockIdx.y * J.total + e] = acc;
 }
 
@@ -670,12 +667,13 @@ __global__ void k_wgrad_reduce2(RedJob J, const float *__restrict__ tmp, int64_t
     if (e >= J.total) return;
     const RedSeg &g = red_seg(J, e);
     float acc = 0.0f;
+#pragma unroll 8
     for (int64_t k = 0; k < ngroups; ++k) acc += tmp[k * J.total + e];
-    const int64_t le = e - g.e0, nw = 9 * (int64_t)g.ci * g.co;
-    if (le < nw)
+    const int64_t le = e - g.e0;
+    if (le < g.nw)
         g.dw[le] = acc;
     else
-        g.db[le - nw] = acc;
+        g.db[le - g.nw] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -731,8 +729,36 @@ __global__ void __launch_bounds__(256) k_sum_parts(const double *part, int n, do
 // b1, b2 are the decay rates, ob1 = 1 - b1 and ob2 = 1 - b2 (formed in FP64
 // on the host: 1 - b2 taken in FP32 from the rounded 0.999f is 1.3e-5 off),
 // c1, c2 the bias corrections 1 - b^t.
+// The updated parameter is also written where k_prepare would put it in the
+// prepared weights (its forward matrix entry, its transposed and flipped
+// input-gradient entry, or its bias), so no separate preparation pass runs;
+// the zero padding of the prepared matrices is never touched.
+__device__ __forceinline__ void prep_store(int64_t e, float val, uint16_t *prep)
+{
+    const PrepLayout P = prep_layout();
+    int l = 0;
+    while (l < 3 && e >= master_w(l + 1)) ++l;
+    const int Ci = kCi[l], Co = kCo[l];
+    const int64_t le = e - master_w(l);
+    if (le >= 9LL * Ci * Co) {
+        reinterpret_cast<float *>(prep + P.bias[l])[le - 9LL * Ci * Co] = val;
+        return;
+    }
+    const int co = (int)(le % Co), ci = (int)((le / Co) % Ci), tap = (int)(le / ((int64_t)Co * Ci));
+    const uint16_t hb = f2bf(val);
+    {
+        const int k = Ci >= 32 ? 32 * tap + ci : tap * cpad(Ci) + ci;   // K index (chunk kc = k / 32)
+        prep[P.fwd[l] + ((int64_t)(k / 32) * 16 * ntile(Co) + co) * 32 + k % 32] = hb;
+    }
+    if (l >= 1) {
+        const int tf = 8 - tap;
+        const int k = Co >= 32 ? 32 * tf + co : tf * cpad(Co) + co;
+        prep[P.bwd[l] + ((int64_t)(k / 32) * 32 + ci) * 32 + k % 32] = hb;
+    }
+}
+
 __global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float ob1,
-                       float ob2, float eps, float c1, float c2)
+                       float ob2, float eps, float c1, float c2, uint16_t *prep)
 {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const float ge = g[e];
@@ -740,7 +766,9 @@ __global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t n, 
         const float ve = b2 * v[e] + ob2 * ge * ge;
         m[e] = me;
         v[e] = ve;
-        p[e] -= lr * (me / c1) / (sqrtf(ve / c2) + eps);
+        const float pe = p[e] - lr * (me / c1) / (sqrtf(ve / c2) + eps);
+        p[e] = pe;
+        prep_store(e, pe, prep);
     }
 }
 
@@ -821,10 +849,7 @@ static int64_t wgrad_groups(ConvDims d)
     return (m + kRedGroup - 1) / kRedGroup;
 }
 
-static int64_t slot_floats(int l)
-{
-    return 9LL * 16 * ntile(kCi[l]) * 16 * ntile(kCo[l]) + 16 * ntile(kCo[l]);
-}
+static int64_t slot_floats(int l) { return 9LL * kCi[l] * kCo[l] + kCo[l]; }
 
 static uint64_t al256(uint64_t b) { return (b + 255) & ~(uint64_t)255; }
 
@@ -870,13 +895,9 @@ static void wgrad_slots_launch(int l, const uint16_t *xcm, const uint16_t *gcm, 
     g.part = part;
     g.dw = dw;
     g.db = db;
-    g.ci = kCi[l];
-    g.co = kCo[l];
-    g.cip = 16 * ntile(kCi[l]);
-    g.cop = 16 * ntile(kCo[l]);
-    g.slot = slot_floats(l);
+    g.nw = 9LL * kCi[l] * kCo[l];
     g.nslots = slots;
-    g.nout = 9LL * kCi[l] * kCo[l] + kCo[l];
+    g.nout = slot_floats(l);
     g.e0 = J.total;
     J.total += g.nout;
 }
@@ -1039,10 +1060,8 @@ hipError_t cnn_train_step(float *params, float *adam_m, float *adam_v, int64_t t
     const float c1 = (float)(1.0 - pow(b1, (double)t)), c2 = (float)(1.0 - pow(b2, (double)t));
     hipLaunchKernelGGL(k_adam, dim3(blocks_for(QSQ_CNN_PARAMS, 256)), dim3(256), 0, st, params, g, adam_m, adam_v,
                        (int64_t)QSQ_CNN_PARAMS, lr, (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f,
-                       c1, c2);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return cnn_prepare(params, prep, st);
+                       c1, c2, static_cast<uint16_t *>(prep));
+    return hipGetLastError();
 }
 
 }  // namespace qsq

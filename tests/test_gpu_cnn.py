@@ -157,6 +157,12 @@ def test_adam_update_matches_oracle():
               f"mean |update| {u.mean():.2e}")
         assert em.max() <= 1.0 and ev.max() <= 1.0 and ep.max() <= 1.0
         assert np.count_nonzero(gr) > 0.5 * gr.size and np.median(u[gr != 0]) > 0.5 * lr
+        # the step refreshed the prepared weights from the updated parameters:
+        # bit for bit what qsq_cnn_prepare makes of them
+        refreshed = prop.prep.clone()
+        prop.prepare()
+        torch.cuda.synchronize()
+        assert torch.equal(refreshed, prop.prep)
 
 
 def test_training_lowers_the_loss():

@@ -687,19 +687,20 @@ __global__ void __launch_bounds__(256) k_loss(const float *out, const float *mas
     __shared__ double red[256];
     double s = 0.0;
     const double invP = 1.0 / (double)P;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
-        const float z = out[2 * p], qh = out[2 * p + 1], t = mask[p], tq = logq[p];
+    // (pixel indices fit 32 bits: n h w < 2^31)
+    for (int p = (int)(blockIdx.x * blockDim.x + threadIdx.x); p < (int)P; p += (int)(gridDim.x * blockDim.x)) {
+        const float2 zo = reinterpret_cast<const float2 *>(out)[p];
+        const float z = zo.x, qh = zo.y, t = mask[p], tq = logq[p];
         const bool valid = isfinite(tq);
         const float sp = fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z)));
         const float dq = valid ? qh - tq : 0.0f;
         s += (double)(sp - t * z) + (double)lam * (double)dq * (double)dq;
         const float sig = 1.0f / (1.0f + expf(-z));
         const uint16_t g0 = f2bf((float)((sig - t) * invP)), g1 = f2bf((float)(2.0 * lam * dq * invP));
-        g[2 * p] = g0;
-        g[2 * p + 1] = g1;
-        const int64_t row = p / w, x = p % w;
-        g_cm[(row * 2 + 0) * w + x] = g0;
-        g_cm[(row * 2 + 1) * w + x] = g1;
+        reinterpret_cast<uint32_t *>(g)[p] = (uint32_t)g0 | ((uint32_t)g1 << 16);
+        const int row = p / w, x = p - row * w;
+        g_cm[(int64_t)(row * 2 + 0) * w + x] = g0;
+        g_cm[(int64_t)(row * 2 + 1) * w + x] = g1;
     }
     red[threadIdx.x] = s;
     __syncthreads();

@@ -105,6 +105,11 @@ def parse():
     ap.add_argument("--learn-streams", type=int, default=4, help="learned workload: streams the scored maps use")
     ap.add_argument("--learn-batch", type=int, default=256, help="learned workload: tiles per training step")
     ap.add_argument("--learn-group", type=int, default=8, help="learned workload: maps in flight at once")
+    ap.add_argument("--train-only", action="store_true",
+                    help="learned workload: only time the network's training step and forward pass on seeded "
+                         "random 64x64 tiles at each of --train-batches tiles")
+    ap.add_argument("--train-batches", default="64,128,256,512,1024",
+                    help="with --train-only: comma-separated batch sizes (tiles)")
     ap.add_argument("--cpu-fraction", type=float, default=0.25,
                     help="batch workload: fraction of each field's seeds the oracle traces")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -131,7 +136,7 @@ def main():
     if args.workload == "batch":
         return bench_batch(args)
     if args.workload == "learned":
-        return bench_learned(args)
+        return bench_train_only(args) if args.train_only else bench_learned(args)
     return bench_field_map(args)
 
 
@@ -919,6 +924,46 @@ def score_learned(test, make_field, prop, m, r, thr, nstreams, group, dev):
     extra = dict(mask_recall=tp / max(tp + fn, 1), mask_precision=tp / max(tp + fp, 1),
                  proposed_pixel_fraction=prop_px / (n * side * side), rule_pixel_fraction=rule_px / (n * side * side))
     return methods, extra
+
+
+def bench_train_only(args):
+    """The network's kernels alone: training steps (forward, loss, backward,
+    Adam with the prepared-weight refresh) and forward passes on seeded random
+    64x64 tiles, --steps timed after --warmup, HIP events; one JSON line."""
+    import torch
+
+    from paper_1609_00724_amd import learn
+    dev = torch.device("cuda:0")
+    g = torch.Generator().manual_seed(0)
+    flop_fwd = 2 * 64 * 64 * sum(9 * ci * co for ci, co in zip(learn.CHANNELS[:-1], learn.CHANNELS[1:]))
+    prop = learn.Proposer(learn.init_params(1, dev))
+    rows = []
+    for bs in (int(b) for b in args.train_batches.split(",")):
+        x = torch.randn(bs, 64, 64, 3, generator=g).to(dev)
+        mask = (torch.rand(bs, 64, 64, generator=g) < 0.2).float().to(dev)
+        logq = torch.randn(bs, 64, 64, generator=g).to(dev)
+        for _ in range(args.warmup):
+            prop.train_step(x, mask, logq, lr=1e-9)
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record()
+        for _ in range(args.steps):
+            prop.train_step(x, mask, logq, lr=1e-9)
+        e[1].record()
+        for _ in range(args.steps):
+            prop.forward(x)
+        e[2].record()
+        torch.cuda.synchronize()
+        ms, fms = e[0].elapsed_time(e[1]) / args.steps, e[1].elapsed_time(e[2]) / args.steps
+        rows.append({"tiles": bs, "train_step_ms": ms, "train_tflops": bs * flop_fwd * 3 / ms / 1e9,
+                     "forward_ms": fms, "forward_tflops": bs * flop_fwd / fms / 1e9})
+        print(f"bench: {rows[-1]}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "learned proposer: BF16-MFMA training step throughput", "unit": "TFLOP/s",
+                      "value": next((r["train_tflops"] for r in rows if r["tiles"] == 256), rows[-1]["train_tflops"]),
+                      "n_gpus": 1, "higher_is_better": True, "dtype": "bf16", "data": "synthetic",
+                      "config": {"workload": "seeded random 64x64 tiles, 3 -> 32 -> 32 -> 32 -> 2 channels"},
+                      "steps": args.steps, "warmup": args.warmup, "mfma_peak_tflops_bf16": 2500.0,
+                      "batches": rows}))
 
 
 def bench_learned(args):

@@ -566,6 +566,26 @@ struct Brick {
     Corner c000, c100, c010, c110, c001, c101, c011, c111;
 };
 
+#ifndef QSQ_MASKED_REFRESH
+#define QSQ_MASKED_REFRESH 1
+#endif
+
+typedef uint32_t u32x3_t __attribute__((ext_vector_type(3)));
+
+// the direction part of a node record, loaded straight into a corner
+template <typename S>
+__device__ __forceinline__ void load_corner(__amdgpu_buffer_rsrc_t rsrc, int off, Corner &c)
+{
+    if constexpr (std::is_same<S, float>::value) {
+        const u32x3_t v = __builtin_amdgcn_raw_buffer_load_b96(rsrc, off, 0, 0);
+        c.x = __uint_as_float(v.x);
+        c.y = __uint_as_float(v.y);
+        c.z = __uint_as_float(v.z);
+    } else {
+        load_dir<S>(rsrc, off, c.x, c.y, c.z);
+    }
+}
+
 template <typename S>
 __device__ __forceinline__ void refresh_corner(__amdgpu_buffer_rsrc_t rsrc, int off, bool miss, Corner &c)
 {
@@ -605,6 +625,24 @@ __device__ __forceinline__ T rhs_regs(__amdgpu_buffer_rsrc_t rsrc, int bytes, co
         b = c[2] * sz + c[1] * sy + c[0];
     }
     const bool miss = b != cell;
+#if QSQ_MASKED_REFRESH
+    if (miss) {
+        // only the lanes that moved load (the memory pipeline returns data for
+        // active lanes alone), the direction part only (12 bytes of FP32)
+        constexpr int NB = node_bytes<S>();
+        const int o = NB * b;
+        const int ox = NB * sx, oy = NB * sy, oz = NB * sz;
+        load_corner<S>(rsrc, o, br.c000);
+        load_corner<S>(rsrc, o + ox, br.c100);
+        load_corner<S>(rsrc, o + oy, br.c010);
+        load_corner<S>(rsrc, o + oy + ox, br.c110);
+        load_corner<S>(rsrc, o + oz, br.c001);
+        load_corner<S>(rsrc, o + oz + ox, br.c101);
+        load_corner<S>(rsrc, o + oz + oy, br.c011);
+        load_corner<S>(rsrc, o + oz + oy + ox, br.c111);
+        cell = b;
+    }
+#else
     if (__ballot(miss)) {
         constexpr int NB = node_bytes<S>();
         // lanes that stayed in their cell read past the end (no access, zeros) and keep their registers
@@ -620,6 +658,7 @@ __device__ __forceinline__ T rhs_regs(__amdgpu_buffer_rsrc_t rsrc, int bytes, co
         refresh_corner<S>(rsrc, o + oz + oy + ox, miss, br.c111);
         cell = b;
     }
+#endif
     T val[3], dx[3], dy[3], dz[3];
 #define QSQ_COMPB(F, k)                                                                               \
     lerp_tree<T>((T)br.c000.F, (T)br.c100.F, (T)br.c010.F, (T)br.c110.F, (T)br.c001.F, (T)br.c101.F,  \

@@ -42,13 +42,19 @@ def _bf16_tensor(a, dev):
     return torch.from_numpy(ref.bf16_round(a).astype(np.float32)).to(dev).to(torch.bfloat16).view(torch.int16)
 
 
+# tile shapes: one 64-pixel column chunk; the narrowest tile (half a chunk);
+# three chunks, the middle one with image on both sides and the last half empty
+SHAPES = [(2, 64, 64), (3, 32, 32), (1, 32, 160)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("layer", [0, 1, 2, 3])
-def test_layer_forward(layer):
+def test_layer_forward(layer, shape):
     import torch
 
     from paper_1609_00724_amd import learn
     prop, wr, br, g, dev = _setup()
-    n, h, w = 2, 64, 64
+    n, h, w = shape
     if layer == 0:
         x = g.normal(size=(n, h, w, 3)).astype(np.float32)
         xin = torch.from_numpy(x).to(dev)
@@ -60,17 +66,18 @@ def test_layer_forward(layer):
     if layer < 3:
         want = np.maximum(want, 0.0)
     err = _rel_l2(out, want)
-    print(f"layer {layer} forward rel L2 {err:.2e}")
+    print(f"layer {layer} {shape} forward rel L2 {err:.2e}")
     assert err <= 1e-5
 
 
+@pytest.mark.parametrize("shape", [(2, 64, 96)] + SHAPES[1:])
 @pytest.mark.parametrize("layer", [0, 1, 2, 3])
-def test_layer_backward(layer):
+def test_layer_backward(layer, shape):
     import torch
 
     from paper_1609_00724_amd import learn
     prop, wr, br, g, dev = _setup(12)
-    n, h, w = 2, 64, 96
+    n, h, w = shape
     ci, co = CH[layer], CH[layer + 1]
     if layer == 0:
         x = g.normal(size=(n, h, w, 3)).astype(np.float32)
@@ -83,7 +90,7 @@ def test_layer_backward(layer):
     rdw, rdb, rdx = ref.conv3x3_backward(ref.bf16_round(x), wr[layer], ref.bf16_round(dy), need_dx=layer > 0)
     e = (_rel_l2(dw.cpu().numpy(), rdw), _rel_l2(db.cpu().numpy(), rdb),
          _rel_l2(dx.cpu().numpy(), rdx) if layer > 0 else 0.0)
-    print(f"layer {layer} backward rel L2 dw {e[0]:.2e} db {e[1]:.2e} dx {e[2]:.2e}")
+    print(f"layer {layer} {shape} backward rel L2 dw {e[0]:.2e} db {e[1]:.2e} dx {e[2]:.2e}")
     assert max(e) <= 1e-5
 
 

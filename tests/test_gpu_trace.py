@@ -160,6 +160,42 @@ def test_spatial_order_steps_every_line_once(oracle_mod, small_charges, n):
         assert (ref["status"] == o["status"]).mean() >= 0.99
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_cell_cache_gathers_bit_identical_at_long_steps(small_charges, storage):
+    """With steps of up to 4 cells most stage points land in another cell, and
+    in a wave some lanes move while others stay: the register cell cache
+    (corners loaded by the lanes that moved only), its LDS form and, for FP32
+    records, the register cache over brick records give the same outputs as
+    direct corner loads, bit for bit, for FP32 and BF16 records."""
+    import torch
+
+    from paper_1609_00724_amd import _abi as A
+    from paper_1609_00724_amd.api import TracePlan, make_opts
+    c = small_charges
+    h = min(c["spacing"])
+    fg = gpu_field(c["b"], c["origin"], c["spacing"], storage=storage)
+    gathers = [A.GATHER_DIRECT, A.GATHER_REGS, A.GATHER_CACHED]
+    if storage == "f32":
+        fg.add_bricks()
+        gathers.append(A.GATHER_BRICKS)
+    dev = torch.device("cuda:0")
+    n = 3000
+    seeds = torch.from_numpy(np.ascontiguousarray(_mixed_seeds(n, 77).T)).to(dev)
+    res = {}
+    for gather in gathers:
+        plan = TracePlan(n, dev, want_steps=True)
+        opts = make_opts(1e-2, 1e-2, h_init=0.1 * h, h_max=4 * h, step_dtype="f32",
+                         launch=A.launch_word(2, 128, gather))
+        out = plan.run(fg, seeds, opts)
+        torch.cuda.synchronize()
+        res[gather] = {k: v.clone() for k, v in out.items()}
+    ref = res[A.GATHER_DIRECT]
+    for gather, r in res.items():
+        for k in ref:
+            assert torch.equal(torch.nan_to_num(r[k], nan=-7.0), torch.nan_to_num(ref[k], nan=-7.0)), (gather, k)
+    assert int((ref["steps"][0] > 3).sum()) > n // 4
+
+
 @pytest.mark.parametrize("n", [1, 3, 8, 9, 65, 1000])
 def test_xcd_parts_edge_counts(small_charges, n):
     """The work list split into per-XCD parts (QSQ_LAUNCH_PARTS) with fewer

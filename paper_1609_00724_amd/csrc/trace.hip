@@ -566,8 +566,8 @@ struct Brick {
     Corner c000, c100, c010, c110, c001, c101, c011, c111;
 };
 
-#ifndef QSQ_MASKED_REFRESH
-#define QSQ_MASKED_REFRESH 1
+#ifndef QSQ_SECOND_CELL
+#define QSQ_SECOND_CELL 1
 #endif
 
 typedef uint32_t u32x3_t __attribute__((ext_vector_type(3)));
@@ -586,15 +586,6 @@ __device__ __forceinline__ void load_corner(__amdgpu_buffer_rsrc_t rsrc, int off
     }
 }
 
-template <typename S>
-__device__ __forceinline__ void refresh_corner(__amdgpu_buffer_rsrc_t rsrc, int off, bool miss, Corner &c)
-{
-    float x, y, z;
-    load_dir<S>(rsrc, off, x, y, z);
-    c.x = miss ? x : c.x;
-    c.y = miss ? y : c.y;
-    c.z = miss ? z : c.z;
-}
 
 // BRICKS: the records are the field's brick records (2 x 2 x 2 node bricks,
 // bricks x fastest): node (i, j, k) sits at ((k/2 nby + j/2) nbx + i/2) 8 +
@@ -604,7 +595,7 @@ __device__ __forceinline__ void refresh_corner(__amdgpu_buffer_rsrc_t rsrc, int 
 template <typename T, typename S, int MODE, bool BRICKS = false>
 __device__ __forceinline__ T rhs_regs(__amdgpu_buffer_rsrc_t rsrc, int bytes, const Geom &g, const int ib[3],
                                       const T q[3], T sigma, const T d1[3], const T d2[3], T kx[3], T k1[3],
-                                      T k2[3], int &cell, Brick &br)
+                                      T k2[3], int &cell, Brick &br, float4 *slot, int stride, int &cell2)
 {
     int c[3];
     T t[3];
@@ -625,40 +616,51 @@ __device__ __forceinline__ T rhs_regs(__amdgpu_buffer_rsrc_t rsrc, int bytes, co
         b = c[2] * sz + c[1] * sy + c[0];
     }
     const bool miss = b != cell;
-#if QSQ_MASKED_REFRESH
     if (miss) {
         // only the lanes that moved load (the memory pipeline returns data for
         // active lanes alone), the direction part only (12 bytes of FP32)
         constexpr int NB = node_bytes<S>();
-        const int o = NB * b;
-        const int ox = NB * sx, oy = NB * sy, oz = NB * sz;
-        load_corner<S>(rsrc, o, br.c000);
-        load_corner<S>(rsrc, o + ox, br.c100);
-        load_corner<S>(rsrc, o + oy, br.c010);
-        load_corner<S>(rsrc, o + oy + ox, br.c110);
-        load_corner<S>(rsrc, o + oz, br.c001);
-        load_corner<S>(rsrc, o + oz + ox, br.c101);
-        load_corner<S>(rsrc, o + oz + oy, br.c011);
-        load_corner<S>(rsrc, o + oz + oy + ox, br.c111);
-        cell = b;
-    }
-#else
-    if (__ballot(miss)) {
-        constexpr int NB = node_bytes<S>();
-        // lanes that stayed in their cell read past the end (no access, zeros) and keep their registers
-        const int o = miss ? NB * b : bytes;
-        const int ox = NB * sx, oy = NB * sy, oz = NB * sz;
-        refresh_corner<S>(rsrc, o, miss, br.c000);
-        refresh_corner<S>(rsrc, o + ox, miss, br.c100);
-        refresh_corner<S>(rsrc, o + oy, miss, br.c010);
-        refresh_corner<S>(rsrc, o + oy + ox, miss, br.c110);
-        refresh_corner<S>(rsrc, o + oz, miss, br.c001);
-        refresh_corner<S>(rsrc, o + oz + ox, miss, br.c101);
-        refresh_corner<S>(rsrc, o + oz + oy, miss, br.c011);
-        refresh_corner<S>(rsrc, o + oz + oy + ox, miss, br.c111);
-        cell = b;
-    }
+#if QSQ_SECOND_CELL
+        // the cell left behind is parked in the lane's LDS slot; a lane that
+        // moves back into it takes its corners from there instead of memory
+        const bool back = b == cell2;
+        float4 keep[kCachePlanes];
+        if (back) {
+#pragma unroll
+            for (int j = 0; j < kCachePlanes; ++j) keep[j] = slot[j * stride];
+        }
+        slot[0 * stride] = make_float4(br.c000.x, br.c000.y, br.c000.z, br.c100.x);
+        slot[1 * stride] = make_float4(br.c100.y, br.c100.z, br.c010.x, br.c010.y);
+        slot[2 * stride] = make_float4(br.c010.z, br.c110.x, br.c110.y, br.c110.z);
+        slot[3 * stride] = make_float4(br.c001.x, br.c001.y, br.c001.z, br.c101.x);
+        slot[4 * stride] = make_float4(br.c101.y, br.c101.z, br.c011.x, br.c011.y);
+        slot[5 * stride] = make_float4(br.c011.z, br.c111.x, br.c111.y, br.c111.z);
+        cell2 = cell;
+        if (back) {
+            br.c000 = Corner{keep[0].x, keep[0].y, keep[0].z};
+            br.c100 = Corner{keep[0].w, keep[1].x, keep[1].y};
+            br.c010 = Corner{keep[1].z, keep[1].w, keep[2].x};
+            br.c110 = Corner{keep[2].y, keep[2].z, keep[2].w};
+            br.c001 = Corner{keep[3].x, keep[3].y, keep[3].z};
+            br.c101 = Corner{keep[3].w, keep[4].x, keep[4].y};
+            br.c011 = Corner{keep[4].z, keep[4].w, keep[5].x};
+            br.c111 = Corner{keep[5].y, keep[5].z, keep[5].w};
+        } else
 #endif
+        {
+            const int o = NB * b;
+            const int ox = NB * sx, oy = NB * sy, oz = NB * sz;
+            load_corner<S>(rsrc, o, br.c000);
+            load_corner<S>(rsrc, o + ox, br.c100);
+            load_corner<S>(rsrc, o + oy, br.c010);
+            load_corner<S>(rsrc, o + oy + ox, br.c110);
+            load_corner<S>(rsrc, o + oz, br.c001);
+            load_corner<S>(rsrc, o + oz + ox, br.c101);
+            load_corner<S>(rsrc, o + oz + oy, br.c011);
+            load_corner<S>(rsrc, o + oz + oy + ox, br.c111);
+        }
+        cell = b;
+    }
     T val[3], dx[3], dy[3], dz[3];
 #define QSQ_COMPB(F, k)                                                                               \
     lerp_tree<T>((T)br.c000.F, (T)br.c100.F, (T)br.c010.F, (T)br.c110.F, (T)br.c001.F, (T)br.c101.F,  \
@@ -741,8 +743,9 @@ __device__ __forceinline__ T rhs_step(const S *__restrict__ nodes, __amdgpu_buff
     if constexpr (GATHER == kGatherLds)
         return rhs_cached<T, S, MODE>(rsrc, bytes, g, ib, q, sigma, d1, d2, kx, k1, k2, cc, slot, stride);
     else if constexpr (GATHER == kGatherRegs || GATHER == kGatherBricks)
+        // (cc[0], the LDS variant's cell key, keys the register cache's parked cell)
         return rhs_regs<T, S, MODE, GATHER == kGatherBricks>(rsrc, bytes, g, ib, q, sigma, d1, d2, kx, k1, k2, cell,
-                                                             br);
+                                                             br, slot, stride, cc[0]);
     else
         return rhs<T, S, MODE, GATHER == kGatherCells>(nodes, g, ib, q, sigma, d1, d2, kx, k1, k2);
 }
@@ -2415,10 +2418,12 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
         const bool fits = field_bytes < limit;
         if (gather == 5 && job.bricks && brick_bytes < limit) {
             kern = trace_kernel<T, S, MODE, kGatherBricks, false>(euler);
+            lds = QSQ_SECOND_CELL ? kCachePlanes * wg * sizeof(float4) : 0;
         } else if (gather == 4 && job.cells) {
             kern = trace_kernel<T, S, MODE, kGatherCells, false>(euler);
         } else if ((gather == 3 || gather == 5 || gather == 0) && fits) {
             kern = trace_kernel<T, S, MODE, kGatherRegs, false>(euler);
+            lds = QSQ_SECOND_CELL ? kCachePlanes * wg * sizeof(float4) : 0;
         } else if (gather == 2 && fits) {
             kern = trace_kernel<T, S, MODE, kGatherLds, false>(euler);
             lds = kCachePlanes * wg * sizeof(float4);

@@ -6,7 +6,8 @@
 // stays the fallback and the reference its proposals are scored against.
 //
 // Every contraction runs on the matrix cores: v_mfma_f32_16x16x32_bf16 (BF16
-// operands, FP32 accumulation), one wave per 16x16 output tile.
+// operands, FP32 accumulation), each wave accumulating one or more 16x16
+// output tiles.
 //   forward / input gradient: M = 16 pixels of a row, N = 16 output channels,
 //     K = 32 (one tap's 32 input channels, or all 9 taps of a 2-3 channel
 //     input packed into one chunk)

@@ -248,6 +248,30 @@ def fixed_error(plan, field, seeds_dev, ref, h, variants, log):
 # map and volume workloads
 # ---------------------------------------------------------------------------
 
+def kept_by_level(keys, steps, levels):
+    """Kept samples of a refined map by refinement level (0: the base
+    lattice) with the step attempts of their lines (both halves).  Keys of
+    the regular lattice tell the level: base cells sit at q B^r + B^r / 2
+    (B = 2^DIM, B^r = 2^levels), level 1 adds the multiples of B^r and level
+    j >= 2 the odd multiples of 2^(levels - j)."""
+    import numpy as np
+    k = keys.cpu().numpy().astype(np.uint64)
+    a = steps.cpu().numpy().astype(np.int64)
+    tz = np.zeros(k.shape, np.int64)
+    for _ in range(levels):
+        even = (k & np.uint64(1)) == 0
+        tz += even
+        k = np.where(even, k >> np.uint64(1), k)
+    lev = np.where(tz >= levels, 1, np.where(tz == levels - 1, 0, levels - tz))
+    out = []
+    for j in range(levels + 1):
+        aj = a[lev == j]
+        if aj.size:
+            out.append({"level": j, "lines": int(aj.size), "attempts": int(aj.sum()),
+                        "mean_attempts": float(aj.mean()), "max_attempts": int(aj.max())})
+    return out
+
+
 def bench_field_map(args):
     """A refined Q / length / FLEDGE map: the 3D volume of the flux-rope field
     (default) or the photospheric slice of the 4-charge field, at the
@@ -381,6 +405,7 @@ def bench_field_map(args):
     own_flops = traced_flops * own
     achieved = own_flops / (ms_trace / 1e3) / 1e12 if ms_trace > 0 else 0.0
     traffic, traffic_word = measured_traffic(args.workload)
+    levels = kept_by_level(res["keys"], res["steps"], dims * r)
     grid_txt = "x".join(str(v) for v in w["n"])
     kernel_txt = {"linear": "", "quadratic": " (triquadratic interpolation)",
                   "cubic": " (tricubic interpolation)"}[args.order]
@@ -436,6 +461,7 @@ def bench_field_map(args):
         },
         "kernel_ms_per_step": {"step": ms_trace / args.steps, "land": ms_land / args.steps,
                                "assemble": ms_asm / args.steps},
+        "kept_by_level": levels,
         "launch_shape": tuned,
         "wall_s_timed": wall,
         "setup_s": t_gen,

@@ -108,3 +108,28 @@ def test_rel_log10_err_masks():
     ref = {"q_perp": np.array([10.0, 1e7, np.nan, 100.0]), "status": np.array([1, 1, 1, 2])}
     e = bench.rel_log10_err(np.array([10.0 ** 1.001, 1e7, 5.0, 100.0]), np.array([1, 1, 1, 3]), ref)
     assert e.size == 1 and e[0] == pytest.approx(1e-3)
+
+
+@pytest.mark.parametrize("dim,r", [(2, 2), (3, 2), (2, 1)])
+def test_kept_by_level_follows_the_bisection(dim, r):
+    """Levels recovered from keys match a lattice built by bisection: base keys
+    q B^r + B^r / 2, then each level the integer midpoints of neighbouring keys
+    (the first level also past the last base key)."""
+    import numpy as np
+    import torch
+    levels, blk, nb = dim * r, 1 << (dim * r), 5
+    keys = [q * blk + blk // 2 for q in range(nb)]
+    level_of = {k: 0 for k in keys}
+    for j in range(1, levels + 1):
+        cur = sorted(level_of) + ([nb * blk + blk // 2] if j == 1 else [])
+        for a, b in zip(cur[:-1], cur[1:]):
+            level_of[(a + b) // 2] = j
+    ks = np.array(sorted(level_of), np.int64)
+    att = np.array([10 * level_of[k] + 1 for k in ks], np.int32)
+    rows = bench.kept_by_level(torch.from_numpy(ks), torch.from_numpy(att), levels)
+    assert [row["level"] for row in rows] == list(range(levels + 1))
+    for row in rows:
+        want = [k for k in ks if level_of[k] == row["level"]]
+        assert row["lines"] == len(want)
+        assert row["attempts"] == len(want) * (10 * row["level"] + 1)
+        assert row["max_attempts"] == 10 * row["level"] + 1

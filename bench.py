@@ -95,6 +95,8 @@ def parse():
                     help="add the field's cell records (8 corner records per cell) and let the tuner try them")
     ap.add_argument("--no-bricks", action="store_true",
                     help="do not add the field's brick records (2x2x2 node bricks) for the tuner to try")
+    ap.add_argument("--no-dirs", action="store_true",
+                    help="do not add the field's direction records (96 bytes per cell) for the tuner to try")
     ap.add_argument("--accuracy-lines", type=int, default=2048)
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the accuracy and BF16 legs after the timed region (counter runs)")
@@ -308,6 +310,8 @@ def bench_field_map(args):
         field.add_cells()
     if not args.no_bricks and args.order == "linear":
         field.add_bricks()
+    if not args.no_dirs and args.order == "linear":
+        field.add_cell_dirs()
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
     h = min(w["spacing"])
@@ -359,6 +363,12 @@ def bench_field_map(args):
                 cands += autotune.candidates(lanes=(1, 2, 4), wgs=(64, 256), gathers=(A.GATHER_CELLS,))
             if field.bricks_ws is not None:
                 cands += autotune.candidates(lanes=(1, 2), wgs=(64, 128, 256), gathers=(A.GATHER_BRICKS,))
+            if field.dirs_ws is not None:
+                cands += autotune.candidates(lanes=(1, 2), wgs=(64, 128, 256), gathers=(A.GATHER_DIRS,))
+                if field.bricks_ws is not None:
+                    # brick records for the base lattice, direction records after it
+                    cands += [w | A.launch_word(refine_gather=A.GATHER_DIRS)
+                              for w in autotune.candidates(lanes=(2,), wgs=(64, 128, 256), gathers=(A.GATHER_BRICKS,))]
             batches = (args.refine_batch,) if args.refine_batch > 0 else (1, 2, 3)
             (word, batch), table = autotune.tune_map(plan, field, opts, reps=1, cands=cands, batches=batches)
         else:
@@ -366,6 +376,8 @@ def bench_field_map(args):
             cands = autotune.candidates()
             if field.bricks_ws is not None:
                 cands += autotune.candidates(gathers=(A.GATHER_BRICKS,))
+            if field.dirs_ws is not None:
+                cands += autotune.candidates(gathers=(A.GATHER_DIRS,))
             (word, batch), table = autotune.tune_map(plan, field, opts, reps=2, cands=cands, batches=batches)
         opts.launch = word
         plan.d.refine_batch = batch

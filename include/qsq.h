@@ -138,6 +138,12 @@ typedef struct qsq_field {
                               2 (j%2) + i%2 with nbx = (n0+1)/2, nby = (n1+1)/2;
                               padding nodes zero.  Read by launch gather 5 only */
     uint64_t brick_bytes;  /* size of the brick records (0 without) */
+    void *dirs;            /* NULL, or device direction records (qsq_field_add_cell_dirs,
+                              FP32 storage only): for each of the (n0-1)(n1-1)(n2-1)
+                              cells, x fastest, the first 3 values of its 8 corner
+                              records in the order a + 2b + 4c, 24 floats (96 bytes)
+                              contiguous.  Read by launch gather 6 only */
+    uint64_t dir_bytes;    /* size of the direction records (0 without) */
 } qsq_field;
 
 /* Geometry of a field (Sect. 3.1).  SPHERICAL: the grid axes are longitude phi,
@@ -189,15 +195,26 @@ typedef struct qsq_trace_opts {
  *          field with cell records; otherwise direct; identical results),
  *          5 = the register cache of 3 reading the field's brick records (same
  *          conditions as 3, field with brick records; otherwise as 3;
- *          identical results)
+ *          identical results),
+ *          6 = the register cache of 3 reading the field's direction records
+ *          (FP32 storage and stepping, one field per call, field with
+ *          direction records; otherwise as 3; identical results)
  * and the flag
  *   QSQ_LAUNCH_PARTS  split the work list of the persistent stepping launch
  *          into 8 contiguous parts with a counter each; workgroup b starts in
  *          part b mod 8 (the XCD it is dispatched to, so that one XCD's L2
  *          serves lines whose seeds lie together) and moves on to the other
- *          parts once its own is used up (scheduling only: identical results) */
+ *          parts once its own is used up (scheduling only: identical results)
+ * and, read by qsq_qmap and qsq_vmap only (other calls ignore it),
+ *   QSQ_LAUNCH_REFINE_GATHER(g)  gather (1..6, as above) of every stepping
+ *          launch after the base lattice (proposals, refinement rounds,
+ *          shifted re-pass); 0 (default): the word's gather.  The base
+ *          lattice and the sparser refinement lines differ in how often lines
+ *          in flight share cells, so each may want its own record layout
+ *          (identical results) */
 #define QSQ_LAUNCH(lanes, wg, gather) (((lanes) & 15) | (((wg) & 3) << 4) | (((gather) & 7) << 6))
 #define QSQ_LAUNCH_PARTS (1 << 9)
+#define QSQ_LAUNCH_REFINE_GATHER(g) (((g) & 7) << 10)
 
 /* Per-seed results (device arrays of n entries; fp_* are SoA planes 3 x n:
  * x at [0,n), y at [n,2n), z at [2n,3n)).  Any pointer except status may be
@@ -280,6 +297,24 @@ uint64_t qsq_field_brick_bytes(const qsq_grid *g, int storage);
  * rectilinear field), WORKSPACE_TOO_SMALL, HIP.
  */
 int qsq_field_add_bricks(qsq_field *f, void *ws, uint64_t ws_bytes, void *stream);
+
+/* Bytes of direction records for grid g: 96 per cell for FP32 storage, 0 for
+ * any other storage (not offered). */
+uint64_t qsq_field_cell_dir_bytes(const qsq_grid *g, int storage);
+
+/*
+ * Add direction records to a prepared FP32 field: for each cell the direction
+ * part (first 3 values) of its 8 corner records (Sect. 3.2), 96 contiguous
+ * bytes (layout at qsq_field.dirs), in `ws` (device, >=
+ * qsq_field_cell_dir_bytes, 256-byte aligned), so that the stepping kernel's
+ * register cache (launch gather 6) loads a cell in six 16-byte loads from at
+ * most two 128-byte lines; every other pass reads f->nodes, and the values,
+ * so every result, are those of the node records.  FP32 trilinear Cartesian
+ * fields with uniform axes only.  Sets f->dirs and f->dir_bytes.  Errors:
+ * INVALID_ARG (f invalid, ws NULL or misaligned), UNSUPPORTED (other storage,
+ * higher order, spherical or rectilinear field), WORKSPACE_TOO_SMALL, HIP.
+ */
+int qsq_field_add_cell_dirs(qsq_field *f, void *ws, uint64_t ws_bytes, void *stream);
 
 /* ---- tracing (Sect. 3.1-3.5) ------------------------------------------ */
 

@@ -29,7 +29,7 @@ STATUS_OPEN = 1 << 16
 # every entry point include/qsq.h declares
 EXPORTS = ["qsq_abi_version", "qsq_status_string", "qsq_last_error", "qsq_field_bytes",
            "qsq_field_init", "qsq_field_cell_bytes", "qsq_field_add_cells", "qsq_field_brick_bytes",
-           "qsq_field_add_bricks", "qsq_trace_scratch_bytes",
+           "qsq_field_add_bricks", "qsq_field_cell_dir_bytes", "qsq_field_add_cell_dirs", "qsq_trace_scratch_bytes",
            "qsq_trace", "qsq_fledge",
            "qsq_hilbert2_d2xy", "qsq_hilbert2_xy2d", "qsq_qmap_scratch_bytes", "qsq_qmap",
            "qsq_profile_enable", "qsq_profile_reset", "qsq_profile_read",
@@ -47,17 +47,19 @@ TRACE_NOALLOC_MAX_SEEDS = 1 << 18
 KERNEL_STEP, KERNEL_LAND, KERNEL_ASSEMBLE = 0, 1, 2
 
 WG_CODES = {256: 0, 64: 1, 128: 2}
-GATHER_AUTO, GATHER_DIRECT, GATHER_CACHED, GATHER_REGS, GATHER_CELLS, GATHER_BRICKS = 0, 1, 2, 3, 4, 5
+GATHER_AUTO, GATHER_DIRECT, GATHER_CACHED, GATHER_REGS, GATHER_CELLS, GATHER_BRICKS, GATHER_DIRS = range(7)
 
 
 LAUNCH_PARTS = 1 << 9
 
 
-def launch_word(lanes=0, wg=256, gather=GATHER_AUTO, parts=False):
-    """QSQ_LAUNCH(lanes, wg, gather), with QSQ_LAUNCH_PARTS if parts, of include/qsq.h."""
-    if not 0 <= lanes <= 15 or wg not in WG_CODES or gather not in (0, 1, 2, 3, 4, 5):
-        raise ValueError("launch shape outside QSQ_LAUNCH(0..15, 64|128|256, 0..5)")
-    return (lanes & 15) | (WG_CODES[wg] << 4) | (gather << 6) | (LAUNCH_PARTS if parts else 0)
+def launch_word(lanes=0, wg=256, gather=GATHER_AUTO, parts=False, refine_gather=0):
+    """QSQ_LAUNCH(lanes, wg, gather), with QSQ_LAUNCH_PARTS if parts and
+    QSQ_LAUNCH_REFINE_GATHER(refine_gather), of include/qsq.h."""
+    if not 0 <= lanes <= 15 or wg not in WG_CODES or gather not in range(7) or refine_gather not in range(7):
+        raise ValueError("launch shape outside QSQ_LAUNCH(0..15, 64|128|256, 0..6), refine gather 0..6")
+    return ((lanes & 15) | (WG_CODES[wg] << 4) | (gather << 6) | (LAUNCH_PARTS if parts else 0)
+            | (refine_gather << 10))
 
 
 class Grid(C.Structure):
@@ -68,7 +70,8 @@ class FieldDesc(C.Structure):
     _fields_ = [("grid", Grid), ("storage", C.c_int32), ("mode", C.c_int32),
                 ("nodes", C.c_void_p), ("bytes", C.c_uint64), ("cells", C.c_void_p), ("cell_bytes", C.c_uint64),
                 ("order", C.c_int32), ("geometry", C.c_int32), ("coords", C.c_void_p * 3),
-                ("bricks", C.c_void_p), ("brick_bytes", C.c_uint64)]
+                ("bricks", C.c_void_p), ("brick_bytes", C.c_uint64), ("dirs", C.c_void_p),
+                ("dir_bytes", C.c_uint64)]
 
 
 class TraceOpts(C.Structure):
@@ -138,6 +141,10 @@ def _load():
     L.qsq_field_brick_bytes.argtypes = [C.POINTER(Grid), I]
     L.qsq_field_add_bricks.restype = I
     L.qsq_field_add_bricks.argtypes = [C.POINTER(FieldDesc), P, U64, P]
+    L.qsq_field_cell_dir_bytes.restype = U64
+    L.qsq_field_cell_dir_bytes.argtypes = [C.POINTER(Grid), I]
+    L.qsq_field_add_cell_dirs.restype = I
+    L.qsq_field_add_cell_dirs.argtypes = [C.POINTER(FieldDesc), P, U64, P]
     L.qsq_trace_scratch_bytes.argtypes = [I64]
     L.qsq_trace.restype = I
     L.qsq_trace.argtypes = [C.POINTER(FieldDesc), P, I64, C.POINTER(TraceOpts), C.POINTER(TraceOut),

@@ -46,6 +46,7 @@ class Field:
         self.ws = ws
         self.cells_ws = None
         self.bricks_ws = None
+        self.dirs_ws = None
 
     def add_cells(self, stream=None):
         """Add cell records (the 8 corner records of every cell, contiguous),
@@ -63,6 +64,16 @@ class Field:
         ws = _bytes_tensor(nbytes, self.ws.device)
         check(lib.qsq_field_add_bricks(C.byref(self.desc), _p(ws), ws.numel() * 8, _stream(stream)))
         self.bricks_ws = ws
+        return self
+
+    def add_cell_dirs(self, stream=None):
+        """Add direction records (each cell's 8 corner directions, 96
+        contiguous bytes; FP32 fields), read by the stepping kernel's gather 6;
+        returns self."""
+        nbytes = lib.qsq_field_cell_dir_bytes(C.byref(self.desc.grid), self.desc.storage)
+        ws = _bytes_tensor(nbytes, self.ws.device)
+        check(lib.qsq_field_add_cell_dirs(C.byref(self.desc), _p(ws), ws.numel() * 8, _stream(stream)))
+        self.dirs_ws = ws
         return self
 
     @property

@@ -119,10 +119,13 @@ def tune_batch(sets, opts, reps=3, cands=None):
 def describe(word):
     lanes = word & 15 or 8
     wg = {0: 256, 1: 64, 2: 128}[(word >> 4) & 3]
-    gather = {0: "auto", 1: "direct", 2: "lds-cache", 3: "reg-cache", 4: "cell-records",
-              5: "reg-cache-bricks"}[(word >> 6) & 7]
-    return {"word": int(word), "lanes_per_cu": lanes * 256, "workgroup": wg, "gather": gather,
-            "xcd_parts": bool(word & A.LAUNCH_PARTS)}
+    names = {0: "auto", 1: "direct", 2: "lds-cache", 3: "reg-cache", 4: "cell-records",
+             5: "reg-cache-bricks", 6: "reg-cache-dirs"}
+    out = {"word": int(word), "lanes_per_cu": lanes * 256, "workgroup": wg, "gather": names[(word >> 6) & 7],
+           "xcd_parts": bool(word & A.LAUNCH_PARTS)}
+    if (word >> 10) & 7:
+        out["refine_gather"] = names[(word >> 10) & 7]
+    return out
 
 
 def tune_map(plan, field, opts, reps=3, cands=None, batches=None):

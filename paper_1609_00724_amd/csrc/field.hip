@@ -135,6 +135,43 @@ __global__ void __launch_bounds__(256) k_brick_records(const R *__restrict__ nod
     }
 }
 
+// Direction records: for each cell (x fastest) the direction part (3 FP32
+// values) of its 8 corner records in the order a + 2b + 4c of corner
+// (i+a, j+b, k+c), 96 contiguous bytes, so that a cell's corners come in six
+// 16-byte loads from at most two 128-byte lines.  One thread per (cell, corner).
+__global__ void __launch_bounds__(256) k_cell_dirs(const float4 *__restrict__ nodes, int64_t nx, int64_t ny,
+                                                   int64_t ncells, float *__restrict__ dirs)
+{
+    const int64_t cx = nx - 1, cy = ny - 1;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 8 * ncells;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e >> 3;
+        const int v = (int)(e & 7);
+        const int64_t i = c % cx, j = (c / cx) % cy, k = c / (cx * cy);
+        const float4 r = nodes[((k + (v >> 2)) * ny + j + ((v >> 1) & 1)) * nx + i + (v & 1)];
+        dirs[3 * e] = r.x;
+        dirs[3 * e + 1] = r.y;
+        dirs[3 * e + 2] = r.z;
+    }
+}
+
+uint64_t cell_dir_bytes(const qsq_grid *g)
+{
+    return 96 * (uint64_t)(g->n[0] - 1) * (uint64_t)(g->n[1] - 1) * (uint64_t)(g->n[2] - 1);
+}
+
+hipError_t launch_cell_dirs(const qsq_field *f, void *ws, hipStream_t st)
+{
+    const int64_t nx = f->grid.n[0], ny = f->grid.n[1];
+    const int64_t ncells = (nx - 1) * (ny - 1) * (f->grid.n[2] - 1);
+    const int cus = device_cu_count();
+    const int64_t want = (8 * ncells + 255) / 256;
+    const int blocks = (int)(want < (int64_t)cus * 32 ? want : (int64_t)cus * 32);
+    hipLaunchKernelGGL(k_cell_dirs, dim3(blocks), dim3(256), 0, st, static_cast<const float4 *>(f->nodes), nx, ny,
+                       ncells, static_cast<float *>(ws));
+    return hipGetLastError();
+}
+
 uint64_t brick_record_bytes(const qsq_grid *g, int storage)
 {
     const uint64_t rec = storage == QSQ_F64 ? 32 : storage == QSQ_F32 ? 16 : 8;

@@ -1066,6 +1066,7 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
     job.nodes = f->nodes;
     job.cells = f->cells;
     job.bricks = f->bricks;
+    job.dirs = static_cast<const float *>(f->dirs);
     job.storage = f->storage;
     job.mode = job_mode(f);
     job.g = g;
@@ -1095,6 +1096,10 @@ static hipError_t launch_map(const qsq_field *f, const Geom &g, const StepOpts &
         e = launch_trace(job, step_dtype, st);
         if (e != hipSuccess) return e;
     }
+    // every stepping launch after the base lattice (proposals, refinement
+    // rounds, shifted re-pass) takes the refinement gather, if the word names one
+    const int rgather = (o.launch >> 10) & 7;
+    if (rgather) job.o.launch = (o.launch & ~(7 << 6)) | (rgather << 6);
     if (out->fledge) {
         float *img = reinterpret_cast<float *>(base + Lo.img);
         hipLaunchKernelGGL((k_fll_raster<DIM>), dim3(grid_for(nb)), dim3(256), 0, st, rg, nb, A.fll, img);

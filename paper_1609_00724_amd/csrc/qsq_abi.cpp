@@ -68,6 +68,8 @@ int check_field(const qsq_field *f)
         return fail(QSQ_ERR_INVALID_ARG, "field cell_bytes smaller than the grid's cell records");
     if (f->bricks && f->brick_bytes < qsq::brick_record_bytes(&f->grid, f->storage))
         return fail(QSQ_ERR_INVALID_ARG, "brick bytes smaller than the grid needs");
+    if (f->dirs && (f->storage != QSQ_F32 || f->dir_bytes < qsq::cell_dir_bytes(&f->grid)))
+        return fail(QSQ_ERR_INVALID_ARG, "direction records need FP32 storage and dir_bytes for every cell");
     if (f->order < 0 || f->order > QSQ_ORDER_CUBIC) return fail(QSQ_ERR_INVALID_ARG, "field order %d", f->order);
     if (f->geometry != QSQ_GEOMETRY_CARTESIAN && f->geometry != QSQ_GEOMETRY_SPHERICAL)
         return fail(QSQ_ERR_INVALID_ARG, "field geometry %d", f->geometry);
@@ -106,8 +108,11 @@ int make_geom_opts(const qsq_field *f, const qsq_trace_opts *o, qsq::Geom *g, qs
     if (!isfinite(o->h_init) || !isfinite(o->h_max) || !isfinite(o->max_length))
         return fail(QSQ_ERR_INVALID_ARG, "h_init, h_max and max_length must be finite");
     if (o->flags & ~QSQ_FLAG_SKIP_OPEN) return fail(QSQ_ERR_INVALID_ARG, "unknown flags 0x%x", o->flags);
-    if ((o->launch & ~0x3ff) || ((o->launch >> 4) & 3) == 3 || ((o->launch >> 6) & 7) > 5)
-        return fail(QSQ_ERR_INVALID_ARG, "launch word 0x%x outside QSQ_LAUNCH(0..15, 0..2, 0..5) | QSQ_LAUNCH_PARTS",
+    if ((o->launch & ~0x1fff) || ((o->launch >> 4) & 3) == 3 || ((o->launch >> 6) & 7) > 6 ||
+        ((o->launch >> 10) & 7) > 6)
+        return fail(QSQ_ERR_INVALID_ARG,
+                    "launch word 0x%x outside QSQ_LAUNCH(0..15, 0..2, 0..6) | QSQ_LAUNCH_PARTS | "
+                    "QSQ_LAUNCH_REFINE_GATHER(0..6)",
                     o->launch);
     double hmin_grid = f->grid.spacing[0];
     double extent = 0.0;
@@ -293,6 +298,8 @@ int qsq_field_init(const qsq_grid *g, const void *bx, const void *by, const void
     out->cell_bytes = 0;
     out->bricks = nullptr;
     out->brick_bytes = 0;
+    out->dirs = nullptr;
+    out->dir_bytes = 0;
     out->order = QSQ_ORDER_LINEAR;
     out->geometry = QSQ_GEOMETRY_CARTESIAN;
     out->coords[0] = out->coords[1] = out->coords[2] = nullptr;
@@ -347,6 +354,30 @@ int qsq_field_add_bricks(qsq_field *f, void *ws, uint64_t ws_bytes, void *stream
     return ok();
 }
 
+uint64_t qsq_field_cell_dir_bytes(const qsq_grid *g, int storage)
+{
+    if (!g || g->n[0] < 2 || g->n[1] < 2 || g->n[2] < 2 || storage != QSQ_F32) return 0;
+    return qsq::cell_dir_bytes(g);
+}
+
+int qsq_field_add_cell_dirs(qsq_field *f, void *ws, uint64_t ws_bytes, void *stream)
+{
+    int rc = check_field(f);
+    if (rc) return rc;
+    if (f->storage != QSQ_F32 || qsq::job_mode(f) > 1)
+        return fail(QSQ_ERR_UNSUPPORTED, "direction records take FP32 trilinear Cartesian fields with uniform axes");
+    if (!ws || !aligned(ws, 256)) return fail(QSQ_ERR_INVALID_ARG, "direction workspace NULL or not 256-byte aligned");
+    const uint64_t need = qsq_field_cell_dir_bytes(&f->grid, f->storage);
+    if (ws_bytes < need)
+        return fail(QSQ_ERR_WORKSPACE_TOO_SMALL, "direction workspace %llu < %llu bytes",
+                    (unsigned long long)ws_bytes, (unsigned long long)need);
+    hipError_t e = qsq::launch_cell_dirs(f, ws, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "qsq_field_add_cell_dirs");
+    f->dirs = ws;
+    f->dir_bytes = need;
+    return ok();
+}
+
 uint64_t qsq_trace_scratch_bytes(int64_t n)
 {
     if (n < 0) return 0;
@@ -376,6 +407,7 @@ int qsq_trace(const qsq_field *f, const double *seeds, int64_t n, const qsq_trac
     job.nodes = f->nodes;
     job.cells = f->cells;
     job.bricks = f->bricks;
+    job.dirs = static_cast<const float *>(f->dirs);
     job.storage = f->storage;
     job.mode = qsq::job_mode(f);
     job.g = g;

@@ -94,6 +94,7 @@ struct TraceJob {
     const void *nodes;
     const void *cells;  // cell records (nullable): 8 corner records per cell
     const void *bricks; // brick records (nullable): the nodes in 2 x 2 x 2 bricks
+    const float *dirs;  // direction records (nullable): 24 FP32 values per cell
     int storage;        // QSQ_F32 / QSQ_F64
     int mode;           // QSQ_INTERP_*
     Geom g;
@@ -181,6 +182,8 @@ hipError_t launch_cell_records(const qsq_field *f, void *ws, hipStream_t st);
 // Brick records (2 x 2 x 2 node bricks) copied from a prepared field's nodes.
 uint64_t brick_record_bytes(const qsq_grid *g, int storage);
 hipError_t launch_brick_records(const qsq_field *f, void *ws, hipStream_t st);
+uint64_t cell_dir_bytes(const qsq_grid *g);
+hipError_t launch_cell_dirs(const qsq_field *f, void *ws, hipStream_t st);
 hipError_t launch_field_init(const qsq_grid *g, const void *bx, const void *by, const void *bz,
                              int in_dtype, int storage, int mode, void *ws, hipStream_t stream);
 

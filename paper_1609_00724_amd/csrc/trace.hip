@@ -587,22 +587,46 @@ __device__ __forceinline__ void load_corner(__amdgpu_buffer_rsrc_t rsrc, int off
 }
 
 
+// the 24 direction values of a cell's corners packed in six float4 (corner
+// order a + 2b + 4c, 3 values each): the parked cell's LDS slot and the
+// direction records share this packing
+__device__ __forceinline__ void unpack_cell(const float4 v[6], Brick &br)
+{
+    br.c000 = Corner{v[0].x, v[0].y, v[0].z};
+    br.c100 = Corner{v[0].w, v[1].x, v[1].y};
+    br.c010 = Corner{v[1].z, v[1].w, v[2].x};
+    br.c110 = Corner{v[2].y, v[2].z, v[2].w};
+    br.c001 = Corner{v[3].x, v[3].y, v[3].z};
+    br.c101 = Corner{v[3].w, v[4].x, v[4].y};
+    br.c011 = Corner{v[4].z, v[4].w, v[5].x};
+    br.c111 = Corner{v[5].y, v[5].z, v[5].w};
+}
+
+// record layouts of the register cache
+constexpr int kLayoutNodes = 0, kLayoutBricks = 1, kLayoutDirs = 2;
+
 // BRICKS: the records are the field's brick records (2 x 2 x 2 node bricks,
 // bricks x fastest): node (i, j, k) sits at ((k/2 nby + j/2) nbx + i/2) 8 +
 // 4 (k & 1) + 2 (j & 1) + (i & 1), so the step from a corner to its neighbour
 // along an axis is 1, 2, 4 records from an even index and 7, 8 nbx - 2,
-// 8 nbx nby - 4 from an odd one
-template <typename T, typename S, int MODE, bool BRICKS = false>
-__device__ __forceinline__ T rhs_regs(__amdgpu_buffer_rsrc_t rsrc, int bytes, const Geom &g, const int ib[3],
-                                      const T q[3], T sigma, const T d1[3], const T d2[3], T kx[3], T k1[3],
-                                      T k2[3], int &cell, Brick &br, float4 *slot, int stride, int &cell2)
+// 8 nbx nby - 4 from an odd one.  DIRS: `dirs` holds the field's direction
+// records, the cell's 24 values in six 16-byte loads (global addresses: the
+// records may exceed 2 GiB), keyed by the cell's index.
+template <typename T, typename S, int MODE, int LAYOUT = kLayoutNodes>
+__device__ __forceinline__ T rhs_regs(__amdgpu_buffer_rsrc_t rsrc, int bytes, const float4 *__restrict__ dirs,
+                                      const Geom &g, const int ib[3], const T q[3], T sigma, const T d1[3],
+                                      const T d2[3], T kx[3], T k1[3], T k2[3], int &cell, Brick &br, float4 *slot,
+                                      int stride, int &cell2)
 {
     int c[3];
     T t[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) cell_of(ib[d], q[d], g.n[d], c[d], t[d]);
     int b, sx, sy, sz;
-    if constexpr (BRICKS) {
+    if constexpr (LAYOUT == kLayoutDirs) {
+        b = (c[2] * (g.n[1] - 1) + c[1]) * (g.n[0] - 1) + c[0];
+        sx = sy = sz = 0;
+    } else if constexpr (LAYOUT == kLayoutBricks) {
         const int nbx = (g.n[0] + 1) >> 1, nby = (g.n[1] + 1) >> 1;
         b = (((c[2] >> 1) * nby + (c[1] >> 1)) * nbx + (c[0] >> 1)) * 8 + ((c[2] & 1) << 2) + ((c[1] & 1) << 1) +
             (c[0] & 1);
@@ -637,17 +661,16 @@ __device__ __forceinline__ T rhs_regs(__amdgpu_buffer_rsrc_t rsrc, int bytes, co
         slot[5 * stride] = make_float4(br.c011.z, br.c111.x, br.c111.y, br.c111.z);
         cell2 = cell;
         if (back) {
-            br.c000 = Corner{keep[0].x, keep[0].y, keep[0].z};
-            br.c100 = Corner{keep[0].w, keep[1].x, keep[1].y};
-            br.c010 = Corner{keep[1].z, keep[1].w, keep[2].x};
-            br.c110 = Corner{keep[2].y, keep[2].z, keep[2].w};
-            br.c001 = Corner{keep[3].x, keep[3].y, keep[3].z};
-            br.c101 = Corner{keep[3].w, keep[4].x, keep[4].y};
-            br.c011 = Corner{keep[4].z, keep[4].w, keep[5].x};
-            br.c111 = Corner{keep[5].y, keep[5].z, keep[5].w};
+            unpack_cell(keep, br);
         } else
 #endif
-        {
+        if constexpr (LAYOUT == kLayoutDirs) {
+            const float4 *p = dirs + 6 * (int64_t)b;
+            float4 v[6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) v[j] = p[j];
+            unpack_cell(v, br);
+        } else {
             const int o = NB * b;
             const int ox = NB * sx, oy = NB * sy, oz = NB * sz;
             load_corner<S>(rsrc, o, br.c000);
@@ -731,7 +754,8 @@ __device__ __forceinline__ double err_ratio(double a, double b) { return a / b; 
 // gather variants of the stepping kernel: direct corner loads, the LDS cell
 // cache and the register cell cache (the caches: FP32 or BF16 storage, FP32
 // stepping, one field below 2 GiB)
-constexpr int kGatherDirect = 0, kGatherLds = 1, kGatherRegs = 2, kGatherCells = 3, kGatherBricks = 4;
+constexpr int kGatherDirect = 0, kGatherLds = 1, kGatherRegs = 2, kGatherCells = 3, kGatherBricks = 4,
+              kGatherDirs = 5;
 
 // one RHS evaluation of the stepping kernel
 template <typename T, typename S, int MODE, int GATHER>
@@ -742,10 +766,13 @@ __device__ __forceinline__ T rhs_step(const S *__restrict__ nodes, __amdgpu_buff
 {
     if constexpr (GATHER == kGatherLds)
         return rhs_cached<T, S, MODE>(rsrc, bytes, g, ib, q, sigma, d1, d2, kx, k1, k2, cc, slot, stride);
-    else if constexpr (GATHER == kGatherRegs || GATHER == kGatherBricks)
-        // (cc[0], the LDS variant's cell key, keys the register cache's parked cell)
-        return rhs_regs<T, S, MODE, GATHER == kGatherBricks>(rsrc, bytes, g, ib, q, sigma, d1, d2, kx, k1, k2, cell,
-                                                             br, slot, stride, cc[0]);
+    else if constexpr (GATHER == kGatherRegs || GATHER == kGatherBricks || GATHER == kGatherDirs)
+        // (cc[0], the LDS variant's cell key, keys the register cache's parked
+        // cell; the direction records' variant gets them as `nodes`)
+        return rhs_regs<T, S, MODE,
+                        GATHER == kGatherBricks ? kLayoutBricks : GATHER == kGatherDirs ? kLayoutDirs : kLayoutNodes>(
+            rsrc, bytes, reinterpret_cast<const float4 *>(nodes), g, ib, q, sigma, d1, d2, kx, k1, k2, cell, br, slot,
+            stride, cc[0]);
     else
         return rhs<T, S, MODE, GATHER == kGatherCells>(nodes, g, ib, q, sigma, d1, d2, kx, k1, k2);
 }
@@ -1071,11 +1098,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EULER 
 {
     static_assert(GATHER == kGatherDirect || (!BATCH && sizeof(T) == 4),
                   "cell caches: one field per launch, FP32 corner values");
-    constexpr bool CACHED = GATHER == kGatherLds || GATHER == kGatherRegs || GATHER == kGatherBricks;
+    static_assert(GATHER != kGatherDirs || std::is_same<S, float>::value, "direction records: FP32 storage");
+    constexpr bool CACHED =
+        GATHER == kGatherLds || GATHER == kGatherRegs || GATHER == kGatherBricks || GATHER == kGatherDirs;
     // field and step limits of the lane's line: launch constants for one
     // field, reloaded from the set table at each refill in a batch (the cell
     // records' variant reads them in place of the node records)
-    const S *__restrict__ nodes = static_cast<const S *>(GATHER == kGatherCells ? job.cells : job.nodes);
+    const S *__restrict__ nodes = static_cast<const S *>(
+        GATHER == kGatherCells ? job.cells : GATHER == kGatherDirs ? static_cast<const void *>(job.dirs) : job.nodes);
     Geom gl = job.g;
     const Geom &g = gl;
     const StepOpts &o = job.o;
@@ -2416,12 +2446,18 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
                                      ((job.g.n[1] + 1) / 2) * ((job.g.n[2] + 1) / 2);
         const uint64_t limit = ((uint64_t)1 << 31) - ((uint64_t)1 << 26);
         const bool fits = field_bytes < limit;
-        if (gather == 5 && job.bricks && brick_bytes < limit) {
+        const void *dirs_kern = nullptr;
+        if constexpr (std::is_same<S, float>::value)
+            if (gather == 6 && job.dirs) dirs_kern = trace_kernel<T, S, MODE, kGatherDirs, false>(euler);
+        if (dirs_kern) {
+            kern = dirs_kern;
+            lds = QSQ_SECOND_CELL ? kCachePlanes * wg * sizeof(float4) : 0;
+        } else if (gather == 5 && job.bricks && brick_bytes < limit) {
             kern = trace_kernel<T, S, MODE, kGatherBricks, false>(euler);
             lds = QSQ_SECOND_CELL ? kCachePlanes * wg * sizeof(float4) : 0;
         } else if (gather == 4 && job.cells) {
             kern = trace_kernel<T, S, MODE, kGatherCells, false>(euler);
-        } else if ((gather == 3 || gather == 5 || gather == 0) && fits) {
+        } else if ((gather == 3 || gather == 5 || gather == 6 || gather == 0) && fits) {
             kern = trace_kernel<T, S, MODE, kGatherRegs, false>(euler);
             lds = QSQ_SECOND_CELL ? kCachePlanes * wg * sizeof(float4) : 0;
         } else if (gather == 2 && fits) {

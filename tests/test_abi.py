@@ -95,7 +95,7 @@ def test_invalid_arguments_rejected_before_launch(qsq):
     assert L.qsq_trace(C.byref(f), _fake(7), 10, C.byref(o), C.byref(t), _fake(8), 1 << 20, None) == \
         A.ERR_UNSUPPORTED
     o.step_dtype = A.F32
-    for bad in (0x30, 0x400, 0x180):      # workgroup code 3; bits above the word; gather 6
+    for bad in (0x30, 0x2000, 0x1c0, 0x1c00):   # workgroup code 3; bits above the word; gather 7; refine gather 7
         o.launch = bad
         assert L.qsq_trace(C.byref(f), _fake(7), 10, C.byref(o), C.byref(t), _fake(8), 1 << 20, None) == \
             A.ERR_INVALID_ARG
@@ -291,3 +291,32 @@ def test_brick_record_sizes_and_limits(qsq):
     f.order = A.ORDER_LINEAR
     rc = qsq.lib.qsq_field_add_bricks(C.byref(f), 256, 16, None)
     assert rc == A.ERR_WORKSPACE_TOO_SMALL
+
+
+def test_direction_record_sizes_and_limits(qsq):
+    """Direction records: 96 bytes per cell for FP32 fields and none for other
+    storage; other storage, higher orders, a short workspace and a descriptor
+    claiming fewer direction bytes than the grid's cells need are refused
+    before any work."""
+    from paper_1609_00724_amd import _abi as A
+    g = A.Grid()
+    g.n[:] = (5, 4, 3)
+    assert qsq.lib.qsq_field_cell_dir_bytes(C.byref(g), A.F32) == 96 * 4 * 3 * 2
+    assert qsq.lib.qsq_field_cell_dir_bytes(C.byref(g), A.BF16) == 0
+    assert qsq.lib.qsq_field_cell_dir_bytes(C.byref(g), A.F64) == 0
+    f = A.FieldDesc()
+    f.grid.n[:] = (8, 8, 8)
+    f.grid.spacing[:] = (1.0, 1.0, 1.0)
+    f.storage, f.mode, f.nodes, f.bytes = A.BF16, A.INTERP_PAPER, 256, 8 ** 3 * 8
+    rc = qsq.lib.qsq_field_add_cell_dirs(C.byref(f), 256, 1 << 20, None)
+    assert rc == A.ERR_UNSUPPORTED and b"direction" in qsq.lib.qsq_last_error()
+    f.storage, f.bytes = A.F32, 8 ** 3 * 16
+    f.order = A.ORDER_CUBIC
+    rc = qsq.lib.qsq_field_add_cell_dirs(C.byref(f), 256, 1 << 20, None)
+    assert rc == A.ERR_UNSUPPORTED
+    f.order = A.ORDER_LINEAR
+    rc = qsq.lib.qsq_field_add_cell_dirs(C.byref(f), 256, 96 * 7 ** 3 - 1, None)
+    assert rc == A.ERR_WORKSPACE_TOO_SMALL
+    f.dirs, f.dir_bytes = 256, 96 * 7 ** 3 - 1
+    rc = qsq.lib.qsq_field_add_cell_dirs(C.byref(f), 256, 96 * 7 ** 3, None)
+    assert rc == A.ERR_INVALID_ARG and b"direction" in qsq.lib.qsq_last_error()

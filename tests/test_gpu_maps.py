@@ -367,8 +367,10 @@ def test_shifted_repass_vs_oracle(oracle_mod, c2, dims, shift):
 
 def test_volume_map_cell_records_identical(c2):
     """A refined volume map stepped with the cell records (gather 4) equals the
-    map stepped with the register cell cache and with direct loads bit for
-    bit: the same corner values reach the same arithmetic."""
+    map stepped with the register cell cache (over node, brick or direction
+    records), with direct loads, and with another gather for the refinement
+    rounds than for the base lattice, bit for bit: the same corner values
+    reach the same arithmetic."""
     import paper_1609_00724_amd as q
     from paper_1609_00724_amd import _abi as A
     from paper_1609_00724_amd.api import QMapPlan, VolumeSpec, make_opts
@@ -379,14 +381,17 @@ def test_volume_map_cell_records_identical(c2):
         fg.add_cells()
     if fg.bricks_ws is None:
         fg.add_bricks()
+    if fg.dirs_ws is None:
+        fg.add_cell_dirs()
     spec = VolumeSpec(-1.0, 1.0, -1.0, 1.0, 0.0, 1.0, 5, 2, 6, 0.02, 1)
     out = []
-    for gather, parts in ((A.GATHER_CELLS, False), (A.GATHER_REGS, False), (A.GATHER_DIRECT, False),
-                          (A.GATHER_REGS, True), (A.GATHER_DIRECT, True), (A.GATHER_BRICKS, False),
-                          (A.GATHER_BRICKS, True)):
+    for gather, parts, rg in ((A.GATHER_CELLS, False, 0), (A.GATHER_REGS, False, 0), (A.GATHER_DIRECT, False, 0),
+                              (A.GATHER_REGS, True, 0), (A.GATHER_DIRECT, True, 0), (A.GATHER_BRICKS, False, 0),
+                              (A.GATHER_BRICKS, True, 0), (A.GATHER_DIRS, False, 0),
+                              (A.GATHER_BRICKS, False, A.GATHER_DIRS), (A.GATHER_DIRECT, True, A.GATHER_DIRS)):
         plan = QMapPlan(spec, 8 ** 7, dev, want_steps=True)
         opts = make_opts(1e-2, 1e-2, h_init=0.1 * h, h_max=4 * h, step_dtype="f32",
-                         launch=A.launch_word(1, 256, gather, parts))
+                         launch=A.launch_word(1, 256, gather, parts, refine_gather=rg))
         plan.run(fg, opts)
         torch.cuda.synchronize()
         r = plan.result()

@@ -165,8 +165,9 @@ def test_cell_cache_gathers_bit_identical_at_long_steps(small_charges, storage):
     """With steps of up to 4 cells most stage points land in another cell, and
     in a wave some lanes move while others stay: the register cell cache
     (corners loaded by the lanes that moved only), its LDS form and, for FP32
-    records, the register cache over brick records give the same outputs as
-    direct corner loads, bit for bit, for FP32 and BF16 records."""
+    records, the register cache over brick records and over direction records
+    give the same outputs as direct corner loads, bit for bit, for FP32 and
+    BF16 records."""
     import torch
 
     from paper_1609_00724_amd import _abi as A
@@ -177,7 +178,8 @@ def test_cell_cache_gathers_bit_identical_at_long_steps(small_charges, storage):
     gathers = [A.GATHER_DIRECT, A.GATHER_REGS, A.GATHER_CACHED]
     if storage == "f32":
         fg.add_bricks()
-        gathers.append(A.GATHER_BRICKS)
+        fg.add_cell_dirs()
+        gathers += [A.GATHER_BRICKS, A.GATHER_DIRS]
     dev = torch.device("cuda:0")
     n = 3000
     seeds = torch.from_numpy(np.ascontiguousarray(_mixed_seeds(n, 77).T)).to(dev)
@@ -194,6 +196,40 @@ def test_cell_cache_gathers_bit_identical_at_long_steps(small_charges, storage):
         for k in ref:
             assert torch.equal(torch.nan_to_num(r[k], nan=-7.0), torch.nan_to_num(ref[k], nan=-7.0)), (gather, k)
     assert int((ref["steps"][0] > 3).sum()) > n // 4
+
+
+def test_direction_records_on_an_uneven_grid():
+    """A grid with a different node count on every axis (so that a cell index
+    with the axes swapped would read another cell): the register cache over
+    direction records and over brick records, at steps of up to 4 cells,
+    give the direct corner loads' outputs bit for bit, with and without the
+    per-XCD parts."""
+    import torch
+
+    from paper_1609_00724_amd import _abi as A
+    from paper_1609_00724_amd.api import TracePlan, make_opts
+    n = (89, 71, 41)
+    b = synth.sample_charges(CH, n, dtype=np.float32)
+    origin, spacing = synth.grid_geometry(n)
+    h = min(spacing)
+    fg = gpu_field(b, origin, spacing).add_bricks().add_cell_dirs()
+    assert fg.desc.dir_bytes == 96 * 88 * 70 * 40
+    dev = torch.device("cuda:0")
+    m = 2000
+    seeds = torch.from_numpy(np.ascontiguousarray(_mixed_seeds(m, 78).T)).to(dev)
+    res = {}
+    for word in (A.launch_word(2, 128, A.GATHER_DIRECT), A.launch_word(2, 128, A.GATHER_BRICKS),
+                 A.launch_word(2, 128, A.GATHER_DIRS), A.launch_word(1, 64, A.GATHER_DIRS, parts=True)):
+        plan = TracePlan(m, dev, want_steps=True)
+        opts = make_opts(1e-2, 1e-2, h_init=0.1 * h, h_max=4 * h, step_dtype="f32", launch=word)
+        out = plan.run(fg, seeds, opts)
+        torch.cuda.synchronize()
+        res[word] = {k: v.clone() for k, v in out.items()}
+    ref = res[A.launch_word(2, 128, A.GATHER_DIRECT)]
+    for word, r in res.items():
+        for k in ref:
+            assert torch.equal(torch.nan_to_num(r[k], nan=-7.0), torch.nan_to_num(ref[k], nan=-7.0)), (word, k)
+    assert int((ref["steps"][0] > 3).sum()) > m // 4
 
 
 @pytest.mark.parametrize("n", [1, 3, 8, 9, 65, 1000])

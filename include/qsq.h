@@ -198,7 +198,8 @@ typedef struct qsq_trace_opts {
  *          identical results),
  *          6 = the register cache of 3 reading the field's direction records
  *          (FP32 storage and stepping, one field per call, field with
- *          direction records; otherwise as 3; identical results)
+ *          direction records, fewer than 2^31 cells; otherwise as 3;
+ *          identical results)
  * and the flag
  *   QSQ_LAUNCH_PARTS  split the work list of the persistent stepping launch
  *          into 8 contiguous parts with a counter each; workgroup b starts in

@@ -2446,9 +2446,13 @@ static hipError_t launch_typed(const TraceJob &job, hipStream_t st)
                                      ((job.g.n[1] + 1) / 2) * ((job.g.n[2] + 1) / 2);
         const uint64_t limit = ((uint64_t)1 << 31) - ((uint64_t)1 << 26);
         const bool fits = field_bytes < limit;
+        // the direction records' variant keys cells by a 32-bit cell index
+        const uint64_t ncells =
+            (uint64_t)(job.g.n[0] - 1) * (uint64_t)(job.g.n[1] - 1) * (uint64_t)(job.g.n[2] - 1);
         const void *dirs_kern = nullptr;
         if constexpr (std::is_same<S, float>::value)
-            if (gather == 6 && job.dirs) dirs_kern = trace_kernel<T, S, MODE, kGatherDirs, false>(euler);
+            if (gather == 6 && job.dirs && ncells < ((uint64_t)1 << 31))
+                dirs_kern = trace_kernel<T, S, MODE, kGatherDirs, false>(euler);
         if (dirs_kern) {
             kern = dirs_kern;
             lds = QSQ_SECOND_CELL ? kCachePlanes * wg * sizeof(float4) : 0;
